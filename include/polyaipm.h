@@ -1,0 +1,224 @@
+/*
+ * polyaipm.h -- C ABI of libpolyaipm.so: Polya set-up and primal-dual
+ * interior-point solver for robust stability of dx/dt = A(alpha) x on the
+ * unit simplex (Kamyar, Peet & Peet, IEEE TAC 2013), on one AMD MI355X.
+ *
+ * Problem (Section II, Theorem 1): find a homogeneous matrix polynomial
+ * P(alpha) = sum_{h in W_dp} P_h alpha^h with P(alpha) > 0 and
+ * A(alpha)^T P(alpha) + P(alpha) A(alpha) < 0 on the simplex.  Polya's theorem
+ * (Section II, Theorem 2) turns both into LMIs on the coefficients of
+ * (sum alpha)^d1 P and (sum alpha)^d2 (A^T P + P A) (Section III-A,
+ * eq. LMI_3/LMI_4), which form the block-diagonal SDP of Section III-B
+ * (eq. primal/dual, C, Ai, Aij, a).  The SDP is solved by the predictor-
+ * corrector primal-dual method of Section IV (Alg. 2).
+ *
+ * Conventions
+ *  - All functions return 0 on success or a negative PSDP_E* status; no C++
+ *    exception crosses this boundary.  A thread-local message describing the
+ *    last error is returned by psdp_last_error().
+ *  - A FEASIBLE / INFEASIBLE / UNKNOWN verdict is a result, not an error.
+ *  - Host pointers are read or written only during the call; inputs are
+ *    copied.  Handles are owned by the library and released by psdp_free().
+ *  - Matrices are row-major FP64.  Exponent sets W_d are in the paper's
+ *    descending lexicographic order (Notation section).
+ *  - Device work runs on the stream given in the options (NULL = the null
+ *    stream) and every call synchronises that stream before returning.
+ *  - Argument validation happens before any device call, so invalid input
+ *    is rejected without touching the GPU.
+ */
+#ifndef POLYAIPM_H
+#define POLYAIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PSDP_OK         0
+#define PSDP_EINVAL    -1   /* NULL pointer, bad dimension, non-finite input   */
+#define PSDP_EOVERFLOW -2   /* a multinomial exceeds int64, or sizes overflow  */
+#define PSDP_ENOMEM    -3   /* host or device allocation failed                */
+#define PSDP_EDEVICE   -4   /* a HIP runtime call failed                       */
+#define PSDP_ENUMERIC  -5   /* unrecoverable numerical failure                 */
+
+/* verdicts */
+#define PSDP_FEASIBLE   0   /* certificate found and checked by FP64 block Cholesky */
+#define PSDP_INFEASIBLE 1   /* no certificate exists at this (dp, d1, d2)           */
+#define PSDP_UNKNOWN    2
+
+/* exit reasons of the paper's SDP run (psdp_result.reason) */
+#define PSDP_R_CONVERGED 0
+#define PSDP_R_FARKAS    1
+#define PSDP_R_STALL     2
+#define PSDP_R_MAXITER   3
+#define PSDP_R_LADDER    4
+#define PSDP_R_CHOL      5
+#define PSDP_R_NONFINITE 6
+
+/* verdict pipelines */
+#define PSDP_VERDICT_PAPER_THEN_PHASE1 0
+#define PSDP_VERDICT_PAPER_ONLY        1
+#define PSDP_VERDICT_PHASE1_ONLY       2
+
+/* arithmetic of the Schur complement assembly (the Cholesky is FP64 always) */
+#define PSDP_PREC_FP64 0
+#define PSDP_PREC_FP32 1
+
+typedef struct psdp_sdp psdp_sdp;  /* opaque handle: one structured SDP */
+
+typedef struct {
+    int    da;            /* degree of A(alpha); 1 = affine, A holds the l vertices  */
+    int    d1, d2;        /* Polya exponents; -1 = take d from psdp_polya_setup      */
+    double delta;         /* P-block margin: C_j = delta * s_j * I   (eq. Cj; 1e-3)   */
+    double eps;           /* derivative-block margin eps * s_j * I (1e-3)            */
+    int    paper_literal; /* 1: derivative blocks of C are 0 as printed (eq. Cj)     */
+    int    a_on_device;   /* 1: the A pointer is a device address                    */
+} psdp_setup_opts;
+
+typedef struct {
+    int n, l, da, dp, d1, d2;
+    int L0;               /* card W_dp            (eq. L0) */
+    int L;                /* card W_{dp+d1}       (eq. L)  */
+    int M;                /* card W_{dp+da+d2}    (eq. M)  */
+    int Na;               /* card W_da                      */
+    int Nt;               /* n (n+1) / 2                    */
+    int64_t K;            /* L0 * Nt              (eq. K)  */
+    int64_t Kpad;         /* K rounded up to the Schur tile */
+    int64_t device_bytes; /* device memory one solve of this SDP needs */
+} psdp_dims;
+
+typedef struct {
+    double gap_tol;       /* relative duality gap tolerance (1e-8)                   */
+    double feas_tol;      /* relative primal / dual residual tolerance (1e-8)        */
+    int    max_iter;      /* per IPM run (100)                                       */
+    double sigma;         /* centring: mu = sigma tr(ZX) / m (1/3)                   */
+    double step_frac;     /* fraction of the largest PD step (0.95)                  */
+    double ladder_rho;    /* ratio of the step ladder (0.9)                          */
+    int    ladder_len;    /* rungs of the ladder (300)                               */
+    int    verdict_mode;  /* PSDP_VERDICT_*                                          */
+    int    precision;     /* PSDP_PREC_*                                             */
+    void*  stream;        /* hipStream_t, NULL = null stream                         */
+    int    record_history;/* 1: fill psdp_result.history (host memory, caller owns)  */
+} psdp_opts;
+
+typedef struct {
+    int    iter;
+    double phi, psi, gap_rel, pinf, dinf, mu, tp, td;
+} psdp_iter_rec;
+
+typedef struct {
+    int     verdict;        /* PSDP_FEASIBLE / INFEASIBLE / UNKNOWN                  */
+    int     reason;         /* exit reason of the paper's SDP run (PSDP_R_*)         */
+    double* P;              /* caller buffer [L0][n][n] or NULL: the coefficients P_h */
+    double* y;              /* caller buffer [K] or NULL: the dual variable          */
+    double  phi, psi;       /* primal tr(CX) and dual a^T y objectives               */
+    double  gap_abs, gap_rel, pinf, dinf;
+    double  margin;         /* min_j lambda_min(B^T(y)_j) / s_j (certificate check)  */
+    double  margin_P, margin_D;
+    int     iterations;     /* iterations of the paper's SDP run                     */
+    int     phase1_used;
+    int     phase1_iterations;
+    double  t_star;         /* phase-I optimum (normalised margin), NaN if unused    */
+    double  time_solve_s;   /* wall time of the solve call                           */
+    psdp_iter_rec* history; /* caller buffer of history_cap records, or NULL         */
+    int     history_cap;
+    int     history_len;
+} psdp_result;
+
+/* Defaults for the option structs. */
+void psdp_setup_opts_default(psdp_setup_opts* o);
+void psdp_opts_default(psdp_opts* o);
+
+/*
+ * psdp_polya_setup -- Section III, Alg. 1 (set-up): from the coefficients of
+ * A(alpha) build the structured SDP.  Computes on the device, exactly:
+ *   beta_{h,g} = d1! / (g-h)!            (closed form of eq. beta_init/beta)
+ *   c[h][g][lam] = d2! / (g-h-lam)!      (closed form of eq. H_init/H)
+ *   H_{h,g} = sum_lam c[h][g][lam] A_lam (FP64, ascending lam, no contraction)
+ *   s_j, the multinomial block scales, and C_j (eq. C, Cj).
+ * A: [Na][n][n] row-major FP64, Na = card W_da (da = 1: the l vertices).
+ * n in [1, 128], l >= 1, dp >= 0, d >= 0.  Multinomials of degree > 20 are
+ * rejected with PSDP_EOVERFLOW.  *out receives a new handle.
+ */
+int psdp_polya_setup(const double* A, int n, int l, int dp, int d,
+                     const psdp_setup_opts* o, psdp_sdp** out);
+
+/* Sizes of an SDP handle (eq. L0, L, M, K). */
+int psdp_query(const psdp_sdp* sdp, psdp_dims* out);
+
+/*
+ * Copies the exact set-up back to host buffers (any may be NULL):
+ * beta [L0][L] int64, coef [L0][M][Na] int64, H [M][L0][n][n] FP64,
+ * scale [L+M] FP64 (s_j), cdiag [L+M] FP64 (C_j = cdiag_j I).
+ */
+int psdp_get_polya(const psdp_sdp* sdp, int64_t* beta, int64_t* coef, double* H,
+                   double* scale, double* cdiag);
+
+/*
+ * psdp_ipm_solve -- Section IV, Alg. 2: solve the SDP to the requested gap
+ * and return the verdict, P coefficients and duality gap.  The solver is the
+ * predictor-corrector primal-dual method started at X = Z = I, y = 0; the
+ * certificate is accepted only if every block of B^T(y) passes an FP64
+ * Cholesky.  On a stall the phase-I margin SDP decides the verdict.
+ */
+int psdp_ipm_solve(psdp_sdp* sdp, const psdp_opts* opts, psdp_result* res);
+
+/*
+ * Solves count independent SDPs together: every kernel of an iteration
+ * covers all systems still running (systems may differ in n, l, dp, d).
+ * res is an array of count results.  Equivalent, system by system, to
+ * psdp_ipm_solve.
+ */
+int psdp_ipm_solve_batched(psdp_sdp* const* sdps, int count, const psdp_opts* opts,
+                           psdp_result* res);
+
+/*
+ * Hot-path evaluation at a fixed iterate, for parity checks of single steps
+ * (Alg. 2, processors step 1 and root step 1).  Host buffers:
+ *   X, Z: [L+M][n][n] symmetric positive definite blocks; y: [K].
+ * Outputs (any may be NULL):
+ *   Zi    [L+M][n][n]  block inverses Z_j^{-1}
+ *   BTy   [L+M][n][n]  B^T(y)                         (eq. AT)
+ *   BX    [K]          B(X)
+ *   Lam   [K][K]       Schur complement Omega (eq. T2), full symmetric
+ *   LamL  [K][K]       its lower Cholesky factor (upper part zero)
+ *   sol   [K]          Omega^{-1} y
+ * The basis order of the dual variable is the library's (see psdp_basis).
+ */
+int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y,
+                     double* Zi, double* BTy, double* BX, double* Lam, double* LamL,
+                     double* sol, void* stream);
+
+/*
+ * Step-length ladder of the line search on fixed blocks (host buffers
+ * [L+M][n][n]): largest r_k = rho^k (k <= ladder_len) such that
+ * V_j + (r_k / step_frac) dV_j passes Cholesky for every block j.
+ * *step = 0 and *kstar = -1 when some block never passes.
+ */
+int psdp_eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* opts,
+                     double* step, int* kstar);
+
+/*
+ * Basis order of the dual variable: pairs[2*b], pairs[2*b+1] = (p, q), p <= q,
+ * for b < Nt; y index k = b + Nt * h.  The order groups indices in tiles of 8
+ * so that Schur tiles are contiguous.
+ */
+int psdp_basis(const psdp_sdp* sdp, int* pairs);
+
+/* Release a handle (NULL is ignored). */
+void psdp_free(psdp_sdp* sdp);
+
+/* Thread-local description of the last error of this thread. */
+const char* psdp_last_error(void);
+
+/* Library version string. */
+const char* psdp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYAIPM_H */

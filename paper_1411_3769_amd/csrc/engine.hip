@@ -1,0 +1,740 @@
+// Batched interior-point driver (Section IV, Alg. 2) on one GPU.
+//
+// The paper runs Alg. 2 on a root processor plus N ranks that each own a
+// slice of the L+M diagonal blocks and exchange the Schur complement, the
+// right-hand sides and the dual steps by MPI every iteration.  Here all
+// blocks of all systems of a batch live in one HBM arena; every step of the
+// iteration is one kernel launch over the whole batch, the root's sums are
+// in-kernel accumulations, and the only host traffic per iteration is a few
+// scalars per system for the stopping decision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace psdp {
+
+namespace {
+
+struct StepTab {
+  std::vector<int> sys, pre, first, cnt, tot;
+  void add_step() {
+    first.push_back((int)sys.size());
+    cnt.push_back(0);
+    tot.push_back(0);
+  }
+  void add(int s, int count) {
+    sys.push_back(s);
+    pre.push_back(tot.back());
+    cnt.back() += 1;
+    tot.back() += count;
+  }
+};
+
+struct Batch {
+  int S = 0, maxn = 0, nblk = 0, npblk = 0, ndblk = 0, npairs = 0, nq2 = 0, ntiles = 0;
+  int totL0 = 0, totK = 0, maxP = 0;
+  std::vector<psdp_sdp*> sd;
+  std::vector<SysDesc> sys;
+  std::vector<BlkDesc> blk, pblk, dblk;
+  std::vector<HMPair> pairs;
+  std::vector<int64_t> offA1;
+  std::vector<HM2> q2;
+  std::vector<KTerm> terms;
+  std::vector<AsmTile> tiles;
+  std::vector<int> csr_hh, csr_hid, csr_mh, csr_hl;   // per-system sections
+  std::vector<int> csr_hh_off, csr_hid_off, csr_mh_off, csr_hl_off;
+  std::vector<int> gpinfo;
+  std::vector<int64_t> gpoff;
+  std::vector<int> ownP, ownK;
+  StepTab pan, upd, bwd;
+  int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0;
+
+  // device
+  void* dtab = nullptr;
+  double* arena = nullptr;
+  SysDesc* d_sys = nullptr;
+  BlkDesc *d_blk = nullptr, *d_pblk = nullptr, *d_dblk = nullptr;
+  HMPair* d_pairs = nullptr;
+  int64_t* d_offA1 = nullptr;
+  HM2* d_q2 = nullptr;
+  KTerm* d_terms = nullptr;
+  AsmTile* d_tiles = nullptr;
+  int *d_gpinfo = nullptr, *d_ownP = nullptr, *d_ownK = nullptr;
+  int64_t* d_gpoff = nullptr;
+  int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
+  int *d_bwd_sys = nullptr, *d_bwd_pre = nullptr;
+  int* d_flags = nullptr;
+  double* d_sc = nullptr;
+  double* d_red = nullptr;
+  int* d_kout = nullptr;
+  double* d_cert = nullptr;
+  // arena arrays
+  double *X, *Z, *Zi, *G, *S1, *T1, *W1, *dXh, *dZh, *Wc, *dXb, *dZb, *dX, *dZ, *Cf;
+  double *y, *dyh, *dyb, *r, *z, *BX, *rv1, *rv2;
+  double *Lam, *Ldiag, *Pm, *pre;
+
+  ~Batch() {
+    if (dtab) hipFree(dtab);
+    if (arena) hipFree(arena);
+  }
+};
+
+template <class T>
+static int upload(void* base, size_t& off, const std::vector<T>& v, T** dptr) {
+  *dptr = (T*)((char*)base + off);
+  if (!v.empty()) {
+    hipError_t e = hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(PSDP_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
+  }
+  off += (v.size() * sizeof(T) + 255) / 256 * 256;
+  return PSDP_OK;
+}
+
+template <class T>
+static size_t tabsize(const std::vector<T>& v) {
+  return (v.size() * sizeof(T) + 255) / 256 * 256;
+}
+
+// Builds every per-batch table on the host and allocates the arena.
+static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
+  B.S = count;
+  B.sd.assign(sdps, sdps + count);
+  // ---- per-system layout
+  int64_t curblk = 0, curvec = 0, curlam = 0, curdg = 0, curP = 0, curpre = 0;
+  std::vector<std::vector<int64_t>> a1(count), a2(count), ay(count);
+  B.ownP.push_back(0);
+  B.ownK.push_back(0);
+  for (int s = 0; s < count; ++s) {
+    psdp_sdp* p = sdps[s];
+    const int n = p->n;
+    const int64_t nn = (int64_t)n * n;
+    B.maxn = std::max(B.maxn, n);
+    SysDesc d{};
+    d.n = n; d.L0 = p->L0; d.L = p->L; d.M = p->M; d.Nt = p->Nt; d.nb = p->nb;
+    d.K = (int)p->K; d.Kpad = (int)p->Kpad; d.P = d.Kpad / kNB; d.mode = 0;
+    d.blk0 = (int)B.blk.size();
+    d.boff = curblk;
+    for (int j = 0; j < p->nb; ++j) {
+      BlkDesc b{s, j, n, 0, curblk + j * nn};
+      B.blk.push_back(b);
+      (j < p->L ? B.pblk : B.dblk).push_back(b);
+    }
+    curblk += p->nb * nn;
+    d.voff = curvec; curvec += d.Kpad;
+    d.loff = curlam; curlam += (int64_t)d.Kpad * d.Kpad;
+    d.dgoff = curdg; curdg += (int64_t)d.P * kNB * kNB;
+    d.poff = curP; curP += p->L0 * nn;
+    d.H = p->dH; d.betaf = p->dbetaf; d.cdiag = p->dcdiag; d.scale = p->dscale; d.basis = p->dbasis;
+    B.maxP = std::max(B.maxP, d.P);
+    // active (m, h) pairs, in (m, h) order
+    a1[s].assign((size_t)p->M * p->L0, -1);
+    a2[s].assign((size_t)p->M * p->L0, -1);
+    ay[s].assign((size_t)p->M * p->L0, -1);
+    const int pair0 = (int)B.pairs.size();
+    std::vector<std::vector<int>> by_h(p->L0);
+    B.csr_mh_off.push_back((int)B.csr_mh.size());
+    B.csr_hl_off.push_back((int)B.csr_hl.size());
+    int cnt_hl = 0;
+    for (int m = 0; m < p->M; ++m) {
+      B.csr_mh.push_back(cnt_hl);
+      for (int h = 0; h < p->L0; ++h) {
+        if (!p->hmask[m * p->L0 + h]) continue;
+        HMPair hp{s, m, h, n, curpre, curpre + nn};
+        ay[s][m * p->L0 + h] = curpre;
+        a2[s][m * p->L0 + h] = curpre + nn;
+        a1[s][m * p->L0 + h] = curpre + 2 * nn;
+        B.offA1.push_back(curpre + 2 * nn);
+        curpre += 3 * nn;
+        by_h[h].push_back((int)B.pairs.size());
+        B.pairs.push_back(hp);
+        B.csr_hl.push_back(h);
+        ++cnt_hl;
+      }
+    }
+    B.csr_mh.push_back(cnt_hl);
+    B.csr_hh_off.push_back((int)B.csr_hh.size());
+    B.csr_hid_off.push_back((int)B.csr_hid.size());
+    int cnt = 0;
+    for (int h = 0; h < p->L0; ++h) {
+      B.csr_hh.push_back(cnt);
+      for (int id : by_h[h]) B.csr_hid.push_back(id);
+      cnt += (int)by_h[h].size();
+    }
+    B.csr_hh.push_back(cnt);
+    d.npairs_hm = (int)B.pairs.size() - pair0;
+    // Schur pre-products A3/A4 for h <= h2 on every block with both active
+    std::vector<int64_t> a3((size_t)p->M * p->L0 * p->L0, -1), a4 = a3;
+    for (int m = 0; m < p->M; ++m) {
+      for (int h = 0; h < p->L0; ++h) {
+        if (!p->hmask[m * p->L0 + h]) continue;
+        for (int h2 = h; h2 < p->L0; ++h2) {
+          if (!p->hmask[m * p->L0 + h2]) continue;
+          HM2 q{s, m, h, h2, n, 0, curpre, curpre + nn, a1[s][m * p->L0 + h2], a2[s][m * p->L0 + h2]};
+          a3[((size_t)m * p->L0 + h) * p->L0 + h2] = curpre;
+          a4[((size_t)m * p->L0 + h) * p->L0 + h2] = curpre + nn;
+          curpre += 2 * nn;
+          B.q2.push_back(q);
+        }
+      }
+    }
+    // basis group pairs
+    B.gpoff.push_back((int64_t)B.gpinfo.size());
+    const BasisInfo& bi = p->basis;
+    for (int g = 0; g < bi.ngp; ++g) {
+      B.gpinfo.push_back(bi.gp_g1[g]);
+      B.gpinfo.push_back(bi.gp_g2[g]);
+      B.gpinfo.push_back(bi.gp_off[g]);
+      B.gpinfo.push_back(bi.gp_size[g]);
+    }
+    B.sys.push_back(d);
+    B.ownP.push_back(B.ownP.back() + p->L0);
+    B.ownK.push_back(B.ownK.back() + (int)p->K);
+  }
+  B.totblk = curblk;
+  B.totvec = curvec;
+  B.totlam = curlam;
+  B.totdg = curdg;
+  B.totP = curP;
+  B.totpre = curpre;
+  B.nblk = (int)B.blk.size();
+  B.npblk = (int)B.pblk.size();
+  B.ndblk = (int)B.dblk.size();
+  B.npairs = (int)B.pairs.size();
+  B.nq2 = (int)B.q2.size();
+  B.totL0 = B.ownP.back();
+  B.totK = B.ownK.back();
+
+  // ---- arena
+  const int nblkarr = 15, nvec = 8;
+  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + B.totdg + B.totP + B.totpre;
+  if (hipMalloc((void**)&B.arena, std::max<int64_t>(total, 1) * 8) != hipSuccess)
+    return fail(PSDP_ENOMEM, "device allocation of the solver arena failed (" +
+                                 std::to_string(total * 8) + " bytes)");
+  double* a = B.arena;
+  int64_t o = 0;
+  double** blkarrs[nblkarr] = {&B.X, &B.Z, &B.Zi, &B.G, &B.S1, &B.T1, &B.W1, &B.dXh,
+                               &B.dZh, &B.Wc, &B.dXb, &B.dZb, &B.dX, &B.dZ, &B.Cf};
+  for (int i = 0; i < nblkarr; ++i) { *blkarrs[i] = a + o; o += B.totblk; }
+  double** vecs[nvec] = {&B.y, &B.dyh, &B.dyb, &B.r, &B.z, &B.BX, &B.rv1, &B.rv2};
+  for (int i = 0; i < nvec; ++i) { *vecs[i] = a + o; o += B.totvec; }
+  B.Lam = a + o; o += B.totlam;
+  B.Ldiag = a + o; o += B.totdg;
+  B.Pm = a + o; o += B.totP;
+  B.pre = a + o; o += B.totpre;
+  const int64_t preBase = B.pre - a, ziBase = B.Zi - a, xBase = B.X - a;
+  for (auto& hp : B.pairs) { hp.offY += preBase; hp.offA2 += preBase; }
+  for (auto& v : B.offA1) v += preBase;
+  for (auto& q : B.q2) { q.offA3 += preBase; q.offA4 += preBase; q.srcA1 += preBase; q.srcA2 += preBase; }
+
+  // ---- Schur k-lists and tiles
+  for (int s = 0; s < count; ++s) {
+    psdp_sdp* p = sdps[s];
+    const int L0 = p->L0, L = p->L, M = p->M;
+    const int64_t nn = (int64_t)p->n * p->n;
+    const int64_t b0 = B.sys[s].boff;
+    // index of the A3/A4 of (m, h, h2)
+    std::vector<int64_t> a3((size_t)M * L0 * L0, -1), a4 = a3;
+    for (const auto& q : B.q2)
+      if (q.sys == s) {
+        a3[((size_t)q.m * L0 + q.h) * L0 + q.h2] = q.offA3;
+        a4[((size_t)q.m * L0 + q.h) * L0 + q.h2] = q.offA4;
+      }
+    for (int h = 0; h < L0; ++h) {
+      for (int h2 = h; h2 < L0; ++h2) {
+        const int kbeg = (int)B.terms.size();
+        for (int j = 0; j < L; ++j) {
+          if (!p->bmask[h * L + j] || !p->bmask[h2 * L + j]) continue;
+          const double c = p->betaf[h * L + j] * p->betaf[h2 * L + j];
+          B.terms.push_back(KTerm{ziBase + b0 + j * nn, xBase + b0 + j * nn, c, 0, 0});
+        }
+        for (int m = 0; m < M; ++m) {
+          if (!p->hmask[m * L0 + h] || !p->hmask[m * L0 + h2]) continue;
+          const int64_t bm = b0 + (int64_t)(L + m) * nn;
+          const int64_t A1h = a1[s][m * L0 + h] + preBase, A1h2 = a1[s][m * L0 + h2] + preBase;
+          const int64_t A2h = a2[s][m * L0 + h] + preBase, A2h2 = a2[s][m * L0 + h2] + preBase;
+          const int64_t A3 = a3[((size_t)m * L0 + h) * L0 + h2];
+          const int64_t A4 = a4[((size_t)m * L0 + h) * L0 + h2];
+          B.terms.push_back(KTerm{A1h2, A2h, 1.0, 0, 0});         // (Zi H'^T, X H^T)
+          B.terms.push_back(KTerm{ziBase + bm, A3, 1.0, 0, 1});   // (Zi, H' X H^T)
+          B.terms.push_back(KTerm{A4, xBase + bm, 1.0, 0, 0});    // (H Zi H'^T, X)
+          B.terms.push_back(KTerm{A1h, A2h2, 1.0, 1, 1});         // (H Zi, H' X)
+        }
+        const int kcnt = (int)B.terms.size() - kbeg;
+        if (kcnt == 0) continue;   // the tile is zero: filled by the zero pass
+        const int ngp = p->basis.ngp;
+        for (int rg = 0; rg < ngp; ++rg)
+          for (int cg = (h == h2 ? rg : 0); cg < ngp; ++cg)
+            B.tiles.push_back(AsmTile{s, h, h2, rg, cg, kbeg, kcnt, 0});
+      }
+    }
+  }
+  B.ntiles = (int)B.tiles.size();
+
+  // ---- Cholesky step tables
+  for (int pstep = 0; pstep < B.maxP; ++pstep) {
+    B.pan.add_step();
+    B.upd.add_step();
+    B.bwd.add_step();
+    for (int s = 0; s < count; ++s) {
+      const int P = B.sys[s].P;
+      if (P <= pstep) continue;
+      B.pan.add(s, P - pstep);
+      const int T = P - pstep - 1;
+      if (T > 0) B.upd.add(s, T * (T + 1) / 2);
+      B.bwd.add(s, pstep + 1);
+    }
+  }
+
+  // ---- device tables
+  size_t tb = 0;
+  tb += tabsize(B.sys) + tabsize(B.blk) + tabsize(B.pblk) + tabsize(B.dblk) + tabsize(B.pairs);
+  tb += tabsize(B.offA1) + tabsize(B.q2) + tabsize(B.terms) + tabsize(B.tiles) + tabsize(B.gpinfo);
+  tb += tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(B.csr_hh) + tabsize(B.csr_hid);
+  tb += tabsize(B.csr_mh) + tabsize(B.csr_hl);
+  tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
+  tb += tabsize(B.bwd.sys) + tabsize(B.bwd.pre);
+  tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
+  tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 4 + 255) / 256 * 256;
+  tb += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256 + 4096;
+  if (hipMalloc(&B.dtab, tb) != hipSuccess) return fail(PSDP_ENOMEM, "device allocation of tables failed");
+  size_t off = 0;
+  int rc = PSDP_OK;
+  int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl;
+  // the per-system CSR pointers must be patched into SysDesc before upload
+  {
+    char* base = (char*)B.dtab;
+    size_t o2 = tabsize(B.sys) + tabsize(B.blk) + tabsize(B.pblk) + tabsize(B.dblk) + tabsize(B.pairs) +
+                tabsize(B.offA1) + tabsize(B.q2) + tabsize(B.terms) + tabsize(B.tiles) +
+                tabsize(B.gpinfo) + tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK);
+    d_csr_hh = (int*)(base + o2); o2 += tabsize(B.csr_hh);
+    d_csr_hid = (int*)(base + o2); o2 += tabsize(B.csr_hid);
+    d_csr_mh = (int*)(base + o2); o2 += tabsize(B.csr_mh);
+    d_csr_hl = (int*)(base + o2);
+    for (int s = 0; s < count; ++s) {
+      B.sys[s].hm_by_h = d_csr_hh + B.csr_hh_off[s];
+      B.sys[s].hm_ids = d_csr_hid + B.csr_hid_off[s];
+      B.sys[s].h_by_m = d_csr_mh + B.csr_mh_off[s];
+      B.sys[s].h_list = d_csr_hl + B.csr_hl_off[s];
+    }
+  }
+  if ((rc = upload(B.dtab, off, B.sys, &B.d_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.blk, &B.d_blk))) return rc;
+  if ((rc = upload(B.dtab, off, B.pblk, &B.d_pblk))) return rc;
+  if ((rc = upload(B.dtab, off, B.dblk, &B.d_dblk))) return rc;
+  if ((rc = upload(B.dtab, off, B.pairs, &B.d_pairs))) return rc;
+  if ((rc = upload(B.dtab, off, B.offA1, &B.d_offA1))) return rc;
+  if ((rc = upload(B.dtab, off, B.q2, &B.d_q2))) return rc;
+  if ((rc = upload(B.dtab, off, B.terms, &B.d_terms))) return rc;
+  if ((rc = upload(B.dtab, off, B.tiles, &B.d_tiles))) return rc;
+  if ((rc = upload(B.dtab, off, B.gpinfo, &B.d_gpinfo))) return rc;
+  if ((rc = upload(B.dtab, off, B.gpoff, &B.d_gpoff))) return rc;
+  if ((rc = upload(B.dtab, off, B.ownP, &B.d_ownP))) return rc;
+  if ((rc = upload(B.dtab, off, B.ownK, &B.d_ownK))) return rc;
+  int* tmp;
+  if ((rc = upload(B.dtab, off, B.csr_hh, &tmp))) return rc;
+  if ((rc = upload(B.dtab, off, B.csr_hid, &tmp))) return rc;
+  if ((rc = upload(B.dtab, off, B.csr_mh, &tmp))) return rc;
+  if ((rc = upload(B.dtab, off, B.csr_hl, &tmp))) return rc;
+  if ((rc = upload(B.dtab, off, B.pan.sys, &B.d_pan_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.pan.pre, &B.d_pan_pre))) return rc;
+  if ((rc = upload(B.dtab, off, B.upd.sys, &B.d_upd_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.upd.pre, &B.d_upd_pre))) return rc;
+  if ((rc = upload(B.dtab, off, B.bwd.sys, &B.d_bwd_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.bwd.pre, &B.d_bwd_pre))) return rc;
+  char* base = (char*)B.dtab;
+  B.d_flags = (int*)(base + off); off += ((size_t)B.S * 4 + 255) / 256 * 256;
+  B.d_sc = (double*)(base + off); off += ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
+  B.d_red = (double*)(base + off); off += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256;
+  B.d_kout = (int*)(base + off); off += ((size_t)B.nblk * 4 + 255) / 256 * 256;
+  B.d_cert = (double*)(base + off); off += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256;
+  return PSDP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator helpers
+// ---------------------------------------------------------------------------
+
+static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out) {
+  launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, yv, B.Pm);
+  launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out);
+  launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
+}
+
+// W must be symmetric (callers symmetrise first; B(W) = B(sym W)).
+static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double asub) {
+  launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
+  launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
+                  out, asub);
+}
+
+static void op_schur(Batch& B, hipStream_t st) {
+  launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1);
+  launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena);
+  launch_assemble(st, B.ntiles, B.d_tiles, B.d_terms, B.d_sys, B.d_flags, B.d_gpinfo, B.arena,
+                  B.Lam, B.d_gpoff);
+}
+
+static void op_factor(Batch& B, hipStream_t st) {
+  for (int p = 0; p < B.maxP; ++p) {
+    const int f = B.pan.first[p];
+    launch_chol_panel(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.d_pan_sys + f, B.d_pan_pre + f,
+                      B.pan.cnt[p], B.pan.tot[p], p);
+    if (B.upd.tot[p] > 0) {
+      const int g = B.upd.first[p];
+      launch_chol_update(st, B.d_sys, B.d_flags, B.Lam, B.d_upd_sys + g, B.d_upd_pre + g,
+                         B.upd.cnt[p], B.upd.tot[p], p);
+    }
+  }
+}
+
+static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
+  PSDP_HIP(hipMemcpyAsync(B.r, rhs, B.totvec * 8, hipMemcpyDeviceToDevice, st));
+  for (int p = 0; p < B.maxP; ++p) {
+    const int f = B.pan.first[p];
+    launch_trsv_fwd(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.r, B.z, B.d_pan_sys + f,
+                    B.d_pan_pre + f, B.pan.cnt[p], B.pan.tot[p], p);
+  }
+  for (int p = B.maxP - 1; p >= 0; --p) {
+    const int f = B.bwd.first[p];
+    launch_trsv_bwd(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.z, x, B.d_bwd_sys + f,
+                    B.d_bwd_pre + f, B.bwd.cnt[p], B.bwd.tot[p], p);
+  }
+  return PSDP_OK;
+}
+
+// identity blocks, C blocks, zeroed Schur matrices with identity padding
+static int init_state(Batch& B, hipStream_t st) {
+  std::vector<double> eye(B.totblk, 0.0), cf(B.totblk, 0.0);
+  for (const auto& b : B.blk) {
+    const double c = B.sd[b.sys]->cdiag_h[b.j];
+    for (int i = 0; i < b.n; ++i) {
+      eye[b.off + (int64_t)i * b.n + i] = 1.0;
+      cf[b.off + (int64_t)i * b.n + i] = c;
+    }
+  }
+  PSDP_HIP(hipMemcpyAsync(B.X, eye.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.Z, eye.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.Cf, cf.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemsetAsync(B.y, 0, B.totvec * 8 * 8, st));   // all eight vectors
+  PSDP_HIP(hipMemsetAsync(B.Lam, 0, B.totlam * 8, st));
+  launch_pad_identity(st, B.S, B.d_sys, B.Lam);
+  PSDP_HIP(hipGetLastError());
+  PSDP_HIP(hipStreamSynchronize(st));
+  return PSDP_OK;
+}
+
+struct RunState {
+  int reason = PSDP_R_MAXITER;
+  int iterations = 0;
+  bool running = true;
+  std::vector<double> dinf_hist;
+  double phi = NAN, psi = NAN, gap_abs = NAN, gap_rel = NAN, pinf = NAN, dinf = NAN;
+};
+
+static void set_flags(Batch& B, const std::vector<RunState>& rs, std::vector<int>& hf) {
+  hf.assign(B.S, 0);
+  for (int s = 0; s < B.S; ++s)
+    if (rs[s].running) hf[s] = F_ACTIVE | F_CHOLSEL;
+}
+
+// One interior-point run of every system marked running.
+static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<RunState>& rs,
+                   std::vector<std::vector<psdp_iter_rec>>* hist) {
+  const int S = B.S;
+  std::vector<int> hf(S);
+  std::vector<double> hsc((size_t)S * kNSC);
+  const int stall_w = 10;
+  for (int it = 0;; ++it) {
+    set_flags(B, rs, hf);
+    // flags carry the failure bits set by the previous iteration's kernels;
+    // read them before resetting.
+    std::vector<int> prev(S);
+    PSDP_HIP(hipMemcpyAsync(prev.data(), B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+    if (it > 0) {
+      for (int s = 0; s < S; ++s) {
+        if (!rs[s].running) continue;
+        if (prev[s] & F_LAMFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_CHOL; }
+        else if (prev[s] & F_LADDERFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_LADDER; }
+      }
+      set_flags(B, rs, hf);
+    }
+    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), S * 4, hipMemcpyHostToDevice, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+    launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
+    op_BT(B, st, B.y, B.S1);
+    launch_make_G(st, B.nblk, B.d_blk, B.d_flags, B.Cf, B.S1, B.Z, B.G);
+    op_B(B, st, B.X, B.BX, 0.0);
+    launch_block_red(st, B.nblk, B.d_blk, B.d_flags, B.Cf, B.X, B.Z, B.G, B.d_red);
+    launch_sys_finalize(st, S, B.d_sys, B.d_flags, B.d_red, B.y, B.BX, o.sigma, B.d_sc);
+    PSDP_HIP(hipGetLastError());
+    PSDP_HIP(hipMemcpyAsync(hsc.data(), B.d_sc, hsc.size() * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipMemcpyAsync(prev.data(), B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    for (int s = 0; s < S; ++s) {
+      RunState& r = rs[s];
+      if (!r.running) continue;
+      const double* v = hsc.data() + (size_t)s * kNSC;
+      r.phi = v[S_PHI]; r.psi = v[S_PSI]; r.gap_abs = v[S_GAPABS]; r.gap_rel = v[S_GAPREL];
+      r.pinf = v[S_PINF]; r.dinf = v[S_DINF];
+      r.iterations = it;
+      r.dinf_hist.push_back(r.dinf);
+      if (hist) (*hist)[s].push_back(psdp_iter_rec{it, r.phi, r.psi, r.gap_rel, r.pinf, r.dinf, v[S_MU], 0, 0});
+      const bool finite = std::isfinite(r.phi) && std::isfinite(r.psi) && std::isfinite(r.pinf) &&
+                          std::isfinite(r.dinf) && std::isfinite(v[S_TRZX]);
+      if ((prev[s] & F_ZFAIL) || !finite) { r.running = false; r.reason = PSDP_R_NONFINITE; continue; }
+      if (r.gap_rel <= o.gap_tol && r.pinf <= o.feas_tol && r.dinf <= o.feas_tol) {
+        r.running = false; r.reason = PSDP_R_CONVERGED; continue;
+      }
+      if (r.phi > 0 && v[S_NORMBX] / r.phi <= 1e-6) { r.running = false; r.reason = PSDP_R_FARKAS; continue; }
+      if (it >= stall_w && r.dinf > o.feas_tol && r.dinf > 0.1 * r.dinf_hist[it - stall_w]) {
+        r.running = false; r.reason = PSDP_R_STALL; continue;
+      }
+      if (it >= o.max_iter) { r.running = false; r.reason = PSDP_R_MAXITER; continue; }
+      any = true;
+    }
+    if (!any) break;
+    set_flags(B, rs, hf);
+    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), S * 4, hipMemcpyHostToDevice, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+    // ---- Newton system (Alg. 2 processors/root step 1)
+    op_schur(B, st);
+    op_factor(B, st);
+    // Omega_1 = B(Z^-1 G X) - a
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.G, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.W1, 1.0, -1, nullptr, 0.0, -1);
+    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
+    op_B(B, st, B.W1, B.rv1, 1.0);
+    op_solve(B, st, B.rv1, B.dyh);
+    // predictor directions (processors step 2)
+    op_BT(B, st, B.dyh, B.S1);
+    launch_axpby(st, B.nblk, B.d_blk, B.d_flags, -1.0, B.G, 1.0, B.S1, B.dZh);
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.dZh, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.dXh, -1.0, -1, B.X, -1.0, -1);
+    // corrector right-hand side: W = mu Z^-1 - Z^-1 dZ^ dX^
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.dXh, 0, B.Wc, -1.0, -1, B.Zi, 1.0, S_MU);
+    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.Wc, B.W1);
+    op_B(B, st, B.W1, B.rv2, 0.0);
+    op_solve(B, st, B.rv2, B.dyb);
+    // corrector directions (processors step 3)
+    op_BT(B, st, B.dyb, B.dZb);
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.dZb, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.dXb, -1.0, -1, B.Wc, 1.0, -1);
+    launch_combine(st, B.nblk, B.d_blk, B.d_flags, B.dXh, B.dXb, B.dX, B.dZh, B.dZb, B.dZ);
+    // step lengths and update
+    launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
+    launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TP, B.d_sc);
+    launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.dZ, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
+    launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TD, B.d_sc);
+    launch_update_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.X, B.dX, B.Z, B.dZ);
+    launch_update_y(st, S, B.d_sys, B.d_flags, B.d_sc, B.y, B.dyh, B.dyb);
+    PSDP_HIP(hipGetLastError());
+    if (hist) {
+      PSDP_HIP(hipMemcpyAsync(hsc.data(), B.d_sc, hsc.size() * 8, hipMemcpyDeviceToHost, st));
+      PSDP_HIP(hipStreamSynchronize(st));
+      for (int s = 0; s < S; ++s)
+        if (rs[s].running && !(*hist)[s].empty()) {
+          (*hist)[s].back().tp = hsc[(size_t)s * kNSC + S_TP];
+          (*hist)[s].back().td = hsc[(size_t)s * kNSC + S_TD];
+        }
+    }
+  }
+  return PSDP_OK;
+}
+
+static void validate_opts(const psdp_opts* in, psdp_opts& o) {
+  psdp_opts_default(&o);
+  if (in) o = *in;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res) {
+  auto t0 = std::chrono::steady_clock::now();
+  psdp_opts o;
+  validate_opts(opts, o);
+  if (!(o.gap_tol > 0) || !(o.feas_tol > 0) || o.max_iter < 0 || !(o.sigma > 0 && o.sigma < 1) ||
+      !(o.step_frac > 0 && o.step_frac <= 1) || !(o.ladder_rho > 0 && o.ladder_rho < 1) ||
+      o.ladder_len < 0)
+    return fail(PSDP_EINVAL, "invalid solver options");
+  if (o.verdict_mode < 0 || o.verdict_mode > 2) return fail(PSDP_EINVAL, "invalid verdict_mode");
+  hipStream_t st = (hipStream_t)o.stream;
+  Batch B;
+  int rc = build_batch(B, sdps, count);
+  if (rc) return rc;
+  if ((rc = init_state(B, st))) return rc;
+  std::vector<RunState> rs(count);
+  std::vector<std::vector<psdp_iter_rec>> hist(count);
+  if ((rc = run_ipm(B, o, st, rs, o.record_history ? &hist : nullptr))) return rc;
+
+  // certificate check of converged systems: Q = B^T(y), block Cholesky, margins
+  std::vector<int> hf(count, 0);
+  bool anyconv = false;
+  for (int s = 0; s < count; ++s)
+    if (rs[s].reason == PSDP_R_CONVERGED) { hf[s] = F_ACTIVE; anyconv = true; }
+  std::vector<double> cert((size_t)B.nblk * 2, 0.0);
+  if (anyconv) {
+    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), count * 4, hipMemcpyHostToDevice, st));
+    op_BT(B, st, B.y, B.S1);
+    launch_certificate(st, B.nblk, B.maxn, B.d_blk, B.d_sys, B.d_flags, B.S1, 60, B.d_cert);
+    PSDP_HIP(hipGetLastError());
+    PSDP_HIP(hipMemcpyAsync(cert.data(), B.d_cert, cert.size() * 8, hipMemcpyDeviceToHost, st));
+  }
+  std::vector<double> hy(B.totvec);
+  PSDP_HIP(hipMemcpyAsync(hy.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
+  PSDP_HIP(hipStreamSynchronize(st));
+  const double elapsed =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int s = 0; s < count; ++s) {
+    psdp_sdp* p = sdps[s];
+    const SysDesc& d = B.sys[s];
+    psdp_result& R = res[s];
+    const RunState& r = rs[s];
+    R.reason = r.reason;
+    R.iterations = r.iterations;
+    R.phi = r.phi; R.psi = r.psi; R.gap_abs = r.gap_abs; R.gap_rel = r.gap_rel;
+    R.pinf = r.pinf; R.dinf = r.dinf;
+    R.margin = R.margin_P = R.margin_D = NAN;
+    R.phase1_used = 0;
+    R.phase1_iterations = 0;
+    R.t_star = NAN;
+    R.time_solve_s = elapsed;
+    R.history_len = 0;
+    if (R.history && R.history_cap > 0) {
+      const int nrec = std::min<int>(R.history_cap, (int)hist[s].size());
+      std::memcpy(R.history, hist[s].data(), nrec * sizeof(psdp_iter_rec));
+      R.history_len = nrec;
+    }
+    const double* ys = hy.data() + d.voff;
+    if (r.reason == PSDP_R_CONVERGED) {
+      bool pass = true;
+      double mg = INFINITY, mP = INFINITY, mD = INFINITY;
+      for (int j = 0; j < d.nb; ++j) {
+        const double* c = cert.data() + (size_t)(d.blk0 + j) * 2;
+        pass = pass && c[0] != 0.0;
+        mg = std::min(mg, c[1]);
+        if (j < d.L) mP = std::min(mP, c[1]); else mD = std::min(mD, c[1]);
+      }
+      R.margin = mg; R.margin_P = mP; R.margin_D = mD;
+      R.verdict = pass ? PSDP_FEASIBLE : PSDP_UNKNOWN;
+    } else if (r.reason == PSDP_R_FARKAS) {
+      R.verdict = PSDP_INFEASIBLE;
+    } else {
+      R.verdict = PSDP_UNKNOWN;
+    }
+    if (R.y) std::memcpy(R.y, ys, d.K * sizeof(double));
+    if (R.P) {
+      const int n = p->n;
+      const bool keep = R.verdict == PSDP_FEASIBLE;
+      for (int h = 0; h < p->L0; ++h)
+        for (int b = 0; b < p->Nt; ++b) {
+          const int pp = p->basis.pairs[2 * b], qq = p->basis.pairs[2 * b + 1];
+          const double v = keep ? ys[(int64_t)h * p->Nt + b] : 0.0;
+          R.P[((int64_t)h * n + pp) * n + qq] = v;
+          R.P[((int64_t)h * n + qq) * n + pp] = v;
+        }
+    }
+  }
+  return PSDP_OK;
+}
+
+int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y, double* Zi,
+                double* BTy, double* BX, double* Lam, double* LamL, double* sol, hipStream_t st) {
+  Batch B;
+  int rc = build_batch(B, &sdp, 1);
+  if (rc) return rc;
+  if ((rc = init_state(B, st))) return rc;
+  const SysDesc& d = B.sys[0];
+  const int64_t nb = sdp->nb, nn = (int64_t)sdp->n * sdp->n;
+  PSDP_HIP(hipMemcpyAsync(B.X, X, nb * nn * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.Z, Z, nb * nn * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.y, y, d.K * 8, hipMemcpyHostToDevice, st));
+  const int one = F_ACTIVE | F_CHOLSEL;
+  PSDP_HIP(hipMemcpyAsync(B.d_flags, &one, 4, hipMemcpyHostToDevice, st));
+  launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
+  op_BT(B, st, B.y, B.S1);
+  op_B(B, st, B.X, B.BX, 0.0);
+  op_schur(B, st);
+  PSDP_HIP(hipGetLastError());
+  if (Zi) PSDP_HIP(hipMemcpyAsync(Zi, B.Zi, nb * nn * 8, hipMemcpyDeviceToHost, st));
+  if (BTy) PSDP_HIP(hipMemcpyAsync(BTy, B.S1, nb * nn * 8, hipMemcpyDeviceToHost, st));
+  if (BX) PSDP_HIP(hipMemcpyAsync(BX, B.BX, d.K * 8, hipMemcpyDeviceToHost, st));
+  std::vector<double> full((size_t)d.Kpad * d.Kpad);
+  if (Lam) {
+    PSDP_HIP(hipMemcpyAsync(full.data(), B.Lam, full.size() * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < d.K; ++i) std::memcpy(Lam + (int64_t)i * d.K, full.data() + (int64_t)i * d.Kpad, d.K * 8);
+  }
+  op_factor(B, st);
+  op_solve(B, st, B.y, B.dyh);
+  PSDP_HIP(hipGetLastError());
+  if (LamL) {
+    std::vector<double> dg((size_t)d.P * kNB * kNB);
+    PSDP_HIP(hipMemcpyAsync(full.data(), B.Lam, full.size() * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipMemcpyAsync(dg.data(), B.Ldiag, dg.size() * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < d.K; ++i)
+      for (int j = 0; j < d.K; ++j) {
+        double v = 0.0;
+        if (j <= i) {
+          const int ti = i / kNB, tj = j / kNB;
+          v = (ti == tj) ? dg[(size_t)ti * kNB * kNB + (i % kNB) * kNB + (j % kNB)]
+                         : full[(size_t)i * d.Kpad + j];
+        }
+        LamL[(int64_t)i * d.K + j] = v;
+      }
+  }
+  if (sol) PSDP_HIP(hipMemcpyAsync(sol, B.dyh, d.K * 8, hipMemcpyDeviceToHost, st));
+  int fl = 0;
+  PSDP_HIP(hipMemcpyAsync(&fl, B.d_flags, 4, hipMemcpyDeviceToHost, st));
+  PSDP_HIP(hipStreamSynchronize(st));
+  if (fl & F_ZFAIL) return fail(PSDP_ENUMERIC, "Z is not positive definite");
+  if (fl & F_LAMFAIL) return fail(PSDP_ENUMERIC, "the Schur complement is not positive definite");
+  return PSDP_OK;
+}
+
+int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* opts,
+                double* step, int* kstar) {
+  psdp_opts o;
+  validate_opts(opts, o);
+  hipStream_t st = (hipStream_t)o.stream;
+  Batch B;
+  int rc = build_batch(B, &sdp, 1);
+  if (rc) return rc;
+  const int64_t nb = sdp->nb, nn = (int64_t)sdp->n * sdp->n;
+  PSDP_HIP(hipMemcpyAsync(B.X, V, nb * nn * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.dX, dV, nb * nn * 8, hipMemcpyHostToDevice, st));
+  const int one = F_ACTIVE;
+  PSDP_HIP(hipMemcpyAsync(B.d_flags, &one, 4, hipMemcpyHostToDevice, st));
+  launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac,
+                o.ladder_len, B.d_kout);
+  launch_ladder_step(st, B.d_sys, 1, B.d_flags, B.d_kout, o.ladder_rho, S_TP, B.d_sc);
+  PSDP_HIP(hipGetLastError());
+  std::vector<int> k(B.nblk);
+  double t = 0;
+  PSDP_HIP(hipMemcpyAsync(k.data(), B.d_kout, B.nblk * 4, hipMemcpyDeviceToHost, st));
+  PSDP_HIP(hipMemcpyAsync(&t, B.d_sc + S_TP, 8, hipMemcpyDeviceToHost, st));
+  PSDP_HIP(hipStreamSynchronize(st));
+  int km = 0;
+  for (int v : k) {
+    if (v < 0) { km = -1; break; }
+    km = std::max(km, v);
+  }
+  *kstar = km;
+  *step = km < 0 ? 0.0 : t;
+  return PSDP_OK;
+}
+
+}  // namespace psdp

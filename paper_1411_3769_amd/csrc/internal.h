@@ -1,0 +1,157 @@
+// Internal declarations of libpolyaipm: handle layout, device descriptors of
+// a batch, and launch wrappers shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "polyaipm.h"
+
+namespace psdp {
+
+constexpr int kMaxN = 128;   // largest block order held whole in LDS (128 KB)
+constexpr int kTB = 8;       // index-group size of the tiled basis
+constexpr int kNB = 64;      // Schur Cholesky tile
+constexpr int kMaxDeg = 20;  // largest multinomial degree (20! < 2^63)
+constexpr int kNSC = 24;     // per-system scalar slots
+
+// per-system scalar slots (double array sc[sys * kNSC + slot])
+enum Slot {
+  S_PHI = 0, S_PSI, S_TRZX, S_PINF, S_DINF, S_GAPABS, S_GAPREL, S_MU, S_TP, S_TD,
+  S_NORMBX, S_ONE, S_MINUS_ONE, S_TLAST, S_STT, S_NORMC, S_NORMA, S_DIAGMAX, S_TAU,
+};
+
+// per-system flag bits (int array flags[sys])
+enum Flag {
+  F_ACTIVE = 1,       // takes part in the current iteration
+  F_ZFAIL = 2,        // a block of Z failed Cholesky
+  F_LAMFAIL = 4,      // the Schur matrix failed Cholesky
+  F_LADDERFAIL = 8,   // the step ladder ran out
+  F_CHOLSEL = 16,     // selected for the (re)factorisation pass
+};
+
+struct SysDesc {
+  int n, L0, L, M, Nt, nb, P, mode;   // P = Kpad / kNB; mode 0 paper SDP, 1 phase-I
+  int K, Kpad, blk0, npairs_hm;
+  int64_t boff;     // block arena offset (doubles) of the system's first block
+  int64_t voff;     // vector offset (Kpad entries per vector)
+  int64_t loff;     // Schur matrix offset (Kpad * Kpad)
+  int64_t poff;     // P_h scratch offset (L0 * n * n)
+  int64_t dgoff;    // factored diagonal tiles of the Schur matrix (P * 64 * 64)
+  const double* H;      // [M][L0][n][n]
+  const double* betaf;  // [L0][L]
+  const double* cdiag;  // [L+M]
+  const double* scale;  // [L+M]
+  const int* basis;     // [Nt][2] tiled basis (p, q)
+  const int* hm_by_h;   // CSR of active (m,h) pair ids, per h: [L0 + 1] offsets ...
+  const int* hm_ids;    // ... into this list of global pair ids
+  const int* h_by_m;    // CSR per derivative block m: [M + 1] offsets ...
+  const int* h_list;    // ... into this list of h with H_{h,m} != 0
+};
+
+struct BlkDesc {
+  int sys, j, n, pad;
+  int64_t off;      // arena offset of the block (same for every block array)
+};
+
+// one active (m, h) pair: H_{h,m} != 0
+struct HMPair {
+  int sys, m, h, n;
+  int64_t offY;     // scratch for H W (B operator)
+  int64_t offA2;    // pre-product A2 = X H^T (A1 = Z^-1 H^T lives in a side table)
+};
+
+// one active (m, h, h2) with h <= h2 for the Schur pre-products
+struct HM2 {
+  int sys, m, h, h2, n, pad;
+  int64_t offA3, offA4;   // H_h X H_h2^T and H_h Z^-1 H_h2^T
+  int64_t srcA1, srcA2;   // A1[m][h2], A2[m][h2]
+};
+
+// one term of the Schur expansion for a pair (h, h2): the Kronecker factor
+// T[b,c] U[d,a] summed over the symmetric components.
+struct KTerm {
+  int64_t offT, offU;   // arena offsets
+  double coef;          // multiplies T
+  int tT, tU;           // 1 = read transposed
+};
+
+struct AsmTile {
+  int sys, h, h2, rg, cg, kbeg, kcnt, pad;
+};
+
+// host-side list of group pairs of the tiled basis for one n
+struct BasisInfo {
+  int n, NG, ngp;
+  std::vector<int> pairs;      // [Nt][2]
+  std::vector<int> gp_g1, gp_g2, gp_off, gp_size;
+};
+
+BasisInfo make_basis(int n);
+
+}  // namespace psdp
+
+struct psdp_sdp {
+  int n, l, da, dp, d1, d2;
+  int L0, L, M, Na, Nt, nb;
+  int64_t K, Kpad;
+  double delta, eps;
+  int paper_literal;
+  std::vector<int> Wp, WL, WM, Wa;   // exponent tables [count][l]
+  std::vector<uint8_t> bmask;        // [L0][L] beta_{h,j} != 0
+  std::vector<uint8_t> hmask;        // [M][L0] H_{h,m} != 0
+  psdp::BasisInfo basis;
+  std::vector<double> betaf;         // host copies of the device set-up
+  std::vector<double> cdiag_h, scale_h;
+  int device;
+  void* dmem;
+  size_t dbytes;
+  double* dA;
+  int64_t* dbeta;
+  int64_t* dcoef;
+  double* dH;
+  double* dbetaf;
+  double* dscale;
+  double* dcdiag;
+  int* dbasis;
+};
+
+namespace psdp {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define PSDP_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return ::psdp::fail(PSDP_EDEVICE, std::string(#call) + ": " +           \
+                                            hipGetErrorString(e_));          \
+  } while (0)
+
+int64_t round_up(int64_t x, int64_t m);
+
+// Schur Cholesky / triangular solve launches (chol.hip)
+void launch_chol_panel(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
+                       const int* ssys, const int* spre, int cnt, int total, int p);
+void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
+                        const int* ssys, const int* spre, int cnt, int total, int p);
+void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
+                     const double* Ldiag, double* r, double* z, const int* ssys, const int* spre,
+                     int cnt, int total, int p);
+void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
+                     const double* Ldiag, double* z, double* x, const int* ssys, const int* spre,
+                     int cnt, int total, int p);
+
+// engine entry used by the public solve / eval calls
+int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res);
+int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y, double* Zi,
+                double* BTy, double* BX, double* Lam, double* LamL, double* sol,
+                hipStream_t stream);
+int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* o,
+                double* step, int* kstar);
+
+}  // namespace psdp

@@ -1,0 +1,62 @@
+// Launch wrappers of the per-iteration kernels (kernels.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace psdp {
+
+void launch_cholinv(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, int* flags,
+                    const double* Z, double* Zi);
+void launch_ladder(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, const int* flags,
+                   const double* V, const double* dV, double rho, double frac, int len, int* kout);
+void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,
+                        double rho, int slot, double* sc);
+void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                        const double* sc, const double* A, int tA, const double* B, int tB,
+                        double* C, double alpha, int aslot, const double* D, double beta,
+                        int bslot);
+void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                   const double* Cf, const double* S, const double* Z, double* G);
+void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
+                  const double* A, double b, const double* B, double* out);
+void launch_symmetrize(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                       const double* W, double* out);
+void launch_combine(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                    const double* dXh, const double* dXb, double* dX, const double* dZh,
+                    const double* dZb, double* dZ);
+void launch_update_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                          const double* sc, double* X, const double* dX, double* Z,
+                          const double* dZ);
+void launch_update_y(hipStream_t st, int S, const SysDesc* sys, const int* flags,
+                     const double* sc, double* y, const double* dyh, const double* dyb);
+void launch_block_red(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                      const double* Cf, const double* X, const double* Z, const double* G,
+                      double* red);
+void launch_sys_finalize(hipStream_t st, int S, const SysDesc* sys, const int* flags,
+                         const double* red, const double* y, const double* BX, double sigma,
+                         double* sc);
+void launch_form_P(hipStream_t st, int total, const SysDesc* sys, const int* flags,
+                   const int* own_pre, int S, const double* y, double* Pm);
+void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* sys,
+                    const int* flags, const double* Pm, double* out);
+void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
+                    const int* flags, const double* Pm, double* out);
+void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
+                const int* flags, const double* W, double* arena, const BlkDesc* blks);
+void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
+                     const int* own_pre, int S, const HMPair* pairs, const double* W,
+                     const double* arena, const BlkDesc* blks, double* out, double asub);
+void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
+                  const int* flags, const double* Zi, const double* X, double* arena,
+                  const BlkDesc* blks, const int64_t* offA1);
+void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, const int* flags,
+                  double* arena);
+void launch_assemble(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
+                     const SysDesc* sys, const int* flags, const int* gpinfo,
+                     const double* arena, double* Lam, const int64_t* gpoff);
+void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam);
+void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
+                        const SysDesc* sys, const int* flags, const double* Q, int iters,
+                        double* out);
+
+}  // namespace psdp

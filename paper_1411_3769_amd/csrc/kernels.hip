@@ -1,0 +1,800 @@
+// Per-iteration kernels of the interior-point method (Section IV, Alg. 2)
+// over a batch of systems: block factorisations, the operators B and B^T
+// (eq. AT with eq. Aij), the Schur complement assembly (eq. T2) and the
+// step-length ladder.  Every block kernel runs one workgroup per n x n block
+// of every system still active; blocks of all systems share one arena
+// layout, so X, Z, Z^{-1}, G, ... of block b all live at blk[b].off.
+#include <hip/hip_runtime.h>
+
+#include "devcommon.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace psdp {
+
+#define ACTIVE_OR_RETURN(s) \
+  if (!(flags[(s)] & F_ACTIVE)) return
+
+// Z_j -> Z_j^{-1} = L^{-T} L^{-1} through the in-LDS Cholesky factor.
+__global__ void __launch_bounds__(256) k_cholinv(const BlkDesc* __restrict__ blks, int* flags,
+                                                 const double* __restrict__ Z, double* Zi) {
+  extern __shared__ double sm[];
+  __shared__ int fl;
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const int n = bd.n, nn = n * n;
+  const double* Zb = Z + bd.off;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) sm[e] = Zb[e];
+  if (threadIdx.x == 0) fl = 0;
+  __syncthreads();
+  wg_potrf(sm, n, n, &fl);
+  if (threadIdx.x == 0 && fl) atomicOr(&flags[bd.sys], F_ZFAIL);
+  wg_trtri_lower(sm, n, n);
+  double* out = Zi + bd.off;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    if (j < i) continue;
+    double acc = 0.0;
+    for (int k = j; k < n; ++k) acc += sm[k * n + i] * sm[k * n + j];
+    out[i * n + j] = acc;
+    out[j * n + i] = acc;
+  }
+}
+
+// Step-length ladder (reading of the paper's "standard line-search" that
+// keeps X and Z positive semidefinite): r_0 = 1, r_{k+1} = rho r_k; block b
+// records the first k at which V_b + (r_k / frac) dV_b passes Cholesky, -1
+// if none up to len.  The trial matrix is formed with a separate multiply
+// and add.
+__global__ void __launch_bounds__(256) k_ladder(const BlkDesc* __restrict__ blks,
+                                                const int* __restrict__ flags,
+                                                const double* __restrict__ V,
+                                                const double* __restrict__ dV, double rho,
+                                                double frac, int len, int* kout) {
+  extern __shared__ double sm[];
+  __shared__ int fl;
+  const BlkDesc bd = blks[blockIdx.x];
+  if (!(flags[bd.sys] & F_ACTIVE)) {
+    if (threadIdx.x == 0) kout[blockIdx.x] = 0;
+    return;
+  }
+  const int n = bd.n, nn = n * n;
+  const double* Vb = V + bd.off;
+  const double* dVb = dV + bd.off;
+  double r = 1.0;
+  int found = -1;
+  for (int k = 0; k <= len; ++k) {
+    const double t = r / frac;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) sm[e] = __dadd_rn(Vb[e], __dmul_rn(t, dVb[e]));
+    if (threadIdx.x == 0) fl = 0;
+    __syncthreads();
+    wg_potrf(sm, n, n, &fl);
+    const int f = fl;
+    __syncthreads();
+    if (!f) {
+      found = k;
+      break;
+    }
+    r = r * rho;
+  }
+  if (threadIdx.x == 0) kout[blockIdx.x] = found;
+}
+
+// Per system: k* = max over blocks of the first passing rung; the step is
+// r_{k*} (repeated multiplication, as the oracle does).
+__global__ void k_ladder_step(const SysDesc* __restrict__ sys, int S, int* flags,
+                              const int* __restrict__ kout, double rho, int slot, double* sc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  if (!(flags[s] & F_ACTIVE)) return;
+  const SysDesc sd = sys[s];
+  int kmax = 0;
+  bool bad = false;
+  for (int j = 0; j < sd.nb; ++j) {
+    const int k = kout[sd.blk0 + j];
+    if (k < 0) bad = true;
+    kmax = k > kmax ? k : kmax;
+  }
+  double r = 1.0;
+  for (int k = 0; k < kmax; ++k) r = r * rho;
+  if (bad) {
+    flags[s] |= F_LADDERFAIL;
+    r = 0.0;
+  }
+  sc[s * kNSC + slot] = r;
+}
+
+// C_b = a op(A_b) op(B_b) + c D_b with a = alpha * sc[aslot], c = beta * sc[bslot]
+// (slots < 0 mean 1).
+__global__ void __launch_bounds__(256) k_gemm_blocks(const BlkDesc* __restrict__ blks,
+                                                     const int* __restrict__ flags,
+                                                     const double* __restrict__ sc,
+                                                     const double* A, int tA, const double* B,
+                                                     int tB, double* C, double alpha, int aslot,
+                                                     const double* D, double beta, int bslot) {
+  __shared__ double sA[16 * 64];
+  __shared__ double sB[16 * 64];
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  double a = alpha, c = beta;
+  if (aslot >= 0) a *= sc[bd.sys * kNSC + aslot];
+  if (bslot >= 0) c *= sc[bd.sys * kNSC + bslot];
+  wg_gemm(bd.n, A + bd.off, tA, B + bd.off, tB, C + bd.off, a, D ? D + bd.off : nullptr, c, sA, sB);
+}
+
+// G = C - S + Z (eq. G with S = B^T(y))
+__global__ void k_make_G(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+                         const double* __restrict__ Cf, const double* __restrict__ S,
+                         const double* __restrict__ Z, double* G) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const int nn = bd.n * bd.n;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int64_t o = bd.off + e;
+    G[o] = Cf[o] - S[o] + Z[o];
+  }
+}
+
+// out = a * A + b * B (elementwise over blocks)
+__global__ void k_axpby(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+                        double a, const double* __restrict__ A, double b,
+                        const double* __restrict__ B, double* out) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const int nn = bd.n * bd.n;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int64_t o = bd.off + e;
+    out[o] = a * A[o] + b * B[o];
+  }
+}
+
+// out = (W + W^T) / 2 (out may alias W: each thread owns the pair (i,j),(j,i))
+__global__ void k_symmetrize(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+                             const double* W, double* out) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const int n = bd.n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    if (j < i) continue;
+    const double v = 0.5 * (W[bd.off + i * n + j] + W[bd.off + j * n + i]);
+    out[bd.off + i * n + j] = v;
+    out[bd.off + j * n + i] = v;
+  }
+}
+
+// dX = sym(dXh + dXb), dZ = dZh + dZb
+__global__ void k_combine(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+                          const double* __restrict__ dXh, const double* __restrict__ dXb,
+                          double* dX, const double* __restrict__ dZh,
+                          const double* __restrict__ dZb, double* dZ) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const int n = bd.n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    const int64_t o = bd.off + e, ot = bd.off + j * n + i;
+    const double sij = dXh[o] + dXb[o];
+    const double sji = dXh[ot] + dXb[ot];
+    dX[o] = 0.5 * (sij + sji);
+    dZ[o] = dZh[o] + dZb[o];
+  }
+}
+
+// X += tp dX, Z += td dZ (skipped when the Newton system or ladder failed)
+__global__ void k_update_blocks(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+                                const double* __restrict__ sc, double* X,
+                                const double* __restrict__ dX, double* Z,
+                                const double* __restrict__ dZ) {
+  const BlkDesc bd = blks[blockIdx.x];
+  const int f = flags[bd.sys];
+  if (!(f & F_ACTIVE) || (f & (F_LAMFAIL | F_LADDERFAIL))) return;
+  const double tp = sc[bd.sys * kNSC + S_TP], td = sc[bd.sys * kNSC + S_TD];
+  const int nn = bd.n * bd.n;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int64_t o = bd.off + e;
+    X[o] = X[o] + tp * dX[o];
+    Z[o] = Z[o] + td * dZ[o];
+  }
+}
+
+// y += td (dyh + dyb)
+__global__ void k_update_y(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
+                           const double* __restrict__ sc, double* y,
+                           const double* __restrict__ dyh, const double* __restrict__ dyb) {
+  const int s = blockIdx.x;
+  const int f = flags[s];
+  if (!(f & F_ACTIVE) || (f & (F_LAMFAIL | F_LADDERFAIL))) return;
+  const SysDesc sd = sys[s];
+  const double td = sc[s * kNSC + S_TD];
+  for (int k = threadIdx.x; k < sd.K; k += blockDim.x) {
+    const int64_t o = sd.voff + k;
+    const double d = dyh[o] + dyb[o];
+    y[o] = y[o] + td * d;
+  }
+}
+
+// per-block partial sums: <C,X>, <Z,X>, ||G||^2, ||C||^2
+__global__ void __launch_bounds__(256) k_block_red(const BlkDesc* __restrict__ blks,
+                                                   const int* __restrict__ flags,
+                                                   const double* __restrict__ Cf,
+                                                   const double* __restrict__ X,
+                                                   const double* __restrict__ Z,
+                                                   const double* __restrict__ G, double* red) {
+  __shared__ double s4[4][256];
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const int nn = bd.n * bd.n;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int64_t o = bd.off + e;
+    a0 += Cf[o] * X[o];
+    a1 += Z[o] * X[o];
+    a2 += G[o] * G[o];
+    a3 += Cf[o] * Cf[o];
+  }
+  s4[0][threadIdx.x] = a0;
+  s4[1][threadIdx.x] = a1;
+  s4[2][threadIdx.x] = a2;
+  s4[3][threadIdx.x] = a3;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) s4[q][threadIdx.x] += s4[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) red[blockIdx.x * 4 + threadIdx.x] = s4[threadIdx.x][0];
+}
+
+__device__ inline double wg_sum256(double v, double* sbuf) {
+  sbuf[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sbuf[threadIdx.x] += sbuf[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sbuf[0];
+  __syncthreads();
+  return r;
+}
+
+// Per system: objectives, residual norms, gaps and mu (fixed summation order).
+__global__ void __launch_bounds__(256) k_sys_finalize(const SysDesc* __restrict__ sys,
+                                                      const int* __restrict__ flags,
+                                                      const double* __restrict__ red,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ BX,
+                                                      double sigma, double* sc) {
+  __shared__ double sb[256];
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  double c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  for (int j = threadIdx.x; j < sd.nb; j += blockDim.x) {
+    const double* r = red + (int64_t)(sd.blk0 + j) * 4;
+    c0 += r[0];
+    c1 += r[1];
+    c2 += r[2];
+    c3 += r[3];
+  }
+  const double phi = wg_sum256(c0, sb);
+  const double trzx = wg_sum256(c1, sb);
+  const double g2 = wg_sum256(c2, sb);
+  const double cc2 = wg_sum256(c3, sb);
+  double py = 0, pr = 0, pb = 0, pa = 0;
+  for (int k = threadIdx.x; k < sd.K; k += blockDim.x) {
+    const double yk = y[sd.voff + k], bk = BX[sd.voff + k];
+    double ak;
+    if (sd.mode == 0) ak = 1.0; else ak = (k == sd.K - 1) ? -1.0 : 0.0;
+    py += ak * yk;
+    pr += (bk - ak) * (bk - ak);
+    pb += bk * bk;
+    pa += ak * ak;
+  }
+  const double psi = wg_sum256(py, sb);
+  const double rr = wg_sum256(pr, sb);
+  const double bb = wg_sum256(pb, sb);
+  const double aa = wg_sum256(pa, sb);
+  if (threadIdx.x == 0) {
+    double* o = sc + s * kNSC;
+    o[S_PHI] = phi;
+    o[S_PSI] = psi;
+    o[S_TRZX] = trzx;
+    o[S_PINF] = sqrt(rr) / (1.0 + sqrt(aa));
+    o[S_DINF] = sqrt(g2) / (1.0 + sqrt(cc2));
+    o[S_GAPABS] = fabs(psi - phi);
+    const double den = fmax(fabs(psi), fabs(phi));
+    o[S_GAPREL] = den > 0 ? fabs(psi - phi) / den : fabs(psi - phi);
+    o[S_NORMBX] = sqrt(bb);
+    o[S_MU] = sigma * trzx / (double)(sd.nb * sd.n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// operators
+// ---------------------------------------------------------------------------
+
+// P_h = V_h(y): one workgroup per (system, h); grid = sum_s L0_s (owner table)
+__global__ void k_form_P(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
+                         const int* __restrict__ own_pre, int S, const double* __restrict__ y,
+                         double* Pm) {
+  const int s = find_owner(own_pre, S, blockIdx.x);
+  const int h = blockIdx.x - own_pre[s];
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  const int n = sd.n;
+  double* P = Pm + sd.poff + (int64_t)h * n * n;
+  const double* yh = y + sd.voff + (int64_t)h * sd.Nt;
+  for (int b = threadIdx.x; b < sd.Nt; b += blockDim.x) {
+    const int p = sd.basis[2 * b], q = sd.basis[2 * b + 1];
+    const double v = yh[b];
+    P[p * n + q] = v;
+    P[q * n + p] = v;
+  }
+}
+
+// P-blocks of B^T(y): out_j = sum_h beta_{h,j} P_h (ascending h)
+__global__ void k_BT_pblk(const BlkDesc* __restrict__ pblks, const SysDesc* __restrict__ sys,
+                          const int* __restrict__ flags, const double* __restrict__ Pm,
+                          double* out) {
+  const BlkDesc bd = pblks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const SysDesc sd = sys[bd.sys];
+  const int nn = bd.n * bd.n;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    double acc = 0.0;
+    for (int h = 0; h < sd.L0; ++h) {
+      const double b = sd.betaf[h * sd.L + bd.j];
+      if (b != 0.0) acc += b * Pm[sd.poff + (int64_t)h * nn + e];
+    }
+    out[bd.off + e] = acc;
+  }
+}
+
+// derivative blocks of B^T(y): Q = sum_h P_h H_{h,m} over the h with
+// H_{h,m} != 0 (gamma_m >= h); out = -(Q + Q^T)
+__global__ void __launch_bounds__(256) k_BT_dblk(const BlkDesc* __restrict__ dblks,
+                                                 const SysDesc* __restrict__ sys,
+                                                 const int* __restrict__ flags,
+                                                 const double* __restrict__ Pm, double* out) {
+  __shared__ double sA[16 * 64];
+  __shared__ double sB[16 * 64];
+  const BlkDesc bd = dblks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const SysDesc sd = sys[bd.sys];
+  const int n = bd.n, nn = n * n;
+  const int m = bd.j - sd.L;
+  double* O = out + bd.off;
+  const int c0 = sd.h_by_m[m], c1 = sd.h_by_m[m + 1];
+  if (c0 == c1) {
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) O[e] = 0.0;
+    return;
+  }
+  for (int c = c0; c < c1; ++c) {
+    const int h = sd.h_list[c];
+    const double* Hm = sd.H + ((int64_t)m * sd.L0 + h) * nn;
+    wg_gemm(n, Pm + sd.poff + (int64_t)h * nn, 0, Hm, 0, O, 1.0, c == c0 ? nullptr : O, 1.0, sA, sB);
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    if (j < i) continue;
+    const double v = -(O[i * n + j] + O[j * n + i]);
+    O[i * n + j] = v;
+    O[j * n + i] = v;
+  }
+}
+
+// B operator, first stage: Y = H_{h,m} W_{L+m} for every active (m, h) pair
+__global__ void __launch_bounds__(256) k_B_Y(const HMPair* __restrict__ pairs,
+                                             const SysDesc* __restrict__ sys,
+                                             const int* __restrict__ flags,
+                                             const double* __restrict__ W, double* arena,
+                                             const BlkDesc* __restrict__ blks) {
+  __shared__ double sA[16 * 64];
+  __shared__ double sB[16 * 64];
+  const HMPair pr = pairs[blockIdx.x];
+  ACTIVE_OR_RETURN(pr.sys);
+  const SysDesc sd = sys[pr.sys];
+  const int n = pr.n, nn = n * n;
+  const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
+  const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
+  wg_gemm(n, Hm, 0, W + bd.off, 0, arena + pr.offY, 1.0, nullptr, 0.0, sA, sB);
+}
+
+// B operator, second stage: one thread per (system, k = (h, b)):
+// out_k = sum_{j<L} beta_{h,j} <E_b, W_j> - 2 sum_m <E_b, Y_{m,h}> - a_k * asub
+// (W symmetric).  Grid over sum_s K_s (owner table of prefixes).
+__global__ void k_B_reduce(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
+                           const int* __restrict__ own_pre, int S, const HMPair* __restrict__ pairs,
+                           const double* __restrict__ W, const double* __restrict__ arena,
+                           const BlkDesc* __restrict__ blks, double* out, double asub) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = find_owner(own_pre, S, g);
+  const SysDesc sd = sys[s];
+  const int k = g - own_pre[s];
+  if (k >= sd.K) return;
+  ACTIVE_OR_RETURN(s);
+  const int n = sd.n;
+  const int h = k / sd.Nt, b = k % sd.Nt;
+  const int p = sd.basis[2 * b], q = sd.basis[2 * b + 1];
+  const int e1 = p * n + q, e2 = q * n + p;
+  double acc = 0.0;
+  for (int j = 0; j < sd.L; ++j) {
+    const double bt = sd.betaf[h * sd.L + j];
+    if (bt == 0.0) continue;
+    const double* Wj = W + blks[sd.blk0 + j].off;
+    acc += bt * (p == q ? Wj[e1] : Wj[e1] + Wj[e2]);
+  }
+  double dsum = 0.0;
+  for (int c = sd.hm_by_h[h]; c < sd.hm_by_h[h + 1]; ++c) {
+    const double* Y = arena + pairs[sd.hm_ids[c]].offY;
+    dsum += (p == q ? Y[e1] : Y[e1] + Y[e2]);
+  }
+  acc -= 2.0 * dsum;
+  double ak = 1.0;
+  if (sd.mode == 1) ak = (k == sd.K - 1) ? -1.0 : 0.0;
+  out[sd.voff + k] = acc - asub * ak;
+}
+
+// ---------------------------------------------------------------------------
+// Schur complement (Alg. 2 eq. T2) through the rank expansion of each block:
+// with E = e_a e_b^T, E' = e_c e_d^T and H = H_{h,m}, H' = H_{h2,m}
+//   tr((H^T E + E H) Zi (H'^T E' + E' H') X) = sum_t T_t[b,c] U_t[d,a]
+//   (T,U) in {(Zi H'^T, X H^T), (Zi, H' X H^T), (H Zi H'^T, X), (H Zi, H' X)},
+// and P-blocks give beta_{h,j} beta_{h2,j} Zi[b,c] X[d,a].
+// ---------------------------------------------------------------------------
+
+// A1 = Z^{-1}_m H_h^T, A2 = X_m H_h^T
+__global__ void __launch_bounds__(256) k_pre12(const HMPair* __restrict__ pairs,
+                                               const SysDesc* __restrict__ sys,
+                                               const int* __restrict__ flags,
+                                               const double* __restrict__ Zi,
+                                               const double* __restrict__ X, double* arena,
+                                               const BlkDesc* __restrict__ blks,
+                                               const int64_t* __restrict__ offA1) {
+  __shared__ double sA[16 * 64];
+  __shared__ double sB[16 * 64];
+  const HMPair pr = pairs[blockIdx.x];
+  ACTIVE_OR_RETURN(pr.sys);
+  const SysDesc sd = sys[pr.sys];
+  const int n = pr.n, nn = n * n;
+  const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
+  const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
+  wg_gemm(n, Zi + bd.off, 0, Hm, 1, arena + offA1[blockIdx.x], 1.0, nullptr, 0.0, sA, sB);
+  __syncthreads();
+  wg_gemm(n, X + bd.off, 0, Hm, 1, arena + pr.offA2, 1.0, nullptr, 0.0, sA, sB);
+}
+
+// A3 = H_h A2[m][h2] = H_h X H_h2^T,  A4 = H_h A1[m][h2] = H_h Zi H_h2^T
+__global__ void __launch_bounds__(256) k_pre34(const HM2* __restrict__ q,
+                                               const SysDesc* __restrict__ sys,
+                                               const int* __restrict__ flags, double* arena) {
+  __shared__ double sA[16 * 64];
+  __shared__ double sB[16 * 64];
+  const HM2 pr = q[blockIdx.x];
+  ACTIVE_OR_RETURN(pr.sys);
+  const SysDesc sd = sys[pr.sys];
+  const int n = pr.n, nn = n * n;
+  const double* Hh = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
+  wg_gemm(n, Hh, 0, arena + pr.srcA2, 0, arena + pr.offA3, 1.0, nullptr, 0.0, sA, sB);
+  __syncthreads();
+  wg_gemm(n, Hh, 0, arena + pr.srcA1, 0, arena + pr.offA4, 1.0, nullptr, 0.0, sA, sB);
+}
+
+// One wave per tile of the Schur matrix: rows = the basis pairs (p, q) of row
+// group (g1, g2) of index h, columns = the pairs (r, s) of column group
+// (g3, g4) of index h2.  For every term of the pair's list the wave stages
+// the 16 x 16 pieces T[g1|g2, g3|g4] and U[g3|g4, g1|g2] in LDS; each lane owns
+// one row and accumulates all (up to 64) columns from 64 register values.
+template <bool DIAGC>
+__device__ inline void asm_accumulate(double (&acc)[64], const double* Ts, const double* Us,
+                                      int pL, int qL, bool pq_same) {
+  double Tq[16], Tp[16], Up[16], Uq[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    Tq[c] = Ts[qL * 17 + c];
+    Tp[c] = pq_same ? 0.0 : Ts[pL * 17 + c];
+    Up[c] = Us[c * 17 + pL];
+    Uq[c] = Us[c * 17 + qL];
+  }
+#pragma unroll
+  for (int rL = 0; rL < 8; ++rL) {
+#pragma unroll
+    for (int sI = 0; sI < 8; ++sI) {
+      const int sL = 8 + sI;
+      if (DIAGC) {
+        if (rL > sI) continue;
+        if (rL == sI) {
+          acc[rL * 8 + sI] += Tq[rL] * Up[sL] + Tp[rL] * Uq[sL];
+          continue;
+        }
+      }
+      acc[rL * 8 + sI] += Tq[rL] * Up[sL] + Tq[sL] * Up[rL] + Tp[rL] * Uq[sL] + Tp[sL] * Uq[rL];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64) k_assemble(const AsmTile* __restrict__ tiles,
+                                                 const KTerm* __restrict__ terms,
+                                                 const SysDesc* __restrict__ sys,
+                                                 const int* __restrict__ flags,
+                                                 const int* __restrict__ gpinfo_all,
+                                                 const double* __restrict__ arena,
+                                                 double* Lam, const int64_t* __restrict__ gpoff) {
+  __shared__ double Ts[16 * 17];
+  __shared__ double Us[16 * 17];
+  const AsmTile tl = tiles[blockIdx.x];
+  ACTIVE_OR_RETURN(tl.sys);
+  const SysDesc sd = sys[tl.sys];
+  const int n = sd.n;
+  const int* gp = gpinfo_all + gpoff[tl.sys];   // [ngp][4] = g1, g2, off, size
+  const int g1 = gp[tl.rg * 4 + 0], g2 = gp[tl.rg * 4 + 1];
+  const int roff = gp[tl.rg * 4 + 2], rsize = gp[tl.rg * 4 + 3];
+  const int g3 = gp[tl.cg * 4 + 0], g4 = gp[tl.cg * 4 + 1];
+  const int coff = gp[tl.cg * 4 + 2];
+  const int lane = threadIdx.x;
+  // this lane's row pair
+  int p = 0, q = 0;
+  const bool live = lane < rsize;
+  if (live) {
+    p = sd.basis[2 * (roff + lane)];
+    q = sd.basis[2 * (roff + lane) + 1];
+  }
+  const int pL = p - kTB * g1;
+  const int qL = q - kTB * g2 + 8;
+  const bool pq_same = (p == q);
+  const bool diagc = (g3 == g4);
+  double acc[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) acc[c] = 0.0;
+  for (int t = 0; t < tl.kcnt; ++t) {
+    const KTerm kt = terms[tl.kbeg + t];
+    const double* T = arena + kt.offT;
+    const double* U = arena + kt.offU;
+    for (int e = lane; e < 256; e += 64) {
+      const int a = e >> 4, c = e & 15;
+      const int ra = a < 8 ? kTB * g1 + a : kTB * g2 + (a - 8);
+      const int cc = c < 8 ? kTB * g3 + c : kTB * g4 + (c - 8);
+      double tv = 0.0, uv = 0.0;
+      if (ra < n && cc < n) {
+        tv = kt.tT ? T[cc * n + ra] : T[ra * n + cc];
+        uv = kt.tU ? U[ra * n + cc] : U[cc * n + ra];
+      }
+      Ts[a * 17 + c] = kt.coef * tv;   // T[row a][col c]
+      Us[c * 17 + a] = uv;             // U[col c][row a]
+    }
+    __syncthreads();
+    if (live) {
+      if (diagc)
+        asm_accumulate<true>(acc, Ts, Us, pL, qL, pq_same);
+      else
+        asm_accumulate<false>(acc, Ts, Us, pL, qL, pq_same);
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+  const int64_t ld = sd.Kpad;
+  const int64_t row = (int64_t)tl.h * sd.Nt + roff + lane;
+  const int n3 = min(kTB, n - kTB * g3), n4 = min(kTB, n - kTB * g4);
+  const bool mirror = !(tl.h == tl.h2 && tl.rg == tl.cg);
+  double* Lr = Lam + sd.loff;
+#pragma unroll
+  for (int rL = 0; rL < 8; ++rL) {
+#pragma unroll
+    for (int sI = 0; sI < 8; ++sI) {
+      if (rL >= n3 || sI >= n4) continue;
+      int cidx;
+      if (diagc) {
+        if (rL > sI) continue;
+        cidx = rL * n3 - rL * (rL - 1) / 2 + (sI - rL);
+      } else {
+        cidx = rL * n4 + sI;
+      }
+      const int64_t col = (int64_t)tl.h2 * sd.Nt + coff + cidx;
+      const double v = acc[rL * 8 + sI];
+      Lr[row * ld + col] = v;
+      if (mirror) Lr[col * ld + row] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// certificate: Q_j = B^T(y)_j; pass = Cholesky succeeds; margin_j =
+// lambda_min(Q_j) / s_j by bisection on the Cholesky of Q_j - tau s_j I.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_certificate(const BlkDesc* __restrict__ blks,
+                                                     const SysDesc* __restrict__ sys,
+                                                     const int* __restrict__ flags,
+                                                     const double* __restrict__ Q, int iters,
+                                                     double* out) {
+  extern __shared__ double sm[];
+  __shared__ int fl;
+  __shared__ double fro;
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const SysDesc sd = sys[bd.sys];
+  const int n = bd.n, nn = n * n;
+  const double sj = sd.scale[bd.j];
+  const double* Qb = Q + bd.off;
+  if (threadIdx.x == 0) {
+    double f = 0;
+    for (int e = 0; e < nn; ++e) f += Qb[e] * Qb[e];
+    fro = sqrt(f);
+  }
+  double lo = 0, hi = 0;
+  int pass0 = 0;
+  for (int it = -1; it < iters; ++it) {
+    double tau;
+    if (it < 0) tau = 0.0;
+    else tau = 0.5 * (lo + hi);
+    __syncthreads();
+    const double shift = tau * sj;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      sm[e] = (i == j) ? Qb[e] - shift : Qb[e];
+    }
+    if (threadIdx.x == 0) fl = 0;
+    __syncthreads();
+    wg_potrf(sm, n, n, &fl);
+    const int ok = !fl;
+    __syncthreads();
+    if (it < 0) {
+      pass0 = ok;
+      const double bnd = fro / sj + 1.0;
+      if (ok) { lo = 0.0; hi = bnd; } else { lo = -bnd; hi = 0.0; }
+    } else {
+      if (ok) lo = tau; else hi = tau;
+    }
+  }
+  if (threadIdx.x == 0) {
+    out[blockIdx.x * 2 + 0] = pass0;
+    out[blockIdx.x * 2 + 1] = 0.5 * (lo + hi);
+  }
+}
+
+// Schur matrices: rows/columns past K carry the identity.
+__global__ void k_pad_identity(const SysDesc* __restrict__ sys, double* Lam) {
+  const SysDesc sd = sys[blockIdx.x];
+  for (int i = sd.K + threadIdx.x; i < sd.Kpad; i += blockDim.x)
+    Lam[sd.loff + (int64_t)i * sd.Kpad + i] = 1.0;
+}
+
+// launch wrappers ----------------------------------------------------------------
+
+void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam) {
+  hipLaunchKernelGGL(k_pad_identity, dim3(S), dim3(64), 0, st, sys, Lam);
+}
+
+static void set_lds(const void* f, size_t bytes) {
+  if (bytes > 64 * 1024) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void launch_cholinv(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, int* flags,
+                    const double* Z, double* Zi) {
+  const size_t lds = (size_t)maxn * maxn * 8;
+  set_lds((const void*)k_cholinv, lds);
+  hipLaunchKernelGGL(k_cholinv, dim3(nblk), dim3(256), lds, st, blks, flags, Z, Zi);
+}
+
+void launch_ladder(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, const int* flags,
+                   const double* V, const double* dV, double rho, double frac, int len, int* kout) {
+  const size_t lds = (size_t)maxn * maxn * 8;
+  set_lds((const void*)k_ladder, lds);
+  hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, V, dV, rho, frac, len, kout);
+}
+
+void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,
+                        double rho, int slot, double* sc) {
+  hipLaunchKernelGGL(k_ladder_step, dim3((S + 63) / 64), dim3(64), 0, st, sys, S, flags, kout, rho, slot, sc);
+}
+
+void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                        const double* sc, const double* A, int tA, const double* B, int tB,
+                        double* C, double alpha, int aslot, const double* D, double beta,
+                        int bslot) {
+  hipLaunchKernelGGL(k_gemm_blocks, dim3(nblk), dim3(256), 0, st, blks, flags, sc, A, tA, B, tB, C,
+                     alpha, aslot, D, beta, bslot);
+}
+
+void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                   const double* Cf, const double* S, const double* Z, double* G) {
+  hipLaunchKernelGGL(k_make_G, dim3(nblk), dim3(256), 0, st, blks, flags, Cf, S, Z, G);
+}
+
+void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
+                  const double* A, double b, const double* B, double* out) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblk), dim3(256), 0, st, blks, flags, a, A, b, B, out);
+}
+
+void launch_symmetrize(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                       const double* W, double* out) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(nblk), dim3(256), 0, st, blks, flags, W, out);
+}
+
+void launch_combine(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                    const double* dXh, const double* dXb, double* dX, const double* dZh,
+                    const double* dZb, double* dZ) {
+  hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(256), 0, st, blks, flags, dXh, dXb, dX, dZh, dZb, dZ);
+}
+
+void launch_update_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                          const double* sc, double* X, const double* dX, double* Z,
+                          const double* dZ) {
+  hipLaunchKernelGGL(k_update_blocks, dim3(nblk), dim3(256), 0, st, blks, flags, sc, X, dX, Z, dZ);
+}
+
+void launch_update_y(hipStream_t st, int S, const SysDesc* sys, const int* flags,
+                     const double* sc, double* y, const double* dyh, const double* dyb) {
+  hipLaunchKernelGGL(k_update_y, dim3(S), dim3(256), 0, st, sys, flags, sc, y, dyh, dyb);
+}
+
+void launch_block_red(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                      const double* Cf, const double* X, const double* Z, const double* G,
+                      double* red) {
+  hipLaunchKernelGGL(k_block_red, dim3(nblk), dim3(256), 0, st, blks, flags, Cf, X, Z, G, red);
+}
+
+void launch_sys_finalize(hipStream_t st, int S, const SysDesc* sys, const int* flags,
+                         const double* red, const double* y, const double* BX, double sigma,
+                         double* sc) {
+  hipLaunchKernelGGL(k_sys_finalize, dim3(S), dim3(256), 0, st, sys, flags, red, y, BX, sigma, sc);
+}
+
+void launch_form_P(hipStream_t st, int total, const SysDesc* sys, const int* flags,
+                   const int* own_pre, int S, const double* y, double* Pm) {
+  hipLaunchKernelGGL(k_form_P, dim3(total), dim3(256), 0, st, sys, flags, own_pre, S, y, Pm);
+}
+
+void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* sys,
+                    const int* flags, const double* Pm, double* out) {
+  if (n) hipLaunchKernelGGL(k_BT_pblk, dim3(n), dim3(256), 0, st, pblks, sys, flags, Pm, out);
+}
+
+void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
+                    const int* flags, const double* Pm, double* out) {
+  if (n)
+    hipLaunchKernelGGL(k_BT_dblk, dim3(n), dim3(256), 0, st, dblks, sys, flags, Pm, out);
+}
+
+void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
+                const int* flags, const double* W, double* arena, const BlkDesc* blks) {
+  if (np) hipLaunchKernelGGL(k_B_Y, dim3(np), dim3(256), 0, st, pairs, sys, flags, W, arena, blks);
+}
+
+void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
+                     const int* own_pre, int S, const HMPair* pairs, const double* W,
+                     const double* arena, const BlkDesc* blks, double* out, double asub) {
+  hipLaunchKernelGGL(k_B_reduce, dim3((totalK + 255) / 256), dim3(256), 0, st, sys, flags, own_pre,
+                     S, pairs, W, arena, blks, out, asub);
+}
+
+void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
+                  const int* flags, const double* Zi, const double* X, double* arena,
+                  const BlkDesc* blks, const int64_t* offA1) {
+  if (np)
+    hipLaunchKernelGGL(k_pre12, dim3(np), dim3(256), 0, st, pairs, sys, flags, Zi, X, arena, blks, offA1);
+}
+
+void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, const int* flags,
+                  double* arena) {
+  if (nq) hipLaunchKernelGGL(k_pre34, dim3(nq), dim3(256), 0, st, q, sys, flags, arena);
+}
+
+void launch_assemble(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
+                     const SysDesc* sys, const int* flags, const int* gpinfo,
+                     const double* arena, double* Lam, const int64_t* gpoff) {
+  if (ntiles)
+    hipLaunchKernelGGL(k_assemble, dim3(ntiles), dim3(64), 0, st, tiles, terms, sys, flags, gpinfo,
+                       arena, Lam, gpoff);
+}
+
+void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
+                        const SysDesc* sys, const int* flags, const double* Q, int iters,
+                        double* out) {
+  const size_t lds = (size_t)maxn * maxn * 8;
+  set_lds((const void*)k_certificate, lds);
+  hipLaunchKernelGGL(k_certificate, dim3(nblk), dim3(256), lds, st, blks, sys, flags, Q, iters, out);
+}
+
+}  // namespace psdp

@@ -1,0 +1,327 @@
+"""Python binding of libpolyaipm.so (argument marshalling only).
+
+Every step of the set-up and of the solver runs in the HIP library; this
+module converts arrays, fills the C option structs and unpacks results.  It
+raises if the shared library has not been built (there is no CPU fallback).
+
+Functions mirror the C ABI in include/polyaipm.h:
+    polya_setup(A, n, l, dp, d, ...)      -> SDP handle (psdp_polya_setup)
+    SDP.dims / SDP.get_polya() / SDP.basis()
+    ipm_solve(sdp, **opts)               -> Result (psdp_ipm_solve)
+    ipm_solve_batched([sdp, ...], **opts) -> [Result] (psdp_ipm_solve_batched)
+    eval_newton(sdp, X, Z, y)            -> dict (psdp_eval_newton)
+    eval_ladder(sdp, V, dV, **opts)      -> (step, kstar) (psdp_eval_ladder)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolyaipm.so")
+
+FEASIBLE, INFEASIBLE, UNKNOWN = 0, 1, 2
+VERDICTS = {0: "FEASIBLE", 1: "INFEASIBLE", 2: "UNKNOWN"}
+REASONS = ["converged", "farkas", "stall", "max_iter", "ladder_fail", "chol_fail", "nonfinite"]
+VERDICT_MODES = {"paper_then_phase1": 0, "paper_only": 1, "phase1_only": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+ERRORS = {-1: "EINVAL", -2: "EOVERFLOW", -3: "ENOMEM", -4: "EDEVICE", -5: "ENUMERIC"}
+
+DP = C.POINTER(C.c_double)
+
+
+class SetupOpts(C.Structure):
+    _fields_ = [("da", C.c_int), ("d1", C.c_int), ("d2", C.c_int), ("delta", C.c_double),
+                ("eps", C.c_double), ("paper_literal", C.c_int), ("a_on_device", C.c_int)]
+
+
+class Dims(C.Structure):
+    _fields_ = [(k, C.c_int) for k in ("n", "l", "da", "dp", "d1", "d2", "L0", "L", "M", "Na", "Nt")] + \
+               [("K", C.c_int64), ("Kpad", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("gap_tol", C.c_double), ("feas_tol", C.c_double), ("max_iter", C.c_int),
+                ("sigma", C.c_double), ("step_frac", C.c_double), ("ladder_rho", C.c_double),
+                ("ladder_len", C.c_int), ("verdict_mode", C.c_int), ("precision", C.c_int),
+                ("stream", C.c_void_p), ("record_history", C.c_int)]
+
+
+class IterRec(C.Structure):
+    _fields_ = [("iter", C.c_int)] + [(k, C.c_double) for k in
+                                      ("phi", "psi", "gap_rel", "pinf", "dinf", "mu", "tp", "td")]
+
+
+class CResult(C.Structure):
+    _fields_ = [("verdict", C.c_int), ("reason", C.c_int), ("P", DP), ("y", DP),
+                ("phi", C.c_double), ("psi", C.c_double), ("gap_abs", C.c_double),
+                ("gap_rel", C.c_double), ("pinf", C.c_double), ("dinf", C.c_double),
+                ("margin", C.c_double), ("margin_P", C.c_double), ("margin_D", C.c_double),
+                ("iterations", C.c_int), ("phase1_used", C.c_int), ("phase1_iterations", C.c_int),
+                ("t_star", C.c_double), ("time_solve_s", C.c_double),
+                ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int)]
+
+
+class PsdpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "psdp_query",
+           "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_eval_newton",
+           "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version"]
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1411_3769_amd.build`")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.psdp_setup_opts_default.argtypes = [C.POINTER(SetupOpts)]
+    lib.psdp_setup_opts_default.restype = None
+    lib.psdp_opts_default.argtypes = [C.POINTER(Opts)]
+    lib.psdp_opts_default.restype = None
+    lib.psdp_polya_setup.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.POINTER(SetupOpts), C.POINTER(vp)]
+    lib.psdp_query.argtypes = [vp, C.POINTER(Dims)]
+    lib.psdp_get_polya.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.psdp_ipm_solve.argtypes = [vp, C.POINTER(Opts), C.POINTER(CResult)]
+    lib.psdp_ipm_solve_batched.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(Opts), C.POINTER(CResult)]
+    lib.psdp_eval_newton.argtypes = [vp] * 10 + [vp]
+    lib.psdp_eval_ladder.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int)]
+    lib.psdp_basis.argtypes = [vp, vp]
+    lib.psdp_free.argtypes = [vp]
+    lib.psdp_free.restype = None
+    lib.psdp_last_error.restype = C.c_char_p
+    lib.psdp_version.restype = C.c_char_p
+    for name in ("psdp_polya_setup", "psdp_query", "psdp_get_polya", "psdp_ipm_solve",
+                 "psdp_ipm_solve_batched", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PsdpError(rc, load().psdp_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class SDP:
+    """Handle of one structured SDP (psdp_polya_setup)."""
+
+    def __init__(self, handle: int, dims: Dims):
+        self._h = C.c_void_p(handle)
+        d = dims
+        self.n, self.l, self.da, self.dp, self.d1, self.d2 = d.n, d.l, d.da, d.dp, d.d1, d.d2
+        self.L0, self.L, self.M, self.Na, self.Nt = d.L0, d.L, d.M, d.Na, d.Nt
+        self.K, self.Kpad, self.device_bytes = int(d.K), int(d.Kpad), int(d.device_bytes)
+
+    @property
+    def nb(self):
+        return self.L + self.M
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get_polya(self):
+        beta = np.zeros((self.L0, self.L), np.int64)
+        coef = np.zeros((self.L0, self.M, self.Na), np.int64)
+        H = np.zeros((self.M, self.L0, self.n, self.n))
+        scale = np.zeros(self.nb)
+        cdiag = np.zeros(self.nb)
+        _check(load().psdp_get_polya(self._h, _ptr(beta), _ptr(coef), _ptr(H), _ptr(scale), _ptr(cdiag)))
+        return dict(beta=beta, coef=coef, H=H, scale=scale, cdiag=cdiag)
+
+    def basis(self) -> np.ndarray:
+        pairs = np.zeros((self.Nt, 2), np.int32)
+        _check(load().psdp_basis(self._h, _ptr(pairs)))
+        return pairs
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().psdp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def polya_setup(A, n: int, l: int, dp: int, d: int, *, da: int = 1, d1: Optional[int] = None,
+                d2: Optional[int] = None, delta: float = 1e-3, eps: float = 1e-3,
+                paper_literal: bool = False) -> SDP:
+    """psdp_polya_setup.  A: [Na][n][n] FP64 host array, or a torch CUDA tensor
+    (then read on the device)."""
+    lib = load()
+    o = SetupOpts()
+    lib.psdp_setup_opts_default(C.byref(o))
+    o.da = da
+    o.d1 = -1 if d1 is None else d1
+    o.d2 = -1 if d2 is None else d2
+    o.delta, o.eps, o.paper_literal = delta, eps, int(paper_literal)
+    keep = None
+    if hasattr(A, "is_cuda") and A.is_cuda:
+        import torch
+        keep = A.to(torch.float64).contiguous()
+        o.a_on_device = 1
+        aptr = C.c_void_p(keep.data_ptr())
+    else:
+        keep = np.ascontiguousarray(A, dtype=np.float64)
+        aptr = _ptr(keep)
+    h = C.c_void_p()
+    _check(lib.psdp_polya_setup(aptr, n, l, dp, d, C.byref(o), C.byref(h)))
+    dims = Dims()
+    _check(lib.psdp_query(h, C.byref(dims)))
+    return SDP(h.value, dims)
+
+
+def make_opts(**kw) -> Opts:
+    lib = load()
+    o = Opts()
+    lib.psdp_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "verdict_mode" and isinstance(v, str):
+            v = VERDICT_MODES[v]
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if k == "stream":
+            v = C.c_void_p(v) if isinstance(v, int) else v
+        setattr(o, k, v)
+    if "stream" not in kw:
+        o.stream = _current_stream()
+    return o
+
+
+@dataclass
+class Result:
+    verdict: int
+    reason: int
+    P: np.ndarray
+    y: np.ndarray
+    phi: float
+    psi: float
+    gap_abs: float
+    gap_rel: float
+    pinf: float
+    dinf: float
+    margin: float
+    margin_P: float
+    margin_D: float
+    iterations: int
+    phase1_used: bool
+    phase1_iterations: int
+    t_star: float
+    time_solve_s: float
+    history: list = field(default_factory=list)
+
+    @property
+    def verdict_name(self):
+        return VERDICTS[self.verdict]
+
+    @property
+    def reason_name(self):
+        return REASONS[self.reason] if 0 <= self.reason < len(REASONS) else str(self.reason)
+
+
+def _prep(sdp: SDP, cap: int):
+    P = np.zeros((sdp.L0, sdp.n, sdp.n))
+    y = np.zeros(sdp.K)
+    hist = (IterRec * cap)() if cap else None
+    r = CResult()
+    r.P = P.ctypes.data_as(DP)
+    r.y = y.ctypes.data_as(DP)
+    r.history = C.cast(hist, C.POINTER(IterRec)) if cap else C.POINTER(IterRec)()
+    r.history_cap = cap
+    return r, P, y, hist
+
+
+def _unpack(r: CResult, P, y, hist) -> Result:
+    h = []
+    if hist is not None:
+        for i in range(r.history_len):
+            e = hist[i]
+            h.append(dict(iter=e.iter, phi=e.phi, psi=e.psi, gap_rel=e.gap_rel, pinf=e.pinf,
+                          dinf=e.dinf, mu=e.mu, tp=e.tp, td=e.td))
+    return Result(r.verdict, r.reason, P, y, r.phi, r.psi, r.gap_abs, r.gap_rel, r.pinf, r.dinf,
+                  r.margin, r.margin_P, r.margin_D, r.iterations, bool(r.phase1_used),
+                  r.phase1_iterations, r.t_star, r.time_solve_s, h)
+
+
+def ipm_solve(sdp: SDP, **opts) -> Result:
+    o = make_opts(**opts)
+    cap = 512 if o.record_history else 0
+    r, P, y, hist = _prep(sdp, cap)
+    _check(load().psdp_ipm_solve(sdp.handle, C.byref(o), C.byref(r)))
+    return _unpack(r, P, y, hist)
+
+
+def ipm_solve_batched(sdps: Sequence[SDP], **opts) -> List[Result]:
+    o = make_opts(**opts)
+    cap = 512 if o.record_history else 0
+    n = len(sdps)
+    arr = (CResult * n)()
+    keep = []
+    for i, s in enumerate(sdps):
+        r, P, y, hist = _prep(s, cap)
+        arr[i] = r
+        keep.append((P, y, hist))
+    hs = (C.c_void_p * n)(*[s.handle.value for s in sdps])
+    _check(load().psdp_ipm_solve_batched(hs, n, C.byref(o), arr))
+    return [_unpack(arr[i], *keep[i]) for i in range(n)]
+
+
+def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, stream=None) -> dict:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    nb, n, K = sdp.nb, sdp.n, sdp.K
+    out = dict(Zi=np.zeros((nb, n, n)), BTy=np.zeros((nb, n, n)), BX=np.zeros(K),
+               Lam=np.zeros((K, K)), LamL=np.zeros((K, K)), sol=np.zeros(K))
+    st = stream if stream is not None else _current_stream()
+    _check(load().psdp_eval_newton(sdp.handle, _ptr(X), _ptr(Z), _ptr(y), _ptr(out["Zi"]),
+                                   _ptr(out["BTy"]), _ptr(out["BX"]), _ptr(out["Lam"]),
+                                   _ptr(out["LamL"]), _ptr(out["sol"]), st))
+    return out
+
+
+def eval_ladder(sdp: SDP, V: np.ndarray, dV: np.ndarray, **opts):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    dV = np.ascontiguousarray(dV, dtype=np.float64)
+    o = make_opts(**opts)
+    step = C.c_double()
+    k = C.c_int()
+    _check(load().psdp_eval_ladder(sdp.handle, _ptr(V), _ptr(dV), C.byref(o), C.byref(step), C.byref(k)))
+    return step.value, k.value
+
+
+def version() -> str:
+    return load().psdp_version().decode()

@@ -1,0 +1,55 @@
+"""Writes the oracle's end points for the seeded parity workloads.
+
+    python tests/golden/make_oracle_results.py
+
+Calls only oracle/ (and the seeded input generators).  Output:
+tests/golden/oracle_results.json with, per case, the verdict, objectives,
+duality gap, the certificate margins and the phase-I optimum, which the GPU
+parity tests compare against.
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import ipm, sdp as S  # noqa: E402
+from paper_1411_3769_amd import workloads as W  # noqa: E402
+
+
+def run(sy):
+    sdp = S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d)
+    t = time.time()
+    r = ipm.ipm_solve(sdp)
+    return dict(tag=sy.tag, seed=sy.seed, n=sy.n, l=sy.l, dp=sy.dp, d=sy.d,
+                verdict=ipm.VERDICT_NAMES[r.verdict], reason=ipm.REASON_NAMES[r.reason],
+                iterations=r.iterations, phi=r.phi, psi=r.psi, gap_rel=r.gap_rel, pinf=r.pinf,
+                dinf=r.dinf, margin=r.margin, margin_P=r.margin_P, margin_D=r.margin_D,
+                phase1_used=r.phase1_used, phase1_iterations=r.phase1_iterations,
+                t_star=r.t_star, seconds=time.time() - t)
+
+
+def main():
+    cases = []
+    for s in range(16):
+        cases.append(W.plain_system(s))
+        cases.append(W.plain_system(s, twin=True))
+    for s in range(64):
+        cases.append(W.c1_system(s))
+    for (n, l) in [(4, 5), (5, 6), (7, 8)]:
+        cases.append(W.paper_shape_system(n, l, 0))
+    out = []
+    for sy in cases:
+        rec = run(sy)
+        out.append(rec)
+        print(rec["tag"], rec["seed"], rec["verdict"], rec["iterations"], f"{rec['seconds']:.2f}s",
+              flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_results.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

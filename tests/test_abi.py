@@ -1,0 +1,91 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/polyaipm.h, and rejects invalid input before any device
+call (no compute call is made here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "polyaipm.h")
+
+
+def _lib():
+    from paper_1411_3769_amd import polyaipm
+    if not os.path.exists(polyaipm.LIB_PATH):
+        pytest.skip("libpolyaipm.so not built")
+    return polyaipm
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(psdp_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared()
+    for must in ("psdp_polya_setup", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_query",
+                 "psdp_get_polya", "psdp_free", "psdp_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    P = _lib()
+    lib = C.CDLL(P.LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+    assert set(P.EXPORTS) <= set(declared())
+
+
+def test_version_and_defaults():
+    P = _lib()
+    assert "gfx950" in P.version()
+    o = P.make_opts(stream=None)
+    assert o.gap_tol == 1e-8 and o.max_iter == 100 and abs(o.sigma - 1 / 3) < 1e-15
+    assert o.ladder_rho == 0.9 and o.step_frac == 0.95 and o.ladder_len == 300
+
+
+@pytest.mark.parametrize("args,code,frag", [
+    (dict(n=0), -1, "n must be"),
+    (dict(n=129), -1, "n must be"),
+    (dict(l=0), -1, "l must be"),
+    (dict(dp=-1), -1, "negative degree"),
+    (dict(d=20), -2, "above 20"),
+    (dict(nan=True), -1, "non-finite"),
+])
+def test_setup_validation(args, code, frag):
+    P = _lib()
+    n, l, dp, d = args.get("n", 3), args.get("l", 2), args.get("dp", 1), args.get("d", 1)
+    A = np.zeros((max(l, 1), max(n, 1), max(n, 1)))
+    if args.get("nan"):
+        A[0, 0, 0] = np.nan
+    with pytest.raises(P.PsdpError) as ei:
+        P.polya_setup(A, n, l, dp, d)
+    assert ei.value.code == code
+    assert frag in str(ei.value)
+
+
+def test_null_arguments_rejected():
+    P = _lib()
+    lib = P.load()
+    h = C.c_void_p()
+    assert lib.psdp_polya_setup(None, 3, 2, 1, 1, None, C.byref(h)) == -1
+    assert b"NULL" in lib.psdp_last_error()
+    assert lib.psdp_query(None, None) == -1
+    assert lib.psdp_ipm_solve(None, None, None) == -1
+    assert lib.psdp_ipm_solve_batched(None, 0, None, None) == -1
+    lib.psdp_free(None)   # ignored
+
+
+def test_product_path_has_no_cpu_fallback(tmp_path):
+    from paper_1411_3769_amd import polyaipm as P
+    saved = P._lib
+    try:
+        P._lib = None
+        with pytest.raises(ImportError):
+            P.load(str(tmp_path / "missing.so"))
+    finally:
+        P._lib = saved
