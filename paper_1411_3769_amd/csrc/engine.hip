@@ -79,7 +79,9 @@ struct Batch {
   double* d_cert = nullptr;
   // arena arrays
   double *X, *Z, *Zi, *G, *S1, *T1, *W1, *dXh, *dZh, *Wc, *dXb, *dZb, *dX, *dZ, *Cf;
-  double *y, *dyh, *dyb, *r, *z, *BX, *rv1, *rv2;
+  double *y, *dyh, *dyb, *r, *z, *BX, *rv1, *rv2, *ylift, *vtmp;
+  bool any_phase1 = false;
+  int maxK = 0;
   double *Lam, *Ldiag, *Pm, *pre;
 
   ~Batch() {
@@ -198,6 +200,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
     B.sys.push_back(d);
     B.ownP.push_back(B.ownP.back() + p->L0);
     B.ownK.push_back(B.ownK.back() + (int)p->K);
+    B.maxK = std::max(B.maxK, (int)p->K);
   }
   B.totblk = curblk;
   B.totvec = curvec;
@@ -214,7 +217,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   B.totK = B.ownK.back();
 
   // ---- arena
-  const int nblkarr = 15, nvec = 8;
+  const int nblkarr = 15, nvec = 10;
   const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + B.totdg + B.totP + B.totpre;
   if (hipMalloc((void**)&B.arena, std::max<int64_t>(total, 1) * 8) != hipSuccess)
     return fail(PSDP_ENOMEM, "device allocation of the solver arena failed (" +
@@ -224,7 +227,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   double** blkarrs[nblkarr] = {&B.X, &B.Z, &B.Zi, &B.G, &B.S1, &B.T1, &B.W1, &B.dXh,
                                &B.dZh, &B.Wc, &B.dXb, &B.dZb, &B.dX, &B.dZ, &B.Cf};
   for (int i = 0; i < nblkarr; ++i) { *blkarrs[i] = a + o; o += B.totblk; }
-  double** vecs[nvec] = {&B.y, &B.dyh, &B.dyb, &B.r, &B.z, &B.BX, &B.rv1, &B.rv2};
+  double** vecs[nvec] = {&B.y, &B.dyh, &B.dyb, &B.r, &B.z, &B.BX, &B.rv1, &B.rv2, &B.ylift, &B.vtmp};
   for (int i = 0; i < nvec; ++i) { *vecs[i] = a + o; o += B.totvec; }
   B.Lam = a + o; o += B.totlam;
   B.Ldiag = a + o; o += B.totdg;
@@ -363,17 +366,27 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
 // operator helpers
 // ---------------------------------------------------------------------------
 
-static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out) {
-  launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, yv, B.Pm);
+// B^T(y) for every active system; phase-I systems use B'^T (lift + t D).
+static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool phase_aware = true) {
+  const double* ybase = yv;
+  if (phase_aware && B.any_phase1) {
+    launch_lift(st, B.S, B.d_sys, B.d_flags, yv, B.ylift);
+    ybase = B.ylift;
+  }
+  launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, ybase, B.Pm);
   launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out);
   launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
+  if (phase_aware && B.any_phase1) launch_sub_tD(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, yv, out);
 }
 
-// W must be symmetric (callers symmetrise first; B(W) = B(sym W)).
-static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double asub) {
+// B(W) - asub * a; W must be symmetric (callers symmetrise first; B(W) =
+// B(sym W)).  Phase-I systems get B'(W) - asub * a'.
+static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double asub,
+                 bool phase_aware = true) {
   launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
   launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
                   out, asub);
+  if (phase_aware && B.any_phase1) launch_B_phase1(st, B.S, B.d_sys, B.d_flags, B.d_blk, W, out, asub);
 }
 
 static void op_schur(Batch& B, hipStream_t st) {
@@ -381,6 +394,13 @@ static void op_schur(Batch& B, hipStream_t st) {
   launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena);
   launch_assemble(st, B.ntiles, B.d_tiles, B.d_terms, B.d_sys, B.d_flags, B.d_gpinfo, B.arena,
                   B.Lam, B.d_gpoff);
+  if (B.any_phase1) {
+    // phase-I: v = B(D Z^-1 X) and the rank-2 + border transform
+    launch_gemm_scaled(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, B.Zi, B.X, B.W1);
+    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
+    op_B(B, st, B.W1, B.vtmp, 0.0, false);
+    launch_lam_phase1(st, B.S, B.maxK, B.d_sys, B.d_flags, B.d_blk, B.W1, B.vtmp, B.Lam);
+  }
 }
 
 static void op_factor(Batch& B, hipStream_t st) {
@@ -424,7 +444,7 @@ static int init_state(Batch& B, hipStream_t st) {
   PSDP_HIP(hipMemcpyAsync(B.X, eye.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
   PSDP_HIP(hipMemcpyAsync(B.Z, eye.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
   PSDP_HIP(hipMemcpyAsync(B.Cf, cf.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
-  PSDP_HIP(hipMemsetAsync(B.y, 0, B.totvec * 8 * 8, st));   // all eight vectors
+  PSDP_HIP(hipMemsetAsync(B.y, 0, B.totvec * 8 * 10, st));   // all ten vectors
   PSDP_HIP(hipMemsetAsync(B.Lam, 0, B.totlam * 8, st));
   launch_pad_identity(st, B.S, B.d_sys, B.Lam);
   PSDP_HIP(hipGetLastError());
@@ -493,12 +513,17 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       const bool finite = std::isfinite(r.phi) && std::isfinite(r.psi) && std::isfinite(r.pinf) &&
                           std::isfinite(r.dinf) && std::isfinite(v[S_TRZX]);
       if ((prev[s] & F_ZFAIL) || !finite) { r.running = false; r.reason = PSDP_R_NONFINITE; continue; }
-      if (r.gap_rel <= o.gap_tol && r.pinf <= o.feas_tol && r.dinf <= o.feas_tol) {
+      const bool ph1 = B.sys[s].mode == 1;
+      const bool gap_ok = r.gap_rel <= o.gap_tol || (ph1 && r.gap_abs <= 1e-2 * o.gap_tol);
+      if (gap_ok && r.pinf <= o.feas_tol && r.dinf <= o.feas_tol) {
         r.running = false; r.reason = PSDP_R_CONVERGED; continue;
       }
-      if (r.phi > 0 && v[S_NORMBX] / r.phi <= 1e-6) { r.running = false; r.reason = PSDP_R_FARKAS; continue; }
-      if (it >= stall_w && r.dinf > o.feas_tol && r.dinf > 0.1 * r.dinf_hist[it - stall_w]) {
-        r.running = false; r.reason = PSDP_R_STALL; continue;
+      if (!ph1) {
+        if (r.phi > 0 && v[S_NORMBX] / r.phi <= 1e-6) { r.running = false; r.reason = PSDP_R_FARKAS; continue; }
+        // stall: the dual residual, above tolerance, has not fallen 10x in 10 iterations
+        if (it >= stall_w && r.dinf > o.feas_tol && r.dinf > 0.1 * r.dinf_hist[it - stall_w]) {
+          r.running = false; r.reason = PSDP_R_STALL; continue;
+        }
       }
       if (it >= o.max_iter) { r.running = false; r.reason = PSDP_R_MAXITER; continue; }
       any = true;
@@ -575,26 +600,106 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
   int rc = build_batch(B, sdps, count);
   if (rc) return rc;
   if ((rc = init_state(B, st))) return rc;
-  std::vector<RunState> rs(count);
   std::vector<std::vector<psdp_iter_rec>> hist(count);
-  if ((rc = run_ipm(B, o, st, rs, o.record_history ? &hist : nullptr))) return rc;
+  std::vector<RunState> rs(count);
+  std::vector<double> y1(B.totvec, 0.0), y2(B.totvec, 0.0);
 
-  // certificate check of converged systems: Q = B^T(y), block Cholesky, margins
-  std::vector<int> hf(count, 0);
-  bool anyconv = false;
-  for (int s = 0; s < count; ++s)
-    if (rs[s].reason == PSDP_R_CONVERGED) { hf[s] = F_ACTIVE; anyconv = true; }
-  std::vector<double> cert((size_t)B.nblk * 2, 0.0);
-  if (anyconv) {
+  // pass 1: the paper's SDP
+  if (o.verdict_mode != PSDP_VERDICT_PHASE1_ONLY) {
+    if ((rc = run_ipm(B, o, st, rs, o.record_history ? &hist : nullptr))) return rc;
+    PSDP_HIP(hipMemcpyAsync(y1.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+  } else {
+    for (auto& r : rs) { r.running = false; r.reason = -1; }
+  }
+
+  // pass 2: phase-I margin SDP for the undecided systems
+  std::vector<char> need(count, 0);
+  bool anyneed = false;
+  for (int s = 0; s < count; ++s) {
+    if (o.verdict_mode == PSDP_VERDICT_PHASE1_ONLY) need[s] = 1;
+    else if (o.verdict_mode == PSDP_VERDICT_PAPER_THEN_PHASE1 && rs[s].reason != PSDP_R_CONVERGED &&
+             rs[s].reason != PSDP_R_FARKAS)
+      need[s] = 1;
+    anyneed = anyneed || need[s];
+  }
+  std::vector<RunState> r1(count);
+  if (anyneed) {
+    for (int s = 0; s < count; ++s) {
+      B.sys[s].mode = need[s] ? 1 : 0;
+      r1[s].running = need[s];
+    }
+    B.any_phase1 = true;
+    PSDP_HIP(hipMemcpy(B.d_sys, B.sys.data(), B.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
+    if ((rc = init_state(B, st))) return rc;
+    std::vector<int> hf(count, 0);
+    for (int s = 0; s < count; ++s) hf[s] = need[s] ? F_ACTIVE : 0;
     PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), count * 4, hipMemcpyHostToDevice, st));
-    op_BT(B, st, B.y, B.S1);
+    launch_phase1_vectors(st, count, B.d_sys, B.d_flags, B.y, B.rv1);
+    op_BT(B, st, B.rv1, B.S1, false);                                  // B_K
+    launch_axpby(st, B.nblk, B.d_blk, B.d_flags, -1.0, B.S1, 0.0, B.S1, B.Cf);   // C' = -B_K
+    PSDP_HIP(hipGetLastError());
+    PSDP_HIP(hipStreamSynchronize(st));
+    std::vector<std::vector<psdp_iter_rec>> h2(count);
+    if ((rc = run_ipm(B, o, st, r1, nullptr))) return rc;
+    PSDP_HIP(hipMemcpyAsync(y2.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipStreamSynchronize(st));
+  }
+
+  // verdicts; certificate vectors
+  std::vector<double> ycert(B.totvec, 0.0);
+  std::vector<int> verdict(count, PSDP_UNKNOWN), wantcert(count, 0);
+  std::vector<double> tstar(count, NAN);
+  for (int s = 0; s < count; ++s) {
+    const SysDesc& d = B.sys[s];
+    psdp_sdp* p = sdps[s];
+    if (!need[s]) {
+      if (rs[s].reason == PSDP_R_CONVERGED) {
+        wantcert[s] = 1;
+        std::memcpy(ycert.data() + d.voff, y1.data() + d.voff, d.K * 8);
+      } else if (rs[s].reason == PSDP_R_FARKAS) {
+        verdict[s] = PSDP_INFEASIBLE;
+      }
+      continue;
+    }
+    const double* yp = y2.data() + d.voff;
+    const double t = yp[d.K - 1];
+    tstar[s] = t;
+    const RunState& q = r1[s];
+    const bool decided = q.reason == PSDP_R_CONVERGED ||
+                         (q.reason == PSDP_R_CHOL && std::fabs(t) > q.gap_abs && q.pinf <= 1e-6 &&
+                          q.dinf <= 1e-6);
+    if (decided && t > 1e-6) {
+      // y = (u, 1 - sum u), rescaled so that B^T(y) >= C
+      double su = 0.0;
+      for (int k = 0; k < d.K - 1; ++k) su += yp[k];
+      double cmax = 0.0;
+      for (int j = 0; j < d.nb; ++j) cmax = std::max(cmax, p->cdiag_h[j] / p->scale_h[j]);
+      const double ratio = cmax / t;
+      double* yc = ycert.data() + d.voff;
+      for (int k = 0; k < d.K - 1; ++k) yc[k] = yp[k] * ratio;
+      yc[d.K - 1] = (-su + 1.0) * ratio;
+      wantcert[s] = 1;
+    } else if (decided && t < -1e-6) {
+      verdict[s] = PSDP_INFEASIBLE;
+    }
+  }
+  std::vector<double> cert((size_t)B.nblk * 2, 0.0);
+  bool anycert = false;
+  std::vector<int> hf(count, 0);
+  for (int s = 0; s < count; ++s) {
+    hf[s] = wantcert[s] ? F_ACTIVE : 0;
+    anycert = anycert || wantcert[s];
+  }
+  if (anycert) {
+    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), count * 4, hipMemcpyHostToDevice, st));
+    PSDP_HIP(hipMemcpyAsync(B.y, ycert.data(), B.totvec * 8, hipMemcpyHostToDevice, st));
+    op_BT(B, st, B.y, B.S1, false);
     launch_certificate(st, B.nblk, B.maxn, B.d_blk, B.d_sys, B.d_flags, B.S1, 60, B.d_cert);
     PSDP_HIP(hipGetLastError());
     PSDP_HIP(hipMemcpyAsync(cert.data(), B.d_cert, cert.size() * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipStreamSynchronize(st));
   }
-  std::vector<double> hy(B.totvec);
-  PSDP_HIP(hipMemcpyAsync(hy.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
-  PSDP_HIP(hipStreamSynchronize(st));
   const double elapsed =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int s = 0; s < count; ++s) {
@@ -607,9 +712,9 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
     R.phi = r.phi; R.psi = r.psi; R.gap_abs = r.gap_abs; R.gap_rel = r.gap_rel;
     R.pinf = r.pinf; R.dinf = r.dinf;
     R.margin = R.margin_P = R.margin_D = NAN;
-    R.phase1_used = 0;
-    R.phase1_iterations = 0;
-    R.t_star = NAN;
+    R.phase1_used = need[s];
+    R.phase1_iterations = need[s] ? r1[s].iterations : 0;
+    R.t_star = tstar[s];
     R.time_solve_s = elapsed;
     R.history_len = 0;
     if (R.history && R.history_cap > 0) {
@@ -617,8 +722,9 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
       std::memcpy(R.history, hist[s].data(), nrec * sizeof(psdp_iter_rec));
       R.history_len = nrec;
     }
-    const double* ys = hy.data() + d.voff;
-    if (r.reason == PSDP_R_CONVERGED) {
+    int v = verdict[s];
+    const double* yc = ycert.data() + d.voff;
+    if (wantcert[s]) {
       bool pass = true;
       double mg = INFINITY, mP = INFINITY, mD = INFINITY;
       for (int j = 0; j < d.nb; ++j) {
@@ -628,22 +734,29 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
         if (j < d.L) mP = std::min(mP, c[1]); else mD = std::min(mD, c[1]);
       }
       R.margin = mg; R.margin_P = mP; R.margin_D = mD;
-      R.verdict = pass ? PSDP_FEASIBLE : PSDP_UNKNOWN;
-    } else if (r.reason == PSDP_R_FARKAS) {
-      R.verdict = PSDP_INFEASIBLE;
-    } else {
-      R.verdict = PSDP_UNKNOWN;
+      v = pass ? PSDP_FEASIBLE : PSDP_UNKNOWN;
+      if (need[s]) {
+        double sum = 0.0;
+        for (int k = 0; k < d.K; ++k) sum += yc[k];
+        R.phi = NAN; R.psi = sum; R.gap_abs = NAN; R.gap_rel = NAN;
+        R.pinf = r1[s].pinf; R.dinf = r1[s].dinf;
+      }
+    } else if (need[s]) {
+      R.phi = R.psi = R.gap_abs = R.gap_rel = NAN;
+      R.pinf = r1[s].pinf; R.dinf = r1[s].dinf;
     }
-    if (R.y) std::memcpy(R.y, ys, d.K * sizeof(double));
+    R.verdict = v;
+    const double* yout = need[s] ? yc : y1.data() + d.voff;
+    if (R.y) std::memcpy(R.y, yout, d.K * sizeof(double));
     if (R.P) {
       const int n = p->n;
-      const bool keep = R.verdict == PSDP_FEASIBLE;
+      const bool keep = v == PSDP_FEASIBLE;
       for (int h = 0; h < p->L0; ++h)
         for (int b = 0; b < p->Nt; ++b) {
           const int pp = p->basis.pairs[2 * b], qq = p->basis.pairs[2 * b + 1];
-          const double v = keep ? ys[(int64_t)h * p->Nt + b] : 0.0;
-          R.P[((int64_t)h * n + pp) * n + qq] = v;
-          R.P[((int64_t)h * n + qq) * n + pp] = v;
+          const double val = keep ? yc[(int64_t)h * p->Nt + b] : 0.0;
+          R.P[((int64_t)h * n + pp) * n + qq] = val;
+          R.P[((int64_t)h * n + qq) * n + pp] = val;
         }
     }
   }

@@ -59,4 +59,17 @@ void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,
                         double* out);
 
+void launch_lift(hipStream_t st, int S, const SysDesc* sys, const int* flags, const double* yin,
+                 double* yout);
+void launch_sub_tD(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                   const int* flags, const double* yp, double* out);
+void launch_B_phase1(hipStream_t st, int S, const SysDesc* sys, const int* flags,
+                     const BlkDesc* blks, const double* W, double* out, double asub);
+void launch_gemm_scaled(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                        const int* flags, const double* A, const double* B, double* C);
+void launch_lam_phase1(hipStream_t st, int S, int maxK, const SysDesc* sys, const int* flags,
+                       const BlkDesc* blks, const double* W, const double* v, double* Lam);
+void launch_phase1_vectors(hipStream_t st, int S, const SysDesc* sys, const int* flags, double* yp,
+                           double* eK);
+
 }  // namespace psdp

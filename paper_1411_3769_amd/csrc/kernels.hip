@@ -432,9 +432,7 @@ __global__ void k_B_reduce(const SysDesc* __restrict__ sys, const int* __restric
     dsum += (p == q ? Y[e1] : Y[e1] + Y[e2]);
   }
   acc -= 2.0 * dsum;
-  double ak = 1.0;
-  if (sd.mode == 1) ak = (k == sd.K - 1) ? -1.0 : 0.0;
-  out[sd.voff + k] = acc - asub * ak;
+  out[sd.voff + k] = sd.mode == 0 ? acc - asub : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -660,6 +658,152 @@ __global__ void k_pad_identity(const SysDesc* __restrict__ sys, double* Lam) {
     Lam[sd.loff + (int64_t)i * sd.Kpad + i] = 1.0;
 }
 
+
+// ---------------------------------------------------------------------------
+// phase-I margin SDP (max t s.t. B^T(y) - t D >= 0, a^T y = 1, with y_K
+// eliminated): operators and Schur complement expressed through the paper's.
+// ---------------------------------------------------------------------------
+
+// yout = (u, -sum u) for phase-I systems (u = the first K-1 entries of yin),
+// a plain copy for the others.
+__global__ void __launch_bounds__(256) k_lift(const SysDesc* __restrict__ sys,
+                                              const int* __restrict__ flags,
+                                              const double* __restrict__ yin, double* yout) {
+  __shared__ double sb[256];
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  const double* a = yin + sd.voff;
+  double* b = yout + sd.voff;
+  if (sd.mode == 0) {
+    for (int k = threadIdx.x; k < sd.K; k += blockDim.x) b[k] = a[k];
+    return;
+  }
+  double part = 0.0;
+  for (int k = threadIdx.x; k < sd.K - 1; k += blockDim.x) {
+    b[k] = a[k];
+    part += a[k];
+  }
+  const double tot = wg_sum256(part, sb);
+  if (threadIdx.x == 0) b[sd.K - 1] = -tot;
+}
+
+// out_j -= t s_j I for phase-I systems (t = the last entry of y')
+__global__ void k_sub_tD(const BlkDesc* __restrict__ blks, const SysDesc* __restrict__ sys,
+                         const int* __restrict__ flags, const double* __restrict__ yp,
+                         double* out) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const SysDesc sd = sys[bd.sys];
+  if (sd.mode != 1) return;
+  const double t = yp[sd.voff + sd.K - 1];
+  const double sj = sd.scale[bd.j];
+  for (int i = threadIdx.x; i < bd.n; i += blockDim.x) out[bd.off + i * bd.n + i] -= t * sj;
+}
+
+// B'(W) from B(W) in place: out_i -= out_{K-1} (i < K-1),
+// out_{K-1} = -sum_j s_j tr(W_j); then the phase-I a' = (0,..,0,-1) enters
+// as out_{K-1} += asub.
+__global__ void __launch_bounds__(256) k_B_phase1(const SysDesc* __restrict__ sys,
+                                                  const int* __restrict__ flags,
+                                                  const BlkDesc* __restrict__ blks,
+                                                  const double* __restrict__ W, double* out,
+                                                  double asub) {
+  __shared__ double sb[256];
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  if (sd.mode != 1) return;
+  double* o = out + sd.voff;
+  const double last = o[sd.K - 1];
+  double part = 0.0;
+  for (int e = threadIdx.x; e < sd.nb * sd.n; e += blockDim.x) {
+    const int j = e / sd.n, i = e % sd.n;
+    const BlkDesc bd = blks[sd.blk0 + j];
+    part += sd.scale[j] * W[bd.off + i * sd.n + i];
+  }
+  const double tr = wg_sum256(part, sb);   // all threads have read `last`
+  for (int k = threadIdx.x; k < sd.K - 1; k += blockDim.x) o[k] -= last;
+  if (threadIdx.x == 0) o[sd.K - 1] = -tr + asub;
+}
+
+// W_j = s_j Z^{-1}_j X_j
+__global__ void __launch_bounds__(256) k_gemm_scaled(const BlkDesc* __restrict__ blks,
+                                                     const SysDesc* __restrict__ sys,
+                                                     const int* __restrict__ flags,
+                                                     const double* A, const double* B, double* C) {
+  __shared__ double sA[16 * 64];
+  __shared__ double sB[16 * 64];
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const SysDesc sd = sys[bd.sys];
+  if (sd.mode != 1) return;
+  wg_gemm(bd.n, A + bd.off, 0, B + bd.off, 0, C + bd.off, sd.scale[bd.j], nullptr, 0.0, sA, sB);
+}
+
+// Lambda'_ij = Lambda_ij - Lambda_{K-1,i} - Lambda_{K-1,j} + Lambda_{K-1,K-1}
+// for i, j < K-1 (lower triangle read, both triangles written); one workgroup
+// per row i (grid.x over rows, grid.y over systems).
+__global__ void k_lam_phase1_a(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
+                               double* Lam) {
+  const int s = blockIdx.y, i = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  if (sd.mode != 1 || i >= sd.K - 1) return;
+  double* A = Lam + sd.loff;
+  const int64_t ld = sd.Kpad;
+  const int64_t last = (int64_t)(sd.K - 1) * ld;
+  const double cK = A[last + sd.K - 1];
+  const double ci = A[last + i];
+  for (int j = threadIdx.x; j <= i; j += blockDim.x) {
+    const double v = A[(int64_t)i * ld + j] - ci - A[last + j] + cK;
+    A[(int64_t)i * ld + j] = v;
+    if (j != i) A[(int64_t)j * ld + i] = v;
+  }
+}
+
+// last row/column: Lambda'_{t,j} = -(v_j - v_{K-1}), Lambda'_{t,t} =
+// sum_j s_j tr(W_j) with W_j = s_j Z^{-1}_j X_j and v = B(W).
+__global__ void __launch_bounds__(256) k_lam_phase1_b(const SysDesc* __restrict__ sys,
+                                                      const int* __restrict__ flags,
+                                                      const BlkDesc* __restrict__ blks,
+                                                      const double* __restrict__ W,
+                                                      const double* __restrict__ v, double* Lam) {
+  __shared__ double sb[256];
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  if (sd.mode != 1) return;
+  double part = 0.0;
+  for (int e = threadIdx.x; e < sd.nb * sd.n; e += blockDim.x) {
+    const int j = e / sd.n, i = e % sd.n;
+    part += sd.scale[j] * W[blks[sd.blk0 + j].off + i * sd.n + i];
+  }
+  const double tt = wg_sum256(part, sb);
+  double* A = Lam + sd.loff;
+  const int64_t ld = sd.Kpad;
+  const double* vs = v + sd.voff;
+  const double vK = vs[sd.K - 1];
+  for (int j = threadIdx.x; j < sd.K - 1; j += blockDim.x) {
+    const double val = -(vs[j] - vK);
+    A[(int64_t)(sd.K - 1) * ld + j] = val;
+    A[(int64_t)j * ld + sd.K - 1] = val;
+  }
+  if (threadIdx.x == 0) A[(int64_t)(sd.K - 1) * ld + sd.K - 1] = tt;
+}
+
+// phase-I starting point y' = (1/K, ..., 1/K, 0), and e_K for building C'.
+__global__ void k_phase1_vectors(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
+                                 double* yp, double* eK) {
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  for (int k = threadIdx.x; k < sd.Kpad; k += blockDim.x) {
+    yp[sd.voff + k] = k < sd.K - 1 ? 1.0 / sd.K : 0.0;
+    eK[sd.voff + k] = k == sd.K - 1 ? 1.0 : 0.0;
+  }
+}
+
 // launch wrappers ----------------------------------------------------------------
 
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam) {
@@ -795,6 +939,36 @@ void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
   const size_t lds = (size_t)maxn * maxn * 8;
   set_lds((const void*)k_certificate, lds);
   hipLaunchKernelGGL(k_certificate, dim3(nblk), dim3(256), lds, st, blks, sys, flags, Q, iters, out);
+}
+
+}  // namespace psdp
+
+namespace psdp {
+
+void launch_lift(hipStream_t st, int S, const SysDesc* sys, const int* flags, const double* yin,
+                 double* yout) {
+  hipLaunchKernelGGL(k_lift, dim3(S), dim3(256), 0, st, sys, flags, yin, yout);
+}
+void launch_sub_tD(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                   const int* flags, const double* yp, double* out) {
+  hipLaunchKernelGGL(k_sub_tD, dim3(nblk), dim3(64), 0, st, blks, sys, flags, yp, out);
+}
+void launch_B_phase1(hipStream_t st, int S, const SysDesc* sys, const int* flags,
+                     const BlkDesc* blks, const double* W, double* out, double asub) {
+  hipLaunchKernelGGL(k_B_phase1, dim3(S), dim3(256), 0, st, sys, flags, blks, W, out, asub);
+}
+void launch_gemm_scaled(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                        const int* flags, const double* A, const double* B, double* C) {
+  hipLaunchKernelGGL(k_gemm_scaled, dim3(nblk), dim3(256), 0, st, blks, sys, flags, A, B, C);
+}
+void launch_lam_phase1(hipStream_t st, int S, int maxK, const SysDesc* sys, const int* flags,
+                       const BlkDesc* blks, const double* W, const double* v, double* Lam) {
+  hipLaunchKernelGGL(k_lam_phase1_a, dim3(maxK, S), dim3(256), 0, st, sys, flags, Lam);
+  hipLaunchKernelGGL(k_lam_phase1_b, dim3(S), dim3(256), 0, st, sys, flags, blks, W, v, Lam);
+}
+void launch_phase1_vectors(hipStream_t st, int S, const SysDesc* sys, const int* flags, double* yp,
+                           double* eK) {
+  hipLaunchKernelGGL(k_phase1_vectors, dim3(S), dim3(256), 0, st, sys, flags, yp, eK);
 }
 
 }  // namespace psdp
