@@ -90,6 +90,22 @@ typedef struct {
     int64_t device_bytes; /* device memory one solve of this SDP needs */
 } psdp_dims;
 
+/* launch classes timed with HIP events when psdp_opts.prof is set */
+#define PSDP_PROF_CHOLINV      0   /* block Cholesky + inverse of Z              */
+#define PSDP_PROF_BT           1   /* B^T(y) (eq. AT)                            */
+#define PSDP_PROF_B            2   /* B(W)                                       */
+#define PSDP_PROF_PRE          3   /* Schur pre-products Z^-1 H^T, X H^T, ...    */
+#define PSDP_PROF_ASSEMBLE     4   /* Schur complement assembly (eq. T2)         */
+#define PSDP_PROF_CHOL_PANEL   5   /* Schur Cholesky: diagonal + panel solve     */
+#define PSDP_PROF_CHOL_UPDATE  6   /* Schur Cholesky: trailing update            */
+#define PSDP_PROF_TRSV         7   /* the two triangular solves                  */
+#define PSDP_PROF_GEMM         8   /* block products of the directions           */
+#define PSDP_PROF_LADDER       9   /* step-length ladder                         */
+#define PSDP_PROF_MISC        10   /* residuals, reductions, updates             */
+#define PSDP_PROF_CERT        11   /* certificate check                          */
+#define PSDP_PROF_PHASE1      12   /* phase-I transforms                         */
+#define PSDP_NPROF            16
+
 typedef struct {
     double gap_tol;       /* relative duality gap tolerance (1e-8)                   */
     double feas_tol;      /* relative primal / dual residual tolerance (1e-8)        */
@@ -102,6 +118,10 @@ typedef struct {
     int    precision;     /* PSDP_PREC_*                                             */
     void*  stream;        /* hipStream_t, NULL = null stream                         */
     int    record_history;/* 1: fill psdp_result.history (host memory, caller owns)  */
+    double* prof;         /* NULL, or a caller array [PSDP_NPROF][2] that receives,  */
+                          /* per launch class, the summed device time (ms) and the   */
+                          /* number of launches, measured with HIP events on the     */
+                          /* solver stream (accumulated, not cleared)                */
 } psdp_opts;
 
 typedef struct {

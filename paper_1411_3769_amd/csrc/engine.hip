@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -39,7 +40,46 @@ struct StepTab {
   }
 };
 
+// HIP-event timing of launch classes on the solver stream.
+struct Prof {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> ev;
+  size_t next = 0;
+  std::vector<std::array<size_t, 3>> pend;
+  double* out = nullptr;
+  size_t mark() {
+    if (!on) return 0;
+    if (next == ev.size()) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      ev.push_back(e);
+    }
+    hipEventRecord(ev[next], st);
+    return next++;
+  }
+  void add(int cls, size_t a, size_t b) {
+    if (on) pend.push_back({(size_t)cls, a, b});
+  }
+  // after a stream synchronisation: accumulate and recycle the events
+  void harvest() {
+    if (!on) return;
+    for (const auto& p : pend) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[p[1]], ev[p[2]]);
+      out[2 * p[0]] += ms;
+      out[2 * p[0] + 1] += 1.0;
+    }
+    pend.clear();
+    next = 0;
+  }
+  ~Prof() {
+    for (auto e : ev) hipEventDestroy(e);
+  }
+};
+
 struct Batch {
+  Prof prof;
   int S = 0, maxn = 0, nblk = 0, npblk = 0, ndblk = 0, npairs = 0, nq2 = 0, ntiles = 0;
   int totL0 = 0, totK = 0, maxP = 0;
   std::vector<psdp_sdp*> sd;
@@ -368,6 +408,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
 
 // B^T(y) for every active system; phase-I systems use B'^T (lift + t D).
 static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool phase_aware = true) {
+  const size_t m0 = B.prof.mark();
   const double* ybase = yv;
   if (phase_aware && B.any_phase1) {
     launch_lift(st, B.S, B.d_sys, B.d_flags, yv, B.ylift);
@@ -377,46 +418,60 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
   launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out);
   launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
   if (phase_aware && B.any_phase1) launch_sub_tD(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, yv, out);
+  B.prof.add(PSDP_PROF_BT, m0, B.prof.mark());
 }
 
 // B(W) - asub * a; W must be symmetric (callers symmetrise first; B(W) =
 // B(sym W)).  Phase-I systems get B'(W) - asub * a'.
 static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double asub,
                  bool phase_aware = true) {
+  const size_t m0 = B.prof.mark();
   launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
   launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
                   out, asub);
   if (phase_aware && B.any_phase1) launch_B_phase1(st, B.S, B.d_sys, B.d_flags, B.d_blk, W, out, asub);
+  B.prof.add(PSDP_PROF_B, m0, B.prof.mark());
 }
 
 static void op_schur(Batch& B, hipStream_t st) {
+  const size_t m0 = B.prof.mark();
   launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1);
   launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena);
+  const size_t m1 = B.prof.mark();
   launch_assemble(st, B.ntiles, B.d_tiles, B.d_terms, B.d_sys, B.d_flags, B.d_gpinfo, B.arena,
                   B.Lam, B.d_gpoff);
+  const size_t m2 = B.prof.mark();
+  B.prof.add(PSDP_PROF_PRE, m0, m1);
+  B.prof.add(PSDP_PROF_ASSEMBLE, m1, m2);
   if (B.any_phase1) {
     // phase-I: v = B(D Z^-1 X) and the rank-2 + border transform
     launch_gemm_scaled(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, B.Zi, B.X, B.W1);
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
     op_B(B, st, B.W1, B.vtmp, 0.0, false);
     launch_lam_phase1(st, B.S, B.maxK, B.d_sys, B.d_flags, B.d_blk, B.W1, B.vtmp, B.Lam);
+    B.prof.add(PSDP_PROF_PHASE1, m2, B.prof.mark());
   }
 }
 
 static void op_factor(Batch& B, hipStream_t st) {
   for (int p = 0; p < B.maxP; ++p) {
     const int f = B.pan.first[p];
+    const size_t m0 = B.prof.mark();
     launch_chol_panel(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.d_pan_sys + f, B.d_pan_pre + f,
                       B.pan.cnt[p], B.pan.tot[p], p);
+    const size_t m1 = B.prof.mark();
+    B.prof.add(PSDP_PROF_CHOL_PANEL, m0, m1);
     if (B.upd.tot[p] > 0) {
       const int g = B.upd.first[p];
       launch_chol_update(st, B.d_sys, B.d_flags, B.Lam, B.d_upd_sys + g, B.d_upd_pre + g,
                          B.upd.cnt[p], B.upd.tot[p], p);
+      B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
     }
   }
 }
 
 static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
+  const size_t m0 = B.prof.mark();
   PSDP_HIP(hipMemcpyAsync(B.r, rhs, B.totvec * 8, hipMemcpyDeviceToDevice, st));
   for (int p = 0; p < B.maxP; ++p) {
     const int f = B.pan.first[p];
@@ -428,6 +483,7 @@ static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
     launch_trsv_bwd(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.z, x, B.d_bwd_sys + f,
                     B.d_bwd_pre + f, B.bwd.cnt[p], B.bwd.tot[p], p);
   }
+  B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());
   return PSDP_OK;
 }
 
@@ -480,6 +536,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     std::vector<int> prev(S);
     PSDP_HIP(hipMemcpyAsync(prev.data(), B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
     if (it > 0) {
       for (int s = 0; s < S; ++s) {
         if (!rs[s].running) continue;
@@ -490,16 +547,26 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     }
     PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), S * 4, hipMemcpyHostToDevice, st));
     PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
+    { const size_t pm_ = B.prof.mark();
     launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
+      B.prof.add(PSDP_PROF_CHOLINV, pm_, B.prof.mark()); }
     op_BT(B, st, B.y, B.S1);
+    { const size_t pm_ = B.prof.mark();
     launch_make_G(st, B.nblk, B.d_blk, B.d_flags, B.Cf, B.S1, B.Z, B.G);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     op_B(B, st, B.X, B.BX, 0.0);
+    { const size_t pm_ = B.prof.mark();
     launch_block_red(st, B.nblk, B.d_blk, B.d_flags, B.Cf, B.X, B.Z, B.G, B.d_red);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_sys_finalize(st, S, B.d_sys, B.d_flags, B.d_red, B.y, B.BX, o.sigma, B.d_sc);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     PSDP_HIP(hipGetLastError());
     PSDP_HIP(hipMemcpyAsync(hsc.data(), B.d_sc, hsc.size() * 8, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipMemcpyAsync(prev.data(), B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
     bool any = false;
     for (int s = 0; s < S; ++s) {
       RunState& r = rs[s];
@@ -532,41 +599,77 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     set_flags(B, rs, hf);
     PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), S * 4, hipMemcpyHostToDevice, st));
     PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
     // ---- Newton system (Alg. 2 processors/root step 1)
     op_schur(B, st);
     op_factor(B, st);
     // Omega_1 = B(Z^-1 G X) - a
+    { const size_t pm_ = B.prof.mark();
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.G, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.W1, 1.0, -1, nullptr, 0.0, -1);
+      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     op_B(B, st, B.W1, B.rv1, 1.0);
     op_solve(B, st, B.rv1, B.dyh);
     // predictor directions (processors step 2)
     op_BT(B, st, B.dyh, B.S1);
+    { const size_t pm_ = B.prof.mark();
     launch_axpby(st, B.nblk, B.d_blk, B.d_flags, -1.0, B.G, 1.0, B.S1, B.dZh);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.dZh, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.dXh, -1.0, -1, B.X, -1.0, -1);
+      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     // corrector right-hand side: W = mu Z^-1 - Z^-1 dZ^ dX^
+    { const size_t pm_ = B.prof.mark();
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.dXh, 0, B.Wc, -1.0, -1, B.Zi, 1.0, S_MU);
+      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.Wc, B.W1);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     op_B(B, st, B.W1, B.rv2, 0.0);
     op_solve(B, st, B.rv2, B.dyb);
     // corrector directions (processors step 3)
     op_BT(B, st, B.dyb, B.dZb);
+    { const size_t pm_ = B.prof.mark();
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.dZb, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.dXb, -1.0, -1, B.Wc, 1.0, -1);
+      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_combine(st, B.nblk, B.d_blk, B.d_flags, B.dXh, B.dXb, B.dX, B.dZh, B.dZb, B.dZ);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     // step lengths and update
+    { const size_t pm_ = B.prof.mark();
     launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
+      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TP, B.d_sc);
+      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.dZ, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
+      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TD, B.d_sc);
+      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_update_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.X, B.dX, B.Z, B.dZ);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
+    { const size_t pm_ = B.prof.mark();
     launch_update_y(st, S, B.d_sys, B.d_flags, B.d_sc, B.y, B.dyh, B.dyb);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     PSDP_HIP(hipGetLastError());
     if (hist) {
       PSDP_HIP(hipMemcpyAsync(hsc.data(), B.d_sc, hsc.size() * 8, hipMemcpyDeviceToHost, st));
       PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
       for (int s = 0; s < S; ++s)
         if (rs[s].running && !(*hist)[s].empty()) {
           (*hist)[s].back().tp = hsc[(size_t)s * kNSC + S_TP];
@@ -597,6 +700,9 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
   if (o.verdict_mode < 0 || o.verdict_mode > 2) return fail(PSDP_EINVAL, "invalid verdict_mode");
   hipStream_t st = (hipStream_t)o.stream;
   Batch B;
+  B.prof.on = o.prof != nullptr;
+  B.prof.st = st;
+  B.prof.out = o.prof;
   int rc = build_batch(B, sdps, count);
   if (rc) return rc;
   if ((rc = init_state(B, st))) return rc;
@@ -609,6 +715,7 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
     if ((rc = run_ipm(B, o, st, rs, o.record_history ? &hist : nullptr))) return rc;
     PSDP_HIP(hipMemcpyAsync(y1.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
   } else {
     for (auto& r : rs) { r.running = false; r.reason = -1; }
   }
@@ -644,6 +751,7 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
     if ((rc = run_ipm(B, o, st, r1, nullptr))) return rc;
     PSDP_HIP(hipMemcpyAsync(y2.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
   }
 
   // verdicts; certificate vectors
@@ -695,10 +803,13 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
     PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), count * 4, hipMemcpyHostToDevice, st));
     PSDP_HIP(hipMemcpyAsync(B.y, ycert.data(), B.totvec * 8, hipMemcpyHostToDevice, st));
     op_BT(B, st, B.y, B.S1, false);
+    const size_t pm0 = B.prof.mark();
     launch_certificate(st, B.nblk, B.maxn, B.d_blk, B.d_sys, B.d_flags, B.S1, 60, B.d_cert);
+    B.prof.add(PSDP_PROF_CERT, pm0, B.prof.mark());
     PSDP_HIP(hipGetLastError());
     PSDP_HIP(hipMemcpyAsync(cert.data(), B.d_cert, cert.size() * 8, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
+    B.prof.harvest();
   }
   const double elapsed =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

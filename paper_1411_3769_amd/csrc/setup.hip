@@ -204,6 +204,7 @@ void psdp_opts_default(psdp_opts* o) {
   o->precision = PSDP_PREC_FP64;
   o->stream = nullptr;
   o->record_history = 0;
+  o->prof = nullptr;
 }
 
 const char* psdp_last_error(void) { return g_err.c_str(); }

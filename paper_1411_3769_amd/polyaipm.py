@@ -30,6 +30,14 @@ REASONS = ["converged", "farkas", "stall", "max_iter", "ladder_fail", "chol_fail
 VERDICT_MODES = {"paper_then_phase1": 0, "paper_only": 1, "phase1_only": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 ERRORS = {-1: "EINVAL", -2: "EOVERFLOW", -3: "ENOMEM", -4: "EDEVICE", -5: "ENUMERIC"}
+NPROF = 16
+PROF_CLASSES = ["cholinv", "BT", "B", "pre", "assemble", "chol_panel", "chol_update", "trsv",
+                "gemm", "ladder", "misc", "cert", "phase1"]
+
+
+def new_prof() -> np.ndarray:
+    """Array for psdp_opts.prof: [NPROF][2] = (device ms, launches) per class."""
+    return np.zeros((NPROF, 2))
 
 DP = C.POINTER(C.c_double)
 
@@ -48,7 +56,7 @@ class Opts(C.Structure):
     _fields_ = [("gap_tol", C.c_double), ("feas_tol", C.c_double), ("max_iter", C.c_int),
                 ("sigma", C.c_double), ("step_frac", C.c_double), ("ladder_rho", C.c_double),
                 ("ladder_len", C.c_int), ("verdict_mode", C.c_int), ("precision", C.c_int),
-                ("stream", C.c_void_p), ("record_history", C.c_int)]
+                ("stream", C.c_void_p), ("record_history", C.c_int), ("prof", DP)]
 
 
 class IterRec(C.Structure):
@@ -215,6 +223,8 @@ def make_opts(**kw) -> Opts:
             v = PRECISIONS[v]
         if k == "stream":
             v = C.c_void_p(v) if isinstance(v, int) else v
+        if k == "prof":
+            v = v.ctypes.data_as(DP) if v is not None else DP()
         setattr(o, k, v)
     if "stream" not in kw:
         o.stream = _current_stream()
