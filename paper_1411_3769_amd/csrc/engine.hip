@@ -89,7 +89,8 @@ struct Batch {
   std::vector<int64_t> offA1;
   std::vector<HM2> q2;
   std::vector<KTerm> terms;
-  std::vector<AsmTile> tiles;
+  std::vector<AsmTile> tiles, ptiles;   // grouped tiles (n > 11), whole pairs (n <= 11)
+  int maxn_pair = 0, nptiles = 0;
   std::vector<int> csr_hh, csr_hid, csr_mh, csr_hl;   // per-system sections
   std::vector<int> csr_hh_off, csr_hid_off, csr_mh_off, csr_hl_off;
   std::vector<int> gpinfo;
@@ -108,6 +109,7 @@ struct Batch {
   HM2* d_q2 = nullptr;
   KTerm* d_terms = nullptr;
   AsmTile* d_tiles = nullptr;
+  AsmTile* d_ptiles = nullptr;
   int *d_gpinfo = nullptr, *d_ownP = nullptr, *d_ownK = nullptr;
   int64_t* d_gpoff = nullptr;
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
@@ -312,7 +314,12 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
           B.terms.push_back(KTerm{A1h, A2h2, 1.0, 1, 1});         // (H Zi, H' X)
         }
         const int kcnt = (int)B.terms.size() - kbeg;
-        if (kcnt == 0) continue;   // the tile is zero: filled by the zero pass
+        if (kcnt == 0) continue;   // the block stays zero
+        if (p->n * p->n <= 128) {
+          B.ptiles.push_back(AsmTile{s, h, h2, -1, -1, kbeg, kcnt, 0});
+          B.maxn_pair = std::max(B.maxn_pair, p->n);
+          continue;
+        }
         const int ngp = p->basis.ngp;
         for (int rg = 0; rg < ngp; ++rg)
           for (int cg = (h == h2 ? rg : 0); cg < ngp; ++cg)
@@ -321,6 +328,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
     }
   }
   B.ntiles = (int)B.tiles.size();
+  B.nptiles = (int)B.ptiles.size();
 
   // ---- Cholesky step tables
   for (int pstep = 0; pstep < B.maxP; ++pstep) {
@@ -341,6 +349,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   size_t tb = 0;
   tb += tabsize(B.sys) + tabsize(B.blk) + tabsize(B.pblk) + tabsize(B.dblk) + tabsize(B.pairs);
   tb += tabsize(B.offA1) + tabsize(B.q2) + tabsize(B.terms) + tabsize(B.tiles) + tabsize(B.gpinfo);
+  tb += tabsize(B.ptiles);
   tb += tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(B.csr_hh) + tabsize(B.csr_hid);
   tb += tabsize(B.csr_mh) + tabsize(B.csr_hl);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
@@ -357,7 +366,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
     char* base = (char*)B.dtab;
     size_t o2 = tabsize(B.sys) + tabsize(B.blk) + tabsize(B.pblk) + tabsize(B.dblk) + tabsize(B.pairs) +
                 tabsize(B.offA1) + tabsize(B.q2) + tabsize(B.terms) + tabsize(B.tiles) +
-                tabsize(B.gpinfo) + tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK);
+                tabsize(B.ptiles) + tabsize(B.gpinfo) + tabsize(B.gpoff) + tabsize(B.ownP) +
+                tabsize(B.ownK);
     d_csr_hh = (int*)(base + o2); o2 += tabsize(B.csr_hh);
     d_csr_hid = (int*)(base + o2); o2 += tabsize(B.csr_hid);
     d_csr_mh = (int*)(base + o2); o2 += tabsize(B.csr_mh);
@@ -378,6 +388,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   if ((rc = upload(B.dtab, off, B.q2, &B.d_q2))) return rc;
   if ((rc = upload(B.dtab, off, B.terms, &B.d_terms))) return rc;
   if ((rc = upload(B.dtab, off, B.tiles, &B.d_tiles))) return rc;
+  if ((rc = upload(B.dtab, off, B.ptiles, &B.d_ptiles))) return rc;
   if ((rc = upload(B.dtab, off, B.gpinfo, &B.d_gpinfo))) return rc;
   if ((rc = upload(B.dtab, off, B.gpoff, &B.d_gpoff))) return rc;
   if ((rc = upload(B.dtab, off, B.ownP, &B.d_ownP))) return rc;
@@ -438,8 +449,10 @@ static void op_schur(Batch& B, hipStream_t st) {
   launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1);
   launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena);
   const size_t m1 = B.prof.mark();
-  launch_assemble(st, B.ntiles, B.d_tiles, B.d_terms, B.d_sys, B.d_flags, B.d_gpinfo, B.arena,
-                  B.Lam, B.d_gpoff);
+  launch_assemble_pair(st, B.nptiles, B.maxn_pair, B.d_ptiles, B.d_terms, B.d_sys, B.d_flags,
+                       B.arena, B.Lam);
+  launch_assemble_grp(st, B.ntiles, B.d_tiles, B.d_terms, B.d_sys, B.d_flags, B.d_gpinfo, B.arena,
+                      B.Lam, B.d_gpoff);
   const size_t m2 = B.prof.mark();
   B.prof.add(PSDP_PROF_PRE, m0, m1);
   B.prof.add(PSDP_PROF_ASSEMBLE, m1, m2);

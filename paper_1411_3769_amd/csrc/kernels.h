@@ -54,6 +54,12 @@ void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, cons
 void launch_assemble(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
                      const SysDesc* sys, const int* flags, const int* gpinfo,
                      const double* arena, double* Lam, const int64_t* gpoff);
+void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
+                          const KTerm* terms, const SysDesc* sys, const int* flags,
+                          const double* arena, double* Lam);
+void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
+                         const SysDesc* sys, const int* flags, const int* gpinfo,
+                         const double* arena, double* Lam, const int64_t* gpoff);
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam);
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,

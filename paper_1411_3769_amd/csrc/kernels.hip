@@ -804,6 +804,220 @@ __global__ void k_phase1_vectors(const SysDesc* __restrict__ sys, const int* __r
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Schur complement assembly on FP64 MFMA (v_mfma_f64_16x16x4: A 16x4,
+// B 4x16; lane l supplies A[l%16][l/16] and B[l/16][l%16], and result
+// register i of lane l holds D[4i + l/16][l%16], i = 0..3).
+//
+// For a pair (h, h2) the expansion terms k = (block, t) give
+//   R[(b,c),(d,a)] = sum_k T_k[b,c] U_k[d,a]          (a product of the
+// stacked, flattened T and U: rows n^2, columns n^2, inner dimension #k), and
+//   Lambda[(p,q),(r,s)] = sum_{(a,b) in S(p,q)} sum_{(c,d) in S(r,s)} R[(b,c),(d,a)]
+// with S(p,q) = {(p,q),(q,p)} (p != q) or {(p,p)}.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Small n (n^2 <= 128): one workgroup per (system, h, h2); R accumulated in
+// registers by 4 waves (tiles of 16 x 16), then staged in LDS for the gather.
+constexpr int kPairMaxT = 16;
+__global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict__ tiles,
+                                                       const KTerm* __restrict__ terms,
+                                                       const SysDesc* __restrict__ sys,
+                                                       const int* __restrict__ flags,
+                                                       const double* __restrict__ arena,
+                                                       double* Lam) {
+  extern __shared__ double smem[];
+  const AsmTile tl = tiles[blockIdx.x];
+  ACTIVE_OR_RETURN(tl.sys);
+  const SysDesc sd = sys[tl.sys];
+  const int n = sd.n, n2 = n * n;
+  const int NT = (n2 + 15) / 16, n2p = NT * 16, ntiles = NT * NT;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* sT = smem;
+  double* sU = smem + 4 * n2p;
+  double* R = smem + 8 * n2p;
+  v4d acc[kPairMaxT];
+#pragma unroll
+  for (int t = 0; t < kPairMaxT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < tl.kcnt; k0 += 4) {
+    __syncthreads();
+    for (int e = tid; e < 4 * n2p; e += 256) {
+      const int kk = e / n2p, idx = e - kk * n2p;
+      double tv = 0.0, uv = 0.0;
+      if (k0 + kk < tl.kcnt && idx < n2) {
+        const KTerm kt = terms[tl.kbeg + k0 + kk];
+        const int b = idx / n, c = idx - b * n;
+        const int tr = c * n + b;
+        tv = kt.coef * arena[kt.offT + (kt.tT ? tr : idx)];
+        uv = arena[kt.offU + (kt.tU ? tr : idx)];
+      }
+      sT[e] = tv;
+      sU[e] = uv;
+    }
+    __syncthreads();
+    const int kq = lane >> 4, r16 = lane & 15;
+#pragma unroll
+    for (int t = 0; t < kPairMaxT; ++t) {
+      const int id = wave + 4 * t;
+      if (id < ntiles) {
+        const int ti = id / NT, tj = id - ti * NT;
+        const double a = sT[kq * n2p + ti * 16 + r16];
+        const double b = sU[kq * n2p + tj * 16 + r16];
+        acc[t] = mfma16(a, b, acc[t]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kPairMaxT; ++t) {
+    const int id = wave + 4 * t;
+    if (id < ntiles) {
+      const int ti = id / NT, tj = id - ti * NT;
+      const int col = tj * 16 + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ti * 16 + 4 * i + (lane >> 4);
+        if (row < n2 && col < n2) R[row * n2 + col] = acc[t][i];
+      }
+    }
+  }
+  __syncthreads();
+  const int Nt = sd.Nt;
+  const int64_t ld = sd.Kpad;
+  double* Lr = Lam + sd.loff;
+  for (int e = tid; e < Nt * Nt; e += 256) {
+    const int b1 = e / Nt, b2 = e - b1 * Nt;
+    const int p = sd.basis[2 * b1], q = sd.basis[2 * b1 + 1];
+    const int r = sd.basis[2 * b2], s = sd.basis[2 * b2 + 1];
+    double v = R[(q * n + r) * n2 + s * n + p];
+    if (r != s) v += R[(q * n + s) * n2 + r * n + p];
+    if (p != q) {
+      v += R[(p * n + r) * n2 + s * n + q];
+      if (r != s) v += R[(p * n + s) * n2 + r * n + q];
+    }
+    const int64_t row = (int64_t)tl.h * Nt + b1, col = (int64_t)tl.h2 * Nt + b2;
+    Lr[row * ld + col] = v;
+    if (tl.h != tl.h2) Lr[col * ld + row] = v;
+  }
+}
+
+// General n: one workgroup per Schur tile (row group (g1,g2) of h, column
+// group (g3,g4) of h2; groups of 8 indices).  Wave w accumulates one of the
+// four symmetric components over the stacked terms,
+//   Q1 = sum T[q,r] U[s,p],  Q2 = sum T[q,s] U[r,p],
+//   Q3 = sum T[p,r] U[s,q],  Q4 = sum T[p,s] U[r,q],
+// as a 64 x 64 MFMA product (rows (x,y), columns (z,u) of 8 x 8 indices);
+// the four are added into an LDS tile in (p,q) x (r,s) order (Q3/Q4 only for
+// p != q, Q2/Q4 only for r != s).
+__global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict__ tiles,
+                                                      const KTerm* __restrict__ terms,
+                                                      const SysDesc* __restrict__ sys,
+                                                      const int* __restrict__ flags,
+                                                      const int* __restrict__ gpinfo_all,
+                                                      const double* __restrict__ arena,
+                                                      double* Lam,
+                                                      const int64_t* __restrict__ gpoff) {
+  __shared__ double sT[4 * 16 * 17];
+  __shared__ double sU[4 * 16 * 17];
+  __shared__ double sL[64 * 65];
+  const AsmTile tl = tiles[blockIdx.x];
+  ACTIVE_OR_RETURN(tl.sys);
+  const SysDesc sd = sys[tl.sys];
+  const int n = sd.n;
+  const int* gp = gpinfo_all + gpoff[tl.sys];
+  const int g1 = gp[tl.rg * 4 + 0], g2 = gp[tl.rg * 4 + 1], roff = gp[tl.rg * 4 + 2];
+  const int g3 = gp[tl.cg * 4 + 0], g4 = gp[tl.cg * 4 + 1], coff = gp[tl.cg * 4 + 2];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  // index offsets of the quadrant's row pair (x, y) and column pair (z, u)
+  const int xoff = w < 2 ? 8 : 0, yoff = (w & 1) ? 8 : 0;
+  const int zoff = (w & 1) ? 0 : 8, uoff = w < 2 ? 0 : 8;
+  v4d acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < tl.kcnt; k0 += 4) {
+    __syncthreads();
+    for (int e = tid; e < 4 * 512; e += 256) {
+      const int kk = e >> 9, rem = e & 511, which = rem >> 8;
+      const int a = (rem & 255) >> 4, c = rem & 15;
+      const int ia = a < 8 ? kTB * g1 + a : kTB * g2 + (a - 8);
+      const int jc = c < 8 ? kTB * g3 + c : kTB * g4 + (c - 8);
+      double v = 0.0;
+      if (k0 + kk < tl.kcnt && ia < n && jc < n) {
+        const KTerm kt = terms[tl.kbeg + k0 + kk];
+        if (which == 0) v = kt.coef * arena[kt.offT + (kt.tT ? jc * n + ia : ia * n + jc)];
+        else v = arena[kt.offU + (kt.tU ? ia * n + jc : jc * n + ia)];
+      }
+      if (which == 0) sT[kk * 272 + a * 17 + c] = v;   // T[I_a][J_c]
+      else sU[kk * 272 + c * 17 + a] = v;              // U[J_c][I_a]
+    }
+    __syncthreads();
+    const int kq = lane >> 4, r16 = lane & 15;
+    double av[4], bv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int xi = 2 * t + (r16 >> 3), yi = r16 & 7;
+      av[t] = sT[kq * 272 + (xoff + xi) * 17 + yoff + yi];
+      const int zi = 2 * t + (r16 >> 3), ui = r16 & 7;
+      bv[t] = sU[kq * 272 + (zoff + zi) * 17 + uoff + ui];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t * 4 + u] = mfma16(av[t], bv[u], acc[t * 4 + u]);
+  }
+  // combine the four quadrants in LDS
+  const bool pqdiag = (g1 == g2), rsdiag = (g3 == g4);
+  for (int ph = 0; ph < 4; ++ph) {
+    __syncthreads();
+    if (w == ph) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 16 * t + 4 * i + (lane >> 4), col = 16 * u + (lane & 15);
+            const int xi = row >> 3, yi = row & 7, zi = col >> 3, ui = col & 7;
+            int pi, qi, ri, si;
+            if (w == 0) { pi = ui; qi = xi; ri = yi; si = zi; }
+            else if (w == 1) { pi = ui; qi = xi; ri = zi; si = yi; }
+            else if (w == 2) { pi = xi; qi = ui; ri = yi; si = zi; }
+            else { pi = xi; qi = ui; ri = zi; si = yi; }
+            const bool pq_same = pqdiag && pi == qi, rs_same = rsdiag && ri == si;
+            double v = acc[t * 4 + u][i];
+            if ((w >= 2 && pq_same) || ((w & 1) && rs_same)) v = 0.0;
+            double* dst = sL + (pi * 8 + qi) * 65 + ri * 8 + si;
+            if (w == 0) *dst = v; else *dst += v;
+          }
+    }
+  }
+  __syncthreads();
+  const int n1 = min(kTB, n - kTB * g1), n2s = min(kTB, n - kTB * g2);
+  const int n3 = min(kTB, n - kTB * g3), n4 = min(kTB, n - kTB * g4);
+  const int64_t ld = sd.Kpad;
+  const bool mirror = !(tl.h == tl.h2 && tl.rg == tl.cg);
+  double* Lr = Lam + sd.loff;
+  for (int e = tid; e < 4096; e += 256) {
+    const int rowl = e >> 6, coll = e & 63;
+    const int pi = rowl >> 3, qi = rowl & 7, ri = coll >> 3, si = coll & 7;
+    if (pi >= n1 || qi >= n2s || ri >= n3 || si >= n4) continue;
+    if (pqdiag && qi < pi) continue;
+    if (rsdiag && si < ri) continue;
+    const int bi = pqdiag ? pi * n1 - pi * (pi - 1) / 2 + (qi - pi) : pi * n2s + qi;
+    const int bj = rsdiag ? ri * n3 - ri * (ri - 1) / 2 + (si - ri) : ri * n4 + si;
+    const int64_t row = (int64_t)tl.h * sd.Nt + roff + bi;
+    const int64_t col = (int64_t)tl.h2 * sd.Nt + coff + bj;
+    const double v = sL[rowl * 65 + coll];
+    Lr[row * ld + col] = v;
+    if (mirror) Lr[col * ld + row] = v;
+  }
+}
+
 // launch wrappers ----------------------------------------------------------------
 
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam) {
@@ -969,6 +1183,28 @@ void launch_lam_phase1(hipStream_t st, int S, int maxK, const SysDesc* sys, cons
 void launch_phase1_vectors(hipStream_t st, int S, const SysDesc* sys, const int* flags, double* yp,
                            double* eK) {
   hipLaunchKernelGGL(k_phase1_vectors, dim3(S), dim3(256), 0, st, sys, flags, yp, eK);
+}
+
+}  // namespace psdp
+
+namespace psdp {
+
+void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
+                          const KTerm* terms, const SysDesc* sys, const int* flags,
+                          const double* arena, double* Lam) {
+  if (!ntiles) return;
+  const int n2 = maxn * maxn, n2p = (n2 + 15) / 16 * 16;
+  const size_t lds = (size_t)(8 * n2p + n2 * n2) * 8;
+  set_lds((const void*)k_assemble_pair, lds);
+  hipLaunchKernelGGL(k_assemble_pair, dim3(ntiles), dim3(256), lds, st, tiles, terms, sys, flags, arena, Lam);
+}
+
+void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
+                         const SysDesc* sys, const int* flags, const int* gpinfo,
+                         const double* arena, double* Lam, const int64_t* gpoff) {
+  if (!ntiles) return;
+  hipLaunchKernelGGL(k_assemble_grp, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags, gpinfo,
+                     arena, Lam, gpoff);
 }
 
 }  // namespace psdp
