@@ -7,18 +7,20 @@
 // Kpad, a multiple of 64); rows/columns past K hold the identity, so the
 // factor of the padded matrix is blockdiag(L, I) and no kernel needs ragged
 // edges.  The off-diagonal tiles of the factor overwrite the lower triangle;
-// the factored diagonal tiles go to a separate array Ldiag[P][64][64] (other
-// workgroups of the same step still read the unfactored diagonal tile); the
-// strict upper triangle keeps Lambda.
+// the factored diagonal tiles L_pp and their inverses go to separate arrays
+// (other workgroups of the same step still read the unfactored diagonal
+// tile); the strict upper triangle keeps Lambda.
 //
 // Right-looking blocked algorithm, step p (panel column p):
 //   panel  : every workgroup loads the 64 x 64 diagonal tile, factors it in
-//            LDS (redundantly: this replaces a separate launch), then either
-//            writes L_pp back (tile row p) or solves L_ip = A_ip L_pp^{-T}
-//            for one tile row below it;
-//   update : every tile (i, j), p < j <= i, gets A_ij -= L_ip L_jp^T.
+//            LDS and inverts the factor (redundantly: this replaces two
+//            launches), then either stores L_pp and L_pp^{-1} (first
+//            workgroup) or forms L_ip = A_ip L_pp^{-T} for one tile row;
+//   update : every tile (i, j), p < j <= i, gets A_ij -= L_ip L_jp^T on FP64
+//            MFMA.
 // Steps are launched for the whole batch; a (step, system) table maps
-// workgroups to systems.
+// workgroups to systems.  Triangular solves use the stored inverses, so the
+// diagonal solves are matrix-vector products.
 #include <hip/hip_runtime.h>
 
 #include "devcommon.h"
@@ -27,20 +29,72 @@
 namespace psdp {
 
 constexpr int LDT = kNB + 1;   // LDS leading dimension of a 64 x 64 tile
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-__device__ inline void load_tile_lower(double* s, const double* A, int64_t ld) {
-  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
-    const int r = e / kNB, c = e % kNB;
-    s[r * LDT + c] = A[r * ld + c];
+// In-place lower Cholesky of a 64 x 64 tile in LDS (leading dimension LDT)
+// with 256 threads and two barriers per column: the scaled column, then the
+// rank-one trailing update over a 16 x 16 thread grid (the pivot itself is
+// stored during the update phase, when nobody reads it).  Non-positive or
+// non-finite pivots set *fail and are replaced by 1.
+__device__ inline void tile_potrf64(double* A, int* fail) {
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  for (int k = 0; k < kNB; ++k) {
+    __syncthreads();   // the previous trailing update is complete
+    double d = A[k * LDT + k];
+    const bool bad = !(d > 0.0) || !isfinite(d);
+    if (bad) d = 1.0;
+    const double piv = sqrt(d);
+    if (tid > k && tid < kNB) A[tid * LDT + k] = A[tid * LDT + k] / piv;
+    __syncthreads();   // column k scaled; every thread has read A[k][k]
+    if (tid == k) {
+      A[k * LDT + k] = piv;
+      if (bad) *fail = 1;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = tr + 16 * a;
+      if (i <= k) continue;
+      const double lik = A[i * LDT + k];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = tc + 16 * b;
+        if (j > k && j <= i) A[i * LDT + j] -= lik * A[j * LDT + k];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// X = L^{-1} (lower) for the factor in LDS, by the column sweep from the last
+// column: X[j][j] = 1 / L[j][j] and X[i][j] = -X[j][j] sum_{j<k<=i} X[i][k]
+// L[k][j] for i > j (only columns > j of X are read).  Four lanes per row
+// split the inner products; one barrier per column.  X has leading dimension
+// LDT; its upper part is zero.
+__device__ inline void tile_trinv64(const double* L, double* X) {
+  const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
+  for (int c = q; c < kNB; c += 4) X[i * LDT + c] = 0.0;
+  __syncthreads();
+  for (int j = kNB - 1; j >= 0; --j) {
+    const double xjj = 1.0 / L[j * LDT + j];
+    double part = 0.0;
+    if (i > j)
+      for (int k = j + 1 + q; k <= i; k += 4) part += X[i * LDT + k] * L[k * LDT + j];
+    part += __shfl_xor(part, 1, 4);
+    part += __shfl_xor(part, 2, 4);
+    if (q == 0) {
+      if (i == j) X[i * LDT + j] = xjj;
+      else if (i > j) X[i * LDT + j] = -xjj * part;
+    }
+    __syncthreads();
   }
 }
 
 __global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ sys, int* flags,
-                                                    double* Lam, double* Ldiag,
+                                                    double* Lam, double* Ldiag, double* Linv,
                                                     const int* __restrict__ st_sys,
                                                     const int* __restrict__ st_pre, int cnt, int p) {
   __shared__ double sL[kNB * LDT];
-  __shared__ double sA[kNB * LDT];
+  __shared__ double sX[kNB * LDT];
   __shared__ int fl;
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
@@ -51,53 +105,56 @@ __global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ 
   double* A = Lam + sd.loff;
   const int tid = threadIdx.x;
   if (tid == 0) fl = 0;
-  load_tile_lower(sL, A + (int64_t)p * kNB * ld + (int64_t)p * kNB, ld);
+  const double* App = A + (int64_t)p * kNB * ld + (int64_t)p * kNB;
+  for (int e = tid; e < kNB * kNB; e += 256) sL[(e >> 6) * LDT + (e & 63)] = App[(int64_t)(e >> 6) * ld + (e & 63)];
   __syncthreads();
-  wg_potrf(sL, kNB, LDT, &fl);
+  tile_potrf64(sL, &fl);
+  tile_trinv64(sL, sX);
   if (t == 0) {
     double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
-    for (int e = tid; e < kNB * kNB; e += blockDim.x) {
-      const int r = e / kNB, c = e % kNB;
+    double* Dv = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int r = e >> 6, c = e & 63;
       D[e] = c <= r ? sL[r * LDT + c] : 0.0;
+      Dv[e] = sX[r * LDT + c];
     }
     if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
     return;
   }
+  // L_ip = A_ip L_pp^{-T}: C[r][c] = sum_k A_ip[r][k] X[c][k]
   const int i = p + t;
   double* Ai = A + (int64_t)i * kNB * ld + (int64_t)p * kNB;
-  for (int e = tid; e < kNB * kNB; e += blockDim.x) {
-    const int r = e / kNB, c = e % kNB;
-    sA[r * LDT + c] = Ai[(int64_t)r * ld + c];
-  }
   __syncthreads();
-  // row r of X solves x L_pp^T = a, i.e. L_pp x^T = a^T: forward
-  // substitution, four lanes per row splitting the inner products.
-  const int r = tid >> 2, q = tid & 3;
-  double xr[kNB / 4];
+  for (int e = tid; e < kNB * kNB; e += 256) sL[(e >> 6) * LDT + (e & 63)] = Ai[(int64_t)(e >> 6) * ld + (e & 63)];
+  __syncthreads();
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[4][4] = {};
+  for (int k = 0; k < kNB; ++k) {
+    double a[4], b[4];
 #pragma unroll
-  for (int c = 0; c < kNB; ++c) {
-    double part = 0.0;
+    for (int u = 0; u < 4; ++u) a[u] = sL[(ty + 16 * u) * LDT + k];
 #pragma unroll
-    for (int k = 0; k < c; ++k)
-      if ((k & 3) == q) part += xr[k >> 2] * sL[c * LDT + k];
-    part += __shfl_xor(part, 1, 4);
-    part += __shfl_xor(part, 2, 4);
-    const double xc = (sA[r * LDT + c] - part) / sL[c * LDT + c];
-    if ((c & 3) == q) xr[c >> 2] = xc;
+    for (int v = 0; v < 4; ++v) b[v] = sX[(tx + 16 * v) * LDT + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
   }
 #pragma unroll
-  for (int k = 0; k < kNB / 4; ++k) Ai[(int64_t)r * ld + k * 4 + q] = xr[k];
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ai[(int64_t)(ty + 16 * u) * ld + tx + 16 * v] = acc[u][v];
 }
 
-// A_ij -= L_ip L_jp^T for every tile p < j <= i; 4 x 4 outputs per thread,
-// the inner dimension (64) staged through LDS in chunks of 16.
+// A_ij -= L_ip L_jp^T for every tile p < j <= i, on FP64 MFMA: wave w owns
+// rows 16w..16w+15 and the four 16-column tiles; both panels staged in LDS.
 __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags, double* Lam,
                                                      const int* __restrict__ st_sys,
                                                      const int* __restrict__ st_pre, int cnt,
                                                      int p) {
-  __shared__ double sa[16 * 64];
-  __shared__ double sb[16 * 64];
+  __shared__ double sa[kNB * LDT];
+  __shared__ double sb[kNB * LDT];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
   const int t = blockIdx.x - st_pre[si];
@@ -105,7 +162,6 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
   double* A = Lam + sd.loff;
-  // triangular index t -> (ii >= jj)
   int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
   while (ii * (ii + 1) / 2 > t) --ii;
@@ -114,115 +170,82 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
   const double* Li = A + (int64_t)i * kNB * ld + (int64_t)p * kNB;
   const double* Lj = A + (int64_t)j * kNB * ld + (int64_t)p * kNB;
   double* C = A + (int64_t)i * kNB * ld + (int64_t)j * kNB;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    sa[r * LDT + c] = Li[(int64_t)r * ld + c];
+    sb[r * LDT + c] = Lj[(int64_t)r * ld + c];
+  }
+  __syncthreads();
+  v4d acc[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int u = 0; u < 4; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < kNB; k0 += 4) {
+    const double a = sa[(16 * w + r16) * LDT + k0 + kq];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int k0 = 0; k0 < kNB; k0 += 16) {
-    for (int e = tid; e < 1024; e += 256) {
-      const int kk = e & 15, rr = e >> 4;
-      sa[kk * 64 + rr] = Li[(int64_t)rr * ld + k0 + kk];
-      sb[kk * 64 + rr] = Lj[(int64_t)rr * ld + k0 + kk];
+    for (int u = 0; u < 4; ++u) {
+      const double b = sb[(16 * u + r16) * LDT + k0 + kq];
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
     }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = sa[kk * 64 + ty * 4 + u];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) b[u] = sb[kk * 64 + tx * 4 + u];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-    }
-    __syncthreads();
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int rr = ty * 4 + u;
+    const int cc = 16 * u + r16;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int cc = tx * 4 + v;
-      if (i != j || cc <= rr) C[(int64_t)rr * ld + cc] -= acc[u][v];
+    for (int q = 0; q < 4; ++q) {
+      const int rr = 16 * w + 4 * q + kq;
+      if (i != j || cc <= rr) C[(int64_t)rr * ld + cc] -= acc[u][q];
     }
   }
 }
 
-// wave-level solve of L x = b (lower, 64 x 64 in LDS) by lane-parallel
-// inner products; every lane ends with x[lane].
-__device__ inline double wave_fwd(const double* sL, double b_lane) {
-  const int lane = threadIdx.x & 63;
-  double x = 0.0;
-  for (int c = 0; c < kNB; ++c) {
-    double part = lane < c ? x * sL[c * LDT + lane] : 0.0;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
-    const double bc = __shfl(b_lane, c, 64);
-    const double xc = (bc - part) / sL[c * LDT + c];
-    if (lane == c) x = xc;
+// y = M x or M^T x for a 64 x 64 tile M in global memory (row-major, leading
+// dimension ldm) and x in LDS; four lanes per output row; result in LDS.
+__device__ inline void tile_mv64(const double* M, int64_t ldm, bool trans, const double* x,
+                                 double* y) {
+  const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
+  double part = 0.0;
+  if (!trans) {
+    for (int c = q; c < kNB; c += 4) part += M[(int64_t)row * ldm + c] * x[c];
+  } else {
+    for (int c = q; c < kNB; c += 4) part += M[(int64_t)c * ldm + row] * x[c];
   }
-  return x;
-}
-
-// wave-level solve of L^T x = b.
-__device__ inline double wave_bwd(const double* sL, double b_lane) {
-  const int lane = threadIdx.x & 63;
-  double x = 0.0;
-  for (int c = kNB - 1; c >= 0; --c) {
-    double part = lane > c ? sL[lane * LDT + c] * x : 0.0;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
-    const double bc = __shfl(b_lane, c, 64);
-    const double xc = (bc - part) / sL[c * LDT + c];
-    if (lane == c) x = xc;
-  }
-  return x;
+  part += __shfl_xor(part, 1, 4);
+  part += __shfl_xor(part, 2, 4);
+  if (q == 0) y[row] = part;
 }
 
 // forward step p: z_p = L_pp^{-1} r_p (tile 0 writes it); tiles i > p update
 // r_i -= L_ip z_p.
-__device__ inline void load_diag(double* s, const double* D) {
-  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) s[(e / kNB) * LDT + e % kNB] = D[e];
-}
-
 __global__ void __launch_bounds__(256) k_trsv_fwd(const SysDesc* __restrict__ sys,
                                                   const int* __restrict__ flags,
                                                   const double* __restrict__ Lam,
-                                                  const double* __restrict__ Ldiag, double* r,
+                                                  const double* __restrict__ Linv, double* r,
                                                   double* z, const int* __restrict__ st_sys,
                                                   const int* __restrict__ st_pre, int cnt, int p) {
-  __shared__ double sL[kNB * LDT];
-  __shared__ double sx[kNB];
+  __shared__ double sx[kNB], sz[kNB];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
   const int t = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
-  const double* A = Lam + sd.loff;
   double* rs = r + sd.voff;
   double* zs = z + sd.voff;
-  load_diag(sL, Ldiag + sd.dgoff + (int64_t)p * kNB * kNB);
+  if (threadIdx.x < kNB) sx[threadIdx.x] = rs[p * kNB + threadIdx.x];
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const double x = wave_fwd(sL, rs[p * kNB + threadIdx.x]);
-    sx[threadIdx.x] = x;
-    if (t == 0) zs[p * kNB + threadIdx.x] = x;
+  tile_mv64(Linv + sd.dgoff + (int64_t)p * kNB * kNB, kNB, false, sx, sz);
+  __syncthreads();
+  if (t == 0) {
+    if (threadIdx.x < kNB) zs[p * kNB + threadIdx.x] = sz[threadIdx.x];
+    return;
   }
-  __syncthreads();
-  if (t == 0) return;
   const int i = p + t;
-  const double* Li = A + (int64_t)i * kNB * ld + (int64_t)p * kNB;
-  const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
-  double part = 0.0;
-  for (int c = q; c < kNB; c += 4) part += Li[(int64_t)row * ld + c] * sx[c];
-  part += __shfl_xor(part, 1, 4);
-  part += __shfl_xor(part, 2, 4);
-  if (q == 0) rs[i * kNB + row] -= part;
+  tile_mv64(Lam + sd.loff + (int64_t)i * kNB * ld + (int64_t)p * kNB, ld, false, sz, sx);
+  __syncthreads();
+  if (threadIdx.x < kNB) rs[i * kNB + threadIdx.x] -= sx[threadIdx.x];
 }
 
 // backward step p: x_p = L_pp^{-T} z_p (tile p writes it); tiles i < p
@@ -230,44 +253,92 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const SysDesc* __restrict__ sy
 __global__ void __launch_bounds__(256) k_trsv_bwd(const SysDesc* __restrict__ sys,
                                                   const int* __restrict__ flags,
                                                   const double* __restrict__ Lam,
-                                                  const double* __restrict__ Ldiag, double* z,
+                                                  const double* __restrict__ Linv, double* z,
                                                   double* x, const int* __restrict__ st_sys,
                                                   const int* __restrict__ st_pre, int cnt, int p) {
-  __shared__ double sL[kNB * LDT];
-  __shared__ double sx[kNB];
+  __shared__ double sx[kNB], sz[kNB];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
   const int i = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
-  if (p >= sd.P) return;
   const int64_t ld = sd.Kpad;
-  const double* A = Lam + sd.loff;
   double* zs = z + sd.voff;
   double* xs = x + sd.voff;
-  load_diag(sL, Ldiag + sd.dgoff + (int64_t)p * kNB * kNB);
+  if (threadIdx.x < kNB) sz[threadIdx.x] = zs[p * kNB + threadIdx.x];
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const double v = wave_bwd(sL, zs[p * kNB + threadIdx.x]);
-    sx[threadIdx.x] = v;
-    if (i == p) xs[p * kNB + threadIdx.x] = v;
+  tile_mv64(Linv + sd.dgoff + (int64_t)p * kNB * kNB, kNB, true, sz, sx);
+  __syncthreads();
+  if (i == p) {
+    if (threadIdx.x < kNB) xs[p * kNB + threadIdx.x] = sx[threadIdx.x];
+    return;
   }
+  tile_mv64(Lam + sd.loff + (int64_t)p * kNB * ld + (int64_t)i * kNB, ld, true, sx, sz);
   __syncthreads();
-  if (i == p) return;
-  const double* Lpi = A + (int64_t)p * kNB * ld + (int64_t)i * kNB;
-  const int col = threadIdx.x >> 2, q = threadIdx.x & 3;
-  double part = 0.0;
-  for (int c = q; c < kNB; c += 4) part += Lpi[(int64_t)c * ld + col] * sx[c];
-  part += __shfl_xor(part, 1, 4);
-  part += __shfl_xor(part, 2, 4);
-  if (q == 0) zs[i * kNB + col] -= part;
+  if (threadIdx.x < kNB) zs[i * kNB + threadIdx.x] -= sz[threadIdx.x];
+}
+
+// Whole solve L L^T x = rhs for systems with few tiles: one workgroup per
+// system sweeps all tile steps (no inter-workgroup dependency).  r is
+// scratch; x receives the solution.
+__global__ void __launch_bounds__(256) k_trsv_small(const SysDesc* __restrict__ sys,
+                                                    const int* __restrict__ flags,
+                                                    const int* __restrict__ small_ids,
+                                                    const double* __restrict__ Lam,
+                                                    const double* __restrict__ Linv,
+                                                    const double* __restrict__ rhs, double* r,
+                                                    double* x) {
+  __shared__ double sv[kNB], sw[kNB];
+  const int s = small_ids[blockIdx.x];
+  if (!(flags[s] & F_ACTIVE)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  const double* A = Lam + sd.loff;
+  const double* Di = Linv + sd.dgoff;
+  double* rs = r + sd.voff;
+  double* xs = x + sd.voff;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < sd.Kpad; k += 256) rs[k] = rhs[sd.voff + k];
+  __syncthreads();
+  // forward: z_p = L_pp^{-1} r_p, r_i -= L_ip z_p (z kept in r)
+  for (int p = 0; p < sd.P; ++p) {
+    if (tid < kNB) sv[tid] = rs[p * kNB + tid];
+    __syncthreads();
+    tile_mv64(Di + (int64_t)p * kNB * kNB, kNB, false, sv, sw);
+    __syncthreads();
+    if (tid < kNB) rs[p * kNB + tid] = sw[tid];
+    const int rows = (sd.P - p - 1) * kNB;
+    for (int rr = tid; rr < rows; rr += 256) {
+      const double* Lrow = A + (int64_t)((p + 1) * kNB + rr) * ld + (int64_t)p * kNB;
+      double acc = 0.0;
+      for (int c = 0; c < kNB; ++c) acc += Lrow[c] * sw[c];
+      rs[(p + 1) * kNB + rr] -= acc;
+    }
+    __syncthreads();
+  }
+  // backward: x_p = L_pp^{-T} z_p, z_i -= L_pi^T x_p
+  for (int p = sd.P - 1; p >= 0; --p) {
+    if (tid < kNB) sv[tid] = rs[p * kNB + tid];
+    __syncthreads();
+    tile_mv64(Di + (int64_t)p * kNB * kNB, kNB, true, sv, sw);
+    __syncthreads();
+    if (tid < kNB) xs[p * kNB + tid] = sw[tid];
+    const int cols = p * kNB;
+    for (int cc = tid; cc < cols; cc += 256) {
+      double acc = 0.0;
+      for (int c = 0; c < kNB; ++c) acc += A[(int64_t)(p * kNB + c) * ld + cc] * sw[c];
+      rs[cc] -= acc;
+    }
+    __syncthreads();
+  }
 }
 
 // launch wrappers --------------------------------------------------------------
 
 void launch_chol_panel(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
-                       const int* ssys, const int* spre, int cnt, int total, int p) {
-  hipLaunchKernelGGL(k_chol_panel, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, ssys, spre, cnt, p);
+                       double* Linv, const int* ssys, const int* spre, int cnt, int total, int p) {
+  hipLaunchKernelGGL(k_chol_panel, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, ssys,
+                     spre, cnt, p);
 }
 
 void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
@@ -276,15 +347,23 @@ void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, do
 }
 
 void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Ldiag, double* r, double* z, const int* ssys, const int* spre,
+                     const double* Linv, double* r, double* z, const int* ssys, const int* spre,
                      int cnt, int total, int p) {
-  hipLaunchKernelGGL(k_trsv_fwd, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, r, z, ssys, spre, cnt, p);
+  hipLaunchKernelGGL(k_trsv_fwd, dim3(total), dim3(256), 0, st, sys, flags, Lam, Linv, r, z, ssys, spre, cnt, p);
 }
 
 void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Ldiag, double* z, double* x, const int* ssys, const int* spre,
+                     const double* Linv, double* z, double* x, const int* ssys, const int* spre,
                      int cnt, int total, int p) {
-  hipLaunchKernelGGL(k_trsv_bwd, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, z, x, ssys, spre, cnt, p);
+  hipLaunchKernelGGL(k_trsv_bwd, dim3(total), dim3(256), 0, st, sys, flags, Lam, Linv, z, x, ssys, spre, cnt, p);
+}
+
+void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int* flags,
+                       const int* small_ids, const double* Lam, const double* Linv,
+                       const double* rhs, double* r, double* x) {
+  if (nsmall)
+    hipLaunchKernelGGL(k_trsv_small, dim3(nsmall), dim3(256), 0, st, sys, flags, small_ids, Lam, Linv,
+                       rhs, r, x);
 }
 
 }  // namespace psdp

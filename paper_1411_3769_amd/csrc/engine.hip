@@ -96,7 +96,9 @@ struct Batch {
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
   std::vector<int> ownP, ownK;
-  StepTab pan, upd, bwd;
+  StepTab pan, upd, fwdL, bwdL;     // fwdL/bwdL: solve steps of the large systems only
+  std::vector<int> small_ids;
+  int* d_small = nullptr;
   int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0;
 
   // device
@@ -113,7 +115,7 @@ struct Batch {
   int *d_gpinfo = nullptr, *d_ownP = nullptr, *d_ownK = nullptr;
   int64_t* d_gpoff = nullptr;
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
-  int *d_bwd_sys = nullptr, *d_bwd_pre = nullptr;
+  int *d_fwdL_sys = nullptr, *d_fwdL_pre = nullptr, *d_bwdL_sys = nullptr, *d_bwdL_pre = nullptr;
   int* d_flags = nullptr;
   double* d_sc = nullptr;
   double* d_red = nullptr;
@@ -124,7 +126,7 @@ struct Batch {
   double *y, *dyh, *dyb, *r, *z, *BX, *rv1, *rv2, *ylift, *vtmp;
   bool any_phase1 = false;
   int maxK = 0;
-  double *Lam, *Ldiag, *Pm, *pre;
+  double *Lam, *Ldiag, *Linv, *Pm, *pre;
 
   ~Batch() {
     if (dtab) hipFree(dtab);
@@ -260,7 +262,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
 
   // ---- arena
   const int nblkarr = 15, nvec = 10;
-  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + B.totdg + B.totP + B.totpre;
+  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totP + B.totpre;
   if (hipMalloc((void**)&B.arena, std::max<int64_t>(total, 1) * 8) != hipSuccess)
     return fail(PSDP_ENOMEM, "device allocation of the solver arena failed (" +
                                  std::to_string(total * 8) + " bytes)");
@@ -273,6 +275,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   for (int i = 0; i < nvec; ++i) { *vecs[i] = a + o; o += B.totvec; }
   B.Lam = a + o; o += B.totlam;
   B.Ldiag = a + o; o += B.totdg;
+  B.Linv = a + o; o += B.totdg;
   B.Pm = a + o; o += B.totP;
   B.pre = a + o; o += B.totpre;
   const int64_t preBase = B.pre - a, ziBase = B.Zi - a, xBase = B.X - a;
@@ -331,17 +334,23 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   B.nptiles = (int)B.ptiles.size();
 
   // ---- Cholesky step tables
+  for (int s = 0; s < count; ++s)
+    if (B.sys[s].P <= kSmallP) B.small_ids.push_back(s);
   for (int pstep = 0; pstep < B.maxP; ++pstep) {
     B.pan.add_step();
     B.upd.add_step();
-    B.bwd.add_step();
+    B.fwdL.add_step();
+    B.bwdL.add_step();
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (P <= pstep) continue;
       B.pan.add(s, P - pstep);
       const int T = P - pstep - 1;
       if (T > 0) B.upd.add(s, T * (T + 1) / 2);
-      B.bwd.add(s, pstep + 1);
+      if (P > kSmallP) {
+        B.fwdL.add(s, P - pstep);
+        B.bwdL.add(s, pstep + 1);
+      }
     }
   }
 
@@ -353,7 +362,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   tb += tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(B.csr_hh) + tabsize(B.csr_hid);
   tb += tabsize(B.csr_mh) + tabsize(B.csr_hl);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
-  tb += tabsize(B.bwd.sys) + tabsize(B.bwd.pre);
+  tb += tabsize(B.fwdL.sys) + tabsize(B.fwdL.pre) + tabsize(B.bwdL.sys) + tabsize(B.bwdL.pre);
+  tb += tabsize(B.small_ids);
   tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 4 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256 + 4096;
@@ -402,8 +412,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   if ((rc = upload(B.dtab, off, B.pan.pre, &B.d_pan_pre))) return rc;
   if ((rc = upload(B.dtab, off, B.upd.sys, &B.d_upd_sys))) return rc;
   if ((rc = upload(B.dtab, off, B.upd.pre, &B.d_upd_pre))) return rc;
-  if ((rc = upload(B.dtab, off, B.bwd.sys, &B.d_bwd_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.bwd.pre, &B.d_bwd_pre))) return rc;
+  if ((rc = upload(B.dtab, off, B.fwdL.sys, &B.d_fwdL_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.fwdL.pre, &B.d_fwdL_pre))) return rc;
+  if ((rc = upload(B.dtab, off, B.bwdL.sys, &B.d_bwdL_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.bwdL.pre, &B.d_bwdL_pre))) return rc;
+  if ((rc = upload(B.dtab, off, B.small_ids, &B.d_small))) return rc;
   char* base = (char*)B.dtab;
   B.d_flags = (int*)(base + off); off += ((size_t)B.S * 4 + 255) / 256 * 256;
   B.d_sc = (double*)(base + off); off += ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
@@ -417,6 +430,19 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
 // operator helpers
 // ---------------------------------------------------------------------------
 
+// C_b = alpha op(A_b) op(B_b) + beta D_b over every block (small-n packing when
+// every block has n <= 16).
+static void gemm_blocks(Batch& B, hipStream_t st, const double* A, int tA, const double* Bm, int tB,
+                        double* C, double alpha, int aslot, const double* D, double beta,
+                        int bslot) {
+  if (use_small(B.maxn))
+    launch_gemm_blocks_small(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.d_sc, A, tA, Bm, tB, C, alpha,
+                             aslot, D, beta, bslot);
+  else
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, A, tA, Bm, tB, C, alpha, aslot, D,
+                       beta, bslot);
+}
+
 // B^T(y) for every active system; phase-I systems use B'^T (lift + t D).
 static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool phase_aware = true) {
   const size_t m0 = B.prof.mark();
@@ -427,7 +453,10 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
   }
   launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, ybase, B.Pm);
   launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out);
-  launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
+  if (use_small(B.maxn))
+    launch_BT_dblk_small(st, B.ndblk, B.maxn, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
+  else
+    launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
   if (phase_aware && B.any_phase1) launch_sub_tD(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, yv, out);
   B.prof.add(PSDP_PROF_BT, m0, B.prof.mark());
 }
@@ -437,7 +466,10 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
 static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double asub,
                  bool phase_aware = true) {
   const size_t m0 = B.prof.mark();
-  launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
+  if (use_small(B.maxn))
+    launch_B_Y_small(st, B.npairs, B.maxn, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
+  else
+    launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
   launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
                   out, asub);
   if (phase_aware && B.any_phase1) launch_B_phase1(st, B.S, B.d_sys, B.d_flags, B.d_blk, W, out, asub);
@@ -446,8 +478,14 @@ static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double 
 
 static void op_schur(Batch& B, hipStream_t st) {
   const size_t m0 = B.prof.mark();
-  launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1);
-  launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena);
+  if (use_small(B.maxn)) {
+    launch_pre12_small(st, B.npairs, B.maxn, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk,
+                       B.d_offA1);
+    launch_pre34_small(st, B.nq2, B.maxn, B.d_q2, B.d_sys, B.d_flags, B.arena);
+  } else {
+    launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1);
+    launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena);
+  }
   const size_t m1 = B.prof.mark();
   launch_assemble_pair(st, B.nptiles, B.maxn_pair, B.d_ptiles, B.d_terms, B.d_sys, B.d_flags,
                        B.arena, B.Lam);
@@ -470,8 +508,8 @@ static void op_factor(Batch& B, hipStream_t st) {
   for (int p = 0; p < B.maxP; ++p) {
     const int f = B.pan.first[p];
     const size_t m0 = B.prof.mark();
-    launch_chol_panel(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.d_pan_sys + f, B.d_pan_pre + f,
-                      B.pan.cnt[p], B.pan.tot[p], p);
+    launch_chol_panel(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.d_pan_sys + f,
+                      B.d_pan_pre + f, B.pan.cnt[p], B.pan.tot[p], p);
     const size_t m1 = B.prof.mark();
     B.prof.add(PSDP_PROF_CHOL_PANEL, m0, m1);
     if (B.upd.tot[p] > 0) {
@@ -485,16 +523,22 @@ static void op_factor(Batch& B, hipStream_t st) {
 
 static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
   const size_t m0 = B.prof.mark();
-  PSDP_HIP(hipMemcpyAsync(B.r, rhs, B.totvec * 8, hipMemcpyDeviceToDevice, st));
-  for (int p = 0; p < B.maxP; ++p) {
-    const int f = B.pan.first[p];
-    launch_trsv_fwd(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.r, B.z, B.d_pan_sys + f,
-                    B.d_pan_pre + f, B.pan.cnt[p], B.pan.tot[p], p);
-  }
-  for (int p = B.maxP - 1; p >= 0; --p) {
-    const int f = B.bwd.first[p];
-    launch_trsv_bwd(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.z, x, B.d_bwd_sys + f,
-                    B.d_bwd_pre + f, B.bwd.cnt[p], B.bwd.tot[p], p);
+  launch_trsv_small(st, (int)B.small_ids.size(), B.d_sys, B.d_flags, B.d_small, B.Lam, B.Linv, rhs,
+                    B.r, x);
+  if (B.small_ids.size() < (size_t)B.S) {
+    PSDP_HIP(hipMemcpyAsync(B.r, rhs, B.totvec * 8, hipMemcpyDeviceToDevice, st));
+    for (int p = 0; p < B.maxP; ++p) {
+      if (B.fwdL.tot[p] == 0) continue;
+      const int f = B.fwdL.first[p];
+      launch_trsv_fwd(st, B.d_sys, B.d_flags, B.Lam, B.Linv, B.r, B.z, B.d_fwdL_sys + f,
+                      B.d_fwdL_pre + f, B.fwdL.cnt[p], B.fwdL.tot[p], p);
+    }
+    for (int p = B.maxP - 1; p >= 0; --p) {
+      if (B.bwdL.tot[p] == 0) continue;
+      const int f = B.bwdL.first[p];
+      launch_trsv_bwd(st, B.d_sys, B.d_flags, B.Lam, B.Linv, B.z, x, B.d_bwdL_sys + f,
+                      B.d_bwdL_pre + f, B.bwdL.cnt[p], B.bwdL.tot[p], p);
+    }
   }
   B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());
   return PSDP_OK;
@@ -618,10 +662,10 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     op_factor(B, st);
     // Omega_1 = B(Z^-1 G X) - a
     { const size_t pm_ = B.prof.mark();
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.G, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    gemm_blocks(B, st, B.Zi, 0, B.G, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.W1, 1.0, -1, nullptr, 0.0, -1);
+    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.W1, 1.0, -1, nullptr, 0.0, -1);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
@@ -634,14 +678,14 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     launch_axpby(st, B.nblk, B.d_blk, B.d_flags, -1.0, B.G, 1.0, B.S1, B.dZh);
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.dZh, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    gemm_blocks(B, st, B.Zi, 0, B.dZh, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.dXh, -1.0, -1, B.X, -1.0, -1);
+    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.dXh, -1.0, -1, B.X, -1.0, -1);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     // corrector right-hand side: W = mu Z^-1 - Z^-1 dZ^ dX^
     { const size_t pm_ = B.prof.mark();
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.dXh, 0, B.Wc, -1.0, -1, B.Zi, 1.0, S_MU);
+    gemm_blocks(B, st, B.T1, 0, B.dXh, 0, B.Wc, -1.0, -1, B.Zi, 1.0, S_MU);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.Wc, B.W1);
@@ -651,10 +695,10 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     // corrector directions (processors step 3)
     op_BT(B, st, B.dyb, B.dZb);
     { const size_t pm_ = B.prof.mark();
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.Zi, 0, B.dZb, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    gemm_blocks(B, st, B.Zi, 0, B.dZb, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.T1, 0, B.X, 0, B.dXb, -1.0, -1, B.Wc, 1.0, -1);
+    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.dXb, -1.0, -1, B.Wc, 1.0, -1);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
     launch_combine(st, B.nblk, B.d_blk, B.d_flags, B.dXh, B.dXb, B.dX, B.dZh, B.dZb, B.dZ);

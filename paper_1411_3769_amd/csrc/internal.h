@@ -136,15 +136,19 @@ int64_t round_up(int64_t x, int64_t m);
 
 // Schur Cholesky / triangular solve launches (chol.hip)
 void launch_chol_panel(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
-                       const int* ssys, const int* spre, int cnt, int total, int p);
+                       double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
                         const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Ldiag, double* r, double* z, const int* ssys, const int* spre,
+                     const double* Linv, double* r, double* z, const int* ssys, const int* spre,
                      int cnt, int total, int p);
 void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Ldiag, double* z, double* x, const int* ssys, const int* spre,
+                     const double* Linv, double* z, double* x, const int* ssys, const int* spre,
                      int cnt, int total, int p);
+void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int* flags,
+                       const int* small_ids, const double* Lam, const double* Linv,
+                       const double* rhs, double* r, double* x);
+constexpr int kSmallP = 32;   // systems with at most this many Schur tiles solve in one launch
 
 // engine entry used by the public solve / eval calls
 int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res);

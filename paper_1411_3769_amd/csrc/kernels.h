@@ -60,6 +60,20 @@ void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* t
 void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
                          const SysDesc* sys, const int* flags, const int* gpinfo,
                          const double* arena, double* Lam, const int64_t* gpoff);
+bool use_small(int nmax);
+void launch_gemm_blocks_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks,
+                              const int* flags, const double* sc, const double* A, int tA,
+                              const double* B, int tB, double* C, double alpha, int aslot,
+                              const double* D, double beta, int bslot);
+void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks,
+                          const SysDesc* sys, const int* flags, const double* Pm, double* out);
+void launch_B_Y_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
+                      const int* flags, const double* W, double* arena, const BlkDesc* blks);
+void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
+                        const int* flags, const double* Zi, const double* X, double* arena,
+                        const BlkDesc* blks, const int64_t* offA1);
+void launch_pre34_small(hipStream_t st, int nq, int nmax, const HM2* q, const SysDesc* sys,
+                        const int* flags, double* arena);
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam);
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,

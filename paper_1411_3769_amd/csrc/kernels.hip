@@ -1018,6 +1018,123 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Small blocks (n <= 16): G = 256 / nmax^2 products per workgroup, one output
+// entry per thread, operands read directly (they stay in cache).
+// ---------------------------------------------------------------------------
+__device__ inline double dot_n(int n, int i, int j, const double* __restrict__ A, int tA,
+                               const double* __restrict__ B, int tB) {
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double a = tA ? A[k * n + i] : A[i * n + k];
+    const double b = tB ? B[j * n + k] : B[k * n + j];
+    acc += a * b;
+  }
+  return acc;
+}
+
+#define SMALL_ITEM(count)                                   \
+  const int per_ = nmax * nmax;                             \
+  const int item = blockIdx.x * G + (int)threadIdx.x / per_; \
+  const int e_ = (int)threadIdx.x % per_;                   \
+  if ((int)threadIdx.x >= G * per_ || item >= (count)) return;
+
+__global__ void __launch_bounds__(256) k_gemm_blocks_small(
+    int nblk, int nmax, int G, const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+    const double* __restrict__ sc, const double* A, int tA, const double* B, int tB, double* C,
+    double alpha, int aslot, const double* D, double beta, int bslot) {
+  SMALL_ITEM(nblk);
+  const BlkDesc bd = blks[item];
+  if (!(flags[bd.sys] & F_ACTIVE)) return;
+  const int n = bd.n;
+  if (e_ >= n * n) return;
+  const int i = e_ / n, j = e_ % n;
+  double a = alpha, c = beta;
+  if (aslot >= 0) a *= sc[bd.sys * kNSC + aslot];
+  if (bslot >= 0) c *= sc[bd.sys * kNSC + bslot];
+  double v = a * dot_n(n, i, j, A + bd.off, tA, B + bd.off, tB);
+  if (D) v += c * D[bd.off + e_];
+  C[bd.off + e_] = v;
+}
+
+__global__ void __launch_bounds__(256) k_BT_dblk_small(int nd, int nmax, int G,
+                                                       const BlkDesc* __restrict__ dblks,
+                                                       const SysDesc* __restrict__ sys,
+                                                       const int* __restrict__ flags,
+                                                       const double* __restrict__ Pm, double* out) {
+  SMALL_ITEM(nd);
+  const BlkDesc bd = dblks[item];
+  if (!(flags[bd.sys] & F_ACTIVE)) return;
+  const SysDesc sd = sys[bd.sys];
+  const int n = bd.n, nn = n * n;
+  if (e_ >= nn) return;
+  const int i = e_ / n, j = e_ % n, m = bd.j - sd.L;
+  double acc = 0.0;
+  for (int c = sd.h_by_m[m]; c < sd.h_by_m[m + 1]; ++c) {
+    const int h = sd.h_list[c];
+    const double* Hm = sd.H + ((int64_t)m * sd.L0 + h) * nn;
+    const double* Ph = Pm + sd.poff + (int64_t)h * nn;
+    acc += dot_n(n, i, j, Ph, 0, Hm, 0) + dot_n(n, j, i, Ph, 0, Hm, 0);
+  }
+  out[bd.off + e_] = -acc;
+}
+
+__global__ void __launch_bounds__(256) k_B_Y_small(int np, int nmax, int G,
+                                                   const HMPair* __restrict__ pairs,
+                                                   const SysDesc* __restrict__ sys,
+                                                   const int* __restrict__ flags,
+                                                   const double* __restrict__ W, double* arena,
+                                                   const BlkDesc* __restrict__ blks) {
+  SMALL_ITEM(np);
+  const HMPair pr = pairs[item];
+  if (!(flags[pr.sys] & F_ACTIVE)) return;
+  const SysDesc sd = sys[pr.sys];
+  const int n = pr.n, nn = n * n;
+  if (e_ >= nn) return;
+  const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
+  const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
+  arena[pr.offY + e_] = dot_n(n, e_ / n, e_ % n, Hm, 0, W + bd.off, 0);
+}
+
+__global__ void __launch_bounds__(256) k_pre12_small(int np, int nmax, int G,
+                                                     const HMPair* __restrict__ pairs,
+                                                     const SysDesc* __restrict__ sys,
+                                                     const int* __restrict__ flags,
+                                                     const double* __restrict__ Zi,
+                                                     const double* __restrict__ X, double* arena,
+                                                     const BlkDesc* __restrict__ blks,
+                                                     const int64_t* __restrict__ offA1) {
+  SMALL_ITEM(np);
+  const HMPair pr = pairs[item];
+  if (!(flags[pr.sys] & F_ACTIVE)) return;
+  const SysDesc sd = sys[pr.sys];
+  const int n = pr.n, nn = n * n;
+  if (e_ >= nn) return;
+  const int i = e_ / n, j = e_ % n;
+  const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
+  const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
+  arena[offA1[item] + e_] = dot_n(n, i, j, Zi + bd.off, 0, Hm, 1);
+  arena[pr.offA2 + e_] = dot_n(n, i, j, X + bd.off, 0, Hm, 1);
+}
+
+__global__ void __launch_bounds__(256) k_pre34_small(int nq, int nmax, int G,
+                                                     const HM2* __restrict__ q,
+                                                     const SysDesc* __restrict__ sys,
+                                                     const int* __restrict__ flags,
+                                                     double* arena) {
+  SMALL_ITEM(nq);
+  const HM2 pr = q[item];
+  if (!(flags[pr.sys] & F_ACTIVE)) return;
+  const SysDesc sd = sys[pr.sys];
+  const int n = pr.n, nn = n * n;
+  if (e_ >= nn) return;
+  const int i = e_ / n, j = e_ % n;
+  const double* Hh = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
+  arena[pr.offA3 + e_] = dot_n(n, i, j, Hh, 0, arena + pr.srcA2, 0);
+  arena[pr.offA4 + e_] = dot_n(n, i, j, Hh, 0, arena + pr.srcA1, 0);
+}
+
 // launch wrappers ----------------------------------------------------------------
 
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam) {
@@ -1205,6 +1322,48 @@ void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const
   if (!ntiles) return;
   hipLaunchKernelGGL(k_assemble_grp, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags, gpinfo,
                      arena, Lam, gpoff);
+}
+
+}  // namespace psdp
+
+namespace psdp {
+
+static int small_G(int nmax) { return nmax <= 16 ? 256 / (nmax * nmax) : 0; }
+
+bool use_small(int nmax) { return small_G(nmax) > 0; }
+
+void launch_gemm_blocks_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks,
+                              const int* flags, const double* sc, const double* A, int tA,
+                              const double* B, int tB, double* C, double alpha, int aslot,
+                              const double* D, double beta, int bslot) {
+  const int G = small_G(nmax);
+  hipLaunchKernelGGL(k_gemm_blocks_small, dim3((nblk + G - 1) / G), dim3(256), 0, st, nblk, nmax, G,
+                     blks, flags, sc, A, tA, B, tB, C, alpha, aslot, D, beta, bslot);
+}
+
+void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks,
+                          const SysDesc* sys, const int* flags, const double* Pm, double* out) {
+  const int G = small_G(nmax);
+  if (nd) hipLaunchKernelGGL(k_BT_dblk_small, dim3((nd + G - 1) / G), dim3(256), 0, st, nd, nmax, G, dblks, sys, flags, Pm, out);
+}
+
+void launch_B_Y_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
+                      const int* flags, const double* W, double* arena, const BlkDesc* blks) {
+  const int G = small_G(nmax);
+  if (np) hipLaunchKernelGGL(k_B_Y_small, dim3((np + G - 1) / G), dim3(256), 0, st, np, nmax, G, pairs, sys, flags, W, arena, blks);
+}
+
+void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
+                        const int* flags, const double* Zi, const double* X, double* arena,
+                        const BlkDesc* blks, const int64_t* offA1) {
+  const int G = small_G(nmax);
+  if (np) hipLaunchKernelGGL(k_pre12_small, dim3((np + G - 1) / G), dim3(256), 0, st, np, nmax, G, pairs, sys, flags, Zi, X, arena, blks, offA1);
+}
+
+void launch_pre34_small(hipStream_t st, int nq, int nmax, const HM2* q, const SysDesc* sys,
+                        const int* flags, double* arena) {
+  const int G = small_G(nmax);
+  if (nq) hipLaunchKernelGGL(k_pre34_small, dim3((nq + G - 1) / G), dim3(256), 0, st, nq, nmax, G, q, sys, flags, arena);
 }
 
 }  // namespace psdp
