@@ -31,62 +31,101 @@ namespace psdp {
 constexpr int LDT = kNB + 1;   // LDS leading dimension of a 64 x 64 tile
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// In-place lower Cholesky of a 64 x 64 tile in LDS (leading dimension LDT)
-// with 256 threads and two barriers per column: the scaled column, then the
-// rank-one trailing update over a 16 x 16 thread grid (the pivot itself is
-// stored during the update phase, when nobody reads it).  Non-positive or
-// non-finite pivots set *fail and are replaced by 1.
-__device__ inline void tile_potrf64(double* A, int* fail) {
+// Register-resident factorisation of a 64 x 64 tile with 256 threads: thread
+// (tr, tc) owns rows tr + 16a and columns tc + 16b (a, b < 4).  Column k is
+// broadcast through a double-buffered LDS vector, so each column costs one
+// barrier and eight LDS reads per thread.  Non-positive or non-finite pivots
+// set *fail and are replaced by 1.  On return reg holds L (lower part).
+__device__ inline void reg_potrf64(double (&reg)[4][4], double* colbuf /*2 x 64*/, int* fail) {
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  // publish column 0
+  if (tc == 0)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) colbuf[tr + 16 * a] = reg[a][0];
   for (int k = 0; k < kNB; ++k) {
-    __syncthreads();   // the previous trailing update is complete
-    double d = A[k * LDT + k];
+    __syncthreads();
+    const double* cb = colbuf + (k & 1) * kNB;
+    double d = cb[k];
     const bool bad = !(d > 0.0) || !isfinite(d);
-    if (bad) d = 1.0;
+    d = bad ? 1.0 : d;
     const double piv = sqrt(d);
-    if (tid > k && tid < kNB) A[tid * LDT + k] = A[tid * LDT + k] / piv;
-    __syncthreads();   // column k scaled; every thread has read A[k][k]
-    if (tid == k) {
-      A[k * LDT + k] = piv;
-      if (bad) *fail = 1;
-    }
+    const double rpiv = 1.0 / piv;   // one reciprocal per column, then products
+    if (bad && tid == 0) *fail = 1;
+    double li[4], lj[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) li[a] = cb[tr + 16 * a] * rpiv;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) lj[b] = cb[tc + 16 * b] * rpiv;
+    // branch-free update of the owned 4 x 4 block
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int i = tr + 16 * a;
-      if (i <= k) continue;
-      const double lik = A[i * LDT + k];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int j = tc + 16 * b;
-        if (j > k && j <= i) A[i * LDT + j] -= lik * A[j * LDT + k];
+        const double upd = reg[a][b] - li[a] * lj[b];
+        const double colk = i > k ? li[a] : (i == k ? piv : reg[a][b]);
+        reg[a][b] = j == k ? colk : ((j > k && j <= i) ? upd : reg[a][b]);
+      }
+    }
+    // publish column k+1 (final: all updates through column k applied)
+    const int kn = k + 1;
+    if (kn < kNB && tc == (kn & 15)) {
+      const int bs = kn >> 4;
+      double* nb = colbuf + (kn & 1) * kNB;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double v = bs == 0 ? reg[a][0] : bs == 1 ? reg[a][1] : bs == 2 ? reg[a][2] : reg[a][3];
+        nb[tr + 16 * a] = v;
       }
     }
   }
   __syncthreads();
 }
 
-// X = L^{-1} (lower) for the factor in LDS, by the column sweep from the last
-// column: X[j][j] = 1 / L[j][j] and X[i][j] = -X[j][j] sum_{j<k<=i} X[i][k]
-// L[k][j] for i > j (only columns > j of X are read).  Four lanes per row
-// split the inner products; one barrier per column.  X has leading dimension
-// LDT; its upper part is zero.
-__device__ inline void tile_trinv64(const double* L, double* X) {
-  const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
-  for (int c = q; c < kNB; c += 4) X[i * LDT + c] = 0.0;
+// X = L^{-1} by forward substitution on the identity, register-resident in the
+// same 4 x 4 ownership: step k scales row k of X by 1/L[k][k] (reciprocals
+// of the diagonal precomputed) and removes L[i][k] X[k][:] from every row
+// i > k.  L is read from LDS (leading dimension LDT), row k of X is broadcast
+// through a double-buffered LDS vector.
+__device__ inline void reg_trinv64(const double* sL, double (&X)[4][4], double* rowbuf,
+                                   double* rdiag) {
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  if (tid < kNB) rdiag[tid] = 1.0 / sL[tid * LDT + tid];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) X[a][b] = (tr + 16 * a == tc + 16 * b) ? 1.0 : 0.0;
   __syncthreads();
-  for (int j = kNB - 1; j >= 0; --j) {
-    const double xjj = 1.0 / L[j * LDT + j];
-    double part = 0.0;
-    if (i > j)
-      for (int k = j + 1 + q; k <= i; k += 4) part += X[i * LDT + k] * L[k * LDT + j];
-    part += __shfl_xor(part, 1, 4);
-    part += __shfl_xor(part, 2, 4);
-    if (q == 0) {
-      if (i == j) X[i * LDT + j] = xjj;
-      else if (i > j) X[i * LDT + j] = -xjj * part;
+  for (int k = 0; k < kNB; ++k) {
+    double* rb = rowbuf + (k & 1) * kNB;
+    const double rkk = rdiag[k];
+    // the owners of row k scale it and publish it
+    if (tr == (k & 15)) {
+      const int as = k >> 4;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) X[a][b] = a == as ? X[a][b] * rkk : X[a][b];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double v = as == 0 ? X[0][b] : as == 1 ? X[1][b] : as == 2 ? X[2][b] : X[3][b];
+        rb[tc + 16 * b] = v;
+      }
     }
     __syncthreads();
+    double xk[4], lik[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xk[b] = rb[tc + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lik[a] = sL[(tr + 16 * a) * LDT + k];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (tr + 16 * a > k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) X[a][b] -= lik[a] * xk[b];
   }
+  __syncthreads();
 }
 
 __global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ sys, int* flags,
@@ -95,6 +134,8 @@ __global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ 
                                                     const int* __restrict__ st_pre, int cnt, int p) {
   __shared__ double sL[kNB * LDT];
   __shared__ double sX[kNB * LDT];
+  __shared__ double vbuf[2 * kNB];
+  __shared__ double rdiag[kNB];
   __shared__ int fl;
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
@@ -103,47 +144,63 @@ __global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ 
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
   double* A = Lam + sd.loff;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   if (tid == 0) fl = 0;
   const double* App = A + (int64_t)p * kNB * ld + (int64_t)p * kNB;
-  for (int e = tid; e < kNB * kNB; e += 256) sL[(e >> 6) * LDT + (e & 63)] = App[(int64_t)(e >> 6) * ld + (e & 63)];
+  double reg[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) reg[a][b] = App[(int64_t)(tr + 16 * a) * ld + tc + 16 * b];
+  reg_potrf64(reg, vbuf, &fl);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      sL[i * LDT + j] = j <= i ? reg[a][b] : 0.0;
+    }
   __syncthreads();
-  tile_potrf64(sL, &fl);
-  tile_trinv64(sL, sX);
+  double X[4][4];
+  reg_trinv64(sL, X, vbuf, rdiag);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) sX[(tr + 16 * a) * LDT + tc + 16 * b] = X[a][b];
+  __syncthreads();
   if (t == 0) {
     double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
     double* Dv = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
     for (int e = tid; e < kNB * kNB; e += 256) {
       const int r = e >> 6, c = e & 63;
-      D[e] = c <= r ? sL[r * LDT + c] : 0.0;
+      D[e] = sL[r * LDT + c];
       Dv[e] = sX[r * LDT + c];
     }
     if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
     return;
   }
-  // L_ip = A_ip L_pp^{-T}: C[r][c] = sum_k A_ip[r][k] X[c][k]
+  // L_ip = A_ip L_pp^{-T} on MFMA: C[r][c] = sum_k A_ip[r][k] X[c][k]
   const int i = p + t;
   double* Ai = A + (int64_t)i * kNB * ld + (int64_t)p * kNB;
-  __syncthreads();
   for (int e = tid; e < kNB * kNB; e += 256) sL[(e >> 6) * LDT + (e & 63)] = Ai[(int64_t)(e >> 6) * ld + (e & 63)];
   __syncthreads();
-  const int ty = tid >> 4, tx = tid & 15;
-  double acc[4][4] = {};
-  for (int k = 0; k < kNB; ++k) {
-    double a[4], b[4];
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  v4d acc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = sL[(ty + 16 * u) * LDT + k];
+  for (int u = 0; u < 4; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kNB; k0 += 4) {
+    const double av = sL[(16 * w + r16) * LDT + k0 + kq];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) b[v] = sX[(tx + 16 * v) * LDT + k];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    for (int u = 0; u < 4; ++u) {
+      const double bv = sX[(16 * u + r16) * LDT + k0 + kq];
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Ai[(int64_t)(ty + 16 * u) * ld + tx + 16 * v] = acc[u][v];
+    for (int q = 0; q < 4; ++q) Ai[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16] = acc[u][q];
 }
 
 // A_ij -= L_ip L_jp^T for every tile p < j <= i, on FP64 MFMA: wave w owns
