@@ -63,9 +63,15 @@ extern "C" {
 #define PSDP_VERDICT_PAPER_ONLY        1
 #define PSDP_VERDICT_PHASE1_ONLY       2
 
-/* arithmetic of the Schur complement assembly (the Cholesky is FP64 always) */
+/* arithmetic of the Schur complement assembly (the Cholesky is FP64 always).
+ * FP32 / BF16: the block products are rounded to FP32 / BF16 (BF16 through
+ * FP32, nearest-even) and multiplied on MFMA with FP32 accumulation; every
+ * Newton solve is refined against the FP64 matrix-free Schur product, and a
+ * system falls back to FP64 assembly when the refinement stops converging
+ * (see ir_eta_max). */
 #define PSDP_PREC_FP64 0
 #define PSDP_PREC_FP32 1
+#define PSDP_PREC_BF16 2
 
 typedef struct psdp_sdp psdp_sdp;  /* opaque handle: one structured SDP */
 
@@ -115,7 +121,11 @@ typedef struct {
     double ladder_rho;    /* ratio of the step ladder (0.9)                          */
     int    ladder_len;    /* rungs of the ladder (300)                               */
     int    verdict_mode;  /* PSDP_VERDICT_*                                          */
-    int    precision;     /* PSDP_PREC_*                                             */
+    int    precision;     /* PSDP_PREC_*: arithmetic of the Schur assembly           */
+    int    ir_max;        /* most refinement corrections per Newton solve against   */
+                          /* the matrix-free FP64 product B(Z^-1 B^T(v) X); a solve */
+                          /* stops early once its residual ratio reaches 1e-14 or    */
+                          /* stops falling below 1e-10. -1 = 0 for FP64, 6 for FP32 */
     void*  stream;        /* hipStream_t, NULL = null stream                         */
     int    record_history;/* 1: fill psdp_result.history (host memory, caller owns)  */
     double* prof;         /* NULL, or a caller array [PSDP_NPROF][2] that receives,  */
@@ -143,6 +153,14 @@ typedef struct {
     int     phase1_iterations;
     double  t_star;         /* phase-I optimum (normalised margin), NaN if unused    */
     double  time_solve_s;   /* wall time of the solve call                           */
+    int     iters_lowprec;  /* iterations whose Schur matrix was assembled in FP32   */
+    int     ir_steps;       /* refinement steps applied to this system's solves      */
+    double  ir_eta_max;     /* largest ||Omega - Lambda v0|| / ||Omega|| (inf norms) */
+                            /* after the unrefined solve, over those iterations;     */
+                            /* NaN if none. A ratio above 0.1, a solve that the      */
+                            /* refinement cannot bring below 1e-10, or a failed      */
+                            /* Cholesky of the reduced-precision matrix switches the */
+                            /* system to FP64 assembly for the rest of the run       */
     psdp_iter_rec* history; /* caller buffer of history_cap records, or NULL         */
     int     history_cap;
     int     history_len;

@@ -125,6 +125,10 @@ struct Batch {
   double *X, *Z, *Zi, *G, *S1, *T1, *W1, *dXh, *dZh, *Wc, *dXb, *dZb, *dX, *dZ, *Cf;
   double *y, *dyh, *dyb, *r, *z, *BX, *rv1, *rv2, *ylift, *vtmp;
   bool any_phase1 = false;
+  bool f32 = false;   // precision form: reduced-precision Schur assembly + refinement
+  int prec = PSDP_PREC_FP64;
+  int ir_max = 0;
+  std::vector<char> asm64;   // per system: fell back to FP64 assembly (sticky)
   int maxK = 0;
   double *Lam, *Ldiag, *Linv, *Pm, *pre;
 
@@ -488,9 +492,9 @@ static void op_schur(Batch& B, hipStream_t st) {
   }
   const size_t m1 = B.prof.mark();
   launch_assemble_pair(st, B.nptiles, B.maxn_pair, B.d_ptiles, B.d_terms, B.d_sys, B.d_flags,
-                       B.arena, B.Lam);
+                       B.arena, B.Lam, B.prec);
   launch_assemble_grp(st, B.ntiles, B.d_tiles, B.d_terms, B.d_sys, B.d_flags, B.d_gpinfo, B.arena,
-                      B.Lam, B.d_gpoff);
+                      B.Lam, B.d_gpoff, B.prec);
   const size_t m2 = B.prof.mark();
   B.prof.add(PSDP_PROF_PRE, m0, m1);
   B.prof.add(PSDP_PROF_ASSEMBLE, m1, m2);
@@ -544,6 +548,33 @@ static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
   return PSDP_OK;
 }
 
+// Newton solve with iterative refinement (Section IV-A: Lambda v is
+// B(Z^-1 B^T(v) X), the Schur complement applied without forming it):
+// x = F^{-1} rhs, then up to ir_max corrections x += F^{-1} r with
+// r = rhs - Lambda x in FP64.  Each system leaves the loop (parked) once its
+// residual is accepted or stops falling; in the precision form the systems
+// assembled in FP64 are parked from the start.  first = the iteration's first
+// solve.  Scratch: S1, T1, W1 (block arrays free during the solves), BX, vtmp.
+static int op_solve_refined(Batch& B, hipStream_t st, const double* rhs, double* x, bool first) {
+  int rc = op_solve(B, st, rhs, x);
+  if (rc || B.ir_max == 0) return rc;
+  if (B.f32) launch_park(st, B.S, B.d_flags, 0);
+  for (int k = 0; k <= B.ir_max; ++k) {
+    op_BT(B, st, x, B.S1);
+    gemm_blocks(B, st, B.Zi, 0, B.S1, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.W1, 1.0, -1, nullptr, 0.0, -1);
+    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
+    op_B(B, st, B.W1, B.BX, 0.0);
+    launch_vec_axpby(st, B.S, B.d_sys, B.d_flags, -1.0, B.BX, 1.0, rhs);   // r = rhs - Lambda x
+    launch_ir_check(st, B.S, B.d_sys, B.d_flags, B.BX, rhs, B.d_sc, k, B.ir_max, first ? 1 : 0);
+    if (k == B.ir_max) break;
+    if ((rc = op_solve(B, st, B.BX, B.vtmp))) break;
+    launch_vec_axpby(st, B.S, B.d_sys, B.d_flags, 1.0, x, 1.0, B.vtmp);
+  }
+  launch_park(st, B.S, B.d_flags, 1);
+  return rc;
+}
+
 // identity blocks, C blocks, zeroed Schur matrices with identity padding
 static int init_state(Batch& B, hipStream_t st) {
   std::vector<double> eye(B.totblk, 0.0), cf(B.totblk, 0.0);
@@ -570,13 +601,16 @@ struct RunState {
   int iterations = 0;
   bool running = true;
   std::vector<double> dinf_hist;
+  int it32 = 0;           // iterations assembled in reduced precision
+  int ir_steps = 0;       // refinement corrections applied
+  double eta_max = 0.0;   // largest first refinement residual ratio among them
   double phi = NAN, psi = NAN, gap_abs = NAN, gap_rel = NAN, pinf = NAN, dinf = NAN;
 };
 
 static void set_flags(Batch& B, const std::vector<RunState>& rs, std::vector<int>& hf) {
   hf.assign(B.S, 0);
   for (int s = 0; s < B.S; ++s)
-    if (rs[s].running) hf[s] = F_ACTIVE | F_CHOLSEL;
+    if (rs[s].running) hf[s] = F_ACTIVE | F_CHOLSEL | (B.f32 && !B.asm64[s] ? F_ASM32 : 0);
 }
 
 // One interior-point run of every system marked running.
@@ -586,6 +620,8 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
   std::vector<int> hf(S);
   std::vector<double> hsc((size_t)S * kNSC);
   const int stall_w = 10;
+  std::vector<char> was32(S, 0);   // the previous iteration assembled in FP32
+  std::vector<char> prev_fail(S, 0);
   for (int it = 0;; ++it) {
     set_flags(B, rs, hf);
     // flags carry the failure bits set by the previous iteration's kernels;
@@ -596,8 +632,14 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     B.prof.harvest();
     if (it > 0) {
       for (int s = 0; s < S; ++s) {
+        was32[s] = (prev[s] & F_ASM32) != 0;
+        prev_fail[s] = (prev[s] & F_LAMFAIL) != 0;
         if (!rs[s].running) continue;
-        if (prev[s] & F_LAMFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_CHOL; }
+        if ((prev[s] & F_LAMFAIL) && (prev[s] & F_ASM32)) {
+          // the reduced-precision Schur matrix lost definiteness: the skipped
+          // iteration is repeated with FP64 assembly
+          B.asm64[s] = 1;
+        } else if (prev[s] & F_LAMFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_CHOL; }
         else if (prev[s] & F_LADDERFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_LADDER; }
       }
       set_flags(B, rs, hf);
@@ -633,6 +675,14 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       r.pinf = v[S_PINF]; r.dinf = v[S_DINF];
       r.iterations = it;
       r.dinf_hist.push_back(r.dinf);
+      // refinement no longer contracts fast: FP64 assembly from here on
+      if (it > 0 && B.ir_max > 0 && (was32[s] || !B.f32)) r.ir_steps += (int)v[S_IRSTEPS];
+      if (it > 0 && was32[s]) {
+        ++r.it32;
+        const double eta = (prev_fail[s] || !(v[S_IRETA] == v[S_IRETA])) ? INFINITY : v[S_IRETA];
+        if (B.ir_max > 0) r.eta_max = std::max(r.eta_max, eta);
+        if (B.ir_max > 0 && (!(eta <= kIrSwitch) || v[S_IRFAIL] != 0.0)) B.asm64[s] = 1;
+      }
       if (hist) (*hist)[s].push_back(psdp_iter_rec{it, r.phi, r.psi, r.gap_rel, r.pinf, r.dinf, v[S_MU], 0, 0});
       const bool finite = std::isfinite(r.phi) && std::isfinite(r.psi) && std::isfinite(r.pinf) &&
                           std::isfinite(r.dinf) && std::isfinite(v[S_TRZX]);
@@ -671,7 +721,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     op_B(B, st, B.W1, B.rv1, 1.0);
-    op_solve(B, st, B.rv1, B.dyh);
+    op_solve_refined(B, st, B.rv1, B.dyh, true);
     // predictor directions (processors step 2)
     op_BT(B, st, B.dyh, B.S1);
     { const size_t pm_ = B.prof.mark();
@@ -691,7 +741,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.Wc, B.W1);
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     op_B(B, st, B.W1, B.rv2, 0.0);
-    op_solve(B, st, B.rv2, B.dyb);
+    op_solve_refined(B, st, B.rv2, B.dyb, false);
     // corrector directions (processors step 3)
     op_BT(B, st, B.dyb, B.dZb);
     { const size_t pm_ = B.prof.mark();
@@ -755,8 +805,16 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
       o.ladder_len < 0)
     return fail(PSDP_EINVAL, "invalid solver options");
   if (o.verdict_mode < 0 || o.verdict_mode > 2) return fail(PSDP_EINVAL, "invalid verdict_mode");
+  if (o.precision != PSDP_PREC_FP64 && o.precision != PSDP_PREC_FP32 &&
+      o.precision != PSDP_PREC_BF16)
+    return fail(PSDP_EINVAL, "invalid precision");
+  if (o.ir_max > 50) return fail(PSDP_EINVAL, "ir_max above 50");
   hipStream_t st = (hipStream_t)o.stream;
   Batch B;
+  B.prec = o.precision;
+  B.f32 = o.precision != PSDP_PREC_FP64;
+  B.asm64.assign(count, 0);
+  B.ir_max = o.ir_max >= 0 ? o.ir_max : (B.f32 ? 6 : 0);
   B.prof.on = o.prof != nullptr;
   B.prof.st = st;
   B.prof.out = o.prof;
@@ -884,6 +942,9 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
     R.phase1_iterations = need[s] ? r1[s].iterations : 0;
     R.t_star = tstar[s];
     R.time_solve_s = elapsed;
+    R.iters_lowprec = r.it32 + (need[s] ? r1[s].it32 : 0);
+    R.ir_steps = r.ir_steps + (need[s] ? r1[s].ir_steps : 0);
+    R.ir_eta_max = R.iters_lowprec ? std::max(r.eta_max, need[s] ? r1[s].eta_max : 0.0) : NAN;
     R.history_len = 0;
     if (R.history && R.history_cap > 0) {
       const int nrec = std::min<int>(R.history_cap, (int)hist[s].size());

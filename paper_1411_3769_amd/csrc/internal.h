@@ -22,6 +22,10 @@ constexpr int kNSC = 24;     // per-system scalar slots
 enum Slot {
   S_PHI = 0, S_PSI, S_TRZX, S_PINF, S_DINF, S_GAPABS, S_GAPREL, S_MU, S_TP, S_TD,
   S_NORMBX, S_ONE, S_MINUS_ONE, S_TLAST, S_STT, S_NORMC, S_NORMA, S_DIAGMAX, S_TAU,
+  S_IRETA,   // largest ||rhs - Lambda x0|| / ||rhs|| of the iteration's refined solves
+  S_IRLAST,  // residual ratio of the latest refinement step
+  S_IRFAIL,  // 1 if a solve of the iteration stopped refining above kIrAccept
+  S_IRSTEPS, // refinement corrections applied in the iteration
 };
 
 // per-system flag bits (int array flags[sys])
@@ -31,7 +35,19 @@ enum Flag {
   F_LAMFAIL = 4,      // the Schur matrix failed Cholesky
   F_LADDERFAIL = 8,   // the step ladder ran out
   F_CHOLSEL = 16,     // selected for the (re)factorisation pass
+  F_ASM32 = 32,       // Schur assembly in reduced precision this iteration
+  F_PARK = 64,        // temporarily inactive (FP64-assembled system during refinement)
 };
+
+// Iterative refinement of the Newton solves: a solve is accepted once its
+// residual ratio ||rhs - Lambda x||_inf / ||rhs||_inf falls to kIrTol, or
+// stops falling (by half per step) at or below kIrAccept.  A system whose
+// solve is not accepted, whose first ratio exceeds kIrSwitch, or whose
+// reduced-precision Schur matrix fails Cholesky is assembled in FP64 from
+// the next iteration on.
+constexpr double kIrTol = 1e-14;
+constexpr double kIrAccept = 1e-10;
+constexpr double kIrSwitch = 1e-1;
 
 struct SysDesc {
   int n, L0, L, M, Nt, nb, P, mode;   // P = Kpad / kNB; mode 0 paper SDP, 1 phase-I

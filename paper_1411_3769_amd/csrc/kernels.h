@@ -51,15 +51,12 @@ void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sy
                   const BlkDesc* blks, const int64_t* offA1);
 void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, const int* flags,
                   double* arena);
-void launch_assemble(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
-                     const SysDesc* sys, const int* flags, const int* gpinfo,
-                     const double* arena, double* Lam, const int64_t* gpoff);
 void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                           const KTerm* terms, const SysDesc* sys, const int* flags,
-                          const double* arena, double* Lam);
+                          const double* arena, double* Lam, int prec);
 void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
                          const SysDesc* sys, const int* flags, const int* gpinfo,
-                         const double* arena, double* Lam, const int64_t* gpoff);
+                         const double* arena, double* Lam, const int64_t* gpoff, int prec);
 bool use_small(int nmax);
 void launch_gemm_blocks_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks,
                               const int* flags, const double* sc, const double* A, int tA,
@@ -74,6 +71,11 @@ void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, c
                         const BlkDesc* blks, const int64_t* offA1);
 void launch_pre34_small(hipStream_t st, int nq, int nmax, const HM2* q, const SysDesc* sys,
                         const int* flags, double* arena);
+void launch_park(hipStream_t st, int S, int* flags, int mode);
+void launch_ir_check(hipStream_t st, int S, const SysDesc* sys, int* flags, const double* r,
+                     const double* rhs, double* sc, int k, int kmax, int first_solve);
+void launch_vec_axpby(hipStream_t st, int S, const SysDesc* sys, const int* flags, double a,
+                      double* x, double b, const double* y);
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam);
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,

@@ -6,6 +6,8 @@
 // layout, so X, Z, Z^{-1}, G, ... of block b all live at blk[b].off.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "devcommon.h"
 #include "internal.h"
 #include "kernels.h"
@@ -258,6 +260,21 @@ __device__ inline double wg_sum256(double v, double* sbuf) {
   return r;
 }
 
+// NaN-propagating maximum (a NaN anywhere gives NaN)
+__device__ inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__device__ inline double wg_max256(double v, double* sbuf) {
+  sbuf[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sbuf[threadIdx.x] = nanmax(sbuf[threadIdx.x], sbuf[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double r = sbuf[0];
+  __syncthreads();
+  return r;
+}
+
 // Per system: objectives, residual norms, gaps and mu (fixed summation order).
 __global__ void __launch_bounds__(256) k_sys_finalize(const SysDesc* __restrict__ sys,
                                                       const int* __restrict__ flags,
@@ -478,123 +495,6 @@ __global__ void __launch_bounds__(256) k_pre34(const HM2* __restrict__ q,
   wg_gemm(n, Hh, 0, arena + pr.srcA2, 0, arena + pr.offA3, 1.0, nullptr, 0.0, sA, sB);
   __syncthreads();
   wg_gemm(n, Hh, 0, arena + pr.srcA1, 0, arena + pr.offA4, 1.0, nullptr, 0.0, sA, sB);
-}
-
-// One wave per tile of the Schur matrix: rows = the basis pairs (p, q) of row
-// group (g1, g2) of index h, columns = the pairs (r, s) of column group
-// (g3, g4) of index h2.  For every term of the pair's list the wave stages
-// the 16 x 16 pieces T[g1|g2, g3|g4] and U[g3|g4, g1|g2] in LDS; each lane owns
-// one row and accumulates all (up to 64) columns from 64 register values.
-template <bool DIAGC>
-__device__ inline void asm_accumulate(double (&acc)[64], const double* Ts, const double* Us,
-                                      int pL, int qL, bool pq_same) {
-  double Tq[16], Tp[16], Up[16], Uq[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    Tq[c] = Ts[qL * 17 + c];
-    Tp[c] = pq_same ? 0.0 : Ts[pL * 17 + c];
-    Up[c] = Us[c * 17 + pL];
-    Uq[c] = Us[c * 17 + qL];
-  }
-#pragma unroll
-  for (int rL = 0; rL < 8; ++rL) {
-#pragma unroll
-    for (int sI = 0; sI < 8; ++sI) {
-      const int sL = 8 + sI;
-      if (DIAGC) {
-        if (rL > sI) continue;
-        if (rL == sI) {
-          acc[rL * 8 + sI] += Tq[rL] * Up[sL] + Tp[rL] * Uq[sL];
-          continue;
-        }
-      }
-      acc[rL * 8 + sI] += Tq[rL] * Up[sL] + Tq[sL] * Up[rL] + Tp[rL] * Uq[sL] + Tp[sL] * Uq[rL];
-    }
-  }
-}
-
-__global__ void __launch_bounds__(64) k_assemble(const AsmTile* __restrict__ tiles,
-                                                 const KTerm* __restrict__ terms,
-                                                 const SysDesc* __restrict__ sys,
-                                                 const int* __restrict__ flags,
-                                                 const int* __restrict__ gpinfo_all,
-                                                 const double* __restrict__ arena,
-                                                 double* Lam, const int64_t* __restrict__ gpoff) {
-  __shared__ double Ts[16 * 17];
-  __shared__ double Us[16 * 17];
-  const AsmTile tl = tiles[blockIdx.x];
-  ACTIVE_OR_RETURN(tl.sys);
-  const SysDesc sd = sys[tl.sys];
-  const int n = sd.n;
-  const int* gp = gpinfo_all + gpoff[tl.sys];   // [ngp][4] = g1, g2, off, size
-  const int g1 = gp[tl.rg * 4 + 0], g2 = gp[tl.rg * 4 + 1];
-  const int roff = gp[tl.rg * 4 + 2], rsize = gp[tl.rg * 4 + 3];
-  const int g3 = gp[tl.cg * 4 + 0], g4 = gp[tl.cg * 4 + 1];
-  const int coff = gp[tl.cg * 4 + 2];
-  const int lane = threadIdx.x;
-  // this lane's row pair
-  int p = 0, q = 0;
-  const bool live = lane < rsize;
-  if (live) {
-    p = sd.basis[2 * (roff + lane)];
-    q = sd.basis[2 * (roff + lane) + 1];
-  }
-  const int pL = p - kTB * g1;
-  const int qL = q - kTB * g2 + 8;
-  const bool pq_same = (p == q);
-  const bool diagc = (g3 == g4);
-  double acc[64];
-#pragma unroll
-  for (int c = 0; c < 64; ++c) acc[c] = 0.0;
-  for (int t = 0; t < tl.kcnt; ++t) {
-    const KTerm kt = terms[tl.kbeg + t];
-    const double* T = arena + kt.offT;
-    const double* U = arena + kt.offU;
-    for (int e = lane; e < 256; e += 64) {
-      const int a = e >> 4, c = e & 15;
-      const int ra = a < 8 ? kTB * g1 + a : kTB * g2 + (a - 8);
-      const int cc = c < 8 ? kTB * g3 + c : kTB * g4 + (c - 8);
-      double tv = 0.0, uv = 0.0;
-      if (ra < n && cc < n) {
-        tv = kt.tT ? T[cc * n + ra] : T[ra * n + cc];
-        uv = kt.tU ? U[ra * n + cc] : U[cc * n + ra];
-      }
-      Ts[a * 17 + c] = kt.coef * tv;   // T[row a][col c]
-      Us[c * 17 + a] = uv;             // U[col c][row a]
-    }
-    __syncthreads();
-    if (live) {
-      if (diagc)
-        asm_accumulate<true>(acc, Ts, Us, pL, qL, pq_same);
-      else
-        asm_accumulate<false>(acc, Ts, Us, pL, qL, pq_same);
-    }
-    __syncthreads();
-  }
-  if (!live) return;
-  const int64_t ld = sd.Kpad;
-  const int64_t row = (int64_t)tl.h * sd.Nt + roff + lane;
-  const int n3 = min(kTB, n - kTB * g3), n4 = min(kTB, n - kTB * g4);
-  const bool mirror = !(tl.h == tl.h2 && tl.rg == tl.cg);
-  double* Lr = Lam + sd.loff;
-#pragma unroll
-  for (int rL = 0; rL < 8; ++rL) {
-#pragma unroll
-    for (int sI = 0; sI < 8; ++sI) {
-      if (rL >= n3 || sI >= n4) continue;
-      int cidx;
-      if (diagc) {
-        if (rL > sI) continue;
-        cidx = rL * n3 - rL * (rL - 1) / 2 + (sI - rL);
-      } else {
-        cidx = rL * n4 + sI;
-      }
-      const int64_t col = (int64_t)tl.h2 * sd.Nt + coff + cidx;
-      const double v = acc[rL * 8 + sI];
-      Lr[row * ld + col] = v;
-      if (mirror) Lr[col * ld + row] = v;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -822,9 +722,70 @@ __device__ inline v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Reduced-precision forms (PR = 1: FP32, PR = 2: BF16) stage T and U
+// rounded to the narrow type and accumulate in FP32; the gather and the
+// Schur matrix stay FP64.  v_mfma_f32_16x16x4f32 takes A[l%16][l/16] and
+// B[l/16][l%16]; v_mfma_f32_16x16x16bf16_1k takes A[l%16][4(l/16)+j] and
+// B[4(l/16)+j][l%16], j = 0..3; both return D[4(l/16)+i][l%16] in register i.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// double -> bf16 bits, through FP32, round to nearest even
+__device__ inline unsigned short to_bf16(double x) {
+  const float f = (float)x;
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+template <int PR> struct AsmPrec;
+template <> struct AsmPrec<0> {
+  typedef double stage_t; typedef v4d acc_t; static constexpr int KC = 4;
+  static __device__ stage_t cvt(double x) { return x; }
+};
+template <> struct AsmPrec<1> {
+  typedef float stage_t; typedef v4f acc_t; static constexpr int KC = 4;
+  static __device__ stage_t cvt(double x) { return (float)x; }
+};
+template <> struct AsmPrec<2> {
+  typedef unsigned short stage_t; typedef v4f acc_t; static constexpr int KC = 16;
+  static __device__ stage_t cvt(double x) { return to_bf16(x); }
+};
+
+// One MFMA step; sA / sB point at the lane's first operand element, and
+// successive k (bf16 only) are kstride apart.
+template <int PR>
+__device__ inline typename AsmPrec<PR>::acc_t asm_mfma(const typename AsmPrec<PR>::stage_t* sA,
+                                                       const typename AsmPrec<PR>::stage_t* sB,
+                                                       int kstride,
+                                                       typename AsmPrec<PR>::acc_t c) {
+  if constexpr (PR == 0) return mfma16(*sA, *sB, c);
+  else if constexpr (PR == 1) return __builtin_amdgcn_mfma_f32_16x16x4f32(*sA, *sB, c, 0, 0, 0);
+  else {
+    v4s a, b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[j] = (short)sA[j * kstride];
+      b[j] = (short)sB[j * kstride];
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+}
+
+// output row of result register i (16 x 16 tile)
+template <int PR>
+__device__ inline int asm_row(int lane, int i) {
+  return PR == 0 ? 4 * i + (lane >> 4) : 4 * (lane >> 4) + i;
+}
+
 // Small n (n^2 <= 128): one workgroup per (system, h, h2); R accumulated in
 // registers by 4 waves (tiles of 16 x 16), then staged in LDS for the gather.
+// Terms are staged KC at a time (4; 16 for BF16, one k-group of 4 per lane
+// quarter).
 constexpr int kPairMaxT = 16;
+
+template <int PR>
 __global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict__ tiles,
                                                        const KTerm* __restrict__ terms,
                                                        const SysDesc* __restrict__ sys,
@@ -832,21 +793,26 @@ __global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict
                                                        const double* __restrict__ arena,
                                                        double* Lam) {
   extern __shared__ double smem[];
+  typedef AsmPrec<PR> AP;
+  typedef typename AP::stage_t real;
+  typedef typename AP::acc_t acc_t;
+  constexpr int KC = AP::KC;
   const AsmTile tl = tiles[blockIdx.x];
   ACTIVE_OR_RETURN(tl.sys);
+  if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) return;
   const SysDesc sd = sys[tl.sys];
   const int n = sd.n, n2 = n * n;
   const int NT = (n2 + 15) / 16, n2p = NT * 16, ntiles = NT * NT;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  double* sT = smem;
-  double* sU = smem + 4 * n2p;
-  double* R = smem + 8 * n2p;
-  v4d acc[kPairMaxT];
+  real* sT = reinterpret_cast<real*>(smem);
+  real* sU = sT + KC * n2p;
+  double* R = smem + 8 * n2p;   // staging needs at most 2 KC n2p sizeof(real) <= 64 n2p bytes
+  acc_t acc[kPairMaxT];
 #pragma unroll
-  for (int t = 0; t < kPairMaxT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < tl.kcnt; k0 += 4) {
+  for (int t = 0; t < kPairMaxT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < tl.kcnt; k0 += KC) {
     __syncthreads();
-    for (int e = tid; e < 4 * n2p; e += 256) {
+    for (int e = tid; e < KC * n2p; e += 256) {
       const int kk = e / n2p, idx = e - kk * n2p;
       double tv = 0.0, uv = 0.0;
       if (k0 + kk < tl.kcnt && idx < n2) {
@@ -856,19 +822,19 @@ __global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict
         tv = kt.coef * arena[kt.offT + (kt.tT ? tr : idx)];
         uv = arena[kt.offU + (kt.tU ? tr : idx)];
       }
-      sT[e] = tv;
-      sU[e] = uv;
+      sT[e] = AP::cvt(tv);
+      sU[e] = AP::cvt(uv);
     }
     __syncthreads();
     const int kq = lane >> 4, r16 = lane & 15;
+    const int kb = PR == 2 ? 4 * kq : kq;
 #pragma unroll
     for (int t = 0; t < kPairMaxT; ++t) {
       const int id = wave + 4 * t;
       if (id < ntiles) {
         const int ti = id / NT, tj = id - ti * NT;
-        const double a = sT[kq * n2p + ti * 16 + r16];
-        const double b = sU[kq * n2p + tj * 16 + r16];
-        acc[t] = mfma16(a, b, acc[t]);
+        acc[t] = asm_mfma<PR>(sT + kb * n2p + ti * 16 + r16, sU + kb * n2p + tj * 16 + r16, n2p,
+                              acc[t]);
       }
     }
   }
@@ -881,8 +847,8 @@ __global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict
       const int col = tj * 16 + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = ti * 16 + 4 * i + (lane >> 4);
-        if (row < n2 && col < n2) R[row * n2 + col] = acc[t][i];
+        const int row = ti * 16 + asm_row<PR>(lane, i);
+        if (row < n2 && col < n2) R[row * n2 + col] = (double)acc[t][i];
       }
     }
   }
@@ -914,6 +880,7 @@ __global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict
 // as a 64 x 64 MFMA product (rows (x,y), columns (z,u) of 8 x 8 indices);
 // the four are added into an LDS tile in (p,q) x (r,s) order (Q3/Q4 only for
 // p != q, Q2/Q4 only for r != s).
+template <int PR>
 __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict__ tiles,
                                                       const KTerm* __restrict__ terms,
                                                       const SysDesc* __restrict__ sys,
@@ -922,11 +889,16 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
                                                       const double* __restrict__ arena,
                                                       double* Lam,
                                                       const int64_t* __restrict__ gpoff) {
-  __shared__ double sT[4 * 16 * 17];
-  __shared__ double sU[4 * 16 * 17];
+  typedef AsmPrec<PR> AP;
+  typedef typename AP::stage_t real;
+  typedef typename AP::acc_t acc_t;
+  constexpr int KC = AP::KC;
+  __shared__ real sT[KC * 16 * 17];
+  __shared__ real sU[KC * 16 * 17];
   __shared__ double sL[64 * 65];
   const AsmTile tl = tiles[blockIdx.x];
   ACTIVE_OR_RETURN(tl.sys);
+  if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) return;
   const SysDesc sd = sys[tl.sys];
   const int n = sd.n;
   const int* gp = gpinfo_all + gpoff[tl.sys];
@@ -936,12 +908,12 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
   // index offsets of the quadrant's row pair (x, y) and column pair (z, u)
   const int xoff = w < 2 ? 8 : 0, yoff = (w & 1) ? 8 : 0;
   const int zoff = (w & 1) ? 0 : 8, uoff = w < 2 ? 0 : 8;
-  v4d acc[16];
+  acc_t acc[16];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < tl.kcnt; k0 += 4) {
+  for (int t = 0; t < 16; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < tl.kcnt; k0 += KC) {
     __syncthreads();
-    for (int e = tid; e < 4 * 512; e += 256) {
+    for (int e = tid; e < KC * 512; e += 256) {
       const int kk = e >> 9, rem = e & 511, which = rem >> 8;
       const int a = (rem & 255) >> 4, c = rem & 15;
       const int ia = a < 8 ? kTB * g1 + a : kTB * g2 + (a - 8);
@@ -952,23 +924,23 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
         if (which == 0) v = kt.coef * arena[kt.offT + (kt.tT ? jc * n + ia : ia * n + jc)];
         else v = arena[kt.offU + (kt.tU ? ia * n + jc : jc * n + ia)];
       }
-      if (which == 0) sT[kk * 272 + a * 17 + c] = v;   // T[I_a][J_c]
-      else sU[kk * 272 + c * 17 + a] = v;              // U[J_c][I_a]
+      if (which == 0) sT[kk * 272 + a * 17 + c] = AP::cvt(v);   // T[I_a][J_c]
+      else sU[kk * 272 + c * 17 + a] = AP::cvt(v);              // U[J_c][I_a]
     }
     __syncthreads();
     const int kq = lane >> 4, r16 = lane & 15;
-    double av[4], bv[4];
+    const int kb = PR == 2 ? 4 * kq : kq;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int xi = 2 * t + (r16 >> 3), yi = r16 & 7;
-      av[t] = sT[kq * 272 + (xoff + xi) * 17 + yoff + yi];
-      const int zi = 2 * t + (r16 >> 3), ui = r16 & 7;
-      bv[t] = sU[kq * 272 + (zoff + zi) * 17 + uoff + ui];
+      const real* pa = sT + kb * 272 + (xoff + xi) * 17 + yoff + yi;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int zi = 2 * u + (r16 >> 3), ui = r16 & 7;
+        const real* pb = sU + kb * 272 + (zoff + zi) * 17 + uoff + ui;
+        acc[t * 4 + u] = asm_mfma<PR>(pa, pb, 272, acc[t * 4 + u]);
+      }
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[t * 4 + u] = mfma16(av[t], bv[u], acc[t * 4 + u]);
   }
   // combine the four quadrants in LDS
   const bool pqdiag = (g1 == g2), rsdiag = (g3 == g4);
@@ -981,7 +953,8 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int row = 16 * t + 4 * i + (lane >> 4), col = 16 * u + (lane & 15);
+            const int row = 16 * t + asm_row<PR>(lane, i);
+            const int col = 16 * u + (lane & 15);
             const int xi = row >> 3, yi = row & 7, zi = col >> 3, ui = col & 7;
             int pi, qi, ri, si;
             if (w == 0) { pi = ui; qi = xi; ri = yi; si = zi; }
@@ -989,7 +962,7 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
             else if (w == 2) { pi = xi; qi = ui; ri = yi; si = zi; }
             else { pi = xi; qi = ui; ri = zi; si = yi; }
             const bool pq_same = pqdiag && pi == qi, rs_same = rsdiag && ri == si;
-            double v = acc[t * 4 + u][i];
+            double v = (double)acc[t * 4 + u][i];
             if ((w >= 2 && pq_same) || ((w & 1) && rs_same)) v = 0.0;
             double* dst = sL + (pi * 8 + qi) * 65 + ri * 8 + si;
             if (w == 0) *dst = v; else *dst += v;
@@ -1135,7 +1108,86 @@ __global__ void __launch_bounds__(256) k_pre34_small(int nq, int nmax, int G,
   arena[pr.offA4 + e_] = dot_n(n, i, j, Hh, 0, arena + pr.srcA1, 0);
 }
 
+// x = a * x + b * y over the first K entries of every active system
+__global__ void k_vec_axpby(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
+                            double a, double* x, double b, const double* __restrict__ y) {
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  for (int k = threadIdx.x; k < sd.K; k += blockDim.x) {
+    const int64_t o = sd.voff + k;
+    x[o] = a * x[o] + b * y[o];
+  }
+}
+
+// mode 0: park the active systems assembled in FP64 (they skip refinement);
+// mode 1: re-activate the parked ones
+__global__ void k_park(int S, int* flags, int mode) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int f = flags[s];
+  if (mode == 0) {
+    if ((f & F_ACTIVE) && !(f & F_ASM32)) flags[s] = (f & ~F_ACTIVE) | F_PARK;
+  } else if (f & F_PARK) {
+    flags[s] = (f & ~F_PARK) | F_ACTIVE;
+  }
+}
+
+// Refinement step k of a solve: eta = ||r||_inf / ||rhs||_inf; the system is
+// parked (its x final) once accepted, stagnant, or at step kmax.  Slots:
+// IRETA (eta of step 0, max over the iteration's solves), IRLAST, IRFAIL,
+// IRSTEPS (reset by the iteration's first solve).
+__global__ void __launch_bounds__(256) k_ir_check(const SysDesc* __restrict__ sys, int* flags,
+                                                  const double* __restrict__ r,
+                                                  const double* __restrict__ rhs, double* sc,
+                                                  int k, int kmax, int first_solve) {
+  __shared__ double sb[256];
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  double rn = 0.0, bn = 0.0;
+  for (int i = threadIdx.x; i < sd.K; i += blockDim.x) {
+    rn = nanmax(rn, fabs(r[sd.voff + i]));
+    bn = nanmax(bn, fabs(rhs[sd.voff + i]));
+  }
+  rn = wg_max256(rn, sb);
+  bn = wg_max256(bn, sb);
+  if (threadIdx.x == 0) {
+    double eta = bn > 0.0 ? rn / bn : (rn > 0.0 ? INFINITY : 0.0);
+    if (!(eta == eta)) eta = INFINITY;
+    double* o = sc + (size_t)s * kNSC;
+    if (k == 0) {
+      if (first_solve) { o[S_IRETA] = eta; o[S_IRFAIL] = 0.0; o[S_IRSTEPS] = 0.0; }
+      else o[S_IRETA] = fmax(o[S_IRETA], eta);
+    }
+    const bool stag = k > 0 && !(eta <= 0.5 * o[S_IRLAST]);
+    const bool ok = eta <= kIrTol || (stag && eta <= kIrAccept);
+    if (ok || stag || k == kmax) {
+      if (!ok) o[S_IRFAIL] = 1.0;
+      flags[s] = (flags[s] & ~F_ACTIVE) | F_PARK;
+    } else {
+      o[S_IRSTEPS] += 1.0;
+    }
+    o[S_IRLAST] = eta;
+  }
+}
+
 // launch wrappers ----------------------------------------------------------------
+
+void launch_park(hipStream_t st, int S, int* flags, int mode) {
+  hipLaunchKernelGGL(k_park, dim3((S + 255) / 256), dim3(256), 0, st, S, flags, mode);
+}
+
+void launch_ir_check(hipStream_t st, int S, const SysDesc* sys, int* flags, const double* r,
+                     const double* rhs, double* sc, int k, int kmax, int first_solve) {
+  hipLaunchKernelGGL(k_ir_check, dim3(S), dim3(256), 0, st, sys, flags, r, rhs, sc, k, kmax,
+                     first_solve);
+}
+
+void launch_vec_axpby(hipStream_t st, int S, const SysDesc* sys, const int* flags, double a,
+                      double* x, double b, const double* y) {
+  hipLaunchKernelGGL(k_vec_axpby, dim3(S), dim3(256), 0, st, sys, flags, a, x, b, y);
+}
 
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam) {
   hipLaunchKernelGGL(k_pad_identity, dim3(S), dim3(64), 0, st, sys, Lam);
@@ -1256,14 +1308,6 @@ void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, cons
   if (nq) hipLaunchKernelGGL(k_pre34, dim3(nq), dim3(256), 0, st, q, sys, flags, arena);
 }
 
-void launch_assemble(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
-                     const SysDesc* sys, const int* flags, const int* gpinfo,
-                     const double* arena, double* Lam, const int64_t* gpoff) {
-  if (ntiles)
-    hipLaunchKernelGGL(k_assemble, dim3(ntiles), dim3(64), 0, st, tiles, terms, sys, flags, gpinfo,
-                       arena, Lam, gpoff);
-}
-
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,
                         double* out) {
@@ -1306,22 +1350,41 @@ void launch_phase1_vectors(hipStream_t st, int S, const SysDesc* sys, const int*
 
 namespace psdp {
 
+// prec = PSDP_PREC_FP32 / _BF16: systems flagged F_ASM32 take that
+// reduced-precision kernel, the rest the FP64 one (each kernel skips the
+// other's tiles); PSDP_PREC_FP64: the FP64 kernel only.
+template <int PR>
+static void pair_launch(hipStream_t st, int ntiles, size_t lds, const AsmTile* tiles,
+                        const KTerm* terms, const SysDesc* sys, const int* flags,
+                        const double* arena, double* Lam) {
+  set_lds((const void*)k_assemble_pair<PR>, lds);
+  hipLaunchKernelGGL(k_assemble_pair<PR>, dim3(ntiles), dim3(256), lds, st, tiles, terms, sys, flags,
+                     arena, Lam);
+}
+
 void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                           const KTerm* terms, const SysDesc* sys, const int* flags,
-                          const double* arena, double* Lam) {
+                          const double* arena, double* Lam, int prec) {
   if (!ntiles) return;
   const int n2 = maxn * maxn, n2p = (n2 + 15) / 16 * 16;
   const size_t lds = (size_t)(8 * n2p + n2 * n2) * 8;
-  set_lds((const void*)k_assemble_pair, lds);
-  hipLaunchKernelGGL(k_assemble_pair, dim3(ntiles), dim3(256), lds, st, tiles, terms, sys, flags, arena, Lam);
+  if (prec == PSDP_PREC_FP32) pair_launch<1>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam);
+  if (prec == PSDP_PREC_BF16) pair_launch<2>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam);
+  pair_launch<0>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam);
 }
 
 void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
                          const SysDesc* sys, const int* flags, const int* gpinfo,
-                         const double* arena, double* Lam, const int64_t* gpoff) {
+                         const double* arena, double* Lam, const int64_t* gpoff, int prec) {
   if (!ntiles) return;
-  hipLaunchKernelGGL(k_assemble_grp, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags, gpinfo,
-                     arena, Lam, gpoff);
+  if (prec == PSDP_PREC_FP32)
+    hipLaunchKernelGGL(k_assemble_grp<1>, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags,
+                       gpinfo, arena, Lam, gpoff);
+  if (prec == PSDP_PREC_BF16)
+    hipLaunchKernelGGL(k_assemble_grp<2>, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags,
+                       gpinfo, arena, Lam, gpoff);
+  hipLaunchKernelGGL(k_assemble_grp<0>, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags,
+                     gpinfo, arena, Lam, gpoff);
 }
 
 }  // namespace psdp

@@ -202,6 +202,7 @@ void psdp_opts_default(psdp_opts* o) {
   o->ladder_len = 300;
   o->verdict_mode = PSDP_VERDICT_PAPER_THEN_PHASE1;
   o->precision = PSDP_PREC_FP64;
+  o->ir_max = -1;
   o->stream = nullptr;
   o->record_history = 0;
   o->prof = nullptr;

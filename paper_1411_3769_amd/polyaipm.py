@@ -28,7 +28,7 @@ FEASIBLE, INFEASIBLE, UNKNOWN = 0, 1, 2
 VERDICTS = {0: "FEASIBLE", 1: "INFEASIBLE", 2: "UNKNOWN"}
 REASONS = ["converged", "farkas", "stall", "max_iter", "ladder_fail", "chol_fail", "nonfinite"]
 VERDICT_MODES = {"paper_then_phase1": 0, "paper_only": 1, "phase1_only": 2}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 ERRORS = {-1: "EINVAL", -2: "EOVERFLOW", -3: "ENOMEM", -4: "EDEVICE", -5: "ENUMERIC"}
 NPROF = 16
 PROF_CLASSES = ["cholinv", "BT", "B", "pre", "assemble", "chol_panel", "chol_update", "trsv",
@@ -56,7 +56,7 @@ class Opts(C.Structure):
     _fields_ = [("gap_tol", C.c_double), ("feas_tol", C.c_double), ("max_iter", C.c_int),
                 ("sigma", C.c_double), ("step_frac", C.c_double), ("ladder_rho", C.c_double),
                 ("ladder_len", C.c_int), ("verdict_mode", C.c_int), ("precision", C.c_int),
-                ("stream", C.c_void_p), ("record_history", C.c_int), ("prof", DP)]
+                ("ir_max", C.c_int), ("stream", C.c_void_p), ("record_history", C.c_int), ("prof", DP)]
 
 
 class IterRec(C.Structure):
@@ -70,7 +70,8 @@ class CResult(C.Structure):
                 ("gap_rel", C.c_double), ("pinf", C.c_double), ("dinf", C.c_double),
                 ("margin", C.c_double), ("margin_P", C.c_double), ("margin_D", C.c_double),
                 ("iterations", C.c_int), ("phase1_used", C.c_int), ("phase1_iterations", C.c_int),
-                ("t_star", C.c_double), ("time_solve_s", C.c_double),
+                ("t_star", C.c_double), ("time_solve_s", C.c_double), ("iters_lowprec", C.c_int),
+                ("ir_steps", C.c_int), ("ir_eta_max", C.c_double),
                 ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
 
@@ -251,6 +252,9 @@ class Result:
     phase1_iterations: int
     t_star: float
     time_solve_s: float
+    iters_lowprec: int = 0
+    ir_steps: int = 0
+    ir_eta_max: float = float("nan")
     history: list = field(default_factory=list)
 
     @property
@@ -283,7 +287,8 @@ def _unpack(r: CResult, P, y, hist) -> Result:
                           dinf=e.dinf, mu=e.mu, tp=e.tp, td=e.td))
     return Result(r.verdict, r.reason, P, y, r.phi, r.psi, r.gap_abs, r.gap_rel, r.pinf, r.dinf,
                   r.margin, r.margin_P, r.margin_D, r.iterations, bool(r.phase1_used),
-                  r.phase1_iterations, r.t_star, r.time_solve_s, h)
+                  r.phase1_iterations, r.t_star, r.time_solve_s, r.iters_lowprec,
+                  r.ir_steps, r.ir_eta_max, h)
 
 
 def ipm_solve(sdp: SDP, **opts) -> Result:
