@@ -12,10 +12,9 @@
 // tile); the strict upper triangle keeps Lambda.
 //
 // Right-looking blocked algorithm, step p (panel column p):
-//   panel  : every workgroup loads the 64 x 64 diagonal tile, factors it in
-//            LDS and inverts the factor (redundantly: this replaces two
-//            launches), then either stores L_pp and L_pp^{-1} (first
-//            workgroup) or forms L_ip = A_ip L_pp^{-T} for one tile row;
+//   diag   : one workgroup per system factors the 64 x 64 diagonal tile in
+//            registers and inverts the factor (L_pp, L_pp^{-1} stored);
+//   trsm   : one workgroup per tile row i > p forms L_ip = A_ip L_pp^{-T};
 //   update : every tile (i, j), p < j <= i, gets A_ij -= L_ip L_jp^T on FP64
 //            MFMA.
 // Steps are launched for the whole batch; a (step, system) table maps
@@ -128,22 +127,21 @@ __device__ inline void reg_trinv64(const double* sL, double (&X)[4][4], double* 
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ sys, int* flags,
-                                                    double* Lam, double* Ldiag, double* Linv,
-                                                    const int* __restrict__ st_sys,
-                                                    const int* __restrict__ st_pre, int cnt, int p) {
+// Diagonal step p: one workgroup per system factors the 64 x 64 tile A_pp
+// and inverts the factor, storing L_pp and L_pp^{-1}.
+__global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ sys, int* flags,
+                                                   const double* __restrict__ Lam, double* Ldiag,
+                                                   double* Linv, const int* __restrict__ st_sys,
+                                                   int p) {
   __shared__ double sL[kNB * LDT];
-  __shared__ double sX[kNB * LDT];
   __shared__ double vbuf[2 * kNB];
   __shared__ double rdiag[kNB];
   __shared__ int fl;
-  const int si = find_owner(st_pre, cnt, blockIdx.x);
-  const int s = st_sys[si];
-  const int t = blockIdx.x - st_pre[si];
+  const int s = st_sys[blockIdx.x];
   if (!(flags[s] & F_CHOLSEL)) return;
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
-  double* A = Lam + sd.loff;
+  const double* A = Lam + sd.loff;
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   if (tid == 0) fl = 0;
   const double* App = A + (int64_t)p * kNB * ld + (int64_t)p * kNB;
@@ -153,36 +151,51 @@ __global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ 
 #pragma unroll
     for (int b = 0; b < 4; ++b) reg[a][b] = App[(int64_t)(tr + 16 * a) * ld + tc + 16 * b];
   reg_potrf64(reg, vbuf, &fl);
+  double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int i = tr + 16 * a, j = tc + 16 * b;
-      sL[i * LDT + j] = j <= i ? reg[a][b] : 0.0;
+      const double v = j <= i ? reg[a][b] : 0.0;
+      sL[i * LDT + j] = v;
+      D[i * kNB + j] = v;
     }
   __syncthreads();
   double X[4][4];
   reg_trinv64(sL, X, vbuf, rdiag);
+  double* Dv = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) sX[(tr + 16 * a) * LDT + tc + 16 * b] = X[a][b];
-  __syncthreads();
-  if (t == 0) {
-    double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
-    double* Dv = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
-    for (int e = tid; e < kNB * kNB; e += 256) {
-      const int r = e >> 6, c = e & 63;
-      D[e] = sL[r * LDT + c];
-      Dv[e] = sX[r * LDT + c];
-    }
-    if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
-    return;
+    for (int b = 0; b < 4; ++b) Dv[(tr + 16 * a) * kNB + tc + 16 * b] = X[a][b];
+  if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
+}
+
+// Panel step p: L_ip = A_ip L_pp^{-T} for every tile row i > p, on FP64
+// MFMA (C[r][c] = sum_k A_ip[r][k] X[c][k] with X = L_pp^{-1}).
+__global__ void __launch_bounds__(256) k_chol_trsm(const SysDesc* __restrict__ sys,
+                                                   const int* __restrict__ flags, double* Lam,
+                                                   const double* __restrict__ Linv,
+                                                   const int* __restrict__ st_sys,
+                                                   const int* __restrict__ st_pre, int cnt, int p) {
+  __shared__ double sA[kNB * LDT];
+  __shared__ double sX[kNB * LDT];
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  const int i = p + 1 + t;
+  double* Ai = Lam + sd.loff + (int64_t)i * kNB * ld + (int64_t)p * kNB;
+  const double* Xg = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    sA[r * LDT + c] = Ai[(int64_t)r * ld + c];
+    sX[r * LDT + c] = Xg[e];
   }
-  // L_ip = A_ip L_pp^{-T} on MFMA: C[r][c] = sum_k A_ip[r][k] X[c][k]
-  const int i = p + t;
-  double* Ai = A + (int64_t)i * kNB * ld + (int64_t)p * kNB;
-  for (int e = tid; e < kNB * kNB; e += 256) sL[(e >> 6) * LDT + (e & 63)] = Ai[(int64_t)(e >> 6) * ld + (e & 63)];
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
   v4d acc[4];
@@ -190,7 +203,7 @@ __global__ void __launch_bounds__(256) k_chol_panel(const SysDesc* __restrict__ 
   for (int u = 0; u < 4; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int k0 = 0; k0 < kNB; k0 += 4) {
-    const double av = sL[(16 * w + r16) * LDT + k0 + kq];
+    const double av = sA[(16 * w + r16) * LDT + k0 + kq];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const double bv = sX[(16 * u + r16) * LDT + k0 + kq];
@@ -392,10 +405,18 @@ __global__ void __launch_bounds__(256) k_trsv_small(const SysDesc* __restrict__ 
 
 // launch wrappers --------------------------------------------------------------
 
-void launch_chol_panel(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
-                       double* Linv, const int* ssys, const int* spre, int cnt, int total, int p) {
-  hipLaunchKernelGGL(k_chol_panel, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, ssys,
-                     spre, cnt, p);
+void launch_chol_diag(hipStream_t st, const SysDesc* sys, int* flags, const double* Lam,
+                      double* Ldiag, double* Linv, const int* ssys, int cnt, int p) {
+  if (cnt)
+    hipLaunchKernelGGL(k_chol_diag, dim3(cnt), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, ssys, p);
+}
+
+void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
+                      const double* Linv, const int* ssys, const int* spre, int cnt, int total,
+                      int p) {
+  if (total)
+    hipLaunchKernelGGL(k_chol_trsm, dim3(total), dim3(256), 0, st, sys, flags, Lam, Linv, ssys, spre,
+                       cnt, p);
 }
 
 void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,

@@ -96,7 +96,7 @@ struct Batch {
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
   std::vector<int> ownP, ownK;
-  StepTab pan, upd, fwdL, bwdL;     // fwdL/bwdL: solve steps of the large systems only
+  StepTab pan, trs, upd, fwdL, bwdL;     // fwdL/bwdL: solve steps of the large systems only
   std::vector<int> small_ids;
   int* d_small = nullptr;
   int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0;
@@ -115,6 +115,7 @@ struct Batch {
   int *d_gpinfo = nullptr, *d_ownP = nullptr, *d_ownK = nullptr;
   int64_t* d_gpoff = nullptr;
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
+  int *d_trs_sys = nullptr, *d_trs_pre = nullptr;
   int *d_fwdL_sys = nullptr, *d_fwdL_pre = nullptr, *d_bwdL_sys = nullptr, *d_bwdL_pre = nullptr;
   int* d_flags = nullptr;
   double* d_sc = nullptr;
@@ -130,6 +131,8 @@ struct Batch {
   int ir_max = 0;
   std::vector<char> asm64;   // per system: fell back to FP64 assembly (sticky)
   int maxK = 0;
+  int nmax_small = 0;   // largest block order <= kSmallN in the batch (0: none)
+  int nmin_big = 0;     // the general block kernels skip orders below this
   double *Lam, *Ldiag, *Linv, *Pm, *pre;
 
   ~Batch() {
@@ -168,6 +171,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
     const int n = p->n;
     const int64_t nn = (int64_t)n * n;
     B.maxn = std::max(B.maxn, n);
+    if (n <= kSmallN) B.nmax_small = std::max(B.nmax_small, n);
+    else B.nmin_big = kSmallN + 1;
     SysDesc d{};
     d.n = n; d.L0 = p->L0; d.L = p->L; d.M = p->M; d.Nt = p->Nt; d.nb = p->nb;
     d.K = (int)p->K; d.Kpad = (int)p->Kpad; d.P = d.Kpad / kNB; d.mode = 0;
@@ -342,14 +347,16 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
     if (B.sys[s].P <= kSmallP) B.small_ids.push_back(s);
   for (int pstep = 0; pstep < B.maxP; ++pstep) {
     B.pan.add_step();
+    B.trs.add_step();
     B.upd.add_step();
     B.fwdL.add_step();
     B.bwdL.add_step();
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (P <= pstep) continue;
-      B.pan.add(s, P - pstep);
+      B.pan.add(s, 1);
       const int T = P - pstep - 1;
+      if (T > 0) B.trs.add(s, T);
       if (T > 0) B.upd.add(s, T * (T + 1) / 2);
       if (P > kSmallP) {
         B.fwdL.add(s, P - pstep);
@@ -366,6 +373,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   tb += tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(B.csr_hh) + tabsize(B.csr_hid);
   tb += tabsize(B.csr_mh) + tabsize(B.csr_hl);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
+  tb += tabsize(B.trs.sys) + tabsize(B.trs.pre);
   tb += tabsize(B.fwdL.sys) + tabsize(B.fwdL.pre) + tabsize(B.bwdL.sys) + tabsize(B.bwdL.pre);
   tb += tabsize(B.small_ids);
   tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
@@ -414,6 +422,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   if ((rc = upload(B.dtab, off, B.csr_hl, &tmp))) return rc;
   if ((rc = upload(B.dtab, off, B.pan.sys, &B.d_pan_sys))) return rc;
   if ((rc = upload(B.dtab, off, B.pan.pre, &B.d_pan_pre))) return rc;
+  if ((rc = upload(B.dtab, off, B.trs.sys, &B.d_trs_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.trs.pre, &B.d_trs_pre))) return rc;
   if ((rc = upload(B.dtab, off, B.upd.sys, &B.d_upd_sys))) return rc;
   if ((rc = upload(B.dtab, off, B.upd.pre, &B.d_upd_pre))) return rc;
   if ((rc = upload(B.dtab, off, B.fwdL.sys, &B.d_fwdL_sys))) return rc;
@@ -439,12 +449,12 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
 static void gemm_blocks(Batch& B, hipStream_t st, const double* A, int tA, const double* Bm, int tB,
                         double* C, double alpha, int aslot, const double* D, double beta,
                         int bslot) {
-  if (use_small(B.maxn))
-    launch_gemm_blocks_small(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.d_sc, A, tA, Bm, tB, C, alpha,
-                             aslot, D, beta, bslot);
-  else
+  if (B.nmax_small)
+    launch_gemm_blocks_small(st, B.nblk, B.nmax_small, B.d_blk, B.d_flags, B.d_sc, A, tA, Bm, tB, C,
+                             alpha, aslot, D, beta, bslot);
+  if (B.maxn > kSmallN)
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, A, tA, Bm, tB, C, alpha, aslot, D,
-                       beta, bslot);
+                       beta, bslot, B.nmin_big);
 }
 
 // B^T(y) for every active system; phase-I systems use B'^T (lift + t D).
@@ -457,10 +467,9 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
   }
   launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, ybase, B.Pm);
   launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out);
-  if (use_small(B.maxn))
-    launch_BT_dblk_small(st, B.ndblk, B.maxn, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
-  else
-    launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
+  if (B.nmax_small)
+    launch_BT_dblk_small(st, B.ndblk, B.nmax_small, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
+  if (B.maxn > kSmallN) launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out, B.nmin_big);
   if (phase_aware && B.any_phase1) launch_sub_tD(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, yv, out);
   B.prof.add(PSDP_PROF_BT, m0, B.prof.mark());
 }
@@ -470,10 +479,10 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
 static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double asub,
                  bool phase_aware = true) {
   const size_t m0 = B.prof.mark();
-  if (use_small(B.maxn))
-    launch_B_Y_small(st, B.npairs, B.maxn, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
-  else
-    launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
+  if (B.nmax_small)
+    launch_B_Y_small(st, B.npairs, B.nmax_small, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
+  if (B.maxn > kSmallN)
+    launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk, B.nmin_big);
   launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
                   out, asub);
   if (phase_aware && B.any_phase1) launch_B_phase1(st, B.S, B.d_sys, B.d_flags, B.d_blk, W, out, asub);
@@ -482,13 +491,15 @@ static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double 
 
 static void op_schur(Batch& B, hipStream_t st) {
   const size_t m0 = B.prof.mark();
-  if (use_small(B.maxn)) {
-    launch_pre12_small(st, B.npairs, B.maxn, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk,
-                       B.d_offA1);
-    launch_pre34_small(st, B.nq2, B.maxn, B.d_q2, B.d_sys, B.d_flags, B.arena);
-  } else {
-    launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1);
-    launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena);
+  if (B.nmax_small) {
+    launch_pre12_small(st, B.npairs, B.nmax_small, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena,
+                       B.d_blk, B.d_offA1);
+    launch_pre34_small(st, B.nq2, B.nmax_small, B.d_q2, B.d_sys, B.d_flags, B.arena);
+  }
+  if (B.maxn > kSmallN) {
+    launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1,
+                 B.nmin_big);
+    launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena, B.nmin_big);
   }
   const size_t m1 = B.prof.mark();
   launch_assemble_pair(st, B.nptiles, B.maxn_pair, B.d_ptiles, B.d_terms, B.d_sys, B.d_flags,
@@ -512,8 +523,10 @@ static void op_factor(Batch& B, hipStream_t st) {
   for (int p = 0; p < B.maxP; ++p) {
     const int f = B.pan.first[p];
     const size_t m0 = B.prof.mark();
-    launch_chol_panel(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.d_pan_sys + f,
-                      B.d_pan_pre + f, B.pan.cnt[p], B.pan.tot[p], p);
+    launch_chol_diag(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.d_pan_sys + f, B.pan.cnt[p], p);
+    const int f2 = B.trs.first[p];
+    launch_chol_trsm(st, B.d_sys, B.d_flags, B.Lam, B.Linv, B.d_trs_sys + f2, B.d_trs_pre + f2,
+                     B.trs.cnt[p], B.trs.tot[p], p);
     const size_t m1 = B.prof.mark();
     B.prof.add(PSDP_PROF_CHOL_PANEL, m0, m1);
     if (B.upd.tot[p] > 0) {

@@ -151,8 +151,11 @@ int fail(int code, const std::string& msg);
 int64_t round_up(int64_t x, int64_t m);
 
 // Schur Cholesky / triangular solve launches (chol.hip)
-void launch_chol_panel(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
-                       double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
+void launch_chol_diag(hipStream_t st, const SysDesc* sys, int* flags, const double* Lam,
+                      double* Ldiag, double* Linv, const int* ssys, int cnt, int p);
+void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
+                      const double* Linv, const int* ssys, const int* spre, int cnt, int total,
+                      int p);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
                         const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
@@ -164,6 +167,7 @@ void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const
 void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int* flags,
                        const int* small_ids, const double* Lam, const double* Linv,
                        const double* rhs, double* r, double* x);
+constexpr int kSmallN = 16;   // blocks up to this order take the packed small-block kernels
 constexpr int kSmallP = 32;   // systems with at most this many Schur tiles solve in one launch
 
 // engine entry used by the public solve / eval calls

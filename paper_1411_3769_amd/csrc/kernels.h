@@ -14,7 +14,7 @@ void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, c
 void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                         const double* sc, const double* A, int tA, const double* B, int tB,
                         double* C, double alpha, int aslot, const double* D, double beta,
-                        int bslot);
+                        int bslot, int nmin);
 void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                    const double* Cf, const double* S, const double* Z, double* G);
 void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
@@ -40,17 +40,17 @@ void launch_form_P(hipStream_t st, int total, const SysDesc* sys, const int* fla
 void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* sys,
                     const int* flags, const double* Pm, double* out);
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
-                    const int* flags, const double* Pm, double* out);
+                    const int* flags, const double* Pm, double* out, int nmin);
 void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
-                const int* flags, const double* W, double* arena, const BlkDesc* blks);
+                const int* flags, const double* W, double* arena, const BlkDesc* blks, int nmin);
 void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
                      const int* own_pre, int S, const HMPair* pairs, const double* W,
                      const double* arena, const BlkDesc* blks, double* out, double asub);
 void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
                   const int* flags, const double* Zi, const double* X, double* arena,
-                  const BlkDesc* blks, const int64_t* offA1);
+                  const BlkDesc* blks, const int64_t* offA1, int nmin);
 void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, const int* flags,
-                  double* arena);
+                  double* arena, int nmin);
 void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                           const KTerm* terms, const SysDesc* sys, const int* flags,
                           const double* arena, double* Lam, int prec);
@@ -58,6 +58,7 @@ void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const
                          const SysDesc* sys, const int* flags, const int* gpinfo,
                          const double* arena, double* Lam, const int64_t* gpoff, int prec);
 bool use_small(int nmax);
+
 void launch_gemm_blocks_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks,
                               const int* flags, const double* sc, const double* A, int tA,
                               const double* B, int tB, double* C, double alpha, int aslot,

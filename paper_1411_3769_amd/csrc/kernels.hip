@@ -113,11 +113,13 @@ __global__ void __launch_bounds__(256) k_gemm_blocks(const BlkDesc* __restrict__
                                                      const double* __restrict__ sc,
                                                      const double* A, int tA, const double* B,
                                                      int tB, double* C, double alpha, int aslot,
-                                                     const double* D, double beta, int bslot) {
+                                                     const double* D, double beta, int bslot,
+                                                     int nmin) {
   __shared__ double sA[16 * 64];
   __shared__ double sB[16 * 64];
   const BlkDesc bd = blks[blockIdx.x];
   ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n < nmin) return;
   double a = alpha, c = beta;
   if (aslot >= 0) a *= sc[bd.sys * kNSC + aslot];
   if (bslot >= 0) c *= sc[bd.sys * kNSC + bslot];
@@ -373,11 +375,13 @@ __global__ void k_BT_pblk(const BlkDesc* __restrict__ pblks, const SysDesc* __re
 __global__ void __launch_bounds__(256) k_BT_dblk(const BlkDesc* __restrict__ dblks,
                                                  const SysDesc* __restrict__ sys,
                                                  const int* __restrict__ flags,
-                                                 const double* __restrict__ Pm, double* out) {
+                                                 const double* __restrict__ Pm, double* out,
+                                                 int nmin) {
   __shared__ double sA[16 * 64];
   __shared__ double sB[16 * 64];
   const BlkDesc bd = dblks[blockIdx.x];
   ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n < nmin) return;
   const SysDesc sd = sys[bd.sys];
   const int n = bd.n, nn = n * n;
   const int m = bd.j - sd.L;
@@ -407,11 +411,12 @@ __global__ void __launch_bounds__(256) k_B_Y(const HMPair* __restrict__ pairs,
                                              const SysDesc* __restrict__ sys,
                                              const int* __restrict__ flags,
                                              const double* __restrict__ W, double* arena,
-                                             const BlkDesc* __restrict__ blks) {
+                                             const BlkDesc* __restrict__ blks, int nmin) {
   __shared__ double sA[16 * 64];
   __shared__ double sB[16 * 64];
   const HMPair pr = pairs[blockIdx.x];
   ACTIVE_OR_RETURN(pr.sys);
+  if (pr.n < nmin) return;
   const SysDesc sd = sys[pr.sys];
   const int n = pr.n, nn = n * n;
   const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
@@ -467,11 +472,12 @@ __global__ void __launch_bounds__(256) k_pre12(const HMPair* __restrict__ pairs,
                                                const double* __restrict__ Zi,
                                                const double* __restrict__ X, double* arena,
                                                const BlkDesc* __restrict__ blks,
-                                               const int64_t* __restrict__ offA1) {
+                                               const int64_t* __restrict__ offA1, int nmin) {
   __shared__ double sA[16 * 64];
   __shared__ double sB[16 * 64];
   const HMPair pr = pairs[blockIdx.x];
   ACTIVE_OR_RETURN(pr.sys);
+  if (pr.n < nmin) return;
   const SysDesc sd = sys[pr.sys];
   const int n = pr.n, nn = n * n;
   const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
@@ -484,11 +490,12 @@ __global__ void __launch_bounds__(256) k_pre12(const HMPair* __restrict__ pairs,
 // A3 = H_h A2[m][h2] = H_h X H_h2^T,  A4 = H_h A1[m][h2] = H_h Zi H_h2^T
 __global__ void __launch_bounds__(256) k_pre34(const HM2* __restrict__ q,
                                                const SysDesc* __restrict__ sys,
-                                               const int* __restrict__ flags, double* arena) {
+                                               const int* __restrict__ flags, double* arena, int nmin) {
   __shared__ double sA[16 * 64];
   __shared__ double sB[16 * 64];
   const HM2 pr = q[blockIdx.x];
   ACTIVE_OR_RETURN(pr.sys);
+  if (pr.n < nmin) return;
   const SysDesc sd = sys[pr.sys];
   const int n = pr.n, nn = n * n;
   const double* Hh = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
@@ -1007,6 +1014,8 @@ __device__ inline double dot_n(int n, int i, int j, const double* __restrict__ A
   return acc;
 }
 
+// Items whose order exceeds nmax belong to the general kernels and are
+// skipped (each block takes the same kernel whatever the batch holds).
 #define SMALL_ITEM(count)                                   \
   const int per_ = nmax * nmax;                             \
   const int item = blockIdx.x * G + (int)threadIdx.x / per_; \
@@ -1020,6 +1029,7 @@ __global__ void __launch_bounds__(256) k_gemm_blocks_small(
   SMALL_ITEM(nblk);
   const BlkDesc bd = blks[item];
   if (!(flags[bd.sys] & F_ACTIVE)) return;
+  if (bd.n > nmax) return;
   const int n = bd.n;
   if (e_ >= n * n) return;
   const int i = e_ / n, j = e_ % n;
@@ -1039,6 +1049,7 @@ __global__ void __launch_bounds__(256) k_BT_dblk_small(int nd, int nmax, int G,
   SMALL_ITEM(nd);
   const BlkDesc bd = dblks[item];
   if (!(flags[bd.sys] & F_ACTIVE)) return;
+  if (bd.n > nmax) return;
   const SysDesc sd = sys[bd.sys];
   const int n = bd.n, nn = n * n;
   if (e_ >= nn) return;
@@ -1062,6 +1073,7 @@ __global__ void __launch_bounds__(256) k_B_Y_small(int np, int nmax, int G,
   SMALL_ITEM(np);
   const HMPair pr = pairs[item];
   if (!(flags[pr.sys] & F_ACTIVE)) return;
+  if (pr.n > nmax) return;
   const SysDesc sd = sys[pr.sys];
   const int n = pr.n, nn = n * n;
   if (e_ >= nn) return;
@@ -1081,6 +1093,7 @@ __global__ void __launch_bounds__(256) k_pre12_small(int np, int nmax, int G,
   SMALL_ITEM(np);
   const HMPair pr = pairs[item];
   if (!(flags[pr.sys] & F_ACTIVE)) return;
+  if (pr.n > nmax) return;
   const SysDesc sd = sys[pr.sys];
   const int n = pr.n, nn = n * n;
   if (e_ >= nn) return;
@@ -1099,6 +1112,7 @@ __global__ void __launch_bounds__(256) k_pre34_small(int nq, int nmax, int G,
   SMALL_ITEM(nq);
   const HM2 pr = q[item];
   if (!(flags[pr.sys] & F_ACTIVE)) return;
+  if (pr.n > nmax) return;
   const SysDesc sd = sys[pr.sys];
   const int n = pr.n, nn = n * n;
   if (e_ >= nn) return;
@@ -1219,9 +1233,9 @@ void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, c
 void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                         const double* sc, const double* A, int tA, const double* B, int tB,
                         double* C, double alpha, int aslot, const double* D, double beta,
-                        int bslot) {
+                        int bslot, int nmin) {
   hipLaunchKernelGGL(k_gemm_blocks, dim3(nblk), dim3(256), 0, st, blks, flags, sc, A, tA, B, tB, C,
-                     alpha, aslot, D, beta, bslot);
+                     alpha, aslot, D, beta, bslot, nmin);
 }
 
 void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
@@ -1279,14 +1293,14 @@ void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* 
 }
 
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
-                    const int* flags, const double* Pm, double* out) {
+                    const int* flags, const double* Pm, double* out, int nmin) {
   if (n)
-    hipLaunchKernelGGL(k_BT_dblk, dim3(n), dim3(256), 0, st, dblks, sys, flags, Pm, out);
+    hipLaunchKernelGGL(k_BT_dblk, dim3(n), dim3(256), 0, st, dblks, sys, flags, Pm, out, nmin);
 }
 
 void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
-                const int* flags, const double* W, double* arena, const BlkDesc* blks) {
-  if (np) hipLaunchKernelGGL(k_B_Y, dim3(np), dim3(256), 0, st, pairs, sys, flags, W, arena, blks);
+                const int* flags, const double* W, double* arena, const BlkDesc* blks, int nmin) {
+  if (np) hipLaunchKernelGGL(k_B_Y, dim3(np), dim3(256), 0, st, pairs, sys, flags, W, arena, blks, nmin);
 }
 
 void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
@@ -1298,14 +1312,15 @@ void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* 
 
 void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
                   const int* flags, const double* Zi, const double* X, double* arena,
-                  const BlkDesc* blks, const int64_t* offA1) {
+                  const BlkDesc* blks, const int64_t* offA1, int nmin) {
   if (np)
-    hipLaunchKernelGGL(k_pre12, dim3(np), dim3(256), 0, st, pairs, sys, flags, Zi, X, arena, blks, offA1);
+    hipLaunchKernelGGL(k_pre12, dim3(np), dim3(256), 0, st, pairs, sys, flags, Zi, X, arena, blks, offA1,
+                       nmin);
 }
 
 void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, const int* flags,
-                  double* arena) {
-  if (nq) hipLaunchKernelGGL(k_pre34, dim3(nq), dim3(256), 0, st, q, sys, flags, arena);
+                  double* arena, int nmin) {
+  if (nq) hipLaunchKernelGGL(k_pre34, dim3(nq), dim3(256), 0, st, q, sys, flags, arena, nmin);
 }
 
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
@@ -1391,7 +1406,7 @@ void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const
 
 namespace psdp {
 
-static int small_G(int nmax) { return nmax <= 16 ? 256 / (nmax * nmax) : 0; }
+static int small_G(int nmax) { return nmax >= 1 && nmax <= kSmallN ? 256 / (nmax * nmax) : 0; }
 
 bool use_small(int nmax) { return small_G(nmax) > 0; }
 

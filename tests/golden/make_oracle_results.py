@@ -11,12 +11,20 @@ import json
 import os
 import sys
 import time
+from math import comb
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
 from oracle import ipm, sdp as S  # noqa: E402
 from paper_1411_3769_amd import workloads as W  # noqa: E402
+
+
+MIXED_MAX_K = 300
+
+
+def mixed_K(sy):
+    return comb(sy.l + sy.dp - 1, sy.dp) * sy.n * (sy.n + 1) // 2
 
 
 def run(sy):
@@ -38,11 +46,17 @@ def main():
         cases.append(W.plain_system(s, twin=True))
     for s in range(64):
         cases.append(W.c1_system(s))
-    for (n, l) in [(4, 5), (5, 6), (7, 8)]:
+    for (n, l) in [(4, 5), (5, 6), (7, 8), (16, 3), (24, 2)]:
         cases.append(W.paper_shape_system(n, l, 0))
+    # the members of the 512-system mixed batch small enough for the oracle
+    for i, sy in enumerate(W.mixed_systems(512)):
+        if mixed_K(sy) <= MIXED_MAX_K:
+            cases.append(sy)
     out = []
     for sy in cases:
         rec = run(sy)
+        if rec["tag"].startswith("mixed"):
+            rec["index"] = int(rec["tag"][5:])
         out.append(rec)
         print(rec["tag"], rec["seed"], rec["verdict"], rec["iterations"], f"{rec['seconds']:.2f}s",
               flush=True)

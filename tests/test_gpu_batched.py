@@ -1,0 +1,112 @@
+"""Batched form on the GPU (marker: gpu): many uncertain systems of uneven
+n, l, dp and d in one batched solve (one launch per kernel and IPM step for
+the whole batch).
+
+The batch is the seeded 512-system mixed family (n in [6, 48], l in 2..5,
+dp in 1..2, d in 1..4, perturbation scale in [0.1, 0.5]).  Its members with
+K <= 300 have oracle end points (tests/golden); they are solved together
+with larger members, whose results are checked by properties that hold at
+any size (oracle operators applied to the returned y).
+"""
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+from conftest import GOLDEN
+from oracle import sdp as S
+from paper_1411_3769_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1411_3769_amd import polyaipm
+    polyaipm.load()
+    return polyaipm
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    return W.mixed_systems(512)
+
+
+def _K(sy):
+    return comb(sy.l + sy.dp - 1, sy.dp) * sy.n * (sy.n + 1) // 2
+
+
+def _golden_mixed():
+    with open(os.path.join(GOLDEN, "oracle_results.json")) as fh:
+        return {r["index"]: r for r in json.load(fh) if r["tag"].startswith("mixed")}
+
+
+def _check(rec, r):
+    assert r.verdict_name == rec["verdict"], (rec["tag"], r.verdict_name, r.reason_name)
+    if rec["verdict"] == "FEASIBLE" and not rec["phase1_used"]:
+        assert abs(r.psi - rec["psi"]) <= 1e-6 * abs(rec["psi"])
+        assert abs(r.phi - rec["phi"]) <= 1e-6 * abs(rec["phi"])
+        assert abs(r.margin - rec["margin"]) <= 1e-6 * abs(rec["margin"])
+        assert r.gap_rel <= 1e-8 and r.pinf <= 1e-8 and r.dinf <= 1e-8
+        assert abs(r.iterations - rec["iterations"]) <= 2
+
+
+def _perm(g, n, L0):
+    pairs = g.basis()
+    opos = {pq: b for b, pq in enumerate(S.basis_pairs(n))}
+    Nt = n * (n + 1) // 2
+    bmap = np.array([opos[(int(p), int(q))] for p, q in pairs])
+    return np.concatenate([h * Nt + bmap for h in range(L0)])
+
+
+def _check_properties(sy, g, r):
+    """Certificate facts with the oracle's operators: a^T y = psi, every
+    block of B^T(y) positive definite, margin = min_j lambda_min / s_j."""
+    assert r.verdict_name in ("FEASIBLE", "INFEASIBLE", "UNKNOWN")
+    if r.verdict_name != "FEASIBLE":
+        return
+    sdp = S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d)
+    y = np.empty_like(r.y)
+    y[_perm(g, sy.n, sdp.L0)] = r.y
+    if not r.phase1_used:
+        assert abs(float(sdp.a() @ y) - r.psi) <= 1e-9 * abs(r.psi)
+    Q = sdp.BT(y)
+    lam = np.array([np.linalg.eigvalsh(Q[j])[0] for j in range(sdp.nb)])
+    assert lam.min() > 0
+    assert abs(r.margin - float(np.min(lam / sdp.scale))) <= 1e-6 * abs(r.margin)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mixed_small_members_vs_oracle(P, mixed, prec):
+    gold = _golden_mixed()
+    assert len(gold) >= 40
+    idx = sorted(gold)
+    print(f"mixed batch, {len(idx)} oracle members, {prec}", flush=True)
+    gs = [P.polya_setup(mixed[i].A, mixed[i].n, mixed[i].l, mixed[i].dp, mixed[i].d) for i in idx]
+    rs = P.ipm_solve_batched(gs, precision=prec)
+    for i, r in zip(idx, rs):
+        _check(gold[i], r)
+
+
+def test_mixed_uneven_batch(P, mixed):
+    """Oracle members solved in one batch with larger members (K up to
+    about 2500): the former match the oracle, the latter satisfy the
+    certificate properties, and every member equals its single solve."""
+    gold = _golden_mixed()
+    small = sorted(gold)[:24]
+    large = [i for i, sy in enumerate(mixed) if 300 < _K(sy) <= 2500][:12]
+    idx = small + large
+    print(f"uneven batch: {len(small)} small + {len(large)} large", flush=True)
+    gs = [P.polya_setup(mixed[i].A, mixed[i].n, mixed[i].l, mixed[i].dp, mixed[i].d) for i in idx]
+    rs = P.ipm_solve_batched(gs, precision="fp32")
+    for i, g, r in zip(idx, gs, rs):
+        if i in gold:
+            _check(gold[i], r)
+        else:
+            _check_properties(mixed[i], g, r)
+    for k in (0, len(small)):
+        r1 = P.ipm_solve(gs[k], precision="fp32")
+        assert r1.verdict == rs[k].verdict and r1.iterations == rs[k].iterations
+        assert np.array_equal(r1.y, rs[k].y)
