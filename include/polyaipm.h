@@ -132,6 +132,28 @@ typedef struct {
                           /* per launch class, the summed device time (ms) and the   */
                           /* number of launches, measured with HIP events on the     */
                           /* solver stream (accumulated, not cleared)                */
+    /* Warm start (NULL = cold start X = Z = I, y = 0).  Per system (array of
+     * count host pointers, entries may be NULL): warm_y[s] holds K dual values
+     * in the library's dual order (psdp_basis), warm_logx[s] holds L+M values
+     * s_j.  The start is projected into the interior: y = warm_y,
+     * Z_j = B^T(y)_j - C_j + tau_j I with tau_j = max(0, theta s_j' - lambda_min)
+     * (s_j' the block scale, lambda_min by bisection on FP64 Cholesky), and
+     * X_j from exp(s_j) (see warm_center; s_j = 0 without warm_logx).  The
+     * warm run is the paper's SDP run only, capped at warm_iter_cap
+     * iterations (0: max_iter); a warm-started system that ends without a
+     * certified FEASIBLE verdict or a Farkas ray is solved again from the cold
+     * start (with phase-I as usual); the result says which run it reports. */
+    const double* const* warm_y;
+    const double* const* warm_logx;
+    int    warm_iter_cap;
+    double warm_margin;   /* theta in tau_j = max(0, theta s_j' - lambda_min) (1e-6)  */
+    int    warm_center;   /* 0: X_j = exp(s_j) I; 1 (default): X_j = exp(s_j) n       */
+                          /* Z_j^-1 / tr(Z_j^-1), the projected Z's centred partner   */
+                          /* with block trace exp(s_j) n                              */
+    double label_gap;     /* > 0: record in psdp_result.label_y / label_logx the     */
+                          /* iterate of the paper's SDP run at the first iteration    */
+                          /* whose relative gap is <= label_gap (training labels of   */
+                          /* the learned warm start)                                  */
 } psdp_opts;
 
 typedef struct {
@@ -161,6 +183,14 @@ typedef struct {
                             /* refinement cannot bring below 1e-10, or a failed      */
                             /* Cholesky of the reduced-precision matrix switches the */
                             /* system to FP64 assembly for the rest of the run       */
+    int     warm_used;      /* 1: the reported run started from the warm start       */
+    int     warm_fallback;  /* 1: the warm run was rejected and a cold run followed  */
+    int     warm_iterations;/* iterations of the warm-started run (0 if none)        */
+    double* logx;           /* caller buffer [L+M] or NULL: log(tr(X_j) / n) of the  */
+                            /* final primal iterate of the paper's SDP run           */
+    double* label_y;        /* caller buffers [K] and [L+M] or NULL: y and           */
+    double* label_logx;     /* log(tr(X_j) / n) at the label_gap iterate             */
+    int     label_iter;     /* that iteration (-1: not reached)                      */
     psdp_iter_rec* history; /* caller buffer of history_cap records, or NULL         */
     int     history_cap;
     int     history_len;
@@ -254,6 +284,34 @@ const char* psdp_last_error(void);
 
 /* Library version string. */
 const char* psdp_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start: the network that proposes a starting point (not part of
+ * the paper).  A three-layer perceptron d0 -> d1 -> d2 -> d3 with GELU
+ * (x Phi(x)) on the two hidden layers, trained on the mean squared error
+ * sum_b ||out_b - t_b||^2 / (2 batch) with Adam.  Products run on MFMA with
+ * FP32 accumulation, their operands in FP32 or rounded to BF16
+ * (precision = PSDP_PREC_FP32 / PSDP_PREC_BF16).  Parameters are one FP32
+ * array [W1, b1, W2, b2, W3, b3], W_i row-major [d_i x d_{i-1}].
+ * x, t and out are DEVICE pointers to row-major FP32 [batch x width];
+ * every call synchronizes its stream.
+ * ------------------------------------------------------------------------- */
+typedef struct psdp_mlp psdp_mlp;
+
+int psdp_mlp_create(const int* dims /*[4]*/, int precision, int max_batch, psdp_mlp** out);
+int64_t psdp_mlp_param_count(const psdp_mlp* m);
+/* host FP32 arrays of psdp_mlp_param_count entries; set resets Adam */
+int psdp_mlp_set_params(psdp_mlp* m, const float* host);
+int psdp_mlp_get_params(const psdp_mlp* m, float* host /*or NULL*/, float* grad_host /*or NULL*/);
+/* out [batch x d3] */
+int psdp_mlp_forward(psdp_mlp* m, const float* x, int batch, float* out, void* stream);
+/* forward + backward: the gradient stays on the device (psdp_mlp_get_params
+ * reads it); *loss (host, may be NULL) receives the loss */
+int psdp_mlp_loss_grad(psdp_mlp* m, const float* x, const float* t, int batch, double* loss,
+                       void* stream);
+/* one Adam step with the last gradient (bias-corrected moments) */
+int psdp_mlp_adam(psdp_mlp* m, float lr, float b1, float b2, float eps, void* stream);
+void psdp_mlp_free(psdp_mlp* m);
 
 #ifdef __cplusplus
 }

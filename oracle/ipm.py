@@ -261,13 +261,16 @@ def _solve(R: np.ndarray, tau: float, Lam: np.ndarray, rhs: np.ndarray, opt: Opt
 
 
 def ipm_run(ops, opt: Options, phase1: bool = False,
-            callback: Optional[Callable] = None) -> RunResult:
+            callback: Optional[Callable] = None, start=None, max_iter: Optional[int] = None) -> RunResult:
     n, nb, K = ops.n, ops.nb, ops.K
     m = nb * n
     I = np.eye(n)
     X = np.repeat(I[None], nb, axis=0)
     Z = X.copy()
     y = ops.init_y()
+    if start is not None:
+        X, y, Z = (np.array(v, dtype=np.float64, copy=True) for v in start)
+    cap = opt.max_iter if max_iter is None else max_iter
     a = ops.a
     C = ops.C
     normC = np.linalg.norm(C)
@@ -309,7 +312,7 @@ def ipm_run(ops, opt: Options, phase1: bool = False,
             if it >= w and dinf > opt.feas_tol and dinf > opt.stall_drop * hist[it - w]["dinf"]:
                 reason = STALL
                 break
-        if it >= opt.max_iter:
+        if it >= cap:
             reason = MAXITER
             break
         # Newton system
@@ -380,9 +383,73 @@ class SolveResult:
     phase1_iterations: int = 0
     phase1_reason: int = -1
     t_star: float = float("nan")
+    warm_used: bool = False
+    warm_fallback: bool = False
+    warm_iterations: int = 0
 
 
-def ipm_solve(sdp: PolyaSDP, opt: Optional[Options] = None) -> SolveResult:
+def warm_start_point(sdp: PolyaSDP, y0: np.ndarray, logx: Optional[np.ndarray] = None,
+                     margin: float = 1e-6, center: bool = True):
+    """Interior starting point from a predicted dual vector y0 and predicted
+    log block scales s_j of X (learned warm start; not part of the paper).
+
+    Z_j = B^T(y0)_j - C_j + tau_j I with tau_j = max(0, margin s'_j -
+    lambda_min(B^T(y0)_j - C_j)) (s'_j the block scale), so that Z_j >=
+    margin s'_j I; X_j = exp(s_j) n Z_j^{-1} / tr(Z_j^{-1}) (center) or
+    exp(s_j) I.  lambda_min is taken from the symmetric eigensolver."""
+    nb, n = sdp.nb, sdp.n
+    s = np.zeros(nb) if logx is None else np.asarray(logx, dtype=np.float64)
+    W = sdp.BT(np.asarray(y0, dtype=np.float64)) - sdp.C_blocks()
+    X = np.empty_like(W)
+    Z = np.empty_like(W)
+    I = np.eye(n)
+    for j in range(nb):
+        lam = float(np.linalg.eigvalsh(W[j])[0])
+        tau = max(0.0, margin * sdp.scale[j] - lam)
+        Z[j] = W[j] + tau * I
+        if center:
+            Zi = np.linalg.inv(Z[j])
+            Zi = 0.5 * (Zi + Zi.T)
+            X[j] = np.exp(s[j]) * n * Zi / np.trace(Zi)
+        else:
+            X[j] = np.exp(s[j]) * I
+    return X, np.array(y0, dtype=np.float64), Z
+
+
+def ipm_solve(sdp: PolyaSDP, opt: Optional[Options] = None, warm=None,
+              warm_iter_cap: int = 0, warm_margin: float = 1e-6,
+              warm_center: bool = True) -> SolveResult:
+    """With warm = (y0, logx): the paper's SDP is first solved from
+    warm_start_point (at most warm_iter_cap iterations, 0: max_iter); a
+    converged run with a passing certificate gives FEASIBLE and a Farkas ray
+    INFEASIBLE; anything else falls back to the cold pipeline below.
+    SolveResult.warm_used / warm_fallback / warm_iterations record which."""
+    opt = opt or Options()
+    if warm is not None:
+        start = warm_start_point(sdp, warm[0], warm[1], warm_margin, warm_center)
+        cap = warm_iter_cap if warm_iter_cap > 0 else opt.max_iter
+        r = ipm_run(PaperOps(sdp), opt, start=start, max_iter=min(cap, opt.max_iter))
+        if r.reason == CONVERGED:
+            ok, mg, mP, mD = certificate(sdp, r.y)
+            if ok:
+                res = SolveResult(FEASIBLE, sdp.P_of_y(r.y), r.y, r.phi, r.psi, r.gap_abs, r.gap_rel,
+                                  r.pinf, r.dinf, mg, mP, mD, r.iterations, r.reason)
+                res.warm_used, res.warm_iterations = True, r.iterations
+                return res
+        elif r.reason == FARKAS:
+            nanv = float("nan")
+            res = SolveResult(INFEASIBLE, np.zeros((sdp.L0, sdp.n, sdp.n)), r.y, r.phi, r.psi,
+                              r.gap_abs, r.gap_rel, r.pinf, r.dinf, nanv, nanv, nanv, r.iterations,
+                              r.reason)
+            res.warm_used, res.warm_iterations = True, r.iterations
+            return res
+        res = ipm_solve(sdp, opt)
+        res.warm_fallback, res.warm_iterations = True, r.iterations
+        return res
+    return _solve_cold(sdp, opt)
+
+
+def _solve_cold(sdp: PolyaSDP, opt: Options) -> SolveResult:
     """Verdict pipeline: the paper's SDP first; FEASIBLE when it converges and
     the certificate check passes; INFEASIBLE on a Farkas ray; otherwise the
     phase-I margin SDP decides by the sign of t* (|t*| <= phase1_tol gives

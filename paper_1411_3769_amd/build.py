@@ -26,6 +26,7 @@ SOURCES = {
     "kernels.hip": [],
     "chol.hip": [],
     "engine.hip": [],
+    "mlp.hip": [],
 }
 
 COMMON = [

@@ -610,6 +610,9 @@ static int init_state(Batch& B, hipStream_t st) {
 }
 
 struct RunState {
+  int max_iter = 0;             // iteration cap of this system's run
+  int label_iter = -1;          // iteration whose iterate was recorded as the label
+  std::vector<double> label_y, label_logx;
   int reason = PSDP_R_MAXITER;
   int iterations = 0;
   bool running = true;
@@ -712,8 +715,29 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
           r.running = false; r.reason = PSDP_R_STALL; continue;
         }
       }
-      if (it >= o.max_iter) { r.running = false; r.reason = PSDP_R_MAXITER; continue; }
+      if (it >= r.max_iter) { r.running = false; r.reason = PSDP_R_MAXITER; continue; }
       any = true;
+    }
+    // training labels: the iterate at the first iteration with gap_rel <= label_gap
+    if (o.label_gap > 0) {
+      std::vector<int> want;
+      for (int s = 0; s < S; ++s)
+        if (rs[s].label_iter < 0 && B.sys[s].mode == 0 && std::isfinite(rs[s].gap_rel) &&
+            rs[s].gap_rel <= o.label_gap && !(prev[s] & F_ZFAIL))
+          want.push_back(s);
+      if (!want.empty()) {
+        std::vector<double> yh(B.totvec), lx(B.nblk);
+        launch_block_logtrace(st, B.nblk, B.d_blk, B.d_flags, B.X, B.d_red);
+        PSDP_HIP(hipMemcpyAsync(yh.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
+        PSDP_HIP(hipMemcpyAsync(lx.data(), B.d_red, B.nblk * 8, hipMemcpyDeviceToHost, st));
+        PSDP_HIP(hipStreamSynchronize(st));
+        for (int s : want) {
+          const SysDesc& d = B.sys[s];
+          rs[s].label_iter = it;
+          rs[s].label_y.assign(yh.begin() + d.voff, yh.begin() + d.voff + d.K);
+          rs[s].label_logx.assign(lx.begin() + d.blk0, lx.begin() + d.blk0 + d.nb);
+        }
+      }
     }
     if (!any) break;
     set_flags(B, rs, hf);
@@ -809,10 +833,44 @@ static void validate_opts(const psdp_opts* in, psdp_opts& o) {
 
 // ---------------------------------------------------------------------------
 
-int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res) {
+// Warm start: y from warm_y, Z projected into the interior, X from warm_logx
+// (systems without warm data keep the cold start).
+static int warm_project(Batch& B, hipStream_t st, const psdp_opts& o, const std::vector<char>& warm) {
+  const int S = B.S;
+  std::vector<int> hf(S, 0);
+  std::vector<double> yv(B.totvec, 0.0), lx(B.nblk, 0.0);
+  for (int s = 0; s < S; ++s) {
+    if (!warm[s]) continue;
+    hf[s] = F_ACTIVE;
+    const SysDesc& d = B.sys[s];
+    if (o.warm_y && o.warm_y[s]) std::memcpy(yv.data() + d.voff, o.warm_y[s], d.K * 8);
+    for (int j = 0; j < d.nb; ++j)
+      lx[d.blk0 + j] = (o.warm_logx && o.warm_logx[s]) ? o.warm_logx[s][j] : 0.0;
+  }
+  for (double v : lx)
+    if (!std::isfinite(v) || std::fabs(v) > 700.0) return fail(PSDP_EINVAL, "warm_logx out of range");
+  for (double v : yv)
+    if (!std::isfinite(v)) return fail(PSDP_EINVAL, "warm_y is not finite");
+  PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), S * 4, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.y, yv.data(), B.totvec * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.d_red, lx.data(), B.nblk * 8, hipMemcpyHostToDevice, st));
+  op_BT(B, st, B.y, B.S1, false);
+  launch_axpby(st, B.nblk, B.d_blk, B.d_flags, 1.0, B.S1, -1.0, B.Cf, B.T1);   // W = B^T(y) - C
+  launch_certificate(st, B.nblk, B.maxn, B.d_blk, B.d_sys, B.d_flags, B.T1, 60, B.d_cert);
+  launch_warm_init(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, B.T1, B.d_cert, B.d_red, o.warm_margin,
+                   B.X, B.Z);
+  if (o.warm_center) {
+    launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
+    launch_warm_center(st, B.nblk, B.d_blk, B.d_flags, B.Zi, B.d_red, B.X);
+  }
+  PSDP_HIP(hipGetLastError());
+  PSDP_HIP(hipStreamSynchronize(st));
+  return PSDP_OK;
+}
+
+static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp_result* res,
+                      bool use_warm) {
   auto t0 = std::chrono::steady_clock::now();
-  psdp_opts o;
-  validate_opts(opts, o);
   if (!(o.gap_tol > 0) || !(o.feas_tol > 0) || o.max_iter < 0 || !(o.sigma > 0 && o.sigma < 1) ||
       !(o.step_frac > 0 && o.step_frac <= 1) || !(o.ladder_rho > 0 && o.ladder_rho < 1) ||
       o.ladder_len < 0)
@@ -834,14 +892,31 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
   int rc = build_batch(B, sdps, count);
   if (rc) return rc;
   if ((rc = init_state(B, st))) return rc;
+  std::vector<char> warm(count, 0);
+  bool anywarm = false;
+  if (use_warm)
+    for (int s = 0; s < count; ++s) {
+      warm[s] = (o.warm_y && o.warm_y[s]) || (o.warm_logx && o.warm_logx[s]);
+      anywarm = anywarm || warm[s];
+    }
+  if (anywarm && (rc = warm_project(B, st, o, warm))) return rc;
   std::vector<std::vector<psdp_iter_rec>> hist(count);
+  std::vector<double> logx(B.nblk, NAN);
   std::vector<RunState> rs(count);
+  for (int s = 0; s < count; ++s)
+    rs[s].max_iter = (warm[s] && o.warm_iter_cap > 0) ? std::min(o.max_iter, o.warm_iter_cap) : o.max_iter;
   std::vector<double> y1(B.totvec, 0.0), y2(B.totvec, 0.0);
 
   // pass 1: the paper's SDP
   if (o.verdict_mode != PSDP_VERDICT_PHASE1_ONLY) {
     if ((rc = run_ipm(B, o, st, rs, o.record_history ? &hist : nullptr))) return rc;
     PSDP_HIP(hipMemcpyAsync(y1.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
+    {
+      std::vector<int> hf(count, F_ACTIVE);
+      PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), count * 4, hipMemcpyHostToDevice, st));
+      launch_block_logtrace(st, B.nblk, B.d_blk, B.d_flags, B.X, B.d_red);
+      PSDP_HIP(hipMemcpyAsync(logx.data(), B.d_red, B.nblk * 8, hipMemcpyDeviceToHost, st));
+    }
     PSDP_HIP(hipStreamSynchronize(st));
     B.prof.harvest();
   } else {
@@ -854,11 +929,12 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
   for (int s = 0; s < count; ++s) {
     if (o.verdict_mode == PSDP_VERDICT_PHASE1_ONLY) need[s] = 1;
     else if (o.verdict_mode == PSDP_VERDICT_PAPER_THEN_PHASE1 && rs[s].reason != PSDP_R_CONVERGED &&
-             rs[s].reason != PSDP_R_FARKAS)
+             rs[s].reason != PSDP_R_FARKAS && !warm[s])   // a warm run that fails falls back cold
       need[s] = 1;
     anyneed = anyneed || need[s];
   }
   std::vector<RunState> r1(count);
+  for (auto& q : r1) q.max_iter = o.max_iter;
   if (anyneed) {
     for (int s = 0; s < count; ++s) {
       B.sys[s].mode = need[s] ? 1 : 0;
@@ -958,6 +1034,16 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
     R.iters_lowprec = r.it32 + (need[s] ? r1[s].it32 : 0);
     R.ir_steps = r.ir_steps + (need[s] ? r1[s].ir_steps : 0);
     R.ir_eta_max = R.iters_lowprec ? std::max(r.eta_max, need[s] ? r1[s].eta_max : 0.0) : NAN;
+    R.label_iter = r.label_iter;
+    if (r.label_iter >= 0) {
+      if (R.label_y) std::memcpy(R.label_y, r.label_y.data(), d.K * 8);
+      if (R.label_logx) std::memcpy(R.label_logx, r.label_logx.data(), d.nb * 8);
+    }
+    R.warm_used = warm[s];
+    R.warm_fallback = 0;
+    R.warm_iterations = warm[s] ? r.iterations : 0;
+    if (R.logx)
+      for (int j = 0; j < d.nb; ++j) R.logx[j] = logx[d.blk0 + j];
     R.history_len = 0;
     if (R.history && R.history_cap > 0) {
       const int nrec = std::min<int>(R.history_cap, (int)hist[s].size());
@@ -1002,6 +1088,41 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
         }
     }
   }
+  return PSDP_OK;
+}
+
+int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res) {
+  auto t0 = std::chrono::steady_clock::now();
+  psdp_opts o;
+  validate_opts(opts, o);
+  if (o.warm_iter_cap < 0) return fail(PSDP_EINVAL, "warm_iter_cap < 0");
+  if (!(o.warm_margin >= 0.0) || !(o.warm_margin < 1.0)) return fail(PSDP_EINVAL, "warm_margin not in [0, 1)");
+  int rc = solve_core(sdps, count, o, res, true);
+  if (rc) return rc;
+  // rejected warm starts: solve again from the cold start
+  std::vector<int> redo;
+  for (int s = 0; s < count; ++s)
+    if (res[s].warm_used &&
+        (res[s].verdict == PSDP_UNKNOWN || (o.warm_iter_cap > 0 && res[s].iterations > o.warm_iter_cap)))
+      redo.push_back(s);
+  if (!redo.empty()) {
+    std::vector<psdp_sdp*> sub;
+    std::vector<psdp_result> rr;
+    for (int s : redo) {
+      sub.push_back(sdps[s]);
+      rr.push_back(res[s]);   // same caller buffers
+    }
+    if ((rc = solve_core(sub.data(), (int)sub.size(), o, rr.data(), false))) return rc;
+    for (size_t i = 0; i < redo.size(); ++i) {
+      const int wit = res[redo[i]].warm_iterations;
+      res[redo[i]] = rr[i];
+      res[redo[i]].warm_used = 0;
+      res[redo[i]].warm_fallback = 1;
+      res[redo[i]].warm_iterations = wit;
+    }
+  }
+  const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int s = 0; s < count; ++s) res[s].time_solve_s = el;
   return PSDP_OK;
 }
 

@@ -72,6 +72,13 @@ void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, c
                         const BlkDesc* blks, const int64_t* offA1);
 void launch_pre34_small(hipStream_t st, int nq, int nmax, const HM2* q, const SysDesc* sys,
                         const int* flags, double* arena);
+void launch_warm_init(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                      const int* flags, const double* W, const double* cert, const double* logx,
+                      double theta, double* X, double* Z);
+void launch_warm_center(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                        const double* Zi, const double* logx, double* X);
+void launch_block_logtrace(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                           const double* X, double* out);
 void launch_park(hipStream_t st, int S, int* flags, int mode);
 void launch_ir_check(hipStream_t st, int S, const SysDesc* sys, int* flags, const double* r,
                      const double* rhs, double* sc, int k, int kmax, int first_solve);

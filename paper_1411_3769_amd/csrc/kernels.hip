@@ -1186,7 +1186,76 @@ __global__ void __launch_bounds__(256) k_ir_check(const SysDesc* __restrict__ sy
   }
 }
 
+// Warm start projected into the interior: with W_j = B^T(y)_j - C_j and
+// lambda_min(W_j) = cert[2j+1] s_j (bisection on Cholesky),
+// Z_j = W_j + tau_j I, tau_j = max(0, theta s_j - lambda_min), and
+// X_j = exp(logx_j) I (X_j = I if logx is NULL).
+__global__ void k_warm_init(const BlkDesc* __restrict__ blks, const SysDesc* __restrict__ sys,
+                            const int* __restrict__ flags, const double* __restrict__ W,
+                            const double* __restrict__ cert, const double* __restrict__ logx,
+                            double theta, double* X, double* Z) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const double sj = sys[bd.sys].scale[bd.j];
+  const double lam = cert[2 * blockIdx.x + 1] * sj;
+  const double tau = fmax(0.0, theta * sj - lam);
+  const double xs = logx ? exp(logx[blockIdx.x]) : 1.0;
+  const int n = bd.n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const bool dg = (e / n) == (e % n);
+    Z[bd.off + e] = W[bd.off + e] + (dg ? tau : 0.0);
+    X[bd.off + e] = dg ? xs : 0.0;
+  }
+}
+
+// Centred warm primal: X_j = exp(logx_j) n Zi_j / tr(Zi_j) (Zi = Z^{-1}).
+__global__ void k_warm_center(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+                              const double* __restrict__ Zi, const double* __restrict__ logx,
+                              double* X) {
+  __shared__ double tr;
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const int n = bd.n;
+  if (threadIdx.x < 64) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) t += Zi[bd.off + (int64_t)i * n + i];
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+    if (threadIdx.x == 0) tr = t;
+  }
+  __syncthreads();
+  const double f = (logx ? exp(logx[blockIdx.x]) : 1.0) * n / tr;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) X[bd.off + e] = f * Zi[bd.off + e];
+}
+
+// out[j] = log(tr(X_j) / n) per block (wave 0 of the workgroup)
+__global__ void k_block_logtrace(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+                                 const double* __restrict__ X, double* out) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  double t = 0.0;
+  for (int i = threadIdx.x; i < bd.n; i += 64) t += X[bd.off + (int64_t)i * bd.n + i];
+  for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+  if (threadIdx.x == 0) out[blockIdx.x] = log(t / bd.n);
+}
+
 // launch wrappers ----------------------------------------------------------------
+
+void launch_warm_init(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                      const int* flags, const double* W, const double* cert, const double* logx,
+                      double theta, double* X, double* Z) {
+  hipLaunchKernelGGL(k_warm_init, dim3(nblk), dim3(256), 0, st, blks, sys, flags, W, cert, logx, theta,
+                     X, Z);
+}
+
+void launch_warm_center(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                        const double* Zi, const double* logx, double* X) {
+  hipLaunchKernelGGL(k_warm_center, dim3(nblk), dim3(256), 0, st, blks, flags, Zi, logx, X);
+}
+
+void launch_block_logtrace(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
+                           const double* X, double* out) {
+  hipLaunchKernelGGL(k_block_logtrace, dim3(nblk), dim3(64), 0, st, blks, flags, X, out);
+}
 
 void launch_park(hipStream_t st, int S, int* flags, int mode) {
   hipLaunchKernelGGL(k_park, dim3((S + 255) / 256), dim3(256), 0, st, S, flags, mode);

@@ -206,6 +206,12 @@ void psdp_opts_default(psdp_opts* o) {
   o->stream = nullptr;
   o->record_history = 0;
   o->prof = nullptr;
+  o->warm_y = nullptr;
+  o->warm_logx = nullptr;
+  o->warm_iter_cap = 0;
+  o->warm_margin = 1e-6;
+  o->warm_center = 1;
+  o->label_gap = 0.0;
 }
 
 const char* psdp_last_error(void) { return g_err.c_str(); }

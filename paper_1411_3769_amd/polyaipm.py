@@ -56,7 +56,9 @@ class Opts(C.Structure):
     _fields_ = [("gap_tol", C.c_double), ("feas_tol", C.c_double), ("max_iter", C.c_int),
                 ("sigma", C.c_double), ("step_frac", C.c_double), ("ladder_rho", C.c_double),
                 ("ladder_len", C.c_int), ("verdict_mode", C.c_int), ("precision", C.c_int),
-                ("ir_max", C.c_int), ("stream", C.c_void_p), ("record_history", C.c_int), ("prof", DP)]
+                ("ir_max", C.c_int), ("stream", C.c_void_p), ("record_history", C.c_int), ("prof", DP),
+                ("warm_y", C.POINTER(DP)), ("warm_logx", C.POINTER(DP)), ("warm_iter_cap", C.c_int),
+                ("warm_margin", C.c_double), ("warm_center", C.c_int), ("label_gap", C.c_double)]
 
 
 class IterRec(C.Structure):
@@ -72,6 +74,8 @@ class CResult(C.Structure):
                 ("iterations", C.c_int), ("phase1_used", C.c_int), ("phase1_iterations", C.c_int),
                 ("t_star", C.c_double), ("time_solve_s", C.c_double), ("iters_lowprec", C.c_int),
                 ("ir_steps", C.c_int), ("ir_eta_max", C.c_double),
+                ("warm_used", C.c_int), ("warm_fallback", C.c_int), ("warm_iterations", C.c_int),
+                ("logx", DP), ("label_y", DP), ("label_logx", DP), ("label_iter", C.c_int),
                 ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
 
@@ -85,7 +89,9 @@ _lib = None
 
 EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "psdp_query",
            "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_eval_newton",
-           "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version"]
+           "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version",
+           "psdp_mlp_create", "psdp_mlp_param_count", "psdp_mlp_set_params", "psdp_mlp_get_params",
+           "psdp_mlp_forward", "psdp_mlp_loss_grad", "psdp_mlp_adam", "psdp_mlp_free"]
 
 
 def load(path: str = LIB_PATH):
@@ -95,6 +101,14 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1411_3769_amd.build`")
+    # torch carries its own HIP runtime; it must take the device before this
+    # library's runtime does, or torch finds no GPU afterwards
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp = C.c_void_p
     lib.psdp_setup_opts_default.argtypes = [C.POINTER(SetupOpts)]
@@ -115,8 +129,20 @@ def load(path: str = LIB_PATH):
     lib.psdp_free.restype = None
     lib.psdp_last_error.restype = C.c_char_p
     lib.psdp_version.restype = C.c_char_p
+    lib.psdp_mlp_create.argtypes = [vp, C.c_int, C.c_int, C.POINTER(vp)]
+    lib.psdp_mlp_param_count.argtypes = [vp]
+    lib.psdp_mlp_param_count.restype = C.c_int64
+    lib.psdp_mlp_set_params.argtypes = [vp, vp]
+    lib.psdp_mlp_get_params.argtypes = [vp, vp, vp]
+    lib.psdp_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+    lib.psdp_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
+    lib.psdp_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    lib.psdp_mlp_free.argtypes = [vp]
+    lib.psdp_mlp_free.restype = None
     for name in ("psdp_polya_setup", "psdp_query", "psdp_get_polya", "psdp_ipm_solve",
-                 "psdp_ipm_solve_batched", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis"):
+                 "psdp_ipm_solve_batched", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis",
+                 "psdp_mlp_create", "psdp_mlp_set_params", "psdp_mlp_get_params", "psdp_mlp_forward",
+                 "psdp_mlp_loss_grad", "psdp_mlp_adam"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -255,6 +281,13 @@ class Result:
     iters_lowprec: int = 0
     ir_steps: int = 0
     ir_eta_max: float = float("nan")
+    warm_used: bool = False
+    warm_fallback: bool = False
+    warm_iterations: int = 0
+    logx: np.ndarray = None
+    label_y: np.ndarray = None
+    label_logx: np.ndarray = None
+    label_iter: int = -1
     history: list = field(default_factory=list)
 
     @property
@@ -269,16 +302,45 @@ class Result:
 def _prep(sdp: SDP, cap: int):
     P = np.zeros((sdp.L0, sdp.n, sdp.n))
     y = np.zeros(sdp.K)
+    lx = np.zeros(sdp.L + sdp.M)
+    ly = np.zeros(sdp.K)
+    llx = np.zeros(sdp.L + sdp.M)
     hist = (IterRec * cap)() if cap else None
     r = CResult()
     r.P = P.ctypes.data_as(DP)
     r.y = y.ctypes.data_as(DP)
+    r.logx = lx.ctypes.data_as(DP)
+    r.label_y = ly.ctypes.data_as(DP)
+    r.label_logx = llx.ctypes.data_as(DP)
     r.history = C.cast(hist, C.POINTER(IterRec)) if cap else C.POINTER(IterRec)()
     r.history_cap = cap
-    return r, P, y, hist
+    return r, P, y, (lx, ly, llx), hist
 
 
-def _unpack(r: CResult, P, y, hist) -> Result:
+def _warm_arrays(sdps, warm_y, warm_logx):
+    """Host pointer arrays for the warm start (entries may be None)."""
+    keep, ptrs = [], []
+    for vals, size in ((warm_y, lambda s: s.K), (warm_logx, lambda s: s.L + s.M)):
+        if vals is None:
+            ptrs.append(C.POINTER(DP)())
+            continue
+        if len(vals) != len(sdps):
+            raise ValueError("one warm-start entry per system")
+        arr = (DP * len(sdps))()
+        for i, (v, s) in enumerate(zip(vals, sdps)):
+            if v is None:
+                continue
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            if v.shape != (size(s),):
+                raise ValueError(f"warm-start entry {i} has shape {v.shape}, wants ({size(s)},)")
+            keep.append(v)
+            arr[i] = v.ctypes.data_as(DP)
+        keep.append(arr)
+        ptrs.append(C.cast(arr, C.POINTER(DP)))
+    return ptrs, keep
+
+
+def _unpack(r: CResult, P, y, lx, hist) -> Result:
     h = []
     if hist is not None:
         for i in range(r.history_len):
@@ -288,29 +350,40 @@ def _unpack(r: CResult, P, y, hist) -> Result:
     return Result(r.verdict, r.reason, P, y, r.phi, r.psi, r.gap_abs, r.gap_rel, r.pinf, r.dinf,
                   r.margin, r.margin_P, r.margin_D, r.iterations, bool(r.phase1_used),
                   r.phase1_iterations, r.t_star, r.time_solve_s, r.iters_lowprec,
-                  r.ir_steps, r.ir_eta_max, h)
+                  r.ir_steps, r.ir_eta_max, bool(r.warm_used), bool(r.warm_fallback),
+                  r.warm_iterations, lx[0], lx[1] if r.label_iter >= 0 else None,
+                  lx[2] if r.label_iter >= 0 else None, r.label_iter, h)
 
 
-def ipm_solve(sdp: SDP, **opts) -> Result:
+def ipm_solve(sdp: SDP, warm_y=None, warm_logx=None, **opts) -> Result:
+    """Alg. 2 for one SDP.  warm_y (K values in the library's dual order) and
+    warm_logx (L+M log block scales of X) give an optional warm start."""
     o = make_opts(**opts)
     cap = 512 if o.record_history else 0
-    r, P, y, hist = _prep(sdp, cap)
+    r, P, y, lx, hist = _prep(sdp, cap)
+    (wy, wl), wkeep = _warm_arrays([sdp], None if warm_y is None else [warm_y],
+                                   None if warm_logx is None else [warm_logx])
+    o.warm_y, o.warm_logx = wy, wl
     _check(load().psdp_ipm_solve(sdp.handle, C.byref(o), C.byref(r)))
-    return _unpack(r, P, y, hist)
+    del wkeep
+    return _unpack(r, P, y, lx, hist)
 
 
-def ipm_solve_batched(sdps: Sequence[SDP], **opts) -> List[Result]:
+def ipm_solve_batched(sdps: Sequence[SDP], warm_y=None, warm_logx=None, **opts) -> List[Result]:
     o = make_opts(**opts)
     cap = 512 if o.record_history else 0
     n = len(sdps)
     arr = (CResult * n)()
     keep = []
     for i, s in enumerate(sdps):
-        r, P, y, hist = _prep(s, cap)
+        r, P, y, lx, hist = _prep(s, cap)
         arr[i] = r
-        keep.append((P, y, hist))
+        keep.append((P, y, lx, hist))
+    (wy, wl), wkeep = _warm_arrays(sdps, warm_y, warm_logx)
+    o.warm_y, o.warm_logx = wy, wl
     hs = (C.c_void_p * n)(*[s.handle.value for s in sdps])
     _check(load().psdp_ipm_solve_batched(hs, n, C.byref(o), arr))
+    del wkeep
     return [_unpack(arr[i], *keep[i]) for i in range(n)]
 
 
@@ -340,3 +413,71 @@ def eval_ladder(sdp: SDP, V: np.ndarray, dV: np.ndarray, **opts):
 
 def version() -> str:
     return load().psdp_version().decode()
+
+
+class MLP:
+    """The warm-start network on the device (psdp_mlp_*).  Inputs and
+    targets are CUDA float32 tensors [batch x width]."""
+
+    def __init__(self, dims, precision="bf16", max_batch=256):
+        self.dims = tuple(int(d) for d in dims)
+        self.max_batch = int(max_batch)
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = C.c_void_p()
+        d = (C.c_int * 4)(*self.dims)
+        _check(load().psdp_mlp_create(C.cast(d, C.c_void_p), prec, self.max_batch, C.byref(h)))
+        self._h = h
+        self.nparam = int(load().psdp_mlp_param_count(h))
+
+    def set_params(self, flat: np.ndarray):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        if flat.shape != (self.nparam,):
+            raise ValueError(f"expected {self.nparam} parameters, got {flat.shape}")
+        _check(load().psdp_mlp_set_params(self._h, _ptr(flat)))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.nparam, np.float32)
+        _check(load().psdp_mlp_get_params(self._h, _ptr(out), None))
+        return out
+
+    def get_grad(self) -> np.ndarray:
+        out = np.empty(self.nparam, np.float32)
+        _check(load().psdp_mlp_get_params(self._h, None, _ptr(out)))
+        return out
+
+    @staticmethod
+    def _dev(t, width):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32):
+            raise TypeError("expected a CUDA float32 tensor")
+        if t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous [batch x {width}] tensor")
+        return C.c_void_p(t.data_ptr())
+
+    def forward(self, x):
+        import torch
+        out = torch.empty((x.shape[0], self.dims[3]), device=x.device, dtype=torch.float32)
+        _check(load().psdp_mlp_forward(self._h, self._dev(x, self.dims[0]), int(x.shape[0]),
+                                       C.c_void_p(out.data_ptr()), _current_stream()))
+        return out
+
+    def loss_grad(self, x, t) -> float:
+        loss = C.c_double()
+        _check(load().psdp_mlp_loss_grad(self._h, self._dev(x, self.dims[0]), self._dev(t, self.dims[3]),
+                                         int(x.shape[0]), C.byref(loss), _current_stream()))
+        return loss.value
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        _check(load().psdp_mlp_adam(self._h, lr, b1, b2, eps, _current_stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().psdp_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -125,3 +125,15 @@ def random_spd_blocks(seed: int, nblocks: int, n: int, cond: float = 10.0) -> np
         out[j] = (Q * ev) @ Q.T
         out[j] = 0.5 * (out[j] + out[j].T)
     return out
+
+
+def mlp_init(dims, seed: int) -> np.ndarray:
+    """Initial weights of the warm-start network, flattened as
+    [W1, b1, W2, b2, ...] (W_i [dims[i+1] x dims[i]] row-major): W ~
+    N(0, 1/fan_in), b = 0, drawn in FP32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for din, dout in zip(dims[:-1], dims[1:]):
+        parts.append((rng.standard_normal((dout, din)) / np.sqrt(din)).astype(np.float32).ravel())
+        parts.append(np.zeros(dout, np.float32))
+    return np.concatenate(parts)

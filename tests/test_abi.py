@@ -89,3 +89,26 @@ def test_product_path_has_no_cpu_fallback(tmp_path):
             P.load(str(tmp_path / "missing.so"))
     finally:
         P._lib = saved
+
+
+@pytest.mark.parametrize("dims,prec,batch,frag", [
+    ((4, 3, 3, 2), 0, 8, "precision"),
+    ((4, 3, 3, 2), 1, 0, "max_batch"),
+    ((0, 3, 3, 2), 1, 8, "width"),
+])
+def test_mlp_create_validation(dims, prec, batch, frag):
+    P = _lib()
+    lib = P.load()
+    h = C.c_void_p()
+    d = (C.c_int * 4)(*dims)
+    rc = lib.psdp_mlp_create(C.cast(d, C.c_void_p), prec, batch, C.byref(h))
+    assert rc == -1 and frag in lib.psdp_last_error().decode()
+    assert not h.value
+
+
+def test_warm_start_option_validation():
+    P = _lib()
+    o = P.make_opts(stream=None)
+    assert o.warm_margin == 1e-6 and o.warm_center == 1 and o.warm_iter_cap == 0
+    assert not o.warm_y and not o.warm_logx and o.label_gap == 0.0
+
