@@ -60,6 +60,8 @@ def workload(name):
         return [W.c1_system(s) for s in range(64)], "n10 l4 dp2 d2, 64 seeds (K=550)"
     if name == "n100":
         return [W.c2_system(0)], "n100 l4 dp1 d3, seed 0 (K=20200)"
+    if name == "mixed512":
+        return W.mixed_systems(512), "mixed batch of 512: n 6..48, l 2..5, dp 1..2, d 1..4 (K 42..17640)"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -94,8 +96,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n10")
+    ap.add_argument("--workload", default="n10", help="n10 | n100 | mixed512 | learned")
+    ap.add_argument("--precision", default=None, help="fp64 | fp32 | bf16 (Schur assembly)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--train", type=int, default=20000, help="learned: training solves")
+    ap.add_argument("--test", type=int, default=2000, help="learned: held-out solves")
+    ap.add_argument("--epochs", type=int, default=60, help="learned: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -109,21 +115,32 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     P.load()
+    if args.workload == "learned":
+        return bench_learned(args)
+    prec = args.precision or ("fp32" if args.workload == "mixed512" else "fp64")
     systems, desc = workload(args.workload)
     # inputs resident in HBM before the timed region
     A_dev = [torch.tensor(sy.A, device="cuda:0", dtype=torch.float64) for sy in systems]
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream().cuda_stream
 
+    tsplit = [0.0, 0.0]
+
     def step(prof=None):
+        t0 = time.perf_counter()
         hs = [P.polya_setup(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)]
-        rs = P.ipm_solve_batched(hs, stream=stream, prof=prof)
+        t1 = time.perf_counter()
+        rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=prec)
+        t2 = time.perf_counter()
         for h in hs:
             h.close()
+        tsplit[0] += t1 - t0
+        tsplit[1] += t2 - t1
         return rs
 
     for _ in range(args.warmup):
         step()
+    tsplit[0] = tsplit[1] = 0.0
     prof = P.new_prof()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -142,10 +159,11 @@ def main():
     per = {P.PROF_CLASSES[i]: (prof[i, 0], prof[i, 1]) for i in range(len(P.PROF_CLASSES))}
     dom = max(per, key=lambda k: per[k][0])
     iters_sys = [r.iterations for r in rs]
-    asm_flops = sum(it * schur_flops(sy.n, sy.l, sy.dp, sy.d) for it, sy in zip(iters_sys, systems))
+    its_all = [r.iterations + r.phase1_iterations for r in rs]
+    asm_flops = sum(it * schur_flops(sy.n, sy.l, sy.dp, sy.d) for it, sy in zip(its_all, systems))
     from math import comb
     Ks = [comb(sy.l + sy.dp - 1, sy.l - 1) * sy.n * (sy.n + 1) // 2 for sy in systems]
-    chol_flops = sum(it * k ** 3 / 3.0 for it, k in zip(iters_sys, Ks))
+    chol_flops = sum(it * k ** 3 / 3.0 for it, k in zip(its_all, Ks))
     asm_ms = per["assemble"][0] / args.steps
     chol_ms = (per["chol_panel"][0] + per["chol_update"][0]) / args.steps
     asm_tf = asm_flops / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else None
@@ -177,16 +195,75 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == "fp64" else f"f64 (Schur assembly {prec}, refined)",
         "data": "synthetic (seeded dissipative systems, see workloads.py)",
         "config": {"workload": desc, "systems": len(systems), "gap_tol": 1e-8,
+                   "precision": prec,
+                   "setup_ms_per_step": 1e3 * tsplit[0] / args.steps,
+                   "solve_ms_per_step": 1e3 * tsplit[1] / args.steps,
                    "verdicts": verdicts, "iterations_mean": float(np.mean(iters_sys)),
+                   "lowprec_iterations_mean": float(np.mean([r.iters_lowprec for r in rs])),
                    "schur_assembly_tflops": asm_tf, "schur_cholesky_tflops": chol_tf,
                    "device_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in per.items()}},
         "roofline": roof,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "n10":
         line["cpu_baseline"] = cpu_baseline(systems)
+    print(json.dumps(line))
+
+
+def bench_learned(args):
+    """Learned warm start on the n=32, l=4, dp=1, d=2 family: cold solves
+    of the training seeds give the labels, the network is trained on the
+    GPU, and the timed steps solve the held-out seeds warm (inference and
+    cold fallbacks included).  The held-out cold solves are timed too."""
+    import numpy as np
+    import torch
+    from paper_1411_3769_amd import learned as Lm
+    from paper_1411_3769_amd import workloads as W
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    tr = [W.warm_system(s) for s in range(args.train)]
+    te = [W.warm_system(10**6 + s) for s in range(args.test)]
+    t0 = time.perf_counter()
+    dtr = Lm.solve_cold(tr, log=log)
+    t_label = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    model = Lm.train(dtr, K=2112, epochs=args.epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    cold_s, warm_s, ev = [], [], None
+    for k in range(args.warmup + args.steps):
+        dte = Lm.solve_cold(te, log=log)
+        ev = Lm.evaluate(model, te, dte, log=log)
+        if k >= args.warmup:
+            cold_s.append(dte.cold_seconds)
+            warm_s.append(ev["warm_seconds"])
+    per = lambda v: float(np.mean(v)) / args.test * 256
+    line = {
+        "metric": METRIC,
+        "value": per(warm_s),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * float(np.mean(warm_s)),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (network bf16 with fp32 accumulation)",
+        "data": "synthetic (seeded dissipative systems, see workloads.py)",
+        "config": {"workload": f"learned warm start, n32 l4 dp1 d2 (K=2112): {args.train} training "
+                               f"solves, {args.test} held-out; value = seconds per 256 held-out "
+                               f"systems, warm (inference + solve + fallbacks)",
+                   "cold_s_per_256": per(cold_s),
+                   "warm_iterations_mean": ev["warm_iters_mean"],
+                   "cold_iterations_mean": ev["cold_iters_mean"],
+                   "fallback_rate": ev["fallback_rate"], "verdicts_agree": ev["verdicts_agree"],
+                   "label_seconds": t_label, "train_seconds": t_train, "epochs": args.epochs,
+                   "final_train_loss": model.history[-1]},
+        "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": None, "traffic": None},
+    }
     print(json.dumps(line))
 
 
