@@ -15,8 +15,12 @@
 //   diag   : one workgroup per system factors the 64 x 64 diagonal tile in
 //            registers and inverts the factor (L_pp, L_pp^{-1} stored);
 //   trsm   : one workgroup per tile row i > p forms L_ip = A_ip L_pp^{-T};
-//   update : every tile (i, j), p < j <= i, gets A_ij -= L_ip L_jp^T on FP64
-//            MFMA.
+//   update : two levels.  Panels are grouped in super-panels of kSW; inside
+//            one, each tile (i, j) with p < j <= (end of the super-panel)
+//            gets A_ij -= L_ip L_jp^T right away (narrow update, depth 64);
+//            after the super-panel's last panel, every tile right of it gets
+//            the super-panel's whole contribution in one pass of depth
+//            64 kSW (wide update).  Both on FP64 MFMA.
 // Steps are launched for the whole batch; a (step, system) table maps
 // workgroups to systems.  Triangular solves use the stored inverses, so the
 // diagonal solves are matrix-vector products.
@@ -216,7 +220,8 @@ __global__ void __launch_bounds__(256) k_chol_trsm(const SysDesc* __restrict__ s
     for (int q = 0; q < 4; ++q) Ai[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16] = acc[u][q];
 }
 
-// A_ij -= L_ip L_jp^T for every tile p < j <= i, on FP64 MFMA: wave w owns
+// Narrow update (inside the super-panel of p): A_ij -= L_ip L_jp^T for the
+// columns p < j <= end of the super-panel and every row i >= j, on FP64 MFMA: wave w owns
 // rows 16w..16w+15 and the four 16-column tiles; both panels staged in LDS.
 __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags, double* Lam,
@@ -232,11 +237,12 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
   double* A = Lam + sd.loff;
-  int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-  while (ii * (ii + 1) / 2 > t) --ii;
-  const int jj = t - ii * (ii + 1) / 2;
-  const int i = p + 1 + ii, j = p + 1 + jj;
+  // column j = p + 1 + c (c < number of super-panel columns right of p),
+  // rows i = j .. P-1: column c holds R - c tiles, R = P - p - 1
+  const int R = sd.P - p - 1;
+  int c = 0, base = 0;
+  while (t >= base + (R - c)) { base += R - c; ++c; }
+  const int j = p + 1 + c, i = j + (t - base);
   const double* Li = A + (int64_t)i * kNB * ld + (int64_t)p * kNB;
   const double* Lj = A + (int64_t)j * kNB * ld + (int64_t)p * kNB;
   double* C = A + (int64_t)i * kNB * ld + (int64_t)j * kNB;
@@ -269,6 +275,92 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
       if (i != j || cc <= rr) C[(int64_t)rr * ld + cc] -= acc[u][q];
     }
   }
+}
+
+// Wide update at the end of a super-panel of kSW panels (p = its last
+// panel): A_ij -= sum over the super-panel's panels q of L_iq L_jq^T for every
+// tile pair right of it (depth 64 kSW), on 128 x 128 output blocks (2 x 2
+// tiles; wave w owns the 64 x 64 quadrant (w/2, w%2) as 4 x 4 MFMA tiles).
+// The depth is staged through LDS 16 columns at a time with the next chunk
+// prefetched into registers.  Only the lower triangle (column <= row) of the
+// matrix is written; rows or columns past Kpad are skipped.
+constexpr int kWT = 128, kWK = 16, kWLD = kWK + 1;
+
+__global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restrict__ sys,
+                                                          const int* __restrict__ flags, double* Lam,
+                                                          const int* __restrict__ st_sys,
+                                                          const int* __restrict__ st_pre, int cnt,
+                                                          int p) {
+  __shared__ double sa[kWT * kWLD];
+  __shared__ double sb[kWT * kWLD];
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  double* A = Lam + sd.loff;
+  int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+  while (bi * (bi + 1) / 2 > t) --bi;
+  const int bj = t - bi * (bi + 1) / 2;
+  const int q0 = p + 1;
+  const int r0 = kNB * (q0 + 2 * bi), c0 = kNB * (q0 + 2 * bj);
+  const int nmax = sd.Kpad;
+  const int d0 = kNB * (p - kSW + 1), D = kNB * kSW;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  // staging map: thread loads rows (tid / 16) + 16 u, column tid % 16
+  const int lr = tid >> 4, lk = tid & 15;
+  double ra[8], rb[8];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = lr + 16 * u;
+      ra[u] = r0 + row < nmax ? A[(int64_t)(r0 + row) * ld + d0 + kc + lk] : 0.0;
+      rb[u] = c0 + row < nmax ? A[(int64_t)(c0 + row) * ld + d0 + kc + lk] : 0.0;
+    }
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int kc = 0; kc < D; kc += kWK) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sa[(lr + 16 * u) * kWLD + lk] = ra[u];
+      sb[(lr + 16 * u) * kWLD + lk] = rb[u];
+    }
+    __syncthreads();
+    if (kc + kWK < D) load(kc + kWK);
+#pragma unroll
+    for (int ks = 0; ks < kWK; ks += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sa[(wr + 16 * a + r16) * kWLD + ks + kq];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = sb[(wc + 16 * b + r16) * kWLD + ks + kq];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int R = r0 + wr + 16 * a + 4 * q + kq;
+        const int Cc = c0 + wc + 16 * b + r16;
+        if (R < nmax && Cc < nmax && Cc <= R) A[(int64_t)R * ld + Cc] -= acc[a][b][q];
+      }
 }
 
 // y = M x or M^T x for a 64 x 64 tile M in global memory (row-major, leading
@@ -422,6 +514,13 @@ void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, doub
 void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
                         const int* ssys, const int* spre, int cnt, int total, int p) {
   hipLaunchKernelGGL(k_chol_update, dim3(total), dim3(256), 0, st, sys, flags, Lam, ssys, spre, cnt, p);
+}
+
+void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
+                             const int* ssys, const int* spre, int cnt, int total, int p) {
+  if (total)
+    hipLaunchKernelGGL(k_chol_update_wide, dim3(total), dim3(256), 0, st, sys, flags, Lam, ssys, spre,
+                       cnt, p);
 }
 
 void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,

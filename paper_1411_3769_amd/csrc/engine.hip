@@ -96,7 +96,7 @@ struct Batch {
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
   std::vector<int> ownP, ownK;
-  StepTab pan, trs, upd, fwdL, bwdL;     // fwdL/bwdL: solve steps of the large systems only
+  StepTab pan, trs, upd, wide, fwdL, bwdL;     // fwdL/bwdL: solve steps of the large systems only
   std::vector<int> small_ids;
   int* d_small = nullptr;
   int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0;
@@ -115,7 +115,7 @@ struct Batch {
   int *d_gpinfo = nullptr, *d_ownP = nullptr, *d_ownK = nullptr;
   int64_t* d_gpoff = nullptr;
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
-  int *d_trs_sys = nullptr, *d_trs_pre = nullptr;
+  int *d_trs_sys = nullptr, *d_trs_pre = nullptr, *d_wide_sys = nullptr, *d_wide_pre = nullptr;
   int *d_fwdL_sys = nullptr, *d_fwdL_pre = nullptr, *d_bwdL_sys = nullptr, *d_bwdL_pre = nullptr;
   int* d_flags = nullptr;
   double* d_sc = nullptr;
@@ -349,6 +349,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
     B.pan.add_step();
     B.trs.add_step();
     B.upd.add_step();
+    B.wide.add_step();
     B.fwdL.add_step();
     B.bwdL.add_step();
     for (int s = 0; s < count; ++s) {
@@ -357,7 +358,16 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
       B.pan.add(s, 1);
       const int T = P - pstep - 1;
       if (T > 0) B.trs.add(s, T);
-      if (T > 0) B.upd.add(s, T * (T + 1) / 2);
+      // narrow update: columns p+1 .. end of the super-panel
+      const int se = std::min(P - 1, (pstep / kSW) * kSW + kSW - 1);
+      int nn = 0;
+      for (int j = pstep + 1; j <= se; ++j) nn += P - j;
+      if (nn > 0) B.upd.add(s, nn);
+      // wide update after the super-panel's last panel
+      if (pstep == se && pstep % kSW == kSW - 1 && pstep < P - 1) {
+        const int nb2 = (P - pstep - 1 + 1) / 2;
+        B.wide.add(s, nb2 * (nb2 + 1) / 2);
+      }
       if (P > kSmallP) {
         B.fwdL.add(s, P - pstep);
         B.bwdL.add(s, pstep + 1);
@@ -373,7 +383,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   tb += tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(B.csr_hh) + tabsize(B.csr_hid);
   tb += tabsize(B.csr_mh) + tabsize(B.csr_hl);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
-  tb += tabsize(B.trs.sys) + tabsize(B.trs.pre);
+  tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
   tb += tabsize(B.fwdL.sys) + tabsize(B.fwdL.pre) + tabsize(B.bwdL.sys) + tabsize(B.bwdL.pre);
   tb += tabsize(B.small_ids);
   tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
@@ -424,6 +434,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   if ((rc = upload(B.dtab, off, B.pan.pre, &B.d_pan_pre))) return rc;
   if ((rc = upload(B.dtab, off, B.trs.sys, &B.d_trs_sys))) return rc;
   if ((rc = upload(B.dtab, off, B.trs.pre, &B.d_trs_pre))) return rc;
+  if ((rc = upload(B.dtab, off, B.wide.sys, &B.d_wide_sys))) return rc;
+  if ((rc = upload(B.dtab, off, B.wide.pre, &B.d_wide_pre))) return rc;
   if ((rc = upload(B.dtab, off, B.upd.sys, &B.d_upd_sys))) return rc;
   if ((rc = upload(B.dtab, off, B.upd.pre, &B.d_upd_pre))) return rc;
   if ((rc = upload(B.dtab, off, B.fwdL.sys, &B.d_fwdL_sys))) return rc;
@@ -533,8 +545,13 @@ static void op_factor(Batch& B, hipStream_t st) {
       const int g = B.upd.first[p];
       launch_chol_update(st, B.d_sys, B.d_flags, B.Lam, B.d_upd_sys + g, B.d_upd_pre + g,
                          B.upd.cnt[p], B.upd.tot[p], p);
-      B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
     }
+    if (B.wide.tot[p] > 0) {
+      const int g = B.wide.first[p];
+      launch_chol_update_wide(st, B.d_sys, B.d_flags, B.Lam, B.d_wide_sys + g, B.d_wide_pre + g,
+                              B.wide.cnt[p], B.wide.tot[p], p);
+    }
+    if (B.upd.tot[p] > 0 || B.wide.tot[p] > 0) B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
   }
 }
 

@@ -15,6 +15,7 @@ namespace psdp {
 constexpr int kMaxN = 128;   // largest block order held whole in LDS (128 KB)
 constexpr int kTB = 8;       // index-group size of the tiled basis
 constexpr int kNB = 64;      // Schur Cholesky tile
+constexpr int kSW = 4;       // Cholesky panels per super-panel (depth of the wide update / 64)
 constexpr int kMaxDeg = 20;  // largest multinomial degree (20! < 2^63)
 constexpr int kNSC = 24;     // per-system scalar slots
 
@@ -156,6 +157,8 @@ void launch_chol_diag(hipStream_t st, const SysDesc* sys, int* flags, const doub
 void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
                       const double* Linv, const int* ssys, const int* spre, int cnt, int total,
                       int p);
+void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
+                             const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
                         const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
