@@ -34,101 +34,103 @@ namespace psdp {
 constexpr int LDT = kNB + 1;   // LDS leading dimension of a 64 x 64 tile
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Register-resident factorisation of a 64 x 64 tile with 256 threads: thread
-// (tr, tc) owns rows tr + 16a and columns tc + 16b (a, b < 4).  Column k is
-// broadcast through a double-buffered LDS vector, so each column costs one
-// barrier and eight LDS reads per thread.  Non-positive or non-finite pivots
-// set *fail and are replaced by 1.  On return reg holds L (lower part).
-__device__ inline void reg_potrf64(double (&reg)[4][4], double* colbuf /*2 x 64*/, int* fail) {
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-  // publish column 0
-  if (tc == 0)
+// ---------------------------------------------------------------------------
+// Diagonal tile: blocked factorisation and inverse of a 64 x 64 tile by one
+// workgroup.  The tile is split in 4 x 4 blocks of 16 x 16.  For each block
+// column kb: wave 0 factors the diagonal block in registers and inverts its
+// factor (wave-wide shuffles, no barriers), the other waves form the blocks
+// below it on MFMA (L_ik = A_ik X_kk^T) and update the trailing blocks
+// (A_ij -= L_ik L_jk^T).  The inverse's off-diagonal blocks then follow by
+// block forward substitution, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
+// ---------------------------------------------------------------------------
+constexpr int kLD = 65;          // LDS leading dimension of the 64 x 64 tiles
+constexpr int kBL = 16;          // block order
+
+// 16 x 16 x 16 product on FP64 MFMA for one wave: acc += P Q (qt = false) or
+// P Q^T (qt = true); P, Q in LDS with leading dimension ld.
+__device__ inline v4d mm16(const double* P, const double* Q, bool qt, v4d acc) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) colbuf[tr + 16 * a] = reg[a][0];
-  for (int k = 0; k < kNB; ++k) {
-    __syncthreads();
-    const double* cb = colbuf + (k & 1) * kNB;
-    double d = cb[k];
-    const bool bad = !(d > 0.0) || !isfinite(d);
-    d = bad ? 1.0 : d;
-    const double piv = sqrt(d);
-    const double rpiv = 1.0 / piv;   // one reciprocal per column, then products
-    if (bad && tid == 0) *fail = 1;
-    double li[4], lj[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) li[a] = cb[tr + 16 * a] * rpiv;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) lj[b] = cb[tc + 16 * b] * rpiv;
-    // branch-free update of the owned 4 x 4 block
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = tr + 16 * a;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int j = tc + 16 * b;
-        const double upd = reg[a][b] - li[a] * lj[b];
-        const double colk = i > k ? li[a] : (i == k ? piv : reg[a][b]);
-        reg[a][b] = j == k ? colk : ((j > k && j <= i) ? upd : reg[a][b]);
-      }
-    }
-    // publish column k+1 (final: all updates through column k applied)
-    const int kn = k + 1;
-    if (kn < kNB && tc == (kn & 15)) {
-      const int bs = kn >> 4;
-      double* nb = colbuf + (kn & 1) * kNB;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const double v = bs == 0 ? reg[a][0] : bs == 1 ? reg[a][1] : bs == 2 ? reg[a][2] : reg[a][3];
-        nb[tr + 16 * a] = v;
-      }
-    }
+  for (int ks = 0; ks < 4; ++ks) {
+    const double a = P[r16 * kLD + 4 * ks + kq];
+    const double b = qt ? Q[r16 * kLD + 4 * ks + kq] : Q[(4 * ks + kq) * kLD + r16];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  __syncthreads();
+  return acc;
 }
 
-// X = L^{-1} by forward substitution on the identity, register-resident in the
-// same 4 x 4 ownership: step k scales row k of X by 1/L[k][k] (reciprocals
-// of the diagonal precomputed) and removes L[i][k] X[k][:] from every row
-// i > k.  L is read from LDS (leading dimension LDT), row k of X is broadcast
-// through a double-buffered LDS vector.
-__device__ inline void reg_trinv64(const double* sL, double (&X)[4][4], double* rowbuf,
-                                   double* rdiag) {
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-  if (tid < kNB) rdiag[tid] = 1.0 / sL[tid * LDT + tid];
+// store (sign * acc) or add it (accumulate) into a 16 x 16 block in LDS
+__device__ inline void st16(double* D, v4d acc, double sign, bool add) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) X[a][b] = (tr + 16 * a == tc + 16 * b) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int k = 0; k < kNB; ++k) {
-    double* rb = rowbuf + (k & 1) * kNB;
-    const double rkk = rdiag[k];
-    // the owners of row k scale it and publish it
-    if (tr == (k & 15)) {
-      const int as = k >> 4;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) X[a][b] = a == as ? X[a][b] * rkk : X[a][b];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double v = as == 0 ? X[0][b] : as == 1 ? X[1][b] : as == 2 ? X[2][b] : X[3][b];
-        rb[tc + 16 * b] = v;
-      }
-    }
-    __syncthreads();
-    double xk[4], lik[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) xk[b] = rb[tc + 16 * b];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) lik[a] = sL[(tr + 16 * a) * LDT + k];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-      if (tr + 16 * a > k)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) X[a][b] -= lik[a] * xk[b];
+  for (int i = 0; i < 4; ++i) {
+    double* d = D + (4 * i + kq) * kLD + r16;
+    *d = add ? *d + sign * acc[i] : sign * acc[i];
   }
-  __syncthreads();
+}
+
+// Wave-level factorisation and inverse of the 16 x 16 block at B (leading
+// dimension kLD) by the 64 lanes of one wave: lane (r, g) = (l % 16, l / 16)
+// holds row r, columns 4g..4g+3.  On return B holds L (zeros above the
+// diagonal) and Xb holds L^{-1}.  Non-positive pivots set *fail (replaced by 1).
+__device__ inline void wave_potri16(double* B, double* Xb, int* fail) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  double v[4], rsv[16];
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = B[r * kLD + 4 * g + j];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int kg = k >> 2, kj = k & 3;
+    double d = __shfl(v[kj], k + 16 * kg);
+    const bool b = !(d > 0.0) || !isfinite(d);
+    bad = bad || b;
+    d = b ? 1.0 : d;
+    const double s = sqrt(d), rs = 1.0 / s;
+    rsv[k] = rs;
+    // every lane takes part in every shuffle (a lane outside a shuffle
+    // would hand undefined values to the lanes reading from it)
+    const double ark = __shfl(v[kj], r + 16 * kg);
+    const double lrk = r == k ? s : ark * rs;
+    double lck[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = 4 * g + j;
+      const double ack = __shfl(v[kj], cc + 16 * kg);
+      lck[j] = cc == k ? s : ack * rs;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = 4 * g + j;
+      if (cc > k && r >= cc) v[j] -= lrk * lck[j];
+    }
+    if (g == kg) v[kj] = r > k ? lrk : (r == k ? s : 0.0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[j] = r >= 4 * g + j ? v[j] : 0.0;
+    B[r * kLD + 4 * g + j] = v[j];
+  }
+  // X = L^{-1}: row r' is final once the rows above it are subtracted
+  double x[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] = r == 4 * g + j ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (r == k) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] *= rsv[k];
+    }
+    const double lr = __shfl(v[k & 3], r + 16 * (k >> 2));   // L[r][k]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double xk = __shfl(x[j], k + 16 * g);          // X[k][4g+j]
+      if (r > k) x[j] -= lr * xk;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Xb[r * kLD + 4 * g + j] = x[j];
+  if (bad && lane == 0) *fail = 1;
 }
 
 // Diagonal step p: one workgroup per system factors the 64 x 64 tile A_pp
@@ -137,42 +139,70 @@ __global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ s
                                                    const double* __restrict__ Lam, double* Ldiag,
                                                    double* Linv, const int* __restrict__ st_sys,
                                                    int p) {
-  __shared__ double sL[kNB * LDT];
-  __shared__ double vbuf[2 * kNB];
-  __shared__ double rdiag[kNB];
+  __shared__ double sA[kNB * kLD];
+  __shared__ double sX[kNB * kLD];
+  __shared__ double sT[4 * kBL * kLD];
   __shared__ int fl;
   const int s = st_sys[blockIdx.x];
   if (!(flags[s] & F_CHOLSEL)) return;
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
-  const double* A = Lam + sd.loff;
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  const double* App = Lam + sd.loff + (int64_t)p * kNB * ld + (int64_t)p * kNB;
+  const int tid = threadIdx.x, w = tid >> 6;
   if (tid == 0) fl = 0;
-  const double* App = A + (int64_t)p * kNB * ld + (int64_t)p * kNB;
-  double reg[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) reg[a][b] = App[(int64_t)(tr + 16 * a) * ld + tc + 16 * b];
-  reg_potrf64(reg, vbuf, &fl);
-  double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = tr + 16 * a, j = tc + 16 * b;
-      const double v = j <= i ? reg[a][b] : 0.0;
-      sL[i * LDT + j] = v;
-      D[i * kNB + j] = v;
-    }
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e >> 6, cc = e & 63;
+    sA[r * kLD + cc] = App[(int64_t)r * ld + cc];
+    sX[r * kLD + cc] = 0.0;
+  }
   __syncthreads();
-  double X[4][4];
-  reg_trinv64(sL, X, vbuf, rdiag);
+  auto blk = [](double* M, int i, int j) { return M + (kBL * i) * kLD + kBL * j; };
+  for (int kb = 0; kb < 4; ++kb) {
+    if (w == 0) wave_potri16(blk(sA, kb, kb), blk(sX, kb, kb), &fl);
+    __syncthreads();
+    // L_ik = A_ik X_kk^T for the blocks below (wave w takes i = kb + w); the
+    // result overwrites A_ik after a barrier
+    const bool trs = w >= 1 && kb + w < 4;
+    v4d tacc = v4d{0.0, 0.0, 0.0, 0.0};
+    if (trs) tacc = mm16(blk(sA, kb + w, kb), blk(sX, kb, kb), true, tacc);
+    __syncthreads();
+    if (trs) st16(blk(sA, kb + w, kb), tacc, 1.0, false);
+    __syncthreads();
+    // A_ij -= L_ik L_jk^T for kb < j <= i
+    int t = 0;
+    for (int i = kb + 1; i < 4; ++i)
+      for (int j = kb + 1; j <= i; ++j, ++t) {
+        if ((t & 3) != w) continue;
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+        acc = mm16(blk(sA, i, kb), blk(sA, j, kb), true, acc);
+        st16(blk(sA, i, j), acc, -1.0, true);
+      }
+    __syncthreads();
+  }
+  // off-diagonal blocks of X, by distance d = i - j
+  for (int dd = 1; dd < 4; ++dd) {
+    // T_i = sum_{k=j}^{i-1} L_ik X_kj, wave w takes j = w
+    const int j = w, i = w + dd;
+    if (i < 4) {
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k = j; k < i; ++k) acc = mm16(blk(sA, i, k), blk(sX, k, j), false, acc);
+      st16(sT + w * kBL * kLD, acc, 1.0, false);
+    }
+    __syncthreads();
+    if (i < 4) {
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      acc = mm16(blk(sX, i, i), sT + w * kBL * kLD, false, acc);
+      st16(blk(sX, i, j), acc, -1.0, false);
+    }
+    __syncthreads();
+  }
+  double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
   double* Dv = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) Dv[(tr + 16 * a) * kNB + tc + 16 * b] = X[a][b];
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e >> 6, cc = e & 63;
+    D[e] = cc <= r ? sA[r * kLD + cc] : 0.0;
+    Dv[e] = cc <= r ? sX[r * kLD + cc] : 0.0;
+  }
   if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
 }
 
