@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--workload", default="n10", help="n10 | n100 | mixed512 | learned")
     ap.add_argument("--precision", default=None, help="fp64 | fp32 | bf16 (Schur assembly)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     ap.add_argument("--train", type=int, default=20000, help="learned: training solves")
     ap.add_argument("--test", type=int, default=2000, help="learned: held-out solves")
     ap.add_argument("--epochs", type=int, default=60, help="learned: training epochs")
@@ -115,6 +117,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     P.load()
+    if args.calibrate_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "learned":
         return bench_learned(args)
     prec = args.precision or ("fp32" if args.workload == "mixed512" else "fp64")

@@ -135,9 +135,17 @@ struct Batch {
   int nmin_big = 0;     // the general block kernels skip orders below this
   double *Lam, *Ldiag, *Linv, *Pm, *pre;
 
+  // pinned host mirrors of the per-iteration transfers (flags, scalars)
+  int* h_hf = nullptr;
+  int* h_prev = nullptr;
+  double* h_sc = nullptr;
+
   ~Batch() {
     if (dtab) hipFree(dtab);
     if (arena) hipFree(arena);
+    if (h_hf) hipHostFree(h_hf);
+    if (h_prev) hipHostFree(h_prev);
+    if (h_sc) hipHostFree(h_sc);
   }
 };
 
@@ -449,6 +457,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   B.d_red = (double*)(base + off); off += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256;
   B.d_kout = (int*)(base + off); off += ((size_t)B.nblk * 4 + 255) / 256 * 256;
   B.d_cert = (double*)(base + off); off += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256;
+  if (hipHostMalloc((void**)&B.h_hf, (size_t)B.S * 4) != hipSuccess ||
+      hipHostMalloc((void**)&B.h_prev, (size_t)B.S * 4) != hipSuccess ||
+      hipHostMalloc((void**)&B.h_sc, (size_t)B.S * kNSC * 8) != hipSuccess)
+    return fail(PSDP_ENOMEM, "pinned host buffers");
   return PSDP_OK;
 }
 
@@ -640,29 +652,32 @@ struct RunState {
   double phi = NAN, psi = NAN, gap_abs = NAN, gap_rel = NAN, pinf = NAN, dinf = NAN;
 };
 
-static void set_flags(Batch& B, const std::vector<RunState>& rs, std::vector<int>& hf) {
-  hf.assign(B.S, 0);
+static void set_flags(Batch& B, const std::vector<RunState>& rs, int* hf) {
   for (int s = 0; s < B.S; ++s)
-    if (rs[s].running) hf[s] = F_ACTIVE | F_CHOLSEL | (B.f32 && !B.asm64[s] ? F_ASM32 : 0);
+    hf[s] = rs[s].running ? F_ACTIVE | F_CHOLSEL | (B.f32 && !B.asm64[s] ? F_ASM32 : 0) : 0;
 }
 
 // One interior-point run of every system marked running.
 static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<RunState>& rs,
                    std::vector<std::vector<psdp_iter_rec>>* hist) {
   const int S = B.S;
-  std::vector<int> hf(S);
-  std::vector<double> hsc((size_t)S * kNSC);
+  // pinned buffers: the uploads of hf need no wait (hf is rewritten only
+  // after the next synchronisation), the read-backs are plain DMA
+  int* hf = B.h_hf;
+  int* prev = B.h_prev;
+  double* hsc = B.h_sc;
+  const size_t nsc = (size_t)S * kNSC;
   const int stall_w = 10;
   std::vector<char> was32(S, 0);   // the previous iteration assembled in FP32
   std::vector<char> prev_fail(S, 0);
   for (int it = 0;; ++it) {
-    set_flags(B, rs, hf);
     // flags carry the failure bits set by the previous iteration's kernels;
-    // read them before resetting.
-    std::vector<int> prev(S);
-    PSDP_HIP(hipMemcpyAsync(prev.data(), B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
+    // read them before resetting (hf is only rewritten after this wait: its
+    // last upload may still be in flight until then).
+    PSDP_HIP(hipMemcpyAsync(prev, B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
     B.prof.harvest();
+    set_flags(B, rs, hf);
     if (it > 0) {
       for (int s = 0; s < S; ++s) {
         was32[s] = (prev[s] & F_ASM32) != 0;
@@ -677,9 +692,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       }
       set_flags(B, rs, hf);
     }
-    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), S * 4, hipMemcpyHostToDevice, st));
-    PSDP_HIP(hipStreamSynchronize(st));
-    B.prof.harvest();
+    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
     { const size_t pm_ = B.prof.mark();
     launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
       B.prof.add(PSDP_PROF_CHOLINV, pm_, B.prof.mark()); }
@@ -695,15 +708,15 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     launch_sys_finalize(st, S, B.d_sys, B.d_flags, B.d_red, B.y, B.BX, o.sigma, B.d_sc);
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     PSDP_HIP(hipGetLastError());
-    PSDP_HIP(hipMemcpyAsync(hsc.data(), B.d_sc, hsc.size() * 8, hipMemcpyDeviceToHost, st));
-    PSDP_HIP(hipMemcpyAsync(prev.data(), B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipMemcpyAsync(hsc, B.d_sc, nsc * 8, hipMemcpyDeviceToHost, st));
+    PSDP_HIP(hipMemcpyAsync(prev, B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
     B.prof.harvest();
     bool any = false;
     for (int s = 0; s < S; ++s) {
       RunState& r = rs[s];
       if (!r.running) continue;
-      const double* v = hsc.data() + (size_t)s * kNSC;
+      const double* v = hsc + (size_t)s * kNSC;
       r.phi = v[S_PHI]; r.psi = v[S_PSI]; r.gap_abs = v[S_GAPABS]; r.gap_rel = v[S_GAPREL];
       r.pinf = v[S_PINF]; r.dinf = v[S_DINF];
       r.iterations = it;
@@ -758,9 +771,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     }
     if (!any) break;
     set_flags(B, rs, hf);
-    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf.data(), S * 4, hipMemcpyHostToDevice, st));
-    PSDP_HIP(hipStreamSynchronize(st));
-    B.prof.harvest();
+    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
     // ---- Newton system (Alg. 2 processors/root step 1)
     op_schur(B, st);
     op_factor(B, st);
@@ -828,7 +839,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     PSDP_HIP(hipGetLastError());
     if (hist) {
-      PSDP_HIP(hipMemcpyAsync(hsc.data(), B.d_sc, hsc.size() * 8, hipMemcpyDeviceToHost, st));
+      PSDP_HIP(hipMemcpyAsync(hsc, B.d_sc, nsc * 8, hipMemcpyDeviceToHost, st));
       PSDP_HIP(hipStreamSynchronize(st));
     B.prof.harvest();
       for (int s = 0; s < S; ++s)

@@ -151,6 +151,18 @@ __global__ void k_coef_H(const int* __restrict__ Wp, const int* __restrict__ WM,
   }
 }
 
+// *bad = 1 if any of the n values is not finite (one workgroup)
+__global__ void k_nonfinite(const double* __restrict__ v, int64_t n, double* bad) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mine |= !isfinite(v[i]);
+  if (mine) atomicOr(&any, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *bad = any ? 1.0 : 0.0;
+}
+
 __global__ void k_scale(const int* __restrict__ Wp, const int* __restrict__ WL,
                         const int* __restrict__ WM, int l, int L0, int L, int M, int dp,
                         int dM, const int64_t* __restrict__ beta, double delta, double eps,
@@ -286,10 +298,24 @@ int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_se
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t r = off; off += (bytes + 255) / 256 * 256; return r; };
     const size_t oA = take(Na * nn * 8), oB = take(L0 * L * 8), oC = take(L0 * M * Na * 8);
-    const size_t oH = take(M * L0 * nn * 8), oBf = take(L0 * L * 8), oS = take((L + M) * 8);
-    const size_t oCd = take((L + M) * 8), oBa = take(Nt * 2 * 4);
-    const size_t oWp = take(s->Wp.size() * 4), oWL = take(s->WL.size() * 4);
-    const size_t oWM = take(s->WM.size() * 4), oWa = take(s->Wa.size() * 4);
+    const size_t oH = take(M * L0 * nn * 8);
+    // read-back region, contiguous: betaf, scale, cdiag, non-finite flag of A
+    const int64_t nrb = L0 * L + 2 * (L + M) + 1;
+    const size_t oRb = take(nrb * 8);
+    const size_t oBf = oRb, oS = oRb + L0 * L * 8, oCd = oS + (L + M) * 8, oBad = oCd + (L + M) * 8;
+    // integer tables, contiguous: basis, Wp, WL, WM, Wa
+    std::vector<int> tab;
+    tab.insert(tab.end(), s->basis.pairs.begin(), s->basis.pairs.end());
+    const size_t iWp = tab.size();
+    tab.insert(tab.end(), s->Wp.begin(), s->Wp.end());
+    const size_t iWL = tab.size();
+    tab.insert(tab.end(), s->WL.begin(), s->WL.end());
+    const size_t iWM = tab.size();
+    tab.insert(tab.end(), s->WM.begin(), s->WM.end());
+    const size_t iWa = tab.size();
+    tab.insert(tab.end(), s->Wa.begin(), s->Wa.end());
+    const size_t oBa = take(tab.size() * 4);
+    const size_t oWp = oBa + iWp * 4, oWL = oBa + iWL * 4, oWM = oBa + iWM * 4, oWa = oBa + iWa * 4;
     s->dbytes = off;
     if (hipMalloc(&s->dmem, off) != hipSuccess) {
       delete s;
@@ -316,15 +342,18 @@ int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_se
       delete s;
       return fail(code, msg);
     };
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fact, sizeof(fact)) != hipSuccess)
-      return cleanup(PSDP_EDEVICE, "copy of the factorial table failed");
+    // the factorial table goes to constant memory once per device
+    static bool fact_done[64] = {false};
+    if (dev < 0 || dev >= 64) return cleanup(PSDP_EDEVICE, "device index out of range");
+    if (!fact_done[dev]) {
+      if (hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fact, sizeof(fact)) != hipSuccess)
+        return cleanup(PSDP_EDEVICE, "copy of the factorial table failed");
+      fact_done[dev] = true;
+    }
     hipError_t e = hipSuccess;
-    e = hipMemcpy(s->dA, A, Na * nn * 8, opt.a_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(s->dbasis, s->basis.pairs.data(), Nt * 2 * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dWp, s->Wp.data(), s->Wp.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dWL, s->WL.data(), s->WL.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dWM, s->WM.data(), s->WM.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dWa, s->Wa.data(), s->Wa.size() * 4, hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(s->dA, A, Na * nn * 8,
+                       opt.a_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->dbasis, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, 0);
     if (e != hipSuccess) return cleanup(PSDP_EDEVICE, std::string("set-up copy: ") + hipGetErrorString(e));
 
     {
@@ -337,25 +366,19 @@ int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_se
       hipLaunchKernelGGL(k_scale, dim3((nbk + 255) / 256), dim3(256), 0, 0, dWp, dWL, dWM, l,
                          (int)L0, (int)L, (int)M, dp, dp + da + d2, s->dbeta, s->delta, s->eps,
                          s->dscale, s->dcdiag);
+      double* dbad = (double*)(base + oBad);
+      hipLaunchKernelGGL(k_nonfinite, dim3(1), dim3(256), 0, 0, s->dA, Na * nn, dbad);
       e = hipGetLastError();
-      if (e == hipSuccess) e = hipDeviceSynchronize();
       if (e != hipSuccess) return cleanup(PSDP_EDEVICE, std::string("set-up kernels: ") + hipGetErrorString(e));
     }
-    s->betaf.resize(L0 * L);
-    s->cdiag_h.resize(L + M);
-    s->scale_h.resize(L + M);
-    e = hipMemcpy(s->betaf.data(), s->dbetaf, L0 * L * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(s->cdiag_h.data(), s->dcdiag, (L + M) * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(s->scale_h.data(), s->dscale, (L + M) * 8, hipMemcpyDeviceToHost);
+    // one read-back (it also waits for the kernels)
+    std::vector<double> rb(nrb);
+    e = hipMemcpy(rb.data(), s->dbetaf, nrb * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return cleanup(PSDP_EDEVICE, std::string("set-up read-back: ") + hipGetErrorString(e));
-    if (opt.a_on_device) {
-      // validate the device copy of A now that it is resident
-      std::vector<double> hA(Na * nn);
-      if (hipMemcpy(hA.data(), s->dA, Na * nn * 8, hipMemcpyDeviceToHost) != hipSuccess)
-        return cleanup(PSDP_EDEVICE, "copy of A failed");
-      for (double v : hA)
-        if (!std::isfinite(v)) return cleanup(PSDP_EINVAL, "A has a non-finite entry");
-    }
+    if (rb[nrb - 1] != 0.0) return cleanup(PSDP_EINVAL, "A has a non-finite entry");
+    s->betaf.assign(rb.begin(), rb.begin() + L0 * L);
+    s->scale_h.assign(rb.begin() + L0 * L, rb.begin() + L0 * L + (L + M));
+    s->cdiag_h.assign(rb.begin() + L0 * L + (L + M), rb.begin() + L0 * L + 2 * (L + M));
     *out = s;
     return PSDP_OK;
   } catch (const std::bad_alloc&) {
