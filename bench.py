@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--workload", default="n10", help="n10 | n100 | mixed512 | learned")
     ap.add_argument("--precision", default=None, help="fp64 | fp32 | bf16 (Schur assembly)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     ap.add_argument("--train", type=int, default=20000, help="learned: training solves")
@@ -139,7 +140,8 @@ def main():
         t0 = time.perf_counter()
         hs = [P.polya_setup(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)]
         t1 = time.perf_counter()
-        rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=prec)
+        rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=prec,
+                                 use_graph=0 if args.no_graph else 1)
         t2 = time.perf_counter()
         for h in hs:
             h.close()
@@ -150,16 +152,27 @@ def main():
     for _ in range(args.warmup):
         step()
     tsplit[0] = tsplit[1] = 0.0
-    prof = P.new_prof()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
     for _ in range(args.steps):
-        results.append(step(prof))
+        results.append(step())
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = el / args.steps * 1e3
     rs = results[-1]
+    split = (1e3 * tsplit[0] / args.steps, 1e3 * tsplit[1] / args.steps)
+    # Per-class device times: HIP events on the solver stream around each
+    # launch class, in a profiled pass of the same steps right after the
+    # timed region (events recorded inside hipGraphs carry no timestamps, so
+    # this pass launches eagerly; kernel durations are unchanged).
+    prof = P.new_prof()
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(args.steps):
+        step(prof)
+    torch.cuda.synchronize()
+    prof_ms = (time.perf_counter() - tp) / args.steps * 1e3
     verdicts = {}
     for r in rs:
         verdicts[r.verdict_name] = verdicts.get(r.verdict_name, 0) + 1
@@ -208,8 +221,8 @@ def main():
         "data": "synthetic (seeded dissipative systems, see workloads.py)",
         "config": {"workload": desc, "systems": len(systems), "gap_tol": 1e-8,
                    "precision": prec,
-                   "setup_ms_per_step": 1e3 * tsplit[0] / args.steps,
-                   "solve_ms_per_step": 1e3 * tsplit[1] / args.steps,
+                   "setup_ms_per_step": split[0], "solve_ms_per_step": split[1],
+                   "hip_graphs": not args.no_graph, "profiled_pass_ms_per_step": prof_ms,
                    "verdicts": verdicts, "iterations_mean": float(np.mean(iters_sys)),
                    "lowprec_iterations_mean": float(np.mean([r.iters_lowprec for r in rs])),
                    "schur_assembly_tflops": asm_tf, "schur_cholesky_tflops": chol_tf,

@@ -126,7 +126,8 @@ typedef struct {
                           /* the matrix-free FP64 product B(Z^-1 B^T(v) X); a solve */
                           /* stops early once its residual ratio reaches 1e-14 or    */
                           /* stops falling below 1e-10. -1 = 0 for FP64, 6 for FP32 */
-    void*  stream;        /* hipStream_t, NULL = null stream                         */
+    void*  stream;        /* hipStream_t, NULL = null stream: the solve runs on a    */
+                          /* private stream ordered after it and returns when done  */
     int    record_history;/* 1: fill psdp_result.history (host memory, caller owns)  */
     double* prof;         /* NULL, or a caller array [PSDP_NPROF][2] that receives,  */
                           /* per launch class, the summed device time (ms) and the   */
@@ -150,6 +151,8 @@ typedef struct {
     int    warm_center;   /* 0: X_j = exp(s_j) I; 1 (default): X_j = exp(s_j) n       */
                           /* Z_j^-1 / tr(Z_j^-1), the projected Z's centred partner   */
                           /* with block trace exp(s_j) n                              */
+    int    use_graph;     /* 1 (default): each iteration's launches are captured once */
+                          /* into two hipGraphs and replayed; 0: launched one by one */
     double label_gap;     /* > 0: record in psdp_result.label_y / label_logx the     */
                           /* iterate of the paper's SDP run at the first iteration    */
                           /* whose relative gap is <= label_gap (training labels of   */

@@ -13,9 +13,12 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -24,6 +27,66 @@
 namespace psdp {
 
 namespace {
+
+// Device blocks released by finished solves are kept (a few per device) and
+// handed to later solves of no larger size, so that batches of the same
+// shape do not pay hipMalloc / hipFree each call.
+struct DevCache {
+  std::mutex mu;
+  struct Blk { int dev; void* p; size_t bytes; };
+  std::vector<Blk> blks;
+};
+static DevCache g_cache;
+constexpr size_t kCacheBlocks = 6;
+
+static void* dev_alloc(size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_cache.mu);
+    size_t best = SIZE_MAX;
+    int bi = -1;
+    for (size_t i = 0; i < g_cache.blks.size(); ++i) {
+      const auto& b = g_cache.blks[i];
+      if (b.dev == dev && b.bytes >= bytes && b.bytes <= 2 * bytes + (1 << 20) && b.bytes < best) {
+        best = b.bytes;
+        bi = (int)i;
+      }
+    }
+    if (bi >= 0) {
+      void* p = g_cache.blks[bi].p;
+      g_cache.blks.erase(g_cache.blks.begin() + bi);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    // drop the cached blocks of this device and try once more
+    std::lock_guard<std::mutex> lk(g_cache.mu);
+    for (size_t i = 0; i < g_cache.blks.size();) {
+      if (g_cache.blks[i].dev == dev) {
+        hipFree(g_cache.blks[i].p);
+        g_cache.blks.erase(g_cache.blks.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+    (void)hipGetLastError();
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  }
+  return p;
+}
+
+static void dev_release(void* p, size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { hipFree(p); return; }
+  std::lock_guard<std::mutex> lk(g_cache.mu);
+  g_cache.blks.push_back({dev, p, bytes});
+  while (g_cache.blks.size() > kCacheBlocks) {
+    hipFree(g_cache.blks.front().p);
+    g_cache.blks.erase(g_cache.blks.begin());
+  }
+}
 
 struct StepTab {
   std::vector<int> sys, pre, first, cnt, tot;
@@ -46,6 +109,7 @@ struct Prof {
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> ev;
   size_t next = 0;
+  size_t base = 0;   // events below base belong to captured graphs
   std::vector<std::array<size_t, 3>> pend;
   double* out = nullptr;
   size_t mark() {
@@ -61,6 +125,16 @@ struct Prof {
   void add(int cls, size_t a, size_t b) {
     if (on) pend.push_back({(size_t)cls, a, b});
   }
+  // continue with n never-recorded events (created now, outside any capture)
+  void fresh(size_t n) {
+    if (!on) return;
+    for (size_t i = 0; i < n; ++i) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      ev.push_back(e);
+    }
+    next = ev.size() - n;
+  }
   // after a stream synchronisation: accumulate and recycle the events
   void harvest() {
     if (!on) return;
@@ -71,7 +145,7 @@ struct Prof {
       out[2 * p[0] + 1] += 1.0;
     }
     pend.clear();
-    next = 0;
+    next = base;
   }
   ~Prof() {
     for (auto e : ev) hipEventDestroy(e);
@@ -126,6 +200,7 @@ struct Batch {
   double *X, *Z, *Zi, *G, *S1, *T1, *W1, *dXh, *dZh, *Wc, *dXb, *dZb, *dX, *dZ, *Cf;
   double *y, *dyh, *dyb, *r, *z, *BX, *rv1, *rv2, *ylift, *vtmp;
   bool any_phase1 = false;
+  bool use_graph = false;   // replay each iteration's launches from hipGraphs
   bool f32 = false;   // precision form: reduced-precision Schur assembly + refinement
   int prec = PSDP_PREC_FP64;
   int ir_max = 0;
@@ -140,23 +215,27 @@ struct Batch {
   int* h_prev = nullptr;
   double* h_sc = nullptr;
 
+  size_t dtab_bytes = 0, arena_bytes = 0;
+
   ~Batch() {
-    if (dtab) hipFree(dtab);
-    if (arena) hipFree(arena);
+    if (dtab) dev_release(dtab, dtab_bytes);
+    if (arena) dev_release(arena, arena_bytes);
     if (h_hf) hipHostFree(h_hf);
     if (h_prev) hipHostFree(h_prev);
     if (h_sc) hipHostFree(h_sc);
   }
 };
 
+// places table v at offset off of the device table block (base) and of its
+// host image (stage); the image goes up in one copy once every table is in
 template <class T>
-static int upload(void* base, size_t& off, const std::vector<T>& v, T** dptr) {
+static int upload(void* base, std::vector<char>& stage, size_t& off, const std::vector<T>& v,
+                  T** dptr) {
   *dptr = (T*)((char*)base + off);
-  if (!v.empty()) {
-    hipError_t e = hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return fail(PSDP_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
-  }
-  off += (v.size() * sizeof(T) + 255) / 256 * 256;
+  const size_t bytes = v.size() * sizeof(T);
+  if (off + bytes > stage.size()) return fail(PSDP_EINVAL, "table image overflow");
+  if (bytes) std::memcpy(stage.data() + off, v.data(), bytes);
+  off += (bytes + 255) / 256 * 256;
   return PSDP_OK;
 }
 
@@ -280,7 +359,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   // ---- arena
   const int nblkarr = 15, nvec = 10;
   const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totP + B.totpre;
-  if (hipMalloc((void**)&B.arena, std::max<int64_t>(total, 1) * 8) != hipSuccess)
+  B.arena_bytes = (size_t)std::max<int64_t>(total, 1) * 8;
+  if (!(B.arena = (double*)dev_alloc(B.arena_bytes)))
     return fail(PSDP_ENOMEM, "device allocation of the solver arena failed (" +
                                  std::to_string(total * 8) + " bytes)");
   double* a = B.arena;
@@ -397,9 +477,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
   tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 4 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256 + 4096;
-  if (hipMalloc(&B.dtab, tb) != hipSuccess) return fail(PSDP_ENOMEM, "device allocation of tables failed");
+  B.dtab_bytes = tb;
+  if (!(B.dtab = dev_alloc(tb))) return fail(PSDP_ENOMEM, "device allocation of tables failed");
   size_t off = 0;
   int rc = PSDP_OK;
+  std::vector<char> stage(tb, 0);
   int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl;
   // the per-system CSR pointers must be patched into SysDesc before upload
   {
@@ -419,38 +501,39 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
       B.sys[s].h_list = d_csr_hl + B.csr_hl_off[s];
     }
   }
-  if ((rc = upload(B.dtab, off, B.sys, &B.d_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.blk, &B.d_blk))) return rc;
-  if ((rc = upload(B.dtab, off, B.pblk, &B.d_pblk))) return rc;
-  if ((rc = upload(B.dtab, off, B.dblk, &B.d_dblk))) return rc;
-  if ((rc = upload(B.dtab, off, B.pairs, &B.d_pairs))) return rc;
-  if ((rc = upload(B.dtab, off, B.offA1, &B.d_offA1))) return rc;
-  if ((rc = upload(B.dtab, off, B.q2, &B.d_q2))) return rc;
-  if ((rc = upload(B.dtab, off, B.terms, &B.d_terms))) return rc;
-  if ((rc = upload(B.dtab, off, B.tiles, &B.d_tiles))) return rc;
-  if ((rc = upload(B.dtab, off, B.ptiles, &B.d_ptiles))) return rc;
-  if ((rc = upload(B.dtab, off, B.gpinfo, &B.d_gpinfo))) return rc;
-  if ((rc = upload(B.dtab, off, B.gpoff, &B.d_gpoff))) return rc;
-  if ((rc = upload(B.dtab, off, B.ownP, &B.d_ownP))) return rc;
-  if ((rc = upload(B.dtab, off, B.ownK, &B.d_ownK))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.sys, &B.d_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.blk, &B.d_blk))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.pblk, &B.d_pblk))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.dblk, &B.d_dblk))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.pairs, &B.d_pairs))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.offA1, &B.d_offA1))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.q2, &B.d_q2))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.terms, &B.d_terms))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.tiles, &B.d_tiles))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.ptiles, &B.d_ptiles))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gpinfo, &B.d_gpinfo))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gpoff, &B.d_gpoff))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.ownP, &B.d_ownP))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.ownK, &B.d_ownK))) return rc;
   int* tmp;
-  if ((rc = upload(B.dtab, off, B.csr_hh, &tmp))) return rc;
-  if ((rc = upload(B.dtab, off, B.csr_hid, &tmp))) return rc;
-  if ((rc = upload(B.dtab, off, B.csr_mh, &tmp))) return rc;
-  if ((rc = upload(B.dtab, off, B.csr_hl, &tmp))) return rc;
-  if ((rc = upload(B.dtab, off, B.pan.sys, &B.d_pan_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.pan.pre, &B.d_pan_pre))) return rc;
-  if ((rc = upload(B.dtab, off, B.trs.sys, &B.d_trs_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.trs.pre, &B.d_trs_pre))) return rc;
-  if ((rc = upload(B.dtab, off, B.wide.sys, &B.d_wide_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.wide.pre, &B.d_wide_pre))) return rc;
-  if ((rc = upload(B.dtab, off, B.upd.sys, &B.d_upd_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.upd.pre, &B.d_upd_pre))) return rc;
-  if ((rc = upload(B.dtab, off, B.fwdL.sys, &B.d_fwdL_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.fwdL.pre, &B.d_fwdL_pre))) return rc;
-  if ((rc = upload(B.dtab, off, B.bwdL.sys, &B.d_bwdL_sys))) return rc;
-  if ((rc = upload(B.dtab, off, B.bwdL.pre, &B.d_bwdL_pre))) return rc;
-  if ((rc = upload(B.dtab, off, B.small_ids, &B.d_small))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.csr_hh, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.csr_hid, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.csr_mh, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.csr_hl, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.pan.sys, &B.d_pan_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.pan.pre, &B.d_pan_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.trs.sys, &B.d_trs_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.trs.pre, &B.d_trs_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.wide.sys, &B.d_wide_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.wide.pre, &B.d_wide_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.upd.sys, &B.d_upd_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.upd.pre, &B.d_upd_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.fwdL.sys, &B.d_fwdL_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.fwdL.pre, &B.d_fwdL_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.bwdL.sys, &B.d_bwdL_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.bwdL.pre, &B.d_bwdL_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.small_ids, &B.d_small))) return rc;
+  PSDP_HIP(hipMemcpy(B.dtab, stage.data(), off, hipMemcpyHostToDevice));
   char* base = (char*)B.dtab;
   B.d_flags = (int*)(base + off); off += ((size_t)B.S * 4 + 255) / 256 * 256;
   B.d_sc = (double*)(base + off); off += ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
@@ -619,17 +702,7 @@ static int op_solve_refined(Batch& B, hipStream_t st, const double* rhs, double*
 
 // identity blocks, C blocks, zeroed Schur matrices with identity padding
 static int init_state(Batch& B, hipStream_t st) {
-  std::vector<double> eye(B.totblk, 0.0), cf(B.totblk, 0.0);
-  for (const auto& b : B.blk) {
-    const double c = B.sd[b.sys]->cdiag_h[b.j];
-    for (int i = 0; i < b.n; ++i) {
-      eye[b.off + (int64_t)i * b.n + i] = 1.0;
-      cf[b.off + (int64_t)i * b.n + i] = c;
-    }
-  }
-  PSDP_HIP(hipMemcpyAsync(B.X, eye.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
-  PSDP_HIP(hipMemcpyAsync(B.Z, eye.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
-  PSDP_HIP(hipMemcpyAsync(B.Cf, cf.data(), B.totblk * 8, hipMemcpyHostToDevice, st));
+  launch_init_blocks(st, B.nblk, B.d_blk, B.d_sys, B.X, B.Z, B.Cf);
   PSDP_HIP(hipMemsetAsync(B.y, 0, B.totvec * 8 * 10, st));   // all ten vectors
   PSDP_HIP(hipMemsetAsync(B.Lam, 0, B.totlam * 8, st));
   launch_pad_identity(st, B.S, B.d_sys, B.Lam);
@@ -657,6 +730,84 @@ static void set_flags(Batch& B, const std::vector<RunState>& rs, int* hf) {
     hf[s] = rs[s].running ? F_ACTIVE | F_CHOLSEL | (B.f32 && !B.asm64[s] ? F_ASM32 : 0) : 0;
 }
 
+// Private solver stream, started after the caller's stream (default priority).
+struct SolveStream {
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  int open(hipStream_t caller) {
+    PSDP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    PSDP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    PSDP_HIP(hipEventRecord(ev, caller));
+    PSDP_HIP(hipStreamWaitEvent(st, ev, 0));
+    return PSDP_OK;
+  }
+  ~SolveStream() {
+    if (st) {
+      hipStreamSynchronize(st);
+      hipStreamDestroy(st);
+    }
+    if (ev) hipEventDestroy(ev);
+  }
+};
+
+// A captured sequence of launches (hipGraph) replayed once per iteration.
+// Capture happens on first use; if the runtime refuses it the sequence runs
+// eagerly from then on.  Event pairs recorded by the profiler inside the
+// sequence are replayed with it.
+struct GraphRun {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool failed = false;
+  std::vector<std::array<size_t, 3>> pairs;
+  ~GraphRun() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  }
+};
+
+template <class F>
+static int replay(Batch& B, hipStream_t st, GraphRun& g, F&& fn) {
+  // HIP events recorded by graph nodes carry no timestamps, so the
+  // per-class profiler runs the launches eagerly
+  if (!B.use_graph || g.failed || B.prof.on) return fn();
+  if (!g.exec) {
+    static const bool dbg = std::getenv("PSDP_GRAPH_DEBUG") != nullptr;
+    const size_t p0 = B.prof.pend.size();
+    B.prof.fresh(1024 + 8 * (size_t)B.maxP);
+    hipError_t eb = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+      if (dbg) std::fprintf(stderr, "graph: begin capture: %s\n", hipGetErrorString(eb));
+      (void)hipGetLastError();
+      g.failed = true;
+      return fn();
+    }
+    const int rc = fn();
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &gr);
+    hipError_t ei = hipSuccess;
+    if (rc == PSDP_OK && ec == hipSuccess && gr) ei = hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0);
+    if (rc != PSDP_OK || ec != hipSuccess || !gr || ei != hipSuccess) {
+      if (dbg)
+        std::fprintf(stderr, "graph: capture failed (body %d: %s; end %s; instantiate %s)\n", rc,
+                     rc ? psdp_last_error() : "", hipGetErrorString(ec), hipGetErrorString(ei));
+      (void)hipGetLastError();
+      if (gr) hipGraphDestroy(gr);
+      g.exec = nullptr;
+      g.failed = true;
+      B.prof.pend.resize(p0);
+      B.prof.fresh(1024 + 8 * (size_t)B.maxP);
+      return fn();
+    }
+    g.graph = gr;
+    g.pairs.assign(B.prof.pend.begin() + p0, B.prof.pend.end());
+    B.prof.pend.resize(p0);
+    B.prof.base = B.prof.next;   // the graph's events stay reserved
+  }
+  PSDP_HIP(hipGraphLaunch(g.exec, st));
+  B.prof.pend.insert(B.prof.pend.end(), g.pairs.begin(), g.pairs.end());
+  return PSDP_OK;
+}
+
 // One interior-point run of every system marked running.
 static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<RunState>& rs,
                    std::vector<std::vector<psdp_iter_rec>>* hist) {
@@ -670,29 +821,16 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
   const int stall_w = 10;
   std::vector<char> was32(S, 0);   // the previous iteration assembled in FP32
   std::vector<char> prev_fail(S, 0);
+  // One synchronisation per iteration: after the residual kernels the host
+  // reads the scalars and the flags (which still carry the failure bits of
+  // the previous Newton step and of this iteration's Z^-1), decides, and
+  // uploads the flags of the Newton step without waiting.
+  set_flags(B, rs, hf);
+  PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
+  GraphRun g1, g2;
   for (int it = 0;; ++it) {
-    // flags carry the failure bits set by the previous iteration's kernels;
-    // read them before resetting (hf is only rewritten after this wait: its
-    // last upload may still be in flight until then).
-    PSDP_HIP(hipMemcpyAsync(prev, B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
-    PSDP_HIP(hipStreamSynchronize(st));
-    B.prof.harvest();
-    set_flags(B, rs, hf);
-    if (it > 0) {
-      for (int s = 0; s < S; ++s) {
-        was32[s] = (prev[s] & F_ASM32) != 0;
-        prev_fail[s] = (prev[s] & F_LAMFAIL) != 0;
-        if (!rs[s].running) continue;
-        if ((prev[s] & F_LAMFAIL) && (prev[s] & F_ASM32)) {
-          // the reduced-precision Schur matrix lost definiteness: the skipped
-          // iteration is repeated with FP64 assembly
-          B.asm64[s] = 1;
-        } else if (prev[s] & F_LAMFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_CHOL; }
-        else if (prev[s] & F_LADDERFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_LADDER; }
-      }
-      set_flags(B, rs, hf);
-    }
-    PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
+    // residuals, objectives and the scalars the host decides on
+    auto part1 = [&]() -> int {
     { const size_t pm_ = B.prof.mark();
     launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
       B.prof.add(PSDP_PROF_CHOLINV, pm_, B.prof.mark()); }
@@ -710,8 +848,26 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     PSDP_HIP(hipGetLastError());
     PSDP_HIP(hipMemcpyAsync(hsc, B.d_sc, nsc * 8, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipMemcpyAsync(prev, B.d_flags, S * 4, hipMemcpyDeviceToHost, st));
+      return PSDP_OK;
+    };
+    int rc = replay(B, st, g1, part1);
+    if (rc) return rc;
     PSDP_HIP(hipStreamSynchronize(st));
     B.prof.harvest();
+    if (it > 0) {
+      // failure bits of the previous Newton step
+      for (int s = 0; s < S; ++s) {
+        was32[s] = (prev[s] & F_ASM32) != 0;
+        prev_fail[s] = (prev[s] & F_LAMFAIL) != 0;
+        if (!rs[s].running) continue;
+        if ((prev[s] & F_LAMFAIL) && (prev[s] & F_ASM32)) {
+          // the reduced-precision Schur matrix lost definiteness: the skipped
+          // step is repeated with FP64 assembly
+          B.asm64[s] = 1;
+        } else if (prev[s] & F_LAMFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_CHOL; }
+        else if (prev[s] & F_LADDERFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_LADDER; }
+      }
+    }
     bool any = false;
     for (int s = 0; s < S; ++s) {
       RunState& r = rs[s];
@@ -771,6 +927,8 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     }
     if (!any) break;
     set_flags(B, rs, hf);
+    // the Newton step: Schur complement, factor, solves, directions, steps
+    auto part2 = [&]() -> int {
     PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
     // ---- Newton system (Alg. 2 processors/root step 1)
     op_schur(B, st);
@@ -838,6 +996,9 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     launch_update_y(st, S, B.d_sys, B.d_flags, B.d_sc, B.y, B.dyh, B.dyb);
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     PSDP_HIP(hipGetLastError());
+      return PSDP_OK;
+    };
+    if ((rc = replay(B, st, g2, part2))) return rc;
     if (hist) {
       PSDP_HIP(hipMemcpyAsync(hsc, B.d_sc, nsc * 8, hipMemcpyDeviceToHost, st));
       PSDP_HIP(hipStreamSynchronize(st));
@@ -908,8 +1069,13 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
       o.precision != PSDP_PREC_BF16)
     return fail(PSDP_EINVAL, "invalid precision");
   if (o.ir_max > 50) return fail(PSDP_EINVAL, "ir_max above 50");
-  hipStream_t st = (hipStream_t)o.stream;
+  // all work runs on a private stream (capturable into graphs) ordered
+  // after the caller's stream
+  SolveStream ss;
+  if (int rc0 = ss.open((hipStream_t)o.stream)) return rc0;
+  hipStream_t st = ss.st;
   Batch B;
+  B.use_graph = o.use_graph != 0;
   B.prec = o.precision;
   B.f32 = o.precision != PSDP_PREC_FP64;
   B.asm64.assign(count, 0);

@@ -72,6 +72,8 @@ void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, c
                         const BlkDesc* blks, const int64_t* offA1);
 void launch_pre34_small(hipStream_t st, int nq, int nmax, const HM2* q, const SysDesc* sys,
                         const int* flags, double* arena);
+void launch_init_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys, double* X,
+                        double* Z, double* Cf);
 void launch_warm_init(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
                       const int* flags, const double* W, const double* cert, const double* logx,
                       double theta, double* X, double* Z);

@@ -1238,7 +1238,26 @@ __global__ void k_block_logtrace(const BlkDesc* __restrict__ blks, const int* __
   if (threadIdx.x == 0) out[blockIdx.x] = log(t / bd.n);
 }
 
+// cold start of every block: X = Z = I, C_j = cdiag_j I
+__global__ void k_init_blocks(const BlkDesc* __restrict__ blks, const SysDesc* __restrict__ sys,
+                              double* X, double* Z, double* Cf) {
+  const BlkDesc bd = blks[blockIdx.x];
+  const double c = sys[bd.sys].cdiag[bd.j];
+  const int n = bd.n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const bool dg = (e / n) == (e % n);
+    X[bd.off + e] = dg ? 1.0 : 0.0;
+    Z[bd.off + e] = dg ? 1.0 : 0.0;
+    Cf[bd.off + e] = dg ? c : 0.0;
+  }
+}
+
 // launch wrappers ----------------------------------------------------------------
+
+void launch_init_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys, double* X,
+                        double* Z, double* Cf) {
+  if (nblk) hipLaunchKernelGGL(k_init_blocks, dim3(nblk), dim3(256), 0, st, blks, sys, X, Z, Cf);
+}
 
 void launch_warm_init(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
                       const int* flags, const double* W, const double* cert, const double* logx,

@@ -58,7 +58,8 @@ class Opts(C.Structure):
                 ("ladder_len", C.c_int), ("verdict_mode", C.c_int), ("precision", C.c_int),
                 ("ir_max", C.c_int), ("stream", C.c_void_p), ("record_history", C.c_int), ("prof", DP),
                 ("warm_y", C.POINTER(DP)), ("warm_logx", C.POINTER(DP)), ("warm_iter_cap", C.c_int),
-                ("warm_margin", C.c_double), ("warm_center", C.c_int), ("label_gap", C.c_double)]
+                ("warm_margin", C.c_double), ("warm_center", C.c_int), ("use_graph", C.c_int),
+                ("label_gap", C.c_double)]
 
 
 class IterRec(C.Structure):

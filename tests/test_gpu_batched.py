@@ -110,3 +110,22 @@ def test_mixed_uneven_batch(P, mixed):
         r1 = P.ipm_solve(gs[k], precision="fp32")
         assert r1.verdict == rs[k].verdict and r1.iterations == rs[k].iterations
         assert np.array_equal(r1.y, rs[k].y)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_equals_eager(P, prec):
+    """Iterations replayed from captured hipGraphs give bit-identical results
+    to launching every kernel one by one (phase-I twins included)."""
+    sys_ = [W.c1_system(s) for s in range(4)] + [W.plain_system(s, twin=True) for s in range(3)] + \
+        [W.paper_shape_system(16, 3, 0)]
+    gs = [P.polya_setup(sy.A, sy.n, sy.l, sy.dp, sy.d) for sy in sys_]
+    print(f"graph vs eager, {prec}", flush=True)
+    prof = P.new_prof()
+    rg = P.ipm_solve_batched(gs, precision=prec, use_graph=1, prof=prof)
+    re = P.ipm_solve_batched(gs, precision=prec, use_graph=0)
+    for a, b in zip(rg, re):
+        assert a.verdict == b.verdict and a.iterations == b.iterations
+        assert a.phase1_used == b.phase1_used and a.phase1_iterations == b.phase1_iterations
+        assert np.array_equal(a.y, b.y)
+    # the profiler sees the replayed launches too
+    assert prof[P.PROF_CLASSES.index("assemble"), 1] >= sum(r.iterations for r in rg[:1])
