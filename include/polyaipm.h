@@ -151,6 +151,12 @@ typedef struct {
     int    warm_center;   /* 0: X_j = exp(s_j) I; 1 (default): X_j = exp(s_j) n       */
                           /* Z_j^-1 / tr(Z_j^-1), the projected Z's centred partner   */
                           /* with block trace exp(s_j) n                              */
+    int    asm_path;      /* Schur assembly kernels: 1 whole (h, h') pairs per        */
+                          /* workgroup (n^2 <= 128), 0 grouped 64 x 64 tiles, -1     */
+                          /* (default) chosen per block order by the autotuner       */
+    int    solve_path;    /* triangular solves: 1 one workgroup per system (at most  */
+                          /* 32 tiles of 64), 0 one launch per tile step, -1         */
+                          /* (default) chosen per tile count by the autotuner        */
     int    use_graph;     /* 1 (default): each iteration's launches are captured once */
                           /* into two hipGraphs and replayed; 0: launched one by one */
     double label_gap;     /* > 0: record in psdp_result.label_y / label_logx the     */
@@ -194,6 +200,8 @@ typedef struct {
     double* label_y;        /* caller buffers [K] and [L+M] or NULL: y and           */
     double* label_logx;     /* log(tr(X_j) / n) at the label_gap iterate             */
     int     label_iter;     /* that iteration (-1: not reached)                      */
+    int     asm_path;       /* paths this system took (see psdp_opts)                */
+    int     solve_path;
     psdp_iter_rec* history; /* caller buffer of history_cap records, or NULL         */
     int     history_cap;
     int     history_len;

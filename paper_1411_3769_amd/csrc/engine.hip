@@ -18,6 +18,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -201,6 +202,7 @@ struct Batch {
   double *y, *dyh, *dyb, *r, *z, *BX, *rv1, *rv2, *ylift, *vtmp;
   bool any_phase1 = false;
   bool use_graph = false;   // replay each iteration's launches from hipGraphs
+  std::vector<char> use_pair, use_small;   // kernel paths per system
   bool f32 = false;   // precision form: reduced-precision Schur assembly + refinement
   int prec = PSDP_PREC_FP64;
   int ir_max = 0;
@@ -245,7 +247,29 @@ static size_t tabsize(const std::vector<T>& v) {
 }
 
 // Builds every per-batch table on the host and allocates the arena.
-static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
+// Kernel paths per system: whole-pair assembly (n^2 <= 128 only) or grouped
+// tiles; the whole solve in one workgroup (P <= kSmallP only) or tile steps.
+struct Choice {
+  std::vector<char> pair, small;
+};
+
+static Choice default_choice(psdp_sdp* const* sdps, int count) {
+  Choice c;
+  for (int s = 0; s < count; ++s) {
+    c.pair.push_back(sdps[s]->n * sdps[s]->n <= 128);
+    c.small.push_back(sdps[s]->Kpad / kNB <= kSmallP);
+  }
+  return c;
+}
+
+static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice* ch = nullptr) {
+  Choice dflt;
+  if (!ch) {
+    dflt = default_choice(sdps, count);
+    ch = &dflt;
+  }
+  B.use_pair = ch->pair;
+  B.use_small = ch->small;
   B.S = count;
   B.sd.assign(sdps, sdps + count);
   // ---- per-system layout
@@ -415,7 +439,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
         }
         const int kcnt = (int)B.terms.size() - kbeg;
         if (kcnt == 0) continue;   // the block stays zero
-        if (p->n * p->n <= 128) {
+        if (ch->pair[s] && p->n * p->n <= 128) {
           B.ptiles.push_back(AsmTile{s, h, h2, -1, -1, kbeg, kcnt, 0});
           B.maxn_pair = std::max(B.maxn_pair, p->n);
           continue;
@@ -432,7 +456,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
 
   // ---- Cholesky step tables
   for (int s = 0; s < count; ++s)
-    if (B.sys[s].P <= kSmallP) B.small_ids.push_back(s);
+    if (ch->small[s] && B.sys[s].P <= kSmallP) B.small_ids.push_back(s);
   for (int pstep = 0; pstep < B.maxP; ++pstep) {
     B.pan.add_step();
     B.trs.add_step();
@@ -456,7 +480,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count) {
         const int nb2 = (P - pstep - 1 + 1) / 2;
         B.wide.add(s, nb2 * (nb2 + 1) / 2);
       }
-      if (P > kSmallP) {
+      if (!(ch->small[s] && P <= kSmallP)) {
         B.fwdL.add(s, P - pstep);
         B.bwdL.add(s, pstep + 1);
       }
@@ -1057,6 +1081,103 @@ static int warm_project(Batch& B, hipStream_t st, const psdp_opts& o, const std:
   return PSDP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: for each block order n with n^2 <= 128 the assembly path (whole
+// pairs or grouped tiles) and for each tile count P <= kSmallP the solve path
+// (one workgroup per system or tile steps) are timed once per process with
+// HIP events on up to 8 systems of the batch, and the faster is kept.  Both
+// paths of each choice compute the same quantities (they differ in rounding
+// order only).
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, char> g_tune;   // (0, n) assembly, (1, P) solve -> 1 = pair / one wg
+
+template <class F>
+static float time_ms(hipStream_t st, int reps, F&& fn) {
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  fn();   // warm-up
+  hipEventRecord(a, st);
+  for (int i = 0; i < reps; ++i) fn();
+  hipEventRecord(b, st);
+  hipEventSynchronize(b);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, a, b);
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms / reps;
+}
+
+static int trial_batch(Batch& T, psdp_sdp* const* sub, int cnt, const Choice& c, hipStream_t st) {
+  int rc = build_batch(T, sub, cnt, &c);
+  if (rc) return rc;
+  if ((rc = init_state(T, st))) return rc;
+  std::vector<int> hf(cnt, F_ACTIVE | F_CHOLSEL);
+  PSDP_HIP(hipMemcpy(T.d_flags, hf.data(), cnt * 4, hipMemcpyHostToDevice));
+  return PSDP_OK;
+}
+
+static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hipStream_t st,
+                       Choice& ch) {
+  ch = default_choice(sdps, count);
+  for (int s = 0; s < count; ++s) {
+    const bool can_pair = sdps[s]->n * sdps[s]->n <= 128;
+    const bool can_small = sdps[s]->Kpad / kNB <= kSmallP;
+    if (o.asm_path >= 0) ch.pair[s] = can_pair && o.asm_path == 1;
+    if (o.solve_path >= 0) ch.small[s] = can_small && o.solve_path == 1;
+  }
+  for (int kind = 0; kind < 2; ++kind) {
+    if ((kind == 0 ? o.asm_path : o.solve_path) >= 0) continue;
+    std::map<int, std::vector<int>> want;   // key -> systems
+    for (int s = 0; s < count; ++s) {
+      const int key = kind == 0 ? sdps[s]->n : (int)(sdps[s]->Kpad / kNB);
+      const bool able = kind == 0 ? key * key <= 128 : key <= kSmallP;
+      if (!able) continue;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tune.count({kind, key})) continue;
+      }
+      if (want[key].size() < 8) want[key].push_back(s);
+    }
+    for (auto& kv : want) {
+      std::vector<psdp_sdp*> sub;
+      for (int s : kv.second) sub.push_back(sdps[s]);
+      const int cnt = (int)sub.size();
+      float t[2] = {0.f, 0.f};
+      for (int v = 0; v < 2; ++v) {
+        Choice c = default_choice(sub.data(), cnt);
+        for (int i = 0; i < cnt; ++i) (kind == 0 ? c.pair : c.small)[i] = (char)v;
+        Batch T;
+        if (int rc = trial_batch(T, sub.data(), cnt, c, st)) return rc;
+        if (kind == 0) {
+          t[v] = time_ms(st, 3, [&]() { op_schur(T, st); });
+        } else {
+          op_schur(T, st);
+          op_factor(T, st);
+          t[v] = time_ms(st, 3, [&]() { op_solve(T, st, T.rv1, T.dyh); });
+        }
+        PSDP_HIP(hipGetLastError());
+      }
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[{kind, kv.first}] = t[1] <= t[0] ? 1 : 0;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int s = 0; s < count; ++s) {
+    if (o.asm_path < 0 && sdps[s]->n * sdps[s]->n <= 128) {
+      auto it = g_tune.find({0, sdps[s]->n});
+      if (it != g_tune.end()) ch.pair[s] = it->second;
+    }
+    const int P = (int)(sdps[s]->Kpad / kNB);
+    if (o.solve_path < 0 && P <= kSmallP) {
+      auto it = g_tune.find({1, P});
+      if (it != g_tune.end()) ch.small[s] = it->second;
+    }
+  }
+  return PSDP_OK;
+}
+
 static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp_result* res,
                       bool use_warm) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1083,8 +1204,10 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
   B.prof.on = o.prof != nullptr;
   B.prof.st = st;
   B.prof.out = o.prof;
-  int rc = build_batch(B, sdps, count);
+  Choice ch;
+  int rc = tune_choice(sdps, count, o, st, ch);
   if (rc) return rc;
+  if ((rc = build_batch(B, sdps, count, &ch))) return rc;
   if ((rc = init_state(B, st))) return rc;
   std::vector<char> warm(count, 0);
   bool anywarm = false;
@@ -1228,6 +1351,8 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     R.iters_lowprec = r.it32 + (need[s] ? r1[s].it32 : 0);
     R.ir_steps = r.ir_steps + (need[s] ? r1[s].ir_steps : 0);
     R.ir_eta_max = R.iters_lowprec ? std::max(r.eta_max, need[s] ? r1[s].eta_max : 0.0) : NAN;
+    R.asm_path = B.use_pair[s] && p->n * p->n <= 128;
+    R.solve_path = B.use_small[s] && d.P <= kSmallP;
     R.label_iter = r.label_iter;
     if (r.label_iter >= 0) {
       if (R.label_y) std::memcpy(R.label_y, r.label_y.data(), d.K * 8);

@@ -223,6 +223,8 @@ void psdp_opts_default(psdp_opts* o) {
   o->warm_iter_cap = 0;
   o->warm_margin = 1e-6;
   o->warm_center = 1;
+  o->asm_path = -1;
+  o->solve_path = -1;
   o->use_graph = 1;
   o->label_gap = 0.0;
 }

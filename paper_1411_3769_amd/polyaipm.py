@@ -58,7 +58,8 @@ class Opts(C.Structure):
                 ("ladder_len", C.c_int), ("verdict_mode", C.c_int), ("precision", C.c_int),
                 ("ir_max", C.c_int), ("stream", C.c_void_p), ("record_history", C.c_int), ("prof", DP),
                 ("warm_y", C.POINTER(DP)), ("warm_logx", C.POINTER(DP)), ("warm_iter_cap", C.c_int),
-                ("warm_margin", C.c_double), ("warm_center", C.c_int), ("use_graph", C.c_int),
+                ("warm_margin", C.c_double), ("warm_center", C.c_int), ("asm_path", C.c_int),
+                ("solve_path", C.c_int), ("use_graph", C.c_int),
                 ("label_gap", C.c_double)]
 
 
@@ -77,6 +78,7 @@ class CResult(C.Structure):
                 ("ir_steps", C.c_int), ("ir_eta_max", C.c_double),
                 ("warm_used", C.c_int), ("warm_fallback", C.c_int), ("warm_iterations", C.c_int),
                 ("logx", DP), ("label_y", DP), ("label_logx", DP), ("label_iter", C.c_int),
+                ("asm_path", C.c_int), ("solve_path", C.c_int),
                 ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
 
@@ -289,6 +291,8 @@ class Result:
     label_y: np.ndarray = None
     label_logx: np.ndarray = None
     label_iter: int = -1
+    asm_path: int = -1
+    solve_path: int = -1
     history: list = field(default_factory=list)
 
     @property
@@ -353,7 +357,7 @@ def _unpack(r: CResult, P, y, lx, hist) -> Result:
                   r.phase1_iterations, r.t_star, r.time_solve_s, r.iters_lowprec,
                   r.ir_steps, r.ir_eta_max, bool(r.warm_used), bool(r.warm_fallback),
                   r.warm_iterations, lx[0], lx[1] if r.label_iter >= 0 else None,
-                  lx[2] if r.label_iter >= 0 else None, r.label_iter, h)
+                  lx[2] if r.label_iter >= 0 else None, r.label_iter, r.asm_path, r.solve_path, h)
 
 
 def ipm_solve(sdp: SDP, warm_y=None, warm_logx=None, **opts) -> Result:

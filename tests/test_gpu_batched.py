@@ -129,3 +129,21 @@ def test_graph_replay_equals_eager(P, prec):
         assert np.array_equal(a.y, b.y)
     # the profiler sees the replayed launches too
     assert prof[P.PROF_CLASSES.index("assemble"), 1] >= sum(r.iterations for r in rg[:1])
+
+
+@pytest.mark.parametrize("asm_path,solve_path", [(0, 0), (0, 1), (1, 0), (1, 1), (-1, -1)])
+def test_kernel_paths_match_oracle(P, asm_path, solve_path):
+    """Every assembly / solve path the autotuner can pick gives the oracle's
+    end points; the result reports the path taken."""
+    with open(os.path.join(GOLDEN, "oracle_results.json")) as fh:
+        recs = {r["seed"]: r for r in json.load(fh) if r["tag"] == "n10"}
+    seeds = [0, 9, 17, 33]
+    gs = [P.polya_setup(W.c1_system(s).A, 10, 4, 2, 2) for s in seeds]
+    print(f"paths asm={asm_path} solve={solve_path}", flush=True)
+    rs = P.ipm_solve_batched(gs, asm_path=asm_path, solve_path=solve_path)
+    for s, r in zip(seeds, rs):
+        _check(recs[s], r)
+        if asm_path >= 0:
+            assert r.asm_path == asm_path
+        if solve_path >= 0:
+            assert r.solve_path == solve_path
