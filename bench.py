@@ -28,6 +28,16 @@ METRIC = "IPM time-to-certificate @gap 1e-8: FP64 vs mixed/warm-start; Schur TFL
 PEAK_FP64 = 78.6          # TFLOP/s, FP64 vector and FP64 matrix (MI355X)
 PEAK_HBM = 8000.0         # GB/s
 
+# HBM bytes per launch of the dominant kernel, from the two rocprofv3 --pmc
+# runs summarised in profiles/hbm_counters_n10_batch64.md (FETCH_SIZE and
+# WRITE_SIZE in KiB per dispatch, scaled by what they read for a plain
+# 256 MiB device copy: x2.000 and x1.000).  Valid for the kernel version
+# those runs measured; None once it changes.
+PMC_TRAFFIC = {
+    ("n10", "assemble"): dict(kernel="k_assemble_pair<0>", fetch_kib=85553.3, write_kib=145150.6,
+                              fetch_scale=2.0, write_scale=1.0),
+}
+
 
 def _mons(l, d):
     out = []
@@ -194,15 +204,21 @@ def main():
     avg_ms = per[dom][0] / max(per[dom][1], 1)
     if dom == "assemble":
         per_launch = asm_flops / max(launches, 1)
-        roof = dict(bound="alu", achieved=per_launch / (avg_ms * 1e-3) / 1e12, peak=PEAK_FP64,
-                    unit="TFLOP/s", kernel="k_assemble (Schur complement assembly, FP64 FMA)")
+        roof = dict(bound="mfma", achieved=per_launch / (avg_ms * 1e-3) / 1e12, peak=PEAK_FP64,
+                    unit="TFLOP/s",
+                    kernel="k_assemble_pair / k_assemble_grp (Schur complement assembly, FP64 MFMA)")
     elif dom in ("chol_update", "chol_panel"):
-        roof = dict(bound="alu", achieved=chol_tf, peak=PEAK_FP64, unit="TFLOP/s",
-                    kernel="k_chol_panel + k_chol_update (Schur Cholesky, FP64 FMA)")
+        roof = dict(bound="mfma", achieved=chol_tf, peak=PEAK_FP64, unit="TFLOP/s",
+                    kernel="k_chol_diag + k_chol_trsm + k_chol_update(_wide) (Schur Cholesky, FP64 MFMA)")
     else:
-        roof = dict(bound="alu", achieved=None, peak=PEAK_FP64, unit="TFLOP/s", kernel=dom)
+        roof = dict(bound="mfma", achieved=None, peak=PEAK_FP64, unit="TFLOP/s", kernel=dom)
     roof["frac"] = (roof["achieved"] / roof["peak"]) if roof.get("achieved") else None
-    roof["traffic"] = None
+    tr = PMC_TRAFFIC.get((args.workload, dom)) if prec == "fp64" else None
+    roof["traffic"] = (1024.0 * (tr["fetch_kib"] * tr["fetch_scale"] + tr["write_kib"] * tr["write_scale"])
+                       if tr else None)
+    if tr:
+        roof["traffic_unit"] = "bytes per launch (HBM read + write, rocprofv3 counters)"
+        roof["traffic_GBps"] = roof["traffic"] / (avg_ms * 1e-3) / 1e9
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = launches
 
