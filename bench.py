@@ -33,10 +33,7 @@ PEAK_HBM = 8000.0         # GB/s
 # WRITE_SIZE in KiB per dispatch, scaled by what they read for a plain
 # 256 MiB device copy: x2.000 and x1.000).  Valid for the kernel version
 # those runs measured; None once it changes.
-PMC_TRAFFIC = {
-    ("n10", "assemble"): dict(kernel="k_assemble_pair<0>", fetch_kib=85553.3, write_kib=145150.6,
-                              fetch_scale=2.0, write_scale=1.0),
-}
+PMC_TRAFFIC = {}
 
 
 def _mons(l, d):

@@ -171,7 +171,7 @@ struct Batch {
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
   std::vector<int> ownP, ownK;
-  StepTab pan, trs, upd, wide, fwdL, bwdL;     // fwdL/bwdL: solve steps of the large systems only
+  StepTab pan, trs, upd, wide, fwdL, bwdL;   // fwdL/bwdL: tile-step solves of the systems not solved in one workgroup
   std::vector<int> small_ids;
   int* d_small = nullptr;
   int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0;
@@ -210,7 +210,7 @@ struct Batch {
   int maxK = 0;
   int nmax_small = 0;   // largest block order <= kSmallN in the batch (0: none)
   int nmin_big = 0;     // the general block kernels skip orders below this
-  double *Lam, *Ldiag, *Linv, *Pm, *pre;
+  double *Lam, *Ldiag, *Linv, *Pm, *pre, *rscr;
 
   // pinned host mirrors of the per-iteration transfers (flags, scalars)
   int* h_hf = nullptr;
@@ -382,7 +382,13 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
 
   // ---- arena
   const int nblkarr = 15, nvec = 10;
-  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totP + B.totpre;
+  // whole-pair assembly scratch: one n^2 x n^2 slot per workgroup of its grid
+  int pn = 0;
+  for (int s = 0; s < count; ++s)
+    if (ch->pair[s] && sdps[s]->n * sdps[s]->n <= 128) pn = std::max(pn, sdps[s]->n);
+  const int64_t totrs = pn ? (int64_t)kPairGrid * pn * pn * pn * pn : 0;
+  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totP + B.totpre +
+                        totrs;
   B.arena_bytes = (size_t)std::max<int64_t>(total, 1) * 8;
   if (!(B.arena = (double*)dev_alloc(B.arena_bytes)))
     return fail(PSDP_ENOMEM, "device allocation of the solver arena failed (" +
@@ -399,6 +405,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.Linv = a + o; o += B.totdg;
   B.Pm = a + o; o += B.totP;
   B.pre = a + o; o += B.totpre;
+  B.rscr = a + o; o += totrs;
   const int64_t preBase = B.pre - a, ziBase = B.Zi - a, xBase = B.X - a;
   for (auto& hp : B.pairs) { hp.offY += preBase; hp.offA2 += preBase; }
   for (auto& v : B.offA1) v += preBase;
@@ -464,12 +471,17 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.wide.add_step();
     B.fwdL.add_step();
     B.bwdL.add_step();
+
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (P <= pstep) continue;
       B.pan.add(s, 1);
       const int T = P - pstep - 1;
       if (T > 0) B.trs.add(s, T);
+      if (!(ch->small[s] && P <= kSmallP)) {
+        B.fwdL.add(s, P - pstep);
+        B.bwdL.add(s, pstep + 1);
+      }
       // narrow update: columns p+1 .. end of the super-panel
       const int se = std::min(P - 1, (pstep / kSW) * kSW + kSW - 1);
       int nn = 0;
@@ -480,10 +492,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
         const int nb2 = (P - pstep - 1 + 1) / 2;
         B.wide.add(s, nb2 * (nb2 + 1) / 2);
       }
-      if (!(ch->small[s] && P <= kSmallP)) {
-        B.fwdL.add(s, P - pstep);
-        B.bwdL.add(s, pstep + 1);
-      }
+
     }
   }
 
@@ -634,7 +643,7 @@ static void op_schur(Batch& B, hipStream_t st) {
   }
   const size_t m1 = B.prof.mark();
   launch_assemble_pair(st, B.nptiles, B.maxn_pair, B.d_ptiles, B.d_terms, B.d_sys, B.d_flags,
-                       B.arena, B.Lam, B.prec);
+                       B.arena, B.Lam, B.prec, B.rscr);
   launch_assemble_grp(st, B.ntiles, B.d_tiles, B.d_terms, B.d_sys, B.d_flags, B.d_gpinfo, B.arena,
                       B.Lam, B.d_gpoff, B.prec);
   const size_t m2 = B.prof.mark();

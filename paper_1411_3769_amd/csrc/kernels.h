@@ -53,7 +53,7 @@ void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, cons
                   double* arena, int nmin);
 void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                           const KTerm* terms, const SysDesc* sys, const int* flags,
-                          const double* arena, double* Lam, int prec);
+                          const double* arena, double* Lam, int prec, double* rscr);
 void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
                          const SysDesc* sys, const int* flags, const int* gpinfo,
                          const double* arena, double* Lam, const int64_t* gpoff, int prec);

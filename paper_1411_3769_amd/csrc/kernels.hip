@@ -793,27 +793,31 @@ __device__ inline int asm_row(int lane, int i) {
 constexpr int kPairMaxT = 16;
 
 template <int PR>
-__global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict__ tiles,
+__global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict__ tiles, int npt,
                                                        const KTerm* __restrict__ terms,
                                                        const SysDesc* __restrict__ sys,
                                                        const int* __restrict__ flags,
                                                        const double* __restrict__ arena,
-                                                       double* Lam) {
+                                                       double* Lam, double* rscr, int rslot) {
   extern __shared__ double smem[];
   typedef AsmPrec<PR> AP;
   typedef typename AP::stage_t real;
   typedef typename AP::acc_t acc_t;
   constexpr int KC = AP::KC;
-  const AsmTile tl = tiles[blockIdx.x];
-  ACTIVE_OR_RETURN(tl.sys);
-  if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) return;
+  // R of the pair goes to this workgroup's slot of global scratch (it is
+  // read back through L2); LDS only stages the terms, so several workgroups
+  // share a CU.  The grid strides over the pairs.
+  double* R = rscr + (int64_t)blockIdx.x * rslot;
+  for (int tix = blockIdx.x; tix < npt; tix += gridDim.x) {
+  const AsmTile tl = tiles[tix];
+  if (!(flags[tl.sys] & F_ACTIVE)) continue;
+  if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) continue;
   const SysDesc sd = sys[tl.sys];
   const int n = sd.n, n2 = n * n;
   const int NT = (n2 + 15) / 16, n2p = NT * 16, ntiles = NT * NT;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   real* sT = reinterpret_cast<real*>(smem);
   real* sU = sT + KC * n2p;
-  double* R = smem + 8 * n2p;   // staging needs at most 2 KC n2p sizeof(real) <= 64 n2p bytes
   acc_t acc[kPairMaxT];
 #pragma unroll
   for (int t = 0; t < kPairMaxT; ++t) acc[t] = acc_t{0, 0, 0, 0};
@@ -845,7 +849,6 @@ __global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict
       }
     }
   }
-  __syncthreads();
 #pragma unroll
   for (int t = 0; t < kPairMaxT; ++t) {
     const int id = wave + 4 * t;
@@ -876,6 +879,8 @@ __global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict
     const int64_t row = (int64_t)tl.h * Nt + b1, col = (int64_t)tl.h2 * Nt + b2;
     Lr[row * ld + col] = v;
     if (tl.h != tl.h2) Lr[col * ld + row] = v;
+  }
+  __syncthreads();   // R is rewritten by the next pair
   }
 }
 
@@ -1459,21 +1464,22 @@ namespace psdp {
 template <int PR>
 static void pair_launch(hipStream_t st, int ntiles, size_t lds, const AsmTile* tiles,
                         const KTerm* terms, const SysDesc* sys, const int* flags,
-                        const double* arena, double* Lam) {
-  set_lds((const void*)k_assemble_pair<PR>, lds);
-  hipLaunchKernelGGL(k_assemble_pair<PR>, dim3(ntiles), dim3(256), lds, st, tiles, terms, sys, flags,
-                     arena, Lam);
+                        const double* arena, double* Lam, double* rscr, int rslot) {
+  const int grid = ntiles < kPairGrid ? ntiles : kPairGrid;
+  hipLaunchKernelGGL(k_assemble_pair<PR>, dim3(grid), dim3(256), lds, st, tiles, ntiles, terms, sys,
+                     flags, arena, Lam, rscr, rslot);
 }
 
 void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                           const KTerm* terms, const SysDesc* sys, const int* flags,
-                          const double* arena, double* Lam, int prec) {
+                          const double* arena, double* Lam, int prec, double* rscr) {
   if (!ntiles) return;
   const int n2 = maxn * maxn, n2p = (n2 + 15) / 16 * 16;
-  const size_t lds = (size_t)(8 * n2p + n2 * n2) * 8;
-  if (prec == PSDP_PREC_FP32) pair_launch<1>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam);
-  if (prec == PSDP_PREC_BF16) pair_launch<2>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam);
-  pair_launch<0>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam);
+  const size_t lds = (size_t)(8 * n2p) * 8;   // staging of the largest form (FP64 / BF16)
+  const int rslot = n2 * n2;
+  if (prec == PSDP_PREC_FP32) pair_launch<1>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam, rscr, rslot);
+  if (prec == PSDP_PREC_BF16) pair_launch<2>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam, rscr, rslot);
+  pair_launch<0>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam, rscr, rslot);
 }
 
 void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
