@@ -904,9 +904,10 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
   typedef AsmPrec<PR> AP;
   typedef typename AP::stage_t real;
   typedef typename AP::acc_t acc_t;
-  constexpr int KC = AP::KC;
-  __shared__ real sT[KC * 16 * 17];
-  __shared__ real sU[KC * 16 * 17];
+  constexpr int KC = AP::KC;                 // depth of one MFMA
+  constexpr int KS = PR == 2 ? 16 : 8;       // terms per LDS stage
+  __shared__ real sT[KS * 16 * 17];
+  __shared__ real sU[KS * 16 * 17];
   __shared__ double sL[64 * 65];
   const AsmTile tl = tiles[blockIdx.x];
   ACTIVE_OR_RETURN(tl.sys);
@@ -920,37 +921,55 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
   // index offsets of the quadrant's row pair (x, y) and column pair (z, u)
   const int xoff = w < 2 ? 8 : 0, yoff = (w & 1) ? 8 : 0;
   const int zoff = (w & 1) ? 0 : 8, uoff = w < 2 ? 0 : 8;
+  // every thread stages entry (a, c) of T and of U for each term of a stage
+  const int sa = tid >> 4, sc = tid & 15;
+  const int ia = sa < 8 ? kTB * g1 + sa : kTB * g2 + (sa - 8);
+  const int jc = sc < 8 ? kTB * g3 + sc : kTB * g4 + (sc - 8);
+  const bool inb = ia < n && jc < n;
+  const int iN = ia * n + jc, iT = jc * n + ia;
+  double vT[KS], vU[KS];
+  // the next stage is fetched into registers while the current one is
+  // multiplied
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      double tv = 0.0, uv = 0.0;
+      if (inb && k0 + kk < tl.kcnt) {
+        const KTerm kt = terms[tl.kbeg + k0 + kk];
+        tv = kt.coef * arena[kt.offT + (kt.tT ? iT : iN)];
+        uv = arena[kt.offU + (kt.tU ? iN : iT)];
+      }
+      vT[kk] = tv;
+      vU[kk] = uv;
+    }
+  };
   acc_t acc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  for (int k0 = 0; k0 < tl.kcnt; k0 += KC) {
+  fetch(0);
+  for (int k0 = 0; k0 < tl.kcnt; k0 += KS) {
     __syncthreads();
-    for (int e = tid; e < KC * 512; e += 256) {
-      const int kk = e >> 9, rem = e & 511, which = rem >> 8;
-      const int a = (rem & 255) >> 4, c = rem & 15;
-      const int ia = a < 8 ? kTB * g1 + a : kTB * g2 + (a - 8);
-      const int jc = c < 8 ? kTB * g3 + c : kTB * g4 + (c - 8);
-      double v = 0.0;
-      if (k0 + kk < tl.kcnt && ia < n && jc < n) {
-        const KTerm kt = terms[tl.kbeg + k0 + kk];
-        if (which == 0) v = kt.coef * arena[kt.offT + (kt.tT ? jc * n + ia : ia * n + jc)];
-        else v = arena[kt.offU + (kt.tU ? ia * n + jc : jc * n + ia)];
-      }
-      if (which == 0) sT[kk * 272 + a * 17 + c] = AP::cvt(v);   // T[I_a][J_c]
-      else sU[kk * 272 + c * 17 + a] = AP::cvt(v);              // U[J_c][I_a]
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      sT[kk * 272 + sa * 17 + sc] = AP::cvt(vT[kk]);   // T[I_a][J_c]
+      sU[kk * 272 + sc * 17 + sa] = AP::cvt(vU[kk]);   // U[J_c][I_a]
     }
     __syncthreads();
+    if (k0 + KS < tl.kcnt) fetch(k0 + KS);
     const int kq = lane >> 4, r16 = lane & 15;
-    const int kb = PR == 2 ? 4 * kq : kq;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int xi = 2 * t + (r16 >> 3), yi = r16 & 7;
-      const real* pa = sT + kb * 272 + (xoff + xi) * 17 + yoff + yi;
+    for (int ks = 0; ks < KS; ks += KC) {
+      const int kb = ks + (PR == 2 ? 4 * kq : kq);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int zi = 2 * u + (r16 >> 3), ui = r16 & 7;
-        const real* pb = sU + kb * 272 + (zoff + zi) * 17 + uoff + ui;
-        acc[t * 4 + u] = asm_mfma<PR>(pa, pb, 272, acc[t * 4 + u]);
+      for (int t = 0; t < 4; ++t) {
+        const int xi = 2 * t + (r16 >> 3), yi = r16 & 7;
+        const real* pa = sT + kb * 272 + (xoff + xi) * 17 + yoff + yi;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int zi = 2 * u + (r16 >> 3), ui = r16 & 7;
+          const real* pb = sU + kb * 272 + (zoff + zi) * 17 + uoff + ui;
+          acc[t * 4 + u] = asm_mfma<PR>(pa, pb, 272, acc[t * 4 + u]);
+        }
       }
     }
   }
