@@ -311,10 +311,12 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
 // panel): A_ij -= sum over the super-panel's panels q of L_iq L_jq^T for every
 // tile pair right of it (depth 64 kSW), on 128 x 128 output blocks (2 x 2
 // tiles; wave w owns the 64 x 64 quadrant (w/2, w%2) as 4 x 4 MFMA tiles).
-// The depth is staged through LDS 16 columns at a time with the next chunk
+// The depth is staged through LDS 32 columns at a time with the next chunk
 // prefetched into registers.  Only the lower triangle (column <= row) of the
 // matrix is written; rows or columns past Kpad are skipped.
-constexpr int kWT = 128, kWK = 16, kWLD = kWK + 1;
+constexpr int kWT = 128, kWK = 32, kWLD = kWK + 1;
+constexpr int kWRP = 256 / kWK;          // rows staged per pass
+constexpr int kWU = kWT / kWRP;          // passes (values per thread and operand)
 
 __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restrict__ sys,
                                                           const int* __restrict__ flags, double* Lam,
@@ -341,13 +343,13 @@ __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restr
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int r16 = lane & 15, kq = lane >> 4;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-  // staging map: thread loads rows (tid / 16) + 16 u, column tid % 16
-  const int lr = tid >> 4, lk = tid & 15;
-  double ra[8], rb[8];
+  // staging map: thread loads rows tid / kWK + kWRP u, column tid % kWK
+  const int lr = tid / kWK, lk = tid % kWK;
+  double ra[kWU], rb[kWU];
   auto load = [&](int kc) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int row = lr + 16 * u;
+    for (int u = 0; u < kWU; ++u) {
+      const int row = lr + kWRP * u;
       ra[u] = r0 + row < nmax ? A[(int64_t)(r0 + row) * ld + d0 + kc + lk] : 0.0;
       rb[u] = c0 + row < nmax ? A[(int64_t)(c0 + row) * ld + d0 + kc + lk] : 0.0;
     }
@@ -361,9 +363,9 @@ __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restr
   for (int kc = 0; kc < D; kc += kWK) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      sa[(lr + 16 * u) * kWLD + lk] = ra[u];
-      sb[(lr + 16 * u) * kWLD + lk] = rb[u];
+    for (int u = 0; u < kWU; ++u) {
+      sa[(lr + kWRP * u) * kWLD + lk] = ra[u];
+      sb[(lr + kWRP * u) * kWLD + lk] = rb[u];
     }
     __syncthreads();
     if (kc + kWK < D) load(kc + kWK);

@@ -16,7 +16,7 @@ constexpr int kMaxN = 128;   // largest block order held whole in LDS (128 KB)
 constexpr int kTB = 8;       // index-group size of the tiled basis
 constexpr int kNB = 64;      // Schur Cholesky tile
 constexpr int kPairGrid = 1024;   // workgroups of the whole-pair assembly (grid-stride)
-constexpr int kSW = 4;       // Cholesky panels per super-panel (depth of the wide update / 64)
+constexpr int kSW = 8;       // Cholesky panels per super-panel (depth of the wide update / 64)
 constexpr int kMaxDeg = 20;  // largest multinomial degree (20! < 2^63)
 constexpr int kNSC = 24;     // per-system scalar slots
 
