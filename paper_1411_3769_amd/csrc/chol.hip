@@ -296,13 +296,18 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
       acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
     }
   }
+  double cv[16];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cv[u * 4 + q] = C[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int cc = 16 * u + r16;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int rr = 16 * w + 4 * q + kq;
-      if (i != j || cc <= rr) C[(int64_t)rr * ld + cc] -= acc[u][q];
+      if (i != j || cc <= rr) C[(int64_t)rr * ld + cc] = cv[u * 4 + q] - acc[u][q];
     }
   }
 }
@@ -349,9 +354,14 @@ __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restr
   auto load = [&](int kc) {
 #pragma unroll
     for (int u = 0; u < kWU; ++u) {
+      // rows past Kpad (second half of an edge block) read a valid row and
+      // are zeroed, so the loads need no branches
       const int row = lr + kWRP * u;
-      ra[u] = r0 + row < nmax ? A[(int64_t)(r0 + row) * ld + d0 + kc + lk] : 0.0;
-      rb[u] = c0 + row < nmax ? A[(int64_t)(c0 + row) * ld + d0 + kc + lk] : 0.0;
+      const int ra_r = min(r0 + row, nmax - 1), rb_r = min(c0 + row, nmax - 1);
+      const double va = A[(int64_t)ra_r * ld + d0 + kc + lk];
+      const double vb = A[(int64_t)rb_r * ld + d0 + kc + lk];
+      ra[u] = r0 + row < nmax ? va : 0.0;
+      rb[u] = c0 + row < nmax ? vb : 0.0;
     }
   };
   v4d acc[4][4];
@@ -383,16 +393,30 @@ __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restr
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
   }
+  // C -= acc, one 16-row stripe at a time: all sixteen loads of a stripe are
+  // issued before any store (clamped addresses; masked stores)
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 4; ++a) {
+    double cv[16];
+    int64_t ix[16];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int R = r0 + wr + 16 * a + 4 * q + kq;
         const int Cc = c0 + wc + 16 * b + r16;
-        if (R < nmax && Cc < nmax && Cc <= R) A[(int64_t)R * ld + Cc] -= acc[a][b][q];
+        ix[b * 4 + q] = (int64_t)min(R, nmax - 1) * ld + min(Cc, nmax - 1);
+        cv[b * 4 + q] = A[ix[b * 4 + q]];
       }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int R = r0 + wr + 16 * a + 4 * q + kq;
+        const int Cc = c0 + wc + 16 * b + r16;
+        if (R < nmax && Cc < nmax && Cc <= R) A[ix[b * 4 + q]] = cv[b * 4 + q] - acc[a][b][q];
+      }
+  }
 }
 
 // y = M x or M^T x for a 64 x 64 tile M in global memory (row-major, leading
