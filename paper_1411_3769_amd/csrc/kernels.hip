@@ -786,102 +786,161 @@ __device__ inline int asm_row(int lane, int i) {
   return PR == 0 ? 4 * i + (lane >> 4) : 4 * (lane >> 4) + i;
 }
 
-// Small n (n^2 <= 128): one workgroup per (system, h, h2); R accumulated in
-// registers by 4 waves (tiles of 16 x 16), then staged in LDS for the gather.
-// Terms are staged KC at a time (4; 16 for BF16, one k-group of 4 per lane
-// quarter).
-constexpr int kPairMaxT = 16;
+// Small n (n^2 <= 128): one workgroup of 8 waves per (system, h, h2) pair,
+// the grid striding over pairs.  R = sum_k T_k (x) U_k (n^2 x n^2) is
+// accumulated in registers (16 x 16 MFMA tiles dealt round-robin to the
+// waves), then written out for the gather into Lambda.  Terms are staged
+// kPairKS at a time: every thread owns one entry index (and its transpose)
+// of T and U for a quarter of the stage's terms, fetches the next stage into
+// registers while the current one is multiplied, and writes it to LDS after
+// the barrier.  RL: R lives in LDS (overlaying the staging area), else in
+// this workgroup's slot of global scratch.  TPW: MFMA tiles per wave, at
+// least ceil(NT^2 / 8) for the batch's largest n; a wave's tiles past the
+// system's last are computed on a duplicate and dropped, so the tile loop is
+// branch-free.
+constexpr int kPairKS = 16;
+constexpr int kPairWaves = 8;
 
-template <int PR>
-__global__ void __launch_bounds__(256) k_assemble_pair(const AsmTile* __restrict__ tiles, int npt,
-                                                       const KTerm* __restrict__ terms,
-                                                       const SysDesc* __restrict__ sys,
-                                                       const int* __restrict__ flags,
-                                                       const double* __restrict__ arena,
-                                                       double* Lam, double* rscr, int rslot) {
+template <int PR, bool RL, int TPW>
+__device__ __forceinline__ void assemble_pair(const AsmTile* __restrict__ tiles, int npt,
+                                              const KTerm* __restrict__ terms,
+                                              const SysDesc* __restrict__ sys,
+                                              const int* __restrict__ flags,
+                                              const double* __restrict__ arena, double* Lam,
+                                              double* rscr, int rslot) {
   extern __shared__ double smem[];
   typedef AsmPrec<PR> AP;
   typedef typename AP::stage_t real;
   typedef typename AP::acc_t acc_t;
   constexpr int KC = AP::KC;
-  // R of the pair goes to this workgroup's slot of global scratch (it is
-  // read back through L2); LDS only stages the terms, so several workgroups
-  // share a CU.  The grid strides over the pairs.
-  double* R = rscr + (int64_t)blockIdx.x * rslot;
+  constexpr int KS = kPairKS;
+  constexpr int NQ = kPairWaves / 2;      // thread quarters of 128
+  constexpr int KH = KS / NQ;             // terms per thread and stage
+  constexpr int NTH = 64 * kPairWaves;
+  double* R = RL ? smem : rscr + (int64_t)blockIdx.x * rslot;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qtr = __builtin_amdgcn_readfirstlane(tid >> 7);
+  const int idx = tid & 127;
+  const int kq = lane >> 4, r16 = lane & 15;
+  const int kb = PR == 2 ? 4 * kq : kq;
   for (int tix = blockIdx.x; tix < npt; tix += gridDim.x) {
-  const AsmTile tl = tiles[tix];
-  if (!(flags[tl.sys] & F_ACTIVE)) continue;
-  if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) continue;
-  const SysDesc sd = sys[tl.sys];
-  const int n = sd.n, n2 = n * n;
-  const int NT = (n2 + 15) / 16, n2p = NT * 16, ntiles = NT * NT;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  real* sT = reinterpret_cast<real*>(smem);
-  real* sU = sT + KC * n2p;
-  acc_t acc[kPairMaxT];
+    const AsmTile tl = tiles[tix];
+    if (!(flags[tl.sys] & F_ACTIVE)) continue;
+    if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) continue;
+    const SysDesc sd = sys[tl.sys];
+    const int n = sd.n, n2 = n * n;
+    const int NT = (n2 + 15) / 16, n2p = NT * 16, ntiles = NT * NT;
+    const int kcnt = tl.kcnt;
+    const bool inb = idx < n2;
+    const int ii = inb ? idx : 0;
+    const int ib = ii / n, ic = ii - ib * n;
+    const int itr = ic * n + ib;
+    real* sT = reinterpret_cast<real*>(smem);
+    real* sU = sT + KS * n2p;
+    // raw entries and the term's coefficient (0 past the last term); the
+    // descriptors are read first and the entry loads are unconditional
+    // (clamped), so that a whole stage is in flight at once
+    double vT[KH], vU[KH], cf[KH];
+    auto fetch = [&](int k0) {
+      KTerm kt[KH];
 #pragma unroll
-  for (int t = 0; t < kPairMaxT; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  for (int k0 = 0; k0 < tl.kcnt; k0 += KC) {
+      for (int j = 0; j < KH; ++j) kt[j] = terms[tl.kbeg + min(k0 + qtr + NQ * j, kcnt - 1)];
+#pragma unroll
+      for (int j = 0; j < KH; ++j) {
+        vT[j] = arena[kt[j].offT + (kt[j].tT ? itr : ii)];
+        vU[j] = arena[kt[j].offU + (kt[j].tU ? itr : ii)];
+        cf[j] = k0 + qtr + NQ * j < kcnt ? kt[j].coef : 0.0;
+      }
+    };
+    acc_t acc[TPW];
+    int toff[TPW], uoff[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      acc[t] = acc_t{0, 0, 0, 0};
+      const int id = min(wave + kPairWaves * t, ntiles - 1);
+      const int ti = id / NT;
+      toff[t] = ti * 16;
+      uoff[t] = (id - ti * NT) * 16;
+    }
+    if (kcnt > 0) fetch(0);
+    for (int k0 = 0; k0 < kcnt; k0 += KS) {
+      __syncthreads();   // the previous stage (or pair) is no longer read
+      if (idx < n2p) {
+#pragma unroll
+        for (int j = 0; j < KH; ++j) {
+          const bool ok = inb && cf[j] != 0.0;
+          sT[(qtr + NQ * j) * n2p + idx] = AP::cvt(ok ? cf[j] * vT[j] : 0.0);
+          sU[(qtr + NQ * j) * n2p + idx] = AP::cvt(ok ? vU[j] : 0.0);
+        }
+      }
+      __syncthreads();
+      if (k0 + KS < kcnt) fetch(k0 + KS);
+#pragma unroll 1
+      for (int ks = 0; ks < KS; ks += KC) {
+        const real* bT = sT + (ks + kb) * n2p + r16;
+        const real* bU = sU + (ks + kb) * n2p + r16;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = asm_mfma<PR>(bT + toff[t], bU + uoff[t], n2p, acc[t]);
+      }
+    }
+    if (RL) __syncthreads();   // staging area becomes R
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      if (wave + kPairWaves * t < ntiles) {
+        const int col = uoff[t] + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = toff[t] + asm_row<PR>(lane, i);
+          if (row < n2 && col < n2) R[row * n2 + col] = (double)acc[t][i];
+        }
+      }
+    }
     __syncthreads();
-    for (int e = tid; e < KC * n2p; e += 256) {
-      const int kk = e / n2p, idx = e - kk * n2p;
-      double tv = 0.0, uv = 0.0;
-      if (k0 + kk < tl.kcnt && idx < n2) {
-        const KTerm kt = terms[tl.kbeg + k0 + kk];
-        const int b = idx / n, c = idx - b * n;
-        const int tr = c * n + b;
-        tv = kt.coef * arena[kt.offT + (kt.tT ? tr : idx)];
-        uv = arena[kt.offU + (kt.tU ? tr : idx)];
+    const int Nt = sd.Nt;
+    const int64_t ld = sd.Kpad;
+    double* Lr = Lam + sd.loff;
+#pragma unroll 2
+    for (int e = tid; e < Nt * Nt; e += NTH) {
+      const int b1 = e / Nt, b2 = e - b1 * Nt;
+      const int p = sd.basis[2 * b1], q = sd.basis[2 * b1 + 1];
+      const int r = sd.basis[2 * b2], s = sd.basis[2 * b2 + 1];
+      double v = R[(q * n + r) * n2 + s * n + p];
+      if (r != s) v += R[(q * n + s) * n2 + r * n + p];
+      if (p != q) {
+        v += R[(p * n + r) * n2 + s * n + q];
+        if (r != s) v += R[(p * n + s) * n2 + r * n + q];
       }
-      sT[e] = AP::cvt(tv);
-      sU[e] = AP::cvt(uv);
+      const int64_t row = (int64_t)tl.h * Nt + b1, col = (int64_t)tl.h2 * Nt + b2;
+      Lr[row * ld + col] = v;
+      if (tl.h != tl.h2) Lr[col * ld + row] = v;
     }
-    __syncthreads();
-    const int kq = lane >> 4, r16 = lane & 15;
-    const int kb = PR == 2 ? 4 * kq : kq;
-#pragma unroll
-    for (int t = 0; t < kPairMaxT; ++t) {
-      const int id = wave + 4 * t;
-      if (id < ntiles) {
-        const int ti = id / NT, tj = id - ti * NT;
-        acc[t] = asm_mfma<PR>(sT + kb * n2p + ti * 16 + r16, sU + kb * n2p + tj * 16 + r16, n2p,
-                              acc[t]);
-      }
-    }
+    if (!RL) __syncthreads();   // R is rewritten by the next pair
   }
-#pragma unroll
-  for (int t = 0; t < kPairMaxT; ++t) {
-    const int id = wave + 4 * t;
-    if (id < ntiles) {
-      const int ti = id / NT, tj = id - ti * NT;
-      const int col = tj * 16 + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = ti * 16 + asm_row<PR>(lane, i);
-        if (row < n2 && col < n2) R[row * n2 + col] = (double)acc[t][i];
-      }
-    }
-  }
-  __syncthreads();
-  const int Nt = sd.Nt;
-  const int64_t ld = sd.Kpad;
-  double* Lr = Lam + sd.loff;
-  for (int e = tid; e < Nt * Nt; e += 256) {
-    const int b1 = e / Nt, b2 = e - b1 * Nt;
-    const int p = sd.basis[2 * b1], q = sd.basis[2 * b1 + 1];
-    const int r = sd.basis[2 * b2], s = sd.basis[2 * b2 + 1];
-    double v = R[(q * n + r) * n2 + s * n + p];
-    if (r != s) v += R[(q * n + s) * n2 + r * n + p];
-    if (p != q) {
-      v += R[(p * n + r) * n2 + s * n + q];
-      if (r != s) v += R[(p * n + s) * n2 + r * n + q];
-    }
-    const int64_t row = (int64_t)tl.h * Nt + b1, col = (int64_t)tl.h2 * Nt + b2;
-    Lr[row * ld + col] = v;
-    if (tl.h != tl.h2) Lr[col * ld + row] = v;
-  }
-  __syncthreads();   // R is rewritten by the next pair
-  }
+}
+
+// FP64 / FP32 operands: two workgroups per CU (4 waves a SIMD: at most 128
+// registers a lane)
+template <int PR, bool RL, int TPW>
+__global__ void __launch_bounds__(512, 4) k_assemble_pair(const AsmTile* __restrict__ tiles, int npt,
+                                                          const KTerm* __restrict__ terms,
+                                                          const SysDesc* __restrict__ sys,
+                                                          const int* __restrict__ flags,
+                                                          const double* __restrict__ arena,
+                                                          double* Lam, double* rscr, int rslot) {
+  assemble_pair<PR, RL, TPW>(tiles, npt, terms, sys, flags, arena, Lam, rscr, rslot);
+}
+
+// BF16 operands (more registers for the k-groups of a stage) and n = 11
+// (TPW 8): one workgroup per CU
+template <int PR, bool RL, int TPW>
+__global__ void __launch_bounds__(512) k_assemble_pair_1wg(const AsmTile* __restrict__ tiles, int npt,
+                                                           const KTerm* __restrict__ terms,
+                                                           const SysDesc* __restrict__ sys,
+                                                           const int* __restrict__ flags,
+                                                           const double* __restrict__ arena,
+                                                           double* Lam, double* rscr, int rslot) {
+  assemble_pair<PR, RL, TPW>(tiles, npt, terms, sys, flags, arena, Lam, rscr, rslot);
 }
 
 // General n: one workgroup per Schur tile (row group (g1,g2) of h, column
@@ -1480,25 +1539,41 @@ namespace psdp {
 // prec = PSDP_PREC_FP32 / _BF16: systems flagged F_ASM32 take that
 // reduced-precision kernel, the rest the FP64 one (each kernel skips the
 // other's tiles); PSDP_PREC_FP64: the FP64 kernel only.
+template <int PR, bool RL, int TPW>
+static const void* pair_kernel() {
+  if constexpr (PR == 2 || TPW > 7) return (const void*)k_assemble_pair_1wg<PR, RL, TPW>;
+  else return (const void*)k_assemble_pair<PR, RL, TPW>;
+}
+
 template <int PR>
-static void pair_launch(hipStream_t st, int ntiles, size_t lds, const AsmTile* tiles,
+static void pair_launch(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                         const KTerm* terms, const SysDesc* sys, const int* flags,
-                        const double* arena, double* Lam, double* rscr, int rslot) {
+                        const double* arena, double* Lam, double* rscr) {
   const int grid = ntiles < kPairGrid ? ntiles : kPairGrid;
-  hipLaunchKernelGGL(k_assemble_pair<PR>, dim3(grid), dim3(256), lds, st, tiles, ntiles, terms, sys,
-                     flags, arena, Lam, rscr, rslot);
+  const int n2 = maxn * maxn, NT = (n2 + 15) / 16, n2p = NT * 16;
+  const size_t stage = (size_t)2 * kPairKS * n2p * sizeof(typename AsmPrec<PR>::stage_t);
+  const size_t rbytes = (size_t)n2 * n2 * 8;
+  // R fits LDS next to a second workgroup for n <= 10 (NT <= 7); n = 11
+  // (NT = 8) keeps it in global scratch
+  const void* f = NT <= 4   ? pair_kernel<PR, true, 2>()
+                  : NT <= 6 ? pair_kernel<PR, true, 5>()
+                  : NT <= 7 ? pair_kernel<PR, true, 7>()
+                            : pair_kernel<PR, false, 8>();
+  const size_t lds = NT <= 7 ? (rbytes > stage ? rbytes : stage) : stage;
+  set_lds(f, lds);
+  int rslot = n2 * n2;
+  void* args[] = {(void*)&tiles, (void*)&ntiles, (void*)&terms, (void*)&sys, (void*)&flags,
+                  (void*)&arena, (void*)&Lam, (void*)&rscr, (void*)&rslot};
+  (void)hipLaunchKernel(f, dim3(grid), dim3(64 * kPairWaves), args, lds, st);
 }
 
 void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                           const KTerm* terms, const SysDesc* sys, const int* flags,
                           const double* arena, double* Lam, int prec, double* rscr) {
   if (!ntiles) return;
-  const int n2 = maxn * maxn, n2p = (n2 + 15) / 16 * 16;
-  const size_t lds = (size_t)(8 * n2p) * 8;   // staging of the largest form (FP64 / BF16)
-  const int rslot = n2 * n2;
-  if (prec == PSDP_PREC_FP32) pair_launch<1>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam, rscr, rslot);
-  if (prec == PSDP_PREC_BF16) pair_launch<2>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam, rscr, rslot);
-  pair_launch<0>(st, ntiles, lds, tiles, terms, sys, flags, arena, Lam, rscr, rslot);
+  if (prec == PSDP_PREC_FP32) pair_launch<1>(st, ntiles, maxn, tiles, terms, sys, flags, arena, Lam, rscr);
+  if (prec == PSDP_PREC_BF16) pair_launch<2>(st, ntiles, maxn, tiles, terms, sys, flags, arena, Lam, rscr);
+  pair_launch<0>(st, ntiles, maxn, tiles, terms, sys, flags, arena, Lam, rscr);
 }
 
 void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const KTerm* terms,
