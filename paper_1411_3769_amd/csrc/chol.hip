@@ -150,9 +150,17 @@ __global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ s
   const double* App = Lam + sd.loff + (int64_t)p * kNB * ld + (int64_t)p * kNB;
   const int tid = threadIdx.x, w = tid >> 6;
   if (tid == 0) fl = 0;
-  for (int e = tid; e < kNB * kNB; e += 256) {
+  double ld16[kNB * kNB / 256];   // all loads in flight before the LDS stores
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
+    ld16[it] = App[(int64_t)(e >> 6) * ld + (e & 63)];
+  }
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
     const int r = e >> 6, cc = e & 63;
-    sA[r * kLD + cc] = App[(int64_t)r * ld + cc];
+    sA[r * kLD + cc] = ld16[it];
     sX[r * kLD + cc] = 0.0;
   }
   __syncthreads();
@@ -198,7 +206,9 @@ __global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ s
   }
   double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
   double* Dv = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
-  for (int e = tid; e < kNB * kNB; e += 256) {
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
     const int r = e >> 6, cc = e & 63;
     D[e] = cc <= r ? sA[r * kLD + cc] : 0.0;
     Dv[e] = cc <= r ? sX[r * kLD + cc] : 0.0;
@@ -225,10 +235,19 @@ __global__ void __launch_bounds__(256) k_chol_trsm(const SysDesc* __restrict__ s
   double* Ai = Lam + sd.loff + (int64_t)i * kNB * ld + (int64_t)p * kNB;
   const double* Xg = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kNB * kNB; e += 256) {
+  double la[kNB * kNB / 256], lx[kNB * kNB / 256];   // all loads in flight first
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
+    la[it] = Ai[(int64_t)(e >> 6) * ld + (e & 63)];
+    lx[it] = Xg[e];
+  }
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
     const int r = e >> 6, c = e & 63;
-    sA[r * LDT + c] = Ai[(int64_t)r * ld + c];
-    sX[r * LDT + c] = Xg[e];
+    sA[r * LDT + c] = la[it];
+    sX[r * LDT + c] = lx[it];
   }
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
@@ -277,10 +296,19 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
   const double* Lj = A + (int64_t)j * kNB * ld + (int64_t)p * kNB;
   double* C = A + (int64_t)i * kNB * ld + (int64_t)j * kNB;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int e = tid; e < kNB * kNB; e += 256) {
+  double la[kNB * kNB / 256], lb[kNB * kNB / 256];   // all loads in flight first
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
+    la[it] = Li[(int64_t)(e >> 6) * ld + (e & 63)];
+    lb[it] = Lj[(int64_t)(e >> 6) * ld + (e & 63)];
+  }
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
     const int r = e >> 6, c = e & 63;
-    sa[r * LDT + c] = Li[(int64_t)r * ld + c];
-    sb[r * LDT + c] = Lj[(int64_t)r * ld + c];
+    sa[r * LDT + c] = la[it];
+    sb[r * LDT + c] = lb[it];
   }
   __syncthreads();
   v4d acc[4];
@@ -496,59 +524,129 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const SysDesc* __restrict__ sy
   if (threadIdx.x < kNB) zs[i * kNB + threadIdx.x] -= sz[threadIdx.x];
 }
 
-// Whole solve L L^T x = rhs for systems with few tiles: one workgroup per
-// system sweeps all tile steps (no inter-workgroup dependency).  r is
-// scratch; x receives the solution.
-__global__ void __launch_bounds__(256) k_trsv_small(const SysDesc* __restrict__ sys,
-                                                    const int* __restrict__ flags,
-                                                    const int* __restrict__ small_ids,
-                                                    const double* __restrict__ Lam,
-                                                    const double* __restrict__ Linv,
-                                                    const double* __restrict__ rhs, double* r,
-                                                    double* x) {
-  __shared__ double sv[kNB], sw[kNB];
+// Whole solve L L^T x = rhs for systems with few tiles: one workgroup of 8
+// waves per system sweeps all tile steps (no inter-workgroup dependency); the
+// right-hand side and the iterate stay in LDS.  Each pass over a column panel
+// of L (the rows below its diagonal tile) gives every group of 16 lanes one
+// row at a time, each lane 4 consecutive entries: the forward sweep forms row
+// dots (r_i -= L_ip z_p, right-looking), the backward sweep column sums
+// (x_p = L_pp^{-T} (z_p - sum_i L_ip^T x_i), left-looking), so both read L
+// row-contiguously.  kSvR rows per group are loaded before any is used.
+constexpr int kSvT = 512;         // threads
+constexpr int kSvG = kSvT / 16;   // lane groups
+constexpr int kSvR = 8;           // rows in flight per group
+
+__device__ inline double gsum16(double v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+
+__device__ inline void ld4(const double* p, double* v) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+
+__global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__ sys,
+                                                     const int* __restrict__ flags,
+                                                     const int* __restrict__ small_ids,
+                                                     const double* __restrict__ Lam,
+                                                     const double* __restrict__ Linv,
+                                                     const double* __restrict__ rhs, double* x) {
+  __shared__ double sr[kNB * kSmallP];   // r, overwritten by z, then by x
+  __shared__ double sred[kSvG * kNB];    // per-group partial column sums
+  __shared__ double sv[kNB];
   const int s = small_ids[blockIdx.x];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
+  const int Kp = sd.Kpad, P = sd.P;
   const double* A = Lam + sd.loff;
   const double* Di = Linv + sd.dgoff;
-  double* rs = r + sd.voff;
-  double* xs = x + sd.voff;
-  const int tid = threadIdx.x;
-  for (int k = tid; k < sd.Kpad; k += 256) rs[k] = rhs[sd.voff + k];
+  const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
+  for (int k = tid; k < Kp; k += kSvT) sr[k] = rhs[sd.voff + k];
   __syncthreads();
-  // forward: z_p = L_pp^{-1} r_p, r_i -= L_ip z_p (z kept in r)
-  for (int p = 0; p < sd.P; ++p) {
-    if (tid < kNB) sv[tid] = rs[p * kNB + tid];
+  // forward: z_p = L_pp^{-1} r_p, then r_i -= L_ip z_p below
+  for (int p = 0; p < P; ++p) {
+    const double* D = Di + (int64_t)p * kNB * kNB;
+    double d0[4], d1[4], rp[4];
+    ld4(D + g * kNB + 4 * j, d0);
+    ld4(D + (g + kSvG) * kNB + 4 * j, d1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rp[q] = sr[p * kNB + 4 * j + q];
+    const double z0 = gsum16(d0[0] * rp[0] + d0[1] * rp[1] + d0[2] * rp[2] + d0[3] * rp[3]);
+    const double z1 = gsum16(d1[0] * rp[0] + d1[1] * rp[1] + d1[2] * rp[2] + d1[3] * rp[3]);
+    __syncthreads();   // r_p read by every group
+    if (j == 0) {
+      sr[p * kNB + g] = z0;
+      sr[p * kNB + g + kSvG] = z1;
+    }
     __syncthreads();
-    tile_mv64(Di + (int64_t)p * kNB * kNB, kNB, false, sv, sw);
-    __syncthreads();
-    if (tid < kNB) rs[p * kNB + tid] = sw[tid];
-    const int rows = (sd.P - p - 1) * kNB;
-    for (int rr = tid; rr < rows; rr += 256) {
-      const double* Lrow = A + (int64_t)((p + 1) * kNB + rr) * ld + (int64_t)p * kNB;
-      double acc = 0.0;
-      for (int c = 0; c < kNB; ++c) acc += Lrow[c] * sw[c];
-      rs[(p + 1) * kNB + rr] -= acc;
+    double zp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zp[q] = sr[p * kNB + 4 * j + q];
+    const double* Lp = A + (int64_t)p * kNB + 4 * j;
+    for (int ib = (p + 1) * kNB; ib < Kp; ib += kSvG * kSvR) {
+      double a[kSvR][4];
+#pragma unroll
+      for (int m = 0; m < kSvR; ++m) ld4(Lp + (int64_t)min(ib + g + kSvG * m, Kp - 1) * ld, a[m]);
+#pragma unroll
+      for (int m = 0; m < kSvR; ++m) {
+        const double t = gsum16(a[m][0] * zp[0] + a[m][1] * zp[1] + a[m][2] * zp[2] + a[m][3] * zp[3]);
+        const int i = ib + g + kSvG * m;
+        if (j == 0 && i < Kp) sr[i] -= t;
+      }
     }
     __syncthreads();
   }
-  // backward: x_p = L_pp^{-T} z_p, z_i -= L_pi^T x_p
-  for (int p = sd.P - 1; p >= 0; --p) {
-    if (tid < kNB) sv[tid] = rs[p * kNB + tid];
+  // backward: x_p = L_pp^{-T} (z_p - sum_{i below} L_ip^T x_i)
+  for (int p = P - 1; p >= 0; --p) {
+    const double* D = Di + (int64_t)p * kNB * kNB;
+    double d0[4], d1[4];
+    ld4(D + g * kNB + 4 * j, d0);
+    ld4(D + (g + kSvG) * kNB + 4 * j, d1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* Lp = A + (int64_t)p * kNB + 4 * j;
+    for (int ib = (p + 1) * kNB; ib < Kp; ib += kSvG * kSvR) {
+      double a[kSvR][4], xv[kSvR];
+#pragma unroll
+      for (int m = 0; m < kSvR; ++m) {
+        const int i = ib + g + kSvG * m;
+        ld4(Lp + (int64_t)min(i, Kp - 1) * ld, a[m]);
+        xv[m] = i < Kp ? sr[i] : 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < kSvR; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += a[m][q] * xv[m];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sred[g * kNB + 4 * j + q] = acc[q];
     __syncthreads();
-    tile_mv64(Di + (int64_t)p * kNB * kNB, kNB, true, sv, sw);
+    if (tid < kNB) {
+      double t = sr[p * kNB + tid];
+      for (int gg = 0; gg < kSvG; ++gg) t -= sred[gg * kNB + tid];
+      sv[tid] = t;
+    }
     __syncthreads();
-    if (tid < kNB) xs[p * kNB + tid] = sw[tid];
-    const int cols = p * kNB;
-    for (int cc = tid; cc < cols; cc += 256) {
-      double acc = 0.0;
-      for (int c = 0; c < kNB; ++c) acc += A[(int64_t)(p * kNB + c) * ld + cc] * sw[c];
-      rs[cc] -= acc;
+    const double v0 = sv[g], v1 = sv[g + kSvG];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sred[g * kNB + 4 * j + q] = d0[q] * v0 + d1[q] * v1;
+    __syncthreads();
+    if (tid < kNB) {
+      double t = 0.0;
+      for (int gg = 0; gg < kSvG; ++gg) t += sred[gg * kNB + tid];
+      sr[p * kNB + tid] = t;
     }
     __syncthreads();
   }
+  for (int k = tid; k < Kp; k += kSvT) x[sd.voff + k] = sr[k];
 }
 
 // launch wrappers --------------------------------------------------------------
@@ -593,10 +691,10 @@ void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const
 
 void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int* flags,
                        const int* small_ids, const double* Lam, const double* Linv,
-                       const double* rhs, double* r, double* x) {
+                       const double* rhs, double* x) {
   if (nsmall)
-    hipLaunchKernelGGL(k_trsv_small, dim3(nsmall), dim3(256), 0, st, sys, flags, small_ids, Lam, Linv,
-                       rhs, r, x);
+    hipLaunchKernelGGL(k_trsv_small, dim3(nsmall), dim3(kSvT), 0, st, sys, flags, small_ids, Lam, Linv,
+                       rhs, x);
 }
 
 }  // namespace psdp

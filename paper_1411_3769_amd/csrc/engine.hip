@@ -366,12 +366,14 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.ownK.push_back(B.ownK.back() + (int)p->K);
     B.maxK = std::max(B.maxK, (int)p->K);
   }
-  B.totblk = curblk;
-  B.totvec = curvec;
-  B.totlam = curlam;
-  B.totdg = curdg;
-  B.totP = curP;
-  B.totpre = curpre;
+  // every arena array starts on a 256-byte boundary (vector loads of 16 bytes
+  // and more need at least 16)
+  B.totblk = round_up(curblk, 32);
+  B.totvec = round_up(curvec, 32);
+  B.totlam = round_up(curlam, 32);
+  B.totdg = round_up(curdg, 32);
+  B.totP = round_up(curP, 32);
+  B.totpre = round_up(curpre, 32);
   B.nblk = (int)B.blk.size();
   B.npblk = (int)B.pblk.size();
   B.ndblk = (int)B.dblk.size();
@@ -685,8 +687,7 @@ static void op_factor(Batch& B, hipStream_t st) {
 
 static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
   const size_t m0 = B.prof.mark();
-  launch_trsv_small(st, (int)B.small_ids.size(), B.d_sys, B.d_flags, B.d_small, B.Lam, B.Linv, rhs,
-                    B.r, x);
+  launch_trsv_small(st, (int)B.small_ids.size(), B.d_sys, B.d_flags, B.d_small, B.Lam, B.Linv, rhs, x);
   if (B.small_ids.size() < (size_t)B.S) {
     PSDP_HIP(hipMemcpyAsync(B.r, rhs, B.totvec * 8, hipMemcpyDeviceToDevice, st));
     for (int p = 0; p < B.maxP; ++p) {

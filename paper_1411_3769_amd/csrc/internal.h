@@ -170,7 +170,7 @@ void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const
                      int cnt, int total, int p);
 void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int* flags,
                        const int* small_ids, const double* Lam, const double* Linv,
-                       const double* rhs, double* r, double* x);
+                       const double* rhs, double* x);
 constexpr int kSmallN = 16;   // blocks up to this order take the packed small-block kernels
 constexpr int kSmallP = 32;   // systems with at most this many Schur tiles solve in one launch
 
