@@ -441,14 +441,18 @@ __global__ void k_B_reduce(const SysDesc* __restrict__ sys, const int* __restric
   const int h = k / sd.Nt, b = k % sd.Nt;
   const int p = sd.basis[2 * b], q = sd.basis[2 * b + 1];
   const int e1 = p * n + q, e2 = q * n + p;
+  // loads of a term do not wait on its coefficient, so unrolled iterations
+  // overlap; a zero coefficient still drops the term
   double acc = 0.0;
+#pragma unroll 4
   for (int j = 0; j < sd.L; ++j) {
     const double bt = sd.betaf[h * sd.L + j];
-    if (bt == 0.0) continue;
     const double* Wj = W + blks[sd.blk0 + j].off;
-    acc += bt * (p == q ? Wj[e1] : Wj[e1] + Wj[e2]);
+    const double w = p == q ? Wj[e1] : Wj[e1] + Wj[e2];
+    acc += bt != 0.0 ? bt * w : 0.0;
   }
   double dsum = 0.0;
+#pragma unroll 4
   for (int c = sd.hm_by_h[h]; c < sd.hm_by_h[h + 1]; ++c) {
     const double* Y = arena + pairs[sd.hm_ids[c]].offY;
     dsum += (p == q ? Y[e1] : Y[e1] + Y[e2]);
