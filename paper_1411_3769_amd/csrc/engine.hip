@@ -484,8 +484,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
         B.fwdL.add(s, P - pstep);
         B.bwdL.add(s, pstep + 1);
       }
-      // narrow update: columns p+1 .. end of the super-panel
-      const int se = std::min(P - 1, (pstep / kSW) * kSW + kSW - 1);
+      // narrow update: columns p+1 .. end of the super-panel; a super-panel
+      // followed by fewer than kSW panels absorbs them (their wide update
+      // would be one long, nearly empty launch)
+      int se = (pstep / kSW) * kSW + kSW - 1;
+      if (P - 1 - se < kSW) se = P - 1;
       int nn = 0;
       for (int j = pstep + 1; j <= se; ++j) nn += P - j;
       if (nn > 0) B.upd.add(s, nn);
