@@ -150,40 +150,15 @@ __device__ inline void wave_potri16(double* B, double* Xb, int* fail) {
   if (bad && lane == 0) *fail = 1;
 }
 
-// Diagonal step p: one workgroup per system factors the 64 x 64 tile A_pp
-// and inverts the factor, storing L_pp and L_pp^{-1}.
-__global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ sys, int* flags,
-                                                   const double* __restrict__ Lam, double* Ldiag,
-                                                   double* Linv, const int* __restrict__ st_sys,
-                                                   int p) {
-  __shared__ double sA[kNB * kLD];
-  __shared__ double sX[kNB * kLD];
-  __shared__ double sT[4 * kBL * kLD];
-  __shared__ int fl;
-  const int s = st_sys[blockIdx.x];
-  if (!(flags[s] & F_CHOLSEL)) return;
-  const SysDesc sd = sys[s];
-  const int64_t ld = sd.Kpad;
-  const double* App = Lam + sd.loff + (int64_t)p * kNB * ld + (int64_t)p * kNB;
-  const int tid = threadIdx.x, w = tid >> 6;
-  if (tid == 0) fl = 0;
-  double ld16[kNB * kNB / 256];   // all loads in flight before the LDS stores
-#pragma unroll
-  for (int it = 0; it < kNB * kNB / 256; ++it) {
-    const int e = tid + 256 * it;
-    ld16[it] = App[(int64_t)(e >> 6) * ld + (e & 63)];
-  }
-#pragma unroll
-  for (int it = 0; it < kNB * kNB / 256; ++it) {
-    const int e = tid + 256 * it;
-    const int r = e >> 6, cc = e & 63;
-    sA[r * kLD + cc] = ld16[it];
-    sX[r * kLD + cc] = 0.0;
-  }
-  __syncthreads();
+// Factorisation and inverse of the 64 x 64 tile in sA (lower triangle read)
+// by the 4 waves of a workgroup: on return sA holds L_pp (lower triangle) and
+// sX (zero on entry) holds L_pp^{-1}.  The strictly upper blocks of sA serve
+// as scratch for the inverse.  Non-positive pivots set *fl.
+__device__ void diag_tile(double* sA, double* sX, int* fl) {
+  const int w = threadIdx.x >> 6;
   auto blk = [](double* M, int i, int j) { return M + (kBL * i) * kLD + kBL * j; };
   for (int kb = 0; kb < 4; ++kb) {
-    if (w == 0) wave_potri16(blk(sA, kb, kb), blk(sX, kb, kb), &fl);
+    if (w == 0) wave_potri16(blk(sA, kb, kb), blk(sX, kb, kb), fl);
     __syncthreads();
     // L_ik = A_ik X_kk^T for the blocks below (wave w takes i = kb + w); the
     // result overwrites A_ik after a barrier
@@ -206,23 +181,28 @@ __global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ s
   }
   // off-diagonal blocks of X, by distance d = i - j
   for (int dd = 1; dd < 4; ++dd) {
-    // T_i = sum_{k=j}^{i-1} L_ik X_kj, wave w takes j = w
+    // T = sum_{k=j}^{i-1} L_ik X_kj, wave w takes j = w; T goes to the upper
+    // block (0, w + 1) of sA
     const int j = w, i = w + dd;
+    double* T = blk(sA, 0, w + 1);
     if (i < 4) {
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
       for (int k = j; k < i; ++k) acc = mm16(blk(sA, i, k), blk(sX, k, j), false, acc);
-      st16(sT + w * kBL * kLD, acc, 1.0, false);
+      st16(T, acc, 1.0, false);
     }
     __syncthreads();
     if (i < 4) {
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      acc = mm16(blk(sX, i, i), sT + w * kBL * kLD, false, acc);
+      acc = mm16(blk(sX, i, i), T, false, acc);
       st16(blk(sX, i, j), acc, -1.0, false);
     }
     __syncthreads();
   }
-  double* D = Ldiag + sd.dgoff + (int64_t)p * kNB * kNB;
-  double* Dv = Linv + sd.dgoff + (int64_t)p * kNB * kNB;
+}
+
+// store the lower triangles of sA (L_pp) and sX (L_pp^{-1}) as dense tiles
+__device__ inline void store_diag(const double* sA, const double* sX, double* D, double* Dv) {
+  const int tid = threadIdx.x;
 #pragma unroll
   for (int it = 0; it < kNB * kNB / 256; ++it) {
     const int e = tid + 256 * it;
@@ -230,6 +210,41 @@ __global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ s
     D[e] = cc <= r ? sA[r * kLD + cc] : 0.0;
     Dv[e] = cc <= r ? sX[r * kLD + cc] : 0.0;
   }
+}
+
+// Diagonal step p: one workgroup per system factors the 64 x 64 tile A_pp
+// and inverts the factor, storing L_pp and L_pp^{-1}.  (Inside a
+// super-panel the narrow update of step p - 1 does this instead.)
+__global__ void __launch_bounds__(256) k_chol_diag(const SysDesc* __restrict__ sys, int* flags,
+                                                   const double* __restrict__ Lam, double* Ldiag,
+                                                   double* Linv, const int* __restrict__ st_sys,
+                                                   int p) {
+  __shared__ double sA[kNB * kLD];
+  __shared__ double sX[kNB * kLD];
+  __shared__ int fl;
+  const int s = st_sys[blockIdx.x];
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  const double* App = Lam + sd.loff + (int64_t)p * kNB * ld + (int64_t)p * kNB;
+  const int tid = threadIdx.x;
+  if (tid == 0) fl = 0;
+  double ld16[kNB * kNB / 256];   // all loads in flight before the LDS stores
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
+    ld16[it] = App[(int64_t)(e >> 6) * ld + (e & 63)];
+  }
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
+    const int r = e >> 6, cc = e & 63;
+    sA[r * kLD + cc] = ld16[it];
+    sX[r * kLD + cc] = 0.0;
+  }
+  __syncthreads();
+  diag_tile(sA, sX, &fl);
+  store_diag(sA, sX, Ldiag + sd.dgoff + (int64_t)p * kNB * kNB, Linv + sd.dgoff + (int64_t)p * kNB * kNB);
   if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
 }
 
@@ -289,16 +304,34 @@ __global__ void __launch_bounds__(256) k_chol_trsm(const SysDesc* __restrict__ s
 // Narrow update (inside the super-panel of p): A_ij -= L_ip L_jp^T for the
 // columns p < j <= end of the super-panel and every row i >= j, on FP64 MFMA: wave w owns
 // rows 16w..16w+15 and the four 16-column tiles; both panels staged in LDS.
+// The workgroup of tile (p+1, p+1) then factors and inverts it (the diagonal
+// step of p + 1), overlapped with the other tiles' updates.
 __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__ sys,
-                                                     const int* __restrict__ flags, double* Lam,
-                                                     const int* __restrict__ st_sys,
+                                                     int* flags, double* Lam, double* Ldiag,
+                                                     double* Linv, const int* __restrict__ st_sys,
                                                      const int* __restrict__ st_pre, int cnt,
                                                      int p) {
   __shared__ double sa[kNB * LDT];
   __shared__ double sb[kNB * LDT];
-  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  __shared__ int fl;
+  // the first cnt workgroups take tile (p+1, p+1) of each system, so that the
+  // diagonal steps start first; the rest follow system by system
+  int si, t;
+  if ((int)blockIdx.x < cnt) {
+    si = blockIdx.x;
+    t = 0;
+  } else {
+    const int b = blockIdx.x - cnt;   // last si with st_pre[si] - si <= b
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (st_pre[mid] - mid <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    si = lo;
+    t = 1 + b - (st_pre[si] - si);
+  }
   const int s = st_sys[si];
-  const int t = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_CHOLSEL)) return;
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
@@ -355,6 +388,22 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
       if (i != j || cc <= rr) C[(int64_t)rr * ld + cc] = cv[u * 4 + q] - acc[u][q];
     }
   }
+  if (t != 0) return;   // tile (p+1, p+1): the next diagonal step
+  if (tid == 0) fl = 0;
+  __syncthreads();      // the operand panels are no longer read
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sa[(16 * w + 4 * q + kq) * LDT + 16 * u + r16] = cv[u * 4 + q] - acc[u][q];
+#pragma unroll
+  for (int it = 0; it < kNB * kNB / 256; ++it) {
+    const int e = tid + 256 * it;
+    sb[(e >> 6) * LDT + (e & 63)] = 0.0;
+  }
+  __syncthreads();
+  diag_tile(sa, sb, &fl);
+  store_diag(sa, sb, Ldiag + sd.dgoff + (int64_t)j * kNB * kNB, Linv + sd.dgoff + (int64_t)j * kNB * kNB);
+  if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
 }
 
 // Wide update at the end of a super-panel of kSW panels (p = its last
@@ -682,9 +731,10 @@ void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, doub
                        cnt, p);
 }
 
-void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
-                        const int* ssys, const int* spre, int cnt, int total, int p) {
-  hipLaunchKernelGGL(k_chol_update, dim3(total), dim3(256), 0, st, sys, flags, Lam, ssys, spre, cnt, p);
+void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
+                        double* Linv, const int* ssys, const int* spre, int cnt, int total, int p) {
+  hipLaunchKernelGGL(k_chol_update, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, ssys,
+                     spre, cnt, p);
 }
 
 void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,

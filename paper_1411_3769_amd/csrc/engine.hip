@@ -474,21 +474,27 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.fwdL.add_step();
     B.bwdL.add_step();
 
+    // last column of the narrow update of step q (super-panel end; a
+    // super-panel followed by fewer than kSW panels absorbs them, since
+    // their wide update would be one long, nearly empty launch)
+    auto sp_end = [](int P, int q) {
+      const int se = (q / kSW) * kSW + kSW - 1;
+      return P - 1 - se < kSW ? P - 1 : se;
+    };
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (P <= pstep) continue;
-      B.pan.add(s, 1);
+      // after a narrow update of step pstep - 1 its workgroup of tile
+      // (pstep, pstep) has already factored the diagonal tile
+      if (pstep == 0 || sp_end(P, pstep - 1) < pstep) B.pan.add(s, 1);
       const int T = P - pstep - 1;
       if (T > 0) B.trs.add(s, T);
       if (!(ch->small[s] && P <= kSmallP)) {
         B.fwdL.add(s, P - pstep);
         B.bwdL.add(s, pstep + 1);
       }
-      // narrow update: columns p+1 .. end of the super-panel; a super-panel
-      // followed by fewer than kSW panels absorbs them (their wide update
-      // would be one long, nearly empty launch)
-      int se = (pstep / kSW) * kSW + kSW - 1;
-      if (P - 1 - se < kSW) se = P - 1;
+      // narrow update: columns p+1 .. end of the super-panel
+      const int se = sp_end(P, pstep);
       int nn = 0;
       for (int j = pstep + 1; j <= se; ++j) nn += P - j;
       if (nn > 0) B.upd.add(s, nn);
@@ -676,7 +682,7 @@ static void op_factor(Batch& B, hipStream_t st) {
     B.prof.add(PSDP_PROF_CHOL_PANEL, m0, m1);
     if (B.upd.tot[p] > 0) {
       const int g = B.upd.first[p];
-      launch_chol_update(st, B.d_sys, B.d_flags, B.Lam, B.d_upd_sys + g, B.d_upd_pre + g,
+      launch_chol_update(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.d_upd_sys + g, B.d_upd_pre + g,
                          B.upd.cnt[p], B.upd.tot[p], p);
     }
     if (B.wide.tot[p] > 0) {

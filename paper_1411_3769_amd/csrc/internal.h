@@ -160,8 +160,8 @@ void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, doub
                       int p);
 void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
                              const int* ssys, const int* spre, int cnt, int total, int p);
-void launch_chol_update(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
-                        const int* ssys, const int* spre, int cnt, int total, int p);
+void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
+                        double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
                      const double* Linv, double* r, double* z, const int* ssys, const int* spre,
                      int cnt, int total, int p);
