@@ -1088,10 +1088,13 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
 
 // ---------------------------------------------------------------------------
 // Small blocks (n <= 16): G = 256 / nmax^2 products per workgroup, one output
-// entry per thread, operands read directly (they stay in cache).
+// entry per thread.  Every thread first stages one entry of each operand in
+// LDS (so each operand element is read from memory once, not n times), then
+// forms its dot products from LDS.  Items whose order exceeds nmax belong to
+// the general kernels and are skipped (each block takes the same kernel
+// whatever the batch holds).
 // ---------------------------------------------------------------------------
-__device__ inline double dot_n(int n, int i, int j, const double* __restrict__ A, int tA,
-                               const double* __restrict__ B, int tB) {
+__device__ inline double dot_n(int n, int i, int j, const double* A, int tA, const double* B, int tB) {
   double acc = 0.0;
   for (int k = 0; k < n; ++k) {
     const double a = tA ? A[k * n + i] : A[i * n + k];
@@ -1101,74 +1104,136 @@ __device__ inline double dot_n(int n, int i, int j, const double* __restrict__ A
   return acc;
 }
 
-// Items whose order exceeds nmax belong to the general kernels and are
-// skipped (each block takes the same kernel whatever the batch holds).
-#define SMALL_ITEM(count)                                   \
-  const int per_ = nmax * nmax;                             \
-  const int item = blockIdx.x * G + (int)threadIdx.x / per_; \
-  const int e_ = (int)threadIdx.x % per_;                   \
-  if ((int)threadIdx.x >= G * per_ || item >= (count)) return;
+// this thread's item (li within the workgroup) and entry e
+struct SmallSlot {
+  int li, item, e, per;
+  bool ok;
+};
+
+__device__ inline SmallSlot small_slot(int nmax, int G, int count) {
+  SmallSlot t;
+  t.per = nmax * nmax;
+  t.li = (int)threadIdx.x / t.per;
+  t.item = blockIdx.x * G + t.li;
+  t.e = (int)threadIdx.x - t.li * t.per;
+  t.ok = (int)threadIdx.x < G * t.per && t.item < count;
+  return t;
+}
 
 __global__ void __launch_bounds__(256) k_gemm_blocks_small(
     int nblk, int nmax, int G, const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
     const double* __restrict__ sc, const double* A, int tA, const double* B, int tB, double* C,
     double alpha, int aslot, const double* D, double beta, int bslot) {
-  SMALL_ITEM(nblk);
-  const BlkDesc bd = blks[item];
-  if (!(flags[bd.sys] & F_ACTIVE)) return;
-  if (bd.n > nmax) return;
-  const int n = bd.n;
-  if (e_ >= n * n) return;
-  const int i = e_ / n, j = e_ % n;
-  double a = alpha, c = beta;
+  __shared__ double sA[256], sB[256];
+  SmallSlot t = small_slot(nmax, G, nblk);
+  BlkDesc bd{};
+  if (t.ok) {
+    bd = blks[t.item];
+    t.ok = (flags[bd.sys] & F_ACTIVE) && bd.n <= nmax && t.e < bd.n * bd.n;
+  }
+  double* pa = sA + t.li * t.per;
+  double* pb = sB + t.li * t.per;
+  if (t.ok) {
+    pa[t.e] = A[bd.off + t.e];
+    pb[t.e] = B[bd.off + t.e];
+  }
+  __syncthreads();
+  if (!t.ok) return;
+  const int n = bd.n, i = t.e / n, j = t.e - i * n;
+  double a = alpha, cc = beta;
   if (aslot >= 0) a *= sc[bd.sys * kNSC + aslot];
-  if (bslot >= 0) c *= sc[bd.sys * kNSC + bslot];
-  double v = a * dot_n(n, i, j, A + bd.off, tA, B + bd.off, tB);
-  if (D) v += c * D[bd.off + e_];
-  C[bd.off + e_] = v;
+  if (bslot >= 0) cc *= sc[bd.sys * kNSC + bslot];
+  double v = a * dot_n(n, i, j, pa, tA, pb, tB);
+  if (D) v += cc * D[bd.off + t.e];
+  C[bd.off + t.e] = v;
 }
 
+// -sum_h (P_h H_{m,h} + (P_h H_{m,h})^T) for each d-block m; the workgroup
+// steps through the longest h list of its items, the next (P_h, H_{m,h}) pair
+// fetched into registers while the current one is multiplied
 __global__ void __launch_bounds__(256) k_BT_dblk_small(int nd, int nmax, int G,
                                                        const BlkDesc* __restrict__ dblks,
                                                        const SysDesc* __restrict__ sys,
                                                        const int* __restrict__ flags,
                                                        const double* __restrict__ Pm, double* out) {
-  SMALL_ITEM(nd);
-  const BlkDesc bd = dblks[item];
-  if (!(flags[bd.sys] & F_ACTIVE)) return;
-  if (bd.n > nmax) return;
-  const SysDesc sd = sys[bd.sys];
-  const int n = bd.n, nn = n * n;
-  if (e_ >= nn) return;
-  const int i = e_ / n, j = e_ % n, m = bd.j - sd.L;
-  double acc = 0.0;
-  for (int c = sd.h_by_m[m]; c < sd.h_by_m[m + 1]; ++c) {
-    const int h = sd.h_list[c];
-    const double* Hm = sd.H + ((int64_t)m * sd.L0 + h) * nn;
-    const double* Ph = Pm + sd.poff + (int64_t)h * nn;
-    acc += dot_n(n, i, j, Ph, 0, Hm, 0) + dot_n(n, j, i, Ph, 0, Hm, 0);
+  __shared__ double sP[256], sH[256];
+  __shared__ int smax;
+  SmallSlot t = small_slot(nmax, G, nd);
+  BlkDesc bd{};
+  SysDesc sd{};
+  int c0 = 0, cnt = 0, m = 0;
+  if (t.ok) {
+    bd = dblks[t.item];
+    t.ok = (flags[bd.sys] & F_ACTIVE) && bd.n <= nmax;
   }
-  out[bd.off + e_] = -acc;
+  if (t.ok) {
+    sd = sys[bd.sys];
+    m = bd.j - sd.L;
+    c0 = sd.h_by_m[m];
+    cnt = sd.h_by_m[m + 1] - c0;
+  }
+  if (threadIdx.x == 0) smax = 0;
+  __syncthreads();
+  if (t.ok && t.e == 0) atomicMax(&smax, cnt);
+  const int n = bd.n, nn = n * n;
+  const bool act = t.ok && t.e < nn;
+  const int i = act ? t.e / n : 0, j = act ? t.e - i * n : 0;
+  double* pp = sP + t.li * t.per;
+  double* ph = sH + t.li * t.per;
+  double vp = 0.0, vh = 0.0;
+  auto fetch = [&](int c) {
+    if (act && c < cnt) {
+      const int h = sd.h_list[c0 + c];
+      vp = Pm[sd.poff + (int64_t)h * nn + t.e];
+      vh = sd.H[((int64_t)m * sd.L0 + h) * nn + t.e];
+    }
+  };
+  fetch(0);
+  __syncthreads();
+  const int cmax = smax;
+  double acc = 0.0;
+  for (int c = 0; c < cmax; ++c) {
+    if (act && c < cnt) {
+      pp[t.e] = vp;
+      ph[t.e] = vh;
+    }
+    __syncthreads();
+    fetch(c + 1);
+    if (act && c < cnt) acc += dot_n(n, i, j, pp, 0, ph, 0) + dot_n(n, j, i, pp, 0, ph, 0);
+    __syncthreads();
+  }
+  if (act) out[bd.off + t.e] = -acc;
 }
 
+// Y_{m,h} = H_{m,h} W_m
 __global__ void __launch_bounds__(256) k_B_Y_small(int np, int nmax, int G,
                                                    const HMPair* __restrict__ pairs,
                                                    const SysDesc* __restrict__ sys,
                                                    const int* __restrict__ flags,
                                                    const double* __restrict__ W, double* arena,
                                                    const BlkDesc* __restrict__ blks) {
-  SMALL_ITEM(np);
-  const HMPair pr = pairs[item];
-  if (!(flags[pr.sys] & F_ACTIVE)) return;
-  if (pr.n > nmax) return;
-  const SysDesc sd = sys[pr.sys];
+  __shared__ double sH[256], sW[256];
+  SmallSlot t = small_slot(nmax, G, np);
+  HMPair pr{};
+  if (t.ok) {
+    pr = pairs[t.item];
+    t.ok = (flags[pr.sys] & F_ACTIVE) && pr.n <= nmax && t.e < pr.n * pr.n;
+  }
   const int n = pr.n, nn = n * n;
-  if (e_ >= nn) return;
-  const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
-  const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
-  arena[pr.offY + e_] = dot_n(n, e_ / n, e_ % n, Hm, 0, W + bd.off, 0);
+  double* ph = sH + t.li * t.per;
+  double* pw = sW + t.li * t.per;
+  if (t.ok) {
+    const SysDesc* sd = sys + pr.sys;
+    const BlkDesc bd = blks[sd->blk0 + sd->L + pr.m];
+    ph[t.e] = sd->H[((int64_t)pr.m * sd->L0 + pr.h) * nn + t.e];
+    pw[t.e] = W[bd.off + t.e];
+  }
+  __syncthreads();
+  if (!t.ok) return;
+  arena[pr.offY + t.e] = dot_n(n, t.e / n, t.e % n, ph, 0, pw, 0);
 }
 
+// A1 = Z^-1_m H_{m,h}^T, A2 = X_m H_{m,h}^T
 __global__ void __launch_bounds__(256) k_pre12_small(int np, int nmax, int G,
                                                      const HMPair* __restrict__ pairs,
                                                      const SysDesc* __restrict__ sys,
@@ -1177,36 +1242,59 @@ __global__ void __launch_bounds__(256) k_pre12_small(int np, int nmax, int G,
                                                      const double* __restrict__ X, double* arena,
                                                      const BlkDesc* __restrict__ blks,
                                                      const int64_t* __restrict__ offA1) {
-  SMALL_ITEM(np);
-  const HMPair pr = pairs[item];
-  if (!(flags[pr.sys] & F_ACTIVE)) return;
-  if (pr.n > nmax) return;
-  const SysDesc sd = sys[pr.sys];
+  __shared__ double sZ[256], sX[256], sH[256];
+  SmallSlot t = small_slot(nmax, G, np);
+  HMPair pr{};
+  if (t.ok) {
+    pr = pairs[t.item];
+    t.ok = (flags[pr.sys] & F_ACTIVE) && pr.n <= nmax && t.e < pr.n * pr.n;
+  }
   const int n = pr.n, nn = n * n;
-  if (e_ >= nn) return;
-  const int i = e_ / n, j = e_ % n;
-  const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
-  const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
-  arena[offA1[item] + e_] = dot_n(n, i, j, Zi + bd.off, 0, Hm, 1);
-  arena[pr.offA2 + e_] = dot_n(n, i, j, X + bd.off, 0, Hm, 1);
+  double* pz = sZ + t.li * t.per;
+  double* px = sX + t.li * t.per;
+  double* ph = sH + t.li * t.per;
+  if (t.ok) {
+    const SysDesc* sd = sys + pr.sys;
+    const BlkDesc bd = blks[sd->blk0 + sd->L + pr.m];
+    pz[t.e] = Zi[bd.off + t.e];
+    px[t.e] = X[bd.off + t.e];
+    ph[t.e] = sd->H[((int64_t)pr.m * sd->L0 + pr.h) * nn + t.e];
+  }
+  __syncthreads();
+  if (!t.ok) return;
+  const int i = t.e / n, j = t.e - i * n;
+  arena[offA1[t.item] + t.e] = dot_n(n, i, j, pz, 0, ph, 1);
+  arena[pr.offA2 + t.e] = dot_n(n, i, j, px, 0, ph, 1);
 }
 
+// A3 = H_{m,h} A2[m][h2], A4 = H_{m,h} A1[m][h2]
 __global__ void __launch_bounds__(256) k_pre34_small(int nq, int nmax, int G,
                                                      const HM2* __restrict__ q,
                                                      const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags,
                                                      double* arena) {
-  SMALL_ITEM(nq);
-  const HM2 pr = q[item];
-  if (!(flags[pr.sys] & F_ACTIVE)) return;
-  if (pr.n > nmax) return;
-  const SysDesc sd = sys[pr.sys];
+  __shared__ double sH[256], s2[256], s1[256];
+  SmallSlot t = small_slot(nmax, G, nq);
+  HM2 pr{};
+  if (t.ok) {
+    pr = q[t.item];
+    t.ok = (flags[pr.sys] & F_ACTIVE) && pr.n <= nmax && t.e < pr.n * pr.n;
+  }
   const int n = pr.n, nn = n * n;
-  if (e_ >= nn) return;
-  const int i = e_ / n, j = e_ % n;
-  const double* Hh = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
-  arena[pr.offA3 + e_] = dot_n(n, i, j, Hh, 0, arena + pr.srcA2, 0);
-  arena[pr.offA4 + e_] = dot_n(n, i, j, Hh, 0, arena + pr.srcA1, 0);
+  double* ph = sH + t.li * t.per;
+  double* p2 = s2 + t.li * t.per;
+  double* p1 = s1 + t.li * t.per;
+  if (t.ok) {
+    const SysDesc* sd = sys + pr.sys;
+    ph[t.e] = sd->H[((int64_t)pr.m * sd->L0 + pr.h) * nn + t.e];
+    p2[t.e] = arena[pr.srcA2 + t.e];
+    p1[t.e] = arena[pr.srcA1 + t.e];
+  }
+  __syncthreads();
+  if (!t.ok) return;
+  const int i = t.e / n, j = t.e - i * n;
+  arena[pr.offA3 + t.e] = dot_n(n, i, j, ph, 0, p2, 0);
+  arena[pr.offA4 + t.e] = dot_n(n, i, j, ph, 0, p1, 0);
 }
 
 // x = a * x + b * y over the first K entries of every active system
