@@ -69,23 +69,6 @@ __device__ inline void st16(double* D, v4d acc, double sign, bool add) {
   }
 }
 
-// 1/sqrt(d) for a positive finite d: the hardware estimate refined by two
-// Newton steps for the inverse square root, y += y (1 - d y^2) / 2.
-__device__ inline double rsqrt_nr(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
-  return y;
-}
-
-// value of v in lane l (l uniform) for every lane
-__device__ inline double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Wave-level factorisation and inverse of the 16 x 16 block at B (leading
 // dimension kLD) by the 64 lanes of one wave: lane (r, g) = (l % 16, l / 16)
 // holds row r, columns 4g..4g+3.  On return B holds L (zeros above the

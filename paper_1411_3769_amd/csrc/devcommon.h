@@ -71,6 +71,50 @@ __device__ inline void wg_gemm(int n, const double* __restrict__ A, int tA,
   }
 }
 
+// 1/sqrt(d) for a positive finite d: the hardware estimate refined by two
+// Newton steps for the inverse square root, y += y (1 - d y^2) / 2.
+__device__ inline double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+  return y;
+}
+
+// value of v in lane l (l uniform) for every lane
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Whether the Cholesky factorisation of the symmetric 16 x 16 matrix held by
+// one wave succeeds (every pivot positive and finite).  Lane (r, g) =
+// (l % 16, l / 16) holds row r, columns 4g .. 4g + 3 in v (only the lower
+// triangle is read; v is overwritten); the result is the same on every lane.
+__device__ inline bool wave_chol_ok16(double* v) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int kg = k >> 2, kj = k & 3;
+    double d = readlane_d(v[kj], k + 16 * kg);
+    const bool b = !(d > 0.0) || !isfinite(d);
+    bad = bad || b;
+    d = b ? 1.0 : d;
+    const double rs = rsqrt_nr(d);
+    // every lane takes part in every shuffle
+    const double lrk = __shfl(v[kj], r + 16 * kg) * rs;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = 4 * g + j;
+      const double lck = __shfl(v[kj], cc + 16 * kg) * rs;
+      if (cc > k && r >= cc) v[j] -= lrk * lck;
+    }
+  }
+  return !bad;
+}
+
 // In-place lower Cholesky of the n x n matrix in LDS (leading dimension ld).
 // Reads only the lower triangle.  A pivot that is not a positive finite
 // number marks failure (*fail = 1) and is replaced by 1 so the sweep stays

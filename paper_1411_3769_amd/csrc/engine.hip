@@ -1021,13 +1021,13 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     // step lengths and update
     { const size_t pm_ = B.prof.mark();
-    launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
+    launch_ladder(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
       B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
     launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TP, B.d_sc);
       B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
-    launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.dZ, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
+    launch_ladder(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.Z, B.dZ, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
       B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
     launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TD, B.d_sc);
@@ -1532,7 +1532,7 @@ int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opt
   PSDP_HIP(hipMemcpyAsync(B.dX, dV, nb * nn * 8, hipMemcpyHostToDevice, st));
   const int one = F_ACTIVE;
   PSDP_HIP(hipMemcpyAsync(B.d_flags, &one, 4, hipMemcpyHostToDevice, st));
-  launch_ladder(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac,
+  launch_ladder(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac,
                 o.ladder_len, B.d_kout);
   launch_ladder_step(st, B.d_sys, 1, B.d_flags, B.d_kout, o.ladder_rho, S_TP, B.d_sc);
   PSDP_HIP(hipGetLastError());

@@ -7,8 +7,9 @@ namespace psdp {
 
 void launch_cholinv(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, int* flags,
                     const double* Z, double* Zi);
-void launch_ladder(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, const int* flags,
-                   const double* V, const double* dV, double rho, double frac, int len, int* kout);
+void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
+                   const int* flags, const double* V, const double* dV, double rho, double frac,
+                   int len, int* kout);
 void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,
                         double rho, int slot, double* sc);
 void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,

@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(256) k_ladder(const BlkDesc* __restrict__ blks
   extern __shared__ double sm[];
   __shared__ int fl;
   const BlkDesc bd = blks[blockIdx.x];
+  if (bd.n <= kSmallN) return;   // k_ladder16
   if (!(flags[bd.sys] & F_ACTIVE)) {
     if (threadIdx.x == 0) kout[blockIdx.x] = 0;
     return;
@@ -82,21 +83,77 @@ __global__ void __launch_bounds__(256) k_ladder(const BlkDesc* __restrict__ blks
   if (threadIdx.x == 0) kout[blockIdx.x] = found;
 }
 
+// The same ladder for blocks of order <= 16: the block sits in the registers
+// of each wave (lane (r, g) holds row r, columns 4g..4g+3; identity past n),
+// and the 4 waves test 4 consecutive rungs at once with the wave Cholesky.
+__global__ void __launch_bounds__(256) k_ladder16(const BlkDesc* __restrict__ blks,
+                                                  const int* __restrict__ flags,
+                                                  const double* __restrict__ V,
+                                                  const double* __restrict__ dV, double rho,
+                                                  double frac, int len, int* kout) {
+  __shared__ int spass[4];
+  const BlkDesc bd = blks[blockIdx.x];
+  if (bd.n > kSmallN) return;   // k_ladder
+  if (!(flags[bd.sys] & F_ACTIVE)) {
+    if (threadIdx.x == 0) kout[blockIdx.x] = 0;
+    return;
+  }
+  const int n = bd.n, w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  double v0[4], dv[4];
+  bool in[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int cc = 4 * g + j;
+    in[j] = r < n && cc < n;
+    v0[j] = in[j] ? V[bd.off + r * n + cc] : (r == cc ? 1.0 : 0.0);
+    dv[j] = in[j] ? dV[bd.off + r * n + cc] : 0.0;
+  }
+  int found = -1;
+  for (int k0 = 0; k0 <= len; k0 += 4) {
+    const int k = k0 + w;
+    double rk = 1.0;
+    for (int i = 0; i < k; ++i) rk = rk * rho;
+    const double t = rk / frac;
+    double tv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tv[j] = in[j] ? __dadd_rn(v0[j], __dmul_rn(t, dv[j])) : v0[j];
+    const bool ok = wave_chol_ok16(tv) && k <= len;
+    if (lane == 0) spass[w] = ok;
+    __syncthreads();
+    int f = -1;
+    for (int ww = 3; ww >= 0; --ww)
+      if (spass[ww]) f = k0 + ww;
+    __syncthreads();
+    if (f >= 0) {
+      found = f;
+      break;
+    }
+  }
+  if (threadIdx.x == 0) kout[blockIdx.x] = found;
+}
+
 // Per system: k* = max over blocks of the first passing rung; the step is
-// r_{k*} (repeated multiplication, as the oracle does).
-__global__ void k_ladder_step(const SysDesc* __restrict__ sys, int S, int* flags,
-                              const int* __restrict__ kout, double rho, int slot, double* sc) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// r_{k*} (repeated multiplication, as the oracle does).  One wave per system.
+__global__ void __launch_bounds__(256) k_ladder_step(const SysDesc* __restrict__ sys, int S, int* flags,
+                                                     const int* __restrict__ kout, double rho, int slot,
+                                                     double* sc) {
+  const int s = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (s >= S) return;
   if (!(flags[s] & F_ACTIVE)) return;
-  const SysDesc sd = sys[s];
-  int kmax = 0;
-  bool bad = false;
-  for (int j = 0; j < sd.nb; ++j) {
-    const int k = kout[sd.blk0 + j];
-    if (k < 0) bad = true;
+  const int blk0 = sys[s].blk0, nb = sys[s].nb;
+  int kmax = 0, bad = 0;
+  for (int j = lane; j < nb; j += 64) {
+    const int k = kout[blk0 + j];
+    bad |= k < 0;
     kmax = k > kmax ? k : kmax;
   }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int ko = __shfl_xor(kmax, m);
+    kmax = ko > kmax ? ko : kmax;
+    bad |= __shfl_xor(bad, m);
+  }
+  if (lane != 0) return;
   double r = 1.0;
   for (int k = 0; k < kmax; ++k) r = r * rho;
   if (bad) {
@@ -521,6 +578,7 @@ __global__ void __launch_bounds__(256) k_certificate(const BlkDesc* __restrict__
   __shared__ int fl;
   __shared__ double fro;
   const BlkDesc bd = blks[blockIdx.x];
+  if (bd.n <= kSmallN) return;   // k_certificate16
   ACTIVE_OR_RETURN(bd.sys);
   const SysDesc sd = sys[bd.sys];
   const int n = bd.n, nn = n * n;
@@ -559,6 +617,55 @@ __global__ void __launch_bounds__(256) k_certificate(const BlkDesc* __restrict__
   if (threadIdx.x == 0) {
     out[blockIdx.x * 2 + 0] = pass0;
     out[blockIdx.x * 2 + 1] = 0.5 * (lo + hi);
+  }
+}
+
+// The same certificate for blocks of order <= 16, one wave per block: the
+// block stays in registers (identity past n, never shifted) and each
+// bisection step is one wave Cholesky.
+__global__ void __launch_bounds__(256) k_certificate16(const BlkDesc* __restrict__ blks, int nblk,
+                                                       const SysDesc* __restrict__ sys,
+                                                       const int* __restrict__ flags,
+                                                       const double* __restrict__ Q, int iters,
+                                                       double* out) {
+  const int b = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b >= nblk) return;
+  const BlkDesc bd = blks[b];
+  if (bd.n > kSmallN) return;   // k_certificate
+  if (!(flags[bd.sys] & F_ACTIVE)) return;
+  const int n = bd.n, r = lane & 15, g = lane >> 4;
+  const double sj = sys[bd.sys].scale[bd.j];
+  double q[4], f = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int cc = 4 * g + j;
+    const bool in = r < n && cc < n;
+    q[j] = in ? Q[bd.off + r * n + cc] : (r == cc ? 1.0 : 0.0);
+    if (in) f += q[j] * q[j];
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) f += __shfl_xor(f, m);
+  const double fro = sqrt(f);
+  double lo = 0, hi = 0;
+  int pass0 = 0;
+  for (int it = -1; it < iters; ++it) {
+    const double tau = it < 0 ? 0.0 : 0.5 * (lo + hi);
+    const double shift = tau * sj;
+    double tv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tv[j] = (r == 4 * g + j && r < n) ? q[j] - shift : q[j];
+    const bool ok = wave_chol_ok16(tv);
+    if (it < 0) {
+      pass0 = ok;
+      const double bnd = fro / sj + 1.0;
+      if (ok) { lo = 0.0; hi = bnd; } else { lo = -bnd; hi = 0.0; }
+    } else {
+      if (ok) lo = tau; else hi = tau;
+    }
+  }
+  if (lane == 0) {
+    out[b * 2 + 0] = pass0;
+    out[b * 2 + 1] = 0.5 * (lo + hi);
   }
 }
 
@@ -1481,16 +1588,21 @@ void launch_cholinv(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, int
   hipLaunchKernelGGL(k_cholinv, dim3(nblk), dim3(256), lds, st, blks, flags, Z, Zi);
 }
 
-void launch_ladder(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, const int* flags,
-                   const double* V, const double* dV, double rho, double frac, int len, int* kout) {
-  const size_t lds = (size_t)maxn * maxn * 8;
-  set_lds((const void*)k_ladder, lds);
-  hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, V, dV, rho, frac, len, kout);
+void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
+                   const int* flags, const double* V, const double* dV, double rho, double frac,
+                   int len, int* kout) {
+  if (nmax_small)
+    hipLaunchKernelGGL(k_ladder16, dim3(nblk), dim3(256), 0, st, blks, flags, V, dV, rho, frac, len, kout);
+  if (maxn > kSmallN) {
+    const size_t lds = (size_t)maxn * maxn * 8;
+    set_lds((const void*)k_ladder, lds);
+    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, V, dV, rho, frac, len, kout);
+  }
 }
 
 void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,
                         double rho, int slot, double* sc) {
-  hipLaunchKernelGGL(k_ladder_step, dim3((S + 63) / 64), dim3(64), 0, st, sys, S, flags, kout, rho, slot, sc);
+  hipLaunchKernelGGL(k_ladder_step, dim3((S + 3) / 4), dim3(256), 0, st, sys, S, flags, kout, rho, slot, sc);
 }
 
 void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
@@ -1589,9 +1701,13 @@ void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, cons
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,
                         double* out) {
-  const size_t lds = (size_t)maxn * maxn * 8;
-  set_lds((const void*)k_certificate, lds);
-  hipLaunchKernelGGL(k_certificate, dim3(nblk), dim3(256), lds, st, blks, sys, flags, Q, iters, out);
+  hipLaunchKernelGGL(k_certificate16, dim3((nblk + 3) / 4), dim3(256), 0, st, blks, nblk, sys, flags, Q,
+                     iters, out);
+  if (maxn > kSmallN) {
+    const size_t lds = (size_t)maxn * maxn * 8;
+    set_lds((const void*)k_certificate, lds);
+    hipLaunchKernelGGL(k_certificate, dim3(nblk), dim3(256), lds, st, blks, sys, flags, Q, iters, out);
+  }
 }
 
 }  // namespace psdp
