@@ -481,41 +481,49 @@ __global__ void __launch_bounds__(256) k_B_Y(const HMPair* __restrict__ pairs,
   wg_gemm(n, Hm, 0, W + bd.off, 0, arena + pr.offY, 1.0, nullptr, 0.0, sA, sB);
 }
 
-// B operator, second stage: one thread per (system, k = (h, b)):
+// B operator, second stage: four lanes per (system, k = (h, b)), each taking
+// every fourth term of both sums, then added across the four:
 // out_k = sum_{j<L} beta_{h,j} <E_b, W_j> - 2 sum_m <E_b, Y_{m,h}> - a_k * asub
-// (W symmetric).  Grid over sum_s K_s (owner table of prefixes).
-__global__ void k_B_reduce(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
-                           const int* __restrict__ own_pre, int S, const HMPair* __restrict__ pairs,
-                           const double* __restrict__ W, const double* __restrict__ arena,
-                           const BlkDesc* __restrict__ blks, double* out, double asub) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+// (W symmetric).  Grid over 4 sum_s K_s (owner table of prefixes).
+__global__ void __launch_bounds__(256) k_B_reduce(const SysDesc* __restrict__ sys,
+                                                  const int* __restrict__ flags,
+                                                  const int* __restrict__ own_pre, int S,
+                                                  const HMPair* __restrict__ pairs,
+                                                  const double* __restrict__ W,
+                                                  const double* __restrict__ arena,
+                                                  const BlkDesc* __restrict__ blks, double* out,
+                                                  double asub) {
+  const int gq = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = gq >> 2, qd = gq & 3;
   const int s = find_owner(own_pre, S, g);
-  const SysDesc sd = sys[s];
+  const SysDesc* sd = sys + s;
   const int k = g - own_pre[s];
-  if (k >= sd.K) return;
-  ACTIVE_OR_RETURN(s);
-  const int n = sd.n;
-  const int h = k / sd.Nt, b = k % sd.Nt;
-  const int p = sd.basis[2 * b], q = sd.basis[2 * b + 1];
-  const int e1 = p * n + q, e2 = q * n + p;
-  // loads of a term do not wait on its coefficient, so unrolled iterations
-  // overlap; a zero coefficient still drops the term
-  double acc = 0.0;
-#pragma unroll 4
-  for (int j = 0; j < sd.L; ++j) {
-    const double bt = sd.betaf[h * sd.L + j];
-    const double* Wj = W + blks[sd.blk0 + j].off;
-    const double w = p == q ? Wj[e1] : Wj[e1] + Wj[e2];
-    acc += bt != 0.0 ? bt * w : 0.0;
+  const bool live = k < sd->K && (flags[s] & F_ACTIVE);
+  double acc = 0.0, dsum = 0.0;
+  if (live) {
+    const int n = sd->n, Nt = sd->Nt, L = sd->L;
+    const int h = k / Nt, b = k - h * Nt;
+    const int p = sd->basis[2 * b], q = sd->basis[2 * b + 1];
+    const int e1 = p * n + q, e2 = q * n + p;
+    for (int j = qd; j < L; j += 4) {
+      const double bt = sd->betaf[h * L + j];
+      const double* Wj = W + blks[sd->blk0 + j].off;
+      const double w = p == q ? Wj[e1] : Wj[e1] + Wj[e2];
+      acc += bt != 0.0 ? bt * w : 0.0;
+    }
+    for (int c = sd->hm_by_h[h] + qd; c < sd->hm_by_h[h + 1]; c += 4) {
+      const double* Y = arena + pairs[sd->hm_ids[c]].offY;
+      dsum += (p == q ? Y[e1] : Y[e1] + Y[e2]);
+    }
   }
-  double dsum = 0.0;
-#pragma unroll 4
-  for (int c = sd.hm_by_h[h]; c < sd.hm_by_h[h + 1]; ++c) {
-    const double* Y = arena + pairs[sd.hm_ids[c]].offY;
-    dsum += (p == q ? Y[e1] : Y[e1] + Y[e2]);
-  }
+  // every lane of the quad takes part in the shuffles
+  acc += __shfl_xor(acc, 1);
+  acc += __shfl_xor(acc, 2);
+  dsum += __shfl_xor(dsum, 1);
+  dsum += __shfl_xor(dsum, 2);
+  if (!live || qd != 0) return;
   acc -= 2.0 * dsum;
-  out[sd.voff + k] = sd.mode == 0 ? acc - asub : acc;
+  out[sd->voff + k] = sd->mode == 0 ? acc - asub : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1681,7 +1689,7 @@ void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
 void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
                      const int* own_pre, int S, const HMPair* pairs, const double* W,
                      const double* arena, const BlkDesc* blks, double* out, double asub) {
-  hipLaunchKernelGGL(k_B_reduce, dim3((totalK + 255) / 256), dim3(256), 0, st, sys, flags, own_pre,
+  hipLaunchKernelGGL(k_B_reduce, dim3((4 * totalK + 255) / 256), dim3(256), 0, st, sys, flags, own_pre,
                      S, pairs, W, arena, blks, out, asub);
 }
 
