@@ -619,14 +619,26 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
   const double* A = Lam + sd.loff;
   const double* Di = Linv + sd.dgoff;
   const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
+  // the next panel's L_pp^{-1} rows and first kSvG kSvR rows of L below it
+  // are loaded before the barrier that ends the current panel
+  double d0[4], d1[4], a[kSvR][4];
+  auto load_di = [&](int q) {
+    const double* D = Di + (int64_t)q * kNB * kNB;
+    ld4(D + g * kNB + 4 * j, d0);
+    ld4(D + (g + kSvG) * kNB + 4 * j, d1);
+  };
+  auto load_rows = [&](int q, int ib) {
+    const double* Lq = A + (int64_t)q * kNB + 4 * j;
+#pragma unroll
+    for (int m = 0; m < kSvR; ++m) ld4(Lq + (int64_t)min(ib + g + kSvG * m, Kp - 1) * ld, a[m]);
+  };
+  load_di(0);
+  if (P > 1) load_rows(0, kNB);
   for (int k = tid; k < Kp; k += kSvT) sr[k] = rhs[sd.voff + k];
   __syncthreads();
   // forward: z_p = L_pp^{-1} r_p, then r_i -= L_ip z_p below
   for (int p = 0; p < P; ++p) {
-    const double* D = Di + (int64_t)p * kNB * kNB;
-    double d0[4], d1[4], rp[4];
-    ld4(D + g * kNB + 4 * j, d0);
-    ld4(D + (g + kSvG) * kNB + 4 * j, d1);
+    double rp[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) rp[q] = sr[p * kNB + 4 * j + q];
     const double z0 = gsum16(d0[0] * rp[0] + d0[1] * rp[1] + d0[2] * rp[2] + d0[3] * rp[3]);
@@ -640,11 +652,8 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
     double zp[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) zp[q] = sr[p * kNB + 4 * j + q];
-    const double* Lp = A + (int64_t)p * kNB + 4 * j;
     for (int ib = (p + 1) * kNB; ib < Kp; ib += kSvG * kSvR) {
-      double a[kSvR][4];
-#pragma unroll
-      for (int m = 0; m < kSvR; ++m) ld4(Lp + (int64_t)min(ib + g + kSvG * m, Kp - 1) * ld, a[m]);
+      if (ib != (p + 1) * kNB) load_rows(p, ib);
 #pragma unroll
       for (int m = 0; m < kSvR; ++m) {
         const double t = gsum16(a[m][0] * zp[0] + a[m][1] * zp[1] + a[m][2] * zp[2] + a[m][3] * zp[3]);
@@ -652,22 +661,22 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
         if (j == 0 && i < Kp) sr[i] -= t;
       }
     }
+    if (p + 1 < P) {
+      load_di(p + 1);
+      if ((p + 2) * kNB < Kp) load_rows(p + 1, (p + 2) * kNB);
+    }
     __syncthreads();
   }
   // backward: x_p = L_pp^{-T} (z_p - sum_{i below} L_ip^T x_i)
+  load_di(P - 1);
   for (int p = P - 1; p >= 0; --p) {
-    const double* D = Di + (int64_t)p * kNB * kNB;
-    double d0[4], d1[4];
-    ld4(D + g * kNB + 4 * j, d0);
-    ld4(D + (g + kSvG) * kNB + 4 * j, d1);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const double* Lp = A + (int64_t)p * kNB + 4 * j;
     for (int ib = (p + 1) * kNB; ib < Kp; ib += kSvG * kSvR) {
-      double a[kSvR][4], xv[kSvR];
+      if (ib != (p + 1) * kNB) load_rows(p, ib);
+      double xv[kSvR];
 #pragma unroll
       for (int m = 0; m < kSvR; ++m) {
         const int i = ib + g + kSvG * m;
-        ld4(Lp + (int64_t)min(i, Kp - 1) * ld, a[m]);
         xv[m] = i < Kp ? sr[i] : 0.0;
       }
 #pragma unroll
@@ -687,6 +696,10 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
     const double v0 = sv[g], v1 = sv[g + kSvG];
 #pragma unroll
     for (int q = 0; q < 4; ++q) sred[g * kNB + 4 * j + q] = d0[q] * v0 + d1[q] * v1;
+    if (p > 0) {
+      load_di(p - 1);
+      load_rows(p - 1, p * kNB);
+    }
     __syncthreads();
     if (tid < kNB) {
       double t = 0.0;
