@@ -28,12 +28,14 @@ METRIC = "IPM time-to-certificate @gap 1e-8: FP64 vs mixed/warm-start; Schur TFL
 PEAK_FP64 = 78.6          # TFLOP/s, FP64 vector and FP64 matrix (MI355X)
 PEAK_HBM = 8000.0         # GB/s
 
-# HBM bytes per launch of the dominant kernel, from the two rocprofv3 --pmc
-# runs summarised in profiles/hbm_counters_n10_batch64.md (FETCH_SIZE and
-# WRITE_SIZE in KiB per dispatch, scaled by what they read for a plain
-# 256 MiB device copy: x2.000 and x1.000).  Valid for the kernel version
-# those runs measured; None once it changes.
-PMC_TRAFFIC = {}
+# HBM bytes per launch of the dominant kernel group, from the two rocprofv3
+# --pmc runs summarised in profiles/hbm_counters_n10_batch64.md (FETCH_SIZE
+# and WRITE_SIZE in KiB per dispatch over the group's dispatches, scaled by
+# what they read for a plain 256 MiB device copy: x2.000 and x1.000).  Valid
+# for the kernel versions those runs measured; drop an entry once they change.
+PMC_TRAFFIC = {
+    ("n10", "cholesky"): dict(fetch_kib=21991.3, fetch_scale=2.000, write_kib=18092.0, write_scale=1.000),
+}
 
 
 def _mons(l, d):

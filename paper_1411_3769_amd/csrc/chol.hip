@@ -12,15 +12,17 @@
 // tile); the strict upper triangle keeps Lambda.
 //
 // Right-looking blocked algorithm, step p (panel column p):
-//   diag   : one workgroup per system factors the 64 x 64 diagonal tile in
-//            registers and inverts the factor (L_pp, L_pp^{-1} stored);
+//   diag   : one workgroup per system factors the 64 x 64 diagonal tile and
+//            inverts the factor (L_pp, L_pp^{-1} stored);
 //   trsm   : one workgroup per tile row i > p forms L_ip = A_ip L_pp^{-T};
-//   update : two levels.  Panels are grouped in super-panels of kSW; inside
-//            one, each tile (i, j) with p < j <= (end of the super-panel)
-//            gets A_ij -= L_ip L_jp^T right away (narrow update, depth 64);
-//            after the super-panel's last panel, every tile right of it gets
-//            the super-panel's whole contribution in one pass of depth
-//            64 kSW (wide update).  Both on FP64 MFMA.
+//   update : two levels.  Panels are grouped in super-panels of kSW (the
+//            last one absorbs a shorter remainder); inside one, each tile
+//            (i, j) with p < j <= (end of the super-panel) gets
+//            A_ij -= L_ip L_jp^T right away (narrow update, depth 64), and
+//            the workgroup of tile (p+1, p+1) goes on to the diagonal step
+//            of p + 1; after the super-panel's last panel, every tile right
+//            of it gets the super-panel's whole contribution in one pass of
+//            depth 64 kSW (wide update).  Both on FP64 MFMA.
 // Steps are launched for the whole batch; a (step, system) table maps
 // workgroups to systems.  Triangular solves use the stored inverses, so the
 // diagonal solves are matrix-vector products.
