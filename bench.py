@@ -33,9 +33,7 @@ PEAK_HBM = 8000.0         # GB/s
 # and WRITE_SIZE in KiB per dispatch over the group's dispatches, scaled by
 # what they read for a plain 256 MiB device copy: x2.000 and x1.000).  Valid
 # for the kernel versions those runs measured; drop an entry once they change.
-PMC_TRAFFIC = {
-    ("n10", "cholesky"): dict(fetch_kib=21991.3, fetch_scale=2.000, write_kib=18092.0, write_scale=1.000),
-}
+PMC_TRAFFIC = {}
 
 
 def _mons(l, d):

@@ -139,7 +139,7 @@ __device__ inline void wave_potri16(double* B, double* Xb, int* fail) {
 // by the 4 waves of a workgroup: on return sA holds L_pp (lower triangle) and
 // sX (zero on entry) holds L_pp^{-1}.  The strictly upper blocks of sA serve
 // as scratch for the inverse.  Non-positive pivots set *fl.
-__device__ void diag_tile(double* sA, double* sX, int* fl) {
+__device__ __forceinline__ void diag_tile(double* sA, double* sX, int* fl) {
   const int w = threadIdx.x >> 6;
   auto blk = [](double* M, int i, int j) { return M + (kBL * i) * kLD + kBL * j; };
   for (int kb = 0; kb < 4; ++kb) {
@@ -498,83 +498,6 @@ __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restr
   }
 }
 
-// y = M x or M^T x for a 64 x 64 tile M in global memory (row-major, leading
-// dimension ldm) and x in LDS; four lanes per output row; result in LDS.
-__device__ inline void tile_mv64(const double* M, int64_t ldm, bool trans, const double* x,
-                                 double* y) {
-  const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
-  double part = 0.0;
-  if (!trans) {
-    for (int c = q; c < kNB; c += 4) part += M[(int64_t)row * ldm + c] * x[c];
-  } else {
-    for (int c = q; c < kNB; c += 4) part += M[(int64_t)c * ldm + row] * x[c];
-  }
-  part += __shfl_xor(part, 1, 4);
-  part += __shfl_xor(part, 2, 4);
-  if (q == 0) y[row] = part;
-}
-
-// forward step p: z_p = L_pp^{-1} r_p (tile 0 writes it); tiles i > p update
-// r_i -= L_ip z_p.
-__global__ void __launch_bounds__(256) k_trsv_fwd(const SysDesc* __restrict__ sys,
-                                                  const int* __restrict__ flags,
-                                                  const double* __restrict__ Lam,
-                                                  const double* __restrict__ Linv, double* r,
-                                                  double* z, const int* __restrict__ st_sys,
-                                                  const int* __restrict__ st_pre, int cnt, int p) {
-  __shared__ double sx[kNB], sz[kNB];
-  const int si = find_owner(st_pre, cnt, blockIdx.x);
-  const int s = st_sys[si];
-  const int t = blockIdx.x - st_pre[si];
-  if (!(flags[s] & F_ACTIVE)) return;
-  const SysDesc sd = sys[s];
-  const int64_t ld = sd.Kpad;
-  double* rs = r + sd.voff;
-  double* zs = z + sd.voff;
-  if (threadIdx.x < kNB) sx[threadIdx.x] = rs[p * kNB + threadIdx.x];
-  __syncthreads();
-  tile_mv64(Linv + sd.dgoff + (int64_t)p * kNB * kNB, kNB, false, sx, sz);
-  __syncthreads();
-  if (t == 0) {
-    if (threadIdx.x < kNB) zs[p * kNB + threadIdx.x] = sz[threadIdx.x];
-    return;
-  }
-  const int i = p + t;
-  tile_mv64(Lam + sd.loff + (int64_t)i * kNB * ld + (int64_t)p * kNB, ld, false, sz, sx);
-  __syncthreads();
-  if (threadIdx.x < kNB) rs[i * kNB + threadIdx.x] -= sx[threadIdx.x];
-}
-
-// backward step p: x_p = L_pp^{-T} z_p (tile p writes it); tiles i < p
-// update z_i -= L_pi^T x_p.
-__global__ void __launch_bounds__(256) k_trsv_bwd(const SysDesc* __restrict__ sys,
-                                                  const int* __restrict__ flags,
-                                                  const double* __restrict__ Lam,
-                                                  const double* __restrict__ Linv, double* z,
-                                                  double* x, const int* __restrict__ st_sys,
-                                                  const int* __restrict__ st_pre, int cnt, int p) {
-  __shared__ double sx[kNB], sz[kNB];
-  const int si = find_owner(st_pre, cnt, blockIdx.x);
-  const int s = st_sys[si];
-  const int i = blockIdx.x - st_pre[si];
-  if (!(flags[s] & F_ACTIVE)) return;
-  const SysDesc sd = sys[s];
-  const int64_t ld = sd.Kpad;
-  double* zs = z + sd.voff;
-  double* xs = x + sd.voff;
-  if (threadIdx.x < kNB) sz[threadIdx.x] = zs[p * kNB + threadIdx.x];
-  __syncthreads();
-  tile_mv64(Linv + sd.dgoff + (int64_t)p * kNB * kNB, kNB, true, sz, sx);
-  __syncthreads();
-  if (i == p) {
-    if (threadIdx.x < kNB) xs[p * kNB + threadIdx.x] = sx[threadIdx.x];
-    return;
-  }
-  tile_mv64(Lam + sd.loff + (int64_t)p * kNB * ld + (int64_t)i * kNB, ld, true, sx, sz);
-  __syncthreads();
-  if (threadIdx.x < kNB) zs[i * kNB + threadIdx.x] -= sz[threadIdx.x];
-}
-
 // Whole solve L L^T x = rhs for systems with few tiles: one workgroup of 8
 // waves per system sweeps all tile steps (no inter-workgroup dependency); the
 // right-hand side and the iterate stay in LDS.  Each pass over a column panel
@@ -604,6 +527,111 @@ __device__ inline void ld4(const double* p, double* v) {
   v[3] = b.y;
 }
 
+// Forward (L z = r) and/or backward (L^T x = z) sweep over the panels p0..p1
+// of one system, restricted to the rows and columns of those panels: sr (LDS)
+// holds entries p0*64 .. (p1+1)*64 - 1 of the vector and is overwritten by the
+// result.  A is the system's matrix (leading dimension ld), Di its stored
+// diagonal-tile inverses.  The next panel's L_pp^{-1} rows and first
+// kSvG kSvR rows of L below it are loaded before the barrier that ends the
+// current panel.
+template <bool FWD, bool BWD>
+__device__ __forceinline__ void solve_range(const double* __restrict__ A, int64_t ld, const double* __restrict__ Di,
+                            int p0, int p1, double* sr, double* sred, double* sv) {
+  const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
+  const int base = p0 * kNB, rend = (p1 + 1) * kNB;
+  double d0[4], d1[4], a[kSvR][4];
+  auto load_di = [&](int q) {
+    const double* D = Di + (int64_t)q * kNB * kNB;
+    ld4(D + g * kNB + 4 * j, d0);
+    ld4(D + (g + kSvG) * kNB + 4 * j, d1);
+  };
+  auto load_rows = [&](int q, int ib) {
+    const double* Lq = A + (int64_t)q * kNB + 4 * j;
+#pragma unroll
+    for (int m = 0; m < kSvR; ++m) ld4(Lq + (int64_t)min(ib + g + kSvG * m, rend - 1) * ld, a[m]);
+  };
+  if constexpr (FWD) {
+    // z_p = L_pp^{-1} r_p, then r_i -= L_ip z_p below (inside the range)
+    load_di(p0);
+    if (p0 < p1) load_rows(p0, (p0 + 1) * kNB);
+    __syncthreads();
+    for (int p = p0; p <= p1; ++p) {
+      double rp[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rp[q] = sr[p * kNB - base + 4 * j + q];
+      const double z0 = gsum16(d0[0] * rp[0] + d0[1] * rp[1] + d0[2] * rp[2] + d0[3] * rp[3]);
+      const double z1 = gsum16(d1[0] * rp[0] + d1[1] * rp[1] + d1[2] * rp[2] + d1[3] * rp[3]);
+      __syncthreads();   // r_p read by every group
+      if (j == 0) {
+        sr[p * kNB - base + g] = z0;
+        sr[p * kNB - base + g + kSvG] = z1;
+      }
+      __syncthreads();
+      double zp[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zp[q] = sr[p * kNB - base + 4 * j + q];
+      for (int ib = (p + 1) * kNB; ib < rend; ib += kSvG * kSvR) {
+        if (ib != (p + 1) * kNB) load_rows(p, ib);
+#pragma unroll
+        for (int m = 0; m < kSvR; ++m) {
+          const double t = gsum16(a[m][0] * zp[0] + a[m][1] * zp[1] + a[m][2] * zp[2] + a[m][3] * zp[3]);
+          const int i = ib + g + kSvG * m;
+          if (j == 0 && i < rend) sr[i - base] -= t;
+        }
+      }
+      if (p < p1) {
+        load_di(p + 1);
+        if (p + 1 < p1) load_rows(p + 1, (p + 2) * kNB);
+      }
+      __syncthreads();
+    }
+  }
+  if constexpr (BWD) {
+    // x_p = L_pp^{-T} (z_p - sum_{i below, inside the range} L_ip^T x_i)
+    load_di(p1);
+    __syncthreads();
+    for (int p = p1; p >= p0; --p) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int ib = (p + 1) * kNB; ib < rend; ib += kSvG * kSvR) {
+        if (ib != (p + 1) * kNB) load_rows(p, ib);
+        double xv[kSvR];
+#pragma unroll
+        for (int m = 0; m < kSvR; ++m) {
+          const int i = ib + g + kSvG * m;
+          xv[m] = i < rend ? sr[i - base] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < kSvR; ++m)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] += a[m][q] * xv[m];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sred[g * kNB + 4 * j + q] = acc[q];
+      __syncthreads();
+      if (tid < kNB) {
+        double t = sr[p * kNB - base + tid];
+        for (int gg = 0; gg < kSvG; ++gg) t -= sred[gg * kNB + tid];
+        sv[tid] = t;
+      }
+      __syncthreads();
+      const double v0 = sv[g], v1 = sv[g + kSvG];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sred[g * kNB + 4 * j + q] = d0[q] * v0 + d1[q] * v1;
+      if (p > p0) {
+        load_di(p - 1);
+        load_rows(p - 1, p * kNB);
+      }
+      __syncthreads();
+      if (tid < kNB) {
+        double t = 0.0;
+        for (int gg = 0; gg < kSvG; ++gg) t += sred[gg * kNB + tid];
+        sr[p * kNB - base + tid] = t;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags,
                                                      const int* __restrict__ small_ids,
@@ -616,101 +644,110 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
   const int s = small_ids[blockIdx.x];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
+  for (int k = threadIdx.x; k < sd.Kpad; k += kSvT) sr[k] = rhs[sd.voff + k];
+  solve_range<true, false>(Lam + sd.loff, sd.Kpad, Linv + sd.dgoff, 0, sd.P - 1, sr, sred, sv);
+  solve_range<false, true>(Lam + sd.loff, sd.Kpad, Linv + sd.dgoff, 0, sd.P - 1, sr, sred, sv);
+  for (int k = threadIdx.x; k < sd.Kpad; k += kSvT) x[sd.voff + k] = sr[k];
+}
+
+// Larger systems solve by groups of kSG panels.  Forward, group q: the
+// diagonal block's sweep (k_trsv_gdiag, one workgroup per system, in place
+// on r) and then one launch for every row tile below it,
+// r_i -= L_{i,group} z_group (k_trsv_gfwd).  Backward, groups in reverse:
+// the diagonal block's transposed sweep (writes x) and then every column
+// tile left of it, z_c -= L_{group,c}^T x_group (k_trsv_gbwd).  Two launches
+// per group and direction instead of one per tile step; the rectangular
+// updates read L at full width.
+__global__ void __launch_bounds__(kSvT) k_trsv_gdiag(const SysDesc* __restrict__ sys,
+                                                     const int* __restrict__ flags,
+                                                     const int* __restrict__ st_sys,
+                                                     const double* __restrict__ Lam,
+                                                     const double* __restrict__ Linv,
+                                                     const double* vin, double* vout, int q,
+                                                     int backward) {
+  __shared__ double sr[kNB * kSG];
+  __shared__ double sred[kSvG * kNB];
+  __shared__ double sv[kNB];
+  const int s = st_sys[blockIdx.x];
+  if (!(flags[s] & F_ACTIVE)) return;
+  const SysDesc sd = sys[s];
+  const int p0 = kSG * q, p1 = min(sd.P, kSG * (q + 1)) - 1;
+  const int base = p0 * kNB, nv = (p1 - p0 + 1) * kNB;
+  for (int k = threadIdx.x; k < nv; k += kSvT) sr[k] = vin[sd.voff + base + k];
+  if (backward) solve_range<false, true>(Lam + sd.loff, sd.Kpad, Linv + sd.dgoff, p0, p1, sr, sred, sv);
+  else solve_range<true, false>(Lam + sd.loff, sd.Kpad, Linv + sd.dgoff, p0, p1, sr, sred, sv);
+  for (int k = threadIdx.x; k < nv; k += kSvT) vout[sd.voff + base + k] = sr[k];
+}
+
+// r_i -= sum_{c in group q} L[i][c] z[c] for the 64 rows of row tile
+// kSG (q+1) + t: every 16-lane group takes 4 rows, each lane 4 columns of
+// every 64-column segment of the group.
+__global__ void __launch_bounds__(256) k_trsv_gfwd(const SysDesc* __restrict__ sys,
+                                                   const int* __restrict__ flags,
+                                                   const int* __restrict__ st_sys,
+                                                   const int* __restrict__ st_pre, int cnt,
+                                                   const double* __restrict__ Lam, double* r, int q) {
+  __shared__ double sz[kNB * kSG];
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
+  if (!(flags[s] & F_ACTIVE)) return;
+  const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
-  const int Kp = sd.Kpad, P = sd.P;
-  const double* A = Lam + sd.loff;
-  const double* Di = Linv + sd.dgoff;
+  const int p0 = kSG * q, nseg = min(sd.P, kSG * (q + 1)) - p0;
+  const int base = p0 * kNB;
   const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
-  // the next panel's L_pp^{-1} rows and first kSvG kSvR rows of L below it
-  // are loaded before the barrier that ends the current panel
-  double d0[4], d1[4], a[kSvR][4];
-  auto load_di = [&](int q) {
-    const double* D = Di + (int64_t)q * kNB * kNB;
-    ld4(D + g * kNB + 4 * j, d0);
-    ld4(D + (g + kSvG) * kNB + 4 * j, d1);
-  };
-  auto load_rows = [&](int q, int ib) {
-    const double* Lq = A + (int64_t)q * kNB + 4 * j;
-#pragma unroll
-    for (int m = 0; m < kSvR; ++m) ld4(Lq + (int64_t)min(ib + g + kSvG * m, Kp - 1) * ld, a[m]);
-  };
-  load_di(0);
-  if (P > 1) load_rows(0, kNB);
-  for (int k = tid; k < Kp; k += kSvT) sr[k] = rhs[sd.voff + k];
+  double* rs = r + sd.voff;
+  for (int k = tid; k < nseg * kNB; k += 256) sz[k] = rs[base + k];
   __syncthreads();
-  // forward: z_p = L_pp^{-1} r_p, then r_i -= L_ip z_p below
-  for (int p = 0; p < P; ++p) {
-    double rp[4];
+  const int i0 = (kSG * (q + 1) + t) * kNB + 4 * g;
+  const double* A = Lam + sd.loff + (int64_t)i0 * ld + base + 4 * j;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int sg = 0; sg < nseg; ++sg) {
+    double zq[4], a[4][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rp[q] = sr[p * kNB + 4 * j + q];
-    const double z0 = gsum16(d0[0] * rp[0] + d0[1] * rp[1] + d0[2] * rp[2] + d0[3] * rp[3]);
-    const double z1 = gsum16(d1[0] * rp[0] + d1[1] * rp[1] + d1[2] * rp[2] + d1[3] * rp[3]);
-    __syncthreads();   // r_p read by every group
-    if (j == 0) {
-      sr[p * kNB + g] = z0;
-      sr[p * kNB + g + kSvG] = z1;
-    }
-    __syncthreads();
-    double zp[4];
+    for (int u = 0; u < 4; ++u) zq[u] = sz[sg * kNB + 4 * j + u];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) zp[q] = sr[p * kNB + 4 * j + q];
-    for (int ib = (p + 1) * kNB; ib < Kp; ib += kSvG * kSvR) {
-      if (ib != (p + 1) * kNB) load_rows(p, ib);
+    for (int m = 0; m < 4; ++m) ld4(A + (int64_t)m * ld + sg * kNB, a[m]);
 #pragma unroll
-      for (int m = 0; m < kSvR; ++m) {
-        const double t = gsum16(a[m][0] * zp[0] + a[m][1] * zp[1] + a[m][2] * zp[2] + a[m][3] * zp[3]);
-        const int i = ib + g + kSvG * m;
-        if (j == 0 && i < Kp) sr[i] -= t;
-      }
-    }
-    if (p + 1 < P) {
-      load_di(p + 1);
-      if ((p + 2) * kNB < Kp) load_rows(p + 1, (p + 2) * kNB);
-    }
-    __syncthreads();
+    for (int m = 0; m < 4; ++m) acc[m] += a[m][0] * zq[0] + a[m][1] * zq[1] + a[m][2] * zq[2] + a[m][3] * zq[3];
   }
-  // backward: x_p = L_pp^{-T} (z_p - sum_{i below} L_ip^T x_i)
-  load_di(P - 1);
-  for (int p = P - 1; p >= 0; --p) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int ib = (p + 1) * kNB; ib < Kp; ib += kSvG * kSvR) {
-      if (ib != (p + 1) * kNB) load_rows(p, ib);
-      double xv[kSvR];
 #pragma unroll
-      for (int m = 0; m < kSvR; ++m) {
-        const int i = ib + g + kSvG * m;
-        xv[m] = i < Kp ? sr[i] : 0.0;
-      }
-#pragma unroll
-      for (int m = 0; m < kSvR; ++m)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += a[m][q] * xv[m];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sred[g * kNB + 4 * j + q] = acc[q];
-    __syncthreads();
-    if (tid < kNB) {
-      double t = sr[p * kNB + tid];
-      for (int gg = 0; gg < kSvG; ++gg) t -= sred[gg * kNB + tid];
-      sv[tid] = t;
-    }
-    __syncthreads();
-    const double v0 = sv[g], v1 = sv[g + kSvG];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sred[g * kNB + 4 * j + q] = d0[q] * v0 + d1[q] * v1;
-    if (p > 0) {
-      load_di(p - 1);
-      load_rows(p - 1, p * kNB);
-    }
-    __syncthreads();
-    if (tid < kNB) {
-      double t = 0.0;
-      for (int gg = 0; gg < kSvG; ++gg) t += sred[gg * kNB + tid];
-      sr[p * kNB + tid] = t;
-    }
-    __syncthreads();
+  for (int m = 0; m < 4; ++m) {
+    const double v = gsum16(acc[m]);
+    if (j == 0) rs[i0 + m] -= v;
   }
-  for (int k = tid; k < Kp; k += kSvT) x[sd.voff + k] = sr[k];
+}
+
+// z_c -= sum_{rows of group q} L[row][c] x[row] for the 64 columns of column
+// tile t (t < kSG q): thread (c, rg) sums every fourth row, then the four
+// partial sums are added in LDS.
+__global__ void __launch_bounds__(256) k_trsv_gbwd(const SysDesc* __restrict__ sys,
+                                                   const int* __restrict__ flags,
+                                                   const int* __restrict__ st_sys,
+                                                   const int* __restrict__ st_pre, int cnt,
+                                                   const double* __restrict__ Lam,
+                                                   const double* __restrict__ x, double* z, int q) {
+  __shared__ double sx[kNB * kSG];
+  __shared__ double sp[4 * kNB];
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
+  if (!(flags[s] & F_ACTIVE)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  const int p0 = kSG * q, nrow = (min(sd.P, kSG * (q + 1)) - p0) * kNB;
+  const int base = p0 * kNB;
+  const int tid = threadIdx.x, cc = tid & 63, rg = tid >> 6;
+  for (int k = tid; k < nrow; k += 256) sx[k] = x[sd.voff + base + k];
+  __syncthreads();
+  const double* A = Lam + sd.loff + (int64_t)base * ld + t * kNB + cc;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int rr = rg; rr < nrow; rr += 4) acc += A[(int64_t)rr * ld] * sx[rr];
+  sp[rg * kNB + cc] = acc;
+  __syncthreads();
+  if (tid < kNB) z[sd.voff + t * kNB + tid] -= sp[tid] + sp[kNB + tid] + sp[2 * kNB + tid] + sp[3 * kNB + tid];
 }
 
 // launch wrappers --------------------------------------------------------------
@@ -742,16 +779,25 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
                        cnt, p);
 }
 
-void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Linv, double* r, double* z, const int* ssys, const int* spre,
-                     int cnt, int total, int p) {
-  hipLaunchKernelGGL(k_trsv_fwd, dim3(total), dim3(256), 0, st, sys, flags, Lam, Linv, r, z, ssys, spre, cnt, p);
+void launch_trsv_gdiag(hipStream_t st, int cnt, const SysDesc* sys, const int* flags, const int* ssys,
+                       const double* Lam, const double* Linv, const double* vin, double* vout, int q,
+                       int backward) {
+  if (cnt)
+    hipLaunchKernelGGL(k_trsv_gdiag, dim3(cnt), dim3(kSvT), 0, st, sys, flags, ssys, Lam, Linv, vin, vout,
+                       q, backward);
 }
 
-void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Linv, double* z, double* x, const int* ssys, const int* spre,
-                     int cnt, int total, int p) {
-  hipLaunchKernelGGL(k_trsv_bwd, dim3(total), dim3(256), 0, st, sys, flags, Lam, Linv, z, x, ssys, spre, cnt, p);
+void launch_trsv_gfwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                      const int* spre, int cnt, int total, const double* Lam, double* r, int q) {
+  if (total)
+    hipLaunchKernelGGL(k_trsv_gfwd, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Lam, r, q);
+}
+
+void launch_trsv_gbwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                      const int* spre, int cnt, int total, const double* Lam, const double* x, double* z,
+                      int q) {
+  if (total)
+    hipLaunchKernelGGL(k_trsv_gbwd, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Lam, x, z, q);
 }
 
 void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int* flags,

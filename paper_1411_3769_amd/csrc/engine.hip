@@ -171,7 +171,12 @@ struct Batch {
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
   std::vector<int> ownP, ownK;
-  StepTab pan, trs, upd, wide, fwdL, bwdL;   // fwdL/bwdL: tile-step solves of the systems not solved in one workgroup
+  StepTab pan, trs, upd, wide;
+  // grouped solves of the systems not solved in one workgroup: per group q,
+  // the diagonal-block sweeps (one per system), the row tiles below the
+  // group (forward) and the column tiles left of it (backward)
+  StepTab gdg, gfu, gbu;
+  int maxNG = 0;
   std::vector<int> small_ids;
   int* d_small = nullptr;
   int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0;
@@ -191,7 +196,8 @@ struct Batch {
   int64_t* d_gpoff = nullptr;
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
   int *d_trs_sys = nullptr, *d_trs_pre = nullptr, *d_wide_sys = nullptr, *d_wide_pre = nullptr;
-  int *d_fwdL_sys = nullptr, *d_fwdL_pre = nullptr, *d_bwdL_sys = nullptr, *d_bwdL_pre = nullptr;
+  int *d_gdg_sys = nullptr, *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr,
+      *d_gbu_pre = nullptr;
   int* d_flags = nullptr;
   double* d_sc = nullptr;
   double* d_red = nullptr;
@@ -471,8 +477,6 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.trs.add_step();
     B.upd.add_step();
     B.wide.add_step();
-    B.fwdL.add_step();
-    B.bwdL.add_step();
 
     // last column of the narrow update of step q (super-panel end; a
     // super-panel followed by fewer than kSW panels absorbs them, since
@@ -489,10 +493,6 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
       if (pstep == 0 || sp_end(P, pstep - 1) < pstep) B.pan.add(s, 1);
       const int T = P - pstep - 1;
       if (T > 0) B.trs.add(s, T);
-      if (!(ch->small[s] && P <= kSmallP)) {
-        B.fwdL.add(s, P - pstep);
-        B.bwdL.add(s, pstep + 1);
-      }
       // narrow update: columns p+1 .. end of the super-panel
       const int se = sp_end(P, pstep);
       int nn = 0;
@@ -507,6 +507,23 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     }
   }
 
+  // ---- grouped solve tables
+  auto tiled = [&](int s) { return !(ch->small[s] && B.sys[s].P <= kSmallP); };
+  for (int s = 0; s < count; ++s)
+    if (tiled(s)) B.maxNG = std::max(B.maxNG, (B.sys[s].P + kSG - 1) / kSG);
+  for (int q = 0; q < B.maxNG; ++q) {
+    B.gdg.add_step();
+    B.gfu.add_step();
+    B.gbu.add_step();
+    for (int s = 0; s < count; ++s) {
+      const int P = B.sys[s].P;
+      if (!tiled(s) || P <= kSG * q) continue;
+      B.gdg.add(s, 1);
+      if (P > kSG * (q + 1)) B.gfu.add(s, P - kSG * (q + 1));
+      if (q > 0) B.gbu.add(s, kSG * q);
+    }
+  }
+
   // ---- device tables
   size_t tb = 0;
   tb += tabsize(B.sys) + tabsize(B.blk) + tabsize(B.pblk) + tabsize(B.dblk) + tabsize(B.pairs);
@@ -516,7 +533,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(B.csr_mh) + tabsize(B.csr_hl);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
-  tb += tabsize(B.fwdL.sys) + tabsize(B.fwdL.pre) + tabsize(B.bwdL.sys) + tabsize(B.bwdL.pre);
+  tb += tabsize(B.gdg.sys) + tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
   tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 4 + 255) / 256 * 256;
@@ -572,10 +589,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.wide.pre, &B.d_wide_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.upd.sys, &B.d_upd_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.upd.pre, &B.d_upd_pre))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.fwdL.sys, &B.d_fwdL_sys))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.fwdL.pre, &B.d_fwdL_pre))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.bwdL.sys, &B.d_bwdL_sys))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.bwdL.pre, &B.d_bwdL_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gdg.sys, &B.d_gdg_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gfu.sys, &B.d_gfu_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gfu.pre, &B.d_gfu_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gbu.sys, &B.d_gbu_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gbu.pre, &B.d_gbu_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.small_ids, &B.d_small))) return rc;
   PSDP_HIP(hipMemcpy(B.dtab, stage.data(), off, hipMemcpyHostToDevice));
   char* base = (char*)B.dtab;
@@ -699,17 +717,19 @@ static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
   launch_trsv_small(st, (int)B.small_ids.size(), B.d_sys, B.d_flags, B.d_small, B.Lam, B.Linv, rhs, x);
   if (B.small_ids.size() < (size_t)B.S) {
     PSDP_HIP(hipMemcpyAsync(B.r, rhs, B.totvec * 8, hipMemcpyDeviceToDevice, st));
-    for (int p = 0; p < B.maxP; ++p) {
-      if (B.fwdL.tot[p] == 0) continue;
-      const int f = B.fwdL.first[p];
-      launch_trsv_fwd(st, B.d_sys, B.d_flags, B.Lam, B.Linv, B.r, B.z, B.d_fwdL_sys + f,
-                      B.d_fwdL_pre + f, B.fwdL.cnt[p], B.fwdL.tot[p], p);
+    for (int q = 0; q < B.maxNG; ++q) {
+      launch_trsv_gdiag(st, B.gdg.cnt[q], B.d_sys, B.d_flags, B.d_gdg_sys + B.gdg.first[q], B.Lam, B.Linv,
+                        B.r, B.r, q, 0);
+      const int f = B.gfu.first[q];
+      launch_trsv_gfwd(st, B.d_sys, B.d_flags, B.d_gfu_sys + f, B.d_gfu_pre + f, B.gfu.cnt[q],
+                       B.gfu.tot[q], B.Lam, B.r, q);
     }
-    for (int p = B.maxP - 1; p >= 0; --p) {
-      if (B.bwdL.tot[p] == 0) continue;
-      const int f = B.bwdL.first[p];
-      launch_trsv_bwd(st, B.d_sys, B.d_flags, B.Lam, B.Linv, B.z, x, B.d_bwdL_sys + f,
-                      B.d_bwdL_pre + f, B.bwdL.cnt[p], B.bwdL.tot[p], p);
+    for (int q = B.maxNG - 1; q >= 0; --q) {
+      launch_trsv_gdiag(st, B.gdg.cnt[q], B.d_sys, B.d_flags, B.d_gdg_sys + B.gdg.first[q], B.Lam, B.Linv,
+                        B.r, x, q, 1);
+      const int f = B.gbu.first[q];
+      launch_trsv_gbwd(st, B.d_sys, B.d_flags, B.d_gbu_sys + f, B.d_gbu_pre + f, B.gbu.cnt[q],
+                       B.gbu.tot[q], B.Lam, x, B.r, q);
     }
   }
   B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());

@@ -162,17 +162,20 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
                              const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
                         double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
-void launch_trsv_fwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Linv, double* r, double* z, const int* ssys, const int* spre,
-                     int cnt, int total, int p);
-void launch_trsv_bwd(hipStream_t st, const SysDesc* sys, const int* flags, const double* Lam,
-                     const double* Linv, double* z, double* x, const int* ssys, const int* spre,
-                     int cnt, int total, int p);
+void launch_trsv_gdiag(hipStream_t st, int cnt, const SysDesc* sys, const int* flags, const int* ssys,
+                       const double* Lam, const double* Linv, const double* vin, double* vout, int q,
+                       int backward);
+void launch_trsv_gfwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                      const int* spre, int cnt, int total, const double* Lam, double* r, int q);
+void launch_trsv_gbwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                      const int* spre, int cnt, int total, const double* Lam, const double* x, double* z,
+                      int q);
 void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int* flags,
                        const int* small_ids, const double* Lam, const double* Linv,
                        const double* rhs, double* x);
 constexpr int kSmallN = 16;   // blocks up to this order take the packed small-block kernels
 constexpr int kSmallP = 32;   // systems with at most this many Schur tiles solve in one launch
+constexpr int kSG = 8;       // panels per group of the tiled triangular solves
 
 // engine entry used by the public solve / eval calls
 int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res);
