@@ -890,7 +890,21 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
   // uploads the flags of the Newton step without waiting.
   set_flags(B, rs, hf);
   PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
-  GraphRun g1, g2;
+  GraphRun g1, g2, g3;
+  // FP64 runs enqueue the next Schur assembly right behind the read-backs
+  // and wait only for those (an event), so the host's decisions overlap the
+  // assembly; it uses the flags of the previous step, which only adds the
+  // assembly of a system that is about to stop.  (The precision form decides
+  // each step's assembly precision on the host, and the class profiler
+  // needs every launch of a class in one place, so both keep the plain
+  // order.)
+  const bool hoist = !B.f32 && !B.prof.on;
+  hipEvent_t ev_rb = nullptr;
+  if (hoist) PSDP_HIP(hipEventCreateWithFlags(&ev_rb, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() { if (e) hipEventDestroy(e); }
+  } ev_guard{ev_rb};
   for (int it = 0;; ++it) {
     // residuals, objectives and the scalars the host decides on
     auto part1 = [&]() -> int {
@@ -915,7 +929,13 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     };
     int rc = replay(B, st, g1, part1);
     if (rc) return rc;
-    PSDP_HIP(hipStreamSynchronize(st));
+    if (hoist) {
+      PSDP_HIP(hipEventRecord(ev_rb, st));
+      if ((rc = replay(B, st, g3, [&]() -> int { op_schur(B, st); return PSDP_OK; }))) return rc;
+      PSDP_HIP(hipEventSynchronize(ev_rb));
+    } else {
+      PSDP_HIP(hipStreamSynchronize(st));
+    }
     B.prof.harvest();
     if (it > 0) {
       // failure bits of the previous Newton step
@@ -994,7 +1014,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     auto part2 = [&]() -> int {
     PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
     // ---- Newton system (Alg. 2 processors/root step 1)
-    op_schur(B, st);
+    if (!hoist) op_schur(B, st);
     op_factor(B, st);
     // Omega_1 = B(Z^-1 G X) - a
     { const size_t pm_ = B.prof.mark();

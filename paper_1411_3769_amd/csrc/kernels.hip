@@ -83,22 +83,24 @@ __global__ void __launch_bounds__(256) k_ladder(const BlkDesc* __restrict__ blks
   if (threadIdx.x == 0) kout[blockIdx.x] = found;
 }
 
-// The same ladder for blocks of order <= 16: the block sits in the registers
-// of each wave (lane (r, g) holds row r, columns 4g..4g+3; identity past n),
-// and the 4 waves test 4 consecutive rungs at once with the wave Cholesky.
-__global__ void __launch_bounds__(256) k_ladder16(const BlkDesc* __restrict__ blks,
+// The same ladder for blocks of order <= 16, one wave per block (four blocks
+// per workgroup): the block sits in the wave's registers (lane (r, g) holds
+// row r, columns 4g..4g+3; identity past n) and the rungs are tried in order
+// with the wave Cholesky (the first rung passes in most iterations).
+__global__ void __launch_bounds__(256) k_ladder16(const BlkDesc* __restrict__ blks, int nblk,
                                                   const int* __restrict__ flags,
                                                   const double* __restrict__ V,
                                                   const double* __restrict__ dV, double rho,
                                                   double frac, int len, int* kout) {
-  __shared__ int spass[4];
-  const BlkDesc bd = blks[blockIdx.x];
+  const int b = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b >= nblk) return;
+  const BlkDesc bd = blks[b];
   if (bd.n > kSmallN) return;   // k_ladder
   if (!(flags[bd.sys] & F_ACTIVE)) {
-    if (threadIdx.x == 0) kout[blockIdx.x] = 0;
+    if (lane == 0) kout[b] = 0;
     return;
   }
-  const int n = bd.n, w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int n = bd.n, r = lane & 15, g = lane >> 4;
   double v0[4], dv[4];
   bool in[4];
 #pragma unroll
@@ -109,27 +111,19 @@ __global__ void __launch_bounds__(256) k_ladder16(const BlkDesc* __restrict__ bl
     dv[j] = in[j] ? dV[bd.off + r * n + cc] : 0.0;
   }
   int found = -1;
-  for (int k0 = 0; k0 <= len; k0 += 4) {
-    const int k = k0 + w;
-    double rk = 1.0;
-    for (int i = 0; i < k; ++i) rk = rk * rho;
+  double rk = 1.0;
+  for (int k = 0; k <= len; ++k) {
     const double t = rk / frac;
     double tv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) tv[j] = in[j] ? __dadd_rn(v0[j], __dmul_rn(t, dv[j])) : v0[j];
-    const bool ok = wave_chol_ok16(tv) && k <= len;
-    if (lane == 0) spass[w] = ok;
-    __syncthreads();
-    int f = -1;
-    for (int ww = 3; ww >= 0; --ww)
-      if (spass[ww]) f = k0 + ww;
-    __syncthreads();
-    if (f >= 0) {
-      found = f;
+    if (wave_chol_ok16(tv)) {
+      found = k;
       break;
     }
+    rk = rk * rho;
   }
-  if (threadIdx.x == 0) kout[blockIdx.x] = found;
+  if (lane == 0) kout[b] = found;
 }
 
 // Per system: k* = max over blocks of the first passing rung; the step is
@@ -1600,7 +1594,8 @@ void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const Blk
                    const int* flags, const double* V, const double* dV, double rho, double frac,
                    int len, int* kout) {
   if (nmax_small)
-    hipLaunchKernelGGL(k_ladder16, dim3(nblk), dim3(256), 0, st, blks, flags, V, dV, rho, frac, len, kout);
+    hipLaunchKernelGGL(k_ladder16, dim3((nblk + 3) / 4), dim3(256), 0, st, blks, nblk, flags, V, dV, rho, frac,
+                       len, kout);
   if (maxn > kSmallN) {
     const size_t lds = (size_t)maxn * maxn * 8;
     set_lds((const void*)k_ladder, lds);
