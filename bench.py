@@ -145,7 +145,7 @@ def main():
 
     def step(prof=None):
         t0 = time.perf_counter()
-        hs = [P.polya_setup(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)]
+        hs = P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)])
         t1 = time.perf_counter()
         rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=prec,
                                  use_graph=0 if args.no_graph else 1)

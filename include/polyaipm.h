@@ -225,6 +225,20 @@ void psdp_opts_default(psdp_opts* o);
 int psdp_polya_setup(const double* A, int n, int l, int dp, int d,
                      const psdp_setup_opts* o, psdp_sdp** out);
 
+/*
+ * psdp_polya_setup_batched -- the set-up of psdp_polya_setup (Section III,
+ * Alg. 1) for count systems in one call: A[i] (host or device per o, as for
+ * psdp_polya_setup), n[i], l[i], dp[i], d[i] describe system i; o (or NULL)
+ * applies to all.  Every system's kernels are queued before one wait for all
+ * read-backs, so the call costs about one set-up, not count of them.  out
+ * (count handles, owned by the caller as from psdp_polya_setup) is all set
+ * on success; on any error no handle is returned (out[i] = NULL), earlier
+ * ones are released, and the message names the failing system.
+ */
+int psdp_polya_setup_batched(int count, const double* const* A, const int* n, const int* l,
+                             const int* dp, const int* d, const psdp_setup_opts* o,
+                             psdp_sdp** out);
+
 /* Sizes of an SDP handle (eq. L0, L, M, K). */
 int psdp_query(const psdp_sdp* sdp, psdp_dims* out);
 

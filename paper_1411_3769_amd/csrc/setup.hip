@@ -233,8 +233,12 @@ const char* psdp_last_error(void) { return g_err.c_str(); }
 
 const char* psdp_version(void) { return "polyaipm 0.1 (gfx950)"; }
 
-int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_setup_opts* o,
-                     psdp_sdp** out) {
+// Set-up of one system up to its kernels, all asynchronous on the null
+// stream; *rb receives the device address of its read-back region (betaf,
+// scale, cdiag, non-finite flag of A: *nrb doubles), which setup_finish
+// parses once the stream has drained.
+static int setup_begin(const double* A, int n, int l, int dp, int d, const psdp_setup_opts* o,
+                       psdp_sdp** out, const double** rb_dev, int64_t* nrb_out) {
   try {
     if (!out) return fail(PSDP_EINVAL, "out is NULL");
     *out = nullptr;
@@ -374,14 +378,8 @@ int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_se
       e = hipGetLastError();
       if (e != hipSuccess) return cleanup(PSDP_EDEVICE, std::string("set-up kernels: ") + hipGetErrorString(e));
     }
-    // one read-back (it also waits for the kernels)
-    std::vector<double> rb(nrb);
-    e = hipMemcpy(rb.data(), s->dbetaf, nrb * 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return cleanup(PSDP_EDEVICE, std::string("set-up read-back: ") + hipGetErrorString(e));
-    if (rb[nrb - 1] != 0.0) return cleanup(PSDP_EINVAL, "A has a non-finite entry");
-    s->betaf.assign(rb.begin(), rb.begin() + L0 * L);
-    s->scale_h.assign(rb.begin() + L0 * L, rb.begin() + L0 * L + (L + M));
-    s->cdiag_h.assign(rb.begin() + L0 * L + (L + M), rb.begin() + L0 * L + 2 * (L + M));
+    *rb_dev = s->dbetaf;
+    *nrb_out = nrb;
     *out = s;
     return PSDP_OK;
   } catch (const std::bad_alloc&) {
@@ -389,6 +387,97 @@ int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_se
   } catch (...) {
     return fail(PSDP_EINVAL, "unexpected exception in psdp_polya_setup");
   }
+}
+
+// Parse the read-back of a begun set-up (host copy rb); on a non-finite A the
+// handle is released and *out cleared.
+static int setup_finish(psdp_sdp** out, const double* rb, int64_t nrb) {
+  psdp_sdp* s = *out;
+  if (rb[nrb - 1] != 0.0) {
+    hipFree(s->dmem);
+    delete s;
+    *out = nullptr;
+    return fail(PSDP_EINVAL, "A has a non-finite entry");
+  }
+  const int64_t L0 = s->L0, L = s->L, M = s->M;
+  s->betaf.assign(rb, rb + L0 * L);
+  s->scale_h.assign(rb + L0 * L, rb + L0 * L + (L + M));
+  s->cdiag_h.assign(rb + L0 * L + (L + M), rb + L0 * L + 2 * (L + M));
+  return PSDP_OK;
+}
+
+int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_setup_opts* o,
+                     psdp_sdp** out) {
+  const double* rb_dev = nullptr;
+  int64_t nrb = 0;
+  int rc = setup_begin(A, n, l, dp, d, o, out, &rb_dev, &nrb);
+  if (rc) return rc;
+  try {
+    // one read-back (it also waits for the kernels)
+    std::vector<double> rb(nrb);
+    const hipError_t e = hipMemcpy(rb.data(), rb_dev, nrb * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      psdp_free(*out);
+      *out = nullptr;
+      return fail(PSDP_EDEVICE, std::string("set-up read-back: ") + hipGetErrorString(e));
+    }
+    return setup_finish(out, rb.data(), nrb);
+  } catch (const std::bad_alloc&) {
+    psdp_free(*out);
+    *out = nullptr;
+    return fail(PSDP_ENOMEM, "host allocation failed");
+  }
+}
+
+int psdp_polya_setup_batched(int count, const double* const* A, const int* n, const int* l,
+                             const int* dp, const int* d, const psdp_setup_opts* o, psdp_sdp** out) {
+  if (count < 0) return fail(PSDP_EINVAL, "count is negative");
+  if (count > 0 && (!A || !n || !l || !dp || !d || !out)) return fail(PSDP_EINVAL, "NULL argument");
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  std::vector<const double*> rb_dev(count, nullptr);
+  std::vector<int64_t> nrb(count, 0), roff(count + 1, 0);
+  auto release = [&]() {
+    for (int i = 0; i < count; ++i) {
+      if (out[i]) psdp_free(out[i]);
+      out[i] = nullptr;
+    }
+  };
+  for (int i = 0; i < count; ++i) {
+    const int rc = setup_begin(A[i], n[i], l[i], dp[i], d[i], o, &out[i], &rb_dev[i], &nrb[i]);
+    if (rc) {
+      const std::string msg = "system " + std::to_string(i) + ": " + psdp_last_error();
+      release();
+      return fail(rc, msg);
+    }
+    roff[i + 1] = roff[i] + nrb[i];
+  }
+  if (count == 0) return PSDP_OK;
+  // every read-back into one pinned buffer, one wait
+  double* host = nullptr;
+  hipError_t e = hipHostMalloc((void**)&host, (size_t)roff[count] * 8, hipHostMallocDefault);
+  for (int i = 0; e == hipSuccess && i < count; ++i)
+    e = hipMemcpyAsync(host + roff[i], rb_dev[i], nrb[i] * 8, hipMemcpyDeviceToHost, 0);
+  if (e == hipSuccess) e = hipStreamSynchronize(0);
+  if (e != hipSuccess) {
+    if (host) hipHostFree(host);
+    release();
+    return fail(PSDP_EDEVICE, std::string("set-up read-back: ") + hipGetErrorString(e));
+  }
+  int rc = PSDP_OK;
+  std::string msg;
+  for (int i = 0; i < count; ++i) {
+    const int ri = setup_finish(&out[i], host + roff[i], nrb[i]);
+    if (ri && !rc) {
+      rc = ri;
+      msg = "system " + std::to_string(i) + ": " + psdp_last_error();
+    }
+  }
+  hipHostFree(host);
+  if (rc) {
+    release();
+    return fail(rc, msg);
+  }
+  return PSDP_OK;
 }
 
 int psdp_query(const psdp_sdp* s, psdp_dims* out) {

@@ -90,7 +90,8 @@ class PsdpError(RuntimeError):
 
 _lib = None
 
-EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "psdp_query",
+EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "psdp_polya_setup_batched",
+           "psdp_query",
            "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_eval_newton",
            "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version",
            "psdp_mlp_create", "psdp_mlp_param_count", "psdp_mlp_set_params", "psdp_mlp_get_params",
@@ -120,6 +121,9 @@ def load(path: str = LIB_PATH):
     lib.psdp_opts_default.restype = None
     lib.psdp_polya_setup.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int,
                                      C.POINTER(SetupOpts), C.POINTER(vp)]
+    lib.psdp_polya_setup_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                             C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(SetupOpts),
+                                             C.POINTER(vp)]
     lib.psdp_query.argtypes = [vp, C.POINTER(Dims)]
     lib.psdp_get_polya.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.psdp_ipm_solve.argtypes = [vp, C.POINTER(Opts), C.POINTER(CResult)]
@@ -240,6 +244,43 @@ def polya_setup(A, n: int, l: int, dp: int, d: int, *, da: int = 1, d1: Optional
     dims = Dims()
     _check(lib.psdp_query(h, C.byref(dims)))
     return SDP(h.value, dims)
+
+
+def polya_setup_batched(systems, *, da: int = 1, delta: float = 1e-3, eps: float = 1e-3,
+                        paper_literal: bool = False) -> list:
+    """psdp_polya_setup_batched.  systems: sequence of (A, n, l, dp, d), every A
+    a host array or every A a torch CUDA tensor.  Returns one SDP per system."""
+    lib = load()
+    systems = list(systems)
+    cnt = len(systems)
+    o = SetupOpts()
+    lib.psdp_setup_opts_default(C.byref(o))
+    o.da = da
+    o.delta, o.eps, o.paper_literal = delta, eps, int(paper_literal)
+    keep, ptrs = [], (C.c_void_p * max(cnt, 1))()
+    dev = [hasattr(s[0], "is_cuda") and s[0].is_cuda for s in systems]
+    if any(dev) and not all(dev):
+        raise ValueError("polya_setup_batched: vertices must be all on the host or all on the device")
+    o.a_on_device = int(bool(dev) and all(dev))
+    for i, (A, *_rest) in enumerate(systems):
+        if o.a_on_device:
+            import torch
+            t = A.to(torch.float64).contiguous()
+            keep.append(t)
+            ptrs[i] = t.data_ptr()
+        else:
+            a = np.ascontiguousarray(A, dtype=np.float64)
+            keep.append(a)
+            ptrs[i] = a.ctypes.data
+    ints = [(C.c_int * max(cnt, 1))(*[int(s[k]) for s in systems]) for k in (1, 2, 3, 4)]
+    out = (C.c_void_p * max(cnt, 1))()
+    _check(lib.psdp_polya_setup_batched(cnt, ptrs, ints[0], ints[1], ints[2], ints[3], C.byref(o), out))
+    res = []
+    for i in range(cnt):
+        dims = Dims()
+        _check(lib.psdp_query(out[i], C.byref(dims)))
+        res.append(SDP(out[i], dims))
+    return res
 
 
 def make_opts(**kw) -> Opts:

@@ -80,6 +80,22 @@ def test_null_arguments_rejected():
     lib.psdp_free(None)   # ignored
 
 
+def test_batched_setup_validation():
+    P = _lib()
+    lib = P.load()
+    out = (C.c_void_p * 2)()
+    assert lib.psdp_polya_setup_batched(-1, None, None, None, None, None, None, out) == -1
+    assert lib.psdp_polya_setup_batched(2, None, None, None, None, None, None, out) == -1
+    assert b"NULL" in lib.psdp_last_error()
+    assert lib.psdp_polya_setup_batched(0, None, None, None, None, None, None, None) == 0
+    A = np.zeros((2, 3, 3))
+    A[0, 0, 0] = np.nan
+    with pytest.raises(P.PsdpError) as ei:
+        P.polya_setup_batched([(A, 3, 2, 1, 1), (np.zeros((2, 3, 3)), 3, 2, 1, 1)])
+    assert ei.value.code == -1
+    assert "system 0" in str(ei.value) and "non-finite" in str(ei.value)
+
+
 def test_product_path_has_no_cpu_fallback(tmp_path):
     from paper_1411_3769_amd import polyaipm as P
     saved = P._lib

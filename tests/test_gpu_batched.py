@@ -147,3 +147,35 @@ def test_kernel_paths_match_oracle(P, asm_path, solve_path):
             assert r.asm_path == asm_path
         if solve_path >= 0:
             assert r.solve_path == solve_path
+
+
+@pytest.mark.parametrize("on_device", [False, True])
+def test_batched_setup_matches_single(P, mixed, on_device):
+    """psdp_polya_setup_batched gives each system the handle psdp_polya_setup
+    gives it: Polya tensors, scales and basis bit for bit."""
+    import torch
+    part = mixed[:24]
+
+    def vertices(sy):
+        return torch.tensor(sy.A, device="cuda", dtype=torch.float64) if on_device else sy.A
+
+    gs = P.polya_setup_batched([(vertices(sy), sy.n, sy.l, sy.dp, sy.d) for sy in part])
+    assert len(gs) == len(part)
+    for sy, g in zip(part, gs):
+        h = P.polya_setup(sy.A, sy.n, sy.l, sy.dp, sy.d)
+        a, b = g.get_polya(), h.get_polya()
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (sy.tag, k)
+        assert np.array_equal(g.basis(), h.basis())
+        h.close()
+        g.close()
+
+
+def test_batched_setup_rejects_nonfinite_device_vertices(P, mixed):
+    import torch
+    part = mixed[:3]
+    As = [torch.tensor(sy.A, device="cuda", dtype=torch.float64) for sy in part]
+    As[1][0, 0, 0] = float("nan")
+    with pytest.raises(P.PsdpError) as ei:
+        P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(As, part)])
+    assert "system 1" in str(ei.value) and "non-finite" in str(ei.value)
