@@ -890,7 +890,6 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
   // uploads the flags of the Newton step without waiting.
   set_flags(B, rs, hf);
   PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
-  GraphRun g1, g2, g3;
   // FP64 runs enqueue the next Schur assembly right behind the read-backs
   // and wait only for those (an event), so the host's decisions overlap the
   // assembly; it uses the flags of the previous step, which only adds the
@@ -905,6 +904,13 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     hipEvent_t e;
     ~EvGuard() { if (e) hipEventDestroy(e); }
   } ev_guard{ev_rb};
+  // the graphs are destroyed before the event above, and only once nothing
+  // launched here is still running (the last hoisted assembly may be)
+  GraphRun g1, g2, g3;
+  struct Drain {
+    hipStream_t s;
+    ~Drain() { hipStreamSynchronize(s); }
+  } drain{st};
   for (int it = 0;; ++it) {
     // residuals, objectives and the scalars the host decides on
     auto part1 = [&]() -> int {
