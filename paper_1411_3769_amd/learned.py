@@ -47,7 +47,7 @@ def solve_cold(systems: Sequence[W.System], batch: int = 256, label_gap: float =
     secs = 0.0
     for b0 in range(0, len(systems), batch):
         part = systems[b0:b0 + batch]
-        gs = [P.polya_setup(s.A, s.n, s.l, s.dp, s.d) for s in part]
+        gs = P.polya_setup_batched([(s.A, s.n, s.l, s.dp, s.d) for s in part])
         t0 = time.perf_counter()
         rs = P.ipm_solve_batched(gs, label_gap=label_gap, **opts)
         secs += time.perf_counter() - t0
@@ -151,7 +151,7 @@ def evaluate(model: WarmStartModel, systems: Sequence[W.System], cold: LabelSet,
     secs = 0.0
     for b0 in range(0, len(systems), batch):
         part = systems[b0:b0 + batch]
-        gs = [P.polya_setup(s.A, s.n, s.l, s.dp, s.d) for s in part]
+        gs = P.polya_setup_batched([(s.A, s.n, s.l, s.dp, s.d) for s in part])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         wy, wl = model.predict(features(part))
