@@ -989,8 +989,10 @@ __device__ __forceinline__ void assemble_pair(const AsmTile* __restrict__ tiles,
       }
       __syncthreads();
       if (k0 + KS < kcnt) fetch(k0 + KS);
+      // a partial last stage multiplies only the k-steps that hold terms
+      const int kend = min(KS, kcnt - k0);
 #pragma unroll 1
-      for (int ks = 0; ks < KS; ks += KC) {
+      for (int ks = 0; ks < kend; ks += KC) {
         const real* bT = sT + (ks + kb) * n2p + r16;
         const real* bU = sU + (ks + kb) * n2p + r16;
 #pragma unroll
@@ -1098,39 +1100,43 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
   const int ia = sa < 8 ? kTB * g1 + sa : kTB * g2 + (sa - 8);
   const int jc = sc < 8 ? kTB * g3 + sc : kTB * g4 + (sc - 8);
   const bool inb = ia < n && jc < n;
-  const int iN = ia * n + jc, iT = jc * n + ia;
-  double vT[KS], vU[KS];
+  const int iN = inb ? ia * n + jc : 0, iT = inb ? jc * n + ia : 0;
   // the next stage is fetched into registers while the current one is
-  // multiplied
+  // multiplied: the stage's term descriptors first, then every entry load
+  // (clamped, unconditional, so that all are in flight together); the
+  // coefficient (0 past the last term) is applied when the stage is staged
+  double vT[KS], vU[KS], cf[KS];
   auto fetch = [&](int k0) {
+    KTerm kt[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) kt[kk] = terms[tl.kbeg + min(k0 + kk, tl.kcnt - 1)];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      double tv = 0.0, uv = 0.0;
-      if (inb && k0 + kk < tl.kcnt) {
-        const KTerm kt = terms[tl.kbeg + k0 + kk];
-        tv = kt.coef * arena[kt.offT + (kt.tT ? iT : iN)];
-        uv = arena[kt.offU + (kt.tU ? iN : iT)];
-      }
-      vT[kk] = tv;
-      vU[kk] = uv;
+      vT[kk] = arena[kt[kk].offT + (kt[kk].tT ? iT : iN)];
+      vU[kk] = arena[kt[kk].offU + (kt[kk].tU ? iN : iT)];
+      cf[kk] = k0 + kk < tl.kcnt ? kt[kk].coef : 0.0;
     }
   };
   acc_t acc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  fetch(0);
+  if (tl.kcnt > 0) fetch(0);
   for (int k0 = 0; k0 < tl.kcnt; k0 += KS) {
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      sT[kk * 272 + sa * 17 + sc] = AP::cvt(vT[kk]);   // T[I_a][J_c]
-      sU[kk * 272 + sc * 17 + sa] = AP::cvt(vU[kk]);   // U[J_c][I_a]
+      const bool ok = inb && cf[kk] != 0.0;
+      sT[kk * 272 + sa * 17 + sc] = AP::cvt(ok ? cf[kk] * vT[kk] : 0.0);   // T[I_a][J_c]
+      sU[kk * 272 + sc * 17 + sa] = AP::cvt(ok ? vU[kk] : 0.0);            // U[J_c][I_a]
     }
     __syncthreads();
     if (k0 + KS < tl.kcnt) fetch(k0 + KS);
     const int kq = lane >> 4, r16 = lane & 15;
+    // a partial last stage multiplies only the k-steps that hold terms
+    const int kend = min(KS, tl.kcnt - k0);
 #pragma unroll
     for (int ks = 0; ks < KS; ks += KC) {
+      if (ks >= kend) break;
       const int kb = ks + (PR == 2 ? 4 * kq : kq);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
