@@ -395,9 +395,10 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
 // panel): A_ij -= sum over the super-panel's panels q of L_iq L_jq^T for every
 // tile pair right of it (depth 64 kSW), on 128 x 128 output blocks (2 x 2
 // tiles; wave w owns the 64 x 64 quadrant (w/2, w%2) as 4 x 4 MFMA tiles).
-// The depth is staged through LDS 32 columns at a time with the next chunk
-// prefetched into registers.  Only the lower triangle (column <= row) of the
-// matrix is written; rows or columns past Kpad are skipped.
+// The depth is staged through two LDS buffers 32 columns at a time, the
+// chunk after next prefetched into registers.  Only the lower triangle
+// (column <= row) of the matrix is written; rows or columns past Kpad are
+// skipped.
 constexpr int kWT = 128, kWK = 32, kWLD = kWK + 1;
 constexpr int kWRP = 256 / kWK;          // rows staged per pass
 constexpr int kWU = kWT / kWRP;          // passes (values per thread and operand)
@@ -407,8 +408,8 @@ __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restr
                                                           const int* __restrict__ st_sys,
                                                           const int* __restrict__ st_pre, int cnt,
                                                           int p) {
-  __shared__ double sa[kWT * kWLD];
-  __shared__ double sb[kWT * kWLD];
+  __shared__ double sa[2][kWT * kWLD];   // two stages: one is multiplied while
+  __shared__ double sb[2][kWT * kWLD];   // the next is written
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
   const int t = blockIdx.x - st_pre[si];
@@ -448,29 +449,39 @@ __global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restr
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  load(0);
-  for (int kc = 0; kc < D; kc += kWK) {
-    __syncthreads();
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < kWU; ++u) {
-      sa[(lr + kWRP * u) * kWLD + lk] = ra[u];
-      sb[(lr + kWRP * u) * kWLD + lk] = rb[u];
+      sa[buf][(lr + kWRP * u) * kWLD + lk] = ra[u];
+      sb[buf][(lr + kWRP * u) * kWLD + lk] = rb[u];
     }
-    __syncthreads();
-    if (kc + kWK < D) load(kc + kWK);
+  };
+  // chunk kc is multiplied from buffer cur while chunk kc + kWK (loaded one
+  // chunk earlier) is written to the other buffer and chunk kc + 2 kWK is
+  // loaded; one barrier per chunk
+  load(0);
+  stage(0);
+  if (kWK < D) load(kWK);
+  __syncthreads();
+  for (int kc = 0, cur = 0; kc < D; kc += kWK, cur ^= 1) {
 #pragma unroll
     for (int ks = 0; ks < kWK; ks += 4) {
       double av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sa[(wr + 16 * a + r16) * kWLD + ks + kq];
+      for (int a = 0; a < 4; ++a) av[a] = sa[cur][(wr + 16 * a + r16) * kWLD + ks + kq];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = sb[(wc + 16 * b + r16) * kWLD + ks + kq];
+      for (int b = 0; b < 4; ++b) bv[b] = sb[cur][(wc + 16 * b + r16) * kWLD + ks + kq];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+    if (kc + kWK < D) {
+      stage(cur ^ 1);
+      if (kc + 2 * kWK < D) load(kc + 2 * kWK);
+    }
+    __syncthreads();
   }
   // C -= acc, one 16-row stripe at a time: all sixteen loads of a stripe are
   // issued before any store (clamped addresses; masked stores)
