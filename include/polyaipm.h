@@ -155,8 +155,9 @@ typedef struct {
                           /* workgroup (n^2 <= 128), 0 grouped 64 x 64 tiles, -1     */
                           /* (default) chosen per block order by the autotuner       */
     int    solve_path;    /* triangular solves: 1 one workgroup per system (at most  */
-                          /* 32 tiles of 64), 0 one launch per tile step, -1         */
-                          /* (default) chosen per tile count by the autotuner        */
+                          /* 32 tiles of 64), 0 by groups of 8 tiles (two launches   */
+                          /* per group and sweep), -1 (default) chosen per tile      */
+                          /* count by the autotuner                                  */
     int    use_graph;     /* 1 (default): each iteration's launches are captured once */
                           /* into two hipGraphs and replayed; 0: launched one by one */
     double label_gap;     /* > 0: record in psdp_result.label_y / label_logx the     */

@@ -667,7 +667,7 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
 // r_i -= L_{i,group} z_group (k_trsv_gfwd).  Backward, groups in reverse:
 // the diagonal block's transposed sweep (writes x) and then every column
 // tile left of it, z_c -= L_{group,c}^T x_group (k_trsv_gbwd).  Two launches
-// per group and direction instead of one per tile step; the rectangular
+// per group and direction instead of one per tile; the rectangular
 // updates read L at full width.
 __global__ void __launch_bounds__(kSvT) k_trsv_gdiag(const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags,

@@ -254,7 +254,8 @@ static size_t tabsize(const std::vector<T>& v) {
 
 // Builds every per-batch table on the host and allocates the arena.
 // Kernel paths per system: whole-pair assembly (n^2 <= 128 only) or grouped
-// tiles; the whole solve in one workgroup (P <= kSmallP only) or tile steps.
+// tiles; the whole solve in one workgroup (P <= kSmallP only) or by groups
+// of kSG tiles.
 struct Choice {
   std::vector<char> pair, small;
 };
@@ -1149,7 +1150,7 @@ static int warm_project(Batch& B, hipStream_t st, const psdp_opts& o, const std:
 // ---------------------------------------------------------------------------
 // Autotuner: for each block order n with n^2 <= 128 the assembly path (whole
 // pairs or grouped tiles) and for each tile count P <= kSmallP the solve path
-// (one workgroup per system or tile steps) are timed once per process with
+// (one workgroup per system or groups of tiles) are timed once per process with
 // HIP events on up to 8 systems of the batch, and the faster is kept.  Both
 // paths of each choice compute the same quantities (they differ in rounding
 // order only).
