@@ -230,11 +230,13 @@ int psdp_polya_setup(const double* A, int n, int l, int dp, int d,
  * psdp_polya_setup_batched -- the set-up of psdp_polya_setup (Section III,
  * Alg. 1) for count systems in one call: A[i] (host or device per o, as for
  * psdp_polya_setup), n[i], l[i], dp[i], d[i] describe system i; o (or NULL)
- * applies to all.  Every system's kernels are queued before one wait for all
- * read-backs, so the call costs about one set-up, not count of them.  out
+ * applies to all.  One device allocation holds every system's set-up, each
+ * set-up kernel is one launch over all systems and one read-back serves
+ * them all, so the call costs about one set-up, not count of them.  out
  * (count handles, owned by the caller as from psdp_polya_setup) is all set
- * on success; on any error no handle is returned (out[i] = NULL), earlier
- * ones are released, and the message names the failing system.
+ * on success; the shared device allocation is returned when the last of the
+ * count handles is freed.  On any error no handle is returned (out[i] =
+ * NULL), nothing stays allocated, and the message names the failing system.
  */
 int psdp_polya_setup_batched(int count, const double* const* A, const int* n, const int* l,
                              const int* dp, const int* d, const psdp_setup_opts* o,
@@ -302,7 +304,8 @@ int psdp_eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psd
  */
 int psdp_basis(const psdp_sdp* sdp, int* pairs);
 
-/* Release a handle (NULL is ignored). */
+/* Release a handle (NULL is ignored).  Device memory of a batched set-up
+ * is returned with the last handle of that call. */
 void psdp_free(psdp_sdp* sdp);
 
 /* Thread-local description of the last error of this thread. */

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -125,8 +126,8 @@ struct psdp_sdp {
   std::vector<double> betaf;         // host copies of the device set-up
   std::vector<double> cdiag_h, scale_h;
   int device;
-  void* dmem;
-  size_t dbytes;
+  std::shared_ptr<void> dmem;   // device block, shared by the handles of one set-up call
+  size_t dbytes;                // this handle's part of it
   double* dA;
   int64_t* dbeta;
   int64_t* dcoef;

@@ -11,7 +11,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -94,6 +97,41 @@ BasisInfo make_basis(int n) {
 // kernels (H1)
 // ---------------------------------------------------------------------------
 
+// What the set-up kernels need of one system; one array of these serves a
+// whole set-up call, and each kernel's grid is the concatenation of the
+// systems' grids (prefix table pre[count + 1] of their block counts).
+struct SetupDesc {
+  const int* Wp;
+  const int* WL;
+  const int* WM;
+  const int* Wa;
+  const double* Asrc;   // device vertices to gather into A, or null (uploaded)
+  double* A;
+  int64_t* beta;
+  double* betaf;
+  int64_t* coef;
+  double* H;
+  double* scale;
+  double* cdiag;
+  double* bad;
+  double delta, eps;
+  int64_t nA;           // Na n^2
+  int l, L0, L, M, Na, n, d1, d2, dp, dM;
+};
+
+constexpr int kGatherBlock = 1024;   // doubles per workgroup of the vertex gather
+
+// the system whose block range holds block b (largest i with pre[i] <= b)
+__device__ inline int find_sys(const int64_t* __restrict__ pre, int count, int64_t b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // d! / prod delta_i! by successive exact divisions (each partial quotient is
 // an integer because the remaining denominators divide the remaining
 // numerator).
@@ -103,44 +141,63 @@ __device__ inline int64_t dev_multinomial(int d, const int* delta, int l) {
   return r;
 }
 
-__global__ void k_beta(const int* __restrict__ Wp, const int* __restrict__ WL, int l, int L0, int L,
-                       int d1, int64_t* __restrict__ beta, double* __restrict__ betaf) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= L0 * L) return;
-  const int h = t / L, j = t % L;
+// device-resident vertices into the handle's own copy
+__global__ void k_gather_A(const SetupDesc* __restrict__ D, const int64_t* __restrict__ pre,
+                           int count) {
+  const int i = find_sys(pre, count, blockIdx.x);
+  const SetupDesc& s = D[i];
+  const int64_t e0 = ((int64_t)blockIdx.x - pre[i]) * kGatherBlock;
+  for (int k = threadIdx.x; k < kGatherBlock; k += blockDim.x) {
+    const int64_t e = e0 + k;
+    if (e < s.nA) s.A[e] = s.Asrc[e];
+  }
+}
+
+// beta_{h,j} = d1! / (w_j - w_h)! for w_j >= w_h, else 0 (one thread each)
+__global__ void k_beta(const SetupDesc* __restrict__ D, const int64_t* __restrict__ pre,
+                       int count) {
+  const int i = find_sys(pre, count, blockIdx.x);
+  const SetupDesc& s = D[i];
+  const int64_t t = ((int64_t)blockIdx.x - pre[i]) * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)s.L0 * s.L) return;
+  const int h = (int)(t / s.L), j = (int)(t % s.L);
+  const int l = s.l;
   int delta[32];
   bool ok = true;
-  for (int i = 0; i < l; ++i) {
-    delta[i] = WL[j * l + i] - Wp[h * l + i];
-    ok = ok && delta[i] >= 0;
+  for (int q = 0; q < l; ++q) {
+    delta[q] = s.WL[j * l + q] - s.Wp[h * l + q];
+    ok = ok && delta[q] >= 0;
   }
-  const int64_t v = ok ? dev_multinomial(d1, delta, l) : 0;
-  beta[t] = v;
-  betaf[t] = (double)v;
+  const int64_t v = ok ? dev_multinomial(s.d1, delta, l) : 0;
+  s.beta[t] = v;
+  s.betaf[t] = (double)v;
 }
 
 // one workgroup per (m, h): integer weights c[h][m][lam] into LDS, then
 // H[m][h] = sum_lam c * A_lam entrywise.
-__global__ void k_coef_H(const int* __restrict__ Wp, const int* __restrict__ WM,
-                         const int* __restrict__ Wa, int l, int L0, int M, int Na, int n, int d2,
-                         const double* __restrict__ A, int64_t* __restrict__ coef,
-                         double* __restrict__ H) {
+__global__ void k_coef_H(const SetupDesc* __restrict__ D, const int64_t* __restrict__ pre,
+                         int count) {
   extern __shared__ int64_t s_c[];
-  const int m = blockIdx.x / L0, h = blockIdx.x % L0;
+  const int i = find_sys(pre, count, blockIdx.x);
+  const SetupDesc& s = D[i];
+  const int64_t loc = (int64_t)blockIdx.x - pre[i];
+  const int m = (int)(loc / s.L0), h = (int)(loc % s.L0);
+  const int l = s.l, Na = s.Na, M = s.M;
   for (int lam = threadIdx.x; lam < Na; lam += blockDim.x) {
     int delta[32];
     bool ok = true;
-    for (int i = 0; i < l; ++i) {
-      delta[i] = WM[m * l + i] - Wp[h * l + i] - Wa[lam * l + i];
-      ok = ok && delta[i] >= 0;
+    for (int q = 0; q < l; ++q) {
+      delta[q] = s.WM[m * l + q] - s.Wp[h * l + q] - s.Wa[lam * l + q];
+      ok = ok && delta[q] >= 0;
     }
-    const int64_t v = ok ? dev_multinomial(d2, delta, l) : 0;
+    const int64_t v = ok ? dev_multinomial(s.d2, delta, l) : 0;
     s_c[lam] = v;
-    coef[((int64_t)h * M + m) * Na + lam] = v;
+    s.coef[((int64_t)h * M + m) * Na + lam] = v;
   }
   __syncthreads();
-  const int nn = n * n;
-  double* out = H + ((int64_t)m * L0 + h) * nn;
+  const int nn = s.n * s.n;
+  const double* A = s.A;
+  double* out = s.H + ((int64_t)m * s.L0 + h) * nn;
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
     double acc = 0.0;
     for (int lam = 0; lam < Na; ++lam) {
@@ -151,34 +208,37 @@ __global__ void k_coef_H(const int* __restrict__ Wp, const int* __restrict__ WM,
   }
 }
 
-// *bad = 1 if any of the n values is not finite (one workgroup)
-__global__ void k_nonfinite(const double* __restrict__ v, int64_t n, double* bad) {
+// *bad = 1 if any entry of the system's A is not finite (one workgroup per
+// system)
+__global__ void k_nonfinite(const SetupDesc* __restrict__ D) {
+  const SetupDesc& s = D[blockIdx.x];
   __shared__ int any;
   if (threadIdx.x == 0) any = 0;
   __syncthreads();
   int mine = 0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mine |= !isfinite(v[i]);
+  for (int64_t e = threadIdx.x; e < s.nA; e += blockDim.x) mine |= !isfinite(s.A[e]);
   if (mine) atomicOr(&any, 1);
   __syncthreads();
-  if (threadIdx.x == 0) *bad = any ? 1.0 : 0.0;
+  if (threadIdx.x == 0) *s.bad = any ? 1.0 : 0.0;
 }
 
-__global__ void k_scale(const int* __restrict__ Wp, const int* __restrict__ WL,
-                        const int* __restrict__ WM, int l, int L0, int L, int M, int dp,
-                        int dM, const int64_t* __restrict__ beta, double delta, double eps,
-                        double* __restrict__ scale, double* __restrict__ cdiag) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= L + M) return;
+__global__ void k_scale(const SetupDesc* __restrict__ D, const int64_t* __restrict__ pre,
+                        int count) {
+  const int i = find_sys(pre, count, blockIdx.x);
+  const SetupDesc& s = D[i];
+  const int j = (int)(((int64_t)blockIdx.x - pre[i]) * blockDim.x + threadIdx.x);
+  const int L = s.L, l = s.l;
+  if (j >= L + s.M) return;
   if (j < L) {
     // eq. Cj: s_j = sum_h beta_{h,j} dp!/h!
-    int64_t s = 0;
-    for (int h = 0; h < L0; ++h) s += beta[h * L + j] * dev_multinomial(dp, Wp + h * l, l);
-    scale[j] = (double)s;
-    cdiag[j] = delta * (double)s;
+    int64_t v = 0;
+    for (int h = 0; h < s.L0; ++h) v += s.beta[h * L + j] * dev_multinomial(s.dp, s.Wp + h * l, l);
+    s.scale[j] = (double)v;
+    s.cdiag[j] = s.delta * (double)v;
   } else {
-    const int64_t s = dev_multinomial(dM, WM + (j - L) * l, l);
-    scale[j] = (double)s;
-    cdiag[j] = eps * (double)s;
+    const int64_t v = dev_multinomial(s.dM, s.WM + (j - L) * l, l);
+    s.scale[j] = (double)v;
+    s.cdiag[j] = s.eps * (double)v;
   }
 }
 
@@ -233,251 +293,288 @@ const char* psdp_last_error(void) { return g_err.c_str(); }
 
 const char* psdp_version(void) { return "polyaipm 0.1 (gfx950)"; }
 
-// Set-up of one system up to its kernels, all asynchronous on the null
-// stream; *rb receives the device address of its read-back region (betaf,
-// scale, cdiag, non-finite flag of A: *nrb doubles), which setup_finish
-// parses once the stream has drained.
-static int setup_begin(const double* A, int n, int l, int dp, int d, const psdp_setup_opts* o,
-                       psdp_sdp** out, const double** rb_dev, int64_t* nrb_out) {
+// Host part of one system's set-up: checks, dimensions, exponent tables,
+// masks and the tiled basis.  Allocates no device memory.
+static int plan_system(const double* A, int n, int l, int dp, int d, const psdp_setup_opts& opt,
+                       psdp_sdp** out) {
+  if (!A) return fail(PSDP_EINVAL, "A is NULL");
+  const int da = opt.da;
+  const int d1 = opt.d1 >= 0 ? opt.d1 : d;
+  const int d2 = opt.d2 >= 0 ? opt.d2 : d;
+  if (n < 1 || n > kMaxN) return fail(PSDP_EINVAL, "n must be in [1, 128]");
+  if (l < 1 || l > 32) return fail(PSDP_EINVAL, "l must be in [1, 32]");
+  if (dp < 0 || da < 1 || d1 < 0 || d2 < 0) return fail(PSDP_EINVAL, "negative degree");
+  if (!(opt.delta > 0.0) || !(opt.eps >= 0.0) || !std::isfinite(opt.delta) ||
+      !std::isfinite(opt.eps))
+    return fail(PSDP_EINVAL, "delta must be > 0 and eps >= 0");
+  if (dp + d1 > kMaxDeg || dp + da + d2 > kMaxDeg)
+    return fail(PSDP_EOVERFLOW, "Polya degree above 20: multinomials exceed int64");
+  const int64_t L0 = binom(l + dp - 1, l - 1), L = binom(l + dp + d1 - 1, l - 1);
+  const int64_t M = binom(l + dp + da + d2 - 1, l - 1), Na = binom(l + da - 1, l - 1);
+  const int64_t Nt = (int64_t)n * (n + 1) / 2;
+  const int64_t K = L0 * Nt;
+  if (L0 > 100000 || L > 10000000 || M > 10000000 || Na > 4096 || K > 200000 ||
+      L0 * L > INT32_MAX || L0 * M > INT32_MAX)
+    return fail(PSDP_EOVERFLOW, "problem dimensions too large");
+  if (!opt.a_on_device) {
+    for (int64_t i = 0; i < Na * n * n; ++i)
+      if (!std::isfinite(A[i])) return fail(PSDP_EINVAL, "A has a non-finite entry");
+  }
+  psdp_sdp* s = new psdp_sdp();
+  s->n = n; s->l = l; s->da = da; s->dp = dp; s->d1 = d1; s->d2 = d2;
+  s->L0 = (int)L0; s->L = (int)L; s->M = (int)M; s->Na = (int)Na; s->Nt = (int)Nt;
+  s->nb = (int)(L + M);
+  s->K = K;
+  s->Kpad = round_up(K, kNB);
+  s->delta = opt.delta;
+  s->eps = opt.paper_literal ? 0.0 : opt.eps;
+  s->paper_literal = opt.paper_literal;
+  s->device = -1;
+  monomials(l, dp, s->Wp);
+  monomials(l, dp + d1, s->WL);
+  monomials(l, dp + da + d2, s->WM);
+  monomials(l, da, s->Wa);
+  s->bmask.assign(L0 * L, 0);
+  for (int h = 0; h < L0; ++h)
+    for (int j = 0; j < L; ++j) {
+      bool ge = true;
+      for (int i = 0; i < l; ++i) ge = ge && s->WL[j * l + i] >= s->Wp[h * l + i];
+      s->bmask[h * L + j] = ge;
+    }
+  s->hmask.assign(M * L0, 0);
+  for (int m = 0; m < M; ++m)
+    for (int h = 0; h < L0; ++h) {
+      bool ge = true;
+      for (int i = 0; i < l; ++i) ge = ge && s->WM[m * l + i] >= s->Wp[h * l + i];
+      s->hmask[m * L0 + h] = ge;
+    }
+  s->basis = make_basis(n);
+  *out = s;
+  return PSDP_OK;
+}
+
+// The factorial table goes to constant memory once per device.
+static int upload_factorials(int dev) {
+  static std::mutex mu;
+  static bool done[64] = {false};
+  if (dev < 0 || dev >= 64) return fail(PSDP_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> g(mu);
+  if (done[dev]) return PSDP_OK;
+  int64_t fact[kMaxDeg + 1];
+  for (int i = 0; i <= kMaxDeg; ++i) fact[i] = host_fact(i);
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fact, sizeof(fact)) != hipSuccess)
+    return fail(PSDP_EDEVICE, "copy of the factorial table failed");
+  done[dev] = true;
+  return PSDP_OK;
+}
+
+// Set-up of count systems with one device block shared by their handles:
+// one upload (descriptors, block prefix tables, exponent tables and host
+// vertices), one launch per set-up kernel over all systems, one read-back
+// (betaf, scale, cdiag and the non-finite flag of A of every system, held
+// contiguously).  label: prefix error messages with the failing system.
+static int setup_many(int count, const double* const* A, const int* n, const int* l,
+                      const int* dp, const int* d, const psdp_setup_opts* o, psdp_sdp** out,
+                      bool label) {
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  auto release = [&]() {
+    for (int i = 0; i < count; ++i) {
+      delete out[i];
+      out[i] = nullptr;
+    }
+  };
+  auto fail_sys = [&](int i, int code, const std::string& msg) {
+    release();
+    return fail(code, label ? "system " + std::to_string(i) + ": " + msg : msg);
+  };
   try {
-    if (!out) return fail(PSDP_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!A) return fail(PSDP_EINVAL, "A is NULL");
     psdp_setup_opts opt;
     psdp_setup_opts_default(&opt);
     if (o) opt = *o;
-    const int da = opt.da;
-    const int d1 = opt.d1 >= 0 ? opt.d1 : d;
-    const int d2 = opt.d2 >= 0 ? opt.d2 : d;
-    if (n < 1 || n > kMaxN) return fail(PSDP_EINVAL, "n must be in [1, 128]");
-    if (l < 1 || l > 32) return fail(PSDP_EINVAL, "l must be in [1, 32]");
-    if (dp < 0 || da < 1 || d1 < 0 || d2 < 0) return fail(PSDP_EINVAL, "negative degree");
-    if (!(opt.delta > 0.0) || !(opt.eps >= 0.0) || !std::isfinite(opt.delta) ||
-        !std::isfinite(opt.eps))
-      return fail(PSDP_EINVAL, "delta must be > 0 and eps >= 0");
-    if (dp + d1 > kMaxDeg || dp + da + d2 > kMaxDeg)
-      return fail(PSDP_EOVERFLOW, "Polya degree above 20: multinomials exceed int64");
-    const int64_t L0 = binom(l + dp - 1, l - 1), L = binom(l + dp + d1 - 1, l - 1);
-    const int64_t M = binom(l + dp + da + d2 - 1, l - 1), Na = binom(l + da - 1, l - 1);
-    const int64_t Nt = (int64_t)n * (n + 1) / 2;
-    const int64_t K = L0 * Nt;
-    if (L0 > 100000 || L > 10000000 || M > 10000000 || Na > 4096 || K > 200000)
-      return fail(PSDP_EOVERFLOW, "problem dimensions too large");
-    if (!opt.a_on_device) {
-      for (int64_t i = 0; i < Na * n * n; ++i)
-        if (!std::isfinite(A[i])) return fail(PSDP_EINVAL, "A has a non-finite entry");
+    for (int i = 0; i < count; ++i) {
+      const int rc = plan_system(A[i], n[i], l[i], dp[i], d[i], opt, &out[i]);
+      if (rc) return fail_sys(i, rc, psdp_last_error());
     }
+    if (count == 0) return PSDP_OK;
+    // first device call: after every argument has been checked
     int dev = 0;
-    PSDP_HIP(hipGetDevice(&dev));
+    if (const hipError_t e = hipGetDevice(&dev)) {
+      release();
+      return fail(PSDP_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < count; ++i) out[i]->device = dev;
+    if (const int rc = upload_factorials(dev)) {
+      const std::string msg = psdp_last_error();
+      release();
+      return fail(rc, msg);
+    }
 
-    psdp_sdp* s = new psdp_sdp();
-    s->n = n; s->l = l; s->da = da; s->dp = dp; s->d1 = d1; s->d2 = d2;
-    s->L0 = (int)L0; s->L = (int)L; s->M = (int)M; s->Na = (int)Na; s->Nt = (int)Nt;
-    s->nb = (int)(L + M);
-    s->K = K;
-    s->Kpad = round_up(K, kNB);
-    s->delta = opt.delta;
-    s->eps = opt.paper_literal ? 0.0 : opt.eps;
-    s->paper_literal = opt.paper_literal;
-    s->device = dev;
-    monomials(l, dp, s->Wp);
-    monomials(l, dp + d1, s->WL);
-    monomials(l, dp + da + d2, s->WM);
-    monomials(l, da, s->Wa);
-    s->bmask.assign(L0 * L, 0);
-    for (int h = 0; h < L0; ++h)
-      for (int j = 0; j < L; ++j) {
-        bool ge = true;
-        for (int i = 0; i < l; ++i) ge = ge && s->WL[j * l + i] >= s->Wp[h * l + i];
-        s->bmask[h * L + j] = ge;
-      }
-    s->hmask.assign(M * L0, 0);
-    for (int m = 0; m < M; ++m)
-      for (int h = 0; h < L0; ++h) {
-        bool ge = true;
-        for (int i = 0; i < l; ++i) ge = ge && s->WM[m * l + i] >= s->Wp[h * l + i];
-        s->hmask[m * L0 + h] = ge;
-      }
-    s->basis = make_basis(n);
-
-    // one device allocation for the handle
-    const int64_t nn = (int64_t)n * n;
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t r = off; off += (bytes + 255) / 256 * 256; return r; };
-    const size_t oA = take(Na * nn * 8), oB = take(L0 * L * 8), oC = take(L0 * M * Na * 8);
-    const size_t oH = take(M * L0 * nn * 8);
-    // read-back region, contiguous: betaf, scale, cdiag, non-finite flag of A
-    const int64_t nrb = L0 * L + 2 * (L + M) + 1;
-    const size_t oRb = take(nrb * 8);
-    const size_t oBf = oRb, oS = oRb + L0 * L * 8, oCd = oS + (L + M) * 8, oBad = oCd + (L + M) * 8;
-    // integer tables, contiguous: basis, Wp, WL, WM, Wa
-    std::vector<int> tab;
-    tab.insert(tab.end(), s->basis.pairs.begin(), s->basis.pairs.end());
-    const size_t iWp = tab.size();
-    tab.insert(tab.end(), s->Wp.begin(), s->Wp.end());
-    const size_t iWL = tab.size();
-    tab.insert(tab.end(), s->WL.begin(), s->WL.end());
-    const size_t iWM = tab.size();
-    tab.insert(tab.end(), s->WM.begin(), s->WM.end());
-    const size_t iWa = tab.size();
-    tab.insert(tab.end(), s->Wa.begin(), s->Wa.end());
-    const size_t oBa = take(tab.size() * 4);
-    const size_t oWp = oBa + iWp * 4, oWL = oBa + iWL * 4, oWM = oBa + iWM * 4, oWa = oBa + iWa * 4;
-    s->dbytes = off;
-    if (hipMalloc(&s->dmem, off) != hipSuccess) {
-      delete s;
+    // layout of the block: [upload | read-back | work]
+    const bool dev_a = opt.a_on_device != 0;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    std::vector<int64_t> preA(count + 1, 0), preB(count + 1, 0), preH(count + 1, 0),
+        preS(count + 1, 0), roff(count + 1, 0);
+    std::vector<size_t> oTab(count), oAu(count), oWork(count);
+    size_t up = al(count * sizeof(SetupDesc)) + 4 * al((count + 1) * sizeof(int64_t));
+    const size_t oPre = al(count * sizeof(SetupDesc));
+    int maxNa = 1;
+    for (int i = 0; i < count; ++i) {
+      const psdp_sdp* s = out[i];
+      const int64_t nA = (int64_t)s->Na * s->n * s->n;
+      const size_t ntab = s->basis.pairs.size() + s->Wp.size() + s->WL.size() + s->WM.size() +
+                          s->Wa.size();
+      oTab[i] = up;
+      up += al(ntab * 4);
+      oAu[i] = up;
+      if (!dev_a) up += al(nA * 8);
+      preA[i + 1] = preA[i] + (dev_a ? (nA + kGatherBlock - 1) / kGatherBlock : 0);
+      preB[i + 1] = preB[i] + ((int64_t)s->L0 * s->L + 255) / 256;
+      preH[i + 1] = preH[i] + (int64_t)s->M * s->L0;
+      preS[i + 1] = preS[i] + ((int64_t)s->L + s->M + 255) / 256;
+      roff[i + 1] = roff[i] + (int64_t)s->L0 * s->L + 2 * ((int64_t)s->L + s->M) + 1;
+      maxNa = std::max(maxNa, s->Na);
+    }
+    if (preB[count] > INT32_MAX || preH[count] > INT32_MAX || preS[count] > INT32_MAX ||
+        preA[count] > INT32_MAX) {
+      release();
+      return fail(PSDP_EOVERFLOW, "set-up grids too large for one call");
+    }
+    const size_t oRb = al(up);
+    size_t off = oRb + al(roff[count] * 8);
+    for (int i = 0; i < count; ++i) {
+      const psdp_sdp* s = out[i];
+      const int64_t nA = (int64_t)s->Na * s->n * s->n;
+      oWork[i] = off;
+      off += al((int64_t)s->L0 * s->L * 8) + al((int64_t)s->L0 * s->M * s->Na * 8) +
+             al((int64_t)s->M * s->L0 * s->n * s->n * 8) + (dev_a ? al(nA * 8) : 0);
+    }
+    void* raw = nullptr;
+    if (hipMalloc(&raw, off) != hipSuccess) {
+      (void)hipGetLastError();
+      release();
       return fail(PSDP_ENOMEM, "device allocation for the set-up failed");
     }
-    char* base = (char*)s->dmem;
-    s->dA = (double*)(base + oA);
-    s->dbeta = (int64_t*)(base + oB);
-    s->dcoef = (int64_t*)(base + oC);
-    s->dH = (double*)(base + oH);
-    s->dbetaf = (double*)(base + oBf);
-    s->dscale = (double*)(base + oS);
-    s->dcdiag = (double*)(base + oCd);
-    s->dbasis = (int*)(base + oBa);
-    int* dWp = (int*)(base + oWp);
-    int* dWL = (int*)(base + oWL);
-    int* dWM = (int*)(base + oWM);
-    int* dWa = (int*)(base + oWa);
+    std::shared_ptr<void> block(raw, [](void* p) { (void)hipFree(p); });
+    char* base = (char*)raw;
 
-    int64_t fact[kMaxDeg + 1];
-    for (int i = 0; i <= kMaxDeg; ++i) fact[i] = host_fact(i);
-    auto cleanup = [&](int code, const std::string& msg) {
-      hipFree(s->dmem);
-      delete s;
-      return fail(code, msg);
-    };
-    // the factorial table goes to constant memory once per device
-    static bool fact_done[64] = {false};
-    if (dev < 0 || dev >= 64) return cleanup(PSDP_EDEVICE, "device index out of range");
-    if (!fact_done[dev]) {
-      if (hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fact, sizeof(fact)) != hipSuccess)
-        return cleanup(PSDP_EDEVICE, "copy of the factorial table failed");
-      fact_done[dev] = true;
+    // host image of the upload region
+    std::vector<char> img(up);
+    SetupDesc* hd = (SetupDesc*)img.data();
+    for (int i = 0; i < count; ++i) {
+      psdp_sdp* s = out[i];
+      const int64_t nA = (int64_t)s->Na * s->n * s->n;
+      int* tab = (int*)(img.data() + oTab[i]);
+      size_t t = 0;
+      auto put = [&](const std::vector<int>& v) {
+        const size_t r = t;
+        std::memcpy(tab + t, v.data(), v.size() * 4);
+        t += v.size();
+        return r;
+      };
+      const size_t iBa = put(s->basis.pairs), iWp = put(s->Wp), iWL = put(s->WL),
+                   iWM = put(s->WM), iWa = put(s->Wa);
+      int* dtab = (int*)(base + oTab[i]);
+      char* w = base + oWork[i];
+      s->dbeta = (int64_t*)w;
+      w += al((int64_t)s->L0 * s->L * 8);
+      s->dcoef = (int64_t*)w;
+      w += al((int64_t)s->L0 * s->M * s->Na * 8);
+      s->dH = (double*)w;
+      w += al((int64_t)s->M * s->L0 * s->n * s->n * 8);
+      if (dev_a) {
+        s->dA = (double*)w;
+      } else {
+        s->dA = (double*)(base + oAu[i]);
+        std::memcpy(img.data() + oAu[i], A[i], nA * 8);
+      }
+      double* rb = (double*)(base + oRb) + roff[i];
+      const int64_t LL = (int64_t)s->L0 * s->L, nbk = (int64_t)s->L + s->M;
+      s->dbetaf = rb;
+      s->dscale = rb + LL;
+      s->dcdiag = rb + LL + nbk;
+      s->dbasis = dtab + iBa;
+      s->dmem = block;
+      s->dbytes = (oAu[i] - oTab[i]) + (dev_a ? 0 : al(nA * 8)) + (roff[i + 1] - roff[i]) * 8 +
+                  (i + 1 < count ? oWork[i + 1] : off) - oWork[i];
+      SetupDesc& q = hd[i];
+      q.Wp = dtab + iWp;
+      q.WL = dtab + iWL;
+      q.WM = dtab + iWM;
+      q.Wa = dtab + iWa;
+      q.Asrc = dev_a ? A[i] : nullptr;
+      q.A = s->dA;
+      q.beta = s->dbeta;
+      q.betaf = s->dbetaf;
+      q.coef = s->dcoef;
+      q.H = s->dH;
+      q.scale = s->dscale;
+      q.cdiag = s->dcdiag;
+      q.bad = rb + LL + 2 * nbk;
+      q.delta = s->delta;
+      q.eps = s->eps;
+      q.nA = nA;
+      q.l = s->l; q.L0 = s->L0; q.L = s->L; q.M = s->M; q.Na = s->Na; q.n = s->n;
+      q.d1 = s->d1; q.d2 = s->d2; q.dp = s->dp; q.dM = s->dp + s->da + s->d2;
     }
-    hipError_t e = hipSuccess;
-    e = hipMemcpyAsync(s->dA, A, Na * nn * 8,
-                       opt.a_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->dbasis, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, 0);
-    if (e != hipSuccess) return cleanup(PSDP_EDEVICE, std::string("set-up copy: ") + hipGetErrorString(e));
+    const size_t pstride = al((count + 1) * sizeof(int64_t));
+    const std::vector<int64_t>* pres[4] = {&preA, &preB, &preH, &preS};
+    for (int k = 0; k < 4; ++k)
+      std::memcpy(img.data() + oPre + k * pstride, pres[k]->data(), (count + 1) * 8);
+    const SetupDesc* dD = (const SetupDesc*)base;
+    const int64_t* dpre[4];
+    for (int k = 0; k < 4; ++k) dpre[k] = (const int64_t*)(base + oPre + k * pstride);
 
-    {
-      const int nt = (int)(L0 * L);
-      hipLaunchKernelGGL(k_beta, dim3((nt + 255) / 256), dim3(256), 0, 0, dWp, dWL, l, (int)L0,
-                         (int)L, d1, s->dbeta, s->dbetaf);
-      hipLaunchKernelGGL(k_coef_H, dim3((unsigned)(M * L0)), dim3(256), Na * 8, 0, dWp, dWM, dWa, l,
-                         (int)L0, (int)M, (int)Na, n, d2, s->dA, s->dcoef, s->dH);
-      const int nbk = (int)(L + M);
-      hipLaunchKernelGGL(k_scale, dim3((nbk + 255) / 256), dim3(256), 0, 0, dWp, dWL, dWM, l,
-                         (int)L0, (int)L, (int)M, dp, dp + da + d2, s->dbeta, s->delta, s->eps,
-                         s->dscale, s->dcdiag);
-      double* dbad = (double*)(base + oBad);
-      hipLaunchKernelGGL(k_nonfinite, dim3(1), dim3(256), 0, 0, s->dA, Na * nn, dbad);
+    hipError_t e = hipMemcpyAsync(base, img.data(), up, hipMemcpyHostToDevice, 0);
+    if (e == hipSuccess) {
+      if (preA[count] > 0)
+        hipLaunchKernelGGL(k_gather_A, dim3((unsigned)preA[count]), dim3(256), 0, 0, dD, dpre[0],
+                           count);
+      hipLaunchKernelGGL(k_beta, dim3((unsigned)preB[count]), dim3(256), 0, 0, dD, dpre[1], count);
+      hipLaunchKernelGGL(k_coef_H, dim3((unsigned)preH[count]), dim3(256), maxNa * 8, 0, dD,
+                         dpre[2], count);
+      hipLaunchKernelGGL(k_scale, dim3((unsigned)preS[count]), dim3(256), 0, 0, dD, dpre[3], count);
+      hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)count), dim3(256), 0, 0, dD);
       e = hipGetLastError();
-      if (e != hipSuccess) return cleanup(PSDP_EDEVICE, std::string("set-up kernels: ") + hipGetErrorString(e));
     }
-    *rb_dev = s->dbetaf;
-    *nrb_out = nrb;
-    *out = s;
+    // one read-back (it also waits for the kernels)
+    std::vector<double> rbh(roff[count]);
+    if (e == hipSuccess)
+      e = hipMemcpy(rbh.data(), base + oRb, roff[count] * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(0);
+      release();
+      return fail(PSDP_EDEVICE, std::string("set-up on the device: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < count; ++i) {
+      psdp_sdp* s = out[i];
+      const double* rb = rbh.data() + roff[i];
+      const int64_t LL = (int64_t)s->L0 * s->L, nbk = (int64_t)s->L + s->M;
+      if (rb[LL + 2 * nbk] != 0.0) return fail_sys(i, PSDP_EINVAL, "A has a non-finite entry");
+      s->betaf.assign(rb, rb + LL);
+      s->scale_h.assign(rb + LL, rb + LL + nbk);
+      s->cdiag_h.assign(rb + LL + nbk, rb + LL + 2 * nbk);
+    }
     return PSDP_OK;
   } catch (const std::bad_alloc&) {
+    release();
     return fail(PSDP_ENOMEM, "host allocation failed");
   } catch (...) {
-    return fail(PSDP_EINVAL, "unexpected exception in psdp_polya_setup");
+    release();
+    return fail(PSDP_EINVAL, "unexpected exception in the set-up");
   }
-}
-
-// Parse the read-back of a begun set-up (host copy rb); on a non-finite A the
-// handle is released and *out cleared.
-static int setup_finish(psdp_sdp** out, const double* rb, int64_t nrb) {
-  psdp_sdp* s = *out;
-  if (rb[nrb - 1] != 0.0) {
-    hipFree(s->dmem);
-    delete s;
-    *out = nullptr;
-    return fail(PSDP_EINVAL, "A has a non-finite entry");
-  }
-  const int64_t L0 = s->L0, L = s->L, M = s->M;
-  s->betaf.assign(rb, rb + L0 * L);
-  s->scale_h.assign(rb + L0 * L, rb + L0 * L + (L + M));
-  s->cdiag_h.assign(rb + L0 * L + (L + M), rb + L0 * L + 2 * (L + M));
-  return PSDP_OK;
 }
 
 int psdp_polya_setup(const double* A, int n, int l, int dp, int d, const psdp_setup_opts* o,
                      psdp_sdp** out) {
-  const double* rb_dev = nullptr;
-  int64_t nrb = 0;
-  int rc = setup_begin(A, n, l, dp, d, o, out, &rb_dev, &nrb);
-  if (rc) return rc;
-  try {
-    // one read-back (it also waits for the kernels)
-    std::vector<double> rb(nrb);
-    const hipError_t e = hipMemcpy(rb.data(), rb_dev, nrb * 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) {
-      psdp_free(*out);
-      *out = nullptr;
-      return fail(PSDP_EDEVICE, std::string("set-up read-back: ") + hipGetErrorString(e));
-    }
-    return setup_finish(out, rb.data(), nrb);
-  } catch (const std::bad_alloc&) {
-    psdp_free(*out);
-    *out = nullptr;
-    return fail(PSDP_ENOMEM, "host allocation failed");
-  }
+  if (!out) return fail(PSDP_EINVAL, "out is NULL");
+  return setup_many(1, &A, &n, &l, &dp, &d, o, out, false);
 }
 
 int psdp_polya_setup_batched(int count, const double* const* A, const int* n, const int* l,
                              const int* dp, const int* d, const psdp_setup_opts* o, psdp_sdp** out) {
   if (count < 0) return fail(PSDP_EINVAL, "count is negative");
   if (count > 0 && (!A || !n || !l || !dp || !d || !out)) return fail(PSDP_EINVAL, "NULL argument");
-  for (int i = 0; i < count; ++i) out[i] = nullptr;
-  std::vector<const double*> rb_dev(count, nullptr);
-  std::vector<int64_t> nrb(count, 0), roff(count + 1, 0);
-  auto release = [&]() {
-    for (int i = 0; i < count; ++i) {
-      if (out[i]) psdp_free(out[i]);
-      out[i] = nullptr;
-    }
-  };
-  for (int i = 0; i < count; ++i) {
-    const int rc = setup_begin(A[i], n[i], l[i], dp[i], d[i], o, &out[i], &rb_dev[i], &nrb[i]);
-    if (rc) {
-      const std::string msg = "system " + std::to_string(i) + ": " + psdp_last_error();
-      release();
-      return fail(rc, msg);
-    }
-    roff[i + 1] = roff[i] + nrb[i];
-  }
-  if (count == 0) return PSDP_OK;
-  // every read-back into one pinned buffer, one wait
-  double* host = nullptr;
-  hipError_t e = hipHostMalloc((void**)&host, (size_t)roff[count] * 8, hipHostMallocDefault);
-  for (int i = 0; e == hipSuccess && i < count; ++i)
-    e = hipMemcpyAsync(host + roff[i], rb_dev[i], nrb[i] * 8, hipMemcpyDeviceToHost, 0);
-  if (e == hipSuccess) e = hipStreamSynchronize(0);
-  if (e != hipSuccess) {
-    if (host) hipHostFree(host);
-    release();
-    return fail(PSDP_EDEVICE, std::string("set-up read-back: ") + hipGetErrorString(e));
-  }
-  int rc = PSDP_OK;
-  std::string msg;
-  for (int i = 0; i < count; ++i) {
-    const int ri = setup_finish(&out[i], host + roff[i], nrb[i]);
-    if (ri && !rc) {
-      rc = ri;
-      msg = "system " + std::to_string(i) + ": " + psdp_last_error();
-    }
-  }
-  hipHostFree(host);
-  if (rc) {
-    release();
-    return fail(rc, msg);
-  }
-  return PSDP_OK;
+  return setup_many(count, A, n, l, dp, d, o, out, true);
 }
 
 int psdp_query(const psdp_sdp* s, psdp_dims* out) {
@@ -518,8 +615,7 @@ int psdp_basis(const psdp_sdp* s, int* pairs) {
 }
 
 void psdp_free(psdp_sdp* s) {
-  if (!s) return;
-  if (s->dmem) hipFree(s->dmem);
+  // the device block goes with the last handle of its set-up call
   delete s;
 }
 
