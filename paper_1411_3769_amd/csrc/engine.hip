@@ -153,23 +153,93 @@ struct Prof {
   }
 };
 
-struct Batch {
-  Prof prof;
-  int S = 0, maxn = 0, nblk = 0, npblk = 0, ndblk = 0, npairs = 0, nq2 = 0, ntiles = 0;
-  int totL0 = 0, totK = 0, maxP = 0;
-  std::vector<psdp_sdp*> sd;
-  std::vector<SysDesc> sys;
+// Host images of the per-batch tables.  They are needed only while a batch
+// is built; their capacity stays with the thread, so that repeated solves of
+// one shape reuse it instead of faulting in fresh pages each call.
+struct HostTables {
   std::vector<BlkDesc> blk, pblk, dblk;
   std::vector<HMPair> pairs;
   std::vector<int64_t> offA1;
   std::vector<HM2> q2;
   std::vector<KTerm> terms;
   std::vector<AsmTile> tiles, ptiles;   // grouped tiles (n > 11), whole pairs (n <= 11)
-  int maxn_pair = 0, nptiles = 0;
   std::vector<int> csr_hh, csr_hid, csr_mh, csr_hl;   // per-system sections
   std::vector<int> csr_hh_off, csr_hid_off, csr_mh_off, csr_hl_off;
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
+  void clear() {
+    blk.clear(); pblk.clear(); dblk.clear(); pairs.clear(); offA1.clear(); q2.clear();
+    terms.clear(); tiles.clear(); ptiles.clear();
+    csr_hh.clear(); csr_hid.clear(); csr_mh.clear(); csr_hl.clear();
+    csr_hh_off.clear(); csr_hid_off.clear(); csr_mh_off.clear(); csr_hl_off.clear();
+    gpinfo.clear(); gpoff.clear();
+  }
+};
+
+static HostTables& host_tables() {
+  static thread_local HostTables t;
+  t.clear();
+  return t;
+}
+
+// Pinned host buffers released by finished solves are kept (a few, bounded
+// in bytes) and handed to later requests of about their size: pinning and
+// unpinning cost tens of microseconds each.
+struct PinCache {
+  std::mutex mu;
+  std::vector<std::pair<void*, size_t>> bufs;
+  size_t bytes = 0;
+};
+static PinCache g_pin;
+constexpr size_t kPinBuffers = 16;
+constexpr size_t kPinBytes = size_t(1) << 30;
+
+static void* pin_alloc(size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  {
+    std::lock_guard<std::mutex> lk(g_pin.mu);
+    int bi = -1;
+    for (size_t i = 0; i < g_pin.bufs.size(); ++i) {
+      const size_t b = g_pin.bufs[i].second;
+      if (b >= bytes && b <= 2 * bytes + (64 << 10) && (bi < 0 || b < g_pin.bufs[bi].second))
+        bi = (int)i;
+    }
+    if (bi >= 0) {
+      void* p = g_pin.bufs[bi].first;
+      g_pin.bytes -= g_pin.bufs[bi].second;
+      g_pin.bufs.erase(g_pin.bufs.begin() + bi);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+// p must come from pin_alloc(bytes) with the same bytes
+static void pin_release(void* p, size_t bytes) {
+  if (!p) return;
+  bytes = std::max<size_t>(bytes, 256);
+  std::lock_guard<std::mutex> lk(g_pin.mu);
+  g_pin.bufs.push_back({p, bytes});
+  g_pin.bytes += bytes;
+  while (g_pin.bufs.size() > kPinBuffers || g_pin.bytes > kPinBytes) {
+    hipHostFree(g_pin.bufs.front().first);
+    g_pin.bytes -= g_pin.bufs.front().second;
+    g_pin.bufs.erase(g_pin.bufs.begin());
+  }
+}
+
+struct Batch {
+  Prof prof;
+  int S = 0, maxn = 0, nblk = 0, npblk = 0, ndblk = 0, npairs = 0, nq2 = 0, ntiles = 0;
+  int totL0 = 0, totK = 0, maxP = 0;
+  std::vector<psdp_sdp*> sd;
+  std::vector<SysDesc> sys;
+  int maxn_pair = 0, nptiles = 0;
   std::vector<int> ownP, ownK;
   StepTab pan, trs, upd, wide;
   // grouped solves of the systems not solved in one workgroup: per group q,
@@ -218,31 +288,36 @@ struct Batch {
   int nmin_big = 0;     // the general block kernels skip orders below this
   double *Lam, *Ldiag, *Linv, *Pm, *pre, *rscr;
 
-  // pinned host mirrors of the per-iteration transfers (flags, scalars)
+  // pinned host mirrors of the per-iteration transfers (flags, scalars),
+  // one cached block
   int* h_hf = nullptr;
   int* h_prev = nullptr;
   double* h_sc = nullptr;
+  void* h_pin = nullptr;
+  size_t h_pin_bytes = 0;
 
   size_t dtab_bytes = 0, arena_bytes = 0;
 
   ~Batch() {
     if (dtab) dev_release(dtab, dtab_bytes);
     if (arena) dev_release(arena, arena_bytes);
-    if (h_hf) hipHostFree(h_hf);
-    if (h_prev) hipHostFree(h_prev);
-    if (h_sc) hipHostFree(h_sc);
+    pin_release(h_pin, h_pin_bytes);
   }
 };
 
 // places table v at offset off of the device table block (base) and of its
 // host image (stage); the image goes up in one copy once every table is in
+struct Stage {
+  char* p;
+  size_t cap;
+};
+
 template <class T>
-static int upload(void* base, std::vector<char>& stage, size_t& off, const std::vector<T>& v,
-                  T** dptr) {
+static int upload(void* base, const Stage& stage, size_t& off, const std::vector<T>& v, T** dptr) {
   *dptr = (T*)((char*)base + off);
   const size_t bytes = v.size() * sizeof(T);
-  if (off + bytes > stage.size()) return fail(PSDP_EINVAL, "table image overflow");
-  if (bytes) std::memcpy(stage.data() + off, v.data(), bytes);
+  if (off + bytes > stage.cap) return fail(PSDP_EINVAL, "table image overflow");
+  if (bytes) std::memcpy(stage.p + off, v.data(), bytes);
   off += (bytes + 255) / 256 * 256;
   return PSDP_OK;
 }
@@ -270,6 +345,7 @@ static Choice default_choice(psdp_sdp* const* sdps, int count) {
 }
 
 static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice* ch = nullptr) {
+  HostTables& H = host_tables();
   Choice dflt;
   if (!ch) {
     dflt = default_choice(sdps, count);
@@ -282,6 +358,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   // ---- per-system layout
   int64_t curblk = 0, curvec = 0, curlam = 0, curdg = 0, curP = 0, curpre = 0;
   std::vector<std::vector<int64_t>> a1(count), a2(count), ay(count);
+  std::vector<size_t> q2beg(count + 1, 0);
   B.ownP.push_back(0);
   B.ownK.push_back(0);
   for (int s = 0; s < count; ++s) {
@@ -294,12 +371,12 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     SysDesc d{};
     d.n = n; d.L0 = p->L0; d.L = p->L; d.M = p->M; d.Nt = p->Nt; d.nb = p->nb;
     d.K = (int)p->K; d.Kpad = (int)p->Kpad; d.P = d.Kpad / kNB; d.mode = 0;
-    d.blk0 = (int)B.blk.size();
+    d.blk0 = (int)H.blk.size();
     d.boff = curblk;
     for (int j = 0; j < p->nb; ++j) {
       BlkDesc b{s, j, n, 0, curblk + j * nn};
-      B.blk.push_back(b);
-      (j < p->L ? B.pblk : B.dblk).push_back(b);
+      H.blk.push_back(b);
+      (j < p->L ? H.pblk : H.dblk).push_back(b);
     }
     curblk += p->nb * nn;
     d.voff = curvec; curvec += d.Kpad;
@@ -312,62 +389,61 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     a1[s].assign((size_t)p->M * p->L0, -1);
     a2[s].assign((size_t)p->M * p->L0, -1);
     ay[s].assign((size_t)p->M * p->L0, -1);
-    const int pair0 = (int)B.pairs.size();
+    const int pair0 = (int)H.pairs.size();
     std::vector<std::vector<int>> by_h(p->L0);
-    B.csr_mh_off.push_back((int)B.csr_mh.size());
-    B.csr_hl_off.push_back((int)B.csr_hl.size());
+    H.csr_mh_off.push_back((int)H.csr_mh.size());
+    H.csr_hl_off.push_back((int)H.csr_hl.size());
     int cnt_hl = 0;
     for (int m = 0; m < p->M; ++m) {
-      B.csr_mh.push_back(cnt_hl);
+      H.csr_mh.push_back(cnt_hl);
       for (int h = 0; h < p->L0; ++h) {
         if (!p->hmask[m * p->L0 + h]) continue;
         HMPair hp{s, m, h, n, curpre, curpre + nn};
         ay[s][m * p->L0 + h] = curpre;
         a2[s][m * p->L0 + h] = curpre + nn;
         a1[s][m * p->L0 + h] = curpre + 2 * nn;
-        B.offA1.push_back(curpre + 2 * nn);
+        H.offA1.push_back(curpre + 2 * nn);
         curpre += 3 * nn;
-        by_h[h].push_back((int)B.pairs.size());
-        B.pairs.push_back(hp);
-        B.csr_hl.push_back(h);
+        by_h[h].push_back((int)H.pairs.size());
+        H.pairs.push_back(hp);
+        H.csr_hl.push_back(h);
         ++cnt_hl;
       }
     }
-    B.csr_mh.push_back(cnt_hl);
-    B.csr_hh_off.push_back((int)B.csr_hh.size());
-    B.csr_hid_off.push_back((int)B.csr_hid.size());
+    H.csr_mh.push_back(cnt_hl);
+    H.csr_hh_off.push_back((int)H.csr_hh.size());
+    H.csr_hid_off.push_back((int)H.csr_hid.size());
     int cnt = 0;
     for (int h = 0; h < p->L0; ++h) {
-      B.csr_hh.push_back(cnt);
-      for (int id : by_h[h]) B.csr_hid.push_back(id);
+      H.csr_hh.push_back(cnt);
+      for (int id : by_h[h]) H.csr_hid.push_back(id);
       cnt += (int)by_h[h].size();
     }
-    B.csr_hh.push_back(cnt);
-    d.npairs_hm = (int)B.pairs.size() - pair0;
+    H.csr_hh.push_back(cnt);
+    d.npairs_hm = (int)H.pairs.size() - pair0;
     // Schur pre-products A3/A4 for h <= h2 on every block with both active
-    std::vector<int64_t> a3((size_t)p->M * p->L0 * p->L0, -1), a4 = a3;
+    q2beg[s] = H.q2.size();
     for (int m = 0; m < p->M; ++m) {
       for (int h = 0; h < p->L0; ++h) {
         if (!p->hmask[m * p->L0 + h]) continue;
         for (int h2 = h; h2 < p->L0; ++h2) {
           if (!p->hmask[m * p->L0 + h2]) continue;
           HM2 q{s, m, h, h2, n, 0, curpre, curpre + nn, a1[s][m * p->L0 + h2], a2[s][m * p->L0 + h2]};
-          a3[((size_t)m * p->L0 + h) * p->L0 + h2] = curpre;
-          a4[((size_t)m * p->L0 + h) * p->L0 + h2] = curpre + nn;
           curpre += 2 * nn;
-          B.q2.push_back(q);
+          H.q2.push_back(q);
         }
       }
     }
     // basis group pairs
-    B.gpoff.push_back((int64_t)B.gpinfo.size());
+    H.gpoff.push_back((int64_t)H.gpinfo.size());
     const BasisInfo& bi = p->basis;
     for (int g = 0; g < bi.ngp; ++g) {
-      B.gpinfo.push_back(bi.gp_g1[g]);
-      B.gpinfo.push_back(bi.gp_g2[g]);
-      B.gpinfo.push_back(bi.gp_off[g]);
-      B.gpinfo.push_back(bi.gp_size[g]);
+      H.gpinfo.push_back(bi.gp_g1[g]);
+      H.gpinfo.push_back(bi.gp_g2[g]);
+      H.gpinfo.push_back(bi.gp_off[g]);
+      H.gpinfo.push_back(bi.gp_size[g]);
     }
+    q2beg[s + 1] = H.q2.size();
     B.sys.push_back(d);
     B.ownP.push_back(B.ownP.back() + p->L0);
     B.ownK.push_back(B.ownK.back() + (int)p->K);
@@ -381,11 +457,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.totdg = round_up(curdg, 32);
   B.totP = round_up(curP, 32);
   B.totpre = round_up(curpre, 32);
-  B.nblk = (int)B.blk.size();
-  B.npblk = (int)B.pblk.size();
-  B.ndblk = (int)B.dblk.size();
-  B.npairs = (int)B.pairs.size();
-  B.nq2 = (int)B.q2.size();
+  B.nblk = (int)H.blk.size();
+  B.npblk = (int)H.pblk.size();
+  B.ndblk = (int)H.dblk.size();
+  B.npairs = (int)H.pairs.size();
+  B.nq2 = (int)H.q2.size();
   B.totL0 = B.ownP.back();
   B.totK = B.ownK.back();
 
@@ -416,30 +492,32 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.pre = a + o; o += B.totpre;
   B.rscr = a + o; o += totrs;
   const int64_t preBase = B.pre - a, ziBase = B.Zi - a, xBase = B.X - a;
-  for (auto& hp : B.pairs) { hp.offY += preBase; hp.offA2 += preBase; }
-  for (auto& v : B.offA1) v += preBase;
-  for (auto& q : B.q2) { q.offA3 += preBase; q.offA4 += preBase; q.srcA1 += preBase; q.srcA2 += preBase; }
+  for (auto& hp : H.pairs) { hp.offY += preBase; hp.offA2 += preBase; }
+  for (auto& v : H.offA1) v += preBase;
+  for (auto& q : H.q2) { q.offA3 += preBase; q.offA4 += preBase; q.srcA1 += preBase; q.srcA2 += preBase; }
 
   // ---- Schur k-lists and tiles
+  std::vector<int64_t> a3, a4;
   for (int s = 0; s < count; ++s) {
     psdp_sdp* p = sdps[s];
     const int L0 = p->L0, L = p->L, M = p->M;
     const int64_t nn = (int64_t)p->n * p->n;
     const int64_t b0 = B.sys[s].boff;
-    // index of the A3/A4 of (m, h, h2)
-    std::vector<int64_t> a3((size_t)M * L0 * L0, -1), a4 = a3;
-    for (const auto& q : B.q2)
-      if (q.sys == s) {
-        a3[((size_t)q.m * L0 + q.h) * L0 + q.h2] = q.offA3;
-        a4[((size_t)q.m * L0 + q.h) * L0 + q.h2] = q.offA4;
-      }
+    // index of the A3/A4 of (m, h, h2), from the system's own pre-products
+    a3.assign((size_t)M * L0 * L0, -1);
+    a4.assign((size_t)M * L0 * L0, -1);
+    for (size_t i = q2beg[s]; i < q2beg[s + 1]; ++i) {
+      const HM2& q = H.q2[i];
+      a3[((size_t)q.m * L0 + q.h) * L0 + q.h2] = q.offA3;
+      a4[((size_t)q.m * L0 + q.h) * L0 + q.h2] = q.offA4;
+    }
     for (int h = 0; h < L0; ++h) {
       for (int h2 = h; h2 < L0; ++h2) {
-        const int kbeg = (int)B.terms.size();
+        const int kbeg = (int)H.terms.size();
         for (int j = 0; j < L; ++j) {
           if (!p->bmask[h * L + j] || !p->bmask[h2 * L + j]) continue;
           const double c = p->betaf[h * L + j] * p->betaf[h2 * L + j];
-          B.terms.push_back(KTerm{ziBase + b0 + j * nn, xBase + b0 + j * nn, c, 0, 0});
+          H.terms.push_back(KTerm{ziBase + b0 + j * nn, xBase + b0 + j * nn, c, 0, 0});
         }
         for (int m = 0; m < M; ++m) {
           if (!p->hmask[m * L0 + h] || !p->hmask[m * L0 + h2]) continue;
@@ -448,27 +526,27 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
           const int64_t A2h = a2[s][m * L0 + h] + preBase, A2h2 = a2[s][m * L0 + h2] + preBase;
           const int64_t A3 = a3[((size_t)m * L0 + h) * L0 + h2];
           const int64_t A4 = a4[((size_t)m * L0 + h) * L0 + h2];
-          B.terms.push_back(KTerm{A1h2, A2h, 1.0, 0, 0});         // (Zi H'^T, X H^T)
-          B.terms.push_back(KTerm{ziBase + bm, A3, 1.0, 0, 1});   // (Zi, H' X H^T)
-          B.terms.push_back(KTerm{A4, xBase + bm, 1.0, 0, 0});    // (H Zi H'^T, X)
-          B.terms.push_back(KTerm{A1h, A2h2, 1.0, 1, 1});         // (H Zi, H' X)
+          H.terms.push_back(KTerm{A1h2, A2h, 1.0, 0, 0});         // (Zi H'^T, X H^T)
+          H.terms.push_back(KTerm{ziBase + bm, A3, 1.0, 0, 1});   // (Zi, H' X H^T)
+          H.terms.push_back(KTerm{A4, xBase + bm, 1.0, 0, 0});    // (H Zi H'^T, X)
+          H.terms.push_back(KTerm{A1h, A2h2, 1.0, 1, 1});         // (H Zi, H' X)
         }
-        const int kcnt = (int)B.terms.size() - kbeg;
+        const int kcnt = (int)H.terms.size() - kbeg;
         if (kcnt == 0) continue;   // the block stays zero
         if (ch->pair[s] && p->n * p->n <= 128) {
-          B.ptiles.push_back(AsmTile{s, h, h2, -1, -1, kbeg, kcnt, 0});
+          H.ptiles.push_back(AsmTile{s, h, h2, -1, -1, kbeg, kcnt, 0});
           B.maxn_pair = std::max(B.maxn_pair, p->n);
           continue;
         }
         const int ngp = p->basis.ngp;
         for (int rg = 0; rg < ngp; ++rg)
           for (int cg = (h == h2 ? rg : 0); cg < ngp; ++cg)
-            B.tiles.push_back(AsmTile{s, h, h2, rg, cg, kbeg, kcnt, 0});
+            H.tiles.push_back(AsmTile{s, h, h2, rg, cg, kbeg, kcnt, 0});
       }
     }
   }
-  B.ntiles = (int)B.tiles.size();
-  B.nptiles = (int)B.ptiles.size();
+  B.ntiles = (int)H.tiles.size();
+  B.nptiles = (int)H.ptiles.size();
 
   // ---- Cholesky step tables
   for (int s = 0; s < count; ++s)
@@ -527,11 +605,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
 
   // ---- device tables
   size_t tb = 0;
-  tb += tabsize(B.sys) + tabsize(B.blk) + tabsize(B.pblk) + tabsize(B.dblk) + tabsize(B.pairs);
-  tb += tabsize(B.offA1) + tabsize(B.q2) + tabsize(B.terms) + tabsize(B.tiles) + tabsize(B.gpinfo);
-  tb += tabsize(B.ptiles);
-  tb += tabsize(B.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(B.csr_hh) + tabsize(B.csr_hid);
-  tb += tabsize(B.csr_mh) + tabsize(B.csr_hl);
+  tb += tabsize(B.sys) + tabsize(H.blk) + tabsize(H.pblk) + tabsize(H.dblk) + tabsize(H.pairs);
+  tb += tabsize(H.offA1) + tabsize(H.q2) + tabsize(H.terms) + tabsize(H.tiles) + tabsize(H.gpinfo);
+  tb += tabsize(H.ptiles);
+  tb += tabsize(H.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(H.csr_hh) + tabsize(H.csr_hid);
+  tb += tabsize(H.csr_mh) + tabsize(H.csr_hl);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
   tb += tabsize(B.gdg.sys) + tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
@@ -543,45 +621,50 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if (!(B.dtab = dev_alloc(tb))) return fail(PSDP_ENOMEM, "device allocation of tables failed");
   size_t off = 0;
   int rc = PSDP_OK;
-  std::vector<char> stage(tb, 0);
+  Stage stage{(char*)pin_alloc(tb), tb};
+  if (!stage.p) return fail(PSDP_ENOMEM, "pinned staging buffer for the tables");
+  struct StageGuard {
+    Stage& s;
+    ~StageGuard() { pin_release(s.p, s.cap); }
+  } stage_guard{stage};
   int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl;
   // the per-system CSR pointers must be patched into SysDesc before upload
   {
     char* base = (char*)B.dtab;
-    size_t o2 = tabsize(B.sys) + tabsize(B.blk) + tabsize(B.pblk) + tabsize(B.dblk) + tabsize(B.pairs) +
-                tabsize(B.offA1) + tabsize(B.q2) + tabsize(B.terms) + tabsize(B.tiles) +
-                tabsize(B.ptiles) + tabsize(B.gpinfo) + tabsize(B.gpoff) + tabsize(B.ownP) +
+    size_t o2 = tabsize(B.sys) + tabsize(H.blk) + tabsize(H.pblk) + tabsize(H.dblk) + tabsize(H.pairs) +
+                tabsize(H.offA1) + tabsize(H.q2) + tabsize(H.terms) + tabsize(H.tiles) +
+                tabsize(H.ptiles) + tabsize(H.gpinfo) + tabsize(H.gpoff) + tabsize(B.ownP) +
                 tabsize(B.ownK);
-    d_csr_hh = (int*)(base + o2); o2 += tabsize(B.csr_hh);
-    d_csr_hid = (int*)(base + o2); o2 += tabsize(B.csr_hid);
-    d_csr_mh = (int*)(base + o2); o2 += tabsize(B.csr_mh);
+    d_csr_hh = (int*)(base + o2); o2 += tabsize(H.csr_hh);
+    d_csr_hid = (int*)(base + o2); o2 += tabsize(H.csr_hid);
+    d_csr_mh = (int*)(base + o2); o2 += tabsize(H.csr_mh);
     d_csr_hl = (int*)(base + o2);
     for (int s = 0; s < count; ++s) {
-      B.sys[s].hm_by_h = d_csr_hh + B.csr_hh_off[s];
-      B.sys[s].hm_ids = d_csr_hid + B.csr_hid_off[s];
-      B.sys[s].h_by_m = d_csr_mh + B.csr_mh_off[s];
-      B.sys[s].h_list = d_csr_hl + B.csr_hl_off[s];
+      B.sys[s].hm_by_h = d_csr_hh + H.csr_hh_off[s];
+      B.sys[s].hm_ids = d_csr_hid + H.csr_hid_off[s];
+      B.sys[s].h_by_m = d_csr_mh + H.csr_mh_off[s];
+      B.sys[s].h_list = d_csr_hl + H.csr_hl_off[s];
     }
   }
   if ((rc = upload(B.dtab, stage, off, B.sys, &B.d_sys))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.blk, &B.d_blk))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.pblk, &B.d_pblk))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.dblk, &B.d_dblk))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.pairs, &B.d_pairs))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.offA1, &B.d_offA1))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.q2, &B.d_q2))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.terms, &B.d_terms))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.tiles, &B.d_tiles))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.ptiles, &B.d_ptiles))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.gpinfo, &B.d_gpinfo))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.gpoff, &B.d_gpoff))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.blk, &B.d_blk))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.pblk, &B.d_pblk))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.dblk, &B.d_dblk))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.pairs, &B.d_pairs))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.offA1, &B.d_offA1))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.q2, &B.d_q2))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.terms, &B.d_terms))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.tiles, &B.d_tiles))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.ptiles, &B.d_ptiles))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.gpinfo, &B.d_gpinfo))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.gpoff, &B.d_gpoff))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.ownP, &B.d_ownP))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.ownK, &B.d_ownK))) return rc;
   int* tmp;
-  if ((rc = upload(B.dtab, stage, off, B.csr_hh, &tmp))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.csr_hid, &tmp))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.csr_mh, &tmp))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.csr_hl, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.csr_hh, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.csr_hid, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.csr_mh, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.csr_hl, &tmp))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.pan.sys, &B.d_pan_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.pan.pre, &B.d_pan_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.trs.sys, &B.d_trs_sys))) return rc;
@@ -596,17 +679,19 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.gbu.sys, &B.d_gbu_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gbu.pre, &B.d_gbu_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.small_ids, &B.d_small))) return rc;
-  PSDP_HIP(hipMemcpy(B.dtab, stage.data(), off, hipMemcpyHostToDevice));
+  PSDP_HIP(hipMemcpy(B.dtab, stage.p, off, hipMemcpyHostToDevice));
   char* base = (char*)B.dtab;
   B.d_flags = (int*)(base + off); off += ((size_t)B.S * 4 + 255) / 256 * 256;
   B.d_sc = (double*)(base + off); off += ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
   B.d_red = (double*)(base + off); off += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256;
   B.d_kout = (int*)(base + off); off += ((size_t)B.nblk * 4 + 255) / 256 * 256;
   B.d_cert = (double*)(base + off); off += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256;
-  if (hipHostMalloc((void**)&B.h_hf, (size_t)B.S * 4) != hipSuccess ||
-      hipHostMalloc((void**)&B.h_prev, (size_t)B.S * 4) != hipSuccess ||
-      hipHostMalloc((void**)&B.h_sc, (size_t)B.S * kNSC * 8) != hipSuccess)
-    return fail(PSDP_ENOMEM, "pinned host buffers");
+  const size_t hf_bytes = ((size_t)B.S * 4 + 255) / 256 * 256;
+  B.h_pin_bytes = 2 * hf_bytes + (size_t)B.S * kNSC * 8;
+  if (!(B.h_pin = pin_alloc(B.h_pin_bytes))) return fail(PSDP_ENOMEM, "pinned host buffers");
+  B.h_hf = (int*)B.h_pin;
+  B.h_prev = (int*)((char*)B.h_pin + hf_bytes);
+  B.h_sc = (double*)((char*)B.h_pin + 2 * hf_bytes);
   return PSDP_OK;
 }
 
@@ -794,12 +879,32 @@ static void set_flags(Batch& B, const std::vector<RunState>& rs, int* hf) {
     hf[s] = rs[s].running ? F_ACTIVE | F_CHOLSEL | (B.f32 && !B.asm64[s] ? F_ASM32 : 0) : 0;
 }
 
+// Idle solver streams, kept per device (creating and destroying a stream
+// costs about a tenth of a millisecond each).
+struct StreamPool {
+  std::mutex mu;
+  std::vector<std::pair<int, hipStream_t>> idle;
+};
+static StreamPool g_streams;
+constexpr size_t kPoolStreams = 8;
+
 // Private solver stream, started after the caller's stream (default priority).
 struct SolveStream {
   hipStream_t st = nullptr;
   hipEvent_t ev = nullptr;
+  int dev = 0;
   int open(hipStream_t caller) {
-    PSDP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    PSDP_HIP(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> lk(g_streams.mu);
+      for (size_t i = 0; i < g_streams.idle.size(); ++i)
+        if (g_streams.idle[i].first == dev) {
+          st = g_streams.idle[i].second;
+          g_streams.idle.erase(g_streams.idle.begin() + i);
+          break;
+        }
+    }
+    if (!st) PSDP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     PSDP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     PSDP_HIP(hipEventRecord(ev, caller));
     PSDP_HIP(hipStreamWaitEvent(st, ev, 0));
@@ -807,8 +912,10 @@ struct SolveStream {
   }
   ~SolveStream() {
     if (st) {
-      hipStreamSynchronize(st);
-      hipStreamDestroy(st);
+      const bool ok = hipStreamSynchronize(st) == hipSuccess;
+      std::lock_guard<std::mutex> lk(g_streams.mu);
+      if (ok && g_streams.idle.size() < kPoolStreams) g_streams.idle.push_back({dev, st});
+      else hipStreamDestroy(st);
     }
     if (ev) hipEventDestroy(ev);
   }

@@ -69,7 +69,9 @@ class IterRec(C.Structure):
 
 
 class CResult(C.Structure):
-    _fields_ = [("verdict", C.c_int), ("reason", C.c_int), ("P", DP), ("y", DP),
+    # caller buffers (double *) are declared as plain addresses: same ABI,
+    # and integer addresses assign without building pointer objects
+    _fields_ = [("verdict", C.c_int), ("reason", C.c_int), ("P", C.c_void_p), ("y", C.c_void_p),
                 ("phi", C.c_double), ("psi", C.c_double), ("gap_abs", C.c_double),
                 ("gap_rel", C.c_double), ("pinf", C.c_double), ("dinf", C.c_double),
                 ("margin", C.c_double), ("margin_P", C.c_double), ("margin_D", C.c_double),
@@ -77,7 +79,8 @@ class CResult(C.Structure):
                 ("t_star", C.c_double), ("time_solve_s", C.c_double), ("iters_lowprec", C.c_int),
                 ("ir_steps", C.c_int), ("ir_eta_max", C.c_double),
                 ("warm_used", C.c_int), ("warm_fallback", C.c_int), ("warm_iterations", C.c_int),
-                ("logx", DP), ("label_y", DP), ("label_logx", DP), ("label_iter", C.c_int),
+                ("logx", C.c_void_p), ("label_y", C.c_void_p), ("label_logx", C.c_void_p),
+                ("label_iter", C.c_int),
                 ("asm_path", C.c_int), ("solve_path", C.c_int),
                 ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
@@ -262,10 +265,11 @@ def polya_setup_batched(systems, *, da: int = 1, delta: float = 1e-3, eps: float
     if any(dev) and not all(dev):
         raise ValueError("polya_setup_batched: vertices must be all on the host or all on the device")
     o.a_on_device = int(bool(dev) and all(dev))
+    if o.a_on_device:
+        import torch
     for i, (A, *_rest) in enumerate(systems):
         if o.a_on_device:
-            import torch
-            t = A.to(torch.float64).contiguous()
+            t = A if A.dtype == torch.float64 and A.is_contiguous() else A.to(torch.float64).contiguous()
             keep.append(t)
             ptrs[i] = t.data_ptr()
         else:
@@ -275,10 +279,15 @@ def polya_setup_batched(systems, *, da: int = 1, delta: float = 1e-3, eps: float
     ints = [(C.c_int * max(cnt, 1))(*[int(s[k]) for s in systems]) for k in (1, 2, 3, 4)]
     out = (C.c_void_p * max(cnt, 1))()
     _check(lib.psdp_polya_setup_batched(cnt, ptrs, ints[0], ints[1], ints[2], ints[3], C.byref(o), out))
-    res = []
-    for i in range(cnt):
-        dims = Dims()
-        _check(lib.psdp_query(out[i], C.byref(dims)))
+    # the sizes depend only on the shape (the options are common to the call)
+    res, dims_of = [], {}
+    for i, sy in enumerate(systems):
+        key = tuple(int(v) for v in sy[1:5])
+        dims = dims_of.get(key)
+        if dims is None:
+            dims = Dims()
+            _check(lib.psdp_query(out[i], C.byref(dims)))
+            dims_of[key] = dims
         res.append(SDP(out[i], dims))
     return res
 
@@ -345,22 +354,30 @@ class Result:
         return REASONS[self.reason] if 0 <= self.reason < len(REASONS) else str(self.reason)
 
 
-def _prep(sdp: SDP, cap: int):
-    P = np.zeros((sdp.L0, sdp.n, sdp.n))
-    y = np.zeros(sdp.K)
-    lx = np.zeros(sdp.L + sdp.M)
-    ly = np.zeros(sdp.K)
-    llx = np.zeros(sdp.L + sdp.M)
-    hist = (IterRec * cap)() if cap else None
-    r = CResult()
-    r.P = P.ctypes.data_as(DP)
-    r.y = y.ctypes.data_as(DP)
-    r.logx = lx.ctypes.data_as(DP)
-    r.label_y = ly.ctypes.data_as(DP)
-    r.label_logx = llx.ctypes.data_as(DP)
-    r.history = C.cast(hist, C.POINTER(IterRec)) if cap else C.POINTER(IterRec)()
-    r.history_cap = cap
-    return r, P, y, (lx, ly, llx), hist
+def _prep_batch(sdps, cap: int, arr):
+    """Caller buffers of every system's result in one host allocation; the
+    entries of arr (CResult) point into it.  Returns per system (P, y,
+    (logx, label_y, label_logx), history)."""
+    sizes = [(s.L0 * s.n * s.n, s.K, s.L + s.M) for s in sdps]
+    total = sum(p + 2 * k + 2 * b for p, k, b in sizes)
+    buf = np.zeros(max(total, 1))
+    base, item = buf.ctypes.data, buf.itemsize
+    out, o = [], 0
+    for i, (s, (p, k, b)) in enumerate(zip(sdps, sizes)):
+        offs = (o, o + p, o + p + k, o + p + k + b, o + p + 2 * k + b)
+        o += p + 2 * k + 2 * b
+        P = buf[offs[0]:offs[1]].reshape(s.L0, s.n, s.n)
+        y, lx = buf[offs[1]:offs[2]], buf[offs[2]:offs[3]]
+        ly, llx = buf[offs[3]:offs[4]], buf[offs[4]:o]
+        r = arr[i]
+        r.P, r.y, r.logx, r.label_y, r.label_logx = (base + item * q for q in offs)
+        hist = None
+        if cap:
+            hist = (IterRec * cap)()
+            r.history = C.cast(hist, C.POINTER(IterRec))
+        r.history_cap = cap
+        out.append((P, y, (lx, ly, llx), hist))
+    return out
 
 
 def _warm_arrays(sdps, warm_y, warm_logx):
@@ -406,13 +423,14 @@ def ipm_solve(sdp: SDP, warm_y=None, warm_logx=None, **opts) -> Result:
     warm_logx (L+M log block scales of X) give an optional warm start."""
     o = make_opts(**opts)
     cap = 512 if o.record_history else 0
-    r, P, y, lx, hist = _prep(sdp, cap)
+    arr = (CResult * 1)()
+    (P, y, lx, hist), = _prep_batch([sdp], cap, arr)
     (wy, wl), wkeep = _warm_arrays([sdp], None if warm_y is None else [warm_y],
                                    None if warm_logx is None else [warm_logx])
     o.warm_y, o.warm_logx = wy, wl
-    _check(load().psdp_ipm_solve(sdp.handle, C.byref(o), C.byref(r)))
+    _check(load().psdp_ipm_solve(sdp.handle, C.byref(o), arr))
     del wkeep
-    return _unpack(r, P, y, lx, hist)
+    return _unpack(arr[0], P, y, lx, hist)
 
 
 def ipm_solve_batched(sdps: Sequence[SDP], warm_y=None, warm_logx=None, **opts) -> List[Result]:
@@ -420,11 +438,7 @@ def ipm_solve_batched(sdps: Sequence[SDP], warm_y=None, warm_logx=None, **opts) 
     cap = 512 if o.record_history else 0
     n = len(sdps)
     arr = (CResult * n)()
-    keep = []
-    for i, s in enumerate(sdps):
-        r, P, y, lx, hist = _prep(s, cap)
-        arr[i] = r
-        keep.append((P, y, lx, hist))
+    keep = _prep_batch(sdps, cap, arr)
     (wy, wl), wkeep = _warm_arrays(sdps, warm_y, warm_logx)
     o.warm_y, o.warm_logx = wy, wl
     hs = (C.c_void_p * n)(*[s.handle.value for s in sdps])
