@@ -1023,7 +1023,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     // residuals, objectives and the scalars the host decides on
     auto part1 = [&]() -> int {
     { const size_t pm_ = B.prof.mark();
-    launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
+    launch_cholinv(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.Z, B.Zi);
       B.prof.add(PSDP_PROF_CHOLINV, pm_, B.prof.mark()); }
     op_BT(B, st, B.y, B.S1);
     { const size_t pm_ = B.prof.mark();
@@ -1246,7 +1246,7 @@ static int warm_project(Batch& B, hipStream_t st, const psdp_opts& o, const std:
   launch_warm_init(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, B.T1, B.d_cert, B.d_red, o.warm_margin,
                    B.X, B.Z);
   if (o.warm_center) {
-    launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
+    launch_cholinv(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.Z, B.Zi);
     launch_warm_center(st, B.nblk, B.d_blk, B.d_flags, B.Zi, B.d_red, B.X);
   }
   PSDP_HIP(hipGetLastError());
@@ -1631,7 +1631,7 @@ int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y
   PSDP_HIP(hipMemcpyAsync(B.y, y, d.K * 8, hipMemcpyHostToDevice, st));
   const int one = F_ACTIVE | F_CHOLSEL;
   PSDP_HIP(hipMemcpyAsync(B.d_flags, &one, 4, hipMemcpyHostToDevice, st));
-  launch_cholinv(st, B.nblk, B.maxn, B.d_blk, B.d_flags, B.Z, B.Zi);
+  launch_cholinv(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.Z, B.Zi);
   op_BT(B, st, B.y, B.S1);
   op_B(B, st, B.X, B.BX, 0.0);
   op_schur(B, st);

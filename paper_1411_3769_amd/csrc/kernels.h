@@ -5,8 +5,8 @@
 
 namespace psdp {
 
-void launch_cholinv(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, int* flags,
-                    const double* Z, double* Zi);
+void launch_cholinv(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
+                    int* flags, const double* Z, double* Zi);
 void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
                    const int* flags, const double* V, const double* dV, double rho, double frac,
                    int len, int* kout);

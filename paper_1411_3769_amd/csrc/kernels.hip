@@ -23,6 +23,7 @@ __global__ void __launch_bounds__(256) k_cholinv(const BlkDesc* __restrict__ blk
   extern __shared__ double sm[];
   __shared__ int fl;
   const BlkDesc bd = blks[blockIdx.x];
+  if (bd.n <= kSmallN) return;   // k_cholinv16
   ACTIVE_OR_RETURN(bd.sys);
   const int n = bd.n, nn = n * n;
   const double* Zb = Z + bd.off;
@@ -41,6 +42,70 @@ __global__ void __launch_bounds__(256) k_cholinv(const BlkDesc* __restrict__ blk
     out[i * n + j] = acc;
     out[j * n + i] = acc;
   }
+}
+
+// Z_j^{-1} for blocks of order <= 16, sixteen lanes per block (sixteen blocks
+// per workgroup), all in registers: lane r holds row r of Z (identity past
+// n).  Z = L L^T with every column scaled by the Newton reciprocal square
+// root of its pivot; lane c then forms column c of X = L^{-1} by forward
+// substitution, and Z^{-1} = X^T X row by row (terms in ascending k, so the
+// result is exactly symmetric).  Row values travel by DPP row broadcasts.
+__global__ void __launch_bounds__(256) k_cholinv16(const BlkDesc* __restrict__ blks, int nblk,
+                                                   int* flags, const double* __restrict__ Z,
+                                                   double* Zi) {
+  const int b = blockIdx.x * 16 + (int)(threadIdx.x >> 4), r = threadIdx.x & 15;
+  if (b >= nblk) return;
+  const BlkDesc bd = blks[b];
+  if (bd.n > kSmallN) return;   // k_cholinv
+  if (!(flags[bd.sys] & F_ACTIVE)) return;
+  const int n = bd.n;
+  const double* Zb = Z + bd.off;
+  double a[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = (r < n && c < n) ? Zb[r * n + c] : (r == c ? 1.0 : 0.0);
+  // lower Cholesky factor, row r of L in a; rs[k] = 1 / L[k][k]
+  double rs[16];
+  bool bad = false;
+  static_for<16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    double d = row_bcast16<k>(a[k]);
+    const bool bb = !(d > 0.0) || !isfinite(d);
+    bad = bad || bb;
+    d = bb ? 1.0 : d;
+    rs[k] = rsqrt_nr(d);
+    const double lrk = r >= k ? a[k] * rs[k] : 0.0;
+    a[k] = lrk;
+    static_for<16>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c > k) {
+        const double lck = row_bcast16<c>(lrk);
+        a[c] = r >= c ? a[c] - lrk * lck : a[c];
+      }
+    });
+  });
+  if (bad && r == 0) atomicOr(&flags[bd.sys], F_ZFAIL);
+  // column r of X = L^{-1}: x[i] = (delta_{ir} - sum_{m<i} L[i][m] x[m]) / L[i][i]
+  double x[16];
+  static_for<16>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    double acc = r == i ? 1.0 : 0.0;
+    static_for<i>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      acc -= row_bcast16<i>(a[m]) * x[m];
+    });
+    x[i] = acc * rs[i];
+  });
+  // row r of X^T X: sum over k >= c of X[k][r] X[k][c]
+  double* out = Zi + bd.off;
+  static_for<16>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    double acc = 0.0;
+    static_for<16>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if constexpr (k >= c) acc += x[k] * row_bcast16<c>(x[k]);
+    });
+    if (r < n && c < n) out[r * n + c] = acc;
+  });
 }
 
 // Step-length ladder (reading of the paper's "standard line-search" that
@@ -1589,11 +1654,15 @@ static void set_lds(const void* f, size_t bytes) {
   if (bytes > 64 * 1024) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-void launch_cholinv(hipStream_t st, int nblk, int maxn, const BlkDesc* blks, int* flags,
-                    const double* Z, double* Zi) {
-  const size_t lds = (size_t)maxn * maxn * 8;
-  set_lds((const void*)k_cholinv, lds);
-  hipLaunchKernelGGL(k_cholinv, dim3(nblk), dim3(256), lds, st, blks, flags, Z, Zi);
+void launch_cholinv(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
+                    int* flags, const double* Z, double* Zi) {
+  if (nmax_small)
+    hipLaunchKernelGGL(k_cholinv16, dim3((nblk + 15) / 16), dim3(256), 0, st, blks, nblk, flags, Z, Zi);
+  if (maxn > kSmallN) {
+    const size_t lds = (size_t)maxn * maxn * 8;
+    set_lds((const void*)k_cholinv, lds);
+    hipLaunchKernelGGL(k_cholinv, dim3(nblk), dim3(256), lds, st, blks, flags, Z, Zi);
+  }
 }
 
 void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
