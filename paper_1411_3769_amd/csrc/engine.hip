@@ -163,14 +163,14 @@ struct HostTables {
   std::vector<HM2> q2;
   std::vector<KTerm> terms;
   std::vector<AsmTile> tiles, ptiles;   // grouped tiles (n > 11), whole pairs (n <= 11)
-  std::vector<int> csr_hh, csr_hid, csr_mh, csr_hl;   // per-system sections
+  std::vector<int> csr_hh, csr_hid, csr_mh, csr_hl, csr_hm;   // per-system sections
   std::vector<int> csr_hh_off, csr_hid_off, csr_mh_off, csr_hl_off;
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
   void clear() {
     blk.clear(); pblk.clear(); dblk.clear(); pairs.clear(); offA1.clear(); q2.clear();
     terms.clear(); tiles.clear(); ptiles.clear();
-    csr_hh.clear(); csr_hid.clear(); csr_mh.clear(); csr_hl.clear();
+    csr_hh.clear(); csr_hid.clear(); csr_mh.clear(); csr_hl.clear(); csr_hm.clear();
     csr_hh_off.clear(); csr_hid_off.clear(); csr_mh_off.clear(); csr_hl_off.clear();
     gpinfo.clear(); gpoff.clear();
   }
@@ -416,7 +416,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     int cnt = 0;
     for (int h = 0; h < p->L0; ++h) {
       H.csr_hh.push_back(cnt);
-      for (int id : by_h[h]) H.csr_hid.push_back(id);
+      for (int id : by_h[h]) {
+        H.csr_hid.push_back(id);
+        H.csr_hm.push_back(H.pairs[id].m);
+      }
       cnt += (int)by_h[h].size();
     }
     H.csr_hh.push_back(cnt);
@@ -609,7 +612,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(H.offA1) + tabsize(H.q2) + tabsize(H.terms) + tabsize(H.tiles) + tabsize(H.gpinfo);
   tb += tabsize(H.ptiles);
   tb += tabsize(H.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(H.csr_hh) + tabsize(H.csr_hid);
-  tb += tabsize(H.csr_mh) + tabsize(H.csr_hl);
+  tb += tabsize(H.csr_mh) + tabsize(H.csr_hl) + tabsize(H.csr_hm);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
   tb += tabsize(B.gdg.sys) + tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
@@ -627,7 +630,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     Stage& s;
     ~StageGuard() { pin_release(s.p, s.cap); }
   } stage_guard{stage};
-  int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl;
+  int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl; int* d_csr_hm;
   // the per-system CSR pointers must be patched into SysDesc before upload
   {
     char* base = (char*)B.dtab;
@@ -638,10 +641,12 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     d_csr_hh = (int*)(base + o2); o2 += tabsize(H.csr_hh);
     d_csr_hid = (int*)(base + o2); o2 += tabsize(H.csr_hid);
     d_csr_mh = (int*)(base + o2); o2 += tabsize(H.csr_mh);
-    d_csr_hl = (int*)(base + o2);
+    d_csr_hl = (int*)(base + o2); o2 += tabsize(H.csr_hl);
+    d_csr_hm = (int*)(base + o2);
     for (int s = 0; s < count; ++s) {
       B.sys[s].hm_by_h = d_csr_hh + H.csr_hh_off[s];
       B.sys[s].hm_ids = d_csr_hid + H.csr_hid_off[s];
+      B.sys[s].hm_m = d_csr_hm + H.csr_hid_off[s];
       B.sys[s].h_by_m = d_csr_mh + H.csr_mh_off[s];
       B.sys[s].h_list = d_csr_hl + H.csr_hl_off[s];
     }
@@ -665,6 +670,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, H.csr_hid, &tmp))) return rc;
   if ((rc = upload(B.dtab, stage, off, H.csr_mh, &tmp))) return rc;
   if ((rc = upload(B.dtab, stage, off, H.csr_hl, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.csr_hm, &tmp))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.pan.sys, &B.d_pan_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.pan.pre, &B.d_pan_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.trs.sys, &B.d_trs_sys))) return rc;
@@ -735,11 +741,12 @@ static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double 
                  bool phase_aware = true) {
   const size_t m0 = B.prof.mark();
   if (B.nmax_small)
-    launch_B_Y_small(st, B.npairs, B.nmax_small, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk);
-  if (B.maxn > kSmallN)
+    launch_B_small(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, W, out, asub);
+  if (B.maxn > kSmallN) {
     launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk, B.nmin_big);
-  launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
-                  out, asub);
+    launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
+                    out, asub, B.nmax_small ? kSmallN : 0);
+  }
   if (phase_aware && B.any_phase1) launch_B_phase1(st, B.S, B.d_sys, B.d_flags, B.d_blk, W, out, asub);
   B.prof.add(PSDP_PROF_B, m0, B.prof.mark());
 }

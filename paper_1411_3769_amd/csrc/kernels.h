@@ -46,7 +46,9 @@ void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
                 const int* flags, const double* W, double* arena, const BlkDesc* blks, int nmin);
 void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
                      const int* own_pre, int S, const HMPair* pairs, const double* W,
-                     const double* arena, const BlkDesc* blks, double* out, double asub);
+                     const double* arena, const BlkDesc* blks, double* out, double asub, int nskip);
+void launch_B_small(hipStream_t st, int totL0, const SysDesc* sys, const int* flags, const int* own_pre,
+                    int S, const double* W, double* out, double asub);
 void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
                   const int* flags, const double* Zi, const double* X, double* arena,
                   const BlkDesc* blks, const int64_t* offA1, int nmin);
@@ -66,8 +68,6 @@ void launch_gemm_blocks_small(hipStream_t st, int nblk, int nmax, const BlkDesc*
                               const double* D, double beta, int bslot);
 void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks,
                           const SysDesc* sys, const int* flags, const double* Pm, double* out);
-void launch_B_Y_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
-                      const int* flags, const double* W, double* arena, const BlkDesc* blks);
 void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
                         const int* flags, const double* Zi, const double* X, double* arena,
                         const BlkDesc* blks, const int64_t* offA1);

@@ -551,13 +551,14 @@ __global__ void __launch_bounds__(256) k_B_reduce(const SysDesc* __restrict__ sy
                                                   const double* __restrict__ W,
                                                   const double* __restrict__ arena,
                                                   const BlkDesc* __restrict__ blks, double* out,
-                                                  double asub) {
+                                                  double asub, int nskip) {
   const int gq = blockIdx.x * blockDim.x + threadIdx.x;
   const int g = gq >> 2, qd = gq & 3;
   const int s = find_owner(own_pre, S, g);
   const SysDesc* sd = sys + s;
   const int k = g - own_pre[s];
-  const bool live = k < sd->K && (flags[s] & F_ACTIVE);
+  // systems with blocks of order <= nskip are left to k_B_small
+  const bool live = k < sd->K && (flags[s] & F_ACTIVE) && sd->n > nskip;
   double acc = 0.0, dsum = 0.0;
   if (live) {
     const int n = sd->n, Nt = sd->Nt, L = sd->L;
@@ -1385,32 +1386,90 @@ __global__ void __launch_bounds__(256) k_BT_dblk_small(int nd, int nmax, int G,
   if (act) out[bd.off + t.e] = -acc;
 }
 
-// Y_{m,h} = H_{m,h} W_m
-__global__ void __launch_bounds__(256) k_B_Y_small(int np, int nmax, int G,
-                                                   const HMPair* __restrict__ pairs,
-                                                   const SysDesc* __restrict__ sys,
-                                                   const int* __restrict__ flags,
-                                                   const double* __restrict__ W, double* arena,
-                                                   const BlkDesc* __restrict__ blks) {
-  __shared__ double sH[256], sW[256];
-  SmallSlot t = small_slot(nmax, G, np);
-  HMPair pr{};
-  if (t.ok) {
-    pr = pairs[t.item];
-    t.ok = (flags[pr.sys] & F_ACTIVE) && pr.n <= nmax && t.e < pr.n * pr.n;
+// B(W) for systems whose blocks have order <= 16, one workgroup of four
+// waves per (system, h), without per-pair products in the arena:
+// S = sum_{j<L} beta_{h,j} W_j and R = sum over the (m, h) pairs of
+// H_{h,m} W_{L+m} (a contraction over (m, k) on FP64 MFMA, operands read
+// straight into the A/B lane layout, zero past n; each wave takes every
+// fourth pair and every fourth j and keeps T_w = S_w - 2 R_w in the D
+// layout), then for every basis pair b = (p, q) of h: out_{(h,b)} =
+// T[p][q] + T[q][p] (T[p][p] if p = q) with T = sum_w T_w, less asub on the
+// paper's SDP.
+constexpr int kBG = 4;   // pairs whose operands one wave loads together
+
+__global__ void __launch_bounds__(256) k_B_small(const SysDesc* __restrict__ sys,
+                                                 const int* __restrict__ flags,
+                                                 const int* __restrict__ own_pre, int S,
+                                                 const double* __restrict__ W, double* out,
+                                                 double asub) {
+  __shared__ double sT[4][256];
+  const int s = find_owner(own_pre, S, blockIdx.x);
+  const int h = blockIdx.x - own_pre[s];
+  ACTIVE_OR_RETURN(s);
+  const SysDesc& sd = sys[s];
+  const int n = sd.n;
+  if (n > kSmallN) return;   // k_B_Y + k_B_reduce
+  const int nn = n * n, L = sd.L, L0 = sd.L0;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const double* Ws = W + sd.boff;
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  // R: pairs c0 + wv, c0 + wv + 4, ..., kBG of them per round
+  const int c0 = sd.hm_by_h[h], c1 = sd.hm_by_h[h + 1];
+  for (int cb = c0 + wv; cb < c1; cb += 4 * kBG) {
+    double av[kBG][4], bv[kBG][4];
+#pragma unroll
+    for (int g = 0; g < kBG; ++g) {
+      const int c = cb + 4 * g;
+      const int m = sd.hm_m[min(c, c1 - 1)];
+      const double* Hc = sd.H + ((int64_t)m * L0 + h) * nn;
+      const double* Wc = Ws + (int64_t)(L + m) * nn;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int k = 4 * ks + kq;
+        const bool ok = c < c1 && k < n && r16 < n;
+        av[g][ks] = ok ? Hc[r16 * n + k] : 0.0;   // A[i][k], i = r16
+        bv[g][ks] = ok ? Wc[k * n + r16] : 0.0;   // B[k][j], j = r16
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kBG; ++g)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        if (4 * ks < n) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g][ks], bv[g][ks], acc, 0, 0, 0);
   }
-  const int n = pr.n, nn = n * n;
-  double* ph = sH + t.li * t.per;
-  double* pw = sW + t.li * t.per;
-  if (t.ok) {
-    const SysDesc* sd = sys + pr.sys;
-    const BlkDesc bd = blks[sd->blk0 + sd->L + pr.m];
-    ph[t.e] = sd->H[((int64_t)pr.m * sd->L0 + pr.h) * nn + t.e];
-    pw[t.e] = W[bd.off + t.e];
+  // S at the D layout: rows 4q + kq, column r16; j' = wv, wv + 4, ...
+  double sv[4] = {0.0, 0.0, 0.0, 0.0};
+  {
+    const double* bh = sd.betaf + (int64_t)h * L;
+    for (int jb = wv; jb < L; jb += 16) {
+      double w[4][4], bt[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = jb + 4 * u;
+        bt[u] = jj < L ? bh[jj] : 0.0;
+        const double* Wj = Ws + (int64_t)min(jj, L - 1) * nn;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 4 * q + kq;
+          w[u][q] = row < n && r16 < n ? Wj[row * n + r16] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sv[q] += bt[u] != 0.0 ? bt[u] * w[u][q] : 0.0;
+    }
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sT[wv][(4 * q + kq) * 16 + r16] = sv[q] - 2.0 * acc[q];
   __syncthreads();
-  if (!t.ok) return;
-  arena[pr.offY + t.e] = dot_n(n, t.e / n, t.e % n, ph, 0, pw, 0);
+  const int t = threadIdx.x;
+  if (t < sd.Nt) {
+    const int p = sd.basis[2 * t], q = sd.basis[2 * t + 1];
+    auto T = [&](int a, int b) { return sT[0][a * 16 + b] + sT[1][a * 16 + b] + sT[2][a * 16 + b] + sT[3][a * 16 + b]; };
+    const double v = p == q ? T(p, p) : T(p, q) + T(q, p);
+    out[sd.voff + (int64_t)h * sd.Nt + t] = sd.mode == 0 ? v - asub : v;
+  }
 }
 
 // A1 = Z^-1_m H_{m,h}^T, A2 = X_m H_{m,h}^T
@@ -1758,9 +1817,15 @@ void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
 
 void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
                      const int* own_pre, int S, const HMPair* pairs, const double* W,
-                     const double* arena, const BlkDesc* blks, double* out, double asub) {
+                     const double* arena, const BlkDesc* blks, double* out, double asub, int nskip) {
   hipLaunchKernelGGL(k_B_reduce, dim3((4 * totalK + 255) / 256), dim3(256), 0, st, sys, flags, own_pre,
-                     S, pairs, W, arena, blks, out, asub);
+                     S, pairs, W, arena, blks, out, asub, nskip);
+}
+
+void launch_B_small(hipStream_t st, int totL0, const SysDesc* sys, const int* flags, const int* own_pre,
+                    int S, const double* W, double* out, double asub) {
+  if (totL0)
+    hipLaunchKernelGGL(k_B_small, dim3(totL0), dim3(256), 0, st, sys, flags, own_pre, S, W, out, asub);
 }
 
 void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
@@ -1897,12 +1962,6 @@ void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks
                           const SysDesc* sys, const int* flags, const double* Pm, double* out) {
   const int G = small_G(nmax);
   if (nd) hipLaunchKernelGGL(k_BT_dblk_small, dim3((nd + G - 1) / G), dim3(256), 0, st, nd, nmax, G, dblks, sys, flags, Pm, out);
-}
-
-void launch_B_Y_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
-                      const int* flags, const double* W, double* arena, const BlkDesc* blks) {
-  const int G = small_G(nmax);
-  if (np) hipLaunchKernelGGL(k_B_Y_small, dim3((np + G - 1) / G), dim3(256), 0, st, np, nmax, G, pairs, sys, flags, W, arena, blks);
 }
 
 void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
