@@ -167,12 +167,14 @@ struct HostTables {
   std::vector<int> csr_hh_off, csr_hid_off, csr_mh_off, csr_hl_off;
   std::vector<int> gpinfo;
   std::vector<int64_t> gpoff;
+  std::vector<int> pq2b;                  // per system [n][n]: basis index of (p, q)
+  std::vector<int64_t> pq2b_off;
   void clear() {
     blk.clear(); pblk.clear(); dblk.clear(); pairs.clear(); offA1.clear(); q2.clear();
     terms.clear(); tiles.clear(); ptiles.clear();
     csr_hh.clear(); csr_hid.clear(); csr_mh.clear(); csr_hl.clear(); csr_hm.clear();
     csr_hh_off.clear(); csr_hid_off.clear(); csr_mh_off.clear(); csr_hl_off.clear();
-    gpinfo.clear(); gpoff.clear();
+    gpinfo.clear(); gpoff.clear(); pq2b.clear(); pq2b_off.clear();
   }
 };
 
@@ -437,6 +439,17 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
         }
       }
     }
+    // entry (p, q) of a symmetric block -> its basis index
+    H.pq2b_off.push_back((int64_t)H.pq2b.size());
+    H.pq2b.resize(H.pq2b.size() + (size_t)nn);
+    {
+      int* t = H.pq2b.data() + H.pq2b_off.back();
+      for (int b = 0; b < p->Nt; ++b) {
+        const int pp = p->basis.pairs[2 * b], qq = p->basis.pairs[2 * b + 1];
+        t[pp * n + qq] = b;
+        t[qq * n + pp] = b;
+      }
+    }
     // basis group pairs
     H.gpoff.push_back((int64_t)H.gpinfo.size());
     const BasisInfo& bi = p->basis;
@@ -612,7 +625,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(H.offA1) + tabsize(H.q2) + tabsize(H.terms) + tabsize(H.tiles) + tabsize(H.gpinfo);
   tb += tabsize(H.ptiles);
   tb += tabsize(H.gpoff) + tabsize(B.ownP) + tabsize(B.ownK) + tabsize(H.csr_hh) + tabsize(H.csr_hid);
-  tb += tabsize(H.csr_mh) + tabsize(H.csr_hl) + tabsize(H.csr_hm);
+  tb += tabsize(H.csr_mh) + tabsize(H.csr_hl) + tabsize(H.csr_hm) + tabsize(H.pq2b);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
   tb += tabsize(B.gdg.sys) + tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
@@ -630,7 +643,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     Stage& s;
     ~StageGuard() { pin_release(s.p, s.cap); }
   } stage_guard{stage};
-  int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl; int* d_csr_hm;
+  int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl; int* d_csr_hm; int* d_pq2b;
   // the per-system CSR pointers must be patched into SysDesc before upload
   {
     char* base = (char*)B.dtab;
@@ -642,8 +655,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     d_csr_hid = (int*)(base + o2); o2 += tabsize(H.csr_hid);
     d_csr_mh = (int*)(base + o2); o2 += tabsize(H.csr_mh);
     d_csr_hl = (int*)(base + o2); o2 += tabsize(H.csr_hl);
-    d_csr_hm = (int*)(base + o2);
+    d_csr_hm = (int*)(base + o2); o2 += tabsize(H.csr_hm);
+    d_pq2b = (int*)(base + o2);
     for (int s = 0; s < count; ++s) {
+      B.sys[s].pq2b = d_pq2b + H.pq2b_off[s];
       B.sys[s].hm_by_h = d_csr_hh + H.csr_hh_off[s];
       B.sys[s].hm_ids = d_csr_hid + H.csr_hid_off[s];
       B.sys[s].hm_m = d_csr_hm + H.csr_hid_off[s];
@@ -671,6 +686,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, H.csr_mh, &tmp))) return rc;
   if ((rc = upload(B.dtab, stage, off, H.csr_hl, &tmp))) return rc;
   if ((rc = upload(B.dtab, stage, off, H.csr_hm, &tmp))) return rc;
+  if ((rc = upload(B.dtab, stage, off, H.pq2b, &tmp))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.pan.sys, &B.d_pan_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.pan.pre, &B.d_pan_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.trs.sys, &B.d_trs_sys))) return rc;
@@ -726,11 +742,13 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
     launch_lift(st, B.S, B.d_sys, B.d_flags, yv, B.ylift);
     ybase = B.ylift;
   }
-  launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, ybase, B.Pm);
-  launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out);
-  if (B.nmax_small)
-    launch_BT_dblk_small(st, B.ndblk, B.nmax_small, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out);
-  if (B.maxn > kSmallN) launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out, B.nmin_big);
+  if (B.nmax_small) launch_BT_small(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, ybase, out);
+  if (B.maxn > kSmallN) {
+    const int nskip = B.nmax_small ? kSmallN : 0;
+    launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, ybase, B.Pm, nskip);
+    launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out, nskip);
+    launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out, B.nmin_big);
+  }
   if (phase_aware && B.any_phase1) launch_sub_tD(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, yv, out);
   B.prof.add(PSDP_PROF_BT, m0, B.prof.mark());
 }

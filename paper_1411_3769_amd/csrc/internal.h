@@ -68,6 +68,7 @@ struct SysDesc {
   const int* hm_by_h;   // CSR of active (m,h) pair ids, per h: [L0 + 1] offsets ...
   const int* hm_ids;    // ... into this list of global pair ids
   const int* hm_m;      // ... and the m of each of those pairs
+  const int* pq2b;      // [n][n]: basis index of entry (p, q) (symmetric)
   const int* h_by_m;    // CSR per derivative block m: [M + 1] offsets ...
   const int* h_list;    // ... into this list of h with H_{h,m} != 0
 };

@@ -37,9 +37,11 @@ void launch_sys_finalize(hipStream_t st, int S, const SysDesc* sys, const int* f
                          const double* red, const double* y, const double* BX, double sigma,
                          double* sc);
 void launch_form_P(hipStream_t st, int total, const SysDesc* sys, const int* flags,
-                   const int* own_pre, int S, const double* y, double* Pm);
+                   const int* own_pre, int S, const double* y, double* Pm, int nskip);
 void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* sys,
-                    const int* flags, const double* Pm, double* out);
+                    const int* flags, const double* Pm, double* out, int nskip);
+void launch_BT_small(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys, const int* flags,
+                     const double* y, double* out);
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
                     const int* flags, const double* Pm, double* out, int nmin);
 void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,

@@ -452,11 +452,12 @@ __global__ void __launch_bounds__(256) k_sys_finalize(const SysDesc* __restrict_
 // P_h = V_h(y): one workgroup per (system, h); grid = sum_s L0_s (owner table)
 __global__ void k_form_P(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
                          const int* __restrict__ own_pre, int S, const double* __restrict__ y,
-                         double* Pm) {
+                         double* Pm, int nskip) {
   const int s = find_owner(own_pre, S, blockIdx.x);
   const int h = blockIdx.x - own_pre[s];
   ACTIVE_OR_RETURN(s);
   const SysDesc sd = sys[s];
+  if (sd.n <= nskip) return;   // k_BT_small
   const int n = sd.n;
   double* P = Pm + sd.poff + (int64_t)h * n * n;
   const double* yh = y + sd.voff + (int64_t)h * sd.Nt;
@@ -471,9 +472,10 @@ __global__ void k_form_P(const SysDesc* __restrict__ sys, const int* __restrict_
 // P-blocks of B^T(y): out_j = sum_h beta_{h,j} P_h (ascending h)
 __global__ void k_BT_pblk(const BlkDesc* __restrict__ pblks, const SysDesc* __restrict__ sys,
                           const int* __restrict__ flags, const double* __restrict__ Pm,
-                          double* out) {
+                          double* out, int nskip) {
   const BlkDesc bd = pblks[blockIdx.x];
   ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n <= nskip) return;   // k_BT_small
   const SysDesc sd = sys[bd.sys];
   const int nn = bd.n * bd.n;
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
@@ -1472,6 +1474,81 @@ __global__ void __launch_bounds__(256) k_B_small(const SysDesc* __restrict__ sys
   }
 }
 
+// B^T(y) for systems whose blocks have order <= 16, one wave per block
+// (four per workgroup), reading P_h = V_h(y) straight from y through the
+// (p, q) -> basis index table: P-blocks out_j = sum_h beta_{h,j} P_h
+// (ascending h); derivative blocks Q = sum_{h : H_{h,m} != 0} P_h H_{h,m} on
+// FP64 MFMA (ascending h), out = -(Q + Q^T) through the wave's LDS tile.
+__global__ void __launch_bounds__(256) k_BT_small(int nblk, const BlkDesc* __restrict__ blks,
+                                                  const SysDesc* __restrict__ sys,
+                                                  const int* __restrict__ flags,
+                                                  const double* __restrict__ y, double* out) {
+  __shared__ double sQ[4][256];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int b = blockIdx.x * 4 + wv;
+  if (b >= nblk) return;
+  const BlkDesc bd = blks[b];
+  if (bd.n > kSmallN) return;   // k_form_P + k_BT_pblk + k_BT_dblk
+  if (!(flags[bd.sys] & F_ACTIVE)) return;
+  const SysDesc& sd = sys[bd.sys];
+  const int n = bd.n, nn = n * n, L = sd.L, L0 = sd.L0, Nt = sd.Nt;
+  const double* yv = y + sd.voff;
+  double* O = out + bd.off;
+  if (bd.j < L) {
+    // entries e = lane + 64 u
+    int ix[4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ix[u] = sd.pq2b[min(lane + 64 * u, nn - 1)];
+    for (int h = 0; h < L0; ++h) {
+      const double bt = sd.betaf[(int64_t)h * L + bd.j];
+      if (bt == 0.0) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += bt * yv[(int64_t)h * Nt + ix[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lane + 64 * u < nn) O[lane + 64 * u] = acc[u];
+    return;
+  }
+  const int m = bd.j - L;
+  const int c0 = sd.h_by_m[m], c1 = sd.h_by_m[m + 1];
+  // A[i][k] = P_h[i][k] = y[h Nt + pq2b[i n + k]], B[k][j] = H_{h,m}[k][j]
+  int ia[4];
+  bool oka[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * ks + kq;
+    oka[ks] = r16 < n && k < n;
+    ia[ks] = oka[ks] ? sd.pq2b[r16 * n + k] : 0;
+  }
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int c = c0; c < c1; ++c) {
+    const int h = sd.h_list[c];
+    const double* Hm = sd.H + ((int64_t)m * L0 + h) * nn;
+    double av[4], bv[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int k = 4 * ks + kq;
+      av[ks] = oka[ks] ? yv[(int64_t)h * Nt + ia[ks]] : 0.0;
+      bv[ks] = k < n && r16 < n ? Hm[k * n + r16] : 0.0;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      if (4 * ks < n) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc, 0, 0, 0);
+  }
+  double* q = sQ[wv];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[(4 * i + kq) * 16 + r16] = acc[i];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = 4 * i + kq;
+    if (row < n && r16 < n) O[row * n + r16] = -(acc[i] + q[r16 * 16 + row]);
+  }
+}
+
 // A1 = Z^-1_m H_{m,h}^T, A2 = X_m H_{m,h}^T
 __global__ void __launch_bounds__(256) k_pre12_small(int np, int nmax, int G,
                                                      const HMPair* __restrict__ pairs,
@@ -1795,13 +1872,19 @@ void launch_sys_finalize(hipStream_t st, int S, const SysDesc* sys, const int* f
 }
 
 void launch_form_P(hipStream_t st, int total, const SysDesc* sys, const int* flags,
-                   const int* own_pre, int S, const double* y, double* Pm) {
-  hipLaunchKernelGGL(k_form_P, dim3(total), dim3(256), 0, st, sys, flags, own_pre, S, y, Pm);
+                   const int* own_pre, int S, const double* y, double* Pm, int nskip) {
+  hipLaunchKernelGGL(k_form_P, dim3(total), dim3(256), 0, st, sys, flags, own_pre, S, y, Pm, nskip);
 }
 
 void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* sys,
-                    const int* flags, const double* Pm, double* out) {
-  if (n) hipLaunchKernelGGL(k_BT_pblk, dim3(n), dim3(256), 0, st, pblks, sys, flags, Pm, out);
+                    const int* flags, const double* Pm, double* out, int nskip) {
+  if (n) hipLaunchKernelGGL(k_BT_pblk, dim3(n), dim3(256), 0, st, pblks, sys, flags, Pm, out, nskip);
+}
+
+void launch_BT_small(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys, const int* flags,
+                     const double* y, double* out) {
+  if (nblk)
+    hipLaunchKernelGGL(k_BT_small, dim3((nblk + 3) / 4), dim3(256), 0, st, nblk, blks, sys, flags, y, out);
 }
 
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
