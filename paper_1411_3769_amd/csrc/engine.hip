@@ -721,17 +721,24 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
 // operator helpers
 // ---------------------------------------------------------------------------
 
-// C_b = alpha op(A_b) op(B_b) + beta D_b over every block (small-n packing when
-// every block has n <= 16).
-static void gemm_blocks(Batch& B, hipStream_t st, const double* A, int tA, const double* Bm, int tB,
-                        double* C, double alpha, int aslot, const double* D, double beta,
-                        int bslot) {
-  if (B.nmax_small)
-    launch_gemm_blocks_small(st, B.nblk, B.nmax_small, B.d_blk, B.d_flags, B.d_sc, A, tA, Bm, tB, C,
-                             alpha, aslot, D, beta, bslot);
+// general block product, blocks above kSmallN only (the small ones take the
+// fused kernels)
+static void gemm_big(Batch& B, hipStream_t st, const double* A, const double* Bm, double* C,
+                     double alpha, const double* D, double beta, int bslot) {
   if (B.maxn > kSmallN)
-    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, A, tA, Bm, tB, C, alpha, aslot, D,
-                       beta, bslot, B.nmin_big);
+    launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, A, 0, Bm, 0, C, alpha, -1, D, beta,
+                       bslot, B.nmin_big);
+}
+
+// W1 = sym(Z^-1 A X) on every block
+static void op_sym_ZAX(Batch& B, hipStream_t st, const double* A) {
+  const int nskip = B.nmax_small ? kSmallN : 0;
+  if (B.nmax_small) launch_sym_ZAX_small(st, B.nblk, B.nmax_small, B.d_blk, B.d_flags, B.Zi, A, B.X, B.W1);
+  if (B.maxn > kSmallN) {
+    gemm_big(B, st, B.Zi, A, B.T1, 1.0, nullptr, 0.0, -1);
+    gemm_big(B, st, B.T1, B.X, B.W1, 1.0, nullptr, 0.0, -1);
+    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1, nskip);
+  }
 }
 
 // B^T(y) for every active system; phase-I systems use B'^T (lift + t D).
@@ -860,9 +867,7 @@ static int op_solve_refined(Batch& B, hipStream_t st, const double* rhs, double*
   if (B.f32) launch_park(st, B.S, B.d_flags, 0);
   for (int k = 0; k <= B.ir_max; ++k) {
     op_BT(B, st, x, B.S1);
-    gemm_blocks(B, st, B.Zi, 0, B.S1, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
-    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.W1, 1.0, -1, nullptr, 0.0, -1);
-    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
+    op_sym_ZAX(B, st, B.S1);
     op_B(B, st, B.W1, B.BX, 0.0);
     launch_vec_axpby(st, B.S, B.d_sys, B.d_flags, -1.0, B.BX, 1.0, rhs);   // r = rhs - Lambda x
     launch_ir_check(st, B.S, B.d_sys, B.d_flags, B.BX, rhs, B.d_sc, k, B.ir_max, first ? 1 : 0);
@@ -1155,49 +1160,44 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     // ---- Newton system (Alg. 2 processors/root step 1)
     if (!hoist) op_schur(B, st);
     op_factor(B, st);
+    // blocks of order <= kSmallN take the fused chains, larger ones the
+    // separate products and elementwise kernels (which skip the former)
+    const int nskip = B.nmax_small ? kSmallN : 0;
     // Omega_1 = B(Z^-1 G X) - a
     { const size_t pm_ = B.prof.mark();
-    gemm_blocks(B, st, B.Zi, 0, B.G, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    op_sym_ZAX(B, st, B.G);
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.W1, 1.0, -1, nullptr, 0.0, -1);
-      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
-      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     op_B(B, st, B.W1, B.rv1, 1.0);
     op_solve_refined(B, st, B.rv1, B.dyh, true);
-    // predictor directions (processors step 2)
+    // predictor directions (processors step 2) and the corrector right-hand
+    // side W = mu Z^-1 - Z^-1 dZ^ dX^
     op_BT(B, st, B.dyh, B.S1);
     { const size_t pm_ = B.prof.mark();
-    launch_axpby(st, B.nblk, B.d_blk, B.d_flags, -1.0, B.G, 1.0, B.S1, B.dZh);
-      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    gemm_blocks(B, st, B.Zi, 0, B.dZh, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    if (B.nmax_small)
+      launch_pred_dir_small(st, B.nblk, B.nmax_small, B.d_blk, B.d_flags, B.d_sc, B.S1, B.G, B.Zi, B.X,
+                            B.dZh, B.dXh, B.Wc, B.W1);
+    if (B.maxn > kSmallN) {
+      launch_axpby(st, B.nblk, B.d_blk, B.d_flags, -1.0, B.G, 1.0, B.S1, B.dZh, nskip);
+      gemm_big(B, st, B.Zi, B.dZh, B.T1, 1.0, nullptr, 0.0, -1);
+      gemm_big(B, st, B.T1, B.X, B.dXh, -1.0, B.X, -1.0, -1);
+      gemm_big(B, st, B.T1, B.dXh, B.Wc, -1.0, B.Zi, 1.0, S_MU);
+      launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.Wc, B.W1, nskip);
+    }
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.dXh, -1.0, -1, B.X, -1.0, -1);
-      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
-    // corrector right-hand side: W = mu Z^-1 - Z^-1 dZ^ dX^
-    { const size_t pm_ = B.prof.mark();
-    gemm_blocks(B, st, B.T1, 0, B.dXh, 0, B.Wc, -1.0, -1, B.Zi, 1.0, S_MU);
-      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.Wc, B.W1);
-      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     op_B(B, st, B.W1, B.rv2, 0.0);
     op_solve_refined(B, st, B.rv2, B.dyb, false);
-    // corrector directions (processors step 3)
+    // corrector directions (processors step 3), summed with the predictor's
     op_BT(B, st, B.dyb, B.dZb);
     { const size_t pm_ = B.prof.mark();
-    gemm_blocks(B, st, B.Zi, 0, B.dZb, 0, B.T1, 1.0, -1, nullptr, 0.0, -1);
+    if (B.nmax_small)
+      launch_corr_dir_small(st, B.nblk, B.nmax_small, B.d_blk, B.d_flags, B.Zi, B.dZb, B.X, B.Wc, B.dXh,
+                            B.dZh, B.dX, B.dZ);
+    if (B.maxn > kSmallN) {
+      gemm_big(B, st, B.Zi, B.dZb, B.T1, 1.0, nullptr, 0.0, -1);
+      gemm_big(B, st, B.T1, B.X, B.dXb, -1.0, B.Wc, 1.0, -1);
+      launch_combine(st, B.nblk, B.d_blk, B.d_flags, B.dXh, B.dXb, B.dX, B.dZh, B.dZb, B.dZ, nskip);
+    }
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    gemm_blocks(B, st, B.T1, 0, B.X, 0, B.dXb, -1.0, -1, B.Wc, 1.0, -1);
-      B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    launch_combine(st, B.nblk, B.d_blk, B.d_flags, B.dXh, B.dXb, B.dX, B.dZh, B.dZb, B.dZ);
-      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     // step lengths and update
     { const size_t pm_ = B.prof.mark();
     launch_ladder(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);

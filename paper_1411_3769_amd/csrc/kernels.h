@@ -19,12 +19,12 @@ void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int
 void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                    const double* Cf, const double* S, const double* Z, double* G);
 void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
-                  const double* A, double b, const double* B, double* out);
+                  const double* A, double b, const double* B, double* out, int nskip = 0);
 void launch_symmetrize(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
-                       const double* W, double* out);
+                       const double* W, double* out, int nskip = 0);
 void launch_combine(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                     const double* dXh, const double* dXb, double* dX, const double* dZh,
-                    const double* dZb, double* dZ);
+                    const double* dZb, double* dZ, int nskip = 0);
 void launch_update_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                           const double* sc, double* X, const double* dX, double* Z,
                           const double* dZ);
@@ -64,10 +64,14 @@ void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const
                          const double* arena, double* Lam, const int64_t* gpoff, int prec);
 bool use_small(int nmax);
 
-void launch_gemm_blocks_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks,
-                              const int* flags, const double* sc, const double* A, int tA,
-                              const double* B, int tB, double* C, double alpha, int aslot,
-                              const double* D, double beta, int bslot);
+void launch_sym_ZAX_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks, const int* flags,
+                          const double* Zi, const double* A, const double* X, double* W1);
+void launch_pred_dir_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks, const int* flags,
+                           const double* sc, const double* S1, const double* Gm, const double* Zi,
+                           const double* X, double* dZh, double* dXh, double* Wc, double* W1);
+void launch_corr_dir_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks, const int* flags,
+                           const double* Zi, const double* dZb, const double* X, const double* Wc,
+                           const double* dXh, const double* dZh, double* dX, double* dZ);
 void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks,
                           const SysDesc* sys, const int* flags, const double* Pm, double* out);
 void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,

@@ -258,9 +258,10 @@ __global__ void k_make_G(const BlkDesc* __restrict__ blks, const int* __restrict
 // out = a * A + b * B (elementwise over blocks)
 __global__ void k_axpby(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
                         double a, const double* __restrict__ A, double b,
-                        const double* __restrict__ B, double* out) {
+                        const double* __restrict__ B, double* out, int nskip) {
   const BlkDesc bd = blks[blockIdx.x];
   ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n <= nskip) return;   // the fused small-block kernels
   const int nn = bd.n * bd.n;
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
     const int64_t o = bd.off + e;
@@ -270,9 +271,10 @@ __global__ void k_axpby(const BlkDesc* __restrict__ blks, const int* __restrict_
 
 // out = (W + W^T) / 2 (out may alias W: each thread owns the pair (i,j),(j,i))
 __global__ void k_symmetrize(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
-                             const double* W, double* out) {
+                             const double* W, double* out, int nskip) {
   const BlkDesc bd = blks[blockIdx.x];
   ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n <= nskip) return;   // the fused small-block kernels
   const int n = bd.n;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
@@ -287,9 +289,10 @@ __global__ void k_symmetrize(const BlkDesc* __restrict__ blks, const int* __rest
 __global__ void k_combine(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
                           const double* __restrict__ dXh, const double* __restrict__ dXb,
                           double* dX, const double* __restrict__ dZh,
-                          const double* __restrict__ dZb, double* dZ) {
+                          const double* __restrict__ dZb, double* dZ, int nskip) {
   const BlkDesc bd = blks[blockIdx.x];
   ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n <= nskip) return;   // k_corr_dir_small
   const int n = bd.n;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
@@ -1303,32 +1306,127 @@ __device__ inline SmallSlot small_slot(int nmax, int G, int count) {
   return t;
 }
 
-__global__ void __launch_bounds__(256) k_gemm_blocks_small(
-    int nblk, int nmax, int G, const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
-    const double* __restrict__ sc, const double* A, int tA, const double* B, int tB, double* C,
-    double alpha, int aslot, const double* D, double beta, int bslot) {
-  __shared__ double sA[256], sB[256];
+// Fused chains of block products for blocks of order <= 16 (G blocks per
+// workgroup, one thread per entry, operands and intermediates in LDS).  Each
+// performs, entry for entry, the arithmetic of the launches it replaces.
+
+// W1 = sym(Z^-1 A X): T = Z^-1 A, W = T X, W1 = (W + W^T) / 2
+__global__ void __launch_bounds__(256) k_sym_ZAX_small(int nblk, int nmax, int G,
+                                                       const BlkDesc* __restrict__ blks,
+                                                       const int* __restrict__ flags,
+                                                       const double* __restrict__ Zi,
+                                                       const double* __restrict__ A,
+                                                       const double* __restrict__ X, double* W1) {
+  __shared__ double sZ[256], sA[256], sX[256], sT[256];
   SmallSlot t = small_slot(nmax, G, nblk);
   BlkDesc bd{};
   if (t.ok) {
     bd = blks[t.item];
     t.ok = (flags[bd.sys] & F_ACTIVE) && bd.n <= nmax && t.e < bd.n * bd.n;
   }
-  double* pa = sA + t.li * t.per;
-  double* pb = sB + t.li * t.per;
+  const int base = t.li * t.per, n = bd.n;
+  const int i = t.ok ? t.e / n : 0, j = t.ok ? t.e - i * n : 0;
+  const int64_t o = bd.off + t.e;
+  double *pz = sZ + base, *pa = sA + base, *px = sX + base, *pt = sT + base;
   if (t.ok) {
-    pa[t.e] = A[bd.off + t.e];
-    pb[t.e] = B[bd.off + t.e];
+    pz[t.e] = Zi[o];
+    pa[t.e] = A[o];
+    px[t.e] = X[o];
   }
   __syncthreads();
-  if (!t.ok) return;
-  const int n = bd.n, i = t.e / n, j = t.e - i * n;
-  double a = alpha, cc = beta;
-  if (aslot >= 0) a *= sc[bd.sys * kNSC + aslot];
-  if (bslot >= 0) cc *= sc[bd.sys * kNSC + bslot];
-  double v = a * dot_n(n, i, j, pa, tA, pb, tB);
-  if (D) v += cc * D[bd.off + t.e];
-  C[bd.off + t.e] = v;
+  if (t.ok) pt[t.e] = 1.0 * dot_n(n, i, j, pz, 0, pa, 0);
+  __syncthreads();
+  if (t.ok) pa[t.e] = 1.0 * dot_n(n, i, j, pt, 0, px, 0);
+  __syncthreads();
+  if (t.ok) W1[o] = 0.5 * (pa[i * n + j] + pa[j * n + i]);
+}
+
+// predictor directions and the corrector's right-hand side:
+// dZh = S1 - G, T = Z^-1 dZh, dXh = -T X - X, Wc = -T dXh + mu Z^-1,
+// W1 = sym(Wc)
+__global__ void __launch_bounds__(256) k_pred_dir_small(
+    int nblk, int nmax, int G, const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+    const double* __restrict__ sc, const double* __restrict__ S1, const double* __restrict__ Gm,
+    const double* __restrict__ Zi, const double* __restrict__ X, double* dZh, double* dXh,
+    double* Wc, double* W1) {
+  __shared__ double sZ[256], sX[256], sD[256], sT[256], sH[256], sC[256];
+  SmallSlot t = small_slot(nmax, G, nblk);
+  BlkDesc bd{};
+  if (t.ok) {
+    bd = blks[t.item];
+    t.ok = (flags[bd.sys] & F_ACTIVE) && bd.n <= nmax && t.e < bd.n * bd.n;
+  }
+  const int base = t.li * t.per, n = bd.n;
+  const int i = t.ok ? t.e / n : 0, j = t.ok ? t.e - i * n : 0;
+  const int64_t o = bd.off + t.e;
+  double *pz = sZ + base, *px = sX + base, *pd = sD + base, *pt = sT + base, *ph = sH + base,
+         *pc = sC + base;
+  if (t.ok) {
+    pz[t.e] = Zi[o];
+    px[t.e] = X[o];
+    const double dz = -1.0 * Gm[o] + 1.0 * S1[o];
+    pd[t.e] = dz;
+    dZh[o] = dz;
+  }
+  __syncthreads();
+  if (t.ok) pt[t.e] = 1.0 * dot_n(n, i, j, pz, 0, pd, 0);
+  __syncthreads();
+  if (t.ok) {
+    double v = -1.0 * dot_n(n, i, j, pt, 0, px, 0);
+    v += -1.0 * px[t.e];
+    ph[t.e] = v;
+    dXh[o] = v;
+  }
+  __syncthreads();
+  if (t.ok) {
+    const double mu = 1.0 * sc[bd.sys * kNSC + S_MU];
+    double v = -1.0 * dot_n(n, i, j, pt, 0, ph, 0);
+    v += mu * pz[t.e];
+    pc[t.e] = v;
+    Wc[o] = v;
+  }
+  __syncthreads();
+  if (t.ok) W1[o] = 0.5 * (pc[i * n + j] + pc[j * n + i]);
+}
+
+// corrector directions and their sum with the predictor's:
+// T = Z^-1 dZb, dXb = -T X + Wc, dX = sym(dXh + dXb), dZ = dZh + dZb
+__global__ void __launch_bounds__(256) k_corr_dir_small(
+    int nblk, int nmax, int G, const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
+    const double* __restrict__ Zi, const double* __restrict__ dZb, const double* __restrict__ X,
+    const double* __restrict__ Wc, const double* __restrict__ dXh, const double* __restrict__ dZh,
+    double* dX, double* dZ) {
+  __shared__ double sZ[256], sB[256], sX[256], sT[256], sS[256];
+  SmallSlot t = small_slot(nmax, G, nblk);
+  BlkDesc bd{};
+  if (t.ok) {
+    bd = blks[t.item];
+    t.ok = (flags[bd.sys] & F_ACTIVE) && bd.n <= nmax && t.e < bd.n * bd.n;
+  }
+  const int base = t.li * t.per, n = bd.n;
+  const int i = t.ok ? t.e / n : 0, j = t.ok ? t.e - i * n : 0;
+  const int64_t o = bd.off + t.e;
+  double *pz = sZ + base, *pb = sB + base, *px = sX + base, *pt = sT + base, *ps = sS + base;
+  double zb = 0.0;
+  if (t.ok) {
+    pz[t.e] = Zi[o];
+    zb = dZb[o];
+    pb[t.e] = zb;
+    px[t.e] = X[o];
+  }
+  __syncthreads();
+  if (t.ok) pt[t.e] = 1.0 * dot_n(n, i, j, pz, 0, pb, 0);
+  __syncthreads();
+  if (t.ok) {
+    double v = -1.0 * dot_n(n, i, j, pt, 0, px, 0);
+    v += 1.0 * Wc[o];
+    ps[t.e] = dXh[o] + v;
+  }
+  __syncthreads();
+  if (t.ok) {
+    dX[o] = 0.5 * (ps[i * n + j] + ps[j * n + i]);
+    dZ[o] = dZh[o] + zb;
+  }
 }
 
 // -sum_h (P_h H_{m,h} + (P_h H_{m,h})^T) for each d-block m; the workgroup
@@ -1833,19 +1931,20 @@ void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* fla
 }
 
 void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
-                  const double* A, double b, const double* B, double* out) {
-  hipLaunchKernelGGL(k_axpby, dim3(nblk), dim3(256), 0, st, blks, flags, a, A, b, B, out);
+                  const double* A, double b, const double* B, double* out, int nskip) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblk), dim3(256), 0, st, blks, flags, a, A, b, B, out, nskip);
 }
 
 void launch_symmetrize(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
-                       const double* W, double* out) {
-  hipLaunchKernelGGL(k_symmetrize, dim3(nblk), dim3(256), 0, st, blks, flags, W, out);
+                       const double* W, double* out, int nskip) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(nblk), dim3(256), 0, st, blks, flags, W, out, nskip);
 }
 
 void launch_combine(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                     const double* dXh, const double* dXb, double* dX, const double* dZh,
-                    const double* dZb, double* dZ) {
-  hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(256), 0, st, blks, flags, dXh, dXb, dX, dZh, dZb, dZ);
+                    const double* dZb, double* dZ, int nskip) {
+  hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(256), 0, st, blks, flags, dXh, dXb, dX, dZh, dZb, dZ,
+                     nskip);
 }
 
 void launch_update_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
@@ -2032,13 +2131,27 @@ static int small_G(int nmax) { return nmax >= 1 && nmax <= kSmallN ? 256 / (nmax
 
 bool use_small(int nmax) { return small_G(nmax) > 0; }
 
-void launch_gemm_blocks_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks,
-                              const int* flags, const double* sc, const double* A, int tA,
-                              const double* B, int tB, double* C, double alpha, int aslot,
-                              const double* D, double beta, int bslot) {
+void launch_sym_ZAX_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks, const int* flags,
+                          const double* Zi, const double* A, const double* X, double* W1) {
   const int G = small_G(nmax);
-  hipLaunchKernelGGL(k_gemm_blocks_small, dim3((nblk + G - 1) / G), dim3(256), 0, st, nblk, nmax, G,
-                     blks, flags, sc, A, tA, B, tB, C, alpha, aslot, D, beta, bslot);
+  hipLaunchKernelGGL(k_sym_ZAX_small, dim3((nblk + G - 1) / G), dim3(256), 0, st, nblk, nmax, G, blks,
+                     flags, Zi, A, X, W1);
+}
+
+void launch_pred_dir_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks, const int* flags,
+                           const double* sc, const double* S1, const double* Gm, const double* Zi,
+                           const double* X, double* dZh, double* dXh, double* Wc, double* W1) {
+  const int G = small_G(nmax);
+  hipLaunchKernelGGL(k_pred_dir_small, dim3((nblk + G - 1) / G), dim3(256), 0, st, nblk, nmax, G, blks,
+                     flags, sc, S1, Gm, Zi, X, dZh, dXh, Wc, W1);
+}
+
+void launch_corr_dir_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks, const int* flags,
+                           const double* Zi, const double* dZb, const double* X, const double* Wc,
+                           const double* dXh, const double* dZh, double* dX, double* dZ) {
+  const int G = small_G(nmax);
+  hipLaunchKernelGGL(k_corr_dir_small, dim3((nblk + G - 1) / G), dim3(256), 0, st, nblk, nmax, G, blks,
+                     flags, Zi, dZb, X, Wc, dXh, dZh, dX, dZ);
 }
 
 void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks,
