@@ -72,66 +72,63 @@ __device__ inline void st16(double* D, v4d acc, double sign, bool add) {
 }
 
 // Wave-level factorisation and inverse of the 16 x 16 block at B (leading
-// dimension kLD) by the 64 lanes of one wave: lane (r, g) = (l % 16, l / 16)
-// holds row r, columns 4g..4g+3.  On return B holds L (zeros above the
-// diagonal) and Xb holds L^{-1}.  Non-positive pivots set *fail (replaced by 1).
+// dimension kLD; lower triangle read).  Lane r of each 16-lane row of the
+// wave holds row r (the four rows of the wave compute the same block; the
+// first writes it).  Column k of L is the pivot's column scaled by the
+// Newton reciprocal square root of the pivot; L goes to B, and lane c then
+// forms column c of X = L^{-1} by forward substitution, reading the rows of
+// L back from B.  Values travel by DPP row broadcasts and LDS broadcasts
+// only, so the dependent chain per column is a broadcast, the reciprocal
+// square root and one multiply-add.  On return B holds L (zeros above the
+// diagonal) and Xb holds L^{-1}.  Non-positive pivots set *fail (replaced
+// by 1).
 __device__ inline void wave_potri16(double* B, double* Xb, int* fail) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  double v[4], rsv[16];
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  double a[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = c <= r ? B[r * kLD + c] : 0.0;
+  double rs[16];
   bool bad = false;
+  static_for<16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    double d = row_bcast16<k>(a[k]);
+    const bool bb = !(d > 0.0) || !isfinite(d);
+    bad = bad || bb;
+    d = bb ? 1.0 : d;
+    rs[k] = rsqrt_nr(d);
+    const double lrk = r > k ? a[k] * rs[k] : (r == k ? d * rs[k] : 0.0);
+    a[k] = lrk;
+    static_for<16>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c > k) {
+        const double lck = row_bcast16<c>(lrk);
+        a[c] = r >= c ? a[c] - lrk * lck : a[c];
+      }
+    });
+  });
+  if (lane < 16) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = B[r * kLD + 4 * g + j];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int kg = k >> 2, kj = k & 3;
-    double d = readlane_d(v[kj], k + 16 * kg);
-    const bool b = !(d > 0.0) || !isfinite(d);
-    bad = bad || b;
-    d = b ? 1.0 : d;
-    const double rs = rsqrt_nr(d), s = d * rs;
-    rsv[k] = rs;
-    // every lane takes part in every shuffle (a lane outside a shuffle
-    // would hand undefined values to the lanes reading from it)
-    const double ark = __shfl(v[kj], r + 16 * kg);
-    const double lrk = r == k ? s : ark * rs;
-    double lck[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = 4 * g + j;
-      const double ack = __shfl(v[kj], cc + 16 * kg);
-      lck[j] = cc == k ? s : ack * rs;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = 4 * g + j;
-      if (cc > k && r >= cc) v[j] -= lrk * lck[j];
-    }
-    if (g == kg) v[kj] = r > k ? lrk : (r == k ? s : 0.0);
+    for (int c = 0; c < 16; ++c) B[r * kLD + c] = a[c];
   }
+  // the wave's LDS accesses complete in order; keep the compiler from
+  // moving the reads of L above its writes
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // column r of X: x[i] = (delta_{ir} - sum_{m<i} L[i][m] x[m]) / L[i][i],
+  // the row of L read back from LDS (one address per row: a broadcast)
+  double x[16];
+  static_for<16>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    double acc = r == i ? 1.0 : 0.0;
+    static_for<i>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      acc -= B[i * kLD + m] * x[m];
+    });
+    x[i] = acc * rs[i];
+  });
+  if (lane < 16) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    v[j] = r >= 4 * g + j ? v[j] : 0.0;
-    B[r * kLD + 4 * g + j] = v[j];
+    for (int i = 0; i < 16; ++i) Xb[i * kLD + r] = x[i];
   }
-  // X = L^{-1}: row r' is final once the rows above it are subtracted
-  double x[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) x[j] = r == 4 * g + j ? 1.0 : 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (r == k) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) x[j] *= rsv[k];
-    }
-    const double lr = __shfl(v[k & 3], r + 16 * (k >> 2));   // L[r][k]
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double xk = __shfl(x[j], k + 16 * g);          // X[k][4g+j]
-      if (r > k) x[j] -= lr * xk;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) Xb[r * kLD + 4 * g + j] = x[j];
   if (bad && lane == 0) *fail = 1;
 }
 
