@@ -110,29 +110,28 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // Whether the Cholesky factorisation of the symmetric 16 x 16 matrix held by
-// one wave succeeds (every pivot positive and finite).  Lane (r, g) =
-// (l % 16, l / 16) holds row r, columns 4g .. 4g + 3 in v (only the lower
-// triangle is read; v is overwritten); the result is the same on every lane.
-__device__ inline bool wave_chol_ok16(double* v) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+// a row of 16 lanes succeeds (every pivot positive and finite): lane r holds
+// row r in a (only the lower triangle is read; a is overwritten).  Column k
+// is scaled by the Newton reciprocal square root of its pivot and values
+// travel by DPP row broadcasts; the result is the same on the row's 16 lanes.
+__device__ __forceinline__ bool rows_chol_ok16(double* a, int r) {
   bool bad = false;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int kg = k >> 2, kj = k & 3;
-    double d = readlane_d(v[kj], k + 16 * kg);
-    const bool b = !(d > 0.0) || !isfinite(d);
-    bad = bad || b;
-    d = b ? 1.0 : d;
+  static_for<16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    double d = row_bcast16<k>(a[k]);
+    const bool bb = !(d > 0.0) || !isfinite(d);
+    bad = bad || bb;
+    d = bb ? 1.0 : d;
     const double rs = rsqrt_nr(d);
-    // every lane takes part in every shuffle
-    const double lrk = __shfl(v[kj], r + 16 * kg) * rs;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = 4 * g + j;
-      const double lck = __shfl(v[kj], cc + 16 * kg) * rs;
-      if (cc > k && r >= cc) v[j] -= lrk * lck;
-    }
-  }
+    const double lrk = a[k] * rs;   // L[r][k] on the lanes r >= k that use it
+    static_for<16>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c > k) {
+        const double lck = row_bcast16<c>(lrk);
+        a[c] = r >= c ? a[c] - lrk * lck : a[c];
+      }
+    });
+  });
   return !bad;
 }
 

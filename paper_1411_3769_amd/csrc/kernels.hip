@@ -148,47 +148,46 @@ __global__ void __launch_bounds__(256) k_ladder(const BlkDesc* __restrict__ blks
   if (threadIdx.x == 0) kout[blockIdx.x] = found;
 }
 
-// The same ladder for blocks of order <= 16, one wave per block (four blocks
-// per workgroup): the block sits in the wave's registers (lane (r, g) holds
-// row r, columns 4g..4g+3; identity past n) and the rungs are tried in order
-// with the wave Cholesky (the first rung passes in most iterations).
+// The same ladder for blocks of order <= 16, sixteen lanes per block
+// (sixteen blocks per workgroup): lane r holds row r of the block (identity
+// past n) and the rungs are tried in order with the row Cholesky test (the
+// first rung passes in most iterations).
 __global__ void __launch_bounds__(256) k_ladder16(const BlkDesc* __restrict__ blks, int nblk,
                                                   const int* __restrict__ flags,
                                                   const double* __restrict__ V,
                                                   const double* __restrict__ dV, double rho,
                                                   double frac, int len, int* kout) {
-  const int b = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 16 + (int)(threadIdx.x >> 4), r = threadIdx.x & 15;
   if (b >= nblk) return;
   const BlkDesc bd = blks[b];
   if (bd.n > kSmallN) return;   // k_ladder
   if (!(flags[bd.sys] & F_ACTIVE)) {
-    if (lane == 0) kout[b] = 0;
+    if (r == 0) kout[b] = 0;
     return;
   }
-  const int n = bd.n, r = lane & 15, g = lane >> 4;
-  double v0[4], dv[4];
-  bool in[4];
+  const int n = bd.n;
+  double v0[16], dv[16];
+  bool in[16];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int cc = 4 * g + j;
-    in[j] = r < n && cc < n;
-    v0[j] = in[j] ? V[bd.off + r * n + cc] : (r == cc ? 1.0 : 0.0);
-    dv[j] = in[j] ? dV[bd.off + r * n + cc] : 0.0;
+  for (int c = 0; c < 16; ++c) {
+    in[c] = c <= r && r < n;
+    v0[c] = in[c] ? V[bd.off + r * n + c] : (r == c ? 1.0 : 0.0);
+    dv[c] = in[c] ? dV[bd.off + r * n + c] : 0.0;
   }
   int found = -1;
   double rk = 1.0;
   for (int k = 0; k <= len; ++k) {
     const double t = rk / frac;
-    double tv[4];
+    double tv[16];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) tv[j] = in[j] ? __dadd_rn(v0[j], __dmul_rn(t, dv[j])) : v0[j];
-    if (wave_chol_ok16(tv)) {
+    for (int c = 0; c < 16; ++c) tv[c] = in[c] ? __dadd_rn(v0[c], __dmul_rn(t, dv[c])) : v0[c];
+    if (rows_chol_ok16(tv, r)) {
       found = k;
       break;
     }
     rk = rk * rho;
   }
-  if (lane == 0) kout[b] = found;
+  if (r == 0) kout[b] = found;
 }
 
 // Per system: k* = max over blocks of the first passing rung; the step is
@@ -693,41 +692,42 @@ __global__ void __launch_bounds__(256) k_certificate(const BlkDesc* __restrict__
   }
 }
 
-// The same certificate for blocks of order <= 16, one wave per block: the
-// block stays in registers (identity past n, never shifted) and each
-// bisection step is one wave Cholesky.
+// The same certificate for blocks of order <= 16, sixteen lanes per block
+// (lane r holds row r): the block stays in registers (identity past n, never
+// shifted) and each bisection step is one row Cholesky test.
 __global__ void __launch_bounds__(256) k_certificate16(const BlkDesc* __restrict__ blks, int nblk,
                                                        const SysDesc* __restrict__ sys,
                                                        const int* __restrict__ flags,
                                                        const double* __restrict__ Q, int iters,
                                                        double* out) {
-  const int b = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 16 + (int)(threadIdx.x >> 4), r = threadIdx.x & 15;
   if (b >= nblk) return;
   const BlkDesc bd = blks[b];
   if (bd.n > kSmallN) return;   // k_certificate
   if (!(flags[bd.sys] & F_ACTIVE)) return;
-  const int n = bd.n, r = lane & 15, g = lane >> 4;
+  const int n = bd.n;
   const double sj = sys[bd.sys].scale[bd.j];
-  double q[4], f = 0.0;
+  double q[16], fg[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int cc = 4 * g + j;
-    const bool in = r < n && cc < n;
-    q[j] = in ? Q[bd.off + r * n + cc] : (r == cc ? 1.0 : 0.0);
-    if (in) f += q[j] * q[j];
+  for (int c = 0; c < 16; ++c) {
+    const bool in = r < n && c < n;
+    q[c] = in ? Q[bd.off + r * n + c] : (r == c ? 1.0 : 0.0);
+    if (in) fg[c >> 2] += q[c] * q[c];
   }
+  // ||Q||_F: column quarters paired (0, 2), (1, 3), then rows by xor 8, 4, 2, 1
+  double f = (fg[0] + fg[2]) + (fg[1] + fg[3]);
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) f += __shfl_xor(f, m);
+  for (int m = 8; m >= 1; m >>= 1) f += __shfl_xor(f, m);
   const double fro = sqrt(f);
   double lo = 0, hi = 0;
   int pass0 = 0;
   for (int it = -1; it < iters; ++it) {
     const double tau = it < 0 ? 0.0 : 0.5 * (lo + hi);
     const double shift = tau * sj;
-    double tv[4];
+    double tv[16];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) tv[j] = (r == 4 * g + j && r < n) ? q[j] - shift : q[j];
-    const bool ok = wave_chol_ok16(tv);
+    for (int c = 0; c < 16; ++c) tv[c] = (r == c && r < n) ? q[c] - shift : q[c];
+    const bool ok = rows_chol_ok16(tv, r);
     if (it < 0) {
       pass0 = ok;
       const double bnd = fro / sj + 1.0;
@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(256) k_certificate16(const BlkDesc* __restrict
       if (ok) lo = tau; else hi = tau;
     }
   }
-  if (lane == 0) {
+  if (r == 0) {
     out[b * 2 + 0] = pass0;
     out[b * 2 + 1] = 0.5 * (lo + hi);
   }
@@ -1903,7 +1903,7 @@ void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const Blk
                    const int* flags, const double* V, const double* dV, double rho, double frac,
                    int len, int* kout) {
   if (nmax_small)
-    hipLaunchKernelGGL(k_ladder16, dim3((nblk + 3) / 4), dim3(256), 0, st, blks, nblk, flags, V, dV, rho, frac,
+    hipLaunchKernelGGL(k_ladder16, dim3((nblk + 15) / 16), dim3(256), 0, st, blks, nblk, flags, V, dV, rho, frac,
                        len, kout);
   if (maxn > kSmallN) {
     const size_t lds = (size_t)maxn * maxn * 8;
@@ -2026,7 +2026,7 @@ void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, cons
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,
                         double* out) {
-  hipLaunchKernelGGL(k_certificate16, dim3((nblk + 3) / 4), dim3(256), 0, st, blks, nblk, sys, flags, Q,
+  hipLaunchKernelGGL(k_certificate16, dim3((nblk + 15) / 16), dim3(256), 0, st, blks, nblk, sys, flags, Q,
                      iters, out);
   if (maxn > kSmallN) {
     const size_t lds = (size_t)maxn * maxn * 8;
