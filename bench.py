@@ -35,6 +35,7 @@ PEAK_HBM = 8000.0         # GB/s
 # what they read for a plain 256 MiB device copy: x2.000 and x1.000).  Valid
 # for the kernel versions those runs measured; drop an entry once they change.
 PMC_TRAFFIC = {
+    ("n10", "cholesky"): dict(fetch_kib=21943.5, fetch_scale=2.000, write_kib=17995.3, write_scale=1.000),
 }
 
 
