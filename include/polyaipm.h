@@ -279,7 +279,8 @@ int psdp_ipm_solve_batched(psdp_sdp* const* sdps, int count, const psdp_opts* op
  *   Zi    [L+M][n][n]  block inverses Z_j^{-1}
  *   BTy   [L+M][n][n]  B^T(y)                         (eq. AT)
  *   BX    [K]          B(X)
- *   Lam   [K][K]       Schur complement Omega (eq. T2), full symmetric
+ *   Lam   [K][K]       Schur complement Omega (eq. T2), full symmetric (built on
+ *                      the device as its lower triangle and mirrored here)
  *   LamL  [K][K]       its lower Cholesky factor (upper part zero)
  *   sol   [K]          Omega^{-1} y
  * The basis order of the dual variable is the library's (see psdp_basis).

@@ -1666,9 +1666,13 @@ int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y
   if (BX) PSDP_HIP(hipMemcpyAsync(BX, B.BX, d.K * 8, hipMemcpyDeviceToHost, st));
   std::vector<double> full((size_t)d.Kpad * d.Kpad);
   if (Lam) {
+    // the assembly builds the lower triangle (all the factorisation reads);
+    // the caller gets it mirrored
     PSDP_HIP(hipMemcpyAsync(full.data(), B.Lam, full.size() * 8, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < d.K; ++i) std::memcpy(Lam + (int64_t)i * d.K, full.data() + (int64_t)i * d.Kpad, d.K * 8);
+    for (int i = 0; i < d.K; ++i)
+      for (int j = 0; j < d.K; ++j)
+        Lam[(int64_t)i * d.K + j] = j <= i ? full[(size_t)i * d.Kpad + j] : full[(size_t)j * d.Kpad + i];
   }
   op_factor(B, st);
   op_solve(B, st, B.y, B.dyh);

@@ -1086,9 +1086,12 @@ __device__ __forceinline__ void assemble_pair(const AsmTile* __restrict__ tiles,
     const int Nt = sd.Nt;
     const int64_t ld = sd.Kpad;
     double* Lr = Lam + sd.loff;
+    // Lambda[(h, b1), (h2, b2)] goes to its lower-triangle place
+    // (h2 Nt + b2, h Nt + b1), the only triangle the factorisation reads;
+    // consecutive threads take consecutive b1, i.e. consecutive columns
 #pragma unroll 2
     for (int e = tid; e < Nt * Nt; e += NTH) {
-      const int b1 = e / Nt, b2 = e - b1 * Nt;
+      const int b2 = e / Nt, b1 = e - b2 * Nt;
       const int p = sd.basis[2 * b1], q = sd.basis[2 * b1 + 1];
       const int r = sd.basis[2 * b2], s = sd.basis[2 * b2 + 1];
       double v = R[(q * n + r) * n2 + s * n + p];
@@ -1098,8 +1101,7 @@ __device__ __forceinline__ void assemble_pair(const AsmTile* __restrict__ tiles,
         if (r != s) v += R[(p * n + s) * n2 + r * n + q];
       }
       const int64_t row = (int64_t)tl.h * Nt + b1, col = (int64_t)tl.h2 * Nt + b2;
-      Lr[row * ld + col] = v;
-      if (tl.h != tl.h2) Lr[col * ld + row] = v;
+      Lr[col * ld + row] = v;
     }
     if (!RL) __syncthreads();   // R is rewritten by the next pair
   }
@@ -1253,10 +1255,11 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
   const int n1 = min(kTB, n - kTB * g1), n2s = min(kTB, n - kTB * g2);
   const int n3 = min(kTB, n - kTB * g3), n4 = min(kTB, n - kTB * g4);
   const int64_t ld = sd.Kpad;
-  const bool mirror = !(tl.h == tl.h2 && tl.rg == tl.cg);
   double* Lr = Lam + sd.loff;
+  // every entry goes to its lower-triangle place (col, row) (a diagonal
+  // tile covers its own transpose); consecutive threads take consecutive rows
   for (int e = tid; e < 4096; e += 256) {
-    const int rowl = e >> 6, coll = e & 63;
+    const int coll = e >> 6, rowl = e & 63;
     const int pi = rowl >> 3, qi = rowl & 7, ri = coll >> 3, si = coll & 7;
     if (pi >= n1 || qi >= n2s || ri >= n3 || si >= n4) continue;
     if (pqdiag && qi < pi) continue;
@@ -1265,9 +1268,7 @@ __global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict_
     const int bj = rsdiag ? ri * n3 - ri * (ri - 1) / 2 + (si - ri) : ri * n4 + si;
     const int64_t row = (int64_t)tl.h * sd.Nt + roff + bi;
     const int64_t col = (int64_t)tl.h2 * sd.Nt + coff + bj;
-    const double v = sL[rowl * 65 + coll];
-    Lr[row * ld + col] = v;
-    if (mirror) Lr[col * ld + row] = v;
+    Lr[col * ld + row] = sL[rowl * 65 + coll];
   }
 }
 
