@@ -742,14 +742,18 @@ static void op_sym_ZAX(Batch& B, hipStream_t st, const double* A) {
 }
 
 // B^T(y) for every active system; phase-I systems use B'^T (lift + t D).
-static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool phase_aware = true) {
+// With G given (phase-unaware callers excluded), also G = C - B^T(y) + Z.
+static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool phase_aware = true,
+                  double* G = nullptr) {
   const size_t m0 = B.prof.mark();
   const double* ybase = yv;
   if (phase_aware && B.any_phase1) {
     launch_lift(st, B.S, B.d_sys, B.d_flags, yv, B.ylift);
     ybase = B.ylift;
   }
-  if (B.nmax_small) launch_BT_small(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, ybase, out);
+  // the small-block epilogue's G would miss the phase-I term added below
+  double* Gs = (G && !(phase_aware && B.any_phase1)) ? G : nullptr;
+  if (B.nmax_small) launch_BT_small(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, ybase, out, B.Cf, B.Z, Gs);
   if (B.maxn > kSmallN) {
     const int nskip = B.nmax_small ? kSmallN : 0;
     launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, ybase, B.Pm, nskip);
@@ -757,6 +761,9 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
     launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out, B.nmin_big);
   }
   if (phase_aware && B.any_phase1) launch_sub_tD(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, yv, out);
+  if (G && !Gs) launch_make_G(st, B.nblk, B.d_blk, B.d_flags, B.Cf, out, B.Z, G, 0);
+  else if (G && B.maxn > kSmallN)
+    launch_make_G(st, B.nblk, B.d_blk, B.d_flags, B.Cf, out, B.Z, G, B.nmax_small ? kSmallN : 0);
   B.prof.add(PSDP_PROF_BT, m0, B.prof.mark());
 }
 
@@ -1055,10 +1062,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     { const size_t pm_ = B.prof.mark();
     launch_cholinv(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.Z, B.Zi);
       B.prof.add(PSDP_PROF_CHOLINV, pm_, B.prof.mark()); }
-    op_BT(B, st, B.y, B.S1);
-    { const size_t pm_ = B.prof.mark();
-    launch_make_G(st, B.nblk, B.d_blk, B.d_flags, B.Cf, B.S1, B.Z, B.G);
-      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
+    op_BT(B, st, B.y, B.S1, true, B.G);
     op_B(B, st, B.X, B.BX, 0.0);
     { const size_t pm_ = B.prof.mark();
     launch_block_red(st, B.nblk, B.d_blk, B.d_flags, B.Cf, B.X, B.Z, B.G, B.d_red);

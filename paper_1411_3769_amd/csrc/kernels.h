@@ -17,7 +17,7 @@ void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int
                         double* C, double alpha, int aslot, const double* D, double beta,
                         int bslot, int nmin);
 void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
-                   const double* Cf, const double* S, const double* Z, double* G);
+                   const double* Cf, const double* S, const double* Z, double* G, int nskip = 0);
 void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
                   const double* A, double b, const double* B, double* out, int nskip = 0);
 void launch_symmetrize(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
@@ -41,7 +41,8 @@ void launch_form_P(hipStream_t st, int total, const SysDesc* sys, const int* fla
 void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* sys,
                     const int* flags, const double* Pm, double* out, int nskip);
 void launch_BT_small(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys, const int* flags,
-                     const double* y, double* out);
+                     const double* y, double* out, const double* Cf = nullptr, const double* Z = nullptr,
+                     double* G = nullptr);
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
                     const int* flags, const double* Pm, double* out, int nmin);
 void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,

@@ -244,9 +244,10 @@ __global__ void __launch_bounds__(256) k_gemm_blocks(const BlkDesc* __restrict__
 // G = C - S + Z (eq. G with S = B^T(y))
 __global__ void k_make_G(const BlkDesc* __restrict__ blks, const int* __restrict__ flags,
                          const double* __restrict__ Cf, const double* __restrict__ S,
-                         const double* __restrict__ Z, double* G) {
+                         const double* __restrict__ Z, double* G, int nskip) {
   const BlkDesc bd = blks[blockIdx.x];
   ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n <= nskip) return;   // k_BT_small's epilogue
   const int nn = bd.n * bd.n;
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
     const int64_t o = bd.off + e;
@@ -1578,10 +1579,13 @@ __global__ void __launch_bounds__(256) k_B_small(const SysDesc* __restrict__ sys
 // (p, q) -> basis index table: P-blocks out_j = sum_h beta_{h,j} P_h
 // (ascending h); derivative blocks Q = sum_{h : H_{h,m} != 0} P_h H_{h,m} on
 // FP64 MFMA (ascending h), out = -(Q + Q^T) through the wave's LDS tile.
+// With G given, also G = C - out + Z (eq. G) from the same registers.
 __global__ void __launch_bounds__(256) k_BT_small(int nblk, const BlkDesc* __restrict__ blks,
                                                   const SysDesc* __restrict__ sys,
                                                   const int* __restrict__ flags,
-                                                  const double* __restrict__ y, double* out) {
+                                                  const double* __restrict__ y, double* out,
+                                                  const double* __restrict__ Cf,
+                                                  const double* __restrict__ Zb, double* G) {
   __shared__ double sQ[4][256];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
   const int b = blockIdx.x * 4 + wv;
@@ -1607,7 +1611,11 @@ __global__ void __launch_bounds__(256) k_BT_small(int nblk, const BlkDesc* __res
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (lane + 64 * u < nn) O[lane + 64 * u] = acc[u];
+      if (lane + 64 * u < nn) {
+        const int64_t o = bd.off + lane + 64 * u;
+        O[lane + 64 * u] = acc[u];
+        if (G) G[o] = Cf[o] - acc[u] + Zb[o];
+      }
     return;
   }
   const int m = bd.j - L;
@@ -1644,7 +1652,14 @@ __global__ void __launch_bounds__(256) k_BT_small(int nblk, const BlkDesc* __res
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int row = 4 * i + kq;
-    if (row < n && r16 < n) O[row * n + r16] = -(acc[i] + q[r16 * 16 + row]);
+    if (row < n && r16 < n) {
+      const double v = -(acc[i] + q[r16 * 16 + row]);
+      O[row * n + r16] = v;
+      if (G) {
+        const int64_t o = bd.off + row * n + r16;
+        G[o] = Cf[o] - v + Zb[o];
+      }
+    }
   }
 }
 
@@ -1927,8 +1942,8 @@ void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int
 }
 
 void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
-                   const double* Cf, const double* S, const double* Z, double* G) {
-  hipLaunchKernelGGL(k_make_G, dim3(nblk), dim3(256), 0, st, blks, flags, Cf, S, Z, G);
+                   const double* Cf, const double* S, const double* Z, double* G, int nskip) {
+  hipLaunchKernelGGL(k_make_G, dim3(nblk), dim3(256), 0, st, blks, flags, Cf, S, Z, G, nskip);
 }
 
 void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
@@ -1982,9 +1997,10 @@ void launch_BT_pblk(hipStream_t st, int n, const BlkDesc* pblks, const SysDesc* 
 }
 
 void launch_BT_small(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys, const int* flags,
-                     const double* y, double* out) {
+                     const double* y, double* out, const double* Cf, const double* Z, double* G) {
   if (nblk)
-    hipLaunchKernelGGL(k_BT_small, dim3((nblk + 3) / 4), dim3(256), 0, st, nblk, blks, sys, flags, y, out);
+    hipLaunchKernelGGL(k_BT_small, dim3((nblk + 3) / 4), dim3(256), 0, st, nblk, blks, sys, flags, y, out,
+                       Cf, Z, G);
 }
 
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
