@@ -631,7 +631,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(B.gdg.sys) + tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
   tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
-  tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 4 + 255) / 256 * 256;
+  tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 2 * 4 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256 + 4096;
   B.dtab_bytes = tb;
   if (!(B.dtab = dev_alloc(tb))) return fail(PSDP_ENOMEM, "device allocation of tables failed");
@@ -706,7 +706,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.d_flags = (int*)(base + off); off += ((size_t)B.S * 4 + 255) / 256 * 256;
   B.d_sc = (double*)(base + off); off += ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
   B.d_red = (double*)(base + off); off += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256;
-  B.d_kout = (int*)(base + off); off += ((size_t)B.nblk * 4 + 255) / 256 * 256;
+  B.d_kout = (int*)(base + off); off += ((size_t)B.nblk * 2 * 4 + 255) / 256 * 256;   // X and Z ladders
   B.d_cert = (double*)(base + off); off += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256;
   const size_t hf_bytes = ((size_t)B.S * 4 + 255) / 256 * 256;
   B.h_pin_bytes = 2 * hf_bytes + (size_t)B.S * kNSC * 8;
@@ -1203,23 +1203,15 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     }
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
     // step lengths and update
+    // both ladders in one launch, then both step lengths with the y update
     { const size_t pm_ = B.prof.mark();
-    launch_ladder(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.X, B.dX, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
-      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TP, B.d_sc);
-      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    launch_ladder(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.Z, B.dZ, o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout);
-      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    launch_ladder_step(st, B.d_sys, S, B.d_flags, B.d_kout, o.ladder_rho, S_TD, B.d_sc);
+    launch_ladder2(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.X, B.dX, B.Z, B.dZ, o.ladder_rho,
+                   o.step_frac, o.ladder_len, B.d_kout, B.d_kout + B.nblk);
+    launch_steps_update_y(st, B.d_sys, S, B.d_flags, B.d_kout, B.d_kout + B.nblk, o.ladder_rho, B.d_sc, B.y,
+                          B.dyh, B.dyb);
       B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();
     launch_update_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, B.X, B.dX, B.Z, B.dZ);
-      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
-    { const size_t pm_ = B.prof.mark();
-    launch_update_y(st, S, B.d_sys, B.d_flags, B.d_sc, B.y, B.dyh, B.dyb);
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark()); }
     PSDP_HIP(hipGetLastError());
       return PSDP_OK;

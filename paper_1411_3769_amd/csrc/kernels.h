@@ -10,6 +10,12 @@ void launch_cholinv(hipStream_t st, int nblk, int maxn, int nmax_small, const Bl
 void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
                    const int* flags, const double* V, const double* dV, double rho, double frac,
                    int len, int* kout);
+void launch_ladder2(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
+                    const int* flags, const double* X, const double* dX, const double* Z,
+                    const double* dZ, double rho, double frac, int len, int* koutX, int* koutZ);
+void launch_steps_update_y(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* koutX,
+                           const int* koutZ, double rho, double* sc, double* y, const double* dyh,
+                           const double* dyb);
 void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,
                         double rho, int slot, double* sc);
 void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
@@ -28,8 +34,6 @@ void launch_combine(hipStream_t st, int nblk, const BlkDesc* blks, const int* fl
 void launch_update_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                           const double* sc, double* X, const double* dX, double* Z,
                           const double* dZ);
-void launch_update_y(hipStream_t st, int S, const SysDesc* sys, const int* flags,
-                     const double* sc, double* y, const double* dyh, const double* dyb);
 void launch_block_red(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                       const double* Cf, const double* X, const double* Z, const double* G,
                       double* red);

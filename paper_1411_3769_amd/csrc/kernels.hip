@@ -151,14 +151,22 @@ __global__ void __launch_bounds__(256) k_ladder(const BlkDesc* __restrict__ blks
 // The same ladder for blocks of order <= 16, sixteen lanes per block
 // (sixteen blocks per workgroup): lane r holds row r of the block (identity
 // past n) and the rungs are tried in order with the row Cholesky test (the
-// first rung passes in most iterations).
+// first rung passes in most iterations).  With nset = 2 the grid covers a
+// second, independent ladder (V2, dV2 -> kout2) over the same blocks.
 __global__ void __launch_bounds__(256) k_ladder16(const BlkDesc* __restrict__ blks, int nblk,
                                                   const int* __restrict__ flags,
-                                                  const double* __restrict__ V,
-                                                  const double* __restrict__ dV, double rho,
-                                                  double frac, int len, int* kout) {
-  const int b = blockIdx.x * 16 + (int)(threadIdx.x >> 4), r = threadIdx.x & 15;
-  if (b >= nblk) return;
+                                                  const double* __restrict__ V1,
+                                                  const double* __restrict__ dV1, double rho,
+                                                  double frac, int len, int* kout1, int nset,
+                                                  const double* __restrict__ V2,
+                                                  const double* __restrict__ dV2, int* kout2) {
+  const int vb = blockIdx.x * 16 + (int)(threadIdx.x >> 4), r = threadIdx.x & 15;
+  if (vb >= nset * nblk) return;
+  const bool second = vb >= nblk;
+  const int b = second ? vb - nblk : vb;
+  const double* V = second ? V2 : V1;
+  const double* dV = second ? dV2 : dV1;
+  int* kout = second ? kout2 : kout1;
   const BlkDesc bd = blks[b];
   if (bd.n > kSmallN) return;   // k_ladder
   if (!(flags[bd.sys] & F_ACTIVE)) {
@@ -219,6 +227,57 @@ __global__ void __launch_bounds__(256) k_ladder_step(const SysDesc* __restrict__
     r = 0.0;
   }
   sc[s * kNSC + slot] = r;
+}
+
+// Both step lengths and the y update (eq. y), one wave per system: for each
+// ladder, the step is rho^{k*} with k* the largest first passing rung over
+// the system's blocks (repeated multiplication), 0 with F_LADDERFAIL if a
+// block found none; S_TP from koutX, S_TD from koutZ; then, unless the
+// Newton system or a ladder failed, y += t_D (dy^ + dy_bar).
+__global__ void __launch_bounds__(256) k_steps_update_y(const SysDesc* __restrict__ sys, int S, int* flags,
+                                                        const int* __restrict__ koutX,
+                                                        const int* __restrict__ koutZ, double rho,
+                                                        double* sc, double* y,
+                                                        const double* __restrict__ dyh,
+                                                        const double* __restrict__ dyb) {
+  const int s = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (s >= S) return;
+  const int f0 = flags[s];
+  if (!(f0 & F_ACTIVE)) return;
+  const SysDesc& sd = sys[s];
+  const int blk0 = sd.blk0, nb = sd.nb;
+  int kx = 0, kz = 0, bx = 0, bz = 0;
+  for (int j = lane; j < nb; j += 64) {
+    const int a = koutX[blk0 + j], c = koutZ[blk0 + j];
+    bx |= a < 0;
+    bz |= c < 0;
+    kx = a > kx ? a : kx;
+    kz = c > kz ? c : kz;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int ox = __shfl_xor(kx, m), oz = __shfl_xor(kz, m);
+    kx = ox > kx ? ox : kx;
+    kz = oz > kz ? oz : kz;
+    bx |= __shfl_xor(bx, m);
+    bz |= __shfl_xor(bz, m);
+  }
+  double tp = 1.0, td = 1.0;
+  for (int k = 0; k < kx; ++k) tp = tp * rho;
+  for (int k = 0; k < kz; ++k) td = td * rho;
+  if (bx) tp = 0.0;
+  if (bz) td = 0.0;
+  if (lane == 0) {
+    if (bx || bz) flags[s] = f0 | F_LADDERFAIL;
+    sc[s * kNSC + S_TP] = tp;
+    sc[s * kNSC + S_TD] = td;
+  }
+  if ((f0 & F_LAMFAIL) || bx || bz) return;
+  for (int k = lane; k < sd.K; k += 64) {
+    const int64_t o = sd.voff + k;
+    const double d = dyh[o] + dyb[o];
+    y[o] = y[o] + td * d;
+  }
 }
 
 // C_b = a op(A_b) op(B_b) + c D_b with a = alpha * sc[aslot], c = beta * sc[bslot]
@@ -322,21 +381,6 @@ __global__ void k_update_blocks(const BlkDesc* __restrict__ blks, const int* __r
 }
 
 // y += td (dyh + dyb)
-__global__ void k_update_y(const SysDesc* __restrict__ sys, const int* __restrict__ flags,
-                           const double* __restrict__ sc, double* y,
-                           const double* __restrict__ dyh, const double* __restrict__ dyb) {
-  const int s = blockIdx.x;
-  const int f = flags[s];
-  if (!(f & F_ACTIVE) || (f & (F_LAMFAIL | F_LADDERFAIL))) return;
-  const SysDesc sd = sys[s];
-  const double td = sc[s * kNSC + S_TD];
-  for (int k = threadIdx.x; k < sd.K; k += blockDim.x) {
-    const int64_t o = sd.voff + k;
-    const double d = dyh[o] + dyb[o];
-    y[o] = y[o] + td * d;
-  }
-}
-
 // per-block partial sums: <C,X>, <Z,X>, ||G||^2, ||C||^2
 __global__ void __launch_bounds__(256) k_block_red(const BlkDesc* __restrict__ blks,
                                                    const int* __restrict__ flags,
@@ -1920,12 +1964,33 @@ void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const Blk
                    int len, int* kout) {
   if (nmax_small)
     hipLaunchKernelGGL(k_ladder16, dim3((nblk + 15) / 16), dim3(256), 0, st, blks, nblk, flags, V, dV, rho, frac,
-                       len, kout);
+                       len, kout, 1, nullptr, nullptr, nullptr);
   if (maxn > kSmallN) {
     const size_t lds = (size_t)maxn * maxn * 8;
     set_lds((const void*)k_ladder, lds);
     hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, V, dV, rho, frac, len, kout);
   }
+}
+
+void launch_ladder2(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
+                    const int* flags, const double* X, const double* dX, const double* Z,
+                    const double* dZ, double rho, double frac, int len, int* koutX, int* koutZ) {
+  if (nmax_small)
+    hipLaunchKernelGGL(k_ladder16, dim3((2 * nblk + 15) / 16), dim3(256), 0, st, blks, nblk, flags, X, dX, rho,
+                       frac, len, koutX, 2, Z, dZ, koutZ);
+  if (maxn > kSmallN) {
+    const size_t lds = (size_t)maxn * maxn * 8;
+    set_lds((const void*)k_ladder, lds);
+    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, X, dX, rho, frac, len, koutX);
+    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, Z, dZ, rho, frac, len, koutZ);
+  }
+}
+
+void launch_steps_update_y(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* koutX,
+                           const int* koutZ, double rho, double* sc, double* y, const double* dyh,
+                           const double* dyb) {
+  hipLaunchKernelGGL(k_steps_update_y, dim3((S + 3) / 4), dim3(256), 0, st, sys, S, flags, koutX, koutZ, rho,
+                     sc, y, dyh, dyb);
 }
 
 void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,
@@ -1967,11 +2032,6 @@ void launch_update_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const i
                           const double* sc, double* X, const double* dX, double* Z,
                           const double* dZ) {
   hipLaunchKernelGGL(k_update_blocks, dim3(nblk), dim3(256), 0, st, blks, flags, sc, X, dX, Z, dZ);
-}
-
-void launch_update_y(hipStream_t st, int S, const SysDesc* sys, const int* flags,
-                     const double* sc, double* y, const double* dyh, const double* dyb) {
-  hipLaunchKernelGGL(k_update_y, dim3(S), dim3(256), 0, st, sys, flags, sc, y, dyh, dyb);
 }
 
 void launch_block_red(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,

@@ -171,6 +171,24 @@ def test_batched_setup_matches_single(P, mixed, on_device):
         g.close()
 
 
+def test_batched_setup_handles_outlive_siblings(P, mixed):
+    """The handles of one batched set-up share a device block that goes with
+    the last of them: after the others are freed (and their memory reused),
+    a survivor still solves exactly like the same system set up alone."""
+    part = mixed[:5]
+    gs = P.polya_setup_batched([(sy.A, sy.n, sy.l, sy.dp, sy.d) for sy in part])
+    for k in (0, 1, 3, 4):
+        gs[k].close()
+    P.polya_setup_batched([(sy.A, sy.n, sy.l, sy.dp, sy.d) for sy in mixed[5:9]])   # reuse freed memory
+    h = P.polya_setup(part[2].A, part[2].n, part[2].l, part[2].dp, part[2].d)
+    print(f"survivor {part[2].tag}", flush=True)
+    a, b = P.ipm_solve(gs[2]), P.ipm_solve(h)
+    assert a.verdict == b.verdict and a.iterations == b.iterations
+    assert np.array_equal(a.y, b.y)
+    gs[2].close()
+    h.close()
+
+
 def test_batched_setup_rejects_nonfinite_device_vertices(P, mixed):
     import torch
     part = mixed[:3]
