@@ -77,8 +77,6 @@ void launch_pred_dir_small(hipStream_t st, int nblk, int nmax, const BlkDesc* bl
 void launch_corr_dir_small(hipStream_t st, int nblk, int nmax, const BlkDesc* blks, const int* flags,
                            const double* Zi, const double* dZb, const double* X, const double* Wc,
                            const double* dXh, const double* dZh, double* dX, double* dZ);
-void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks,
-                          const SysDesc* sys, const int* flags, const double* Pm, double* out);
 void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
                         const int* flags, const double* Zi, const double* X, double* arena,
                         const BlkDesc* blks, const int64_t* offA1);

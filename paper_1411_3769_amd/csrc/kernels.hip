@@ -1475,63 +1475,6 @@ __global__ void __launch_bounds__(256) k_corr_dir_small(
   }
 }
 
-// -sum_h (P_h H_{m,h} + (P_h H_{m,h})^T) for each d-block m; the workgroup
-// steps through the longest h list of its items, the next (P_h, H_{m,h}) pair
-// fetched into registers while the current one is multiplied
-__global__ void __launch_bounds__(256) k_BT_dblk_small(int nd, int nmax, int G,
-                                                       const BlkDesc* __restrict__ dblks,
-                                                       const SysDesc* __restrict__ sys,
-                                                       const int* __restrict__ flags,
-                                                       const double* __restrict__ Pm, double* out) {
-  __shared__ double sP[256], sH[256];
-  __shared__ int smax;
-  SmallSlot t = small_slot(nmax, G, nd);
-  BlkDesc bd{};
-  SysDesc sd{};
-  int c0 = 0, cnt = 0, m = 0;
-  if (t.ok) {
-    bd = dblks[t.item];
-    t.ok = (flags[bd.sys] & F_ACTIVE) && bd.n <= nmax;
-  }
-  if (t.ok) {
-    sd = sys[bd.sys];
-    m = bd.j - sd.L;
-    c0 = sd.h_by_m[m];
-    cnt = sd.h_by_m[m + 1] - c0;
-  }
-  if (threadIdx.x == 0) smax = 0;
-  __syncthreads();
-  if (t.ok && t.e == 0) atomicMax(&smax, cnt);
-  const int n = bd.n, nn = n * n;
-  const bool act = t.ok && t.e < nn;
-  const int i = act ? t.e / n : 0, j = act ? t.e - i * n : 0;
-  double* pp = sP + t.li * t.per;
-  double* ph = sH + t.li * t.per;
-  double vp = 0.0, vh = 0.0;
-  auto fetch = [&](int c) {
-    if (act && c < cnt) {
-      const int h = sd.h_list[c0 + c];
-      vp = Pm[sd.poff + (int64_t)h * nn + t.e];
-      vh = sd.H[((int64_t)m * sd.L0 + h) * nn + t.e];
-    }
-  };
-  fetch(0);
-  __syncthreads();
-  const int cmax = smax;
-  double acc = 0.0;
-  for (int c = 0; c < cmax; ++c) {
-    if (act && c < cnt) {
-      pp[t.e] = vp;
-      ph[t.e] = vh;
-    }
-    __syncthreads();
-    fetch(c + 1);
-    if (act && c < cnt) acc += dot_n(n, i, j, pp, 0, ph, 0) + dot_n(n, j, i, pp, 0, ph, 0);
-    __syncthreads();
-  }
-  if (act) out[bd.off + t.e] = -acc;
-}
-
 // B(W) for systems whose blocks have order <= 16, one workgroup of four
 // waves per (system, h), without per-pair products in the arena:
 // S = sum_{j<L} beta_{h,j} W_j and R = sum over the (m, h) pairs of
@@ -2229,12 +2172,6 @@ void launch_corr_dir_small(hipStream_t st, int nblk, int nmax, const BlkDesc* bl
   const int G = small_G(nmax);
   hipLaunchKernelGGL(k_corr_dir_small, dim3((nblk + G - 1) / G), dim3(256), 0, st, nblk, nmax, G, blks,
                      flags, Zi, dZb, X, Wc, dXh, dZh, dX, dZ);
-}
-
-void launch_BT_dblk_small(hipStream_t st, int nd, int nmax, const BlkDesc* dblks,
-                          const SysDesc* sys, const int* flags, const double* Pm, double* out) {
-  const int G = small_G(nmax);
-  if (nd) hipLaunchKernelGGL(k_BT_dblk_small, dim3((nd + G - 1) / G), dim3(256), 0, st, nd, nmax, G, dblks, sys, flags, Pm, out);
 }
 
 void launch_pre12_small(hipStream_t st, int np, int nmax, const HMPair* pairs, const SysDesc* sys,
