@@ -128,3 +128,32 @@ def test_warm_start_option_validation():
     assert o.warm_margin == 1e-6 and o.warm_center == 1 and o.warm_iter_cap == 0
     assert not o.warm_y and not o.warm_logx and o.label_gap == 0.0
 
+
+
+def test_result_buffers_of_a_batch():
+    """ipm_solve_batched's caller buffers: one host allocation, per system the
+    views P [L0][n][n], y [K], logx / label_logx [L+M], label_y [K], each C
+    result pointing at its own views and no two views overlapping."""
+    import types
+    P = _lib()
+    shapes = [types.SimpleNamespace(L0=10, n=10, K=550, L=35, M=56),
+              types.SimpleNamespace(L0=4, n=3, K=24, L=10, M=20),
+              types.SimpleNamespace(L0=1, n=1, K=1, L=1, M=1)]
+    sdps = shapes * 3
+    arr = (P.CResult * len(sdps))()
+    views = P._prep_batch(sdps, 0, arr)
+    spans = []
+    for s, r, (Pm, y, (lx, ly, llx), hist) in zip(sdps, arr, views):
+        assert Pm.shape == (s.L0, s.n, s.n) and y.shape == (s.K,) and ly.shape == (s.K,)
+        assert lx.shape == (s.L + s.M,) and llx.shape == (s.L + s.M,) and hist is None
+        got = (r.P, r.y, r.logx, r.label_y, r.label_logx)
+        assert got == tuple(a.ctypes.data for a in (Pm, y, lx, ly, llx))
+        assert r.history_cap == 0
+        spans += [(a.ctypes.data, a.ctypes.data + a.nbytes) for a in (Pm, y, lx, ly, llx)]
+    spans.sort()
+    assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:]))
+    # history records when asked for
+    arr2 = (P.CResult * 2)()
+    views2 = P._prep_batch(shapes[:2], 7, arr2)
+    assert all(v[3] is not None and len(v[3]) == 7 for v in views2)
+    assert arr2[0].history_cap == 7
