@@ -26,7 +26,10 @@ predictor equation; the form above is the one that gives B(X + dX^) = a.  mu is
 printed as tr(ZX)/3 without the 1/m normalisation; the normalised form is used.
 dX is symmetrised.  The line search is "standard": a geometric ladder of trial
 steps tested by block Cholesky.  The stopping rule is a scale-relative gap plus
-primal and dual residuals.
+primal and dual residuals.  Options give the paper's own forms as modes: the
+absolute gap test alone (stop_rule="absolute"; with paper_literal set-up,
+whose derivative blocks have C_j = 0, this is the paper as printed), and
+Mehrotra's adaptive sigma in place of the fixed 1/3.
 
 The iteration trajectory itself is parity unpinned (rounding at the Cholesky
 boundary of the ladder can shift an iteration); the end points are pinned by
@@ -65,8 +68,11 @@ class Options:
     shift_growth: float = 100.0
     shift_max: float = 1e-6
     ir_steps: int = 2
+    shift_force: float = 0.0      # > 0: every Schur factorisation starts shifted by this x max diag
     phase1_tol: float = 1e-6
     verdict_mode: str = "paper_then_phase1"   # or "paper_only", "phase1_only"
+    stop_rule: str = "relative"   # or "absolute": the paper's |a^T y - tr(CX)| <= gap_tol alone
+    sigma_rule: str = "fixed"     # or "mehrotra": sigma = (mu_aff / mu)^3 from the predictor step
 
 
 # ---------------------------------------------------------------------------
@@ -232,14 +238,20 @@ class RunResult:
 
 
 def _factor_with_shift(Lam: np.ndarray, opt: Options):
-    """Cholesky of the Schur matrix; on failure retry with a diagonal shift
-    tau = 1e-14 max diag, growing x100 up to shift_max * max diag."""
-    try:
-        return np.linalg.cholesky(Lam), 0.0
-    except np.linalg.LinAlgError:
-        pass
+    """Cholesky of the Schur matrix (Alg. 2, root step 1).  The paper assumes
+    it succeeds; near the optimum the matrix is so ill-conditioned that a
+    pivot can turn non-positive by rounding.  Then the factorisation is
+    retried with a diagonal shift tau = shift_first * max diag, growing
+    x shift_growth while tau <= shift_max * max diag; the first success is
+    kept.  With shift_force > 0 the unshifted attempt is skipped and the
+    first shift is shift_force * max diag.  Returns (R, tau) or (None, None)."""
+    if opt.shift_force <= 0.0:
+        try:
+            return np.linalg.cholesky(Lam), 0.0
+        except np.linalg.LinAlgError:
+            pass
     dmax = float(np.max(np.diag(Lam)))
-    tau = opt.shift_first * dmax
+    tau = (opt.shift_force if opt.shift_force > 0.0 else opt.shift_first) * dmax
     while tau <= opt.shift_max * dmax * (1 + 1e-12):
         try:
             return np.linalg.cholesky(Lam + tau * np.eye(Lam.shape[0])), tau
@@ -249,6 +261,8 @@ def _factor_with_shift(Lam: np.ndarray, opt: Options):
 
 
 def _solve(R: np.ndarray, tau: float, Lam: np.ndarray, rhs: np.ndarray, opt: Options) -> np.ndarray:
+    """Newton solve with the factor R of Lam + tau I; when tau > 0, ir_steps
+    corrections x += (R R^T)^{-1} (rhs - Lam x) against the unshifted Lam."""
     from scipy.linalg import solve_triangular
     def s(b):
         z = solve_triangular(R, b, lower=True)
@@ -279,8 +293,15 @@ def ipm_run(ops, opt: Options, phase1: bool = False,
     reason = MAXITER
     shifts = 0
     it = 0
+    phi = psi = gap_abs = gap_rel = pinf = dinf = float("nan")
     while True:
-        Zi = block_inverse(Z)
+        try:
+            Zi = block_inverse(Z)
+        except np.linalg.LinAlgError:
+            # a block of Z lost definiteness by rounding: the run ends as
+            # non-finite (its last scalars stay those of the previous pass)
+            reason = NONFINITE
+            break
         G = C - ops.BT(y) + Z
         BX = ops.B(X)
         phi = float(np.sum(np.einsum("jab,jba->j", C, X)))
@@ -298,10 +319,17 @@ def ipm_run(ops, opt: Options, phase1: bool = False,
         if not all(np.isfinite([phi, psi, pinf, dinf, trZX])):
             reason = NONFINITE
             break
-        gap_ok = gap_rel <= opt.gap_tol or (phase1 and gap_abs <= 1e-2 * opt.gap_tol)
-        if gap_ok and pinf <= opt.feas_tol and dinf <= opt.feas_tol:
-            reason = CONVERGED
-            break
+        if opt.stop_rule == "absolute" and not phase1:
+            # the paper's stopping test (Section IV-A): the absolute duality
+            # gap alone, with no feasibility test
+            if gap_abs <= opt.gap_tol:
+                reason = CONVERGED
+                break
+        else:
+            gap_ok = gap_rel <= opt.gap_tol or (phase1 and gap_abs <= 1e-2 * opt.gap_tol)
+            if gap_ok and pinf <= opt.feas_tol and dinf <= opt.feas_tol:
+                reason = CONVERGED
+                break
         if not phase1:
             if phi > 0 and np.linalg.norm(BX) / phi <= opt.farkas_tol:
                 reason = FARKAS
@@ -327,7 +355,17 @@ def ipm_run(ops, opt: Options, phase1: bool = False,
         dyh = _solve(R, tau, Lam, ops.B(ZiGX) - a, opt)
         dZh = -G + ops.BT(dyh)
         dXh = -X - np.einsum("jab,jbc,jcd->jad", Zi, dZh, X)
-        mu = opt.sigma * trZX / m
+        sigma = opt.sigma
+        if opt.sigma_rule == "mehrotra":
+            # Mehrotra's heuristic: the predictor step's own step lengths give
+            # mu_aff = tr((Z + td dZ^)(X + tp dX^)) / m and sigma = (mu_aff / mu)^3
+            # (clipped to [0, 1]); if either ladder fails the fixed sigma stays
+            tpa = ladder(X, 0.5 * (dXh + np.transpose(dXh, (0, 2, 1))), opt)
+            tda = ladder(Z, dZh, opt)
+            if tpa is not None and tda is not None:
+                mu_aff = float(np.sum(np.einsum("jab,jba->j", Z + tda * dZh, X + tpa * dXh))) / m
+                sigma = min(1.0, max(0.0, (mu_aff / (trZX / m)) ** 3))
+        mu = sigma * trZX / m
         Wc = mu * Zi - np.einsum("jab,jbc,jcd->jad", Zi, dZh, dXh)
         dyb = _solve(R, tau, Lam, ops.B(Wc), opt)
         dZb = ops.BT(dyb)
@@ -379,6 +417,7 @@ class SolveResult:
     margin_D: float
     iterations: int
     reason: int
+    chol_shifts: int = 0          # iterations whose Schur factorisation needed a shift
     phase1_used: bool = False
     phase1_iterations: int = 0
     phase1_reason: int = -1
@@ -433,7 +472,7 @@ def ipm_solve(sdp: PolyaSDP, opt: Optional[Options] = None, warm=None,
             ok, mg, mP, mD = certificate(sdp, r.y)
             if ok:
                 res = SolveResult(FEASIBLE, sdp.P_of_y(r.y), r.y, r.phi, r.psi, r.gap_abs, r.gap_rel,
-                                  r.pinf, r.dinf, mg, mP, mD, r.iterations, r.reason)
+                                  r.pinf, r.dinf, mg, mP, mD, r.iterations, r.reason, r.shifts)
                 res.warm_used, res.warm_iterations = True, r.iterations
                 return res
         elif r.reason == FARKAS:
@@ -463,14 +502,14 @@ def _solve_cold(sdp: PolyaSDP, opt: Options) -> SolveResult:
             ok, mg, mP, mD = certificate(sdp, r.y)
             verdict = FEASIBLE if ok else UNKNOWN
             return SolveResult(verdict, sdp.P_of_y(r.y), r.y, r.phi, r.psi, r.gap_abs, r.gap_rel,
-                               r.pinf, r.dinf, mg, mP, mD, r.iterations, r.reason)
+                               r.pinf, r.dinf, mg, mP, mD, r.iterations, r.reason, r.shifts)
         if r.reason == FARKAS or opt.verdict_mode == "paper_only":
             v = INFEASIBLE if r.reason == FARKAS else UNKNOWN
             return SolveResult(v, zeroP, r.y, r.phi, r.psi, r.gap_abs, r.gap_rel, r.pinf, r.dinf,
-                               nanv, nanv, nanv, r.iterations, r.reason)
-        its, reason0 = r.iterations, r.reason
+                               nanv, nanv, nanv, r.iterations, r.reason, r.shifts)
+        its, reason0, shifts0 = r.iterations, r.reason, r.shifts
     else:
-        its, reason0 = 0, -1
+        its, reason0, shifts0 = 0, -1, 0
     p1 = Phase1Ops(sdp)
     r1 = ipm_run(p1, opt, phase1=True)
     t = float(r1.y[-1])
@@ -491,6 +530,7 @@ def _solve_cold(sdp: PolyaSDP, opt: Options) -> SolveResult:
     else:
         res = SolveResult(UNKNOWN, zeroP, p1.full_y(r1.y), nanv, nanv, nanv, nanv, r1.pinf, r1.dinf,
                           nanv, nanv, nanv, its, reason0)
+    res.chol_shifts = shifts0 + r1.shifts
     res.phase1_used = True
     res.phase1_iterations = r1.iterations
     res.phase1_reason = r1.reason

@@ -1,11 +1,16 @@
 """Writes the oracle's end points for the seeded parity workloads.
 
-    python tests/golden/make_oracle_results.py
+    python tests/golden/make_oracle_results.py            # small cases
+    python tests/golden/make_oracle_results.py --large    # full-size cases
 
 Calls only oracle/ (and the seeded input generators).  Output:
-tests/golden/oracle_results.json with, per case, the verdict, objectives,
-duality gap, the certificate margins and the phase-I optimum, which the GPU
-parity tests compare against.
+tests/golden/oracle_results.json (small cases) or
+tests/golden/oracle_results_large.json (the n=100 system, held-out members of
+the n=32 warm-start family and the largest members of the mixed batch, each
+solved in the oracle's expanded Schur mode), with, per case, the verdict,
+objectives, duality gap, the certificate margins and the phase-I optimum,
+which the GPU parity tests compare against.  The large file is rewritten
+after every case, so an interrupted run keeps what it finished.
 """
 import json
 import os
@@ -39,7 +44,36 @@ def run(sy):
                 t_star=r.t_star, seconds=time.time() - t)
 
 
+LARGE_MIXED = (200, 36)   # K = 17640 (the batch's largest) and K = 2583
+
+
+def main_large():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_results_large.json")
+    out = []
+    if os.path.exists(path):
+        with open(path) as fh:
+            out = json.load(fh)
+    have = {(r["tag"], r["seed"]) for r in out}
+    mixed = W.mixed_systems(512)
+    cases = [W.c2_system(0)] + [W.warm_system(10**6 + s) for s in range(8)]
+    cases += [mixed[i] for i in LARGE_MIXED]
+    for sy in cases:
+        if (sy.tag, sy.seed) in have:
+            continue
+        rec = run(sy)
+        if rec["tag"].startswith("mixed"):
+            rec["index"] = int(rec["tag"][5:])
+        out.append(rec)
+        print(rec["tag"], rec["seed"], rec["verdict"], rec["iterations"], f"{rec['seconds']:.2f}s",
+              flush=True)
+        with open(path + ".tmp", "w") as fh:
+            json.dump(out, fh, indent=1)
+        os.replace(path + ".tmp", path)
+
+
 def main():
+    if "--large" in sys.argv[1:]:
+        return main_large()
     cases = []
     for s in range(16):
         cases.append(W.plain_system(s))
