@@ -6,12 +6,21 @@ set-up of every system (vertices already resident in HBM), the batched
 predictor-corrector interior-point solve to relative gap 1e-8 (Schur
 complement assembly, its FP64 Cholesky and solves, the step-length ladder,
 updates; phase-I for undecided systems) and the FP64 block-Cholesky
-certificate check.  The default workload is 64 seeded uncertain systems with
-n=10 states, l=4 vertices, dp=2, d=2 (K=550 unknowns, 35 + 56 blocks each).
+certificate check.
+
+The default workload is the single large system n=100, l=4, dp=1, d=3
+(K = 20200 unknowns, a 20200 x 20200 Schur complement): `value` is its FP64
+time-to-certificate; the same line carries the precision forms (Schur
+assembly in FP32 and in BF16 on MFMA, FP64 Cholesky, refinement against the
+FP64 matrix-free product), each with its error against the stored FP64
+oracle end point, the roofline of the dominant kernel group (the Schur
+Cholesky) and the oracle's own time on the host.  Other workloads: n10 (64
+systems n=10, l=4, dp=d=2, K=550), mixed512 (the uneven batch of 512),
+learned (warm start on the n=32 family).
 
 Prints one JSON line; see the design notes for the roofline definitions.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload n10|n100]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload n100|n10|mixed512|learned]
 """
 from __future__ import annotations
 
@@ -75,39 +84,96 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(systems, budget_s=15.0):
-    """The oracle, untuned, on the host: full solves of the first seeds of the
-    workload until about budget_s of CPU time, extrapolated to the batch."""
+def host_threads():
+    """Host threads the oracle may use: this process's CPU affinity set, capped
+    by OMP_NUM_THREADS when it is set (a host shared with other jobs sets it to
+    its share)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
+def _limits(threads):
     try:
         from threadpoolctl import threadpool_limits
+        return threadpool_limits(threads)
     except Exception:       # pragma: no cover
-        threadpool_limits = None
+        import contextlib
+        return contextlib.nullcontext()
+
+
+def cpu_baseline_solves(systems, budget_s, threads):
+    """The oracle, untuned, on the host: full solves of the first seeds of the
+    workload until about budget_s of wall time, extrapolated to the batch."""
     from oracle import ipm, sdp as S
-    ctx = threadpool_limits(1) if threadpool_limits else None
     t0 = time.perf_counter()
     done = 0
-    try:
+    with _limits(threads):
         for sy in systems:
             ipm.ipm_solve(S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d))
             done += 1
             if time.perf_counter() - t0 > budget_s:
                 break
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
     el = time.perf_counter() - t0
-    return dict(value=el / done * len(systems), unit="s", cores=1, kind="oracle",
+    return dict(value=el / done * len(systems), unit="s", cores=threads, kind="oracle",
                 sample=f"{done} of {len(systems)} systems solved by the FP64 oracle "
-                       f"({el:.1f} s, one thread), scaled by {len(systems)}/{done}")
+                       f"({el:.1f} s, {threads} thread{'s' if threads > 1 else ''}), "
+                       f"scaled by {len(systems)}/{done}")
+
+
+def cpu_baseline_iteration(sy, iterations, threads):
+    """The oracle on the large system: its set-up plus one interior-point
+    iteration (expanded-mode Schur complement, LAPACK Cholesky, both solves,
+    directions, ladders, residuals) timed on `threads` host threads, the
+    iteration scaled by the GPU solve's iteration count."""
+    from oracle import ipm, sdp as S
+    with _limits(threads):
+        t0 = time.perf_counter()
+        sdp = S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d)
+        t1 = time.perf_counter()
+        ipm.ipm_run(ipm.PaperOps(sdp), ipm.Options(), max_iter=1)
+        t2 = time.perf_counter()
+    return dict(value=(t1 - t0) + (t2 - t1) * iterations, unit="s", cores=threads, kind="oracle",
+                sample=f"the FP64 oracle's set-up ({t1 - t0:.1f} s) and one IPM iteration "
+                       f"({t2 - t1:.1f} s) of the K=20200 system on {threads} host threads, the "
+                       f"iteration scaled by the GPU run's {iterations} iterations")
+
+
+def oracle_end_point(sy):
+    """Stored FP64 oracle end point of a large system (written by
+    tests/golden/make_oracle_results.py --large), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_results_large.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for rec in json.load(fh):
+            if rec["tag"] == sy.tag and rec["seed"] == sy.seed:
+                return rec
+    return None
+
+
+def error_vs_oracle(r, rec):
+    if rec is None:
+        return None
+    rel = lambda a, b: abs(a - b) / abs(b) if b else None
+    return {"verdict_equal": r.verdict_name == rec["verdict"],
+            "psi_rel": rel(r.psi, rec["psi"]), "phi_rel": rel(r.phi, rec["phi"]),
+            "margin_rel": rel(r.margin, rec["margin"]),
+            "iterations": r.iterations, "oracle_iterations": rec["iterations"]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="n10", help="n10 | n100 | mixed512 | learned")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n100", help="n100 | n10 | mixed512 | learned")
     ap.add_argument("--precision", default=None, help="fp64 | fp32 | bf16 (Schur assembly)")
+    ap.add_argument("--form-steps", type=int, default=3,
+                    help="n100: timed steps of each precision form (at most --steps)")
+    ap.add_argument("--no-forms", action="store_true", help="n100: skip the precision forms")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -128,6 +194,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     P.load()
+    log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.calibrate_copy:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
@@ -137,6 +204,7 @@ def main():
         del src, dst
     if args.workload == "learned":
         return bench_learned(args)
+    big = args.workload == "n100"
     prec = args.precision or ("fp32" if args.workload == "mixed512" else "fp64")
     systems, desc = workload(args.workload)
     # inputs resident in HBM before the timed region
@@ -146,11 +214,11 @@ def main():
 
     tsplit = [0.0, 0.0]
 
-    def step(prof=None):
+    def step(precision, prof=None):
         t0 = time.perf_counter()
         hs = P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)])
         t1 = time.perf_counter()
-        rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=prec,
+        rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=precision,
                                  use_graph=0 if args.no_graph else 1)
         t2 = time.perf_counter()
         for h in hs:
@@ -159,31 +227,55 @@ def main():
         tsplit[1] += t2 - t1
         return rs
 
-    for _ in range(args.warmup):
-        step()
-    tsplit[0] = tsplit[1] = 0.0
-    quiet_gc()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for _ in range(args.steps):
-        results.append(step())
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms = el / args.steps * 1e3
-    rs = results[-1]
-    split = (1e3 * tsplit[0] / args.steps, 1e3 * tsplit[1] / args.steps)
+    def timed(precision, steps, warmup):
+        for _ in range(warmup):
+            step(precision)
+        tsplit[0] = tsplit[1] = 0.0
+        quiet_gc()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = []
+        for _ in range(steps):
+            results.append(step(precision))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return el / steps, results[-1], (tsplit[0] / steps, tsplit[1] / steps)
+
+    log(f"{desc}: {prec}, {args.warmup} warm-up + {args.steps} timed steps")
+    sec, rs, split = timed(prec, args.steps, args.warmup)
+    ms = sec * 1e3
+    log(f"  {ms:.1f} ms per step")
+
+    # the precision forms of the large system, fewer steps each
+    forms = {}
+    if big and not args.no_forms:
+        rec = oracle_end_point(systems[0])
+        forms["fp64"] = {"s": sec, "steps": args.steps, "iterations": rs[0].iterations,
+                         "verdict": rs[0].verdict_name, "error_vs_oracle": error_vs_oracle(rs[0], rec)}
+        for fp in ("fp32", "bf16"):
+            k = max(1, min(args.form_steps, args.steps))
+            log(f"  form {fp}: 1 warm-up + {k} timed steps")
+            fs, frs, _ = timed(fp, k, 1)
+            r = frs[0]
+            forms[fp] = {"s": fs, "steps": k, "iterations": r.iterations,
+                         "lowprec_iterations": r.iters_lowprec, "refinement_steps": r.ir_steps,
+                         "ir_eta_max": r.ir_eta_max if r.ir_eta_max == r.ir_eta_max else None,
+                         "verdict": r.verdict_name, "vs_fp64": fs / sec,
+                         "error_vs_oracle": error_vs_oracle(r, rec)}
+            log(f"    {fs * 1e3:.1f} ms, {r.iters_lowprec} of {r.iterations} iterations in {fp}")
+
     # Per-class device times: HIP events on the solver stream around each
-    # launch class, in a profiled pass of the same steps right after the
-    # timed region (events recorded inside hipGraphs carry no timestamps, so
-    # this pass launches eagerly; kernel durations are unchanged).
+    # launch class, in a profiled pass of the same steps run after the timed
+    # region (events recorded inside hipGraphs carry no timestamps, so this
+    # pass launches eagerly; kernel durations are unchanged).
+    psteps = 1 if big else args.steps
     prof = P.new_prof()
     torch.cuda.synchronize()
     tp = time.perf_counter()
-    for _ in range(args.steps):
-        step(prof)
+    for _ in range(psteps):
+        step(prec, prof)
     torch.cuda.synchronize()
-    prof_ms = (time.perf_counter() - tp) / args.steps * 1e3
+    prof_ms = (time.perf_counter() - tp) / psteps * 1e3
     verdicts = {}
     for r in rs:
         verdicts[r.verdict_name] = verdicts.get(r.verdict_name, 0) + 1
@@ -201,11 +293,16 @@ def main():
     from math import comb
     Ks = [comb(sy.l + sy.dp - 1, sy.l - 1) * sy.n * (sy.n + 1) // 2 for sy in systems]
     chol_flops = sum(it * k ** 3 / 3.0 for it, k in zip(its_all, Ks))
-    asm_ms = per["assemble"][0] / args.steps
-    chol_ms = (per["chol_panel"][0] + per["chol_update"][0]) / args.steps
+    # both triangular sweeps read the factor's lower triangle once: 8 K^2 / 2
+    # bytes each, two solves per iteration
+    solve_bytes = sum(it * 2 * 2 * 8.0 * k * k / 2 for it, k in zip(its_all, Ks))
+    asm_ms = per["assemble"][0] / psteps
+    chol_ms = (per["chol_panel"][0] + per["chol_update"][0]) / psteps
+    trsv_ms = per["trsv"][0] / psteps
     asm_tf = asm_flops / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else None
     chol_tf = chol_flops / (chol_ms * 1e-3) / 1e12 if chol_ms > 0 else None
-    launches = grp[dom][1] / args.steps
+    trsv_gbs = solve_bytes / (trsv_ms * 1e-3) / 1e9 if trsv_ms > 0 else None
+    launches = grp[dom][1] / psteps
     avg_ms = grp[dom][0] / max(grp[dom][1], 1)
     if dom == "assemble":
         per_launch = asm_flops / max(launches, 1)
@@ -242,16 +339,30 @@ def main():
         "data": "synthetic (seeded dissipative systems, see workloads.py)",
         "config": {"workload": desc, "systems": len(systems), "gap_tol": 1e-8,
                    "precision": prec,
-                   "setup_ms_per_step": split[0], "solve_ms_per_step": split[1],
-                   "hip_graphs": not args.no_graph, "profiled_pass_ms_per_step": prof_ms,
+                   "setup_ms_per_step": split[0] * 1e3, "solve_ms_per_step": split[1] * 1e3,
+                   "hip_graph_launches_per_step": rs[0].graph_replays,
+                   "profiled_pass_ms_per_step": prof_ms,
                    "verdicts": verdicts, "iterations_mean": float(np.mean(iters_sys)),
                    "lowprec_iterations_mean": float(np.mean([r.iters_lowprec for r in rs])),
                    "schur_assembly_tflops": asm_tf, "schur_cholesky_tflops": chol_tf,
-                   "device_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in per.items()}},
+                   "triangular_solves_GBps": trsv_gbs,
+                   "device_ms_per_step": {k: round(v[0] / psteps, 3) for k, v in per.items()}},
         "roofline": roof,
     }
-    if not args.no_cpu and args.workload == "n10":
-        line["cpu_baseline"] = cpu_baseline(systems)
+    if forms:
+        line["config"]["forms"] = forms
+    if not args.no_cpu:
+        th = host_threads()
+        if big:
+            log(f"  oracle: one iteration of the large system on {th} host threads")
+            cb = cpu_baseline_iteration(systems[0], its_all[0], th)
+            from paper_1411_3769_amd import workloads as W
+            log("  oracle: n10 seeds on one thread")
+            cb["n10_one_thread"] = cpu_baseline_solves([W.c1_system(s) for s in range(64)], 10.0, 1)
+        else:
+            cb = cpu_baseline_solves(systems, 15.0, th)
+            cb["one_thread"] = cpu_baseline_solves(systems, 10.0, 1)
+        line["cpu_baseline"] = cb
     print(json.dumps(line))
 
 

@@ -73,6 +73,21 @@ extern "C" {
 #define PSDP_PREC_FP32 1
 #define PSDP_PREC_BF16 2
 
+/* stopping tests of the paper's SDP run (psdp_opts.stop_rule).
+ * RELATIVE: |psi - phi| / max(|psi|, |phi|) <= gap_tol and relative primal and
+ * dual residuals <= feas_tol.  ABSOLUTE: the printed test of Section IV-A,
+ * |a^T y - tr(C X)| <= gap_tol alone, with no feasibility test. */
+#define PSDP_STOP_RELATIVE 0
+#define PSDP_STOP_ABSOLUTE 1
+
+/* centring parameter of the corrector (psdp_opts.sigma_rule).
+ * FIXED: mu = sigma tr(ZX) / m.  MEHROTRA: sigma = (mu_aff / mu)^3 clipped to
+ * [0, 1], where mu_aff = tr((Z + t_d dZ^)(X + t_p dX^)) / m uses the step
+ * lengths the ladder gives the predictor directions (the fixed sigma stays
+ * when either ladder finds no step). */
+#define PSDP_SIGMA_FIXED    0
+#define PSDP_SIGMA_MEHROTRA 1
+
 typedef struct psdp_sdp psdp_sdp;  /* opaque handle: one structured SDP */
 
 typedef struct {
@@ -164,6 +179,19 @@ typedef struct {
                           /* iterate of the paper's SDP run at the first iteration    */
                           /* whose relative gap is <= label_gap (training labels of   */
                           /* the learned warm start)                                  */
+    /* Failure of the FP64 Schur factorisation (Alg. 2, root step 1, assumes
+     * it succeeds; near the optimum a pivot can turn non-positive by
+     * rounding).  The step is then retried on Lambda + tau I with
+     * tau = f max_i Lambda_ii, f = 1e-14 first and x100 per further failure
+     * while f <= chol_shift_max, and both Newton solves of that step are
+     * refined against the unshifted FP64 product B(Z^-1 B^T(v) X) (up to six
+     * corrections; ir_max when larger).  A retried step is not counted as an
+     * iteration.  Past chol_shift_max the run ends with PSDP_R_CHOL. */
+    double chol_shift_max;   /* largest f (1e-6); 0 = no shift, a failure ends the run */
+    double chol_shift_force; /* > 0: every factorisation starts at f = this value      */
+                             /* (then x100 on failure), 0 (default) = unshifted first  */
+    int    stop_rule;        /* PSDP_STOP_* (RELATIVE)                                  */
+    int    sigma_rule;       /* PSDP_SIGMA_* (FIXED)                                    */
 } psdp_opts;
 
 typedef struct {
@@ -206,6 +234,12 @@ typedef struct {
     psdp_iter_rec* history; /* caller buffer of history_cap records, or NULL         */
     int     history_cap;
     int     history_len;
+    int     chol_shifts;    /* Newton steps (both runs) whose Schur factorisation    */
+                            /* needed a diagonal shift                               */
+    int     graph_replays;  /* hipGraph launches of the call: each iteration replays  */
+                            /* two or three captured graphs (0: every kernel launched */
+                            /* eagerly; the same count in every result of a batch)    */
+    int     phase1_reason;  /* exit reason (PSDP_R_*) of the phase-I run, -1 if none  */
 } psdp_result;
 
 /* Defaults for the option structs. */

@@ -232,13 +232,19 @@ def schur_dense(sdp: PolyaSDP, X: np.ndarray, Zi: np.ndarray) -> np.ndarray:
 
 def schur_definition(sdp: PolyaSDP, X: np.ndarray, Zi: np.ndarray) -> np.ndarray:
     """Column l of Omega is B(Z^{-1} B^T(e_l) X) (Section IV-A)."""
-    out = np.empty((sdp.K, sdp.K))
+    return schur_definition_columns(sdp, X, Zi, range(sdp.K))
+
+
+def schur_definition_columns(sdp: PolyaSDP, X: np.ndarray, Zi: np.ndarray, cols) -> np.ndarray:
+    """The columns cols of Omega by the definition, [K][len(cols)]."""
+    cols = list(cols)
+    out = np.empty((sdp.K, len(cols)))
     e = np.zeros(sdp.K)
-    for l in range(sdp.K):
+    for i, l in enumerate(cols):
         e[:] = 0.0
         e[l] = 1.0
         W = np.einsum("jab,jbc,jcd->jad", Zi, sdp.BT(e), X)
-        out[:, l] = sdp.B(W)
+        out[:, i] = sdp.B(W)
     return out
 
 

@@ -658,33 +658,152 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
   for (int k = threadIdx.x; k < sd.Kpad; k += kSvT) x[sd.voff + k] = sr[k];
 }
 
-// Larger systems solve by groups of kSG panels.  Forward, group q: the
-// diagonal block's sweep (k_trsv_gdiag, one workgroup per system, in place
-// on r) and then one launch for every row tile below it,
-// r_i -= L_{i,group} z_group (k_trsv_gfwd).  Backward, groups in reverse:
-// the diagonal block's transposed sweep (writes x) and then every column
-// tile left of it, z_c -= L_{group,c}^T x_group (k_trsv_gbwd).  Two launches
-// per group and direction instead of one per tile; the rectangular
-// updates read L at full width.
-__global__ void __launch_bounds__(kSvT) k_trsv_gdiag(const SysDesc* __restrict__ sys,
+// Larger systems solve by groups of kSG panels (kGS rows).  After the
+// factorisation, k_trsv_ginv forms the inverse of each group's diagonal block
+// of the factor, G_q = L_qq^{-1}, and its transpose.  Forward, group q:
+// z_q = G_q r_q (k_trsv_gapply, many workgroups), then r_i -= L_{i,q} z_q for
+// every row tile below the group (k_trsv_gfwd).  Backward, groups in reverse:
+// x_q = G_q^T z_q, then z_c -= L_{q,c}^T x_q for every column tile left of it
+// (k_trsv_gbwd).  Every launch reads its part of L at full width; the only
+// serial chain is the one between groups.
+//
+// G_q by block forward substitution over its 64 x 64 tiles, with the stored
+// inverses X_ii = L_ii^{-1} of the diagonal tiles:
+//   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj   (i > j),
+// one workgroup per (group, tile column j), rows i in order; each product is
+// a 64 x 64 x 64 FP64 MFMA product of LDS-staged tiles (wave w owns the 16
+// rows 16 w .. 16 w + 15 of the result).  Tiles above the diagonal are
+// written as zeros.
+__global__ void __launch_bounds__(256) k_trsv_ginv(const SysDesc* __restrict__ sys,
+                                                   const int* __restrict__ flags,
+                                                   const int* __restrict__ st_sys,
+                                                   const int* __restrict__ st_pre, int cnt,
+                                                   const double* __restrict__ Lam,
+                                                   const double* __restrict__ Linv, double* Ginv) {
+  __shared__ double sL[kNB * kLD];
+  __shared__ double sX[kNB * kLD];
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int q = t / kSG, j = t % kSG;
+  const int p0 = kSG * q, nseg = min(sd.P, p0 + kSG) - p0;
+  if (j >= nseg) return;
+  const int64_t ld = sd.Kpad;
+  const double* A = Lam + sd.loff;
+  const double* Li = Linv + sd.dgoff;
+  double* G = Ginv + sd.gioff + (int64_t)q * 2 * kGS * kGS;
+  double* GT = G + (int64_t)kGS * kGS;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  // tiles (i, j), i < j, of G and their transposes are zero
+  for (int i = 0; i < j; ++i)
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int rr = e >> 6, cc = e & 63;
+      G[(int64_t)(i * kNB + rr) * kGS + j * kNB + cc] = 0.0;
+      GT[(int64_t)(j * kNB + rr) * kGS + i * kNB + cc] = 0.0;
+    }
+  // a 64 x 64 tile into LDS; lower = true keeps only its lower triangle
+  auto stage = [&](double* dst, const double* src, int64_t lds, bool lower) {
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int rr = e >> 6, cc = e & 63;
+      const double v = src[(int64_t)rr * lds + cc];
+      dst[rr * kLD + cc] = (!lower || cc <= rr) ? v : 0.0;
+    }
+  };
+  // X_jj
+  stage(sX, Li + (int64_t)(p0 + j) * kNB * kNB, kNB, true);
+  __syncthreads();
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int rr = e >> 6, cc = e & 63;
+    const double v = sX[rr * kLD + cc];
+    G[(int64_t)(j * kNB + rr) * kGS + j * kNB + cc] = v;
+    GT[(int64_t)(j * kNB + cc) * kGS + j * kNB + rr] = v;
+  }
+  for (int i = j + 1; i < nseg; ++i) {
+    v4d acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k = j; k < i; ++k) {
+      __syncthreads();   // the previous product has read sL and sX
+      stage(sL, A + (int64_t)(p0 + i) * kNB * ld + (int64_t)(p0 + k) * kNB, ld, false);
+      stage(sX, G + (int64_t)(k * kNB) * kGS + j * kNB, kGS, false);
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+          acc[b] = mm16(sL + (16 * w) * kLD + 16 * kb, sX + (16 * kb) * kLD + 16 * b, false, acc[b]);
+    }
+    __syncthreads();
+    // sX = the sum, sL = X_ii; then X_ij = -X_ii sum
+#pragma unroll
+    for (int b = 0; b < 4; ++b) st16(sX + (16 * w) * kLD + 16 * b, acc[b], 1.0, false);
+    stage(sL, Li + (int64_t)(p0 + i) * kNB * kNB, kNB, true);
+    __syncthreads();
+    v4d out[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      out[b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+        out[b] = mm16(sL + (16 * w) * kLD + 16 * kb, sX + (16 * kb) * kLD + 16 * b, false, out[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = 16 * w + 4 * e + kq, cc = 16 * b + r16;
+        const double v = -out[b][e];
+        G[(int64_t)(i * kNB + rr) * kGS + j * kNB + cc] = v;
+        GT[(int64_t)(j * kNB + cc) * kGS + i * kNB + rr] = v;
+      }
+    // the tile just written is read back (as X_kj) by the next rows' products
+    __threadfence_block();
+  }
+}
+
+// vout_q = M vin_q for group q, M = G_q (lower triangular; backward = 0) or
+// G_q^T (upper triangular; backward = 1), rows of the group 16 per
+// workgroup: wave w takes 4 rows, the lanes stride over the row's columns
+// inside the triangle, and a wave reduction gives each entry.
+__global__ void __launch_bounds__(256) k_trsv_gapply(const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags,
                                                      const int* __restrict__ st_sys,
-                                                     const double* __restrict__ Lam,
-                                                     const double* __restrict__ Linv,
-                                                     const double* vin, double* vout, int q,
+                                                     const int* __restrict__ st_pre, int cnt,
+                                                     const double* __restrict__ Ginv,
+                                                     const double* __restrict__ vin, double* vout, int q,
                                                      int backward) {
-  __shared__ double sr[kNB * kSG];
-  __shared__ double sred[kSvG * kNB];
-  __shared__ double sv[kNB];
-  const int s = st_sys[blockIdx.x];
+  __shared__ double sv[kGS];
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
-  const int p0 = kSG * q, p1 = min(sd.P, kSG * (q + 1)) - 1;
-  const int base = p0 * kNB, nv = (p1 - p0 + 1) * kNB;
-  for (int k = threadIdx.x; k < nv; k += kSvT) sr[k] = vin[sd.voff + base + k];
-  if (backward) solve_range<false, true>(Lam + sd.loff, sd.Kpad, Linv + sd.dgoff, p0, p1, sr, sred, sv);
-  else solve_range<true, false>(Lam + sd.loff, sd.Kpad, Linv + sd.dgoff, p0, p1, sr, sred, sv);
-  for (int k = threadIdx.x; k < nv; k += kSvT) vout[sd.voff + base + k] = sr[k];
+  const int p0 = kSG * q, nv = (min(sd.P, p0 + kSG) - p0) * kNB;
+  const int base = p0 * kNB;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int k = tid; k < nv; k += 256) sv[k] = vin[sd.voff + base + k];
+  __syncthreads();
+  const double* M = Ginv + sd.gioff + (int64_t)q * 2 * kGS * kGS + (backward ? (int64_t)kGS * kGS : 0);
+  const int r0 = 16 * t + 4 * w;
+  double acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int r = r0 + m;
+    const int c0 = backward ? (r & ~63) : 0, c1 = backward ? nv : (r | 63) + 1;
+    const double* row = M + (int64_t)r * kGS;
+    double a = 0.0;
+    for (int c = c0 + lane; c < c1; c += 64) a += row[c] * sv[c];
+    acc[m] = a;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double v = acc[m];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) vout[sd.voff + base + r0 + m] = v;
+  }
 }
 
 // r_i -= sum_{c in group q} L[i][c] z[c] for the 64 rows of row tile
@@ -694,7 +813,8 @@ __global__ void __launch_bounds__(256) k_trsv_gfwd(const SysDesc* __restrict__ s
                                                    const int* __restrict__ flags,
                                                    const int* __restrict__ st_sys,
                                                    const int* __restrict__ st_pre, int cnt,
-                                                   const double* __restrict__ Lam, double* r, int q) {
+                                                   const double* __restrict__ Lam,
+                                                   const double* __restrict__ z, double* r, int q) {
   __shared__ double sz[kNB * kSG];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
@@ -706,7 +826,7 @@ __global__ void __launch_bounds__(256) k_trsv_gfwd(const SysDesc* __restrict__ s
   const int base = p0 * kNB;
   const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
   double* rs = r + sd.voff;
-  for (int k = tid; k < nseg * kNB; k += 256) sz[k] = rs[base + k];
+  for (int k = tid; k < nseg * kNB; k += 256) sz[k] = z[sd.voff + base + k];
   __syncthreads();
   const int i0 = (kSG * (q + 1) + t) * kNB + 4 * g;
   const double* A = Lam + sd.loff + (int64_t)i0 * ld + base + 4 * j;
@@ -787,18 +907,26 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
                        cnt, p);
 }
 
-void launch_trsv_gdiag(hipStream_t st, int cnt, const SysDesc* sys, const int* flags, const int* ssys,
-                       const double* Lam, const double* Linv, const double* vin, double* vout, int q,
-                       int backward) {
-  if (cnt)
-    hipLaunchKernelGGL(k_trsv_gdiag, dim3(cnt), dim3(kSvT), 0, st, sys, flags, ssys, Lam, Linv, vin, vout,
-                       q, backward);
+void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                      const int* spre, int cnt, int total, const double* Lam, const double* Linv,
+                      double* Ginv) {
+  if (total)
+    hipLaunchKernelGGL(k_trsv_ginv, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Lam, Linv, Ginv);
+}
+
+void launch_trsv_gapply(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                        const int* spre, int cnt, int total, const double* Ginv, const double* vin,
+                        double* vout, int q, int backward) {
+  if (total)
+    hipLaunchKernelGGL(k_trsv_gapply, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Ginv, vin,
+                       vout, q, backward);
 }
 
 void launch_trsv_gfwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
-                      const int* spre, int cnt, int total, const double* Lam, double* r, int q) {
+                      const int* spre, int cnt, int total, const double* Lam, const double* z, double* r,
+                      int q) {
   if (total)
-    hipLaunchKernelGGL(k_trsv_gfwd, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Lam, r, q);
+    hipLaunchKernelGGL(k_trsv_gfwd, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Lam, z, r, q);
 }
 
 void launch_trsv_gbwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,

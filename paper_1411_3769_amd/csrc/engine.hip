@@ -247,11 +247,12 @@ struct Batch {
   // grouped solves of the systems not solved in one workgroup: per group q,
   // the diagonal-block sweeps (one per system), the row tiles below the
   // group (forward) and the column tiles left of it (backward)
-  StepTab gdg, gfu, gbu;
+  StepTab gin, gap, gfu, gbu;   // G_q inverses (one step); per group q: G_q
+                                // products, row tiles below, column tiles left
   int maxNG = 0;
   std::vector<int> small_ids;
   int* d_small = nullptr;
-  int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0;
+  int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0, totgi = 0;
 
   // device
   void* dtab = nullptr;
@@ -268,9 +269,10 @@ struct Batch {
   int64_t* d_gpoff = nullptr;
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
   int *d_trs_sys = nullptr, *d_trs_pre = nullptr, *d_wide_sys = nullptr, *d_wide_pre = nullptr;
-  int *d_gdg_sys = nullptr, *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr,
-      *d_gbu_pre = nullptr;
+  int *d_gin_sys = nullptr, *d_gin_pre = nullptr, *d_gap_sys = nullptr, *d_gap_pre = nullptr;
+  int *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr, *d_gbu_pre = nullptr;
   int* d_flags = nullptr;
+  double* d_shf = nullptr;   // per system: diagonal shift factor of the Schur factorisation
   double* d_sc = nullptr;
   double* d_red = nullptr;
   int* d_kout = nullptr;
@@ -284,16 +286,19 @@ struct Batch {
   bool f32 = false;   // precision form: reduced-precision Schur assembly + refinement
   int prec = PSDP_PREC_FP64;
   int ir_max = 0;
+  bool shift_pass = false;  // the launches being issued factor some system with a shift
+  int graph_launches = 0;   // hipGraphLaunch calls of this solve
   std::vector<char> asm64;   // per system: fell back to FP64 assembly (sticky)
   int maxK = 0;
   int nmax_small = 0;   // largest block order <= kSmallN in the batch (0: none)
   int nmin_big = 0;     // the general block kernels skip orders below this
-  double *Lam, *Ldiag, *Linv, *Pm, *pre, *rscr;
+  double *Lam, *Ldiag, *Linv, *Ginv, *Pm, *pre, *rscr;
 
   // pinned host mirrors of the per-iteration transfers (flags, scalars),
   // one cached block
   int* h_hf = nullptr;
   int* h_prev = nullptr;
+  double* h_shf = nullptr;
   double* h_sc = nullptr;
   void* h_pin = nullptr;
   size_t h_pin_bytes = 0;
@@ -358,7 +363,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.S = count;
   B.sd.assign(sdps, sdps + count);
   // ---- per-system layout
-  int64_t curblk = 0, curvec = 0, curlam = 0, curdg = 0, curP = 0, curpre = 0;
+  int64_t curblk = 0, curvec = 0, curlam = 0, curdg = 0, curP = 0, curpre = 0, curgi = 0;
   std::vector<std::vector<int64_t>> a1(count), a2(count), ay(count);
   std::vector<size_t> q2beg(count + 1, 0);
   B.ownP.push_back(0);
@@ -384,6 +389,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     d.voff = curvec; curvec += d.Kpad;
     d.loff = curlam; curlam += (int64_t)d.Kpad * d.Kpad;
     d.dgoff = curdg; curdg += (int64_t)d.P * kNB * kNB;
+    d.gioff = -1;
+    if (!(ch->small[s] && d.P <= kSmallP)) {   // grouped solves
+      d.gioff = curgi;
+      curgi += (int64_t)((d.P + kSG - 1) / kSG) * 2 * kGS * kGS;
+    }
     d.poff = curP; curP += p->L0 * nn;
     d.H = p->dH; d.betaf = p->dbetaf; d.cdiag = p->dcdiag; d.scale = p->dscale; d.basis = p->dbasis;
     B.maxP = std::max(B.maxP, d.P);
@@ -473,6 +483,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.totdg = round_up(curdg, 32);
   B.totP = round_up(curP, 32);
   B.totpre = round_up(curpre, 32);
+  B.totgi = round_up(curgi, 32);
   B.nblk = (int)H.blk.size();
   B.npblk = (int)H.pblk.size();
   B.ndblk = (int)H.dblk.size();
@@ -488,8 +499,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   for (int s = 0; s < count; ++s)
     if (ch->pair[s] && sdps[s]->n * sdps[s]->n <= 128) pn = std::max(pn, sdps[s]->n);
   const int64_t totrs = pn ? (int64_t)kPairGrid * pn * pn * pn * pn : 0;
-  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totP + B.totpre +
-                        totrs;
+  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totgi + B.totP +
+                        B.totpre + totrs;
   B.arena_bytes = (size_t)std::max<int64_t>(total, 1) * 8;
   if (!(B.arena = (double*)dev_alloc(B.arena_bytes)))
     return fail(PSDP_ENOMEM, "device allocation of the solver arena failed (" +
@@ -504,6 +515,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.Lam = a + o; o += B.totlam;
   B.Ldiag = a + o; o += B.totdg;
   B.Linv = a + o; o += B.totdg;
+  B.Ginv = a + o; o += B.totgi;
   B.Pm = a + o; o += B.totP;
   B.pre = a + o; o += B.totpre;
   B.rscr = a + o; o += totrs;
@@ -606,14 +618,17 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   auto tiled = [&](int s) { return !(ch->small[s] && B.sys[s].P <= kSmallP); };
   for (int s = 0; s < count; ++s)
     if (tiled(s)) B.maxNG = std::max(B.maxNG, (B.sys[s].P + kSG - 1) / kSG);
+  B.gin.add_step();
+  for (int s = 0; s < count; ++s)
+    if (tiled(s)) B.gin.add(s, (B.sys[s].P + kSG - 1) / kSG * kSG);
   for (int q = 0; q < B.maxNG; ++q) {
-    B.gdg.add_step();
+    B.gap.add_step();
     B.gfu.add_step();
     B.gbu.add_step();
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (!tiled(s) || P <= kSG * q) continue;
-      B.gdg.add(s, 1);
+      B.gap.add(s, (std::min(P, kSG * (q + 1)) - kSG * q) * (kNB / 16));
       if (P > kSG * (q + 1)) B.gfu.add(s, P - kSG * (q + 1));
       if (q > 0) B.gbu.add(s, kSG * q);
     }
@@ -628,9 +643,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(H.csr_mh) + tabsize(H.csr_hl) + tabsize(H.csr_hm) + tabsize(H.pq2b);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
-  tb += tabsize(B.gdg.sys) + tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
+  tb += tabsize(B.gin.sys) + tabsize(B.gin.pre) + tabsize(B.gap.sys) + tabsize(B.gap.pre);
+  tb += tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
   tb += ((size_t)B.S * 4 + 255) / 256 * 256 + ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
+  tb += ((size_t)B.S * 8 + 255) / 256 * 256;   // shift factors
   tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 2 * 4 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256 + 4096;
   B.dtab_bytes = tb;
@@ -695,7 +712,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.wide.pre, &B.d_wide_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.upd.sys, &B.d_upd_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.upd.pre, &B.d_upd_pre))) return rc;
-  if ((rc = upload(B.dtab, stage, off, B.gdg.sys, &B.d_gdg_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gin.sys, &B.d_gin_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gin.pre, &B.d_gin_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gap.sys, &B.d_gap_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.gap.pre, &B.d_gap_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gfu.sys, &B.d_gfu_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gfu.pre, &B.d_gfu_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gbu.sys, &B.d_gbu_sys))) return rc;
@@ -705,15 +725,18 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   char* base = (char*)B.dtab;
   B.d_flags = (int*)(base + off); off += ((size_t)B.S * 4 + 255) / 256 * 256;
   B.d_sc = (double*)(base + off); off += ((size_t)B.S * kNSC * 8 + 255) / 256 * 256;
+  B.d_shf = (double*)(base + off); off += ((size_t)B.S * 8 + 255) / 256 * 256;
   B.d_red = (double*)(base + off); off += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256;
   B.d_kout = (int*)(base + off); off += ((size_t)B.nblk * 2 * 4 + 255) / 256 * 256;   // X and Z ladders
   B.d_cert = (double*)(base + off); off += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256;
   const size_t hf_bytes = ((size_t)B.S * 4 + 255) / 256 * 256;
-  B.h_pin_bytes = 2 * hf_bytes + (size_t)B.S * kNSC * 8;
+  const size_t shf_bytes = ((size_t)B.S * 8 + 255) / 256 * 256;
+  B.h_pin_bytes = 2 * hf_bytes + shf_bytes + (size_t)B.S * kNSC * 8;
   if (!(B.h_pin = pin_alloc(B.h_pin_bytes))) return fail(PSDP_ENOMEM, "pinned host buffers");
   B.h_hf = (int*)B.h_pin;
   B.h_prev = (int*)((char*)B.h_pin + hf_bytes);
-  B.h_sc = (double*)((char*)B.h_pin + 2 * hf_bytes);
+  B.h_shf = (double*)((char*)B.h_pin + 2 * hf_bytes);
+  B.h_sc = (double*)((char*)B.h_pin + 2 * hf_bytes + shf_bytes);
   return PSDP_OK;
 }
 
@@ -835,26 +858,37 @@ static void op_factor(Batch& B, hipStream_t st) {
     }
     if (B.upd.tot[p] > 0 || B.wide.tot[p] > 0) B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
   }
+  // inverses of the diagonal blocks of the grouped solves (timed with them)
+  if (B.gin.tot[0] > 0) {
+    const size_t m0 = B.prof.mark();
+    launch_trsv_ginv(st, B.d_sys, B.d_flags, B.d_gin_sys, B.d_gin_pre, B.gin.cnt[0], B.gin.tot[0], B.Lam,
+                     B.Linv, B.Ginv);
+    B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());
+  }
 }
 
 static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
   const size_t m0 = B.prof.mark();
   launch_trsv_small(st, (int)B.small_ids.size(), B.d_sys, B.d_flags, B.d_small, B.Lam, B.Linv, rhs, x);
   if (B.small_ids.size() < (size_t)B.S) {
+    // forward: z_q = G_q r_q, then the rows below; backward: x_q = G_q^T z_q,
+    // then the columns left (r, z scratch; x written group by group)
     PSDP_HIP(hipMemcpyAsync(B.r, rhs, B.totvec * 8, hipMemcpyDeviceToDevice, st));
     for (int q = 0; q < B.maxNG; ++q) {
-      launch_trsv_gdiag(st, B.gdg.cnt[q], B.d_sys, B.d_flags, B.d_gdg_sys + B.gdg.first[q], B.Lam, B.Linv,
-                        B.r, B.r, q, 0);
+      const int a = B.gap.first[q];
+      launch_trsv_gapply(st, B.d_sys, B.d_flags, B.d_gap_sys + a, B.d_gap_pre + a, B.gap.cnt[q], B.gap.tot[q],
+                         B.Ginv, B.r, B.z, q, 0);
       const int f = B.gfu.first[q];
       launch_trsv_gfwd(st, B.d_sys, B.d_flags, B.d_gfu_sys + f, B.d_gfu_pre + f, B.gfu.cnt[q],
-                       B.gfu.tot[q], B.Lam, B.r, q);
+                       B.gfu.tot[q], B.Lam, B.z, B.r, q);
     }
     for (int q = B.maxNG - 1; q >= 0; --q) {
-      launch_trsv_gdiag(st, B.gdg.cnt[q], B.d_sys, B.d_flags, B.d_gdg_sys + B.gdg.first[q], B.Lam, B.Linv,
-                        B.r, x, q, 1);
+      const int a = B.gap.first[q];
+      launch_trsv_gapply(st, B.d_sys, B.d_flags, B.d_gap_sys + a, B.d_gap_pre + a, B.gap.cnt[q], B.gap.tot[q],
+                         B.Ginv, B.z, x, q, 1);
       const int f = B.gbu.first[q];
       launch_trsv_gbwd(st, B.d_sys, B.d_flags, B.d_gbu_sys + f, B.d_gbu_pre + f, B.gbu.cnt[q],
-                       B.gbu.tot[q], B.Lam, x, B.r, q);
+                       B.gbu.tot[q], B.Lam, x, B.z, q);
     }
   }
   B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());
@@ -870,15 +904,18 @@ static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
 // solve.  Scratch: S1, T1, W1 (block arrays free during the solves), BX, vtmp.
 static int op_solve_refined(Batch& B, hipStream_t st, const double* rhs, double* x, bool first) {
   int rc = op_solve(B, st, rhs, x);
-  if (rc || B.ir_max == 0) return rc;
-  if (B.f32) launch_park(st, B.S, B.d_flags, 0);
-  for (int k = 0; k <= B.ir_max; ++k) {
+  // systems factored with a shift are refined against the unshifted product
+  const int irm = B.shift_pass ? std::max(B.ir_max, kIrShift) : B.ir_max;
+  if (rc || irm == 0) return rc;
+  // refinement of every system only when the caller asked for it in FP64
+  if (B.f32 || B.ir_max == 0) launch_park(st, B.S, B.d_flags, 0);
+  for (int k = 0; k <= irm; ++k) {
     op_BT(B, st, x, B.S1);
     op_sym_ZAX(B, st, B.S1);
     op_B(B, st, B.W1, B.BX, 0.0);
     launch_vec_axpby(st, B.S, B.d_sys, B.d_flags, -1.0, B.BX, 1.0, rhs);   // r = rhs - Lambda x
-    launch_ir_check(st, B.S, B.d_sys, B.d_flags, B.BX, rhs, B.d_sc, k, B.ir_max, first ? 1 : 0);
-    if (k == B.ir_max) break;
+    launch_ir_check(st, B.S, B.d_sys, B.d_flags, B.BX, rhs, B.d_sc, k, irm, first ? 1 : 0);
+    if (k == irm) break;
     if ((rc = op_solve(B, st, B.BX, B.vtmp))) break;
     launch_vec_axpby(st, B.S, B.d_sys, B.d_flags, 1.0, x, 1.0, B.vtmp);
   }
@@ -899,6 +936,9 @@ static int init_state(Batch& B, hipStream_t st) {
 
 struct RunState {
   int max_iter = 0;             // iteration cap of this system's run
+  int retries = 0;              // passes that repeated a failed Newton step (not iterations)
+  int shifts = 0;               // Newton steps whose Schur factorisation needed a shift
+  double shf = 0.0;             // shift factor of the next factorisation (0: none)
   int label_iter = -1;          // iteration whose iterate was recorded as the label
   std::vector<double> label_y, label_logx;
   int reason = PSDP_R_MAXITER;
@@ -912,8 +952,15 @@ struct RunState {
 };
 
 static void set_flags(Batch& B, const std::vector<RunState>& rs, int* hf) {
-  for (int s = 0; s < B.S; ++s)
-    hf[s] = rs[s].running ? F_ACTIVE | F_CHOLSEL | (B.f32 && !B.asm64[s] ? F_ASM32 : 0) : 0;
+  B.shift_pass = false;
+  for (int s = 0; s < B.S; ++s) {
+    const bool sh = rs[s].running && rs[s].shf > 0.0;
+    hf[s] = rs[s].running ? F_ACTIVE | F_CHOLSEL | (B.f32 && !B.asm64[s] ? F_ASM32 : 0) |
+                                (sh ? F_SHIFTED : 0)
+                          : 0;
+    B.h_shf[s] = sh ? rs[s].shf : 0.0;
+    B.shift_pass = B.shift_pass || sh;
+  }
 }
 
 // Idle solver streams, kept per device (creating and destroying a stream
@@ -1012,6 +1059,7 @@ static int replay(Batch& B, hipStream_t st, GraphRun& g, F&& fn) {
     B.prof.base = B.prof.next;   // the graph's events stay reserved
   }
   PSDP_HIP(hipGraphLaunch(g.exec, st));
+  ++B.graph_launches;
   B.prof.pend.insert(B.prof.pend.end(), g.pairs.begin(), g.pairs.end());
   return PSDP_OK;
 }
@@ -1029,6 +1077,9 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
   const int stall_w = 10;
   std::vector<char> was32(S, 0);   // the previous iteration assembled in FP32
   std::vector<char> prev_fail(S, 0);
+  std::vector<char> retry(S, 0);   // this pass repeats the previous (failed) Newton step
+  std::vector<char> was_shift(S, 0);   // the previous Newton step was factored with a shift
+  for (auto& r : rs) r.shf = r.running ? o.chol_shift_force : 0.0;
   // One synchronisation per iteration: after the residual kernels the host
   // reads the scalars and the flags (which still carry the failure bits of
   // the previous Newton step and of this iteration's Z^-1), decides, and
@@ -1051,7 +1102,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
   } ev_guard{ev_rb};
   // the graphs are destroyed before the event above, and only once nothing
   // launched here is still running (the last hoisted assembly may be)
-  GraphRun g1, g2, g3;
+  GraphRun g1, g2, g2s, g3;
   struct Drain {
     hipStream_t s;
     ~Drain() { hipStreamSynchronize(s); }
@@ -1086,17 +1137,31 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     }
     B.prof.harvest();
     if (it > 0) {
-      // failure bits of the previous Newton step
+      // failure bits of the previous Newton step (a failed step left the
+      // iterate unchanged, so this pass can repeat it)
       for (int s = 0; s < S; ++s) {
         was32[s] = (prev[s] & F_ASM32) != 0;
         prev_fail[s] = (prev[s] & F_LAMFAIL) != 0;
-        if (!rs[s].running) continue;
+        was_shift[s] = (prev[s] & F_SHIFTED) != 0;
+        retry[s] = 0;
+        RunState& r = rs[s];
+        if (!r.running) continue;
         if ((prev[s] & F_LAMFAIL) && (prev[s] & F_ASM32)) {
-          // the reduced-precision Schur matrix lost definiteness: the skipped
-          // step is repeated with FP64 assembly
+          // the reduced-precision Schur matrix lost definiteness: the step is
+          // repeated with FP64 assembly (same shift)
           B.asm64[s] = 1;
-        } else if (prev[s] & F_LAMFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_CHOL; }
-        else if (prev[s] & F_LADDERFAIL) { rs[s].running = false; rs[s].reason = PSDP_R_LADDER; }
+          retry[s] = 1;
+        } else if (prev[s] & F_LAMFAIL) {
+          // the FP64 factorisation failed: repeat the step with the next
+          // shift (the run ends below if it exceeds chol_shift_max)
+          r.shf = r.shf > 0.0 ? r.shf * kShiftGrowth : kShiftFirst;
+          retry[s] = 1;
+        } else {
+          if (was_shift[s]) ++r.shifts;
+          r.shf = o.chol_shift_force;   // the next step starts unshifted (or at the forced shift)
+          if (prev[s] & F_LADDERFAIL) { r.running = false; r.reason = PSDP_R_LADDER; }
+        }
+        r.retries += retry[s];
       }
     }
     bool any = false;
@@ -1106,33 +1171,44 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       const double* v = hsc + (size_t)s * kNSC;
       r.phi = v[S_PHI]; r.psi = v[S_PSI]; r.gap_abs = v[S_GAPABS]; r.gap_rel = v[S_GAPREL];
       r.pinf = v[S_PINF]; r.dinf = v[S_DINF];
-      r.iterations = it;
-      r.dinf_hist.push_back(r.dinf);
+      // a repeated step sees the same iterate: same scalars, no new iteration
+      const int ite = it - r.retries;
+      r.iterations = ite;
+      if (!retry[s]) r.dinf_hist.push_back(r.dinf);
       // refinement no longer contracts fast: FP64 assembly from here on
-      if (it > 0 && B.ir_max > 0 && (was32[s] || !B.f32)) r.ir_steps += (int)v[S_IRSTEPS];
-      if (it > 0 && was32[s]) {
+      const bool refined = (B.ir_max > 0 && (was32[s] || !B.f32)) || was_shift[s];
+      if (it > 0 && refined && !retry[s]) r.ir_steps += (int)v[S_IRSTEPS];
+      if (it > 0 && was32[s] && !retry[s]) {
         ++r.it32;
         const double eta = (prev_fail[s] || !(v[S_IRETA] == v[S_IRETA])) ? INFINITY : v[S_IRETA];
         if (B.ir_max > 0) r.eta_max = std::max(r.eta_max, eta);
         if (B.ir_max > 0 && (!(eta <= kIrSwitch) || v[S_IRFAIL] != 0.0)) B.asm64[s] = 1;
       }
-      if (hist) (*hist)[s].push_back(psdp_iter_rec{it, r.phi, r.psi, r.gap_rel, r.pinf, r.dinf, v[S_MU], 0, 0});
+      if (hist && !retry[s])
+        (*hist)[s].push_back(psdp_iter_rec{ite, r.phi, r.psi, r.gap_rel, r.pinf, r.dinf, v[S_MU], 0, 0});
       const bool finite = std::isfinite(r.phi) && std::isfinite(r.psi) && std::isfinite(r.pinf) &&
                           std::isfinite(r.dinf) && std::isfinite(v[S_TRZX]);
       if ((prev[s] & F_ZFAIL) || !finite) { r.running = false; r.reason = PSDP_R_NONFINITE; continue; }
       const bool ph1 = B.sys[s].mode == 1;
-      const bool gap_ok = r.gap_rel <= o.gap_tol || (ph1 && r.gap_abs <= 1e-2 * o.gap_tol);
-      if (gap_ok && r.pinf <= o.feas_tol && r.dinf <= o.feas_tol) {
-        r.running = false; r.reason = PSDP_R_CONVERGED; continue;
+      if (o.stop_rule == PSDP_STOP_ABSOLUTE && !ph1) {
+        // the printed test of Section IV-A: the absolute gap alone
+        if (r.gap_abs <= o.gap_tol) { r.running = false; r.reason = PSDP_R_CONVERGED; continue; }
+      } else {
+        const bool gap_ok = r.gap_rel <= o.gap_tol || (ph1 && r.gap_abs <= 1e-2 * o.gap_tol);
+        if (gap_ok && r.pinf <= o.feas_tol && r.dinf <= o.feas_tol) {
+          r.running = false; r.reason = PSDP_R_CONVERGED; continue;
+        }
       }
       if (!ph1) {
         if (r.phi > 0 && v[S_NORMBX] / r.phi <= 1e-6) { r.running = false; r.reason = PSDP_R_FARKAS; continue; }
         // stall: the dual residual, above tolerance, has not fallen 10x in 10 iterations
-        if (it >= stall_w && r.dinf > o.feas_tol && r.dinf > 0.1 * r.dinf_hist[it - stall_w]) {
+        if (ite >= stall_w && r.dinf > o.feas_tol && r.dinf > 0.1 * r.dinf_hist[ite - stall_w]) {
           r.running = false; r.reason = PSDP_R_STALL; continue;
         }
       }
-      if (it >= r.max_iter) { r.running = false; r.reason = PSDP_R_MAXITER; continue; }
+      if (ite >= r.max_iter) { r.running = false; r.reason = PSDP_R_MAXITER; continue; }
+      // no factorisation left to try for the next Newton step
+      if (r.shf > o.chol_shift_max * (1.0 + 1e-12)) { r.running = false; r.reason = PSDP_R_CHOL; continue; }
       any = true;
     }
     // training labels: the iterate at the first iteration with gap_rel <= label_gap
@@ -1150,7 +1226,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
         PSDP_HIP(hipStreamSynchronize(st));
         for (int s : want) {
           const SysDesc& d = B.sys[s];
-          rs[s].label_iter = it;
+          rs[s].label_iter = rs[s].iterations;
           rs[s].label_y.assign(yh.begin() + d.voff, yh.begin() + d.voff + d.K);
           rs[s].label_logx.assign(lx.begin() + d.blk0, lx.begin() + d.blk0 + d.nb);
         }
@@ -1161,8 +1237,14 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     // the Newton step: Schur complement, factor, solves, directions, steps
     auto part2 = [&]() -> int {
     PSDP_HIP(hipMemcpyAsync(B.d_flags, hf, S * 4, hipMemcpyHostToDevice, st));
+    if (B.shift_pass) PSDP_HIP(hipMemcpyAsync(B.d_shf, B.h_shf, S * 8, hipMemcpyHostToDevice, st));
     // ---- Newton system (Alg. 2 processors/root step 1)
     if (!hoist) op_schur(B, st);
+    if (B.shift_pass) {
+      const size_t pm_ = B.prof.mark();
+      launch_schur_shift(st, S, B.d_sys, B.d_flags, B.d_shf, B.Lam, B.d_sc);
+      B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark());
+    }
     op_factor(B, st);
     // blocks of order <= kSmallN take the fused chains, larger ones the
     // separate products and elementwise kernels (which skip the former)
@@ -1188,6 +1270,16 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.Wc, B.W1, nskip);
     }
       B.prof.add(PSDP_PROF_GEMM, pm_, B.prof.mark()); }
+    if (o.sigma_rule == PSDP_SIGMA_MEHROTRA) {
+      // Mehrotra's sigma from the predictor's step lengths; T1 = sym dX^
+      const size_t pm_ = B.prof.mark();
+      launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.dXh, B.T1, 0);
+      launch_ladder2(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.X, B.T1, B.Z, B.dZh,
+                     o.ladder_rho, o.step_frac, o.ladder_len, B.d_kout, B.d_kout + B.nblk);
+      launch_mehrotra(st, S, B.nblk, B.d_sys, B.d_blk, B.d_flags, B.d_kout, B.d_kout + B.nblk,
+                      o.ladder_rho, o.sigma, B.X, B.T1, B.Z, B.dZh, B.Zi, B.d_red, B.d_sc, B.Wc, B.W1);
+      B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark());
+    }
     op_B(B, st, B.W1, B.rv2, 0.0);
     op_solve_refined(B, st, B.rv2, B.dyb, false);
     // corrector directions (processors step 3), summed with the predictor's
@@ -1216,7 +1308,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     PSDP_HIP(hipGetLastError());
       return PSDP_OK;
     };
-    if ((rc = replay(B, st, g2, part2))) return rc;
+    if ((rc = replay(B, st, B.shift_pass ? g2s : g2, part2))) return rc;
     if (hist) {
       PSDP_HIP(hipMemcpyAsync(hsc, B.d_sc, nsc * 8, hipMemcpyDeviceToHost, st));
       PSDP_HIP(hipStreamSynchronize(st));
@@ -1384,6 +1476,13 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
       o.precision != PSDP_PREC_BF16)
     return fail(PSDP_EINVAL, "invalid precision");
   if (o.ir_max > 50) return fail(PSDP_EINVAL, "ir_max above 50");
+  if (!(o.chol_shift_max >= 0.0 && o.chol_shift_max < 1.0) ||
+      !(o.chol_shift_force >= 0.0 && o.chol_shift_force < 1.0))
+    return fail(PSDP_EINVAL, "chol_shift_max and chol_shift_force must lie in [0, 1)");
+  if (o.stop_rule != PSDP_STOP_RELATIVE && o.stop_rule != PSDP_STOP_ABSOLUTE)
+    return fail(PSDP_EINVAL, "invalid stop_rule");
+  if (o.sigma_rule != PSDP_SIGMA_FIXED && o.sigma_rule != PSDP_SIGMA_MEHROTRA)
+    return fail(PSDP_EINVAL, "invalid sigma_rule");
   // all work runs on a private stream (capturable into graphs) ordered
   // after the caller's stream
   SolveStream ss;
@@ -1545,6 +1644,9 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     R.iters_lowprec = r.it32 + (need[s] ? r1[s].it32 : 0);
     R.ir_steps = r.ir_steps + (need[s] ? r1[s].ir_steps : 0);
     R.ir_eta_max = R.iters_lowprec ? std::max(r.eta_max, need[s] ? r1[s].eta_max : 0.0) : NAN;
+    R.chol_shifts = r.shifts + (need[s] ? r1[s].shifts : 0);
+    R.graph_replays = B.graph_launches;
+    R.phase1_reason = need[s] ? r1[s].reason : -1;
     R.asm_path = B.use_pair[s] && p->n * p->n <= 128;
     R.solve_path = B.use_small[s] && d.P <= kSmallP;
     R.label_iter = r.label_iter;

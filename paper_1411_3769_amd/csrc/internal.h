@@ -19,7 +19,7 @@ constexpr int kNB = 64;      // Schur Cholesky tile
 constexpr int kPairGrid = 1024;   // workgroups of the whole-pair assembly (grid-stride)
 constexpr int kSW = 8;       // Cholesky panels per super-panel (depth of the wide update / 64)
 constexpr int kMaxDeg = 20;  // largest multinomial degree (20! < 2^63)
-constexpr int kNSC = 24;     // per-system scalar slots
+constexpr int kNSC = 32;     // per-system scalar slots
 
 // per-system scalar slots (double array sc[sys * kNSC + slot])
 enum Slot {
@@ -29,6 +29,8 @@ enum Slot {
   S_IRLAST,  // residual ratio of the latest refinement step
   S_IRFAIL,  // 1 if a solve of the iteration stopped refining above kIrAccept
   S_IRSTEPS, // refinement corrections applied in the iteration
+  S_TPA, S_TDA,   // step lengths of the predictor directions (Mehrotra's sigma), -1: none
+  S_MUDELTA,      // change of mu made by Mehrotra's sigma
 };
 
 // per-system flag bits (int array flags[sys])
@@ -40,7 +42,17 @@ enum Flag {
   F_CHOLSEL = 16,     // selected for the (re)factorisation pass
   F_ASM32 = 32,       // Schur assembly in reduced precision this iteration
   F_PARK = 64,        // temporarily inactive (FP64-assembled system during refinement)
+  F_SHIFTED = 128,    // the Schur matrix is factored with a diagonal shift this step
 };
+
+// Failure policy of the FP64 Schur factorisation: the step is retried on
+// Lambda + f max_i Lambda_ii I, f = kShiftFirst, then x kShiftGrowth per
+// failure up to the caller's limit, and its solves are refined against the
+// unshifted matrix-free product with at most kIrShift corrections (more if
+// ir_max asks for more).
+constexpr double kShiftFirst = 1e-14;
+constexpr double kShiftGrowth = 100.0;
+constexpr int kIrShift = 6;
 
 // Iterative refinement of the Newton solves: a solve is accepted once its
 // residual ratio ||rhs - Lambda x||_inf / ||rhs||_inf falls to kIrTol, or
@@ -60,6 +72,8 @@ struct SysDesc {
   int64_t loff;     // Schur matrix offset (Kpad * Kpad)
   int64_t poff;     // P_h scratch offset (L0 * n * n)
   int64_t dgoff;    // factored diagonal tiles of the Schur matrix (P * 64 * 64)
+  int64_t gioff;    // grouped solves: inverses of the factor's diagonal blocks of
+                    // kSG tiles, (L_qq^-1, L_qq^-T) per group, 2 kGS^2 each; -1: none
   const double* H;      // [M][L0][n][n]
   const double* betaf;  // [L0][L]
   const double* cdiag;  // [L+M]
@@ -165,11 +179,15 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
                              const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
                         double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
-void launch_trsv_gdiag(hipStream_t st, int cnt, const SysDesc* sys, const int* flags, const int* ssys,
-                       const double* Lam, const double* Linv, const double* vin, double* vout, int q,
-                       int backward);
+void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                      const int* spre, int cnt, int total, const double* Lam, const double* Linv,
+                      double* Ginv);
+void launch_trsv_gapply(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                        const int* spre, int cnt, int total, const double* Ginv, const double* vin,
+                        double* vout, int q, int backward);
 void launch_trsv_gfwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
-                      const int* spre, int cnt, int total, const double* Lam, double* r, int q);
+                      const int* spre, int cnt, int total, const double* Lam, const double* z, double* r,
+                      int q);
 void launch_trsv_gbwd(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
                       const int* spre, int cnt, int total, const double* Lam, const double* x, double* z,
                       int q);
@@ -179,6 +197,7 @@ void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int
 constexpr int kSmallN = 16;   // blocks up to this order take the packed small-block kernels
 constexpr int kSmallP = 32;   // systems with at most this many Schur tiles solve in one launch
 constexpr int kSG = 8;       // panels per group of the tiled triangular solves
+constexpr int kGS = kSG * kNB;   // rows of such a group
 
 // engine entry used by the public solve / eval calls
 int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res);

@@ -97,6 +97,12 @@ void launch_ir_check(hipStream_t st, int S, const SysDesc* sys, int* flags, cons
 void launch_vec_axpby(hipStream_t st, int S, const SysDesc* sys, const int* flags, double a,
                       double* x, double b, const double* y);
 void launch_pad_identity(hipStream_t st, int S, const SysDesc* sys, double* Lam);
+void launch_mehrotra(hipStream_t st, int S, int nblk, const SysDesc* sys, const BlkDesc* blks,
+                     const int* flags, const int* koutX, const int* koutZ, double rho, double sigma0,
+                     const double* X, const double* dXs, const double* Z, const double* dZh,
+                     const double* Zi, double* red, double* sc, double* Wc, double* W1);
+void launch_schur_shift(hipStream_t st, int S, const SysDesc* sys, const int* flags, const double* shf,
+                        double* Lam, double* sc);
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         const SysDesc* sys, const int* flags, const double* Q, int iters,
                         double* out);

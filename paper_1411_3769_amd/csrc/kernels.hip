@@ -796,6 +796,153 @@ __global__ void k_pad_identity(const SysDesc* __restrict__ sys, double* Lam) {
 
 
 // ---------------------------------------------------------------------------
+// Mehrotra's centring parameter (option): from the ladders of the predictor
+// directions, t_p^a and t_d^a (first passing rungs as for the step lengths),
+// mu_aff = tr((Z + t_d^a dZ^)(X + t_p^a sym dX^)) / m and
+// sigma = min(1, max(0, (mu_aff / mu)^3)) with mu = tr(ZX) / m; the fixed
+// sigma stays if either ladder finds no step.  The corrector right-hand side
+// formed with the fixed sigma is moved to the new mu: W += (mu' - mu) Z^-1.
+// ---------------------------------------------------------------------------
+
+// one wave per system: predictor step lengths into S_TPA / S_TDA (-1: none)
+__global__ void __launch_bounds__(256) k_mehrotra_steps(const SysDesc* __restrict__ sys, int S,
+                                                        const int* __restrict__ flags,
+                                                        const int* __restrict__ koutX,
+                                                        const int* __restrict__ koutZ, double rho,
+                                                        double* sc) {
+  const int s = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (s >= S) return;
+  if (!(flags[s] & F_ACTIVE)) return;
+  const int blk0 = sys[s].blk0, nb = sys[s].nb;
+  int kx = 0, kz = 0, bad = 0;
+  for (int j = lane; j < nb; j += 64) {
+    const int a = koutX[blk0 + j], c = koutZ[blk0 + j];
+    bad |= (a < 0) | (c < 0);
+    kx = a > kx ? a : kx;
+    kz = c > kz ? c : kz;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int ox = __shfl_xor(kx, m), oz = __shfl_xor(kz, m);
+    kx = ox > kx ? ox : kx;
+    kz = oz > kz ? oz : kz;
+    bad |= __shfl_xor(bad, m);
+  }
+  if (lane != 0) return;
+  double tp = 1.0, td = 1.0;
+  for (int k = 0; k < kx; ++k) tp = tp * rho;
+  for (int k = 0; k < kz; ++k) td = td * rho;
+  sc[(size_t)s * kNSC + S_TPA] = bad ? -1.0 : tp;
+  sc[(size_t)s * kNSC + S_TDA] = bad ? -1.0 : td;
+}
+
+// per block: red[4 blk] = tr((Z + td dZ^)(X + tp dXs)), both factors symmetric
+__global__ void __launch_bounds__(256) k_mehrotra_trace(const BlkDesc* __restrict__ blks,
+                                                        const int* __restrict__ flags,
+                                                        const double* __restrict__ sc,
+                                                        const double* __restrict__ X,
+                                                        const double* __restrict__ dXs,
+                                                        const double* __restrict__ Z,
+                                                        const double* __restrict__ dZh, double* red) {
+  __shared__ double sb[256];
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const double tp = sc[(size_t)bd.sys * kNSC + S_TPA], td = sc[(size_t)bd.sys * kNSC + S_TDA];
+  double a = 0.0;
+  for (int e = threadIdx.x; e < bd.n * bd.n; e += blockDim.x) {
+    const int64_t o = bd.off + e;
+    a += (Z[o] + td * dZh[o]) * (X[o] + tp * dXs[o]);
+  }
+  a = wg_sum256(a, sb);
+  if (threadIdx.x == 0) red[(int64_t)blockIdx.x * 4] = a;
+}
+
+// per system: sigma, the new mu and its change
+__global__ void __launch_bounds__(256) k_mehrotra_sigma(const SysDesc* __restrict__ sys,
+                                                        const int* __restrict__ flags,
+                                                        const double* __restrict__ red,
+                                                        double sigma0, double* sc) {
+  __shared__ double sb[256];
+  const int s = blockIdx.x;
+  ACTIVE_OR_RETURN(s);
+  const SysDesc sd = sys[s];
+  double a = 0.0;
+  for (int j = threadIdx.x; j < sd.nb; j += blockDim.x) a += red[(int64_t)(sd.blk0 + j) * 4];
+  a = wg_sum256(a, sb);
+  if (threadIdx.x == 0) {
+    double* o = sc + (size_t)s * kNSC;
+    const double m = (double)(sd.nb * sd.n);
+    const double trzx = o[S_TRZX];
+    double sigma = sigma0;
+    if (o[S_TPA] >= 0.0 && o[S_TDA] >= 0.0) {
+      const double q = (a / m) / (trzx / m);
+      sigma = fmin(1.0, fmax(0.0, q * q * q));
+    }
+    const double mu = sigma * trzx / m;
+    o[S_MUDELTA] = mu - o[S_MU];
+    o[S_MU] = mu;
+  }
+}
+
+// Wc += delta Z^-1 and W1 += delta Z^-1 (W1 = sym Wc; Z^-1 is symmetric)
+__global__ void __launch_bounds__(256) k_mu_fix(const BlkDesc* __restrict__ blks,
+                                                const int* __restrict__ flags,
+                                                const double* __restrict__ sc,
+                                                const double* __restrict__ Zi, double* Wc, double* W1) {
+  const BlkDesc bd = blks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  const double dm = sc[(size_t)bd.sys * kNSC + S_MUDELTA];
+  for (int e = threadIdx.x; e < bd.n * bd.n; e += blockDim.x) {
+    const int64_t o = bd.off + e;
+    Wc[o] = Wc[o] + dm * Zi[o];
+    W1[o] = W1[o] + dm * Zi[o];
+  }
+}
+
+void launch_mehrotra(hipStream_t st, int S, int nblk, const SysDesc* sys, const BlkDesc* blks,
+                     const int* flags, const int* koutX, const int* koutZ, double rho, double sigma0,
+                     const double* X, const double* dXs, const double* Z, const double* dZh,
+                     const double* Zi, double* red, double* sc, double* Wc, double* W1) {
+  if (S <= 0 || nblk <= 0) return;
+  k_mehrotra_steps<<<(S + 3) / 4, 256, 0, st>>>(sys, S, flags, koutX, koutZ, rho, sc);
+  k_mehrotra_trace<<<nblk, 256, 0, st>>>(blks, flags, sc, X, dXs, Z, dZh, red);
+  k_mehrotra_sigma<<<S, 256, 0, st>>>(sys, flags, red, sigma0, sc);
+  k_mu_fix<<<nblk, 256, 0, st>>>(blks, flags, sc, Zi, Wc, W1);
+}
+
+// Diagonal shift of the Schur matrix before it is factored, for the systems
+// flagged F_SHIFTED (the retry after a failed FP64 factorisation, Alg. 2 root
+// step 1): tau = shf[s] max_i Lambda_ii over the system's K unknowns (the
+// assembled matrix, phase-I transform included), Lambda_ii += tau.  One
+// workgroup per system; sc receives max diag and tau.
+__global__ void __launch_bounds__(256) k_schur_shift(const SysDesc* __restrict__ sys,
+                                                     const int* __restrict__ flags,
+                                                     const double* __restrict__ shf, double* Lam,
+                                                     double* sc) {
+  __shared__ double sb[256];
+  const int s = blockIdx.x;
+  const int f = flags[s];
+  if (!(f & F_ACTIVE) || !(f & F_SHIFTED)) return;
+  const SysDesc sd = sys[s];
+  double* A = Lam + sd.loff;
+  const int64_t ld1 = sd.Kpad + 1;
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < sd.K; i += blockDim.x) m = nanmax(m, A[i * ld1]);
+  m = wg_max256(m, sb);
+  const double tau = shf[s] * m;
+  for (int i = threadIdx.x; i < sd.K; i += blockDim.x) A[i * ld1] = A[i * ld1] + tau;
+  if (threadIdx.x == 0) {
+    sc[(size_t)s * kNSC + S_DIAGMAX] = m;
+    sc[(size_t)s * kNSC + S_TAU] = tau;
+  }
+}
+
+void launch_schur_shift(hipStream_t st, int S, const SysDesc* sys, const int* flags, const double* shf,
+                        double* Lam, double* sc) {
+  if (S > 0) k_schur_shift<<<S, 256, 0, st>>>(sys, flags, shf, Lam, sc);
+}
+
+// ---------------------------------------------------------------------------
 // phase-I margin SDP (max t s.t. B^T(y) - t D >= 0, a^T y = 1, with y_K
 // eliminated): operators and Schur complement expressed through the paper's.
 // ---------------------------------------------------------------------------
@@ -1726,14 +1873,14 @@ __global__ void k_vec_axpby(const SysDesc* __restrict__ sys, const int* __restri
   }
 }
 
-// mode 0: park the active systems assembled in FP64 (they skip refinement);
-// mode 1: re-activate the parked ones
+// mode 0: park the active systems assembled in FP64 and factored without a
+// shift (their solves need no refinement); mode 1: re-activate the parked ones
 __global__ void k_park(int S, int* flags, int mode) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   const int f = flags[s];
   if (mode == 0) {
-    if ((f & F_ACTIVE) && !(f & F_ASM32)) flags[s] = (f & ~F_ACTIVE) | F_PARK;
+    if ((f & F_ACTIVE) && !(f & (F_ASM32 | F_SHIFTED))) flags[s] = (f & ~F_ACTIVE) | F_PARK;
   } else if (f & F_PARK) {
     flags[s] = (f & ~F_PARK) | F_ACTIVE;
   }

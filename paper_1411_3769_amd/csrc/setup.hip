@@ -287,6 +287,10 @@ void psdp_opts_default(psdp_opts* o) {
   o->solve_path = -1;
   o->use_graph = 1;
   o->label_gap = 0.0;
+  o->chol_shift_max = 1e-6;
+  o->chol_shift_force = 0.0;
+  o->stop_rule = PSDP_STOP_RELATIVE;
+  o->sigma_rule = PSDP_SIGMA_FIXED;
 }
 
 const char* psdp_last_error(void) { return g_err.c_str(); }

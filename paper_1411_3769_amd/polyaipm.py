@@ -29,6 +29,8 @@ VERDICTS = {0: "FEASIBLE", 1: "INFEASIBLE", 2: "UNKNOWN"}
 REASONS = ["converged", "farkas", "stall", "max_iter", "ladder_fail", "chol_fail", "nonfinite"]
 VERDICT_MODES = {"paper_then_phase1": 0, "paper_only": 1, "phase1_only": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+STOP_RULES = {"relative": 0, "absolute": 1}
+SIGMA_RULES = {"fixed": 0, "mehrotra": 1}
 ERRORS = {-1: "EINVAL", -2: "EOVERFLOW", -3: "ENOMEM", -4: "EDEVICE", -5: "ENUMERIC"}
 NPROF = 16
 PROF_CLASSES = ["cholinv", "BT", "B", "pre", "assemble", "chol_panel", "chol_update", "trsv",
@@ -60,7 +62,8 @@ class Opts(C.Structure):
                 ("warm_y", C.POINTER(DP)), ("warm_logx", C.POINTER(DP)), ("warm_iter_cap", C.c_int),
                 ("warm_margin", C.c_double), ("warm_center", C.c_int), ("asm_path", C.c_int),
                 ("solve_path", C.c_int), ("use_graph", C.c_int),
-                ("label_gap", C.c_double)]
+                ("label_gap", C.c_double), ("chol_shift_max", C.c_double),
+                ("chol_shift_force", C.c_double), ("stop_rule", C.c_int), ("sigma_rule", C.c_int)]
 
 
 class IterRec(C.Structure):
@@ -82,7 +85,8 @@ class CResult(C.Structure):
                 ("logx", C.c_void_p), ("label_y", C.c_void_p), ("label_logx", C.c_void_p),
                 ("label_iter", C.c_int),
                 ("asm_path", C.c_int), ("solve_path", C.c_int),
-                ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int)]
+                ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int),
+                ("chol_shifts", C.c_int), ("graph_replays", C.c_int), ("phase1_reason", C.c_int)]
 
 
 class PsdpError(RuntimeError):
@@ -301,6 +305,10 @@ def make_opts(**kw) -> Opts:
             v = VERDICT_MODES[v]
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
+        if k == "stop_rule" and isinstance(v, str):
+            v = STOP_RULES[v]
+        if k == "sigma_rule" and isinstance(v, str):
+            v = SIGMA_RULES[v]
         if k == "stream":
             v = C.c_void_p(v) if isinstance(v, int) else v
         if k == "prof":
@@ -344,6 +352,9 @@ class Result:
     asm_path: int = -1
     solve_path: int = -1
     history: list = field(default_factory=list)
+    chol_shifts: int = 0
+    graph_replays: int = 0
+    phase1_reason: int = -1
 
     @property
     def verdict_name(self):
@@ -415,7 +426,8 @@ def _unpack(r: CResult, P, y, lx, hist) -> Result:
                   r.phase1_iterations, r.t_star, r.time_solve_s, r.iters_lowprec,
                   r.ir_steps, r.ir_eta_max, bool(r.warm_used), bool(r.warm_fallback),
                   r.warm_iterations, lx[0], lx[1] if r.label_iter >= 0 else None,
-                  lx[2] if r.label_iter >= 0 else None, r.label_iter, r.asm_path, r.solve_path, h)
+                  lx[2] if r.label_iter >= 0 else None, r.label_iter, r.asm_path, r.solve_path, h,
+                  r.chol_shifts, r.graph_replays, r.phase1_reason)
 
 
 def ipm_solve(sdp: SDP, warm_y=None, warm_logx=None, **opts) -> Result:

@@ -120,15 +120,27 @@ def test_graph_replay_equals_eager(P, prec):
         [W.paper_shape_system(16, 3, 0)]
     gs = [P.polya_setup(sy.A, sy.n, sy.l, sy.dp, sy.d) for sy in sys_]
     print(f"graph vs eager, {prec}", flush=True)
-    prof = P.new_prof()
-    rg = P.ipm_solve_batched(gs, precision=prec, use_graph=1, prof=prof)
+    rg = P.ipm_solve_batched(gs, precision=prec, use_graph=1)
     re = P.ipm_solve_batched(gs, precision=prec, use_graph=0)
+    # the graph run replayed captured graphs (every iteration launches two or
+    # three), the eager run none
+    its = max(r.iterations + r.phase1_iterations for r in rg)
+    assert all(r.graph_replays >= 2 * its for r in rg), [r.graph_replays for r in rg]
+    assert all(r.graph_replays == 0 for r in re)
     for a, b in zip(rg, re):
         assert a.verdict == b.verdict and a.iterations == b.iterations
         assert a.phase1_used == b.phase1_used and a.phase1_iterations == b.phase1_iterations
         assert np.array_equal(a.y, b.y)
-    # the profiler sees the replayed launches too
-    assert prof[P.PROF_CLASSES.index("assemble"), 1] >= sum(r.iterations for r in rg[:1])
+    # the class profiler launches eagerly (and, in FP64, without issuing the
+    # next assembly ahead of the host's decisions): same results, and every
+    # launch class is counted
+    prof = P.new_prof()
+    rp = P.ipm_solve_batched(gs, precision=prec, use_graph=1, prof=prof)
+    assert all(r.graph_replays == 0 for r in rp)
+    for a, b in zip(rp, re):
+        assert a.verdict == b.verdict and a.iterations == b.iterations
+        assert np.array_equal(a.y, b.y)
+    assert prof[P.PROF_CLASSES.index("assemble"), 1] >= sum(r.iterations for r in rp[:1])
 
 
 @pytest.mark.parametrize("asm_path,solve_path", [(0, 0), (0, 1), (1, 0), (1, 1), (-1, -1)])

@@ -60,9 +60,13 @@ def test_polya_setup_bit_exact(P, n, l, dp, d):
 
 NEWTON_CASES = [(4, 3, 1, 1, 0), (10, 4, 2, 2, 1), (3, 2, 2, 1, 2), (9, 2, 1, 2, 3), (13, 2, 1, 1, 4),
                 (1, 3, 1, 1, 5), (20, 3, 1, 1, 6)]
+# Schur matrices of 22, 33 and 56 tiles of 64: the factorisation's depth-512
+# wide updates run, the first two with a last super-panel that absorbs a
+# short trailing run; the solves go by groups of 8 tiles
+NEWTON_BIG = [(16, 4, 2, 1, 7), (32, 4, 1, 2, 8), (48, 3, 1, 1, 9)]
 
 
-@pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES)
+@pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES + NEWTON_BIG)
 def test_newton_step_parity(P, n, l, dp, d, seed):
     _flush(f"newton n={n} l={l} dp={dp} d={d} seed={seed}")
     rng = np.random.default_rng(seed)
@@ -81,7 +85,16 @@ def test_newton_step_parity(P, n, l, dp, d, seed):
     assert np.abs(out["BTy"] - BT).max() <= 1e-12 * np.abs(BT).max()
     BX = o.B(X)[perm]
     assert np.abs(out["BX"] - BX).max() <= 1e-12 * np.abs(BX).max()
-    Lam = S.schur_expanded(o, X, Zi)[np.ix_(perm, perm)]
+    if o.K <= 700:
+        # the definition of every column, B(Z^-1 B^T(e_l) X)
+        Lam = S.schur_definition(o, X, Zi)[np.ix_(perm, perm)]
+    else:
+        # the expanded form everywhere, the definition on columns spread over
+        # every tile (first and last column of each, in the library's order)
+        Lam = S.schur_expanded(o, X, Zi)[np.ix_(perm, perm)]
+        cols = sorted({c for t in range(0, o.K, 64) for c in (t, min(t + 63, o.K - 1))})
+        Ld = S.schur_definition_columns(o, X, Zi, [int(perm[c]) for c in cols])[perm]
+        assert np.abs(out["Lam"][:, cols] - Ld).max() <= 1e-12 * np.abs(Ld).max()
     sc = np.abs(Lam).max()
     assert np.abs(out["Lam"] - Lam).max() <= 1e-12 * sc
     Lf = out["LamL"]
