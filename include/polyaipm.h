@@ -306,6 +306,25 @@ int psdp_ipm_solve_batched(psdp_sdp* const* sdps, int count, const psdp_opts* op
                            psdp_result* res);
 
 /*
+ * psdp_ipm_solve_noalloc -- psdp_ipm_solve for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, same results as psdp_ipm_solve run
+ * with the same kernel paths; it calls no hipMalloc, hipFree, hipHostMalloc
+ * or other allocating routine.  Every table and array of the solve lives in
+ * one static device array of PSDP_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends; a system whose
+ * solve needs more (the Schur matrix alone is 8 Kpad^2 bytes: about K <= 3800
+ * fits) is rejected with PSDP_EINVAL before any device work.  The solve runs
+ * eagerly on opts->stream (no private stream, no graphs, no autotuner: the
+ * kernel paths are opts->asm_path / solve_path, -1 = the defaults; the class
+ * profiler is off) and synchronises it before returning.  The array keeps
+ * the last call's contents; each call initialises everything it reads.
+ * Calls that overlap on one device race for the array and must not be made.
+ */
+#define PSDP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int psdp_ipm_solve_noalloc(psdp_sdp* sdp, const psdp_opts* opts, psdp_result* res);
+
+/*
  * Hot-path evaluation at a fixed iterate, for parity checks of single steps
  * (Alg. 2, processors step 1 and root step 1).  Host buffers:
  *   X, Z: [L+M][n][n] symmetric positive definite blocks; y: [K].

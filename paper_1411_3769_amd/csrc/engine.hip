@@ -25,6 +25,10 @@
 #include "internal.h"
 #include "kernels.h"
 
+// Device scratch of the allocation-free solve (see scratch_ptr below).
+static constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace psdp {
 
 namespace {
@@ -304,8 +308,15 @@ struct Batch {
   size_t h_pin_bytes = 0;
 
   size_t dtab_bytes = 0, arena_bytes = 0;
+  // external device memory (the allocation-free solve): tables and arena
+  // are carved from ext, host images live in ordinary host vectors, and
+  // nothing is released here
+  char* ext = nullptr;
+  size_t ext_bytes = 0;
+  std::vector<char> h_img;
 
   ~Batch() {
+    if (ext) return;
     if (dtab) dev_release(dtab, dtab_bytes);
     if (arena) dev_release(arena, arena_bytes);
     pin_release(h_pin, h_pin_bytes);
@@ -352,6 +363,7 @@ static Choice default_choice(psdp_sdp* const* sdps, int count) {
 }
 
 static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice* ch = nullptr) {
+  // B.ext / B.ext_bytes, when set by the caller, replace every device allocation
   HostTables& H = host_tables();
   Choice dflt;
   if (!ch) {
@@ -498,13 +510,21 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   int pn = 0;
   for (int s = 0; s < count; ++s)
     if (ch->pair[s] && sdps[s]->n * sdps[s]->n <= 128) pn = std::max(pn, sdps[s]->n);
-  const int64_t totrs = pn ? (int64_t)kPairGrid * pn * pn * pn * pn : 0;
+  // (only blocks of order 11 keep R in global scratch; smaller ones in LDS)
+  const int64_t totrs = pn * pn > 112 ? (int64_t)kPairGrid * pn * pn * pn * pn : 0;
   const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totgi + B.totP +
                         B.totpre + totrs;
   B.arena_bytes = (size_t)std::max<int64_t>(total, 1) * 8;
-  if (!(B.arena = (double*)dev_alloc(B.arena_bytes)))
+  if (B.ext) {
+    if (B.arena_bytes > B.ext_bytes)
+      return fail(PSDP_EINVAL, "the solve needs " + std::to_string(B.arena_bytes) +
+                                   " bytes of device scratch for its arena alone; the allocation-free "
+                                   "entry point has " + std::to_string(B.ext_bytes));
+    B.arena = (double*)B.ext;
+  } else if (!(B.arena = (double*)dev_alloc(B.arena_bytes))) {
     return fail(PSDP_ENOMEM, "device allocation of the solver arena failed (" +
                                  std::to_string(total * 8) + " bytes)");
+  }
   double* a = B.arena;
   int64_t o = 0;
   double** blkarrs[nblkarr] = {&B.X, &B.Z, &B.Zi, &B.G, &B.S1, &B.T1, &B.W1, &B.dXh,
@@ -651,15 +671,27 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += ((size_t)B.nblk * 4 * 8 + 255) / 256 * 256 + ((size_t)B.nblk * 2 * 4 + 255) / 256 * 256;
   tb += ((size_t)B.nblk * 2 * 8 + 255) / 256 * 256 + 4096;
   B.dtab_bytes = tb;
-  if (!(B.dtab = dev_alloc(tb))) return fail(PSDP_ENOMEM, "device allocation of tables failed");
+  const size_t arena_end = (B.arena_bytes + 255) / 256 * 256;
+  if (B.ext) {
+    if (arena_end + tb > B.ext_bytes)
+      return fail(PSDP_EINVAL, "the solve needs " + std::to_string(arena_end + tb) +
+                                   " bytes of device scratch; the allocation-free entry point has " +
+                                   std::to_string(B.ext_bytes));
+    B.dtab = B.ext + arena_end;
+  } else if (!(B.dtab = dev_alloc(tb))) {
+    return fail(PSDP_ENOMEM, "device allocation of tables failed");
+  }
   size_t off = 0;
   int rc = PSDP_OK;
-  Stage stage{(char*)pin_alloc(tb), tb};
+  static thread_local std::vector<char> ext_stage;
+  if (B.ext && ext_stage.size() < tb) ext_stage.resize(tb);
+  Stage stage{B.ext ? ext_stage.data() : (char*)pin_alloc(tb), tb};
   if (!stage.p) return fail(PSDP_ENOMEM, "pinned staging buffer for the tables");
   struct StageGuard {
     Stage& s;
-    ~StageGuard() { pin_release(s.p, s.cap); }
-  } stage_guard{stage};
+    bool ext;
+    ~StageGuard() { if (!ext) pin_release(s.p, s.cap); }
+  } stage_guard{stage, B.ext != nullptr};
   int* d_csr_hh; int* d_csr_hid; int* d_csr_mh; int* d_csr_hl; int* d_csr_hm; int* d_pq2b;
   // the per-system CSR pointers must be patched into SysDesc before upload
   {
@@ -732,7 +764,12 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   const size_t hf_bytes = ((size_t)B.S * 4 + 255) / 256 * 256;
   const size_t shf_bytes = ((size_t)B.S * 8 + 255) / 256 * 256;
   B.h_pin_bytes = 2 * hf_bytes + shf_bytes + (size_t)B.S * kNSC * 8;
-  if (!(B.h_pin = pin_alloc(B.h_pin_bytes))) return fail(PSDP_ENOMEM, "pinned host buffers");
+  if (B.ext) {
+    B.h_img.resize(B.h_pin_bytes);
+    B.h_pin = B.h_img.data();
+  } else if (!(B.h_pin = pin_alloc(B.h_pin_bytes))) {
+    return fail(PSDP_ENOMEM, "pinned host buffers");
+  }
   B.h_hf = (int*)B.h_pin;
   B.h_prev = (int*)((char*)B.h_pin + hf_bytes);
   B.h_shf = (double*)((char*)B.h_pin + 2 * hf_bytes);
@@ -1093,7 +1130,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
   // each step's assembly precision on the host, and the class profiler
   // needs every launch of a class in one place, so both keep the plain
   // order.)
-  const bool hoist = !B.f32 && !B.prof.on;
+  const bool hoist = !B.f32 && !B.prof.on && !B.ext;
   hipEvent_t ev_rb = nullptr;
   if (hoist) PSDP_HIP(hipEventCreateWithFlags(&ev_rb, hipEventDisableTiming));
   struct EvGuard {
@@ -1464,8 +1501,38 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
   return PSDP_OK;
 }
 
+// Device scratch of the allocation-free solve (psdp_ipm_solve_noalloc):
+// every table and array of such a solve is carved from this array.  Each
+// device holds its own copy until the process ends; the host reaches it only
+// through the address hipGetSymbolAddress returns for the current device
+// (the array's name in host code is not a device address).  Calls on one
+// device share it, so concurrent ones race.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int scratch_ptr(void** out) {
+  int dev = 0;
+  PSDP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PSDP_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PSDP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PSDP_OK;
+}
+
+// ext (or NULL): device memory that holds every table and array of the
+// solve (the allocation-free entry point); the solve then runs eagerly on the
+// caller's stream with the default or requested kernel paths, without the
+// autotuner, graphs, the class profiler or pinned buffers.
 static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp_result* res,
-                      bool use_warm) {
+                      bool use_warm, char* ext = nullptr, size_t ext_bytes = 0) {
   auto t0 = std::chrono::steady_clock::now();
   if (!(o.gap_tol > 0) || !(o.feas_tol > 0) || o.max_iter < 0 || !(o.sigma > 0 && o.sigma < 1) ||
       !(o.step_frac > 0 && o.step_frac <= 1) || !(o.ladder_rho > 0 && o.ladder_rho < 1) ||
@@ -1484,22 +1551,35 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
   if (o.sigma_rule != PSDP_SIGMA_FIXED && o.sigma_rule != PSDP_SIGMA_MEHROTRA)
     return fail(PSDP_EINVAL, "invalid sigma_rule");
   // all work runs on a private stream (capturable into graphs) ordered
-  // after the caller's stream
+  // after the caller's stream; the allocation-free solve uses the caller's
   SolveStream ss;
-  if (int rc0 = ss.open((hipStream_t)o.stream)) return rc0;
-  hipStream_t st = ss.st;
+  hipStream_t st = (hipStream_t)o.stream;
+  if (!ext) {
+    if (int rc0 = ss.open((hipStream_t)o.stream)) return rc0;
+    st = ss.st;
+  }
   Batch B;
-  B.use_graph = o.use_graph != 0;
+  B.ext = ext;
+  B.ext_bytes = ext_bytes;
+  B.use_graph = o.use_graph != 0 && !ext;
   B.prec = o.precision;
   B.f32 = o.precision != PSDP_PREC_FP64;
   B.asm64.assign(count, 0);
   B.ir_max = o.ir_max >= 0 ? o.ir_max : (B.f32 ? 6 : 0);
-  B.prof.on = o.prof != nullptr;
+  B.prof.on = o.prof != nullptr && !ext;
   B.prof.st = st;
   B.prof.out = o.prof;
   Choice ch;
-  int rc = tune_choice(sdps, count, o, st, ch);
-  if (rc) return rc;
+  int rc = PSDP_OK;
+  if (ext) {
+    ch = default_choice(sdps, count);
+    for (int s = 0; s < count; ++s) {
+      if (o.asm_path >= 0) ch.pair[s] = sdps[s]->n * sdps[s]->n <= 128 && o.asm_path == 1;
+      if (o.solve_path >= 0) ch.small[s] = sdps[s]->Kpad / kNB <= kSmallP && o.solve_path == 1;
+    }
+  } else if ((rc = tune_choice(sdps, count, o, st, ch))) {
+    return rc;
+  }
   if ((rc = build_batch(B, sdps, count, &ch))) return rc;
   if ((rc = init_state(B, st))) return rc;
   std::vector<char> warm(count, 0);
@@ -1551,7 +1631,8 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
       r1[s].running = need[s];
     }
     B.any_phase1 = true;
-    PSDP_HIP(hipMemcpy(B.d_sys, B.sys.data(), B.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
+    PSDP_HIP(hipMemcpyAsync(B.d_sys, B.sys.data(), B.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice, st));
+    PSDP_HIP(hipStreamSynchronize(st));
     if ((rc = init_state(B, st))) return rc;
     std::vector<int> hf(count, 0);
     for (int s = 0; s < count; ++s) hf[s] = need[s] ? F_ACTIVE : 0;
@@ -1706,13 +1787,19 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
   return PSDP_OK;
 }
 
-int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res) {
+int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res, bool noalloc) {
   auto t0 = std::chrono::steady_clock::now();
   psdp_opts o;
   validate_opts(opts, o);
   if (o.warm_iter_cap < 0) return fail(PSDP_EINVAL, "warm_iter_cap < 0");
   if (!(o.warm_margin >= 0.0) || !(o.warm_margin < 1.0)) return fail(PSDP_EINVAL, "warm_margin not in [0, 1)");
-  int rc = solve_core(sdps, count, o, res, true);
+  char* ext = nullptr;
+  if (noalloc) {
+    void* p = nullptr;
+    if (int rc0 = scratch_ptr(&p)) return rc0;
+    ext = (char*)p;
+  }
+  int rc = solve_core(sdps, count, o, res, true, ext, kScratchBytes);
   if (rc) return rc;
   // rejected warm starts: solve again from the cold start
   std::vector<int> redo;
@@ -1727,7 +1814,7 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
       sub.push_back(sdps[s]);
       rr.push_back(res[s]);   // same caller buffers
     }
-    if ((rc = solve_core(sub.data(), (int)sub.size(), o, rr.data(), false))) return rc;
+    if ((rc = solve_core(sub.data(), (int)sub.size(), o, rr.data(), false, ext, kScratchBytes))) return rc;
     for (size_t i = 0; i < redo.size(); ++i) {
       const int wit = res[redo[i]].warm_iterations;
       res[redo[i]] = rr[i];

@@ -200,7 +200,8 @@ constexpr int kSG = 8;       // panels per group of the tiled triangular solves
 constexpr int kGS = kSG * kNB;   // rows of such a group
 
 // engine entry used by the public solve / eval calls
-int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res);
+int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res,
+                bool noalloc = false);
 int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y, double* Zi,
                 double* BTy, double* BX, double* Lam, double* LamL, double* sol,
                 hipStream_t stream);

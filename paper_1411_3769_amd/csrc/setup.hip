@@ -628,6 +628,11 @@ int psdp_ipm_solve(psdp_sdp* sdp, const psdp_opts* opts, psdp_result* res) {
   return solve_batch(&sdp, 1, opts, res);
 }
 
+int psdp_ipm_solve_noalloc(psdp_sdp* sdp, const psdp_opts* opts, psdp_result* res) {
+  if (!sdp || !res) return fail(PSDP_EINVAL, "NULL argument");
+  return solve_batch(&sdp, 1, opts, res, true);
+}
+
 int psdp_ipm_solve_batched(psdp_sdp* const* sdps, int count, const psdp_opts* opts,
                            psdp_result* res) {
   if (!sdps || !res || count < 1) return fail(PSDP_EINVAL, "bad batch arguments");

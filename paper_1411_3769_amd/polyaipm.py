@@ -99,7 +99,8 @@ _lib = None
 
 EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "psdp_polya_setup_batched",
            "psdp_query",
-           "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_eval_newton",
+           "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc",
+           "psdp_eval_newton",
            "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version",
            "psdp_mlp_create", "psdp_mlp_param_count", "psdp_mlp_set_params", "psdp_mlp_get_params",
            "psdp_mlp_forward", "psdp_mlp_loss_grad", "psdp_mlp_adam", "psdp_mlp_free"]
@@ -135,6 +136,7 @@ def load(path: str = LIB_PATH):
     lib.psdp_get_polya.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.psdp_ipm_solve.argtypes = [vp, C.POINTER(Opts), C.POINTER(CResult)]
     lib.psdp_ipm_solve_batched.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(Opts), C.POINTER(CResult)]
+    lib.psdp_ipm_solve_noalloc.argtypes = [vp, C.POINTER(Opts), C.POINTER(CResult)]
     lib.psdp_eval_newton.argtypes = [vp] * 10 + [vp]
     lib.psdp_eval_ladder.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double),
                                      C.POINTER(C.c_int)]
@@ -154,7 +156,7 @@ def load(path: str = LIB_PATH):
     lib.psdp_mlp_free.argtypes = [vp]
     lib.psdp_mlp_free.restype = None
     for name in ("psdp_polya_setup", "psdp_query", "psdp_get_polya", "psdp_ipm_solve",
-                 "psdp_ipm_solve_batched", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis",
+                 "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis",
                  "psdp_mlp_create", "psdp_mlp_set_params", "psdp_mlp_get_params", "psdp_mlp_forward",
                  "psdp_mlp_loss_grad", "psdp_mlp_adam"):
         getattr(lib, name).restype = C.c_int
@@ -442,6 +444,18 @@ def ipm_solve(sdp: SDP, warm_y=None, warm_logx=None, **opts) -> Result:
     o.warm_y, o.warm_logx = wy, wl
     _check(load().psdp_ipm_solve(sdp.handle, C.byref(o), arr))
     del wkeep
+    return _unpack(arr[0], P, y, lx, hist)
+
+
+def ipm_solve_noalloc(sdp: SDP, **opts) -> Result:
+    """psdp_ipm_solve_noalloc: Alg. 2 for one SDP with every device buffer in
+    the library's static scratch (no device allocation; eager launches on the
+    caller's stream)."""
+    o = make_opts(**opts)
+    cap = 512 if o.record_history else 0
+    arr = (CResult * 1)()
+    (P, y, lx, hist), = _prep_batch([sdp], cap, arr)
+    _check(load().psdp_ipm_solve_noalloc(sdp.handle, C.byref(o), arr))
     return _unpack(arr[0], P, y, lx, hist)
 
 
