@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n100", help="n100 | n10 | mixed512 | learned")
+    ap.add_argument("--workload", default="n100", help="n100 | n10 | mixed512 | learned | example2")
     ap.add_argument("--precision", default=None, help="fp64 | fp32 | bf16 (Schur assembly)")
     ap.add_argument("--form-steps", type=int, default=3,
                     help="n100: timed steps of each precision form (at most --steps)")
@@ -204,6 +204,8 @@ def main():
         del src, dst
     if args.workload == "learned":
         return bench_learned(args)
+    if args.workload == "example2":
+        return bench_example2(args)
     big = args.workload == "n100"
     prec = args.precision or ("fp32" if args.workload == "mixed512" else "fp64")
     systems, desc = workload(args.workload)
@@ -373,6 +375,61 @@ def quiet_gc():
     instead of torch's whole object graph, a pause of tens of milliseconds."""
     gc.collect()
     gc.freeze()
+
+
+def bench_example2(args):
+    """Section V, Example 2: the certified bound on L (the smallest L with
+    stability on S_L = {sum x = 2L + 1, L <= x_i <= 1}) by bisection over
+    the translated simplices, Polya degrees dp = 2, d = 4, bracket [-0.5, 0.5]
+    to 1e-3.  One step = one whole bisection (set-up and solve of every trial
+    on the device, 8 trials per round in one batch); the oracle runs the same
+    bisection with one trial per round."""
+    import numpy as np
+    import torch
+    from paper_1411_3769_amd import polyaipm as P
+    vals = []
+    with open(os.path.join(ROOT, "tests", "golden", "example2_matrices.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                vals.append([float(v) for v in line.split()])
+    mats = np.array(vals).reshape(6, 3, 3)
+    # A(x) = A1 x1^3 + A2 x1^2 x2 + A3 x1 x2 x3 + A4 x1 x3^2 + A5 x2^3 + A6 x3^3 on
+    # x = G(L) alpha, G(L) = I + L (11^T - I), which maps the simplex onto S_L
+    exps = [(3, 0, 0), (2, 1, 0), (1, 1, 1), (1, 0, 2), (0, 3, 0), (0, 0, 3)]
+    G0, G1 = np.eye(3), np.ones((3, 3)) - np.eye(3)
+    dp, d, tol, width = 2, 4, 1e-3, 8
+    run = lambda: P.bisect_simplex(exps, mats, G0, G1, 3, dp, d, 0.5, -0.5, tol, width=width)
+    for _ in range(args.warmup):
+        run()
+    quiet_gc()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = run()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    line = {
+        "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "the paper's printed Example 2 matrices",
+        "config": {"workload": f"Example 2 bisection, dp={dp} d={d}, tol {tol}, {width} trials per round",
+                   "L_certified": r.t_cert, "L_bracket_other": r.t_other, "trials": len(r.trials),
+                   "paper_L_opt": -0.111},
+        "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP64, "unit": "TFLOP/s", "frac": None,
+                     "traffic": None},
+    }
+    if not args.no_cpu:
+        from oracle import stability as St
+        th = host_threads()
+        with _limits(th):
+            t0 = time.perf_counter()
+            o = St.bisect_simplex(exps, mats, G0, G1, 3, dp, d, 0.5, -0.5, tol)
+            el = time.perf_counter() - t0
+        line["cpu_baseline"] = dict(value=el, unit="s", cores=th, kind="oracle",
+                                    sample=f"the oracle's whole bisection ({len(o.trials)} trials, one per "
+                                           f"round; certified L {o.t_cert:.6f})")
+    print(json.dumps(line))
 
 
 def bench_learned(args):

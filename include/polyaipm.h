@@ -192,6 +192,10 @@ typedef struct {
                              /* (then x100 on failure), 0 (default) = unshifted first  */
     int    stop_rule;        /* PSDP_STOP_* (RELATIVE)                                  */
     int    sigma_rule;       /* PSDP_SIGMA_* (FIXED)                                    */
+    int    chol_panels;      /* Schur Cholesky: 64-wide panels per super-panel, whose   */
+                             /* trailing update is one pass of depth 64 chol_panels     */
+                             /* (1..32); 0 (default) = chosen per tile-count bucket by  */
+                             /* the autotuner among 4, 8 and 16                         */
 } psdp_opts;
 
 typedef struct {
@@ -240,6 +244,7 @@ typedef struct {
                             /* two or three captured graphs (0: every kernel launched */
                             /* eagerly; the same count in every result of a batch)    */
     int     phase1_reason;  /* exit reason (PSDP_R_*) of the phase-I run, -1 if none  */
+    int     chol_panels;    /* super-panel width the Schur Cholesky used             */
 } psdp_result;
 
 /* Defaults for the option structs. */
@@ -357,6 +362,53 @@ int psdp_eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psd
  * so that Schur tiles are contiguous.
  */
 int psdp_basis(const psdp_sdp* sdp, int* pairs);
+
+/*
+ * psdp_poly_on_simplex -- the homogeneous representation of Section II and
+ * the translated simplices of Section V (Examples 1 and 2).  A is given as
+ * count terms A(x) = sum_t mats[t] x^exps[t] in lx variables x (any degrees
+ * <= da, a constant term allowed): exps [count][lx] int, mats [count][n][n]
+ * FP64 row-major.  G [lx][l] row-major maps the unit simplex onto the region
+ * of interest, x = G alpha (NULL: the identity, lx = l).  out [f(l,da)][n][n]
+ * receives the coefficients, on W_da in descending lexicographic order, of
+ *   B(alpha) = sum_t (sum_j alpha_j)^(da - |exps[t]|) mats[t] (G alpha)^exps[t],
+ * a homogeneous polynomial equal to A(G alpha) on Delta_l: the A argument
+ * psdp_polya_setup takes with psdp_setup_opts.da = da.  Host memory only;
+ * no device work.  EINVAL: NULL or non-positive sizes, a negative exponent,
+ * a term of degree above da, non-finite input; EOVERFLOW: da > 20.
+ */
+int psdp_poly_on_simplex(int n, int lx, int count, const int* exps, const double* mats, int l,
+                         const double* G, int da, double* out);
+
+typedef struct {
+    double t;           /* parameter value tried                                  */
+    int    verdict;     /* PSDP_FEASIBLE / INFEASIBLE / UNKNOWN                   */
+    int    iterations;  /* IPM iterations of that trial (paper run + phase-I)     */
+    double margin;      /* certificate margin (NaN without a certificate)         */
+} psdp_bisect_rec;
+
+/*
+ * psdp_bisect_simplex -- the bisection of Section V (Example 1: the largest
+ * rho; Example 2: the smallest L) over regions x = G(t) alpha, alpha in the
+ * unit simplex, G(t) = G0 + t G1 (both [lx][l] row-major).  For every trial t
+ * the system A on the region becomes B = psdp_poly_on_simplex(A, G(t)), whose
+ * Polya SDP at (dp, d) is set up and solved on the device (setup options so
+ * or NULL, its da replaced by A's degree; solver options opts or NULL).  t_feas
+ * is tried first; if it has no certificate, *t_cert = NaN.  Otherwise each
+ * round solves `width` trial values splitting the bracket [t_cert, t_other]
+ * evenly as one batch, moves t_cert to the last certified value before the
+ * first trial without a certificate (FEASIBLE only: UNKNOWN counts as none)
+ * and t_other to that trial, until |t_cert - t_other| <= tol.  On return
+ * *t_cert is the certified end (stability is proved on its region) and
+ * *t_other the other end of the final bracket.  recs (caller buffer of
+ * rec_cap records, or NULL with rec_cap = 0) receives the trials in order,
+ * *nrec their number.  width in [1, 64] (1: plain bisection).
+ */
+int psdp_bisect_simplex(int n, int lx, int count, const int* exps, const double* mats, int l,
+                        const double* G0, const double* G1, int dp, int d, double t_feas,
+                        double t_infeas, double tol, int width, const psdp_setup_opts* so,
+                        const psdp_opts* opts, double* t_cert, double* t_other, psdp_bisect_rec* recs,
+                        int rec_cap, int* nrec);
 
 /* Release a handle (NULL is ignored).  Device memory of a batched set-up
  * is returned with the last handle of that call. */

@@ -19,6 +19,10 @@ IEEE TAC 2013):
   Alg. 2 with the readings listed in the design notes, the line-search
   ladder, the certificate check, the Farkas ray rule and the phase-I margin
   SDP; plus a dense textbook primal-dual solver used to check Theorem 3.
+* ``stability``  the homogeneous representation of A on a translated
+  simplex (Section II and the regions of Section V, Examples 1 and 2) and
+  the bisection over the region's size; a brute-force spectral boundary.
+* ``mlp``    the FP64 network of the learned warm start.
 
 Parity pins live under ``tests/`` (marker ``not gpu``).  Functions whose
 result is not pinned by an independent fact say so in their docstring

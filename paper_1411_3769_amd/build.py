@@ -27,6 +27,7 @@ SOURCES = {
     "chol.hip": [],
     "engine.hip": [],
     "mlp.hip": [],
+    "simplex.hip": [],
 }
 
 COMMON = [

@@ -15,14 +15,15 @@
 //   diag   : one workgroup per system factors the 64 x 64 diagonal tile and
 //            inverts the factor (L_pp, L_pp^{-1} stored);
 //   trsm   : one workgroup per tile row i > p forms L_ip = A_ip L_pp^{-T};
-//   update : two levels.  Panels are grouped in super-panels of kSW (the
+//   update : two levels.  Panels are grouped in super-panels of sw (the
 //            last one absorbs a shorter remainder); inside one, each tile
 //            (i, j) with p < j <= (end of the super-panel) gets
 //            A_ij -= L_ip L_jp^T right away (narrow update, depth 64), and
 //            the workgroup of tile (p+1, p+1) goes on to the diagonal step
 //            of p + 1; after the super-panel's last panel, every tile right
 //            of it gets the super-panel's whole contribution in one pass of
-//            depth 64 kSW (wide update).  Both on FP64 MFMA.
+//            depth 64 sw (wide update).  Both on FP64 MFMA.  sw is chosen
+//            per system (the autotuner times 4, 8 and 16).
 // Steps are launched for the whole batch; a (step, system) table maps
 // workgroups to systems.  Triangular solves use the stored inverses, so the
 // diagonal solves are matrix-vector products.
@@ -388,40 +389,73 @@ __global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__
   if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
 }
 
-// Wide update at the end of a super-panel of kSW panels (p = its last
+// Wide update at the end of a super-panel of sw panels (p = its last
 // panel): A_ij -= sum over the super-panel's panels q of L_iq L_jq^T for every
-// tile pair right of it (depth 64 kSW), on 128 x 128 output blocks (2 x 2
+// tile pair right of it (depth 64 sw), on 128 x 128 output blocks (2 x 2
 // tiles; wave w owns the 64 x 64 quadrant (w/2, w%2) as 4 x 4 MFMA tiles).
-// The depth is staged through two LDS buffers 32 columns at a time, the
-// chunk after next prefetched into registers.  Only the lower triangle
-// (column <= row) of the matrix is written; rows or columns past Kpad are
-// skipped.
-constexpr int kWT = 128, kWK = 32, kWLD = kWK + 1;
+// The depth is staged through two LDS buffers 16 columns at a time, the
+// chunk after next prefetched into registers; 70 KB of LDS and at most 256
+// registers per lane let two workgroups share a compute unit.  Only the
+// lower triangle (column <= row) of the matrix is written; rows or columns
+// past Kpad are skipped.
+//
+// Block order: the dispatcher hands consecutive workgroups to the eight
+// XCDs in turn, so workgroup b is renumbered to give each XCD one
+// contiguous range of the block list; the list walks groups of kWG block
+// rows column by column, so that an XCD's L2 keeps the group's row panels
+// while each column panel is read once per group.
+constexpr int kWT = 128, kWK = 16, kWLD = kWK + 1;
 constexpr int kWRP = 256 / kWK;          // rows staged per pass
 constexpr int kWU = kWT / kWRP;          // passes (values per thread and operand)
+constexpr int kWG = 4;                   // block rows per group of the block order
+constexpr int kXCD = 8;                  // XCDs of the device
 
-__global__ void __launch_bounds__(256) k_chol_update_wide(const SysDesc* __restrict__ sys,
-                                                          const int* __restrict__ flags, double* Lam,
-                                                          const int* __restrict__ st_sys,
-                                                          const int* __restrict__ st_pre, int cnt,
-                                                          int p) {
+// (bi, bj), bj <= bi < nb, of position t of the grouped block order
+__device__ inline void wide_block(int t, int nb, int& bi, int& bj) {
+  // group k holds rows k kWG .. k kWG + kWG - 1; kWG k (kWG k + 1) / 2 blocks precede it
+  int k = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5) / kWG;
+  while (k > 0 && (kWG * k) * (kWG * k + 1) / 2 > t) --k;
+  while ((kWG * (k + 1)) * (kWG * (k + 1) + 1) / 2 <= t) ++k;
+  const int r0 = kWG * k, r1 = min(r0 + kWG, nb) - 1, h = r1 - r0 + 1;
+  int u = t - r0 * (r0 + 1) / 2;
+  if (u < (r0 + 1) * h) {   // columns 0 .. r0: every row of the group
+    bj = u / h;
+    bi = r0 + u % h;
+    return;
+  }
+  u -= (r0 + 1) * h;        // column r0 + j holds the rows r0 + j .. r1
+  int j = 1;
+  while (u >= h - j) {
+    u -= h - j;
+    ++j;
+  }
+  bj = r0 + j;
+  bi = bj + u;
+}
+
+__global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __restrict__ sys,
+                                                             const int* __restrict__ flags, double* Lam,
+                                                             const int* __restrict__ st_sys,
+                                                             const int* __restrict__ st_pre, int cnt,
+                                                             int p) {
   __shared__ double sa[2][kWT * kWLD];   // two stages: one is multiplied while
   __shared__ double sb[2][kWT * kWLD];   // the next is written
-  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int total = gridDim.x, per = total / kXCD, rem = total % kXCD;
+  const int xcd = blockIdx.x % kXCD;
+  const int g = xcd * per + min(xcd, rem) + blockIdx.x / kXCD;
+  const int si = find_owner(st_pre, cnt, g);
   const int s = st_sys[si];
-  const int t = blockIdx.x - st_pre[si];
+  const int t = g - st_pre[si];
   if (!(flags[s] & F_CHOLSEL)) return;
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
   double* A = Lam + sd.loff;
-  int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-  while (bi * (bi + 1) / 2 > t) --bi;
-  const int bj = t - bi * (bi + 1) / 2;
+  int bi, bj;
+  wide_block(t, (sd.P - p - 1 + 1) / 2, bi, bj);
   const int q0 = p + 1;
   const int r0 = kNB * (q0 + 2 * bi), c0 = kNB * (q0 + 2 * bj);
   const int nmax = sd.Kpad;
-  const int d0 = kNB * (p - kSW + 1), D = kNB * kSW;
+  const int d0 = kNB * (p - sd.sw + 1), D = kNB * sd.sw;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int r16 = lane & 15, kq = lane >> 4;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;

@@ -287,6 +287,7 @@ struct Batch {
   bool any_phase1 = false;
   bool use_graph = false;   // replay each iteration's launches from hipGraphs
   std::vector<char> use_pair, use_small;   // kernel paths per system
+  std::vector<int> use_sw;
   bool f32 = false;   // precision form: reduced-precision Schur assembly + refinement
   int prec = PSDP_PREC_FP64;
   int ir_max = 0;
@@ -351,6 +352,7 @@ static size_t tabsize(const std::vector<T>& v) {
 // of kSG tiles.
 struct Choice {
   std::vector<char> pair, small;
+  std::vector<int> sw;   // Schur Cholesky panels per super-panel
 };
 
 static Choice default_choice(psdp_sdp* const* sdps, int count) {
@@ -358,6 +360,7 @@ static Choice default_choice(psdp_sdp* const* sdps, int count) {
   for (int s = 0; s < count; ++s) {
     c.pair.push_back(sdps[s]->n * sdps[s]->n <= 128);
     c.small.push_back(sdps[s]->Kpad / kNB <= kSmallP);
+    c.sw.push_back(kSW);
   }
   return c;
 }
@@ -372,6 +375,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   }
   B.use_pair = ch->pair;
   B.use_small = ch->small;
+  B.use_sw = ch->sw;
   B.S = count;
   B.sd.assign(sdps, sdps + count);
   // ---- per-system layout
@@ -390,6 +394,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     SysDesc d{};
     d.n = n; d.L0 = p->L0; d.L = p->L; d.M = p->M; d.Nt = p->Nt; d.nb = p->nb;
     d.K = (int)p->K; d.Kpad = (int)p->Kpad; d.P = d.Kpad / kNB; d.mode = 0;
+    d.sw = ch->sw[s];
     d.blk0 = (int)H.blk.size();
     d.boff = curblk;
     for (int j = 0; j < p->nb; ++j) {
@@ -606,27 +611,28 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.wide.add_step();
 
     // last column of the narrow update of step q (super-panel end; a
-    // super-panel followed by fewer than kSW panels absorbs them, since
+    // super-panel followed by fewer than sw panels absorbs them, since
     // their wide update would be one long, nearly empty launch)
-    auto sp_end = [](int P, int q) {
-      const int se = (q / kSW) * kSW + kSW - 1;
-      return P - 1 - se < kSW ? P - 1 : se;
+    auto sp_end = [](int P, int q, int sw) {
+      const int se = (q / sw) * sw + sw - 1;
+      return P - 1 - se < sw ? P - 1 : se;
     };
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (P <= pstep) continue;
       // after a narrow update of step pstep - 1 its workgroup of tile
       // (pstep, pstep) has already factored the diagonal tile
-      if (pstep == 0 || sp_end(P, pstep - 1) < pstep) B.pan.add(s, 1);
+      const int sw = B.sys[s].sw;
+      if (pstep == 0 || sp_end(P, pstep - 1, sw) < pstep) B.pan.add(s, 1);
       const int T = P - pstep - 1;
       if (T > 0) B.trs.add(s, T);
       // narrow update: columns p+1 .. end of the super-panel
-      const int se = sp_end(P, pstep);
+      const int se = sp_end(P, pstep, sw);
       int nn = 0;
       for (int j = pstep + 1; j <= se; ++j) nn += P - j;
       if (nn > 0) B.upd.add(s, nn);
       // wide update after the super-panel's last panel
-      if (pstep == se && pstep % kSW == kSW - 1 && pstep < P - 1) {
+      if (pstep == se && pstep % sw == sw - 1 && pstep < P - 1) {
         const int nb2 = (P - pstep - 1 + 1) / 2;
         B.wide.add(s, nb2 * (nb2 + 1) / 2);
       }
@@ -1441,21 +1447,33 @@ static int trial_batch(Batch& T, psdp_sdp* const* sub, int cnt, const Choice& c,
   return PSDP_OK;
 }
 
+// bucket of the super-panel width choice: Schur tile counts 8..15, 16..31,
+// ... share one (below 8 tiles the width makes no difference)
+static int sw_bucket(int P) {
+  if (P < 8) return 0;
+  int b = 0;
+  while ((P >> (b + 1)) > 0) ++b;
+  return b;
+}
+
 static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hipStream_t st,
                        Choice& ch) {
   ch = default_choice(sdps, count);
+  if (o.chol_panels > 0)
+    for (int s = 0; s < count; ++s) ch.sw[s] = o.chol_panels;
   for (int s = 0; s < count; ++s) {
     const bool can_pair = sdps[s]->n * sdps[s]->n <= 128;
     const bool can_small = sdps[s]->Kpad / kNB <= kSmallP;
     if (o.asm_path >= 0) ch.pair[s] = can_pair && o.asm_path == 1;
     if (o.solve_path >= 0) ch.small[s] = can_small && o.solve_path == 1;
   }
-  for (int kind = 0; kind < 2; ++kind) {
-    if ((kind == 0 ? o.asm_path : o.solve_path) >= 0) continue;
+  for (int kind = 0; kind < 3; ++kind) {
+    if ((kind == 0 ? o.asm_path : kind == 1 ? o.solve_path : o.chol_panels) >= (kind == 2 ? 1 : 0)) continue;
     std::map<int, std::vector<int>> want;   // key -> systems
     for (int s = 0; s < count; ++s) {
-      const int key = kind == 0 ? sdps[s]->n : (int)(sdps[s]->Kpad / kNB);
-      const bool able = kind == 0 ? key * key <= 128 : key <= kSmallP;
+      const int P = (int)(sdps[s]->Kpad / kNB);
+      const int key = kind == 0 ? sdps[s]->n : kind == 1 ? P : sw_bucket(P);
+      const bool able = kind == 0 ? key * key <= 128 : kind == 1 ? key <= kSmallP : key > 0;
       if (!able) continue;
       {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1467,23 +1485,36 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
       std::vector<psdp_sdp*> sub;
       for (int s : kv.second) sub.push_back(sdps[s]);
       const int cnt = (int)sub.size();
-      float t[2] = {0.f, 0.f};
-      for (int v = 0; v < 2; ++v) {
+      // candidates: the two paths (kinds 0, 1) or super-panel widths (kind 2)
+      static const int widths[3] = {4, 8, 16};
+      const int nv = kind == 2 ? 3 : 2;
+      float t[3] = {0.f, 0.f, 0.f};
+      for (int v = 0; v < nv; ++v) {
         Choice c = default_choice(sub.data(), cnt);
-        for (int i = 0; i < cnt; ++i) (kind == 0 ? c.pair : c.small)[i] = (char)v;
+        for (int i = 0; i < cnt; ++i) {
+          if (kind == 0) c.pair[i] = (char)v;
+          else if (kind == 1) c.small[i] = (char)v;
+          else c.sw[i] = widths[v];
+        }
         Batch T;
         if (int rc = trial_batch(T, sub.data(), cnt, c, st)) return rc;
         if (kind == 0) {
           t[v] = time_ms(st, 3, [&]() { op_schur(T, st); });
-        } else {
+        } else if (kind == 1) {
           op_schur(T, st);
           op_factor(T, st);
           t[v] = time_ms(st, 3, [&]() { op_solve(T, st, T.rv1, T.dyh); });
+        } else {
+          // the assembly restores the matrix the factorisation overwrites
+          t[v] = time_ms(st, 2, [&]() { op_schur(T, st); op_factor(T, st); });
         }
         PSDP_HIP(hipGetLastError());
       }
+      int best = 0;
+      for (int v = 1; v < nv; ++v)
+        if (t[v] < t[best]) best = v;
       std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune[{kind, kv.first}] = t[1] <= t[0] ? 1 : 0;
+      g_tune[{kind, kv.first}] = kind == 2 ? widths[best] : (t[1] <= t[0] ? 1 : 0);
     }
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1496,6 +1527,10 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
     if (o.solve_path < 0 && P <= kSmallP) {
       auto it = g_tune.find({1, P});
       if (it != g_tune.end()) ch.small[s] = it->second;
+    }
+    if (o.chol_panels <= 0 && sw_bucket(P) > 0) {
+      auto it = g_tune.find({2, sw_bucket(P)});
+      if (it != g_tune.end()) ch.sw[s] = it->second;
     }
   }
   return PSDP_OK;
@@ -1550,6 +1585,8 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     return fail(PSDP_EINVAL, "invalid stop_rule");
   if (o.sigma_rule != PSDP_SIGMA_FIXED && o.sigma_rule != PSDP_SIGMA_MEHROTRA)
     return fail(PSDP_EINVAL, "invalid sigma_rule");
+  if (o.chol_panels < 0 || o.chol_panels > 32)
+    return fail(PSDP_EINVAL, "chol_panels must lie in [0, 32]");
   // all work runs on a private stream (capturable into graphs) ordered
   // after the caller's stream; the allocation-free solve uses the caller's
   SolveStream ss;
@@ -1576,6 +1613,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     for (int s = 0; s < count; ++s) {
       if (o.asm_path >= 0) ch.pair[s] = sdps[s]->n * sdps[s]->n <= 128 && o.asm_path == 1;
       if (o.solve_path >= 0) ch.small[s] = sdps[s]->Kpad / kNB <= kSmallP && o.solve_path == 1;
+      if (o.chol_panels > 0) ch.sw[s] = o.chol_panels;
     }
   } else if ((rc = tune_choice(sdps, count, o, st, ch))) {
     return rc;
@@ -1728,6 +1766,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     R.chol_shifts = r.shifts + (need[s] ? r1[s].shifts : 0);
     R.graph_replays = B.graph_launches;
     R.phase1_reason = need[s] ? r1[s].reason : -1;
+    R.chol_panels = B.use_sw[s];
     R.asm_path = B.use_pair[s] && p->n * p->n <= 128;
     R.solve_path = B.use_small[s] && d.P <= kSmallP;
     R.label_iter = r.label_iter;

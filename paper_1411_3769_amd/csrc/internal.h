@@ -17,7 +17,7 @@ constexpr int kMaxN = 128;   // largest block order held whole in LDS (128 KB)
 constexpr int kTB = 8;       // index-group size of the tiled basis
 constexpr int kNB = 64;      // Schur Cholesky tile
 constexpr int kPairGrid = 1024;   // workgroups of the whole-pair assembly (grid-stride)
-constexpr int kSW = 8;       // Cholesky panels per super-panel (depth of the wide update / 64)
+constexpr int kSW = 8;       // default Cholesky panels per super-panel (depth of the wide update / 64)
 constexpr int kMaxDeg = 20;  // largest multinomial degree (20! < 2^63)
 constexpr int kNSC = 32;     // per-system scalar slots
 
@@ -67,6 +67,7 @@ constexpr double kIrSwitch = 1e-1;
 struct SysDesc {
   int n, L0, L, M, Nt, nb, P, mode;   // P = Kpad / kNB; mode 0 paper SDP, 1 phase-I
   int K, Kpad, blk0, npairs_hm;
+  int sw, spare;    // Schur Cholesky: panels per super-panel (wide update depth 64 sw)
   int64_t boff;     // block arena offset (doubles) of the system's first block
   int64_t voff;     // vector offset (Kpad entries per vector)
   int64_t loff;     // Schur matrix offset (Kpad * Kpad)

@@ -291,6 +291,7 @@ void psdp_opts_default(psdp_opts* o) {
   o->chol_shift_force = 0.0;
   o->stop_rule = PSDP_STOP_RELATIVE;
   o->sigma_rule = PSDP_SIGMA_FIXED;
+  o->chol_panels = 0;
 }
 
 const char* psdp_last_error(void) { return g_err.c_str(); }

@@ -63,7 +63,8 @@ class Opts(C.Structure):
                 ("warm_margin", C.c_double), ("warm_center", C.c_int), ("asm_path", C.c_int),
                 ("solve_path", C.c_int), ("use_graph", C.c_int),
                 ("label_gap", C.c_double), ("chol_shift_max", C.c_double),
-                ("chol_shift_force", C.c_double), ("stop_rule", C.c_int), ("sigma_rule", C.c_int)]
+                ("chol_shift_force", C.c_double), ("stop_rule", C.c_int), ("sigma_rule", C.c_int),
+                ("chol_panels", C.c_int)]
 
 
 class IterRec(C.Structure):
@@ -86,7 +87,12 @@ class CResult(C.Structure):
                 ("label_iter", C.c_int),
                 ("asm_path", C.c_int), ("solve_path", C.c_int),
                 ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int),
-                ("chol_shifts", C.c_int), ("graph_replays", C.c_int), ("phase1_reason", C.c_int)]
+                ("chol_shifts", C.c_int), ("graph_replays", C.c_int), ("phase1_reason", C.c_int),
+                ("chol_panels", C.c_int)]
+
+
+class BisectRec(C.Structure):
+    _fields_ = [("t", C.c_double), ("verdict", C.c_int), ("iterations", C.c_int), ("margin", C.c_double)]
 
 
 class PsdpError(RuntimeError):
@@ -100,7 +106,7 @@ _lib = None
 EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "psdp_polya_setup_batched",
            "psdp_query",
            "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc",
-           "psdp_eval_newton",
+           "psdp_eval_newton", "psdp_poly_on_simplex", "psdp_bisect_simplex",
            "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version",
            "psdp_mlp_create", "psdp_mlp_param_count", "psdp_mlp_set_params", "psdp_mlp_get_params",
            "psdp_mlp_forward", "psdp_mlp_loss_grad", "psdp_mlp_adam", "psdp_mlp_free"]
@@ -137,6 +143,11 @@ def load(path: str = LIB_PATH):
     lib.psdp_ipm_solve.argtypes = [vp, C.POINTER(Opts), C.POINTER(CResult)]
     lib.psdp_ipm_solve_batched.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(Opts), C.POINTER(CResult)]
     lib.psdp_ipm_solve_noalloc.argtypes = [vp, C.POINTER(Opts), C.POINTER(CResult)]
+    lib.psdp_poly_on_simplex.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp]
+    lib.psdp_bisect_simplex.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, C.c_int, C.c_int,
+                                        C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(SetupOpts),
+                                        C.POINTER(Opts), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(BisectRec), C.c_int, C.POINTER(C.c_int)]
     lib.psdp_eval_newton.argtypes = [vp] * 10 + [vp]
     lib.psdp_eval_ladder.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double),
                                      C.POINTER(C.c_int)]
@@ -156,7 +167,8 @@ def load(path: str = LIB_PATH):
     lib.psdp_mlp_free.argtypes = [vp]
     lib.psdp_mlp_free.restype = None
     for name in ("psdp_polya_setup", "psdp_query", "psdp_get_polya", "psdp_ipm_solve",
-                 "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis",
+                 "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc", "psdp_poly_on_simplex",
+                 "psdp_bisect_simplex", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis",
                  "psdp_mlp_create", "psdp_mlp_set_params", "psdp_mlp_get_params", "psdp_mlp_forward",
                  "psdp_mlp_loss_grad", "psdp_mlp_adam"):
         getattr(lib, name).restype = C.c_int
@@ -357,6 +369,7 @@ class Result:
     chol_shifts: int = 0
     graph_replays: int = 0
     phase1_reason: int = -1
+    chol_panels: int = 0
 
     @property
     def verdict_name(self):
@@ -429,7 +442,7 @@ def _unpack(r: CResult, P, y, lx, hist) -> Result:
                   r.ir_steps, r.ir_eta_max, bool(r.warm_used), bool(r.warm_fallback),
                   r.warm_iterations, lx[0], lx[1] if r.label_iter >= 0 else None,
                   lx[2] if r.label_iter >= 0 else None, r.label_iter, r.asm_path, r.solve_path, h,
-                  r.chol_shifts, r.graph_replays, r.phase1_reason)
+                  r.chol_shifts, r.graph_replays, r.phase1_reason, r.chol_panels)
 
 
 def ipm_solve(sdp: SDP, warm_y=None, warm_logx=None, **opts) -> Result:
@@ -495,6 +508,60 @@ def eval_ladder(sdp: SDP, V: np.ndarray, dV: np.ndarray, **opts):
     k = C.c_int()
     _check(load().psdp_eval_ladder(sdp.handle, _ptr(V), _ptr(dV), C.byref(o), C.byref(step), C.byref(k)))
     return step.value, k.value
+
+
+def _terms(exps, mats):
+    exps = np.ascontiguousarray(exps, dtype=np.int32)
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    if exps.ndim != 2 or mats.ndim != 3 or mats.shape[0] != exps.shape[0] or mats.shape[1] != mats.shape[2]:
+        raise ValueError("exps [count][lx] and mats [count][n][n] expected")
+    return exps, mats
+
+
+def poly_on_simplex(exps, mats, G, l: int, da: int) -> np.ndarray:
+    """psdp_poly_on_simplex: coefficients [f(l, da)][n][n] of the homogeneous
+    B(alpha) equal to A(G alpha) on the simplex (G = None: identity)."""
+    from math import comb
+    exps, mats = _terms(exps, mats)
+    count, lx = exps.shape
+    n = mats.shape[1]
+    Gm = None if G is None else np.ascontiguousarray(G, dtype=np.float64)
+    if Gm is not None and Gm.shape != (lx, l):
+        raise ValueError(f"G must be [{lx}][{l}]")
+    out = np.zeros((comb(l + da - 1, l - 1), n, n))
+    _check(load().psdp_poly_on_simplex(n, lx, count, _ptr(exps), _ptr(mats), l, _ptr(Gm), da, _ptr(out)))
+    return out
+
+
+@dataclass
+class BisectResult:
+    t_cert: float
+    t_other: float
+    trials: list
+
+
+def bisect_simplex(exps, mats, G0, G1, l: int, dp: int, d: int, t_feas: float, t_infeas: float,
+                   tol: float, width: int = 1, delta: float = 1e-3, eps: float = 1e-3, **opts) -> BisectResult:
+    """psdp_bisect_simplex: certified end of the bracket over regions
+    x = (G0 + t G1) alpha; trials as (t, verdict, iterations, margin)."""
+    exps, mats = _terms(exps, mats)
+    count, lx = exps.shape
+    n = mats.shape[1]
+    G0 = np.ascontiguousarray(G0, dtype=np.float64)
+    G1 = np.ascontiguousarray(G1, dtype=np.float64)
+    lib = load()
+    so = SetupOpts()
+    lib.psdp_setup_opts_default(C.byref(so))
+    so.delta, so.eps = delta, eps
+    o = make_opts(**opts)
+    cap = 1024
+    recs = (BisectRec * cap)()
+    tc, to, nr = C.c_double(), C.c_double(), C.c_int()
+    _check(lib.psdp_bisect_simplex(n, lx, count, _ptr(exps), _ptr(mats), l, _ptr(G0), _ptr(G1), dp, d,
+                                   t_feas, t_infeas, tol, width, C.byref(so), C.byref(o), C.byref(tc),
+                                   C.byref(to), recs, cap, C.byref(nr)))
+    trials = [(recs[i].t, recs[i].verdict, recs[i].iterations, recs[i].margin) for i in range(nr.value)]
+    return BisectResult(tc.value, to.value, trials)
 
 
 def version() -> str:
