@@ -879,6 +879,17 @@ static void op_schur(Batch& B, hipStream_t st) {
   }
 }
 
+// inverses of the factor's diagonal blocks used by the grouped solves (timed
+// with the solves)
+static void op_ginv(Batch& B, hipStream_t st) {
+  if (B.gin.tot[0] > 0) {
+    const size_t m0 = B.prof.mark();
+    launch_trsv_ginv(st, B.d_sys, B.d_flags, B.d_gin_sys, B.d_gin_pre, B.gin.cnt[0], B.gin.tot[0], B.Lam,
+                     B.Linv, B.Ginv);
+    B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());
+  }
+}
+
 static void op_factor(Batch& B, hipStream_t st) {
   for (int p = 0; p < B.maxP; ++p) {
     const int f = B.pan.first[p];
@@ -901,13 +912,7 @@ static void op_factor(Batch& B, hipStream_t st) {
     }
     if (B.upd.tot[p] > 0 || B.wide.tot[p] > 0) B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
   }
-  // inverses of the diagonal blocks of the grouped solves (timed with them)
-  if (B.gin.tot[0] > 0) {
-    const size_t m0 = B.prof.mark();
-    launch_trsv_ginv(st, B.d_sys, B.d_flags, B.d_gin_sys, B.d_gin_pre, B.gin.cnt[0], B.gin.tot[0], B.Lam,
-                     B.Linv, B.Ginv);
-    B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());
-  }
+  op_ginv(B, st);
 }
 
 static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
@@ -1501,9 +1506,15 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
         if (kind == 0) {
           t[v] = time_ms(st, 3, [&]() { op_schur(T, st); });
         } else if (kind == 1) {
+          // one iteration's share of the path: the grouped path's block
+          // inverses and both Newton solves
           op_schur(T, st);
           op_factor(T, st);
-          t[v] = time_ms(st, 3, [&]() { op_solve(T, st, T.rv1, T.dyh); });
+          t[v] = time_ms(st, 3, [&]() {
+            op_ginv(T, st);
+            op_solve(T, st, T.rv1, T.dyh);
+            op_solve(T, st, T.rv2, T.dyb);
+          });
         } else {
           // the assembly restores the matrix the factorisation overwrites
           t[v] = time_ms(st, 2, [&]() { op_schur(T, st); op_factor(T, st); });

@@ -1332,7 +1332,7 @@ __global__ void __launch_bounds__(512) k_assemble_pair_1wg(const AsmTile* __rest
 // the four are added into an LDS tile in (p,q) x (r,s) order (Q3/Q4 only for
 // p != q, Q2/Q4 only for r != s).
 template <int PR>
-__global__ void __launch_bounds__(256) k_assemble_grp(const AsmTile* __restrict__ tiles,
+__global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restrict__ tiles,
                                                       const KTerm* __restrict__ terms,
                                                       const SysDesc* __restrict__ sys,
                                                       const int* __restrict__ flags,
