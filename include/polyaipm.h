@@ -348,6 +348,16 @@ int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const doub
                      double* sol, void* stream);
 
 /*
+ * The Schur complement Omega (Alg. 2 eq. T2) assembled at a fixed iterate in
+ * the arithmetic of a precision form (PSDP_PREC_*: FP64, or block products
+ * rounded to FP32 / BF16 with FP32 accumulation), for measuring the reduced
+ * forms' error.  X, Z: host [L+M][n][n] symmetric positive definite; Lam:
+ * host [K][K] (full symmetric; the library's dual order, see psdp_basis).
+ */
+int psdp_eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, double* Lam,
+                    void* stream);
+
+/*
  * Step-length ladder of the line search on fixed blocks (host buffers
  * [L+M][n][n]): largest r_k = rho^k (k <= ladder_len) such that
  * V_j + (r_k / step_frac) dV_j passes Cholesky for every block j.

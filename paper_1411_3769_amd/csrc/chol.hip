@@ -465,14 +465,15 @@ __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __re
   auto load = [&](int kc) {
 #pragma unroll
     for (int u = 0; u < kWU; ++u) {
-      // rows past Kpad (second half of an edge block) read a valid row and
-      // are zeroed, so the loads need no branches
+      // rows past Kpad (second half of an edge block) read the last row
+      // instead, so the loads need no branches; what they contribute lands
+      // only in rows or columns of the block that are not stored.  Nothing
+      // uses the values before they are staged one chunk later, so the
+      // loads stay in flight across the chunk's products.
       const int row = lr + kWRP * u;
       const int ra_r = min(r0 + row, nmax - 1), rb_r = min(c0 + row, nmax - 1);
-      const double va = A[(int64_t)ra_r * ld + d0 + kc + lk];
-      const double vb = A[(int64_t)rb_r * ld + d0 + kc + lk];
-      ra[u] = r0 + row < nmax ? va : 0.0;
-      rb[u] = c0 + row < nmax ? vb : 0.0;
+      ra[u] = A[(int64_t)ra_r * ld + d0 + kc + lk];
+      rb[u] = A[(int64_t)rb_r * ld + d0 + kc + lk];
     }
   };
   v4d acc[4][4];

@@ -1937,6 +1937,37 @@ int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y
   return PSDP_OK;
 }
 
+int eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, double* Lam,
+               hipStream_t st) {
+  if (precision != PSDP_PREC_FP64 && precision != PSDP_PREC_FP32 && precision != PSDP_PREC_BF16)
+    return fail(PSDP_EINVAL, "invalid precision");
+  Batch B;
+  B.prec = precision;
+  B.f32 = precision != PSDP_PREC_FP64;
+  int rc = build_batch(B, &sdp, 1);
+  if (rc) return rc;
+  if ((rc = init_state(B, st))) return rc;
+  const SysDesc& d = B.sys[0];
+  const int64_t nb = sdp->nb, nn = (int64_t)sdp->n * sdp->n;
+  PSDP_HIP(hipMemcpyAsync(B.X, X, nb * nn * 8, hipMemcpyHostToDevice, st));
+  PSDP_HIP(hipMemcpyAsync(B.Z, Z, nb * nn * 8, hipMemcpyHostToDevice, st));
+  const int one = F_ACTIVE | F_CHOLSEL | (B.f32 ? F_ASM32 : 0);
+  PSDP_HIP(hipMemcpyAsync(B.d_flags, &one, 4, hipMemcpyHostToDevice, st));
+  launch_cholinv(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.Z, B.Zi);
+  op_schur(B, st);
+  PSDP_HIP(hipGetLastError());
+  std::vector<double> full((size_t)d.Kpad * d.Kpad);
+  PSDP_HIP(hipMemcpyAsync(full.data(), B.Lam, full.size() * 8, hipMemcpyDeviceToHost, st));
+  int fl = 0;
+  PSDP_HIP(hipMemcpyAsync(&fl, B.d_flags, 4, hipMemcpyDeviceToHost, st));
+  PSDP_HIP(hipStreamSynchronize(st));
+  if (fl & F_ZFAIL) return fail(PSDP_ENUMERIC, "Z is not positive definite");
+  for (int i = 0; i < d.K; ++i)
+    for (int j = 0; j < d.K; ++j)
+      Lam[(int64_t)i * d.K + j] = j <= i ? full[(size_t)i * d.Kpad + j] : full[(size_t)j * d.Kpad + i];
+  return PSDP_OK;
+}
+
 int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* opts,
                 double* step, int* kstar) {
   psdp_opts o;

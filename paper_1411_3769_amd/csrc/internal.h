@@ -208,5 +208,7 @@ int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y
                 hipStream_t stream);
 int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* o,
                 double* step, int* kstar);
+int eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, double* Lam,
+               hipStream_t st);
 
 }  // namespace psdp

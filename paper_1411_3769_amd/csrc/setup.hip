@@ -649,6 +649,12 @@ int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const doub
   return eval_newton(sdp, X, Z, y, Zi, BTy, BX, Lam, LamL, sol, (hipStream_t)stream);
 }
 
+int psdp_eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, double* Lam,
+                    void* stream) {
+  if (!sdp || !X || !Z || !Lam) return fail(PSDP_EINVAL, "NULL argument");
+  return eval_schur(sdp, X, Z, precision, Lam, (hipStream_t)stream);
+}
+
 int psdp_eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* opts,
                      double* step, int* kstar) {
   if (!sdp || !V || !dV || !step || !kstar) return fail(PSDP_EINVAL, "NULL argument");

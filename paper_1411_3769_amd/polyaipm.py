@@ -106,7 +106,7 @@ _lib = None
 EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "psdp_polya_setup_batched",
            "psdp_query",
            "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc",
-           "psdp_eval_newton", "psdp_poly_on_simplex", "psdp_bisect_simplex",
+           "psdp_eval_newton", "psdp_eval_schur", "psdp_poly_on_simplex", "psdp_bisect_simplex",
            "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version",
            "psdp_mlp_create", "psdp_mlp_param_count", "psdp_mlp_set_params", "psdp_mlp_get_params",
            "psdp_mlp_forward", "psdp_mlp_loss_grad", "psdp_mlp_adam", "psdp_mlp_free"]
@@ -149,6 +149,7 @@ def load(path: str = LIB_PATH):
                                         C.POINTER(Opts), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(BisectRec), C.c_int, C.POINTER(C.c_int)]
     lib.psdp_eval_newton.argtypes = [vp] * 10 + [vp]
+    lib.psdp_eval_schur.argtypes = [vp, vp, vp, C.c_int, vp, vp]
     lib.psdp_eval_ladder.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double),
                                      C.POINTER(C.c_int)]
     lib.psdp_basis.argtypes = [vp, vp]
@@ -167,7 +168,7 @@ def load(path: str = LIB_PATH):
     lib.psdp_mlp_free.argtypes = [vp]
     lib.psdp_mlp_free.restype = None
     for name in ("psdp_polya_setup", "psdp_query", "psdp_get_polya", "psdp_ipm_solve",
-                 "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc", "psdp_poly_on_simplex",
+                 "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc", "psdp_poly_on_simplex", "psdp_eval_schur",
                  "psdp_bisect_simplex", "psdp_eval_newton", "psdp_eval_ladder", "psdp_basis",
                  "psdp_mlp_create", "psdp_mlp_set_params", "psdp_mlp_get_params", "psdp_mlp_forward",
                  "psdp_mlp_loss_grad", "psdp_mlp_adam"):
@@ -497,6 +498,17 @@ def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, stream=No
     _check(load().psdp_eval_newton(sdp.handle, _ptr(X), _ptr(Z), _ptr(y), _ptr(out["Zi"]),
                                    _ptr(out["BTy"]), _ptr(out["BX"]), _ptr(out["Lam"]),
                                    _ptr(out["LamL"]), _ptr(out["sol"]), st))
+    return out
+
+
+def eval_schur(sdp: SDP, X: np.ndarray, Z: np.ndarray, precision="fp64", stream=None) -> np.ndarray:
+    """psdp_eval_schur: the Schur complement [K][K] at (X, Z) in a precision form."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    out = np.zeros((sdp.K, sdp.K))
+    st = stream if stream is not None else _current_stream()
+    _check(load().psdp_eval_schur(sdp.handle, _ptr(X), _ptr(Z), prec, _ptr(out), st))
     return out
 
 

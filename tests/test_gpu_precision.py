@@ -143,3 +143,37 @@ def _perm(sdp_gpu, n, L0):
     Nt = n * (n + 1) // 2
     bmap = np.array([opos[(int(p), int(q))] for p, q in pairs])
     return np.concatenate([h * Nt + bmap for h in range(L0)])
+
+
+def _perm(g, n, L0):
+    pairs = g.basis()
+    opos = {pq: b for b, pq in enumerate(S.basis_pairs(n))}
+    Nt = n * (n + 1) // 2
+    bmap = np.array([opos[(int(p), int(q))] for p, q in pairs])
+    return np.concatenate([h * Nt + bmap for h in range(L0)])
+
+
+@pytest.mark.parametrize("n,l,dp,d", [(10, 4, 2, 2), (24, 2, 1, 1), (32, 4, 1, 2)])
+def test_reduced_schur_error(P, n, l, dp, d):
+    """The reduced-precision Schur complements against the oracle's FP64 one
+    (definition-checked expanded form) at a fixed iterate: FP64 to rounding,
+    FP32 block products to about FP32's unit roundoff, BF16 to about BF16's;
+    the measured element-wise errors (relative to max |Omega|) are printed."""
+    rng = np.random.default_rng(n)
+    A = W.dissip_vertices(n, n, l, 0.3)
+    g = P.polya_setup(A, n, l, dp, d)
+    o = S.make_sdp(A, n, l, dp, d)
+    X = W.random_spd_blocks(n + 1, o.nb, n)
+    Z = W.random_spd_blocks(n + 2, o.nb, n)
+    perm = _perm(g, n, o.L0)
+    ref = S.schur_expanded(o, X, np.linalg.inv(Z))[np.ix_(perm, perm)]
+    sc = np.abs(ref).max()
+    errs = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        Lp = P.eval_schur(g, X, Z, prec)
+        errs[prec] = float(np.abs(Lp - ref).max() / sc)
+    print(f"Schur complement n={n} K={o.K}: max |Omega_p - Omega| / max |Omega| = "
+          + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert errs["fp64"] <= 1e-12
+    assert 1e-10 <= errs["fp32"] <= 2e-6
+    assert 1e-5 <= errs["bf16"] <= 3e-2
