@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="n100: skip the precision forms")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly")
+    ap.add_argument("--chol-panels", type=int, default=0,
+                    help="Schur Cholesky: -1 left-looking, 1..32 super-panel width, 0 autotuned")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     ap.add_argument("--train", type=int, default=20000, help="learned: training solves")
@@ -221,7 +223,7 @@ def main():
         hs = P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)])
         t1 = time.perf_counter()
         rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=precision,
-                                 use_graph=0 if args.no_graph else 1)
+                                 use_graph=0 if args.no_graph else 1, chol_panels=args.chol_panels)
         t2 = time.perf_counter()
         for h in hs:
             h.close()
@@ -313,7 +315,7 @@ def main():
                     kernel="k_assemble_pair / k_assemble_grp (Schur complement assembly, FP64 MFMA)")
     elif dom == "cholesky":
         roof = dict(bound="mfma", achieved=chol_tf, peak=PEAK_FP64, unit="TFLOP/s",
-                    kernel="k_chol_diag + k_chol_trsm + k_chol_update(_wide) (Schur Cholesky, FP64 MFMA)")
+                    kernel="k_chol_diag + k_chol_trsm + k_chol_update(_wide) + k_chol_left (Schur Cholesky, FP64 MFMA)")
     else:
         roof = dict(bound="mfma", achieved=None, peak=PEAK_FP64, unit="TFLOP/s", kernel=dom)
     roof["frac"] = (roof["achieved"] / roof["peak"]) if roof.get("achieved") else None
@@ -343,6 +345,7 @@ def main():
                    "precision": prec,
                    "setup_ms_per_step": split[0] * 1e3, "solve_ms_per_step": split[1] * 1e3,
                    "hip_graph_launches_per_step": rs[0].graph_replays,
+                   "chol_panels": sorted({r.chol_panels for r in rs}),
                    "profiled_pass_ms_per_step": prof_ms,
                    "verdicts": verdicts, "iterations_mean": float(np.mean(iters_sys)),
                    "lowprec_iterations_mean": float(np.mean([r.iters_lowprec for r in rs])),

@@ -194,8 +194,10 @@ typedef struct {
     int    sigma_rule;       /* PSDP_SIGMA_* (FIXED)                                    */
     int    chol_panels;      /* Schur Cholesky: 64-wide panels per super-panel, whose   */
                              /* trailing update is one pass of depth 64 chol_panels     */
-                             /* (1..32); 0 (default) = chosen per tile-count bucket by  */
-                             /* the autotuner among 4, 8 and 16                         */
+                             /* (1..32); -1 = left-looking (one launch per tile column, */
+                             /* each tile updated once); 0 (default) = chosen per       */
+                             /* tile-count bucket by the autotuner among left-looking   */
+                             /* (below 64 tiles) and widths 4, 8 and 16                 */
 } psdp_opts;
 
 typedef struct {
@@ -244,7 +246,8 @@ typedef struct {
                             /* two or three captured graphs (0: every kernel launched */
                             /* eagerly; the same count in every result of a batch)    */
     int     phase1_reason;  /* exit reason (PSDP_R_*) of the phase-I run, -1 if none  */
-    int     chol_panels;    /* super-panel width the Schur Cholesky used             */
+    int     chol_panels;    /* super-panel width the Schur Cholesky used (0: left-   */
+                            /* looking)                                               */
 } psdp_result;
 
 /* Defaults for the option structs. */
@@ -341,11 +344,13 @@ int psdp_ipm_solve_noalloc(psdp_sdp* sdp, const psdp_opts* opts, psdp_result* re
  *                      the device as its lower triangle and mirrored here)
  *   LamL  [K][K]       its lower Cholesky factor (upper part zero)
  *   sol   [K]          Omega^{-1} y
+ * chol_panels picks the factorisation as psdp_opts.chol_panels does (-1:
+ * left-looking, 1..32: super-panel width), 0 = the default width 8.
  * The basis order of the dual variable is the library's (see psdp_basis).
  */
 int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y,
                      double* Zi, double* BTy, double* BX, double* Lam, double* LamL,
-                     double* sol, void* stream);
+                     double* sol, int chol_panels, void* stream);
 
 /*
  * The Schur complement Omega (Alg. 2 eq. T2) assembled at a fixed iterate in

@@ -74,21 +74,25 @@ __device__ inline void st16(double* D, v4d acc, double sign, bool add) {
 
 // Wave-level factorisation and inverse of the 16 x 16 block at B (leading
 // dimension kLD; lower triangle read).  Lane r of each 16-lane row of the
-// wave holds row r (the four rows of the wave compute the same block; the
-// first writes it).  Column k of L is the pivot's column scaled by the
-// Newton reciprocal square root of the pivot; L goes to B, and lane c then
-// forms column c of X = L^{-1} by forward substitution, reading the rows of
-// L back from B.  Values travel by DPP row broadcasts and LDS broadcasts
-// only, so the dependent chain per column is a broadcast, the reciprocal
-// square root and one multiply-add.  On return B holds L (zeros above the
-// diagonal) and Xb holds L^{-1}.  Non-positive pivots set *fail (replaced
-// by 1).
+// wave holds row r of A (a[]) and column r of X = L^{-1} (x[]); the four
+// rows of the wave compute the same block and the first writes it.  Step k:
+// column k of L is the pivot's column scaled by the Newton reciprocal
+// square root of the pivot, x_k = b_k / L_kk, and every later c gets
+// a_c -= L_rk L_ck and b_c -= L_ck x_k (the forward substitution for X
+// carried along with the factorisation, b starting as the unit vector
+// e_r).  L_ck reaches every lane by a DPP row broadcast from lane c, so no
+// value goes through LDS.  Above the diagonal a[] collects values nothing
+// reads; the store writes zeros there.  On return B holds L (zeros above
+// the diagonal) and Xb holds L^{-1}.  Non-positive pivots set *fail
+// (replaced by 1).
 __device__ inline void wave_potri16(double* B, double* Xb, int* fail) {
   const int lane = threadIdx.x & 63, r = lane & 15;
-  double a[16];
+  double a[16], x[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) a[c] = c <= r ? B[r * kLD + c] : 0.0;
-  double rs[16];
+  for (int c = 0; c < 16; ++c) {
+    a[c] = c <= r ? B[r * kLD + c] : 0.0;
+    x[c] = c == r ? 1.0 : 0.0;
+  }
   bool bad = false;
   static_for<16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -96,39 +100,29 @@ __device__ inline void wave_potri16(double* B, double* Xb, int* fail) {
     const bool bb = !(d > 0.0) || !isfinite(d);
     bad = bad || bb;
     d = bb ? 1.0 : d;
-    rs[k] = rsqrt_nr(d);
-    const double lrk = r > k ? a[k] * rs[k] : (r == k ? d * rs[k] : 0.0);
+    const double rs = rsqrt_nr(d);
+    const double lrk = r > k ? a[k] * rs : (r == k ? d * rs : 0.0);
     a[k] = lrk;
+    x[k] *= rs;
     static_for<16>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       if constexpr (c > k) {
         const double lck = row_bcast16<c>(lrk);
-        a[c] = r >= c ? a[c] - lrk * lck : a[c];
+        a[c] -= lrk * lck;
+        x[c] -= lck * x[k];
+        // x_c is final for this step here: left to itself the compiler
+        // sinks the x updates past the whole factorisation and keeps every
+        // broadcast L_ck alive until then (hundreds of registers)
+        asm volatile("" : "+v"(x[c]));
       }
     });
   });
   if (lane < 16) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) B[r * kLD + c] = a[c];
-  }
-  // the wave's LDS accesses complete in order; keep the compiler from
-  // moving the reads of L above its writes
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  // column r of X: x[i] = (delta_{ir} - sum_{m<i} L[i][m] x[m]) / L[i][i],
-  // the row of L read back from LDS (one address per row: a broadcast)
-  double x[16];
-  static_for<16>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    double acc = r == i ? 1.0 : 0.0;
-    static_for<i>([&](auto mc) {
-      constexpr int m = decltype(mc)::value;
-      acc -= B[i * kLD + m] * x[m];
-    });
-    x[i] = acc * rs[i];
-  });
-  if (lane < 16) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Xb[i * kLD + r] = x[i];
+    for (int c = 0; c < 16; ++c) {
+      B[r * kLD + c] = c <= r ? a[c] : 0.0;
+      Xb[c * kLD + r] = x[c];
+    }
   }
   if (bad && lane == 0) *fail = 1;
 }
@@ -289,7 +283,7 @@ __global__ void __launch_bounds__(256) k_chol_trsm(const SysDesc* __restrict__ s
 // rows 16w..16w+15 and the four 16-column tiles; both panels staged in LDS.
 // The workgroup of tile (p+1, p+1) then factors and inverts it (the diagonal
 // step of p + 1), overlapped with the other tiles' updates.
-__global__ void __launch_bounds__(256) k_chol_update(const SysDesc* __restrict__ sys,
+__global__ void __launch_bounds__(256, 2) k_chol_update(const SysDesc* __restrict__ sys,
                                                      int* flags, double* Lam, double* Ldiag,
                                                      double* Linv, const int* __restrict__ st_sys,
                                                      const int* __restrict__ st_pre, int cnt,
@@ -539,6 +533,165 @@ __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __re
         if (R < nmax && Cc < nmax && Cc <= R) A[ix[b * 4 + q]] = cv[b * 4 + q] - acc[a][b][q];
       }
   }
+}
+
+// Left-looking factorisation for systems with few tiles: one launch per tile
+// column j, one workgroup per tile (i, j), i >= j, of every system in it.
+// The workgroup first forms the previous column's factor tiles it needs,
+// L_{i,j-1} = C_{i,j-1} L_{j-1,j-1}^{-T} and L_{j,j-1} (column j-1 holds the
+// updated tiles C the previous launch left), then
+//   C_ij = A_ij - sum_{k < j} L_ik L_jk^T
+// (the k = j-1 term from those two tiles, the rest read from the stored
+// factor), and the diagonal workgroup factors and inverts C_jj.  Each tile is
+// thus updated once, with one pass of depth 64 j, and a factorisation takes P
+// launches instead of a triangular solve and an update per tile column.
+// Stores: L_{i,j-1} for i > j (nobody else in the launch reads row i); row
+// j's tile L_{j,j-1} is read as C by every workgroup of the launch, so the
+// next launch stores it (its last workgroup, off the diagonal workgroup's
+// longer path), or this one's diagonal workgroup when j is the last column.
+// The tiles of the next k are loaded into registers while the current
+// product runs.
+__global__ void __launch_bounds__(256) k_chol_left(const SysDesc* __restrict__ sys, int* flags, double* Lam,
+                                                   double* Ldiag, double* Linv,
+                                                   const int* __restrict__ st_sys,
+                                                   const int* __restrict__ st_pre, int cnt, int j) {
+  __shared__ double sX[kNB * LDT];
+  __shared__ double sA[kNB * LDT];
+  __shared__ double sB[kNB * LDT];
+  __shared__ int fl;
+  constexpr int NE = kNB * kNB / 256;   // tile elements per thread
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  double* A = Lam + sd.loff;
+  const double* Li = Linv + sd.dgoff;
+  const int P = sd.P, i = j + t;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  auto tile = [&](int r, int c) { return A + (int64_t)r * kNB * ld + (int64_t)c * kNB; };
+  auto gload = [&](double* v, const double* src, int64_t lds) {
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      v[it] = src[(int64_t)(e >> 6) * lds + (e & 63)];
+    }
+  };
+  auto sstore = [&](double* dst, const double* v) {
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      dst[(e >> 6) * LDT + (e & 63)] = v[it];
+    }
+  };
+  // acc += X Y^T for the wave's 16 rows of X (FP64 MFMA)
+  auto prodT = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(16 * w + r16) * LDT + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double b = Y[(16 * u + r16) * LDT + k0 + kq];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+      }
+    }
+  };
+  auto to_lds = [&](double* dst, const v4d* acc) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[(16 * w + 4 * q + kq) * LDT + 16 * u + r16] = acc[u][q];
+  };
+  auto to_global = [&](double* dst, const v4d* acc) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16] = acc[u][q];
+  };
+  const bool own = i == j;   // the diagonal workgroup: row i is row j
+  double* C = tile(i, j);
+  double cv[NE];             // C_ij in the accumulator layout
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cv[u * 4 + q] = C[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16];
+  // L_{j-1,j-2}, which the previous launch's workgroups formed for themselves
+  if (j >= 2 && i == (j < P - 1 ? P - 1 : j)) {
+    double vx[NE], vc[NE];
+    gload(vx, Li + (int64_t)(j - 2) * kNB * kNB, kNB);
+    gload(vc, tile(j - 1, j - 2), ld);
+    sstore(sX, vx);
+    sstore(sA, vc);
+    __syncthreads();
+    v4d l[4] = {};
+    prodT(sA, sX, l);
+    to_global(tile(j - 1, j - 2), l);
+    __syncthreads();
+  }
+  v4d acc[4] = {};
+  if (j >= 1) {
+    double va[NE], vb[NE];   // the next k's tiles, in flight during a product
+    {
+      double vx[NE];
+      gload(vx, Li + (int64_t)(j - 1) * kNB * kNB, kNB);
+      gload(va, tile(i, j - 1), ld);
+      if (!own) gload(vb, tile(j, j - 1), ld);
+      sstore(sX, vx);
+      sstore(sA, va);
+      if (!own) sstore(sB, vb);
+    }
+    if (j >= 2) {
+      gload(va, tile(i, 0), ld);
+      if (!own) gload(vb, tile(j, 0), ld);
+    }
+    __syncthreads();
+    v4d li[4] = {}, lj[4] = {};
+    prodT(sA, sX, li);
+    if (!own) prodT(sB, sX, lj);
+    __syncthreads();
+    to_lds(sA, li);
+    if (!own) to_lds(sB, lj);
+    if (i > j || j == P - 1) to_global(tile(i, j - 1), li);
+    __syncthreads();
+    prodT(sA, own ? sA : sB, acc);
+    for (int k = 0; k < j - 1; ++k) {
+      __syncthreads();
+      sstore(sA, va);
+      if (!own) sstore(sB, vb);
+      if (k + 1 < j - 1) {
+        gload(va, tile(i, k + 1), ld);
+        if (!own) gload(vb, tile(j, k + 1), ld);
+      }
+      __syncthreads();
+      prodT(sA, own ? sA : sB, acc);
+    }
+  }
+  if (!own) {
+    if (j == 0) return;   // the first column is already C
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        C[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16] = cv[u * 4 + q] - acc[u][q];
+    return;
+  }
+  // the diagonal tile: C_jj - acc, factored and inverted
+  if (tid == 0) fl = 0;
+  __syncthreads();   // the product's operands are no longer read
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sA[(16 * w + 4 * q + kq) * LDT + 16 * u + r16] = cv[u * 4 + q] - acc[u][q];
+#pragma unroll
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + 256 * it;
+    sX[(e >> 6) * LDT + (e & 63)] = 0.0;
+  }
+  __syncthreads();
+  diag_tile(sA, sX, &fl);
+  store_diag(sA, sX, Ldiag + sd.dgoff + (int64_t)j * kNB * kNB, Linv + sd.dgoff + (int64_t)j * kNB * kNB);
+  if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
 }
 
 // Whole solve L L^T x = rhs for systems with few tiles: one workgroup of 8
@@ -940,6 +1093,12 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
   if (total)
     hipLaunchKernelGGL(k_chol_update_wide, dim3(total), dim3(256), 0, st, sys, flags, Lam, ssys, spre,
                        cnt, p);
+}
+
+void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
+                      const int* ssys, const int* spre, int cnt, int total, int j) {
+  if (total)
+    hipLaunchKernelGGL(k_chol_left, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, ssys, spre, cnt, j);
 }
 
 void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,

@@ -91,13 +91,11 @@ __device__ inline double readlane_d(double v, int l) {
 }
 
 // value of v in lane C of each row of 16 lanes, for every lane of that row
-// (DPP row broadcast; no LDS).  Every lane of the row must be active.
+// (one 64-bit DPP row_newbcast move; no LDS).  Every lane of the row must
+// be active.
 template <int C>
 __device__ __forceinline__ double row_bcast16(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x150 + C, 0xF, 0xF, false);
-  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x150 + C, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + C, 0xF, 0xF, false);
 }
 
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time

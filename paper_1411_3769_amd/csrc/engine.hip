@@ -248,6 +248,7 @@ struct Batch {
   int maxn_pair = 0, nptiles = 0;
   std::vector<int> ownP, ownK;
   StepTab pan, trs, upd, wide;
+  StepTab lft;   // left-looking factorisation, one step per tile column
   // grouped solves of the systems not solved in one workgroup: per group q,
   // the diagonal-block sweeps (one per system), the row tiles below the
   // group (forward) and the column tiles left of it (backward)
@@ -273,6 +274,7 @@ struct Batch {
   int64_t* d_gpoff = nullptr;
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
   int *d_trs_sys = nullptr, *d_trs_pre = nullptr, *d_wide_sys = nullptr, *d_wide_pre = nullptr;
+  int *d_lft_sys = nullptr, *d_lft_pre = nullptr;
   int *d_gin_sys = nullptr, *d_gin_pre = nullptr, *d_gap_sys = nullptr, *d_gap_pre = nullptr;
   int *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr, *d_gbu_pre = nullptr;
   int* d_flags = nullptr;
@@ -352,7 +354,7 @@ static size_t tabsize(const std::vector<T>& v) {
 // of kSG tiles.
 struct Choice {
   std::vector<char> pair, small;
-  std::vector<int> sw;   // Schur Cholesky panels per super-panel
+  std::vector<int> sw;   // Schur Cholesky panels per super-panel (0: left-looking)
 };
 
 static Choice default_choice(psdp_sdp* const* sdps, int count) {
@@ -609,6 +611,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.trs.add_step();
     B.upd.add_step();
     B.wide.add_step();
+    B.lft.add_step();
 
     // last column of the narrow update of step q (super-panel end; a
     // super-panel followed by fewer than sw panels absorbs them, since
@@ -620,6 +623,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (P <= pstep) continue;
+      if (B.sys[s].sw == 0) {   // left-looking: the tiles of column pstep
+        B.lft.add(s, pstep == 0 ? 1 : P - pstep);
+        continue;
+      }
       // after a narrow update of step pstep - 1 its workgroup of tile
       // (pstep, pstep) has already factored the diagonal tile
       const int sw = B.sys[s].sw;
@@ -669,6 +676,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(H.csr_mh) + tabsize(H.csr_hl) + tabsize(H.csr_hm) + tabsize(H.pq2b);
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
+  tb += tabsize(B.lft.sys) + tabsize(B.lft.pre);
   tb += tabsize(B.gin.sys) + tabsize(B.gin.pre) + tabsize(B.gap.sys) + tabsize(B.gap.pre);
   tb += tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
@@ -750,6 +758,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.wide.pre, &B.d_wide_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.upd.sys, &B.d_upd_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.upd.pre, &B.d_upd_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lft.sys, &B.d_lft_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lft.pre, &B.d_lft_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.sys, &B.d_gin_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.pre, &B.d_gin_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gap.sys, &B.d_gap_sys))) return rc;
@@ -911,6 +921,13 @@ static void op_factor(Batch& B, hipStream_t st) {
                               B.wide.cnt[p], B.wide.tot[p], p);
     }
     if (B.upd.tot[p] > 0 || B.wide.tot[p] > 0) B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
+    if (B.lft.tot[p] > 0) {
+      const int g = B.lft.first[p];
+      const size_t m2 = B.prof.mark();
+      launch_chol_left(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.d_lft_sys + g, B.d_lft_pre + g,
+                       B.lft.cnt[p], B.lft.tot[p], p);
+      B.prof.add(PSDP_PROF_CHOL_UPDATE, m2, B.prof.mark());
+    }
   }
   op_ginv(B, st);
 }
@@ -1452,20 +1469,35 @@ static int trial_batch(Batch& T, psdp_sdp* const* sub, int cnt, const Choice& c,
   return PSDP_OK;
 }
 
-// bucket of the super-panel width choice: Schur tile counts 8..15, 16..31,
-// ... share one (below 8 tiles the width makes no difference)
+// bucket of the factorisation choice: Schur tile counts 2..3, 4..7, 8..15,
+// ... share one (0: a single tile, nothing to choose)
 static int sw_bucket(int P) {
-  if (P < 8) return 0;
+  if (P < 2) return 0;
   int b = 0;
   while ((P >> (b + 1)) > 0) ++b;
   return b;
 }
 
+// candidates of a bucket: left-looking (0) below kLeftMaxP tiles, and the
+// super-panel widths where a super-panel fits
+static std::vector<int> sw_candidates(int bucket) {
+  std::vector<int> c;
+  if ((1 << bucket) < kLeftMaxP) c.push_back(0);
+  if ((2 << bucket) > 8) {
+    c.push_back(4);
+    c.push_back(8);
+    c.push_back(16);
+  } else {
+    c.push_back(kSW);
+  }
+  return c;
+}
+
 static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hipStream_t st,
                        Choice& ch) {
   ch = default_choice(sdps, count);
-  if (o.chol_panels > 0)
-    for (int s = 0; s < count; ++s) ch.sw[s] = o.chol_panels;
+  if (o.chol_panels != 0)
+    for (int s = 0; s < count; ++s) ch.sw[s] = o.chol_panels < 0 ? 0 : o.chol_panels;
   for (int s = 0; s < count; ++s) {
     const bool can_pair = sdps[s]->n * sdps[s]->n <= 128;
     const bool can_small = sdps[s]->Kpad / kNB <= kSmallP;
@@ -1473,7 +1505,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
     if (o.solve_path >= 0) ch.small[s] = can_small && o.solve_path == 1;
   }
   for (int kind = 0; kind < 3; ++kind) {
-    if ((kind == 0 ? o.asm_path : kind == 1 ? o.solve_path : o.chol_panels) >= (kind == 2 ? 1 : 0)) continue;
+    if (kind == 2 ? o.chol_panels != 0 : (kind == 0 ? o.asm_path : o.solve_path) >= 0) continue;
     std::map<int, std::vector<int>> want;   // key -> systems
     for (int s = 0; s < count; ++s) {
       const int P = (int)(sdps[s]->Kpad / kNB);
@@ -1490,10 +1522,10 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
       std::vector<psdp_sdp*> sub;
       for (int s : kv.second) sub.push_back(sdps[s]);
       const int cnt = (int)sub.size();
-      // candidates: the two paths (kinds 0, 1) or super-panel widths (kind 2)
-      static const int widths[3] = {4, 8, 16};
-      const int nv = kind == 2 ? 3 : 2;
-      float t[3] = {0.f, 0.f, 0.f};
+      // candidates: the two paths (kinds 0, 1) or factorisations (kind 2)
+      const std::vector<int> widths = kind == 2 ? sw_candidates(kv.first) : std::vector<int>{};
+      const int nv = kind == 2 ? (int)widths.size() : 2;
+      float t[4] = {0.f, 0.f, 0.f, 0.f};
       for (int v = 0; v < nv; ++v) {
         Choice c = default_choice(sub.data(), cnt);
         for (int i = 0; i < cnt; ++i) {
@@ -1539,7 +1571,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
       auto it = g_tune.find({1, P});
       if (it != g_tune.end()) ch.small[s] = it->second;
     }
-    if (o.chol_panels <= 0 && sw_bucket(P) > 0) {
+    if (o.chol_panels == 0 && sw_bucket(P) > 0) {
       auto it = g_tune.find({2, sw_bucket(P)});
       if (it != g_tune.end()) ch.sw[s] = it->second;
     }
@@ -1596,8 +1628,8 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     return fail(PSDP_EINVAL, "invalid stop_rule");
   if (o.sigma_rule != PSDP_SIGMA_FIXED && o.sigma_rule != PSDP_SIGMA_MEHROTRA)
     return fail(PSDP_EINVAL, "invalid sigma_rule");
-  if (o.chol_panels < 0 || o.chol_panels > 32)
-    return fail(PSDP_EINVAL, "chol_panels must lie in [0, 32]");
+  if (o.chol_panels < -1 || o.chol_panels > 32)
+    return fail(PSDP_EINVAL, "chol_panels must lie in [-1, 32]");
   // all work runs on a private stream (capturable into graphs) ordered
   // after the caller's stream; the allocation-free solve uses the caller's
   SolveStream ss;
@@ -1624,7 +1656,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     for (int s = 0; s < count; ++s) {
       if (o.asm_path >= 0) ch.pair[s] = sdps[s]->n * sdps[s]->n <= 128 && o.asm_path == 1;
       if (o.solve_path >= 0) ch.small[s] = sdps[s]->Kpad / kNB <= kSmallP && o.solve_path == 1;
-      if (o.chol_panels > 0) ch.sw[s] = o.chol_panels;
+      if (o.chol_panels != 0) ch.sw[s] = o.chol_panels < 0 ? 0 : o.chol_panels;
     }
   } else if ((rc = tune_choice(sdps, count, o, st, ch))) {
     return rc;
@@ -1879,9 +1911,12 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
 }
 
 int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y, double* Zi,
-                double* BTy, double* BX, double* Lam, double* LamL, double* sol, hipStream_t st) {
+                double* BTy, double* BX, double* Lam, double* LamL, double* sol, int chol_panels,
+                hipStream_t st) {
   Batch B;
-  int rc = build_batch(B, &sdp, 1);
+  Choice ch = default_choice(&sdp, 1);
+  if (chol_panels != 0) ch.sw[0] = chol_panels < 0 ? 0 : chol_panels;
+  int rc = build_batch(B, &sdp, 1, &ch);
   if (rc) return rc;
   if ((rc = init_state(B, st))) return rc;
   const SysDesc& d = B.sys[0];

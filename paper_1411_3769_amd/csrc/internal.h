@@ -18,6 +18,7 @@ constexpr int kTB = 8;       // index-group size of the tiled basis
 constexpr int kNB = 64;      // Schur Cholesky tile
 constexpr int kPairGrid = 1024;   // workgroups of the whole-pair assembly (grid-stride)
 constexpr int kSW = 8;       // default Cholesky panels per super-panel (depth of the wide update / 64)
+constexpr int kLeftMaxP = 64;  // the autotuner tries the left-looking factorisation below this many tiles
 constexpr int kMaxDeg = 20;  // largest multinomial degree (20! < 2^63)
 constexpr int kNSC = 32;     // per-system scalar slots
 
@@ -180,6 +181,8 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
                              const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
                         double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
+void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
+                      const int* ssys, const int* spre, int cnt, int total, int j);
 void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
                       const int* spre, int cnt, int total, const double* Lam, const double* Linv,
                       double* Ginv);
@@ -204,7 +207,7 @@ constexpr int kGS = kSG * kNB;   // rows of such a group
 int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res,
                 bool noalloc = false);
 int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y, double* Zi,
-                double* BTy, double* BX, double* Lam, double* LamL, double* sol,
+                double* BTy, double* BX, double* Lam, double* LamL, double* sol, int chol_panels,
                 hipStream_t stream);
 int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* o,
                 double* step, int* kstar);

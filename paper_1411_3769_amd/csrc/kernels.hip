@@ -1345,9 +1345,13 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   typedef typename AP::acc_t acc_t;
   constexpr int KC = AP::KC;                 // depth of one MFMA
   constexpr int KS = PR == 2 ? 16 : 8;       // terms per LDS stage
-  __shared__ real sT[KS * 16 * 17];
-  __shared__ real sU[KS * 16 * 17];
-  __shared__ double sL[64 * 65];
+  // the stage buffers and, after the last product, the combined tile share
+  // one LDS block (two workgroups fit a compute unit)
+  constexpr int kStage = 2 * KS * 16 * 17 * (int)sizeof(real), kTile = 64 * 65 * 8;
+  __shared__ __align__(16) char smem[kStage > kTile ? kStage : kTile];
+  real* sT = reinterpret_cast<real*>(smem);
+  real* sU = sT + KS * 16 * 17;
+  double* sL = reinterpret_cast<double*>(smem);
   const AsmTile tl = tiles[blockIdx.x];
   ACTIVE_OR_RETURN(tl.sys);
   if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) return;

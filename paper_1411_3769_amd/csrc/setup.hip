@@ -644,9 +644,10 @@ int psdp_ipm_solve_batched(psdp_sdp* const* sdps, int count, const psdp_opts* op
 
 int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y,
                      double* Zi, double* BTy, double* BX, double* Lam, double* LamL, double* sol,
-                     void* stream) {
+                     int chol_panels, void* stream) {
   if (!sdp || !X || !Z || !y) return fail(PSDP_EINVAL, "NULL argument");
-  return eval_newton(sdp, X, Z, y, Zi, BTy, BX, Lam, LamL, sol, (hipStream_t)stream);
+  if (chol_panels < -1 || chol_panels > 32) return fail(PSDP_EINVAL, "chol_panels must lie in [-1, 32]");
+  return eval_newton(sdp, X, Z, y, Zi, BTy, BX, Lam, LamL, sol, chol_panels, (hipStream_t)stream);
 }
 
 int psdp_eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, double* Lam,

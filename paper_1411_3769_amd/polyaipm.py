@@ -148,7 +148,7 @@ def load(path: str = LIB_PATH):
                                         C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(SetupOpts),
                                         C.POINTER(Opts), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(BisectRec), C.c_int, C.POINTER(C.c_int)]
-    lib.psdp_eval_newton.argtypes = [vp] * 10 + [vp]
+    lib.psdp_eval_newton.argtypes = [vp] * 10 + [C.c_int, vp]
     lib.psdp_eval_schur.argtypes = [vp, vp, vp, C.c_int, vp, vp]
     lib.psdp_eval_ladder.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double),
                                      C.POINTER(C.c_int)]
@@ -487,7 +487,8 @@ def ipm_solve_batched(sdps: Sequence[SDP], warm_y=None, warm_logx=None, **opts) 
     return [_unpack(arr[i], *keep[i]) for i in range(n)]
 
 
-def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, stream=None) -> dict:
+def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, chol_panels=0,
+                stream=None) -> dict:
     X = np.ascontiguousarray(X, dtype=np.float64)
     Z = np.ascontiguousarray(Z, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
@@ -497,7 +498,7 @@ def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, stream=No
     st = stream if stream is not None else _current_stream()
     _check(load().psdp_eval_newton(sdp.handle, _ptr(X), _ptr(Z), _ptr(y), _ptr(out["Zi"]),
                                    _ptr(out["BTy"]), _ptr(out["BX"]), _ptr(out["Lam"]),
-                                   _ptr(out["LamL"]), _ptr(out["sol"]), st))
+                                   _ptr(out["LamL"]), _ptr(out["sol"]), int(chol_panels), st))
     return out
 
 
