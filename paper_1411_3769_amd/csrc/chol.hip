@@ -855,99 +855,164 @@ __global__ void __launch_bounds__(kSvT) k_trsv_small(const SysDesc* __restrict__
 // (k_trsv_gbwd).  Every launch reads its part of L at full width; the only
 // serial chain is the one between groups.
 //
-// G_q by block forward substitution over its 64 x 64 tiles, with the stored
-// inverses X_ii = L_ii^{-1} of the diagonal tiles:
-//   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj   (i > j),
-// one workgroup per (group, tile column j), rows i in order; each product is
-// a 64 x 64 x 64 FP64 MFMA product of LDS-staged tiles (wave w owns the 16
-// rows 16 w .. 16 w + 15 of the result).  Tiles above the diagonal are
-// written as zeros.
+// G_q by recursive doubling over its 64 x 64 tiles, starting from the stored
+// inverses L_ii^{-1} of the diagonal tiles.  For a block split in halves A
+// (first m tiles) and C (next m), with X_AA = L_AA^{-1} and X_CC = L_CC^{-1}
+// known from the previous level,
+//   L^{-1} = [[X_AA, 0], [X_CA, X_CC]],  X_CA = -X_CC (L_CA X_AA),
+// in two launches per level m = 1, 2, 4, ...: T = L_CA X_AA, then
+// X_CA = -X_CC T, one workgroup per 64 x 64 output tile and at most m tile
+// products each (the serial chain is 2 log2(kSG) launches instead of a
+// forward substitution down the group).  T is parked in the upper triangle
+// of G (tile (j, i) holds T_ij), which the last launch clears while it writes
+// G's diagonal tiles and G^T.
+// acc = sum_{k < nk} P_k Q_k over 64 x 64 tiles (row-major, leading
+// dimensions from src), staged through LDS with the next pair's loads in
+// flight during each product; wave w owns rows 16 w .. 16 w + 15.
+template <class Src>
+__device__ __forceinline__ void tile_gemm(double* sP, double* sQ, int nk, Src src, v4d* acc) {
+  constexpr int NE = kNB * kNB / 256;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  double vp[NE], vq[NE];
+  auto gload = [&](int k) {
+    const double *P, *Q;
+    int64_t lp, lq;
+    src(k, P, lp, Q, lq);
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      vp[it] = P[(int64_t)(e >> 6) * lp + (e & 63)];
+      vq[it] = Q[(int64_t)(e >> 6) * lq + (e & 63)];
+    }
+  };
+  if (nk > 0) gload(0);
+  for (int k = 0; k < nk; ++k) {
+    __syncthreads();   // the previous product has read sP and sQ
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      sP[(e >> 6) * LDT + (e & 63)] = vp[it];
+      sQ[(e >> 6) * LDT + (e & 63)] = vq[it];
+    }
+    if (k + 1 < nk) gload(k + 1);
+    __syncthreads();
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = sP[(16 * w + r16) * LDT + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double b = sQ[(k0 + kq) * LDT + 16 * u + r16];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_trsv_ginv(const SysDesc* __restrict__ sys,
                                                    const int* __restrict__ flags,
                                                    const int* __restrict__ st_sys,
                                                    const int* __restrict__ st_pre, int cnt,
                                                    const double* __restrict__ Lam,
-                                                   const double* __restrict__ Linv, double* Ginv) {
-  __shared__ double sL[kNB * kLD];
-  __shared__ double sX[kNB * kLD];
+                                                   const double* __restrict__ Linv, double* Ginv, int m,
+                                                   int phase) {
+  __shared__ double sP[kNB * LDT];
+  __shared__ double sQ[kNB * LDT];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
   const int t = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_CHOLSEL)) return;
   const SysDesc sd = sys[s];
-  const int q = t / kSG, j = t % kSG;
+  const int per = kSG * m / 2;   // output tiles per group at this level
+  const int q = t / per, rem = t % per;
+  const int pair = rem / (m * m), o = rem % (m * m);
+  const int A0 = 2 * m * pair, C0 = A0 + m;
+  const int i = C0 + o / m, j = A0 + o % m;   // group-local tile indices
   const int p0 = kSG * q, nseg = min(sd.P, p0 + kSG) - p0;
-  if (j >= nseg) return;
+  if (i >= nseg) return;
   const int64_t ld = sd.Kpad;
-  const double* A = Lam + sd.loff;
-  const double* Li = Linv + sd.dgoff;
+  const double* Lt = Lam + sd.loff + (int64_t)p0 * kNB * ld + (int64_t)p0 * kNB;   // L_qq
+  const double* Li = Linv + sd.dgoff + (int64_t)p0 * kNB * kNB;
   double* G = Ginv + sd.gioff + (int64_t)q * 2 * kGS * kGS;
-  double* GT = G + (int64_t)kGS * kGS;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
-  // tiles (i, j), i < j, of G and their transposes are zero
-  for (int i = 0; i < j; ++i)
-    for (int e = tid; e < kNB * kNB; e += 256) {
-      const int rr = e >> 6, cc = e & 63;
-      G[(int64_t)(i * kNB + rr) * kGS + j * kNB + cc] = 0.0;
-      GT[(int64_t)(j * kNB + rr) * kGS + i * kNB + cc] = 0.0;
-    }
-  // a 64 x 64 tile into LDS; lower = true keeps only its lower triangle
-  auto stage = [&](double* dst, const double* src, int64_t lds, bool lower) {
-    for (int e = tid; e < kNB * kNB; e += 256) {
-      const int rr = e >> 6, cc = e & 63;
-      const double v = src[(int64_t)rr * lds + cc];
-      dst[rr * kLD + cc] = (!lower || cc <= rr) ? v : 0.0;
+  auto gt = [&](int r, int c) { return G + (int64_t)r * kNB * kGS + (int64_t)c * kNB; };
+  // X_rc of the current level's inputs: the stored diagonal inverses on the
+  // diagonal, G below it
+  auto xt = [&](int r, int c, const double*& p, int64_t& l) {
+    if (r == c) {
+      p = Li + (int64_t)r * kNB * kNB;
+      l = kNB;
+    } else {
+      p = gt(r, c);
+      l = kGS;
     }
   };
-  // X_jj
-  stage(sX, Li + (int64_t)(p0 + j) * kNB * kNB, kNB, true);
-  __syncthreads();
-  for (int e = tid; e < kNB * kNB; e += 256) {
-    const int rr = e >> 6, cc = e & 63;
-    const double v = sX[rr * kLD + cc];
-    G[(int64_t)(j * kNB + rr) * kGS + j * kNB + cc] = v;
-    GT[(int64_t)(j * kNB + cc) * kGS + j * kNB + rr] = v;
+  v4d acc[4] = {};
+  if (phase == 0) {
+    // T_ij = sum_{k = j}^{A0 + m - 1} L_ik X_kj
+    tile_gemm(sP, sQ, A0 + m - j, [&](int kk, const double*& P, int64_t& lp, const double*& Q, int64_t& lq) {
+      const int k = j + kk;
+      P = Lt + (int64_t)i * kNB * ld + (int64_t)k * kNB;
+      lp = ld;
+      xt(k, j, Q, lq);
+    }, acc);
+  } else {
+    // X_ij = -sum_{k = C0}^{i} X_ik T_kj, T_kj parked at tile (j, k)
+    tile_gemm(sP, sQ, i - C0 + 1, [&](int kk, const double*& P, int64_t& lp, const double*& Q, int64_t& lq) {
+      const int k = C0 + kk;
+      xt(i, k, P, lp);
+      Q = gt(j, k);
+      lq = kGS;
+    }, acc);
   }
-  for (int i = j + 1; i < nseg; ++i) {
-    v4d acc[4];
+  double* out = phase == 0 ? gt(j, i) : gt(i, j);
+  const double sg = phase == 0 ? 1.0 : -1.0;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int k = j; k < i; ++k) {
-      __syncthreads();   // the previous product has read sL and sX
-      stage(sL, A + (int64_t)(p0 + i) * kNB * ld + (int64_t)(p0 + k) * kNB, ld, false);
-      stage(sX, G + (int64_t)(k * kNB) * kGS + j * kNB, kGS, false);
-      __syncthreads();
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+    for (int e = 0; e < 4; ++e) out[(int64_t)(16 * w + 4 * e + kq) * kGS + 16 * u + r16] = sg * acc[u][e];
+}
+
+// Last step of G_q: diagonal tiles from the stored inverses, tiles above the
+// diagonal cleared, and G^T; one workgroup per tile (i, j) of the group.
+__global__ void __launch_bounds__(256) k_trsv_gfinish(const SysDesc* __restrict__ sys,
+                                                      const int* __restrict__ flags,
+                                                      const int* __restrict__ st_sys,
+                                                      const int* __restrict__ st_pre, int cnt,
+                                                      const double* __restrict__ Linv, double* Ginv) {
+  __shared__ double sT[kNB * LDT];
+  const int si = find_owner(st_pre, cnt, blockIdx.x);
+  const int s = st_sys[si];
+  const int t = blockIdx.x - st_pre[si];
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int q = t / (kSG * kSG), i = (t / kSG) % kSG, j = t % kSG;
+  const int p0 = kSG * q, nseg = min(sd.P, p0 + kSG) - p0;
+  if (i >= nseg || j >= nseg) return;
+  double* G = Ginv + sd.gioff + (int64_t)q * 2 * kGS * kGS;
+  double* GT = G + (int64_t)kGS * kGS;
+  double* gij = G + (int64_t)i * kNB * kGS + (int64_t)j * kNB;
+  double* gtji = GT + (int64_t)j * kNB * kGS + (int64_t)i * kNB;
+  const double* src = i == j ? Linv + sd.dgoff + (int64_t)(p0 + i) * kNB * kNB : gij;
+  const int64_t ls = i == j ? kNB : kGS;
+  const int tid = threadIdx.x;
+  constexpr int NE = kNB * kNB / 256;
+  double v[NE];
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-          acc[b] = mm16(sL + (16 * w) * kLD + 16 * kb, sX + (16 * kb) * kLD + 16 * b, false, acc[b]);
-    }
-    __syncthreads();
-    // sX = the sum, sL = X_ii; then X_ij = -X_ii sum
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + 256 * it;
+    v[it] = i >= j ? src[(int64_t)(e >> 6) * ls + (e & 63)] : 0.0;
+  }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) st16(sX + (16 * w) * kLD + 16 * b, acc[b], 1.0, false);
-    stage(sL, Li + (int64_t)(p0 + i) * kNB * kNB, kNB, true);
-    __syncthreads();
-    v4d out[4];
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + 256 * it;
+    sT[(e >> 6) * LDT + (e & 63)] = v[it];
+    if (i <= j) gij[(int64_t)(e >> 6) * kGS + (e & 63)] = v[it];
+  }
+  __syncthreads();
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      out[b] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb)
-        out[b] = mm16(sL + (16 * w) * kLD + 16 * kb, sX + (16 * kb) * kLD + 16 * b, false, out[b]);
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int rr = 16 * w + 4 * e + kq, cc = 16 * b + r16;
-        const double v = -out[b][e];
-        G[(int64_t)(i * kNB + rr) * kGS + j * kNB + cc] = v;
-        GT[(int64_t)(j * kNB + cc) * kGS + i * kNB + rr] = v;
-      }
-    // the tile just written is read back (as X_kj) by the next rows' products
-    __threadfence_block();
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + 256 * it;
+    gtji[(int64_t)(e >> 6) * kGS + (e & 63)] = sT[(e & 63) * LDT + (e >> 6)];
   }
 }
 
@@ -955,6 +1020,105 @@ __global__ void __launch_bounds__(256) k_trsv_ginv(const SysDesc* __restrict__ s
 // G_q^T (upper triangular; backward = 1), rows of the group 16 per
 // workgroup: wave w takes 4 rows, the lanes stride over the row's columns
 // inside the triangle, and a wave reduction gives each entry.
+// Apply part: z_q = G_q r_q (or x_q = G_q^T z_q), 16 rows per workgroup, the
+// wave's four rows with every load in flight at once (row r of G_q, lower
+// triangular, ends with its tile's last column; row r of G_q^T starts with
+// its tile's first; columns outside read as zero).
+__device__ __forceinline__ void gapply_part(double* sv, const SysDesc& sd, int t, const double* __restrict__ Ginv,
+                                            const double* __restrict__ vin, double* vout, int q, int backward) {
+  const int p0 = kSG * q, nv = (min(sd.P, p0 + kSG) - p0) * kNB;
+  const int base = p0 * kNB;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int k = tid; k < kGS; k += 256) sv[k] = k < nv ? vin[sd.voff + base + k] : 0.0;
+  const double* M = Ginv + sd.gioff + (int64_t)q * 2 * kGS * kGS + (backward ? (int64_t)kGS * kGS : 0);
+  const int r0 = 16 * t + 4 * w;
+  double g[4][kSG];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int r = r0 + m;
+    const int c0 = backward ? (r & ~63) : 0, c1 = backward ? nv : (r | 63) + 1;
+    const double* row = M + (int64_t)r * kGS;
+#pragma unroll
+    for (int it = 0; it < kSG; ++it) {
+      const int c = 64 * it + lane;
+      g[m][it] = (c >= c0 && c < c1) ? row[c] : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double v = 0.0;
+#pragma unroll
+    for (int it = 0; it < kSG; ++it) v += g[m][it] * sv[64 * it + lane];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) vout[sd.voff + base + r0 + m] = v;
+  }
+}
+
+// Forward update part: r_i -= L_{i,q} z_q for 16 rows i from row tile r0t on
+// (workgroup t takes rows r0t*64 + 16 t ..): one row per 16 lanes, 4
+// columns per lane of each of the group's 64-column segments, all of the
+// row's loads in flight at once.
+__device__ __forceinline__ void gfwd_part(double* sz, const SysDesc& sd, int t, const double* __restrict__ Lam,
+                                          const double* __restrict__ z, double* r, int q, int r0t) {
+  const int64_t ld = sd.Kpad;
+  const int p0 = kSG * q, nseg = min(sd.P, kSG * (q + 1)) - p0;
+  const int base = p0 * kNB;
+  const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
+  for (int k = tid; k < kGS; k += 256) sz[k] = k < nseg * kNB ? z[sd.voff + base + k] : 0.0;
+  const int i0 = r0t * kNB + 16 * t + g;
+  const double* A = Lam + sd.loff + (int64_t)i0 * ld + base + 4 * j;
+  double a[kSG][4];
+#pragma unroll
+  for (int sg = 0; sg < kSG; ++sg) {
+    if (sg < nseg) {
+      ld4(A + sg * kNB, a[sg]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[sg][u] = 0.0;
+    }
+  }
+  __syncthreads();
+  double acc = 0.0;
+#pragma unroll
+  for (int sg = 0; sg < kSG; ++sg)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += a[sg][u] * sz[sg * kNB + 4 * j + u];
+  const double v = gsum16(acc);
+  if (j == 0) r[sd.voff + i0] -= v;
+}
+
+// Backward update part: z_c -= L_{q,c}^T x_q for the 64 columns of column
+// tile c0t + t (64 columns x the group's rows, 4 row phases of 64 lanes; 32
+// loads in flight per lane and batch).
+__device__ __forceinline__ void gbwd_part(double* sx, double* sp, const SysDesc& sd, int t,
+                                          const double* __restrict__ Lam, const double* __restrict__ x, double* z,
+                                          int q, int c0t) {
+  const int64_t ld = sd.Kpad;
+  const int p0 = kSG * q, nrow = (min(sd.P, kSG * (q + 1)) - p0) * kNB;
+  const int base = p0 * kNB;
+  const int tid = threadIdx.x, cc = tid & 63, rg = tid >> 6;
+  const int ct = c0t + t;
+  for (int k = tid; k < kGS; k += 256) sx[k] = k < nrow ? x[sd.voff + base + k] : 0.0;
+  __syncthreads();
+  const double* A = Lam + sd.loff + (int64_t)base * ld + ct * kNB + cc;
+  double acc = 0.0;
+  for (int r0 = 0; r0 < kGS; r0 += 128) {
+    double a[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int rr = r0 + rg + 4 * u;
+      a[u] = rr < nrow ? A[(int64_t)rr * ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc += a[u] * sx[r0 + rg + 4 * u];
+  }
+  sp[rg * kNB + cc] = acc;
+  __syncthreads();
+  if (tid < kNB) z[sd.voff + ct * kNB + tid] -= sp[tid] + sp[kNB + tid] + sp[2 * kNB + tid] + sp[3 * kNB + tid];
+}
+
 __global__ void __launch_bounds__(256) k_trsv_gapply(const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags,
                                                      const int* __restrict__ st_sys,
@@ -965,105 +1129,38 @@ __global__ void __launch_bounds__(256) k_trsv_gapply(const SysDesc* __restrict__
   __shared__ double sv[kGS];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
-  const int t = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
-  const int p0 = kSG * q, nv = (min(sd.P, p0 + kSG) - p0) * kNB;
-  const int base = p0 * kNB;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int k = tid; k < nv; k += 256) sv[k] = vin[sd.voff + base + k];
-  __syncthreads();
-  const double* M = Ginv + sd.gioff + (int64_t)q * 2 * kGS * kGS + (backward ? (int64_t)kGS * kGS : 0);
-  const int r0 = 16 * t + 4 * w;
-  double acc[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int r = r0 + m;
-    const int c0 = backward ? (r & ~63) : 0, c1 = backward ? nv : (r | 63) + 1;
-    const double* row = M + (int64_t)r * kGS;
-    double a = 0.0;
-    for (int c = c0 + lane; c < c1; c += 64) a += row[c] * sv[c];
-    acc[m] = a;
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    double v = acc[m];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) vout[sd.voff + base + r0 + m] = v;
-  }
+  gapply_part(sv, sd, blockIdx.x - st_pre[si], Ginv, vin, vout, q, backward);
 }
 
-// r_i -= sum_{c in group q} L[i][c] z[c] for the 64 rows of row tile
-// kSG (q+1) + t: every 16-lane group takes 4 rows, each lane 4 columns of
-// every 64-column segment of the group.
 __global__ void __launch_bounds__(256) k_trsv_gfwd(const SysDesc* __restrict__ sys,
                                                    const int* __restrict__ flags,
                                                    const int* __restrict__ st_sys,
                                                    const int* __restrict__ st_pre, int cnt,
                                                    const double* __restrict__ Lam,
                                                    const double* __restrict__ z, double* r, int q) {
-  __shared__ double sz[kNB * kSG];
+  __shared__ double sz[kGS];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
-  const int t = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
-  const int64_t ld = sd.Kpad;
-  const int p0 = kSG * q, nseg = min(sd.P, kSG * (q + 1)) - p0;
-  const int base = p0 * kNB;
-  const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
-  double* rs = r + sd.voff;
-  for (int k = tid; k < nseg * kNB; k += 256) sz[k] = z[sd.voff + base + k];
-  __syncthreads();
-  const int i0 = (kSG * (q + 1) + t) * kNB + 4 * g;
-  const double* A = Lam + sd.loff + (int64_t)i0 * ld + base + 4 * j;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int sg = 0; sg < nseg; ++sg) {
-    double zq[4], a[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) zq[u] = sz[sg * kNB + 4 * j + u];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) ld4(A + (int64_t)m * ld + sg * kNB, a[m]);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc[m] += a[m][0] * zq[0] + a[m][1] * zq[1] + a[m][2] * zq[2] + a[m][3] * zq[3];
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const double v = gsum16(acc[m]);
-    if (j == 0) rs[i0 + m] -= v;
-  }
+  gfwd_part(sz, sd, blockIdx.x - st_pre[si], Lam, z, r, q, kSG * (q + 1));
 }
 
-// z_c -= sum_{rows of group q} L[row][c] x[row] for the 64 columns of column
-// tile t (t < kSG q): thread (c, rg) sums every fourth row, then the four
-// partial sums are added in LDS.
 __global__ void __launch_bounds__(256) k_trsv_gbwd(const SysDesc* __restrict__ sys,
                                                    const int* __restrict__ flags,
                                                    const int* __restrict__ st_sys,
                                                    const int* __restrict__ st_pre, int cnt,
                                                    const double* __restrict__ Lam,
                                                    const double* __restrict__ x, double* z, int q) {
-  __shared__ double sx[kNB * kSG];
+  __shared__ double sx[kGS];
   __shared__ double sp[4 * kNB];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
-  const int t = blockIdx.x - st_pre[si];
   if (!(flags[s] & F_ACTIVE)) return;
   const SysDesc sd = sys[s];
-  const int64_t ld = sd.Kpad;
-  const int p0 = kSG * q, nrow = (min(sd.P, kSG * (q + 1)) - p0) * kNB;
-  const int base = p0 * kNB;
-  const int tid = threadIdx.x, cc = tid & 63, rg = tid >> 6;
-  for (int k = tid; k < nrow; k += 256) sx[k] = x[sd.voff + base + k];
-  __syncthreads();
-  const double* A = Lam + sd.loff + (int64_t)base * ld + t * kNB + cc;
-  double acc = 0.0;
-#pragma unroll 8
-  for (int rr = rg; rr < nrow; rr += 4) acc += A[(int64_t)rr * ld] * sx[rr];
-  sp[rg * kNB + cc] = acc;
-  __syncthreads();
-  if (tid < kNB) z[sd.voff + t * kNB + tid] -= sp[tid] + sp[kNB + tid] + sp[2 * kNB + tid] + sp[3 * kNB + tid];
+  gbwd_part(sx, sp, sd, blockIdx.x - st_pre[si], Lam, x, z, q, 0);
 }
 
 // launch wrappers --------------------------------------------------------------
@@ -1103,9 +1200,16 @@ void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* La
 
 void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
                       const int* spre, int cnt, int total, const double* Lam, const double* Linv,
-                      double* Ginv) {
+                      double* Ginv, int m, int phase) {
   if (total)
-    hipLaunchKernelGGL(k_trsv_ginv, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Lam, Linv, Ginv);
+    hipLaunchKernelGGL(k_trsv_ginv, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Lam, Linv, Ginv,
+                       m, phase);
+}
+
+void launch_trsv_gfinish(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                         const int* spre, int cnt, int total, const double* Linv, double* Ginv) {
+  if (total)
+    hipLaunchKernelGGL(k_trsv_gfinish, dim3(total), dim3(256), 0, st, sys, flags, ssys, spre, cnt, Linv, Ginv);
 }
 
 void launch_trsv_gapply(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,

@@ -651,9 +651,13 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   auto tiled = [&](int s) { return !(ch->small[s] && B.sys[s].P <= kSmallP); };
   for (int s = 0; s < count; ++s)
     if (tiled(s)) B.maxNG = std::max(B.maxNG, (B.sys[s].P + kSG - 1) / kSG);
-  B.gin.add_step();
-  for (int s = 0; s < count; ++s)
-    if (tiled(s)) B.gin.add(s, (B.sys[s].P + kSG - 1) / kSG * kSG);
+  // G_q by doubling: step l (block halves of m = 2^l tiles) has kSG m / 2
+  // output tiles per group; the last step covers every tile of the group
+  for (int m = 1; m <= kSG; m *= 2) {
+    B.gin.add_step();
+    for (int s = 0; s < count; ++s)
+      if (tiled(s)) B.gin.add(s, (B.sys[s].P + kSG - 1) / kSG * (m < kSG ? kSG * m / 2 : kSG * kSG));
+  }
   for (int q = 0; q < B.maxNG; ++q) {
     B.gap.add_step();
     B.gfu.add_step();
@@ -662,7 +666,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
       const int P = B.sys[s].P;
       if (!tiled(s) || P <= kSG * q) continue;
       B.gap.add(s, (std::min(P, kSG * (q + 1)) - kSG * q) * (kNB / 16));
-      if (P > kSG * (q + 1)) B.gfu.add(s, P - kSG * (q + 1));
+      if (P > kSG * (q + 1)) B.gfu.add(s, (P - kSG * (q + 1)) * (kNB / 16));
       if (q > 0) B.gbu.add(s, kSG * q);
     }
   }
@@ -894,8 +898,16 @@ static void op_schur(Batch& B, hipStream_t st) {
 static void op_ginv(Batch& B, hipStream_t st) {
   if (B.gin.tot[0] > 0) {
     const size_t m0 = B.prof.mark();
-    launch_trsv_ginv(st, B.d_sys, B.d_flags, B.d_gin_sys, B.d_gin_pre, B.gin.cnt[0], B.gin.tot[0], B.Lam,
-                     B.Linv, B.Ginv);
+    int l = 0;
+    for (int m = 1; m < kSG; m *= 2, ++l) {
+      const int f = B.gin.first[l];
+      for (int ph = 0; ph < 2; ++ph)
+        launch_trsv_ginv(st, B.d_sys, B.d_flags, B.d_gin_sys + f, B.d_gin_pre + f, B.gin.cnt[l], B.gin.tot[l],
+                         B.Lam, B.Linv, B.Ginv, m, ph);
+    }
+    const int f = B.gin.first[l];
+    launch_trsv_gfinish(st, B.d_sys, B.d_flags, B.d_gin_sys + f, B.d_gin_pre + f, B.gin.cnt[l], B.gin.tot[l],
+                        B.Linv, B.Ginv);
     B.prof.add(PSDP_PROF_TRSV, m0, B.prof.mark());
   }
 }

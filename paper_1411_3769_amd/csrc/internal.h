@@ -185,7 +185,9 @@ void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* La
                       const int* ssys, const int* spre, int cnt, int total, int j);
 void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
                       const int* spre, int cnt, int total, const double* Lam, const double* Linv,
-                      double* Ginv);
+                      double* Ginv, int m, int phase);
+void launch_trsv_gfinish(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
+                         const int* spre, int cnt, int total, const double* Linv, double* Ginv);
 void launch_trsv_gapply(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
                         const int* spre, int cnt, int total, const double* Ginv, const double* vin,
                         double* vout, int q, int backward);
@@ -202,6 +204,7 @@ constexpr int kSmallN = 16;   // blocks up to this order take the packed small-b
 constexpr int kSmallP = 32;   // systems with at most this many Schur tiles solve in one launch
 constexpr int kSG = 8;       // panels per group of the tiled triangular solves
 constexpr int kGS = kSG * kNB;   // rows of such a group
+static_assert((kSG & (kSG - 1)) == 0, "the group inverses double block sizes");
 
 // engine entry used by the public solve / eval calls
 int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_result* res,
