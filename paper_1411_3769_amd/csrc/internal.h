@@ -202,7 +202,7 @@ void launch_trsv_small(hipStream_t st, int nsmall, const SysDesc* sys, const int
                        const double* rhs, double* x);
 constexpr int kSmallN = 16;   // blocks up to this order take the packed small-block kernels
 constexpr int kSmallP = 32;   // systems with at most this many Schur tiles solve in one launch
-constexpr int kSG = 8;       // panels per group of the tiled triangular solves
+constexpr int kSG = 16;      // panels per group of the tiled triangular solves
 constexpr int kGS = kSG * kNB;   // rows of such a group
 static_assert((kSG & (kSG - 1)) == 0, "the group inverses double block sizes");
 

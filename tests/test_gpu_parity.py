@@ -63,7 +63,8 @@ NEWTON_CASES = [(4, 3, 1, 1, 0), (10, 4, 2, 2, 1), (3, 2, 2, 1, 2), (9, 2, 1, 2,
                 (1, 3, 1, 1, 5), (20, 3, 1, 1, 6)]
 # Schur matrices of 22, 33 and 56 tiles of 64: the factorisation's depth-512
 # wide updates run, the first two with a last super-panel that absorbs a
-# short trailing run; the solves go by groups of 8 tiles
+# short trailing run; the solves go by groups of 16 tiles, the last one
+# partial in each (6, 1 and 8 tiles)
 NEWTON_BIG = [(16, 4, 2, 1, 7), (32, 4, 1, 2, 8), (48, 3, 1, 1, 9)]
 
 
