@@ -39,12 +39,17 @@ PEAK_FP64 = 78.6          # TFLOP/s, FP64 vector and FP64 matrix (MI355X)
 PEAK_HBM = 8000.0         # GB/s
 
 # HBM bytes per launch of the dominant kernel group, from the two rocprofv3
-# --pmc runs summarised in profiles/hbm_counters_n10_batch64.md (FETCH_SIZE
+# --pmc runs summarised in profiles/hbm_counters_n10_batch64.md and
+# profiles/hbm_counters_n100_fp64.md (FETCH_SIZE
 # and WRITE_SIZE in KiB per dispatch over the group's dispatches, scaled by
 # what they read for a plain 256 MiB device copy: x2.000 and x1.000).  Valid
 # for the kernel versions those runs measured; drop an entry once they change.
 PMC_TRAFFIC = {
-    ("n10", "cholesky"): dict(fetch_kib=21943.5, fetch_scale=2.000, write_kib=17995.3, write_scale=1.000),
+    # n = 10: one super-panel (8 or 16 panels give the same launches at 9 tiles)
+    ("n10", "cholesky"): dict(fetch_kib=21923.0, fetch_scale=2.000, write_kib=17995.3, write_scale=1.000,
+                              widths={8, 16}),
+    ("n100", "cholesky"): dict(fetch_kib=50493.9, fetch_scale=2.000, write_kib=35674.3, write_scale=1.000,
+                               widths={16}),
 }
 
 
@@ -104,23 +109,52 @@ def _limits(threads):
         return contextlib.nullcontext()
 
 
+def _oracle_solve(args):
+    """One full FP64 oracle solve on one host thread (a pool worker)."""
+    A, n, l, dp, d = args
+    from oracle import ipm, sdp as S
+    with _limits(1):
+        ipm.ipm_solve(S.make_sdp(A, n, l, dp, d))
+    return 1
+
+
 def cpu_baseline_solves(systems, budget_s, threads):
-    """The oracle, untuned, on the host: full solves of the first seeds of the
-    workload until about budget_s of wall time, extrapolated to the batch."""
+    """The oracle, untuned, on the host: full solves of the workload's systems
+    until about budget_s of wall time, extrapolated to the batch.  With more
+    than one thread, one system per worker process (each on one BLAS thread)
+    over `threads` processes, started fresh (spawn: nothing of this process's
+    GPU state is inherited)."""
     from oracle import ipm, sdp as S
     t0 = time.perf_counter()
     done = 0
-    with _limits(threads):
-        for sy in systems:
-            ipm.ipm_solve(S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d))
-            done += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-    el = time.perf_counter() - t0
+    if threads <= 1:
+        with _limits(1):
+            for sy in systems:
+                ipm.ipm_solve(S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d))
+                done += 1
+                if time.perf_counter() - t0 > budget_s:
+                    break
+        el = time.perf_counter() - t0
+        desc = "1 thread"
+    else:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=threads, mp_context=mp.get_context("spawn")) as ex:
+            # workers started and warm before the clock runs
+            list(ex.map(int, range(threads)))
+            t0 = time.perf_counter()
+            futs = [ex.submit(_oracle_solve, (sy.A, sy.n, sy.l, sy.dp, sy.d)) for sy in systems]
+            for f in cf.as_completed(futs):
+                done += f.result()
+                if time.perf_counter() - t0 > budget_s:
+                    break
+            el = time.perf_counter() - t0
+            for f in futs:
+                f.cancel()
+        desc = f"{threads} worker processes of one thread each"
     return dict(value=el / done * len(systems), unit="s", cores=threads, kind="oracle",
                 sample=f"{done} of {len(systems)} systems solved by the FP64 oracle "
-                       f"({el:.1f} s, {threads} thread{'s' if threads > 1 else ''}), "
-                       f"scaled by {len(systems)}/{done}")
+                       f"({el:.1f} s, {desc}), scaled by {len(systems)}/{done}")
 
 
 def cpu_baseline_iteration(sy, iterations, threads):
@@ -319,7 +353,13 @@ def main():
     else:
         roof = dict(bound="mfma", achieved=None, peak=PEAK_FP64, unit="TFLOP/s", kernel=dom)
     roof["frac"] = (roof["achieved"] / roof["peak"]) if roof.get("achieved") else None
+    # the device's attainable FP64 matrix-core rate (register-only MFMA chains)
+    att = P.fp64_mfma_rate(stream)
+    roof["attainable"] = att
+    roof["frac_attainable"] = (roof["achieved"] / att) if roof.get("achieved") and att > 0 else None
     tr = PMC_TRAFFIC.get((args.workload, dom)) if prec == "fp64" else None
+    if tr and not {r.chol_panels for r in rs} <= tr["widths"]:
+        tr = None   # the counters were taken for another factorisation
     roof["traffic"] = (1024.0 * (tr["fetch_kib"] * tr["fetch_scale"] + tr["write_kib"] * tr["write_scale"])
                        if tr else None)
     if tr:
@@ -345,6 +385,7 @@ def main():
                    "precision": prec,
                    "setup_ms_per_step": split[0] * 1e3, "solve_ms_per_step": split[1] * 1e3,
                    "hip_graph_launches_per_step": rs[0].graph_replays,
+                   "phase_seconds_last_step": rs[0].phase_times,
                    "chol_panels": sorted({r.chol_panels for r in rs}),
                    "profiled_pass_ms_per_step": prof_ms,
                    "verdicts": verdicts, "iterations_mean": float(np.mean(iters_sys)),

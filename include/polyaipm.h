@@ -248,6 +248,12 @@ typedef struct {
     int     phase1_reason;  /* exit reason (PSDP_R_*) of the phase-I run, -1 if none  */
     int     chol_panels;    /* super-panel width the Schur Cholesky used (0: left-   */
                             /* looking)                                               */
+    /* wall time of the solve call's phases (seconds; one batch shares them):   */
+    double  time_prepare_s; /* kernel-path tuning, tables, first iterate           */
+    double  time_warm_s;    /* warm-start projection (0 without a warm start)     */
+    double  time_paper_s;   /* the paper's SDP run (Alg. 2)                       */
+    double  time_phase1_s;  /* the phase-I margin SDP run (0 if no system used it)*/
+    double  time_cert_s;    /* certificate checks and the extraction of P and y   */
 } psdp_result;
 
 /* Defaults for the option structs. */
@@ -434,6 +440,14 @@ const char* psdp_last_error(void);
 
 /* Library version string. */
 const char* psdp_version(void);
+
+/* Measurement support for callers that report a roofline (not a step of the
+ * method): the attainable FP64 matrix-core rate of the current device in
+ * TFLOP/s, from independent chains of v_mfma_f64_16x16x4 on register
+ * operands at four waves per SIMD, the best of three timed launches on
+ * `stream` (synchronised before returning).  Allocates and frees a small
+ * device buffer.  EINVAL for a NULL tflops, EDEVICE on a HIP error. */
+int psdp_fp64_mfma_rate(double* tflops, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start: the network that proposes a starting point (not part of

@@ -28,6 +28,7 @@ SOURCES = {
     "engine.hip": [],
     "mlp.hip": [],
     "simplex.hip": [],
+    "probe.hip": [],
 }
 
 COMMON = [

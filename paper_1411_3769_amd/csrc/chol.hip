@@ -24,6 +24,9 @@
 //            of it gets the super-panel's whole contribution in one pass of
 //            depth 64 sw (wide update).  Both on FP64 MFMA.  sw is chosen
 //            per system (the autotuner times 4, 8 and 16).
+// Left-looking alternative (k_chol_left, below 64 tiles when the autotuner
+// finds it faster): one launch per tile column; each tile gathers its whole
+// update from the finished columns and is written once.
 // Steps are launched for the whole batch; a (step, system) table maps
 // workgroups to systems.  Triangular solves use the stored inverses, so the
 // diagonal solves are matrix-vector products.

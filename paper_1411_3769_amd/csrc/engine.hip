@@ -1682,7 +1682,16 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
       warm[s] = (o.warm_y && o.warm_y[s]) || (o.warm_logx && o.warm_logx[s]);
       anywarm = anywarm || warm[s];
     }
+  auto since = [](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+  };
+  const double t_prep = since(t0);
+  auto tw = std::chrono::steady_clock::now();
   if (anywarm && (rc = warm_project(B, st, o, warm))) return rc;
+  if (anywarm) PSDP_HIP(hipStreamSynchronize(st));
+  const double t_warm = anywarm ? since(tw) : 0.0;
+  auto tp = std::chrono::steady_clock::now();
+  double t_paper = 0.0, t_ph1 = 0.0;
   std::vector<std::vector<psdp_iter_rec>> hist(count);
   std::vector<double> logx(B.nblk, NAN);
   std::vector<RunState> rs(count);
@@ -1693,6 +1702,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
   // pass 1: the paper's SDP
   if (o.verdict_mode != PSDP_VERDICT_PHASE1_ONLY) {
     if ((rc = run_ipm(B, o, st, rs, o.record_history ? &hist : nullptr))) return rc;
+    t_paper = since(tp);
     PSDP_HIP(hipMemcpyAsync(y1.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
     {
       std::vector<int> hf(count, F_ACTIVE);
@@ -1718,6 +1728,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
   }
   std::vector<RunState> r1(count);
   for (auto& q : r1) q.max_iter = o.max_iter;
+  auto t1p = std::chrono::steady_clock::now();
   if (anyneed) {
     for (int s = 0; s < count; ++s) {
       B.sys[s].mode = need[s] ? 1 : 0;
@@ -1740,7 +1751,9 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     PSDP_HIP(hipMemcpyAsync(y2.data(), B.y, B.totvec * 8, hipMemcpyDeviceToHost, st));
     PSDP_HIP(hipStreamSynchronize(st));
     B.prof.harvest();
+    t_ph1 = since(t1p);
   }
+  auto tc = std::chrono::steady_clock::now();
 
   // verdicts; certificate vectors
   std::vector<double> ycert(B.totvec, 0.0);
@@ -1799,8 +1812,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     PSDP_HIP(hipStreamSynchronize(st));
     B.prof.harvest();
   }
-  const double elapsed =
-      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const double elapsed = since(t0), t_cert = since(tc);
   for (int s = 0; s < count; ++s) {
     psdp_sdp* p = sdps[s];
     const SysDesc& d = B.sys[s];
@@ -1822,6 +1834,11 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     R.graph_replays = B.graph_launches;
     R.phase1_reason = need[s] ? r1[s].reason : -1;
     R.chol_panels = B.use_sw[s];
+    R.time_prepare_s = t_prep;
+    R.time_warm_s = t_warm;
+    R.time_paper_s = t_paper;
+    R.time_phase1_s = t_ph1;
+    R.time_cert_s = t_cert;
     R.asm_path = B.use_pair[s] && p->n * p->n <= 128;
     R.solve_path = B.use_small[s] && d.P <= kSmallP;
     R.label_iter = r.label_iter;

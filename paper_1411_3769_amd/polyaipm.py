@@ -88,7 +88,8 @@ class CResult(C.Structure):
                 ("asm_path", C.c_int), ("solve_path", C.c_int),
                 ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int),
                 ("chol_shifts", C.c_int), ("graph_replays", C.c_int), ("phase1_reason", C.c_int),
-                ("chol_panels", C.c_int)]
+                ("chol_panels", C.c_int), ("time_prepare_s", C.c_double), ("time_warm_s", C.c_double),
+                ("time_paper_s", C.c_double), ("time_phase1_s", C.c_double), ("time_cert_s", C.c_double)]
 
 
 class BisectRec(C.Structure):
@@ -108,6 +109,7 @@ EXPORTS = ["psdp_setup_opts_default", "psdp_opts_default", "psdp_polya_setup", "
            "psdp_get_polya", "psdp_ipm_solve", "psdp_ipm_solve_batched", "psdp_ipm_solve_noalloc",
            "psdp_eval_newton", "psdp_eval_schur", "psdp_poly_on_simplex", "psdp_bisect_simplex",
            "psdp_eval_ladder", "psdp_basis", "psdp_free", "psdp_last_error", "psdp_version",
+           "psdp_fp64_mfma_rate",
            "psdp_mlp_create", "psdp_mlp_param_count", "psdp_mlp_set_params", "psdp_mlp_get_params",
            "psdp_mlp_forward", "psdp_mlp_loss_grad", "psdp_mlp_adam", "psdp_mlp_free"]
 
@@ -157,6 +159,7 @@ def load(path: str = LIB_PATH):
     lib.psdp_free.restype = None
     lib.psdp_last_error.restype = C.c_char_p
     lib.psdp_version.restype = C.c_char_p
+    lib.psdp_fp64_mfma_rate.argtypes = [C.POINTER(C.c_double), vp]
     lib.psdp_mlp_create.argtypes = [vp, C.c_int, C.c_int, C.POINTER(vp)]
     lib.psdp_mlp_param_count.argtypes = [vp]
     lib.psdp_mlp_param_count.restype = C.c_int64
@@ -371,6 +374,7 @@ class Result:
     graph_replays: int = 0
     phase1_reason: int = -1
     chol_panels: int = 0
+    phase_times: dict = field(default_factory=dict)   # wall seconds per phase of the call
 
     @property
     def verdict_name(self):
@@ -443,7 +447,9 @@ def _unpack(r: CResult, P, y, lx, hist) -> Result:
                   r.ir_steps, r.ir_eta_max, bool(r.warm_used), bool(r.warm_fallback),
                   r.warm_iterations, lx[0], lx[1] if r.label_iter >= 0 else None,
                   lx[2] if r.label_iter >= 0 else None, r.label_iter, r.asm_path, r.solve_path, h,
-                  r.chol_shifts, r.graph_replays, r.phase1_reason, r.chol_panels)
+                  r.chol_shifts, r.graph_replays, r.phase1_reason, r.chol_panels,
+                  {"prepare": r.time_prepare_s, "warm": r.time_warm_s, "paper": r.time_paper_s,
+                   "phase1": r.time_phase1_s, "cert": r.time_cert_s})
 
 
 def ipm_solve(sdp: SDP, warm_y=None, warm_logx=None, **opts) -> Result:
@@ -579,6 +585,13 @@ def bisect_simplex(exps, mats, G0, G1, l: int, dp: int, d: int, t_feas: float, t
 
 def version() -> str:
     return load().psdp_version().decode()
+
+
+def fp64_mfma_rate(stream=None) -> float:
+    """psdp_fp64_mfma_rate: attainable FP64 matrix-core TFLOP/s of the device."""
+    v = C.c_double(0.0)
+    _check(load().psdp_fp64_mfma_rate(C.byref(v), stream if stream is not None else _current_stream()))
+    return v.value
 
 
 class MLP:

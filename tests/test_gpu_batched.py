@@ -232,3 +232,18 @@ def test_batched_setup_rejects_nonfinite_device_vertices(P, mixed):
     with pytest.raises(P.PsdpError) as ei:
         P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(As, part)])
     assert "system 1" in str(ei.value) and "non-finite" in str(ei.value)
+
+
+def test_phase_times_and_mfma_rate(P):
+    """The result's per-phase wall times cover the call, and the device's
+    attainable FP64 MFMA rate is positive and below the published peak."""
+    gs = [P.polya_setup(W.c1_system(s).A, 10, 4, 2, 2) for s in range(4)]
+    rs = P.ipm_solve_batched(gs)
+    for r in rs:
+        t = r.phase_times
+        assert set(t) == {"prepare", "warm", "paper", "phase1", "cert"}
+        assert all(v >= 0 for v in t.values()) and t["paper"] > 0 and t["warm"] == 0
+        assert sum(t.values()) <= r.time_solve_s * (1 + 1e-9)
+    rate = P.fp64_mfma_rate()
+    print(f"attainable FP64 MFMA rate {rate:.1f} TFLOP/s", flush=True)
+    assert 5.0 < rate < 78.6
