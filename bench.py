@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly")
     ap.add_argument("--chol-panels", type=int, default=0,
                     help="Schur Cholesky: -1 left-looking, 1..32 super-panel width, 0 autotuned")
+    ap.add_argument("--chol-subpanels", type=int, default=0,
+                    help="with --chol-panels w: sub-panels of this width (a divisor of w), 0 none")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     ap.add_argument("--train", type=int, default=20000, help="learned: training solves")
@@ -257,7 +259,8 @@ def main():
         hs = P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)])
         t1 = time.perf_counter()
         rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=precision,
-                                 use_graph=0 if args.no_graph else 1, chol_panels=args.chol_panels)
+                                 use_graph=0 if args.no_graph else 1, chol_panels=args.chol_panels,
+                                 chol_subpanels=args.chol_subpanels)
         t2 = time.perf_counter()
         for h in hs:
             h.close()
@@ -358,7 +361,8 @@ def main():
     roof["attainable"] = att
     roof["frac_attainable"] = (roof["achieved"] / att) if roof.get("achieved") and att > 0 else None
     tr = PMC_TRAFFIC.get((args.workload, dom)) if prec == "fp64" else None
-    if tr and not {r.chol_panels for r in rs} <= tr["widths"]:
+    if tr and not ({r.chol_panels for r in rs} <= tr["widths"]
+                   and all(r.chol_subpanels == r.chol_panels for r in rs)):
         tr = None   # the counters were taken for another factorisation
     roof["traffic"] = (1024.0 * (tr["fetch_kib"] * tr["fetch_scale"] + tr["write_kib"] * tr["write_scale"])
                        if tr else None)
@@ -387,6 +391,7 @@ def main():
                    "hip_graph_launches_per_step": rs[0].graph_replays,
                    "phase_seconds_last_step": rs[0].phase_times,
                    "chol_panels": sorted({r.chol_panels for r in rs}),
+                   "chol_subpanels": sorted({r.chol_subpanels for r in rs}),
                    "profiled_pass_ms_per_step": prof_ms,
                    "verdicts": verdicts, "iterations_mean": float(np.mean(iters_sys)),
                    "lowprec_iterations_mean": float(np.mean([r.iters_lowprec for r in rs])),

@@ -198,6 +198,11 @@ typedef struct {
                              /* each tile updated once); 0 (default) = chosen per       */
                              /* tile-count bucket by the autotuner among left-looking   */
                              /* (below 64 tiles) and widths 4, 8 and 16                 */
+    int    chol_subpanels;   /* with chol_panels = w > 0: split each super-panel in     */
+                             /* sub-panels of this many panels (a divisor of w); the    */
+                             /* narrow updates stay inside a sub-panel and each         */
+                             /* sub-panel's end brings one update of depth 64 of these  */
+                             /* panels to the rest of its super-panel. 0 = none         */
 } psdp_opts;
 
 typedef struct {
@@ -248,6 +253,7 @@ typedef struct {
     int     phase1_reason;  /* exit reason (PSDP_R_*) of the phase-I run, -1 if none  */
     int     chol_panels;    /* super-panel width the Schur Cholesky used (0: left-   */
                             /* looking)                                               */
+    int     chol_subpanels; /* its sub-panel width (= chol_panels: no sub-panels)    */
     /* wall time of the solve call's phases (seconds; one batch shares them):   */
     double  time_prepare_s; /* kernel-path tuning, tables, first iterate           */
     double  time_warm_s;    /* warm-start projection (0 without a warm start)     */
@@ -350,13 +356,15 @@ int psdp_ipm_solve_noalloc(psdp_sdp* sdp, const psdp_opts* opts, psdp_result* re
  *                      the device as its lower triangle and mirrored here)
  *   LamL  [K][K]       its lower Cholesky factor (upper part zero)
  *   sol   [K]          Omega^{-1} y
- * chol_panels picks the factorisation as psdp_opts.chol_panels does (-1:
- * left-looking, 1..32: super-panel width), 0 = the default width 8.
+ * chol_panels / chol_subpanels pick the factorisation as the psdp_opts
+ * fields of those names do (-1: left-looking, 1..32: super-panel width; a
+ * divisor of it: sub-panel width), 0 = the default width 8 without
+ * sub-panels.
  * The basis order of the dual variable is the library's (see psdp_basis).
  */
 int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y,
                      double* Zi, double* BTy, double* BX, double* Lam, double* LamL,
-                     double* sol, int chol_panels, void* stream);
+                     double* sol, int chol_panels, int chol_subpanels, void* stream);
 
 /*
  * The Schur complement Omega (Alg. 2 eq. T2) assembled at a fixed iterate in

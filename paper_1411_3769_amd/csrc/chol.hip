@@ -430,11 +430,55 @@ __device__ inline void wide_block(int t, int nb, int& bi, int& bj) {
   bi = bj + u;
 }
 
+// (bi, bj) of position t among the blocks bj < ncb, bj <= bi < nrb: groups of
+// kWG block rows, column by column inside a group (the blocks of a sub-panel
+// update: every row below it, the columns up to the end of its super-panel)
+__device__ inline void tall_block(int t, int nrb, int ncb, int& bi, int& bj) {
+  int r0 = 0;
+  // groups that reach the diagonal of the column range
+  while (r0 < ncb && r0 < nrb) {
+    const int r1 = min(r0 + kWG, nrb) - 1, cend = min(ncb, r1 + 1);
+    int cnt = 0;
+    for (int c = 0; c < cend; ++c) cnt += r1 - max(r0, c) + 1;
+    if (t < cnt) {
+      for (int c = 0; c < cend; ++c) {
+        const int h = r1 - max(r0, c) + 1;
+        if (t < h) {
+          bj = c;
+          bi = max(r0, c) + t;
+          return;
+        }
+        t -= h;
+      }
+    }
+    t -= cnt;
+    r0 += kWG;
+  }
+  // below them every group is a full h x ncb rectangle
+  const int g = t / (kWG * ncb);
+  r0 += kWG * g;
+  t -= g * kWG * ncb;
+  const int h = min(r0 + kWG, nrb) - r0;
+  bj = t / h;
+  bi = r0 + t % h;
+}
+
+// last panel of the super-panel of panel q (a super-panel followed by fewer
+// than sw panels absorbs them); the host tables use the same rule
+__device__ inline int sp_end_dev(int P, int q, int sw) {
+  const int se = (q / sw) * sw + sw - 1;
+  return P - 1 - se < sw ? P - 1 : se;
+}
+
+// mid = 0: the update after super-panel p (depth sw panels, every tile right
+// of it); mid = 1: the update after sub-panel p inside a super-panel (depth
+// ssw panels, the rows below it and only the columns up to the end of the
+// super-panel, whose own update adds the whole super-panel later).
 __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __restrict__ sys,
                                                              const int* __restrict__ flags, double* Lam,
                                                              const int* __restrict__ st_sys,
                                                              const int* __restrict__ st_pre, int cnt,
-                                                             int p) {
+                                                             int p, int mid) {
   __shared__ double sa[2][kWT * kWLD];   // two stages: one is multiplied while
   __shared__ double sb[2][kWT * kWLD];   // the next is written
   const int total = gridDim.x, per = total / kXCD, rem = total % kXCD;
@@ -447,12 +491,20 @@ __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __re
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
   double* A = Lam + sd.loff;
-  int bi, bj;
-  wide_block(t, (sd.P - p - 1 + 1) / 2, bi, bj);
+  int bi, bj, cmax = sd.Kpad, dpan = sd.sw;
+  const int nrb = (sd.P - p - 1 + 1) / 2;
+  if (mid) {
+    const int se = sp_end_dev(sd.P, p, sd.sw);
+    tall_block(t, nrb, (se - p + 1) / 2, bi, bj);
+    cmax = kNB * (se + 1);
+    dpan = sd.ssw;
+  } else {
+    wide_block(t, nrb, bi, bj);
+  }
   const int q0 = p + 1;
   const int r0 = kNB * (q0 + 2 * bi), c0 = kNB * (q0 + 2 * bj);
   const int nmax = sd.Kpad;
-  const int d0 = kNB * (p - sd.sw + 1), D = kNB * sd.sw;
+  const int d0 = kNB * (p - dpan + 1), D = kNB * dpan;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int r16 = lane & 15, kq = lane >> 4;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
@@ -533,7 +585,7 @@ __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __re
       for (int q = 0; q < 4; ++q) {
         const int R = r0 + wr + 16 * a + 4 * q + kq;
         const int Cc = c0 + wc + 16 * b + r16;
-        if (R < nmax && Cc < nmax && Cc <= R) A[ix[b * 4 + q]] = cv[b * 4 + q] - acc[a][b][q];
+        if (R < nmax && Cc < cmax && Cc <= R) A[ix[b * 4 + q]] = cv[b * 4 + q] - acc[a][b][q];
       }
   }
 }
@@ -1189,10 +1241,10 @@ void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* 
 }
 
 void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
-                             const int* ssys, const int* spre, int cnt, int total, int p) {
+                             const int* ssys, const int* spre, int cnt, int total, int p, int mid) {
   if (total)
     hipLaunchKernelGGL(k_chol_update_wide, dim3(total), dim3(256), 0, st, sys, flags, Lam, ssys, spre,
-                       cnt, p);
+                       cnt, p, mid);
 }
 
 void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,

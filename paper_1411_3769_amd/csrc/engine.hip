@@ -247,7 +247,7 @@ struct Batch {
   std::vector<SysDesc> sys;
   int maxn_pair = 0, nptiles = 0;
   std::vector<int> ownP, ownK;
-  StepTab pan, trs, upd, wide;
+  StepTab pan, trs, upd, wide, mid;
   StepTab lft;   // left-looking factorisation, one step per tile column
   // grouped solves of the systems not solved in one workgroup: per group q,
   // the diagonal-block sweeps (one per system), the row tiles below the
@@ -275,6 +275,7 @@ struct Batch {
   int *d_pan_sys = nullptr, *d_pan_pre = nullptr, *d_upd_sys = nullptr, *d_upd_pre = nullptr;
   int *d_trs_sys = nullptr, *d_trs_pre = nullptr, *d_wide_sys = nullptr, *d_wide_pre = nullptr;
   int *d_lft_sys = nullptr, *d_lft_pre = nullptr;
+  int *d_mid_sys = nullptr, *d_mid_pre = nullptr;
   int *d_gin_sys = nullptr, *d_gin_pre = nullptr, *d_gap_sys = nullptr, *d_gap_pre = nullptr;
   int *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr, *d_gbu_pre = nullptr;
   int* d_flags = nullptr;
@@ -289,7 +290,7 @@ struct Batch {
   bool any_phase1 = false;
   bool use_graph = false;   // replay each iteration's launches from hipGraphs
   std::vector<char> use_pair, use_small;   // kernel paths per system
-  std::vector<int> use_sw;
+  std::vector<int> use_sw, use_ssw;
   bool f32 = false;   // precision form: reduced-precision Schur assembly + refinement
   int prec = PSDP_PREC_FP64;
   int ir_max = 0;
@@ -355,6 +356,7 @@ static size_t tabsize(const std::vector<T>& v) {
 struct Choice {
   std::vector<char> pair, small;
   std::vector<int> sw;   // Schur Cholesky panels per super-panel (0: left-looking)
+  std::vector<int> ssw;  // panels per sub-panel inside a super-panel (= sw: none)
 };
 
 static Choice default_choice(psdp_sdp* const* sdps, int count) {
@@ -363,6 +365,7 @@ static Choice default_choice(psdp_sdp* const* sdps, int count) {
     c.pair.push_back(sdps[s]->n * sdps[s]->n <= 128);
     c.small.push_back(sdps[s]->Kpad / kNB <= kSmallP);
     c.sw.push_back(kSW);
+    c.ssw.push_back(kSW);
   }
   return c;
 }
@@ -378,6 +381,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.use_pair = ch->pair;
   B.use_small = ch->small;
   B.use_sw = ch->sw;
+  B.use_ssw = ch->ssw;
   B.S = count;
   B.sd.assign(sdps, sdps + count);
   // ---- per-system layout
@@ -397,6 +401,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     d.n = n; d.L0 = p->L0; d.L = p->L; d.M = p->M; d.Nt = p->Nt; d.nb = p->nb;
     d.K = (int)p->K; d.Kpad = (int)p->Kpad; d.P = d.Kpad / kNB; d.mode = 0;
     d.sw = ch->sw[s];
+    d.ssw = ch->ssw[s] > 0 && d.sw > 0 && d.sw % ch->ssw[s] == 0 ? ch->ssw[s] : d.sw;
     d.blk0 = (int)H.blk.size();
     d.boff = curblk;
     for (int j = 0; j < p->nb; ++j) {
@@ -611,6 +616,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.trs.add_step();
     B.upd.add_step();
     B.wide.add_step();
+    B.mid.add_step();
     B.lft.add_step();
 
     // last column of the narrow update of step q (super-panel end; a
@@ -619,6 +625,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     auto sp_end = [](int P, int q, int sw) {
       const int se = (q / sw) * sw + sw - 1;
       return P - 1 - se < sw ? P - 1 : se;
+    };
+    // last panel of the sub-panel of q (sub-panels split a super-panel in
+    // runs of ssw panels; the narrow updates stay inside one)
+    auto sub_end = [&](int P, int q, int sw, int ssw) {
+      return std::min(sp_end(P, q, sw), (q / ssw) * ssw + ssw - 1);
     };
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
@@ -629,15 +640,21 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
       }
       // after a narrow update of step pstep - 1 its workgroup of tile
       // (pstep, pstep) has already factored the diagonal tile
-      const int sw = B.sys[s].sw;
-      if (pstep == 0 || sp_end(P, pstep - 1, sw) < pstep) B.pan.add(s, 1);
+      const int sw = B.sys[s].sw, ssw = B.sys[s].ssw;
+      if (pstep == 0 || sub_end(P, pstep - 1, sw, ssw) < pstep) B.pan.add(s, 1);
       const int T = P - pstep - 1;
       if (T > 0) B.trs.add(s, T);
-      // narrow update: columns p+1 .. end of the super-panel
-      const int se = sp_end(P, pstep, sw);
+      // narrow update: columns p+1 .. end of the sub-panel
+      const int se = sp_end(P, pstep, sw), sse = sub_end(P, pstep, sw, ssw);
       int nn = 0;
-      for (int j = pstep + 1; j <= se; ++j) nn += P - j;
+      for (int j = pstep + 1; j <= sse; ++j) nn += P - j;
       if (nn > 0) B.upd.add(s, nn);
+      // sub-panel update after a sub-panel's last panel: rows below it,
+      // columns up to the super-panel's end, in 128 x 128 blocks
+      if (pstep == sse && pstep < se) {
+        const int nrb = (P - pstep) / 2, ncb = (se - pstep + 1) / 2;
+        B.mid.add(s, ncb * nrb - ncb * (ncb - 1) / 2);
+      }
       // wide update after the super-panel's last panel
       if (pstep == se && pstep % sw == sw - 1 && pstep < P - 1) {
         const int nb2 = (P - pstep - 1 + 1) / 2;
@@ -681,6 +698,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(B.pan.sys) + tabsize(B.pan.pre) + tabsize(B.upd.sys) + tabsize(B.upd.pre);
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
   tb += tabsize(B.lft.sys) + tabsize(B.lft.pre);
+  tb += tabsize(B.mid.sys) + tabsize(B.mid.pre);
   tb += tabsize(B.gin.sys) + tabsize(B.gin.pre) + tabsize(B.gap.sys) + tabsize(B.gap.pre);
   tb += tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
@@ -764,6 +782,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.upd.pre, &B.d_upd_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.lft.sys, &B.d_lft_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.lft.pre, &B.d_lft_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.mid.sys, &B.d_mid_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.mid.pre, &B.d_mid_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.sys, &B.d_gin_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.pre, &B.d_gin_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gap.sys, &B.d_gap_sys))) return rc;
@@ -927,12 +947,18 @@ static void op_factor(Batch& B, hipStream_t st) {
       launch_chol_update(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.d_upd_sys + g, B.d_upd_pre + g,
                          B.upd.cnt[p], B.upd.tot[p], p);
     }
+    if (B.mid.tot[p] > 0) {
+      const int g = B.mid.first[p];
+      launch_chol_update_wide(st, B.d_sys, B.d_flags, B.Lam, B.d_mid_sys + g, B.d_mid_pre + g,
+                              B.mid.cnt[p], B.mid.tot[p], p, 1);
+    }
     if (B.wide.tot[p] > 0) {
       const int g = B.wide.first[p];
       launch_chol_update_wide(st, B.d_sys, B.d_flags, B.Lam, B.d_wide_sys + g, B.d_wide_pre + g,
-                              B.wide.cnt[p], B.wide.tot[p], p);
+                              B.wide.cnt[p], B.wide.tot[p], p, 0);
     }
-    if (B.upd.tot[p] > 0 || B.wide.tot[p] > 0) B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
+    if (B.upd.tot[p] > 0 || B.mid.tot[p] > 0 || B.wide.tot[p] > 0)
+      B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
     if (B.lft.tot[p] > 0) {
       const int g = B.lft.first[p];
       const size_t m2 = B.prof.mark();
@@ -1490,26 +1516,36 @@ static int sw_bucket(int P) {
   return b;
 }
 
-// candidates of a bucket: left-looking (0) below kLeftMaxP tiles, and the
-// super-panel widths where a super-panel fits
+// candidates of a bucket, as sw | ssw << 8: left-looking (0) below kLeftMaxP
+// tiles, and the super-panel widths where a super-panel fits (sub-panels are
+// an explicit option only: at K = 20200 widths 16 in sub-panels of 4 or 8
+// took 2.07 and 2.04 s against 2.02 s per certificate without)
+static int fact_code(int sw, int ssw) { return sw | (ssw << 8); }
 static std::vector<int> sw_candidates(int bucket) {
   std::vector<int> c;
   if ((1 << bucket) < kLeftMaxP) c.push_back(0);
   if ((2 << bucket) > 8) {
-    c.push_back(4);
-    c.push_back(8);
-    c.push_back(16);
+    c.push_back(fact_code(4, 4));
+    c.push_back(fact_code(8, 8));
+    c.push_back(fact_code(16, 16));
   } else {
-    c.push_back(kSW);
+    c.push_back(fact_code(kSW, kSW));
   }
   return c;
+}
+
+// the factorisation an option pair asks for: chol_panels -1 = left-looking,
+// w > 0 = width w with sub-panels of chol_subpanels (0: none)
+static void forced_fact(const psdp_opts& o, int& sw, int& ssw) {
+  sw = o.chol_panels < 0 ? 0 : o.chol_panels;
+  ssw = o.chol_subpanels > 0 ? o.chol_subpanels : sw;
 }
 
 static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hipStream_t st,
                        Choice& ch) {
   ch = default_choice(sdps, count);
   if (o.chol_panels != 0)
-    for (int s = 0; s < count; ++s) ch.sw[s] = o.chol_panels < 0 ? 0 : o.chol_panels;
+    for (int s = 0; s < count; ++s) forced_fact(o, ch.sw[s], ch.ssw[s]);
   for (int s = 0; s < count; ++s) {
     const bool can_pair = sdps[s]->n * sdps[s]->n <= 128;
     const bool can_small = sdps[s]->Kpad / kNB <= kSmallP;
@@ -1537,13 +1573,16 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
       // candidates: the two paths (kinds 0, 1) or factorisations (kind 2)
       const std::vector<int> widths = kind == 2 ? sw_candidates(kv.first) : std::vector<int>{};
       const int nv = kind == 2 ? (int)widths.size() : 2;
-      float t[4] = {0.f, 0.f, 0.f, 0.f};
+      float t[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       for (int v = 0; v < nv; ++v) {
         Choice c = default_choice(sub.data(), cnt);
         for (int i = 0; i < cnt; ++i) {
           if (kind == 0) c.pair[i] = (char)v;
           else if (kind == 1) c.small[i] = (char)v;
-          else c.sw[i] = widths[v];
+          else {
+            c.sw[i] = widths[v] & 255;
+            c.ssw[i] = widths[v] >> 8;
+          }
         }
         Batch T;
         if (int rc = trial_batch(T, sub.data(), cnt, c, st)) return rc;
@@ -1585,7 +1624,10 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
     }
     if (o.chol_panels == 0 && sw_bucket(P) > 0) {
       auto it = g_tune.find({2, sw_bucket(P)});
-      if (it != g_tune.end()) ch.sw[s] = it->second;
+      if (it != g_tune.end()) {
+        ch.sw[s] = it->second & 255;
+        ch.ssw[s] = it->second >> 8;
+      }
     }
   }
   return PSDP_OK;
@@ -1642,6 +1684,8 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     return fail(PSDP_EINVAL, "invalid sigma_rule");
   if (o.chol_panels < -1 || o.chol_panels > 32)
     return fail(PSDP_EINVAL, "chol_panels must lie in [-1, 32]");
+  if (o.chol_subpanels < 0 || (o.chol_subpanels > 0 && (o.chol_panels <= 0 || o.chol_panels % o.chol_subpanels)))
+    return fail(PSDP_EINVAL, "chol_subpanels must divide a chol_panels width (0: none)");
   // all work runs on a private stream (capturable into graphs) ordered
   // after the caller's stream; the allocation-free solve uses the caller's
   SolveStream ss;
@@ -1668,7 +1712,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     for (int s = 0; s < count; ++s) {
       if (o.asm_path >= 0) ch.pair[s] = sdps[s]->n * sdps[s]->n <= 128 && o.asm_path == 1;
       if (o.solve_path >= 0) ch.small[s] = sdps[s]->Kpad / kNB <= kSmallP && o.solve_path == 1;
-      if (o.chol_panels != 0) ch.sw[s] = o.chol_panels < 0 ? 0 : o.chol_panels;
+      if (o.chol_panels != 0) forced_fact(o, ch.sw[s], ch.ssw[s]);
     }
   } else if ((rc = tune_choice(sdps, count, o, st, ch))) {
     return rc;
@@ -1834,6 +1878,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     R.graph_replays = B.graph_launches;
     R.phase1_reason = need[s] ? r1[s].reason : -1;
     R.chol_panels = B.use_sw[s];
+    R.chol_subpanels = B.sys[s].ssw;
     R.time_prepare_s = t_prep;
     R.time_warm_s = t_warm;
     R.time_paper_s = t_paper;
@@ -1941,10 +1986,13 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
 
 int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y, double* Zi,
                 double* BTy, double* BX, double* Lam, double* LamL, double* sol, int chol_panels,
-                hipStream_t st) {
+                int chol_subpanels, hipStream_t st) {
   Batch B;
   Choice ch = default_choice(&sdp, 1);
-  if (chol_panels != 0) ch.sw[0] = chol_panels < 0 ? 0 : chol_panels;
+  if (chol_panels != 0) {
+    ch.sw[0] = chol_panels < 0 ? 0 : chol_panels;
+    ch.ssw[0] = chol_subpanels > 0 ? chol_subpanels : ch.sw[0];
+  }
   int rc = build_batch(B, &sdp, 1, &ch);
   if (rc) return rc;
   if ((rc = init_state(B, st))) return rc;

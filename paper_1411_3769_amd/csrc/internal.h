@@ -68,7 +68,8 @@ constexpr double kIrSwitch = 1e-1;
 struct SysDesc {
   int n, L0, L, M, Nt, nb, P, mode;   // P = Kpad / kNB; mode 0 paper SDP, 1 phase-I
   int K, Kpad, blk0, npairs_hm;
-  int sw, spare;    // Schur Cholesky: panels per super-panel (wide update depth 64 sw)
+  int sw, ssw;      // Schur Cholesky: panels per super-panel (wide update depth 64 sw) and
+                    // per sub-panel inside it (its update depth 64 ssw; ssw = sw: none)
   int64_t boff;     // block arena offset (doubles) of the system's first block
   int64_t voff;     // vector offset (Kpad entries per vector)
   int64_t loff;     // Schur matrix offset (Kpad * Kpad)
@@ -178,7 +179,7 @@ void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, doub
                       const double* Linv, const int* ssys, const int* spre, int cnt, int total,
                       int p);
 void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
-                             const int* ssys, const int* spre, int cnt, int total, int p);
+                             const int* ssys, const int* spre, int cnt, int total, int p, int mid);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
                         double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
@@ -211,7 +212,7 @@ int solve_batch(psdp_sdp* const* sdps, int count, const psdp_opts* opts, psdp_re
                 bool noalloc = false);
 int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y, double* Zi,
                 double* BTy, double* BX, double* Lam, double* LamL, double* sol, int chol_panels,
-                hipStream_t stream);
+                int chol_subpanels, hipStream_t stream);
 int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opts* o,
                 double* step, int* kstar);
 int eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, double* Lam,

@@ -292,6 +292,7 @@ void psdp_opts_default(psdp_opts* o) {
   o->stop_rule = PSDP_STOP_RELATIVE;
   o->sigma_rule = PSDP_SIGMA_FIXED;
   o->chol_panels = 0;
+  o->chol_subpanels = 0;
 }
 
 const char* psdp_last_error(void) { return g_err.c_str(); }
@@ -644,10 +645,13 @@ int psdp_ipm_solve_batched(psdp_sdp* const* sdps, int count, const psdp_opts* op
 
 int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y,
                      double* Zi, double* BTy, double* BX, double* Lam, double* LamL, double* sol,
-                     int chol_panels, void* stream) {
+                     int chol_panels, int chol_subpanels, void* stream) {
   if (!sdp || !X || !Z || !y) return fail(PSDP_EINVAL, "NULL argument");
   if (chol_panels < -1 || chol_panels > 32) return fail(PSDP_EINVAL, "chol_panels must lie in [-1, 32]");
-  return eval_newton(sdp, X, Z, y, Zi, BTy, BX, Lam, LamL, sol, chol_panels, (hipStream_t)stream);
+  if (chol_subpanels < 0 || (chol_subpanels > 0 && (chol_panels <= 0 || chol_panels % chol_subpanels)))
+    return fail(PSDP_EINVAL, "chol_subpanels must divide a chol_panels width (0: none)");
+  return eval_newton(sdp, X, Z, y, Zi, BTy, BX, Lam, LamL, sol, chol_panels, chol_subpanels,
+                     (hipStream_t)stream);
 }
 
 int psdp_eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, double* Lam,

@@ -64,7 +64,7 @@ class Opts(C.Structure):
                 ("solve_path", C.c_int), ("use_graph", C.c_int),
                 ("label_gap", C.c_double), ("chol_shift_max", C.c_double),
                 ("chol_shift_force", C.c_double), ("stop_rule", C.c_int), ("sigma_rule", C.c_int),
-                ("chol_panels", C.c_int)]
+                ("chol_panels", C.c_int), ("chol_subpanels", C.c_int)]
 
 
 class IterRec(C.Structure):
@@ -88,7 +88,8 @@ class CResult(C.Structure):
                 ("asm_path", C.c_int), ("solve_path", C.c_int),
                 ("history", C.POINTER(IterRec)), ("history_cap", C.c_int), ("history_len", C.c_int),
                 ("chol_shifts", C.c_int), ("graph_replays", C.c_int), ("phase1_reason", C.c_int),
-                ("chol_panels", C.c_int), ("time_prepare_s", C.c_double), ("time_warm_s", C.c_double),
+                ("chol_panels", C.c_int), ("chol_subpanels", C.c_int),
+                ("time_prepare_s", C.c_double), ("time_warm_s", C.c_double),
                 ("time_paper_s", C.c_double), ("time_phase1_s", C.c_double), ("time_cert_s", C.c_double)]
 
 
@@ -150,7 +151,7 @@ def load(path: str = LIB_PATH):
                                         C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(SetupOpts),
                                         C.POINTER(Opts), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(BisectRec), C.c_int, C.POINTER(C.c_int)]
-    lib.psdp_eval_newton.argtypes = [vp] * 10 + [C.c_int, vp]
+    lib.psdp_eval_newton.argtypes = [vp] * 10 + [C.c_int, C.c_int, vp]
     lib.psdp_eval_schur.argtypes = [vp, vp, vp, C.c_int, vp, vp]
     lib.psdp_eval_ladder.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double),
                                      C.POINTER(C.c_int)]
@@ -374,6 +375,7 @@ class Result:
     graph_replays: int = 0
     phase1_reason: int = -1
     chol_panels: int = 0
+    chol_subpanels: int = 0
     phase_times: dict = field(default_factory=dict)   # wall seconds per phase of the call
 
     @property
@@ -447,7 +449,7 @@ def _unpack(r: CResult, P, y, lx, hist) -> Result:
                   r.ir_steps, r.ir_eta_max, bool(r.warm_used), bool(r.warm_fallback),
                   r.warm_iterations, lx[0], lx[1] if r.label_iter >= 0 else None,
                   lx[2] if r.label_iter >= 0 else None, r.label_iter, r.asm_path, r.solve_path, h,
-                  r.chol_shifts, r.graph_replays, r.phase1_reason, r.chol_panels,
+                  r.chol_shifts, r.graph_replays, r.phase1_reason, r.chol_panels, r.chol_subpanels,
                   {"prepare": r.time_prepare_s, "warm": r.time_warm_s, "paper": r.time_paper_s,
                    "phase1": r.time_phase1_s, "cert": r.time_cert_s})
 
@@ -494,7 +496,7 @@ def ipm_solve_batched(sdps: Sequence[SDP], warm_y=None, warm_logx=None, **opts) 
 
 
 def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, chol_panels=0,
-                stream=None) -> dict:
+                chol_subpanels=0, stream=None) -> dict:
     X = np.ascontiguousarray(X, dtype=np.float64)
     Z = np.ascontiguousarray(Z, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
@@ -504,7 +506,8 @@ def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, chol_pane
     st = stream if stream is not None else _current_stream()
     _check(load().psdp_eval_newton(sdp.handle, _ptr(X), _ptr(Z), _ptr(y), _ptr(out["Zi"]),
                                    _ptr(out["BTy"]), _ptr(out["BX"]), _ptr(out["Lam"]),
-                                   _ptr(out["LamL"]), _ptr(out["sol"]), int(chol_panels), st))
+                                   _ptr(out["LamL"]), _ptr(out["sol"]), int(chol_panels),
+                                   int(chol_subpanels), st))
     return out
 
 

@@ -161,25 +161,26 @@ def test_kernel_paths_match_oracle(P, asm_path, solve_path):
             assert r.solve_path == solve_path
 
 
-@pytest.mark.parametrize("chol_panels", [-1, 4, 16])
-def test_factorisations_match_oracle(P, chol_panels):
-    """The left-looking factorisation (-1) and super-panel widths 4 and 16
-    give the oracle's end points on n = 10 systems (9 tiles of 64) and on
-    the mixed batch's members with stored end points."""
+@pytest.mark.parametrize("chol_panels,sub", [(-1, 0), (4, 0), (16, 0), (8, 4)])
+def test_factorisations_match_oracle(P, chol_panels, sub):
+    """The left-looking factorisation (-1), super-panel widths 4 and 16, and
+    width 8 in sub-panels of 4 give the oracle's end points on n = 10 systems
+    (9 tiles of 64) and on the mixed batch's members with stored end points."""
     with open(os.path.join(GOLDEN, "oracle_results.json")) as fh:
         recs = {r["seed"]: r for r in json.load(fh) if r["tag"] == "n10"}
     seeds = [0, 9, 17, 33]
     gs = [P.polya_setup(W.c1_system(s).A, 10, 4, 2, 2) for s in seeds]
     print(f"chol_panels={chol_panels}", flush=True)
-    rs = P.ipm_solve_batched(gs, chol_panels=chol_panels)
+    rs = P.ipm_solve_batched(gs, chol_panels=chol_panels, chol_subpanels=sub)
     for s, r in zip(seeds, rs):
         _check(recs[s], r)
         assert r.chol_panels == (0 if chol_panels < 0 else chol_panels)
+        assert r.chol_subpanels == (sub or r.chol_panels)
     gold = _golden_mixed()
     mixed = W.mixed_systems(512)
     idx = sorted(gold)[:64]
     gs = [P.polya_setup(mixed[i].A, mixed[i].n, mixed[i].l, mixed[i].dp, mixed[i].d) for i in idx]
-    rs = P.ipm_solve_batched(gs, chol_panels=chol_panels)
+    rs = P.ipm_solve_batched(gs, chol_panels=chol_panels, chol_subpanels=sub)
     for i, r in zip(idx, rs):
         _check(gold[i], r)
 

@@ -3,7 +3,8 @@
 Bit-exact: beta, the integer H weights, H itself, the block scales and C.
 FP64 hot-path steps at fixed positive definite iterates: Z^{-1}, B^T(y),
 B(X), the Schur complement, its Cholesky factor and a solve (relative 1e-12;
-the factor by the right-looking tiled form and by the left-looking one), and
+the factor by the right-looking tiled form, with and without sub-panels, and
+by the left-looking one), and
 the step ladder (identical rung).  End to end: same verdict, objective
 and certificate margin within 1e-6 relative.
 """
@@ -68,7 +69,9 @@ NEWTON_CASES = [(4, 3, 1, 1, 0), (10, 4, 2, 2, 1), (3, 2, 2, 1, 2), (9, 2, 1, 2,
 NEWTON_BIG = [(16, 4, 2, 1, 7), (32, 4, 1, 2, 8), (48, 3, 1, 1, 9)]
 
 
-@pytest.mark.parametrize("chol", [0, -1])
+# factorisations: default right-looking (width 8), left-looking, and widths
+# 16 / 8 split in sub-panels of 4 (sub-panel updates of depth 256)
+@pytest.mark.parametrize("chol", [(0, 0), (-1, 0), (16, 4), (8, 4)])
 @pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES + NEWTON_BIG)
 def test_newton_step_parity(P, n, l, dp, d, seed, chol):
     _flush(f"newton n={n} l={l} dp={dp} d={d} seed={seed} chol_panels={chol}")
@@ -81,7 +84,7 @@ def test_newton_step_parity(P, n, l, dp, d, seed, chol):
     y_or = rng.standard_normal(o.K)
     perm = _perm(g, n, o.L0)
     y_lib = y_or[perm]
-    out = P.eval_newton(g, X, Z, y_lib, chol_panels=chol)
+    out = P.eval_newton(g, X, Z, y_lib, chol_panels=chol[0], chol_subpanels=chol[1])
     Zi = np.linalg.inv(Z)
     assert np.abs(out["Zi"] - Zi).max() <= 1e-12 * np.abs(Zi).max()
     BT = o.BT(y_or)
