@@ -22,6 +22,9 @@ IEEE TAC 2013):
 * ``stability``  the homogeneous representation of A on a translated
   simplex (Section II and the regions of Section V, Examples 1 and 2) and
   the bisection over the region's size; a brute-force spectral boundary.
+* ``discrete``  the discrete-time form (x+ = A(alpha) x) as an instance of
+  the generalized LMI of Section III-C: 2n x 2n derivative blocks
+  [[b P, P H], [H^T P, b P]] with basis matrices blockdiag(E_b, E_b).
 * ``mlp``    the FP64 network of the learned warm start.
 
 Parity pins live under ``tests/`` (marker ``not gpu``).  Functions whose

@@ -131,7 +131,7 @@ class PaperOps:
     def __init__(self, sdp: PolyaSDP):
         self.sdp = sdp
         self.K = sdp.K
-        self.n = sdp.n
+        self.n = sdp.bn
         self.nb = sdp.nb
         self.C = sdp.C_blocks()
         self.a = sdp.a()
@@ -143,7 +143,7 @@ class PaperOps:
         return self.sdp.B(W)
 
     def schur(self, X, Zi):
-        return schur_expanded(self.sdp, X, Zi)
+        return self.sdp.schur(X, Zi)
 
     def init_y(self):
         return np.zeros(self.K)
@@ -164,7 +164,7 @@ class Phase1Ops:
     def __init__(self, sdp: PolyaSDP):
         self.sdp = sdp
         self.K = sdp.K
-        self.n = sdp.n
+        self.n = sdp.bn
         self.nb = sdp.nb
         self.D = sdp.scale
         eK = np.zeros(sdp.K)
@@ -199,7 +199,7 @@ class Phase1Ops:
         return out
 
     def schur(self, X, Zi):
-        Lm = schur_expanded(self.sdp, X, Zi)
+        Lm = self.sdp.schur(X, Zi)
         K = self.K
         out = np.empty((K, K))
         out[:-1, :-1] = Lm[:-1, :-1] - Lm[:-1, -1:] - Lm[-1:, :-1] + Lm[-1, -1]
@@ -436,7 +436,7 @@ def warm_start_point(sdp: PolyaSDP, y0: np.ndarray, logx: Optional[np.ndarray] =
     lambda_min(B^T(y0)_j - C_j)) (s'_j the block scale), so that Z_j >=
     margin s'_j I; X_j = exp(s_j) n Z_j^{-1} / tr(Z_j^{-1}) (center) or
     exp(s_j) I.  lambda_min is taken from the symmetric eigensolver."""
-    nb, n = sdp.nb, sdp.n
+    nb, n = sdp.nb, sdp.bn
     s = np.zeros(nb) if logx is None else np.asarray(logx, dtype=np.float64)
     W = sdp.BT(np.asarray(y0, dtype=np.float64)) - sdp.C_blocks()
     X = np.empty_like(W)
@@ -477,7 +477,7 @@ def ipm_solve(sdp: PolyaSDP, opt: Optional[Options] = None, warm=None,
                 return res
         elif r.reason == FARKAS:
             nanv = float("nan")
-            res = SolveResult(INFEASIBLE, np.zeros((sdp.L0, sdp.n, sdp.n)), r.y, r.phi, r.psi,
+            res = SolveResult(INFEASIBLE, np.zeros((sdp.L0, sdp.pn, sdp.pn)), r.y, r.phi, r.psi,
                               r.gap_abs, r.gap_rel, r.pinf, r.dinf, nanv, nanv, nanv, r.iterations,
                               r.reason)
             res.warm_used, res.warm_iterations = True, r.iterations
@@ -495,7 +495,7 @@ def _solve_cold(sdp: PolyaSDP, opt: Options) -> SolveResult:
     UNKNOWN)."""
     opt = opt or Options()
     nanv = float("nan")
-    zeroP = np.zeros((sdp.L0, sdp.n, sdp.n))
+    zeroP = np.zeros((sdp.L0, sdp.pn, sdp.pn))
     if opt.verdict_mode != "phase1_only":
         r = ipm_run(PaperOps(sdp), opt)
         if r.reason == CONVERGED:

@@ -91,6 +91,16 @@ class PolyaSDP:
         return self.L + self.M
 
     @property
+    def bn(self) -> int:
+        """Order of every block of the SDP."""
+        return self.n
+
+    @property
+    def pn(self) -> int:
+        """Order of the coefficients P_h (the system's n)."""
+        return self.n
+
+    @property
     def m(self) -> int:
         return self.nb * self.n
 
@@ -191,6 +201,10 @@ class PolyaSDP:
 
     def dense_C(self) -> np.ndarray:
         return np.diag(np.repeat(self.cdiag, self.n))
+
+    def schur(self, X: np.ndarray, Zi: np.ndarray) -> np.ndarray:
+        """The Schur complement (eq. T2) by the expanded Kronecker form."""
+        return schur_expanded(self, X, Zi)
 
     def active_pairs(self, m: int) -> List[int]:
         """h with H_{h,m} not identically zero (gamma_m >= h componentwise)."""
