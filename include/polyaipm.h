@@ -90,6 +90,19 @@ extern "C" {
 
 typedef struct psdp_sdp psdp_sdp;  /* opaque handle: one structured SDP */
 
+/* stability notion (psdp_setup_opts.form).
+ * CONTINUOUS: x' = A(alpha) x, the Lyapunov LMIs of Theorem 1 (Section III).
+ * DISCRETE:   x+ = A(alpha) x, as an instance of the generalized LMI of
+ *   Section III-C: P(alpha) > 0 and [[P, P A], [A^T P, P]] > 0 (equivalent
+ *   to A^T P A - P < 0).  Every block of the SDP has order 2n: the Polya
+ *   coefficient for gamma in W_{dp+da+d2} is
+ *   [[b P_h, P_h H], [H^T P_h, b P_h]] summed over h, with
+ *   b_{h,gamma} = (da+d2)!/(gamma-h)! and H_{h,gamma} as in the continuous
+ *   set-up; the P-blocks hold blockdiag(beta P, beta P).  y, K and the
+ *   objective are unchanged (P_h stays n x n). */
+#define PSDP_FORM_CONTINUOUS 0
+#define PSDP_FORM_DISCRETE   1
+
 typedef struct {
     int    da;            /* degree of A(alpha); 1 = affine, A holds the l vertices  */
     int    d1, d2;        /* Polya exponents; -1 = take d from psdp_polya_setup      */
@@ -97,6 +110,7 @@ typedef struct {
     double eps;           /* derivative-block margin eps * s_j * I (1e-3)            */
     int    paper_literal; /* 1: derivative blocks of C are 0 as printed (eq. Cj)     */
     int    a_on_device;   /* 1: the A pointer is a device address                    */
+    int    form;          /* PSDP_FORM_* (CONTINUOUS)                                 */
 } psdp_setup_opts;
 
 typedef struct {
@@ -109,6 +123,8 @@ typedef struct {
     int64_t K;            /* L0 * Nt              (eq. K)  */
     int64_t Kpad;         /* K rounded up to the Schur tile */
     int64_t device_bytes; /* device memory one solve of this SDP needs */
+    int form;             /* PSDP_FORM_*                    */
+    int bo;               /* order of every block: n, or 2n (discrete form) */
 } psdp_dims;
 
 /* launch classes timed with HIP events when psdp_opts.prof is set */

@@ -359,10 +359,15 @@ struct Choice {
   std::vector<int> ssw;  // panels per sub-panel inside a super-panel (= sw: none)
 };
 
+// the whole-pair assembly kernel serves continuous-form blocks of order
+// n with n^2 <= 128 (the discrete form's terms sit on two diagonal copies of
+// each block, which only the grouped kernel reads)
+static bool pair_ok(const psdp_sdp* p) { return p->form == PSDP_FORM_CONTINUOUS && p->n * p->n <= 128; }
+
 static Choice default_choice(psdp_sdp* const* sdps, int count) {
   Choice c;
   for (int s = 0; s < count; ++s) {
-    c.pair.push_back(sdps[s]->n * sdps[s]->n <= 128);
+    c.pair.push_back(pair_ok(sdps[s]));
     c.small.push_back(sdps[s]->Kpad / kNB <= kSmallP);
     c.sw.push_back(kSW);
     c.ssw.push_back(kSW);
@@ -392,13 +397,15 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.ownK.push_back(0);
   for (int s = 0; s < count; ++s) {
     psdp_sdp* p = sdps[s];
-    const int n = p->n;
+    const int n = p->bo;   // block order
     const int64_t nn = (int64_t)n * n;
     B.maxn = std::max(B.maxn, n);
     if (n <= kSmallN) B.nmax_small = std::max(B.nmax_small, n);
     else B.nmin_big = kSmallN + 1;
     SysDesc d{};
     d.n = n; d.L0 = p->L0; d.L = p->L; d.M = p->M; d.Nt = p->Nt; d.nb = p->nb;
+    d.nbas = p->n;
+    d.copies = n / p->n;
     d.K = (int)p->K; d.Kpad = (int)p->Kpad; d.P = d.Kpad / kNB; d.mode = 0;
     d.sw = ch->sw[s];
     d.ssw = ch->ssw[s] > 0 && d.sw > 0 && d.sw % ch->ssw[s] == 0 ? ch->ssw[s] : d.sw;
@@ -419,7 +426,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
       curgi += (int64_t)((d.P + kSG - 1) / kSG) * 2 * kGS * kGS;
     }
     d.poff = curP; curP += p->L0 * nn;
-    d.H = p->dH; d.betaf = p->dbetaf; d.cdiag = p->dcdiag; d.scale = p->dscale; d.basis = p->dbasis;
+    d.H = p->dHh; d.betaf = p->dbetaf; d.cdiag = p->dcdiag; d.scale = p->dscale; d.basis = p->dbasis;
     B.maxP = std::max(B.maxP, d.P);
     // active (m, h) pairs, in (m, h) order
     a1[s].assign((size_t)p->M * p->L0, -1);
@@ -473,16 +480,18 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
         }
       }
     }
-    // entry (p, q) of a symmetric block -> its basis index
+    // entry (p, q) of a block -> its basis index (-1 off the diagonal copies
+    // of the discrete form's blocks)
     H.pq2b_off.push_back((int64_t)H.pq2b.size());
-    H.pq2b.resize(H.pq2b.size() + (size_t)nn);
+    H.pq2b.resize(H.pq2b.size() + (size_t)nn, -1);
     {
       int* t = H.pq2b.data() + H.pq2b_off.back();
-      for (int b = 0; b < p->Nt; ++b) {
-        const int pp = p->basis.pairs[2 * b], qq = p->basis.pairs[2 * b + 1];
-        t[pp * n + qq] = b;
-        t[qq * n + pp] = b;
-      }
+      for (int c = 0; c < d.copies; ++c)
+        for (int b = 0; b < p->Nt; ++b) {
+          const int pp = c * p->n + p->basis.pairs[2 * b], qq = c * p->n + p->basis.pairs[2 * b + 1];
+          t[pp * n + qq] = b;
+          t[qq * n + pp] = b;
+        }
     }
     // basis group pairs
     H.gpoff.push_back((int64_t)H.gpinfo.size());
@@ -521,7 +530,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   // whole-pair assembly scratch: one n^2 x n^2 slot per workgroup of its grid
   int pn = 0;
   for (int s = 0; s < count; ++s)
-    if (ch->pair[s] && sdps[s]->n * sdps[s]->n <= 128) pn = std::max(pn, sdps[s]->n);
+    if (ch->pair[s] && pair_ok(sdps[s])) pn = std::max(pn, sdps[s]->n);
   // (only blocks of order 11 keep R in global scratch; smaller ones in LDS)
   const int64_t totrs = pn * pn > 112 ? (int64_t)kPairGrid * pn * pn * pn * pn : 0;
   const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totgi + B.totP +
@@ -561,8 +570,21 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   for (int s = 0; s < count; ++s) {
     psdp_sdp* p = sdps[s];
     const int L0 = p->L0, L = p->L, M = p->M;
-    const int64_t nn = (int64_t)p->n * p->n;
+    const int64_t nn = (int64_t)p->bo * p->bo;
     const int64_t b0 = B.sys[s].boff;
+    // a term tr(E T E' U) of the expansion; on the discrete form's blocks the
+    // basis matrices sit on the two diagonal copies, so the term becomes the
+    // four terms of the copy pairs (c1, c2): T's block (c1, c2) with U's
+    // block (c2, c1), read at shifted offsets of the order-2n matrices
+    const int nbs = p->n, bo = p->bo, ncp = bo / nbs;
+    auto add_term = [&](int64_t oT, int64_t oU, double c, int tT, int tU) {
+      for (int c1 = 0; c1 < ncp; ++c1)
+        for (int c2 = 0; c2 < ncp; ++c2) {
+          const int64_t sT = tT ? (int64_t)c2 * nbs * bo + c1 * nbs : (int64_t)c1 * nbs * bo + c2 * nbs;
+          const int64_t sU = tU ? (int64_t)c1 * nbs * bo + c2 * nbs : (int64_t)c2 * nbs * bo + c1 * nbs;
+          H.terms.push_back(KTerm{oT + sT, oU + sU, c, tT, tU});
+        }
+    };
     // index of the A3/A4 of (m, h, h2), from the system's own pre-products
     a3.assign((size_t)M * L0 * L0, -1);
     a4.assign((size_t)M * L0 * L0, -1);
@@ -577,7 +599,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
         for (int j = 0; j < L; ++j) {
           if (!p->bmask[h * L + j] || !p->bmask[h2 * L + j]) continue;
           const double c = p->betaf[h * L + j] * p->betaf[h2 * L + j];
-          H.terms.push_back(KTerm{ziBase + b0 + j * nn, xBase + b0 + j * nn, c, 0, 0});
+          add_term(ziBase + b0 + j * nn, xBase + b0 + j * nn, c, 0, 0);
         }
         for (int m = 0; m < M; ++m) {
           if (!p->hmask[m * L0 + h] || !p->hmask[m * L0 + h2]) continue;
@@ -586,14 +608,14 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
           const int64_t A2h = a2[s][m * L0 + h] + preBase, A2h2 = a2[s][m * L0 + h2] + preBase;
           const int64_t A3 = a3[((size_t)m * L0 + h) * L0 + h2];
           const int64_t A4 = a4[((size_t)m * L0 + h) * L0 + h2];
-          H.terms.push_back(KTerm{A1h2, A2h, 1.0, 0, 0});         // (Zi H'^T, X H^T)
-          H.terms.push_back(KTerm{ziBase + bm, A3, 1.0, 0, 1});   // (Zi, H' X H^T)
-          H.terms.push_back(KTerm{A4, xBase + bm, 1.0, 0, 0});    // (H Zi H'^T, X)
-          H.terms.push_back(KTerm{A1h, A2h2, 1.0, 1, 1});         // (H Zi, H' X)
+          add_term(A1h2, A2h, 1.0, 0, 0);         // (Zi H'^T, X H^T)
+          add_term(ziBase + bm, A3, 1.0, 0, 1);   // (Zi, H' X H^T)
+          add_term(A4, xBase + bm, 1.0, 0, 0);    // (H Zi H'^T, X)
+          add_term(A1h, A2h2, 1.0, 1, 1);         // (H Zi, H' X)
         }
         const int kcnt = (int)H.terms.size() - kbeg;
         if (kcnt == 0) continue;   // the block stays zero
-        if (ch->pair[s] && p->n * p->n <= 128) {
+        if (ch->pair[s] && pair_ok(p)) {
           H.ptiles.push_back(AsmTile{s, h, h2, -1, -1, kbeg, kcnt, 0});
           B.maxn_pair = std::max(B.maxn_pair, p->n);
           continue;
@@ -1547,7 +1569,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
   if (o.chol_panels != 0)
     for (int s = 0; s < count; ++s) forced_fact(o, ch.sw[s], ch.ssw[s]);
   for (int s = 0; s < count; ++s) {
-    const bool can_pair = sdps[s]->n * sdps[s]->n <= 128;
+    const bool can_pair = pair_ok(sdps[s]);
     const bool can_small = sdps[s]->Kpad / kNB <= kSmallP;
     if (o.asm_path >= 0) ch.pair[s] = can_pair && o.asm_path == 1;
     if (o.solve_path >= 0) ch.small[s] = can_small && o.solve_path == 1;
@@ -1558,7 +1580,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
     for (int s = 0; s < count; ++s) {
       const int P = (int)(sdps[s]->Kpad / kNB);
       const int key = kind == 0 ? sdps[s]->n : kind == 1 ? P : sw_bucket(P);
-      const bool able = kind == 0 ? key * key <= 128 : kind == 1 ? key <= kSmallP : key > 0;
+      const bool able = kind == 0 ? pair_ok(sdps[s]) : kind == 1 ? key <= kSmallP : key > 0;
       if (!able) continue;
       {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1613,7 +1635,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (int s = 0; s < count; ++s) {
-    if (o.asm_path < 0 && sdps[s]->n * sdps[s]->n <= 128) {
+    if (o.asm_path < 0 && pair_ok(sdps[s])) {
       auto it = g_tune.find({0, sdps[s]->n});
       if (it != g_tune.end()) ch.pair[s] = it->second;
     }
@@ -1710,7 +1732,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
   if (ext) {
     ch = default_choice(sdps, count);
     for (int s = 0; s < count; ++s) {
-      if (o.asm_path >= 0) ch.pair[s] = sdps[s]->n * sdps[s]->n <= 128 && o.asm_path == 1;
+      if (o.asm_path >= 0) ch.pair[s] = pair_ok(sdps[s]) && o.asm_path == 1;
       if (o.solve_path >= 0) ch.small[s] = sdps[s]->Kpad / kNB <= kSmallP && o.solve_path == 1;
       if (o.chol_panels != 0) forced_fact(o, ch.sw[s], ch.ssw[s]);
     }
@@ -1884,7 +1906,7 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     R.time_paper_s = t_paper;
     R.time_phase1_s = t_ph1;
     R.time_cert_s = t_cert;
-    R.asm_path = B.use_pair[s] && p->n * p->n <= 128;
+    R.asm_path = B.use_pair[s] && pair_ok(p);
     R.solve_path = B.use_small[s] && d.P <= kSmallP;
     R.label_iter = r.label_iter;
     if (r.label_iter >= 0) {
@@ -1997,7 +2019,7 @@ int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y
   if (rc) return rc;
   if ((rc = init_state(B, st))) return rc;
   const SysDesc& d = B.sys[0];
-  const int64_t nb = sdp->nb, nn = (int64_t)sdp->n * sdp->n;
+  const int64_t nb = sdp->nb, nn = (int64_t)sdp->bo * sdp->bo;
   PSDP_HIP(hipMemcpyAsync(B.X, X, nb * nn * 8, hipMemcpyHostToDevice, st));
   PSDP_HIP(hipMemcpyAsync(B.Z, Z, nb * nn * 8, hipMemcpyHostToDevice, st));
   PSDP_HIP(hipMemcpyAsync(B.y, y, d.K * 8, hipMemcpyHostToDevice, st));
@@ -2060,7 +2082,7 @@ int eval_schur(psdp_sdp* sdp, const double* X, const double* Z, int precision, d
   if (rc) return rc;
   if ((rc = init_state(B, st))) return rc;
   const SysDesc& d = B.sys[0];
-  const int64_t nb = sdp->nb, nn = (int64_t)sdp->n * sdp->n;
+  const int64_t nb = sdp->nb, nn = (int64_t)sdp->bo * sdp->bo;
   PSDP_HIP(hipMemcpyAsync(B.X, X, nb * nn * 8, hipMemcpyHostToDevice, st));
   PSDP_HIP(hipMemcpyAsync(B.Z, Z, nb * nn * 8, hipMemcpyHostToDevice, st));
   const int one = F_ACTIVE | F_CHOLSEL | (B.f32 ? F_ASM32 : 0);
@@ -2088,7 +2110,7 @@ int eval_ladder(psdp_sdp* sdp, const double* V, const double* dV, const psdp_opt
   Batch B;
   int rc = build_batch(B, &sdp, 1);
   if (rc) return rc;
-  const int64_t nb = sdp->nb, nn = (int64_t)sdp->n * sdp->n;
+  const int64_t nb = sdp->nb, nn = (int64_t)sdp->bo * sdp->bo;
   PSDP_HIP(hipMemcpyAsync(B.X, V, nb * nn * 8, hipMemcpyHostToDevice, st));
   PSDP_HIP(hipMemcpyAsync(B.dX, dV, nb * nn * 8, hipMemcpyHostToDevice, st));
   const int one = F_ACTIVE;

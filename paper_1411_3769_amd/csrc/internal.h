@@ -67,6 +67,9 @@ constexpr double kIrSwitch = 1e-1;
 
 struct SysDesc {
   int n, L0, L, M, Nt, nb, P, mode;   // P = Kpad / kNB; mode 0 paper SDP, 1 phase-I
+  // n is the order of every block; the basis matrices are nbas x nbas, placed
+  // on the diagonal copies times (discrete form: n = 2 nbas, copies = 2)
+  int nbas, copies;
   int K, Kpad, blk0, npairs_hm;
   int sw, ssw;      // Schur Cholesky: panels per super-panel (wide update depth 64 sw) and
                     // per sub-panel inside it (its update depth 64 ssw; ssw = sw: none)
@@ -77,7 +80,7 @@ struct SysDesc {
   int64_t dgoff;    // factored diagonal tiles of the Schur matrix (P * 64 * 64)
   int64_t gioff;    // grouped solves: inverses of the factor's diagonal blocks of
                     // kSG tiles, (L_qq^-1, L_qq^-T) per group, 2 kGS^2 each; -1: none
-  const double* H;      // [M][L0][n][n]
+  const double* H;      // [M][L0][n][n] (the discrete form's Hh)
   const double* betaf;  // [L0][L]
   const double* cdiag;  // [L+M]
   const double* scale;  // [L+M]
@@ -134,6 +137,8 @@ BasisInfo make_basis(int n);
 
 struct psdp_sdp {
   int n, l, da, dp, d1, d2;
+  int form;   // PSDP_FORM_*
+  int bo;     // order of every block of the SDP: n, or 2n for the discrete form
   int L0, L, M, Na, Nt, nb;
   int64_t K, Kpad;
   double delta, eps;
@@ -151,6 +156,7 @@ struct psdp_sdp {
   int64_t* dbeta;
   int64_t* dcoef;
   double* dH;
+  double* dHh;       // discrete form: [M][L0][2n][2n] [[-b/2 I, -H], [0, -b/2 I]]; else dH
   double* dbetaf;
   double* dscale;
   double* dcdiag;

@@ -505,15 +505,24 @@ __global__ void k_form_P(const SysDesc* __restrict__ sys, const int* __restrict_
   ACTIVE_OR_RETURN(s);
   const SysDesc sd = sys[s];
   if (sd.n <= nskip) return;   // k_BT_small
-  const int n = sd.n;
+  const int n = sd.n, nbs = sd.nbas;
   double* P = Pm + sd.poff + (int64_t)h * n * n;
   const double* yh = y + sd.voff + (int64_t)h * sd.Nt;
   for (int b = threadIdx.x; b < sd.Nt; b += blockDim.x) {
     const int p = sd.basis[2 * b], q = sd.basis[2 * b + 1];
     const double v = yh[b];
-    P[p * n + q] = v;
-    P[q * n + p] = v;
+    for (int c = 0; c < sd.copies; ++c) {   // discrete form: blockdiag(P_h, P_h)
+      const int pc = p + c * nbs, qc = q + c * nbs;
+      P[pc * n + qc] = v;
+      P[qc * n + pc] = v;
+    }
   }
+  if (sd.copies > 1)   // the off-diagonal copies stay zero
+    for (int e = threadIdx.x; e < nbs * nbs; e += blockDim.x) {
+      const int r = e / nbs, c = e % nbs;
+      P[r * n + nbs + c] = 0.0;
+      P[(nbs + r) * n + c] = 0.0;
+    }
 }
 
 // P-blocks of B^T(y): out_j = sum_h beta_{h,j} P_h (ascending h)
@@ -613,16 +622,21 @@ __global__ void __launch_bounds__(256) k_B_reduce(const SysDesc* __restrict__ sy
     const int n = sd->n, Nt = sd->Nt, L = sd->L;
     const int h = k / Nt, b = k - h * Nt;
     const int p = sd->basis[2 * b], q = sd->basis[2 * b + 1];
+    // tr(E_b S) over the basis matrix's diagonal copies (two in the
+    // discrete form's blocks of order 2 nbas)
     const int e1 = p * n + q, e2 = q * n + p;
+    const int sh = sd->copies > 1 ? sd->nbas * (n + 1) : 0;
     for (int j = qd; j < L; j += 4) {
       const double bt = sd->betaf[h * L + j];
       const double* Wj = W + blks[sd->blk0 + j].off;
-      const double w = p == q ? Wj[e1] : Wj[e1] + Wj[e2];
+      double w = p == q ? Wj[e1] : Wj[e1] + Wj[e2];
+      if (sh) w += p == q ? Wj[e1 + sh] : Wj[e1 + sh] + Wj[e2 + sh];
       acc += bt != 0.0 ? bt * w : 0.0;
     }
     for (int c = sd->hm_by_h[h] + qd; c < sd->hm_by_h[h + 1]; c += 4) {
       const double* Y = arena + pairs[sd->hm_ids[c]].offY;
       dsum += (p == q ? Y[e1] : Y[e1] + Y[e2]);
+      if (sh) dsum += (p == q ? Y[e1 + sh] : Y[e1 + sh] + Y[e2 + sh]);
     }
   }
   // every lane of the quad takes part in the shuffles
@@ -1356,7 +1370,7 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   ACTIVE_OR_RETURN(tl.sys);
   if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) return;
   const SysDesc sd = sys[tl.sys];
-  const int n = sd.n;
+  const int n = sd.n, nbs = sd.nbas;   // block order (entry addresses), basis order (indices)
   const int* gp = gpinfo_all + gpoff[tl.sys];
   const int g1 = gp[tl.rg * 4 + 0], g2 = gp[tl.rg * 4 + 1], roff = gp[tl.rg * 4 + 2];
   const int g3 = gp[tl.cg * 4 + 0], g4 = gp[tl.cg * 4 + 1], coff = gp[tl.cg * 4 + 2];
@@ -1368,7 +1382,7 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   const int sa = tid >> 4, sc = tid & 15;
   const int ia = sa < 8 ? kTB * g1 + sa : kTB * g2 + (sa - 8);
   const int jc = sc < 8 ? kTB * g3 + sc : kTB * g4 + (sc - 8);
-  const bool inb = ia < n && jc < n;
+  const bool inb = ia < nbs && jc < nbs;
   const int iN = inb ? ia * n + jc : 0, iT = inb ? jc * n + ia : 0;
   // the next stage is fetched into registers while the current one is
   // multiplied: the stage's term descriptors first, then every entry load
@@ -1448,8 +1462,8 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
     }
   }
   __syncthreads();
-  const int n1 = min(kTB, n - kTB * g1), n2s = min(kTB, n - kTB * g2);
-  const int n3 = min(kTB, n - kTB * g3), n4 = min(kTB, n - kTB * g4);
+  const int n1 = min(kTB, nbs - kTB * g1), n2s = min(kTB, nbs - kTB * g2);
+  const int n3 = min(kTB, nbs - kTB * g3), n4 = min(kTB, nbs - kTB * g4);
   const int64_t ld = sd.Kpad;
   double* Lr = Lam + sd.loff;
   // every entry goes to its lower-triangle place (col, row) (a diagonal
@@ -1707,7 +1721,9 @@ __global__ void __launch_bounds__(256) k_B_small(const SysDesc* __restrict__ sys
   if (t < sd.Nt) {
     const int p = sd.basis[2 * t], q = sd.basis[2 * t + 1];
     auto T = [&](int a, int b) { return sT[0][a * 16 + b] + sT[1][a * 16 + b] + sT[2][a * 16 + b] + sT[3][a * 16 + b]; };
-    const double v = p == q ? T(p, p) : T(p, q) + T(q, p);
+    double v = 0.0;
+    for (int c = 0, o = 0; c < sd.copies; ++c, o += sd.nbas)   // diagonal copies of E_b
+      v += p == q ? T(p + o, p + o) : T(p + o, q + o) + T(q + o, p + o);
     out[sd.voff + (int64_t)h * sd.Nt + t] = sd.mode == 0 ? v - asub : v;
   }
 }
@@ -1745,7 +1761,7 @@ __global__ void __launch_bounds__(256) k_BT_small(int nblk, const BlkDesc* __res
       const double bt = sd.betaf[(int64_t)h * L + bd.j];
       if (bt == 0.0) continue;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += bt * yv[(int64_t)h * Nt + ix[u]];
+      for (int u = 0; u < 4; ++u) acc[u] += ix[u] >= 0 ? bt * yv[(int64_t)h * Nt + ix[u]] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -1764,8 +1780,8 @@ __global__ void __launch_bounds__(256) k_BT_small(int nblk, const BlkDesc* __res
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
     const int k = 4 * ks + kq;
-    oka[ks] = r16 < n && k < n;
-    ia[ks] = oka[ks] ? sd.pq2b[r16 * n + k] : 0;
+    ia[ks] = r16 < n && k < n ? sd.pq2b[r16 * n + k] : -1;
+    oka[ks] = ia[ks] >= 0;   // (entries off the discrete form's diagonal copies are -1)
   }
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
   for (int c = c0; c < c1; ++c) {

@@ -111,12 +111,13 @@ struct SetupDesc {
   double* betaf;
   int64_t* coef;
   double* H;
+  double* Hh;           // discrete form: the 2n x 2n [[-b/2 I, -H], [0, -b/2 I]]; else null
   double* scale;
   double* cdiag;
   double* bad;
   double delta, eps;
   int64_t nA;           // Na n^2
-  int l, L0, L, M, Na, n, d1, d2, dp, dM;
+  int l, L0, L, M, Na, n, d1, d2, dp, dM, da;
 };
 
 constexpr int kGatherBlock = 1024;   // doubles per workgroup of the vertex gather
@@ -208,6 +209,36 @@ __global__ void k_coef_H(const SetupDesc* __restrict__ D, const int64_t* __restr
   }
 }
 
+// Discrete form, one workgroup per (m, h) after k_coef_H:
+// Hh[m][h] = [[-b/2 I, -H[m][h]], [0, -b/2 I]] with b = (da+d2)!/(gamma_m-h)!
+// (0 unless gamma_m >= h): the coefficient of alpha^gamma_m in
+// alpha^h (sum alpha)^(da+d2), which multiplies P_h on the diagonal of the
+// 2n x 2n Polya coefficient [[b P, P H], [H^T P, b P]] = -(Hh^T Eh + Eh Hh).
+__global__ void k_hat_H(const SetupDesc* __restrict__ D, const int64_t* __restrict__ pre, int count) {
+  const int i = find_sys(pre, count, blockIdx.x);
+  const SetupDesc& s = D[i];
+  if (!s.Hh) return;
+  const int64_t loc = (int64_t)blockIdx.x - pre[i];
+  const int m = (int)(loc / s.L0), h = (int)(loc % s.L0);
+  const int l = s.l, n = s.n, n2 = 2 * s.n;
+  int delta[32];
+  bool ok = true;
+  for (int q = 0; q < l; ++q) {
+    delta[q] = s.WM[m * l + q] - s.Wp[h * l + q];
+    ok = ok && delta[q] >= 0;
+  }
+  const double hb = ok ? -0.5 * (double)dev_multinomial(s.da + s.d2, delta, l) : 0.0;
+  const double* Hs = s.H + ((int64_t)m * s.L0 + h) * n * n;
+  double* out = s.Hh + ((int64_t)m * s.L0 + h) * n2 * n2;
+  for (int e = threadIdx.x; e < n2 * n2; e += blockDim.x) {
+    const int r = e / n2, c = e % n2;
+    double v = 0.0;
+    if (r == c) v = hb;
+    else if (r < n && c >= n) v = -Hs[r * n + (c - n)];
+    out[e] = v;
+  }
+}
+
 // *bad = 1 if any entry of the system's A is not finite (one workgroup per
 // system)
 __global__ void k_nonfinite(const SetupDesc* __restrict__ D) {
@@ -261,6 +292,7 @@ void psdp_setup_opts_default(psdp_setup_opts* o) {
   o->eps = 1e-3;
   o->paper_literal = 0;
   o->a_on_device = 0;
+  o->form = PSDP_FORM_CONTINUOUS;
 }
 
 void psdp_opts_default(psdp_opts* o) {
@@ -310,6 +342,10 @@ static int plan_system(const double* A, int n, int l, int dp, int d, const psdp_
   if (n < 1 || n > kMaxN) return fail(PSDP_EINVAL, "n must be in [1, 128]");
   if (l < 1 || l > 32) return fail(PSDP_EINVAL, "l must be in [1, 32]");
   if (dp < 0 || da < 1 || d1 < 0 || d2 < 0) return fail(PSDP_EINVAL, "negative degree");
+  if (opt.form != PSDP_FORM_CONTINUOUS && opt.form != PSDP_FORM_DISCRETE)
+    return fail(PSDP_EINVAL, "invalid form");
+  if (opt.form == PSDP_FORM_DISCRETE && n > kMaxN / 2)
+    return fail(PSDP_EINVAL, "the discrete form takes n in [1, 64] (blocks of order 2n)");
   if (!(opt.delta > 0.0) || !(opt.eps >= 0.0) || !std::isfinite(opt.delta) ||
       !std::isfinite(opt.eps))
     return fail(PSDP_EINVAL, "delta must be > 0 and eps >= 0");
@@ -328,6 +364,8 @@ static int plan_system(const double* A, int n, int l, int dp, int d, const psdp_
   }
   psdp_sdp* s = new psdp_sdp();
   s->n = n; s->l = l; s->da = da; s->dp = dp; s->d1 = d1; s->d2 = d2;
+  s->form = opt.form;
+  s->bo = opt.form == PSDP_FORM_DISCRETE ? 2 * n : n;
   s->L0 = (int)L0; s->L = (int)L; s->M = (int)M; s->Na = (int)Na; s->Nt = (int)Nt;
   s->nb = (int)(L + M);
   s->K = K;
@@ -452,7 +490,8 @@ static int setup_many(int count, const double* const* A, const int* n, const int
       const int64_t nA = (int64_t)s->Na * s->n * s->n;
       oWork[i] = off;
       off += al((int64_t)s->L0 * s->L * 8) + al((int64_t)s->L0 * s->M * s->Na * 8) +
-             al((int64_t)s->M * s->L0 * s->n * s->n * 8) + (dev_a ? al(nA * 8) : 0);
+             al((int64_t)s->M * s->L0 * s->n * s->n * 8) + (dev_a ? al(nA * 8) : 0) +
+             (s->form == PSDP_FORM_DISCRETE ? al((int64_t)s->M * s->L0 * s->bo * s->bo * 8) : 0);
     }
     void* raw = nullptr;
     if (hipMalloc(&raw, off) != hipSuccess) {
@@ -487,6 +526,11 @@ static int setup_many(int count, const double* const* A, const int* n, const int
       w += al((int64_t)s->L0 * s->M * s->Na * 8);
       s->dH = (double*)w;
       w += al((int64_t)s->M * s->L0 * s->n * s->n * 8);
+      s->dHh = s->dH;
+      if (s->form == PSDP_FORM_DISCRETE) {
+        s->dHh = (double*)w;
+        w += al((int64_t)s->M * s->L0 * s->bo * s->bo * 8);
+      }
       if (dev_a) {
         s->dA = (double*)w;
       } else {
@@ -513,6 +557,7 @@ static int setup_many(int count, const double* const* A, const int* n, const int
       q.betaf = s->dbetaf;
       q.coef = s->dcoef;
       q.H = s->dH;
+      q.Hh = s->form == PSDP_FORM_DISCRETE ? s->dHh : nullptr;
       q.scale = s->dscale;
       q.cdiag = s->dcdiag;
       q.bad = rb + LL + 2 * nbk;
@@ -520,7 +565,7 @@ static int setup_many(int count, const double* const* A, const int* n, const int
       q.eps = s->eps;
       q.nA = nA;
       q.l = s->l; q.L0 = s->L0; q.L = s->L; q.M = s->M; q.Na = s->Na; q.n = s->n;
-      q.d1 = s->d1; q.d2 = s->d2; q.dp = s->dp; q.dM = s->dp + s->da + s->d2;
+      q.d1 = s->d1; q.d2 = s->d2; q.dp = s->dp; q.dM = s->dp + s->da + s->d2; q.da = s->da;
     }
     const size_t pstride = al((count + 1) * sizeof(int64_t));
     const std::vector<int64_t>* pres[4] = {&preA, &preB, &preH, &preS};
@@ -539,6 +584,10 @@ static int setup_many(int count, const double* const* A, const int* n, const int
       hipLaunchKernelGGL(k_coef_H, dim3((unsigned)preH[count]), dim3(256), maxNa * 8, 0, dD,
                          dpre[2], count);
       hipLaunchKernelGGL(k_scale, dim3((unsigned)preS[count]), dim3(256), 0, 0, dD, dpre[3], count);
+      bool anyd = false;
+      for (int i = 0; i < count; ++i) anyd = anyd || out[i]->form == PSDP_FORM_DISCRETE;
+      if (anyd)   // after k_coef_H on the same stream
+        hipLaunchKernelGGL(k_hat_H, dim3((unsigned)preH[count]), dim3(256), 0, 0, dD, dpre[2], count);
       hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)count), dim3(256), 0, 0, dD);
       e = hipGetLastError();
     }
@@ -588,7 +637,8 @@ int psdp_query(const psdp_sdp* s, psdp_dims* out) {
   out->n = s->n; out->l = s->l; out->da = s->da; out->dp = s->dp; out->d1 = s->d1; out->d2 = s->d2;
   out->L0 = s->L0; out->L = s->L; out->M = s->M; out->Na = s->Na; out->Nt = s->Nt;
   out->K = s->K; out->Kpad = s->Kpad;
-  const int64_t nn = (int64_t)s->n * s->n;
+  out->form = s->form; out->bo = s->bo;
+  const int64_t nn = (int64_t)s->bo * s->bo;
   int64_t pairs = 0, pairs2 = 0;
   for (int m = 0; m < s->M; ++m) {
     int z = 0;

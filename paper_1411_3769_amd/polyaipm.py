@@ -46,12 +46,14 @@ DP = C.POINTER(C.c_double)
 
 class SetupOpts(C.Structure):
     _fields_ = [("da", C.c_int), ("d1", C.c_int), ("d2", C.c_int), ("delta", C.c_double),
-                ("eps", C.c_double), ("paper_literal", C.c_int), ("a_on_device", C.c_int)]
+                ("eps", C.c_double), ("paper_literal", C.c_int), ("a_on_device", C.c_int),
+                ("form", C.c_int)]
 
 
 class Dims(C.Structure):
     _fields_ = [(k, C.c_int) for k in ("n", "l", "da", "dp", "d1", "d2", "L0", "L", "M", "Na", "Nt")] + \
-               [("K", C.c_int64), ("Kpad", C.c_int64), ("device_bytes", C.c_int64)]
+               [("K", C.c_int64), ("Kpad", C.c_int64), ("device_bytes", C.c_int64), ("form", C.c_int),
+                ("bo", C.c_int)]
 
 
 class Opts(C.Structure):
@@ -209,6 +211,8 @@ class SDP:
         self.n, self.l, self.da, self.dp, self.d1, self.d2 = d.n, d.l, d.da, d.dp, d.d1, d.d2
         self.L0, self.L, self.M, self.Na, self.Nt = d.L0, d.L, d.M, d.Na, d.Nt
         self.K, self.Kpad, self.device_bytes = int(d.K), int(d.Kpad), int(d.device_bytes)
+        self.form = "discrete" if d.form == 1 else "continuous"
+        self.bo = d.bo          # order of every block of the SDP
 
     @property
     def nb(self):
@@ -244,15 +248,20 @@ class SDP:
             pass
 
 
+FORMS = {"continuous": 0, "discrete": 1}
+
+
 def polya_setup(A, n: int, l: int, dp: int, d: int, *, da: int = 1, d1: Optional[int] = None,
                 d2: Optional[int] = None, delta: float = 1e-3, eps: float = 1e-3,
-                paper_literal: bool = False) -> SDP:
+                paper_literal: bool = False, form: str = "continuous") -> SDP:
     """psdp_polya_setup.  A: [Na][n][n] FP64 host array, or a torch CUDA tensor
-    (then read on the device)."""
+    (then read on the device).  form: "continuous" (x' = A x) or "discrete"
+    (x+ = A x)."""
     lib = load()
     o = SetupOpts()
     lib.psdp_setup_opts_default(C.byref(o))
     o.da = da
+    o.form = FORMS[form]
     o.d1 = -1 if d1 is None else d1
     o.d2 = -1 if d2 is None else d2
     o.delta, o.eps, o.paper_literal = delta, eps, int(paper_literal)
@@ -273,7 +282,7 @@ def polya_setup(A, n: int, l: int, dp: int, d: int, *, da: int = 1, d1: Optional
 
 
 def polya_setup_batched(systems, *, da: int = 1, delta: float = 1e-3, eps: float = 1e-3,
-                        paper_literal: bool = False) -> list:
+                        paper_literal: bool = False, form: str = "continuous") -> list:
     """psdp_polya_setup_batched.  systems: sequence of (A, n, l, dp, d), every A
     a host array or every A a torch CUDA tensor.  Returns one SDP per system."""
     lib = load()
@@ -282,6 +291,7 @@ def polya_setup_batched(systems, *, da: int = 1, delta: float = 1e-3, eps: float
     o = SetupOpts()
     lib.psdp_setup_opts_default(C.byref(o))
     o.da = da
+    o.form = FORMS[form]
     o.delta, o.eps, o.paper_literal = delta, eps, int(paper_literal)
     keep, ptrs = [], (C.c_void_p * max(cnt, 1))()
     dev = [hasattr(s[0], "is_cuda") and s[0].is_cuda for s in systems]
@@ -500,7 +510,7 @@ def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, chol_pane
     X = np.ascontiguousarray(X, dtype=np.float64)
     Z = np.ascontiguousarray(Z, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
-    nb, n, K = sdp.nb, sdp.n, sdp.K
+    nb, n, K = sdp.nb, sdp.bo, sdp.K
     out = dict(Zi=np.zeros((nb, n, n)), BTy=np.zeros((nb, n, n)), BX=np.zeros(K),
                Lam=np.zeros((K, K)), LamL=np.zeros((K, K)), sol=np.zeros(K))
     st = stream if stream is not None else _current_stream()
