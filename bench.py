@@ -66,16 +66,19 @@ def _mons(l, d):
     return out
 
 
-def schur_flops(n, l, dp, d):
+def schur_flops(n, l, dp, d, form="continuous"):
     """Algorithmic flops of one Schur complement assembly (structured
     expansion; one triangle): (Nt^2 / 2) (8 sum_j n_j^2 + 32 sum_m z_m^2),
-    n_j / z_m = number of P_h coefficients present in block j / m."""
+    n_j / z_m = number of P_h coefficients present in block j / m; the
+    discrete form's basis matrices sit on two diagonal copies, so each term
+    becomes four (copy pairs) of the same size."""
     Wp, WL, WM = _mons(l, dp), _mons(l, dp + d), _mons(l, dp + 1 + d)
     ge = lambda g, h: all(a >= b for a, b in zip(g, h))
     nj = [sum(ge(g, h) for h in Wp) for g in WL]
     zm = [sum(ge(g, h) for h in Wp) for g in WM]
     Nt = n * (n + 1) // 2
-    return Nt * Nt / 2.0 * (8 * sum(x * x for x in nj) + 32 * sum(x * x for x in zm))
+    return (4.0 if form == "discrete" else 1.0) * Nt * Nt / 2.0 * (
+        8 * sum(x * x for x in nj) + 32 * sum(x * x for x in zm))
 
 
 def workload(name):
@@ -86,6 +89,9 @@ def workload(name):
         return [W.c2_system(0)], "n100 l4 dp1 d3, seed 0 (K=20200)"
     if name == "mixed512":
         return W.mixed_systems(512), "mixed batch of 512: n 6..48, l 2..5, dp 1..2, d 1..4 (K 42..17640)"
+    if name == "discrete":
+        return ([W.discrete_system(s) for s in range(64)],
+                "discrete time x+ = A(alpha) x: n8 l4 dp1 d1, 64 contractive seeds (K=144, blocks of order 16)")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -109,12 +115,17 @@ def _limits(threads):
         return contextlib.nullcontext()
 
 
+def _oracle_sdp(A, n, l, dp, d, form):
+    from oracle import discrete as Dd, sdp as S
+    return (Dd.make_discrete_sdp if form == "discrete" else S.make_sdp)(A, n, l, dp, d)
+
+
 def _oracle_solve(args):
     """One full FP64 oracle solve on one host thread (a pool worker)."""
-    A, n, l, dp, d = args
-    from oracle import ipm, sdp as S
+    A, n, l, dp, d, form = args
+    from oracle import ipm
     with _limits(1):
-        ipm.ipm_solve(S.make_sdp(A, n, l, dp, d))
+        ipm.ipm_solve(_oracle_sdp(A, n, l, dp, d, form))
     return 1
 
 
@@ -124,13 +135,13 @@ def cpu_baseline_solves(systems, budget_s, threads):
     than one thread, one system per worker process (each on one BLAS thread)
     over `threads` processes, started fresh (spawn: nothing of this process's
     GPU state is inherited)."""
-    from oracle import ipm, sdp as S
+    from oracle import ipm
     t0 = time.perf_counter()
     done = 0
     if threads <= 1:
         with _limits(1):
             for sy in systems:
-                ipm.ipm_solve(S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d))
+                ipm.ipm_solve(_oracle_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d, sy.form))
                 done += 1
                 if time.perf_counter() - t0 > budget_s:
                     break
@@ -143,7 +154,7 @@ def cpu_baseline_solves(systems, budget_s, threads):
             # workers started and warm before the clock runs
             list(ex.map(int, range(threads)))
             t0 = time.perf_counter()
-            futs = [ex.submit(_oracle_solve, (sy.A, sy.n, sy.l, sy.dp, sy.d)) for sy in systems]
+            futs = [ex.submit(_oracle_solve, (sy.A, sy.n, sy.l, sy.dp, sy.d, sy.form)) for sy in systems]
             for f in cf.as_completed(futs):
                 done += f.result()
                 if time.perf_counter() - t0 > budget_s:
@@ -203,7 +214,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n100", help="n100 | n10 | mixed512 | learned | example2")
+    ap.add_argument("--workload", default="n100", help="n100 | n10 | mixed512 | discrete | learned | example2")
     ap.add_argument("--precision", default=None, help="fp64 | fp32 | bf16 (Schur assembly)")
     ap.add_argument("--form-steps", type=int, default=3,
                     help="n100: timed steps of each precision form (at most --steps)")
@@ -256,7 +267,8 @@ def main():
 
     def step(precision, prof=None):
         t0 = time.perf_counter()
-        hs = P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)])
+        hs = P.polya_setup_batched([(A, sy.n, sy.l, sy.dp, sy.d) for A, sy in zip(A_dev, systems)],
+                                   form=systems[0].form)
         t1 = time.perf_counter()
         rs = P.ipm_solve_batched(hs, stream=stream, prof=prof, precision=precision,
                                  use_graph=0 if args.no_graph else 1, chol_panels=args.chol_panels,
@@ -330,7 +342,7 @@ def main():
     dom = max(grp, key=lambda k: grp[k][0])
     iters_sys = [r.iterations for r in rs]
     its_all = [r.iterations + r.phase1_iterations for r in rs]
-    asm_flops = sum(it * schur_flops(sy.n, sy.l, sy.dp, sy.d) for it, sy in zip(its_all, systems))
+    asm_flops = sum(it * schur_flops(sy.n, sy.l, sy.dp, sy.d, sy.form) for it, sy in zip(its_all, systems))
     from math import comb
     Ks = [comb(sy.l + sy.dp - 1, sy.l - 1) * sy.n * (sy.n + 1) // 2 for sy in systems]
     chol_flops = sum(it * k ** 3 / 3.0 for it, k in zip(its_all, Ks))

@@ -359,10 +359,10 @@ struct Choice {
   std::vector<int> ssw;  // panels per sub-panel inside a super-panel (= sw: none)
 };
 
-// the whole-pair assembly kernel serves continuous-form blocks of order
-// n with n^2 <= 128 (the discrete form's terms sit on two diagonal copies of
-// each block, which only the grouped kernel reads)
-static bool pair_ok(const psdp_sdp* p) { return p->form == PSDP_FORM_CONTINUOUS && p->n * p->n <= 128; }
+// the whole-pair assembly kernel serves systems whose basis order n has
+// n^2 <= 128 (the discrete form's terms are n x n blocks of its 2n x 2n
+// products, read at their offsets)
+static bool pair_ok(const psdp_sdp* p) { return p->n * p->n <= 128; }
 
 static Choice default_choice(psdp_sdp* const* sdps, int count) {
   Choice c;

@@ -1219,13 +1219,15 @@ __device__ __forceinline__ void assemble_pair(const AsmTile* __restrict__ tiles,
     if (!(flags[tl.sys] & F_ACTIVE)) continue;
     if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) continue;
     const SysDesc sd = sys[tl.sys];
-    const int n = sd.n, n2 = n * n;
+    // entry indices run over the basis order n, addresses over the block
+    // order bo (the discrete form's terms are n x n blocks of 2n x 2n ones)
+    const int n = sd.nbas, bo = sd.n, n2 = n * n;
     const int NT = (n2 + 15) / 16, n2p = NT * 16, ntiles = NT * NT;
     const int kcnt = tl.kcnt;
     const bool inb = idx < n2;
     const int ii = inb ? idx : 0;
     const int ib = ii / n, ic = ii - ib * n;
-    const int itr = ic * n + ib;
+    const int iad = ib * bo + ic, itr = ic * bo + ib;
     real* sT = reinterpret_cast<real*>(smem);
     real* sU = sT + KS * n2p;
     // raw entries and the term's coefficient (0 past the last term); the
@@ -1238,8 +1240,8 @@ __device__ __forceinline__ void assemble_pair(const AsmTile* __restrict__ tiles,
       for (int j = 0; j < KH; ++j) kt[j] = terms[tl.kbeg + min(k0 + qtr + NQ * j, kcnt - 1)];
 #pragma unroll
       for (int j = 0; j < KH; ++j) {
-        vT[j] = arena[kt[j].offT + (kt[j].tT ? itr : ii)];
-        vU[j] = arena[kt[j].offU + (kt[j].tU ? itr : ii)];
+        vT[j] = arena[kt[j].offT + (kt[j].tT ? itr : iad)];
+        vU[j] = arena[kt[j].offU + (kt[j].tU ? itr : iad)];
         cf[j] = k0 + qtr + NQ * j < kcnt ? kt[j].coef : 0.0;
       }
     };

@@ -22,6 +22,10 @@ Families (sizes follow the configurations the solver is measured on):
 * ``mixed``   a meta stream (seed 0) draws, per system, n ~ U{6..48},
               l ~ U{2..5}, dp ~ U{1,2}, d ~ U{1..4}, s ~ U[0.1, 0.5] and a
               64-bit child seed; vertices then come from ``dissip``.
+* ``contract`` (discrete time, x+ = A(alpha) x) rho ~ U[0.6, 0.98] first,
+              then G_1..G_l ~ N(0,1)^{n x n} in order; A_i = rho G_i / ||G_i||_2,
+              so every A(alpha) on the simplex has norm <= rho.  Used at
+              (n=8, l=4, dp=d=1), 64 seeds.
 """
 from __future__ import annotations
 
@@ -41,6 +45,7 @@ class System:
     d: int
     seed: int
     tag: str = ""
+    form: str = "continuous"    # or "discrete": x+ = A(alpha) x
 
 
 def plain_vertices(seed: int, n: int = 4, l: int = 3) -> np.ndarray:
@@ -94,6 +99,21 @@ def warm_system(seed: int) -> System:
     rng = np.random.default_rng(seed)
     s = float(rng.uniform(0.1, 0.5))
     return System(dissip_vertices(seed, 32, 4, s, rng=rng), 32, 4, 1, 2, seed, "n32")
+
+
+def contract_vertices(seed: int, n: int, l: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    rho = float(rng.uniform(0.6, 0.98))
+    out = np.empty((l, n, n))
+    for i in range(l):
+        G = rng.standard_normal((n, n))
+        out[i] = rho * G / np.linalg.norm(G, 2)
+    return out
+
+
+def discrete_system(seed: int) -> System:
+    """Discrete time: n=8, l=4, dp=d=1, contractive vertices (64 seeds 0..63)."""
+    return System(contract_vertices(seed, 8, 4), 8, 4, 1, 1, seed, "d8", "discrete")
 
 
 def mixed_systems(count: int = 512, meta_seed: int = 0) -> list[System]:

@@ -103,15 +103,18 @@ def _contractive(rng, l, n, rho):
     return np.stack(out)
 
 
+@pytest.mark.parametrize("asm_path", [0, 1])
 @pytest.mark.parametrize("seed,n,dp,d", [(0, 3, 1, 1), (1, 6, 1, 1), (2, 10, 1, 1)])
-def test_contractive_polytope(P, seed, n, dp, d):
+def test_contractive_polytope(P, seed, n, dp, d, asm_path):
+    """Both assembly kernels (grouped tiles; whole pairs, n^2 <= 128) read
+    the copy terms."""
     rng = np.random.default_rng(seed)
     A = _contractive(rng, 3, n, 0.9)
-    print(f"discrete contractive n={n}", flush=True)
+    print(f"discrete contractive n={n} asm_path={asm_path}", flush=True)
     o = ipm.ipm_solve(D.make_discrete_sdp(A, n, 3, dp, d))
-    r = P.ipm_solve(P.polya_setup(A, n, 3, dp, d, form="discrete"))
+    r = P.ipm_solve(P.polya_setup(A, n, 3, dp, d, form="discrete"), asm_path=asm_path)
     _match(r, o)
-    assert r.verdict_name == "FEASIBLE"
+    assert r.verdict_name == "FEASIBLE" and r.asm_path == asm_path
 
 
 def test_unstable_vertex(P):
