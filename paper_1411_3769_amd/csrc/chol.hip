@@ -386,6 +386,167 @@ __global__ void __launch_bounds__(256, 2) k_chol_update(const SysDesc* __restric
   if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
 }
 
+// Right-looking step p with the panel solve folded in (systems factored as
+// one super-panel): every workgroup of tile (i, j), j > p, forms the panel
+// tiles it needs, L_ip = C_ip L_pp^{-T} and L_jp, from the column the
+// previous step left and L_pp^{-1}, then C_ij -= L_ip L_jp^T; the workgroup
+// of tile (p+1, p+1) (dispatched first) goes on to factor it.  So a step is
+// one launch instead of a triangular solve and an update.  Column p is read
+// by many workgroups of the step, so its L tiles go to a two-slot panel
+// buffer (slot p % 2, written by the workgroups of column p + 1) and reach
+// the matrix one step later (copied by the workgroups of column p + 2 and
+// the diagonal one); the last step writes its single tile directly.
+__global__ void __launch_bounds__(256, 2) k_chol_fused(const SysDesc* __restrict__ sys, int* flags, double* Lam,
+                                                    double* Ldiag, double* Linv, double* PB,
+                                                    const int* __restrict__ st_sys,
+                                                    const int* __restrict__ st_pre, int cnt, int p) {
+  __shared__ double sX[kNB * LDT];
+  __shared__ double sA[kNB * LDT];
+  __shared__ int fl;
+  constexpr int NE = kNB * kNB / 256;
+  int si, t;
+  if ((int)blockIdx.x < cnt) {
+    si = blockIdx.x;
+    t = 0;
+  } else {
+    const int b = blockIdx.x - cnt;   // last si with st_pre[si] - si <= b
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (st_pre[mid] - mid <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    si = lo;
+    t = 1 + b - (st_pre[si] - si);
+  }
+  const int s = st_sys[si];
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  double* A = Lam + sd.loff;
+  const int P = sd.P, R = P - p - 1;
+  int c = 0, base = 0;
+  while (t >= base + (R - c)) { base += R - c; ++c; }
+  const int j = p + 1 + c, i = j + (t - base);
+  const bool own = i == j;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  auto tile = [&](int r, int cc) { return A + (int64_t)r * kNB * ld + (int64_t)cc * kNB; };
+  double* pb = PB + sd.pboff;
+  auto slot = [&](int q, int r) { return pb + ((int64_t)(q & 1) * P + r) * kNB * kNB; };
+  auto gload = [&](double* v, const double* src, int64_t lds) {
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      v[it] = src[(int64_t)(e >> 6) * lds + (e & 63)];
+    }
+  };
+  auto sstore = [&](double* dst, const double* v) {
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      dst[(e >> 6) * LDT + (e & 63)] = v[it];
+    }
+  };
+  auto prodT = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(16 * w + r16) * LDT + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double b = Y[(16 * u + r16) * LDT + k0 + kq];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+      }
+    }
+  };
+  auto to_lds = [&](double* dst, const v4d* acc) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[(16 * w + 4 * q + kq) * LDT + 16 * u + r16] = acc[u][q];
+  };
+  auto to_tile = [&](double* dst, int64_t lds, const v4d* acc) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[(int64_t)(16 * w + 4 * q + kq) * lds + 16 * u + r16] = acc[u][q];
+  };
+  auto copy_tile = [&](double* dst, const double* src) {   // panel slot -> matrix
+    double v[NE];
+    gload(v, src, kNB);
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      dst[(int64_t)(e >> 6) * ld + (e & 63)] = v[it];
+    }
+  };
+  // operands in registers first: L_pp^{-1}, C_ip, C_jp (C_ij later, in
+  // flight during the last product)
+  double vx[NE], va[NE], vb[NE], cv[NE];
+  gload(vx, Linv + sd.dgoff + (int64_t)p * kNB * kNB, kNB);
+  gload(va, tile(i, p), ld);
+  if (!own) gload(vb, tile(j, p), ld);
+  double* C = tile(i, j);
+  // the previous step's panel tiles of this row (and, for the diagonal
+  // workgroup, of row p) into the matrix
+  if (p >= 1 && j == p + 1) {
+    copy_tile(tile(i, p - 1), slot(p - 1, i));
+    if (own) copy_tile(tile(p, p - 1), slot(p - 1, p));
+  }
+  sstore(sX, vx);
+  sstore(sA, va);
+  __syncthreads();
+  v4d li[4] = {}, lj[4] = {};
+  prodT(sA, sX, li);
+  if (!own) {
+    __syncthreads();
+    sstore(sA, vb);
+    __syncthreads();
+    prodT(sA, sX, lj);
+  }
+  if (j == p + 1) {
+    if (p == P - 2) to_tile(tile(i, p), ld, li);   // the last step's only tile
+    else to_tile(slot(p, i), kNB, li);
+  }
+  __syncthreads();
+  to_lds(sA, li);
+  if (!own) to_lds(sX, lj);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cv[u * 4 + q] = C[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16];
+  __syncthreads();
+  v4d acc[4] = {};
+  prodT(sA, own ? sA : sX, acc);
+  if (t != 0) {   // every tile but (p+1, p+1); diagonal ones keep their upper part
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int cc = 16 * u + r16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = 16 * w + 4 * q + kq;
+        if (!own || cc <= rr) C[(int64_t)rr * ld + cc] = cv[u * 4 + q] - acc[u][q];
+      }
+    }
+    return;
+  }
+  // tile (p+1, p+1): the next diagonal step
+  if (tid == 0) fl = 0;
+  __syncthreads();   // the product's operands are no longer read
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sA[(16 * w + 4 * q + kq) * LDT + 16 * u + r16] = cv[u * 4 + q] - acc[u][q];
+#pragma unroll
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + 256 * it;
+    sX[(e >> 6) * LDT + (e & 63)] = 0.0;
+  }
+  __syncthreads();
+  diag_tile(sA, sX, &fl);
+  store_diag(sA, sX, Ldiag + sd.dgoff + (int64_t)j * kNB * kNB, Linv + sd.dgoff + (int64_t)j * kNB * kNB);
+  if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
+}
+
 // Wide update at the end of a super-panel of sw panels (p = its last
 // panel): A_ij -= sum over the super-panel's panels q of L_iq L_jq^T for every
 // tile pair right of it (depth 64 sw), on 128 x 128 output blocks (2 x 2
@@ -1245,6 +1406,13 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
   if (total)
     hipLaunchKernelGGL(k_chol_update_wide, dim3(total), dim3(256), 0, st, sys, flags, Lam, ssys, spre,
                        cnt, p, mid);
+}
+
+void launch_chol_fused(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
+                       double* PB, const int* ssys, const int* spre, int cnt, int total, int p) {
+  if (total)
+    hipLaunchKernelGGL(k_chol_fused, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, PB, ssys, spre,
+                       cnt, p);
 }
 
 void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,

@@ -249,6 +249,7 @@ struct Batch {
   std::vector<int> ownP, ownK;
   StepTab pan, trs, upd, wide, mid;
   StepTab lft;   // left-looking factorisation, one step per tile column
+  StepTab fus;   // right-looking steps with the panel solve folded in
   // grouped solves of the systems not solved in one workgroup: per group q,
   // the diagonal-block sweeps (one per system), the row tiles below the
   // group (forward) and the column tiles left of it (backward)
@@ -257,7 +258,7 @@ struct Batch {
   int maxNG = 0;
   std::vector<int> small_ids;
   int* d_small = nullptr;
-  int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0, totgi = 0;
+  int64_t totblk = 0, totvec = 0, totlam = 0, totdg = 0, totP = 0, totpre = 0, totgi = 0, totpb = 0;
 
   // device
   void* dtab = nullptr;
@@ -276,6 +277,7 @@ struct Batch {
   int *d_trs_sys = nullptr, *d_trs_pre = nullptr, *d_wide_sys = nullptr, *d_wide_pre = nullptr;
   int *d_lft_sys = nullptr, *d_lft_pre = nullptr;
   int *d_mid_sys = nullptr, *d_mid_pre = nullptr;
+  int *d_fus_sys = nullptr, *d_fus_pre = nullptr;
   int *d_gin_sys = nullptr, *d_gin_pre = nullptr, *d_gap_sys = nullptr, *d_gap_pre = nullptr;
   int *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr, *d_gbu_pre = nullptr;
   int* d_flags = nullptr;
@@ -300,7 +302,7 @@ struct Batch {
   int maxK = 0;
   int nmax_small = 0;   // largest block order <= kSmallN in the batch (0: none)
   int nmin_big = 0;     // the general block kernels skip orders below this
-  double *Lam, *Ldiag, *Linv, *Ginv, *Pm, *pre, *rscr;
+  double *Lam, *Ldiag, *Linv, *Ginv, *Pm, *pre, *rscr, *PB;
 
   // pinned host mirrors of the per-iteration transfers (flags, scalars),
   // one cached block
@@ -355,7 +357,8 @@ static size_t tabsize(const std::vector<T>& v) {
 // of kSG tiles.
 struct Choice {
   std::vector<char> pair, small;
-  std::vector<int> sw;   // Schur Cholesky panels per super-panel (0: left-looking)
+  std::vector<int> sw;   // Schur Cholesky panels per super-panel (0: left-looking, -2: the
+                         // right-looking steps with the panel solve folded in)
   std::vector<int> ssw;  // panels per sub-panel inside a super-panel (= sw: none)
 };
 
@@ -390,7 +393,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.S = count;
   B.sd.assign(sdps, sdps + count);
   // ---- per-system layout
-  int64_t curblk = 0, curvec = 0, curlam = 0, curdg = 0, curP = 0, curpre = 0, curgi = 0;
+  int64_t curblk = 0, curvec = 0, curlam = 0, curdg = 0, curP = 0, curpre = 0, curgi = 0, curpb = 0;
   std::vector<std::vector<int64_t>> a1(count), a2(count), ay(count);
   std::vector<size_t> q2beg(count + 1, 0);
   B.ownP.push_back(0);
@@ -420,6 +423,11 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     d.voff = curvec; curvec += d.Kpad;
     d.loff = curlam; curlam += (int64_t)d.Kpad * d.Kpad;
     d.dgoff = curdg; curdg += (int64_t)d.P * kNB * kNB;
+    d.pboff = -1;
+    if (d.sw == -2) {   // two panel slots of P tiles
+      d.pboff = curpb;
+      curpb += 2 * (int64_t)d.P * kNB * kNB;
+    }
     d.gioff = -1;
     if (!(ch->small[s] && d.P <= kSmallP)) {   // grouped solves
       d.gioff = curgi;
@@ -517,6 +525,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.totP = round_up(curP, 32);
   B.totpre = round_up(curpre, 32);
   B.totgi = round_up(curgi, 32);
+  B.totpb = round_up(curpb, 32);
   B.nblk = (int)H.blk.size();
   B.npblk = (int)H.pblk.size();
   B.ndblk = (int)H.dblk.size();
@@ -533,7 +542,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     if (ch->pair[s] && pair_ok(sdps[s])) pn = std::max(pn, sdps[s]->n);
   // (only blocks of order 11 keep R in global scratch; smaller ones in LDS)
   const int64_t totrs = pn * pn > 112 ? (int64_t)kPairGrid * pn * pn * pn * pn : 0;
-  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totgi + B.totP +
+  const int64_t total = nblkarr * B.totblk + nvec * B.totvec + B.totlam + 2 * B.totdg + B.totgi + B.totpb + B.totP +
                         B.totpre + totrs;
   B.arena_bytes = (size_t)std::max<int64_t>(total, 1) * 8;
   if (B.ext) {
@@ -557,6 +566,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   B.Ldiag = a + o; o += B.totdg;
   B.Linv = a + o; o += B.totdg;
   B.Ginv = a + o; o += B.totgi;
+  B.PB = a + o; o += B.totpb;
   B.Pm = a + o; o += B.totP;
   B.pre = a + o; o += B.totpre;
   B.rscr = a + o; o += totrs;
@@ -640,6 +650,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.wide.add_step();
     B.mid.add_step();
     B.lft.add_step();
+    B.fus.add_step();
 
     // last column of the narrow update of step q (super-panel end; a
     // super-panel followed by fewer than sw panels absorbs them, since
@@ -656,6 +667,13 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
       if (P <= pstep) continue;
+      if (B.sys[s].sw == -2) {   // one launch per step: the first diagonal, then the updates
+        if (pstep == 0) B.pan.add(s, 1);
+        int nn = 0;
+        for (int j = pstep + 1; j < P; ++j) nn += P - j;
+        if (nn > 0) B.fus.add(s, nn);
+        continue;
+      }
       if (B.sys[s].sw == 0) {   // left-looking: the tiles of column pstep
         B.lft.add(s, pstep == 0 ? 1 : P - pstep);
         continue;
@@ -721,6 +739,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(B.trs.sys) + tabsize(B.trs.pre) + tabsize(B.wide.sys) + tabsize(B.wide.pre);
   tb += tabsize(B.lft.sys) + tabsize(B.lft.pre);
   tb += tabsize(B.mid.sys) + tabsize(B.mid.pre);
+  tb += tabsize(B.fus.sys) + tabsize(B.fus.pre);
   tb += tabsize(B.gin.sys) + tabsize(B.gin.pre) + tabsize(B.gap.sys) + tabsize(B.gap.pre);
   tb += tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
@@ -806,6 +825,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.lft.pre, &B.d_lft_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.mid.sys, &B.d_mid_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.mid.pre, &B.d_mid_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.fus.sys, &B.d_fus_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.fus.pre, &B.d_fus_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.sys, &B.d_gin_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.pre, &B.d_gin_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gap.sys, &B.d_gap_sys))) return rc;
@@ -981,6 +1002,13 @@ static void op_factor(Batch& B, hipStream_t st) {
     }
     if (B.upd.tot[p] > 0 || B.mid.tot[p] > 0 || B.wide.tot[p] > 0)
       B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
+    if (B.fus.tot[p] > 0) {
+      const int g = B.fus.first[p];
+      const size_t m2 = B.prof.mark();
+      launch_chol_fused(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.PB, B.d_fus_sys + g, B.d_fus_pre + g,
+                        B.fus.cnt[p], B.fus.tot[p], p);
+      B.prof.add(PSDP_PROF_CHOL_UPDATE, m2, B.prof.mark());
+    }
     if (B.lft.tot[p] > 0) {
       const int g = B.lft.first[p];
       const size_t m2 = B.prof.mark();
@@ -1542,10 +1570,14 @@ static int sw_bucket(int P) {
 // tiles, and the super-panel widths where a super-panel fits (sub-panels are
 // an explicit option only: at K = 20200 widths 16 in sub-panels of 4 or 8
 // took 2.07 and 2.04 s against 2.02 s per certificate without)
-static int fact_code(int sw, int ssw) { return sw | (ssw << 8); }
+static int fact_code(int sw, int ssw) { return (sw < 0 ? 254 : sw) | (ssw << 8); }
+static int code_sw(int code) { return (code & 255) == 254 ? -2 : code & 255; }
 static std::vector<int> sw_candidates(int bucket) {
   std::vector<int> c;
-  if ((1 << bucket) < kLeftMaxP) c.push_back(0);
+  if ((1 << bucket) < kLeftMaxP) {
+    c.push_back(0);                    // left-looking
+    c.push_back(fact_code(-2, 0));     // right-looking with the panel solve folded in
+  }
   if ((2 << bucket) > 8) {
     c.push_back(fact_code(4, 4));
     c.push_back(fact_code(8, 8));
@@ -1559,7 +1591,7 @@ static std::vector<int> sw_candidates(int bucket) {
 // the factorisation an option pair asks for: chol_panels -1 = left-looking,
 // w > 0 = width w with sub-panels of chol_subpanels (0: none)
 static void forced_fact(const psdp_opts& o, int& sw, int& ssw) {
-  sw = o.chol_panels < 0 ? 0 : o.chol_panels;
+  sw = o.chol_panels == -1 ? 0 : o.chol_panels;
   ssw = o.chol_subpanels > 0 ? o.chol_subpanels : sw;
 }
 
@@ -1586,7 +1618,11 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
         std::lock_guard<std::mutex> lk(g_tune_mu);
         if (g_tune.count({kind, key})) continue;
       }
-      if (want[key].size() < 8) want[key].push_back(s);
+      // trial batches: 8 systems per key for the assembly and solve paths;
+      // the factorisation's launches are shared by the whole batch, so its
+      // trials take up to 64 (the forms differ in work per launch, which
+      // only a batch of the real size weighs against their launch counts)
+      if (want[key].size() < (kind == 2 ? 64u : 8u)) want[key].push_back(s);
     }
     for (auto& kv : want) {
       std::vector<psdp_sdp*> sub;
@@ -1602,7 +1638,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
           if (kind == 0) c.pair[i] = (char)v;
           else if (kind == 1) c.small[i] = (char)v;
           else {
-            c.sw[i] = widths[v] & 255;
+            c.sw[i] = code_sw(widths[v]);
             c.ssw[i] = widths[v] >> 8;
           }
         }
@@ -1647,7 +1683,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
     if (o.chol_panels == 0 && sw_bucket(P) > 0) {
       auto it = g_tune.find({2, sw_bucket(P)});
       if (it != g_tune.end()) {
-        ch.sw[s] = it->second & 255;
+        ch.sw[s] = code_sw(it->second);
         ch.ssw[s] = it->second >> 8;
       }
     }
@@ -1704,8 +1740,8 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     return fail(PSDP_EINVAL, "invalid stop_rule");
   if (o.sigma_rule != PSDP_SIGMA_FIXED && o.sigma_rule != PSDP_SIGMA_MEHROTRA)
     return fail(PSDP_EINVAL, "invalid sigma_rule");
-  if (o.chol_panels < -1 || o.chol_panels > 32)
-    return fail(PSDP_EINVAL, "chol_panels must lie in [-1, 32]");
+  if (o.chol_panels < -2 || o.chol_panels > 32)
+    return fail(PSDP_EINVAL, "chol_panels must lie in [-2, 32]");
   if (o.chol_subpanels < 0 || (o.chol_subpanels > 0 && (o.chol_panels <= 0 || o.chol_panels % o.chol_subpanels)))
     return fail(PSDP_EINVAL, "chol_subpanels must divide a chol_panels width (0: none)");
   // all work runs on a private stream (capturable into graphs) ordered
@@ -2012,7 +2048,7 @@ int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y
   Batch B;
   Choice ch = default_choice(&sdp, 1);
   if (chol_panels != 0) {
-    ch.sw[0] = chol_panels < 0 ? 0 : chol_panels;
+    ch.sw[0] = chol_panels == -1 ? 0 : chol_panels;
     ch.ssw[0] = chol_subpanels > 0 ? chol_subpanels : ch.sw[0];
   }
   int rc = build_batch(B, &sdp, 1, &ch);

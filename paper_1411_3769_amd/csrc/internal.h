@@ -78,6 +78,7 @@ struct SysDesc {
   int64_t loff;     // Schur matrix offset (Kpad * Kpad)
   int64_t poff;     // P_h scratch offset (L0 * n * n)
   int64_t dgoff;    // factored diagonal tiles of the Schur matrix (P * 64 * 64)
+  int64_t pboff;    // panel buffer of the fused factorisation (2 P 64^2), -1: none
   int64_t gioff;    // grouped solves: inverses of the factor's diagonal blocks of
                     // kSG tiles, (L_qq^-1, L_qq^-T) per group, 2 kGS^2 each; -1: none
   const double* H;      // [M][L0][n][n] (the discrete form's Hh)
@@ -188,6 +189,8 @@ void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flag
                              const int* ssys, const int* spre, int cnt, int total, int p, int mid);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
                         double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
+void launch_chol_fused(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
+                       double* PB, const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
                       const int* ssys, const int* spre, int cnt, int total, int j);
 void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,

@@ -161,11 +161,12 @@ def test_kernel_paths_match_oracle(P, asm_path, solve_path):
             assert r.solve_path == solve_path
 
 
-@pytest.mark.parametrize("chol_panels,sub", [(-1, 0), (4, 0), (16, 0), (8, 4)])
+@pytest.mark.parametrize("chol_panels,sub", [(-1, 0), (-2, 0), (4, 0), (16, 0), (8, 4)])
 def test_factorisations_match_oracle(P, chol_panels, sub):
-    """The left-looking factorisation (-1), super-panel widths 4 and 16, and
-    width 8 in sub-panels of 4 give the oracle's end points on n = 10 systems
-    (9 tiles of 64) and on the mixed batch's members with stored end points."""
+    """The left-looking factorisation (-1), the panel solves folded into the
+    updates (-2), super-panel widths 4 and 16, and width 8 in sub-panels of 4
+    give the oracle's end points on n = 10 systems (9 tiles of 64) and on the
+    mixed batch's members with stored end points."""
     with open(os.path.join(GOLDEN, "oracle_results.json")) as fh:
         recs = {r["seed"]: r for r in json.load(fh) if r["tag"] == "n10"}
     seeds = [0, 9, 17, 33]
@@ -174,7 +175,7 @@ def test_factorisations_match_oracle(P, chol_panels, sub):
     rs = P.ipm_solve_batched(gs, chol_panels=chol_panels, chol_subpanels=sub)
     for s, r in zip(seeds, rs):
         _check(recs[s], r)
-        assert r.chol_panels == (0 if chol_panels < 0 else chol_panels)
+        assert r.chol_panels == (0 if chol_panels == -1 else chol_panels)
         assert r.chol_subpanels == (sub or r.chol_panels)
     gold = _golden_mixed()
     mixed = W.mixed_systems(512)

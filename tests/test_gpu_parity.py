@@ -69,9 +69,10 @@ NEWTON_CASES = [(4, 3, 1, 1, 0), (10, 4, 2, 2, 1), (3, 2, 2, 1, 2), (9, 2, 1, 2,
 NEWTON_BIG = [(16, 4, 2, 1, 7), (32, 4, 1, 2, 8), (48, 3, 1, 1, 9)]
 
 
-# factorisations: default right-looking (width 8), left-looking, and widths
-# 16 / 8 split in sub-panels of 4 (sub-panel updates of depth 256)
-@pytest.mark.parametrize("chol", [(0, 0), (-1, 0), (16, 4), (8, 4)])
+# factorisations: default right-looking (width 8), left-looking, panel
+# solves folded into the updates, and widths 16 / 8 split in sub-panels of 4
+# (sub-panel updates of depth 256)
+@pytest.mark.parametrize("chol", [(0, 0), (-1, 0), (-2, 0), (16, 4), (8, 4)])
 @pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES + NEWTON_BIG)
 def test_newton_step_parity(P, n, l, dp, d, seed, chol):
     _flush(f"newton n={n} l={l} dp={dp} d={d} seed={seed} chol_panels={chol}")
