@@ -660,9 +660,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
       return P - 1 - se < sw ? P - 1 : se;
     };
     // last panel of the sub-panel of q (sub-panels split a super-panel in
-    // runs of ssw panels; the narrow updates stay inside one)
+    // runs of ssw panels; the narrow updates stay inside one).  ssw = sw
+    // means none: a super-panel that absorbed a short tail stays whole
     auto sub_end = [&](int P, int q, int sw, int ssw) {
-      return std::min(sp_end(P, q, sw), (q / ssw) * ssw + ssw - 1);
+      return ssw >= sw ? sp_end(P, q, sw) : std::min(sp_end(P, q, sw), (q / ssw) * ssw + ssw - 1);
     };
     for (int s = 0; s < count; ++s) {
       const int P = B.sys[s].P;
