@@ -566,7 +566,6 @@ constexpr int kWT = 128, kWK = 16, kWLD = kWK + 1;
 constexpr int kWRP = 256 / kWK;          // rows staged per pass
 constexpr int kWU = kWT / kWRP;          // passes (values per thread and operand)
 constexpr int kWG = 4;                   // block rows per group of the block order
-constexpr int kXCD = 8;                  // XCDs of the device
 
 // (bi, bj), bj <= bi < nb, of position t of the grouped block order
 __device__ inline void wide_block(int t, int nb, int& bi, int& bj) {
@@ -642,9 +641,7 @@ __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __re
                                                              int p, int mid) {
   __shared__ double sa[2][kWT * kWLD];   // two stages: one is multiplied while
   __shared__ double sb[2][kWT * kWLD];   // the next is written
-  const int total = gridDim.x, per = total / kXCD, rem = total % kXCD;
-  const int xcd = blockIdx.x % kXCD;
-  const int g = xcd * per + min(xcd, rem) + blockIdx.x / kXCD;
+  const int g = xcd_order(blockIdx.x, gridDim.x);
   const int si = find_owner(st_pre, cnt, g);
   const int s = st_sys[si];
   const int t = g - st_pre[si];

@@ -90,6 +90,16 @@ __device__ inline double readlane_d(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// The dispatcher hands consecutive workgroups to the device's eight XCDs in
+// turn.  xcd_order(b, total) renumbers workgroup b of a grid of total so
+// that each XCD receives one contiguous range of [0, total): neighbouring
+// work items, which read the same operands, then share one XCD's L2.
+constexpr int kXCD = 8;
+__device__ __forceinline__ int xcd_order(int b, int total) {
+  const int per = total / kXCD, rem = total % kXCD, x = b % kXCD;
+  return x * per + min(x, rem) + b / kXCD;
+}
+
 // value of v in lane C of each row of 16 lanes, for every lane of that row
 // (one 64-bit DPP row_newbcast move; no LDS).  Every lane of the row must
 // be active.

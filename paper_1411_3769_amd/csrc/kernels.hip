@@ -1361,16 +1361,18 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   typedef typename AP::acc_t acc_t;
   constexpr int KC = AP::KC;                 // depth of one MFMA
   constexpr int KS = PR == 2 ? 16 : 8;       // terms per LDS stage
-  // the stage buffers and, after the last product, the combined tile share
-  // one LDS block (two workgroups fit a compute unit)
-  constexpr int kStage = 2 * KS * 16 * 17 * (int)sizeof(real), kTile = 64 * 65 * 8;
+  // two stage buffers (one multiplied while the next is written) and, after
+  // the last product, the combined tile share one LDS block (two workgroups
+  // fit a compute unit)
+  constexpr int kOp = KS * 16 * 17;          // one operand of one stage
+  constexpr int kStage = 4 * kOp * (int)sizeof(real), kTile = 64 * 65 * 8;
   __shared__ __align__(16) char smem[kStage > kTile ? kStage : kTile];
-  real* sT = reinterpret_cast<real*>(smem);
-  real* sU = sT + KS * 16 * 17;
+  real* const sbuf = reinterpret_cast<real*>(smem);   // T of buffer b at 2 b kOp, U after it
   double* sL = reinterpret_cast<double*>(smem);
   const AsmTile tl = tiles[blockIdx.x];
   ACTIVE_OR_RETURN(tl.sys);
   if (((flags[tl.sys] & F_ASM32) != 0) != (PR != 0)) return;
+  if (tl.kcnt <= 0) return;   // (a pair without terms gets no tiles)
   const SysDesc sd = sys[tl.sys];
   const int n = sd.n, nbs = sd.nbas;   // block order (entry addresses), basis order (indices)
   const int* gp = gpinfo_all + gpoff[tl.sys];
@@ -1386,10 +1388,13 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   const int jc = sc < 8 ? kTB * g3 + sc : kTB * g4 + (sc - 8);
   const bool inb = ia < nbs && jc < nbs;
   const int iN = inb ? ia * n + jc : 0, iT = inb ? jc * n + ia : 0;
-  // the next stage is fetched into registers while the current one is
-  // multiplied: the stage's term descriptors first, then every entry load
-  // (clamped, unconditional, so that all are in flight together); the
-  // coefficient (0 past the last term) is applied when the stage is staged
+  // Stage st is multiplied from LDS buffer st % 2 while the registers holding
+  // stage st + 1 are written to the other buffer and stage st + 2 is
+  // fetched into them: the stage's term descriptors first, then every entry
+  // load (clamped, unconditional, so that all are in flight together); the
+  // coefficient (0 past the last term) is applied when the stage is written.
+  // One barrier per stage: a buffer is rewritten only after every wave has
+  // passed the barrier that ends its last product.
   double vT[KS], vU[KS], cf[KS];
   auto fetch = [&](int k0) {
     KTerm kt[KS];
@@ -1402,21 +1407,30 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
       cf[kk] = k0 + kk < tl.kcnt ? kt[kk].coef : 0.0;
     }
   };
-  acc_t acc[16];
-#pragma unroll
-  for (int t = 0; t < 16; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  if (tl.kcnt > 0) fetch(0);
-  for (int k0 = 0; k0 < tl.kcnt; k0 += KS) {
-    __syncthreads();
+  auto put = [&](int b) {
+    real* dT = sbuf + 2 * b * kOp;
+    real* dU = dT + kOp;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       const bool ok = inb && cf[kk] != 0.0;
-      sT[kk * 272 + sa * 17 + sc] = AP::cvt(ok ? cf[kk] * vT[kk] : 0.0);   // T[I_a][J_c]
-      sU[kk * 272 + sc * 17 + sa] = AP::cvt(ok ? vU[kk] : 0.0);            // U[J_c][I_a]
+      dT[kk * 272 + sa * 17 + sc] = AP::cvt(ok ? cf[kk] * vT[kk] : 0.0);   // T[I_a][J_c]
+      dU[kk * 272 + sc * 17 + sa] = AP::cvt(ok ? vU[kk] : 0.0);            // U[J_c][I_a]
     }
-    __syncthreads();
-    if (k0 + KS < tl.kcnt) fetch(k0 + KS);
-    const int kq = lane >> 4, r16 = lane & 15;
+  };
+  acc_t acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  const int kq = lane >> 4, r16 = lane & 15;
+  fetch(0);
+  put(0);
+  fetch(KS);
+  __syncthreads();
+  for (int st = 0, k0 = 0; k0 < tl.kcnt; ++st, k0 += KS) {
+    const int b = st & 1;
+    put(b ^ 1);          // stage st + 1 (zeros past the end)
+    fetch(k0 + 2 * KS);
+    const real* sT = sbuf + 2 * b * kOp;
+    const real* sU = sT + kOp;
     // a partial last stage multiplies only the k-steps that hold terms
     const int kend = min(KS, tl.kcnt - k0);
 #pragma unroll
@@ -1435,6 +1449,7 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
         }
       }
     }
+    __syncthreads();
   }
   // combine the four quadrants in LDS
   const bool pqdiag = (g1 == g2), rsdiag = (g3 == g4);
