@@ -213,9 +213,11 @@ typedef struct {
                              /* (1..32); -1 = left-looking (one launch per tile column, */
                              /* each tile updated once); -2 = right-looking with each   */
                              /* step's panel solve folded into its update (one launch   */
-                             /* per step); 0 (default) = chosen per tile-count bucket   */
-                             /* by the autotuner among -1 and -2 (below 64 tiles) and   */
-                             /* widths 4, 8 and 16                                      */
+                             /* per step); -3 = look-ahead right-looking (one launch    */
+                             /* per step: the next column's diagonal factorisation and  */
+                             /* panel solve beside the update); 0 (default) = chosen    */
+                             /* per tile-count bucket by the autotuner among -1, -2,    */
+                             /* -3 (below 64 tiles) and widths 4, 8 and 16              */
     int    chol_subpanels;   /* with chol_panels = w > 0: split each super-panel in     */
                              /* sub-panels of this many panels (a divisor of w); the    */
                              /* narrow updates stay inside a sub-panel and each         */
@@ -270,7 +272,8 @@ typedef struct {
                             /* eagerly; the same count in every result of a batch)    */
     int     phase1_reason;  /* exit reason (PSDP_R_*) of the phase-I run, -1 if none  */
     int     chol_panels;    /* super-panel width the Schur Cholesky used (0: left-   */
-                            /* looking, -2: panel solves folded into the updates)     */
+                            /* looking, -2: panel solves folded into the updates,     */
+                            /* -3: look-ahead steps)                                  */
     int     chol_subpanels; /* its sub-panel width (= chol_panels: no sub-panels)    */
     /* wall time of the solve call's phases (seconds; one batch shares them):   */
     double  time_prepare_s; /* kernel-path tuning, tables, first iterate           */
@@ -376,7 +379,8 @@ int psdp_ipm_solve_noalloc(psdp_sdp* sdp, const psdp_opts* opts, psdp_result* re
  *   sol   [K]          Omega^{-1} y
  * chol_panels / chol_subpanels pick the factorisation as the psdp_opts
  * fields of those names do (-1: left-looking, -2: panel solves folded into
- * the updates, 1..32: super-panel width; a divisor of it: sub-panel width),
+ * the updates, -3: look-ahead steps, 1..32: super-panel width; a divisor of
+ * it: sub-panel width),
  * 0 = the default width 8 without sub-panels.
  * The basis order of the dual variable is the library's (see psdp_basis).
  */

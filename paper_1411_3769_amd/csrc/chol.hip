@@ -386,6 +386,160 @@ __global__ void __launch_bounds__(256, 2) k_chol_update(const SysDesc* __restric
   if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
 }
 
+// Look-ahead right-looking step p (systems factored as one super-panel).  On
+// entry column p holds L and L_pp^{-1} is stored.  Light workgroups update
+// the tiles right of column p + 1, A_ij -= L_ip L_jp^T (j >= p + 2).  Heavy
+// workgroups, one per tile (i, p+1) with i >= p + 1 and dispatched first,
+// each form the updated diagonal tile A_{p+1,p+1} - L_{p+1,p} L_{p+1,p}^T
+// and factor and invert it: the same operations on the same operands in
+// every such workgroup, so the same bits.  The diagonal tile's workgroup
+// stores L_{p+1,p+1} and its inverse; the others apply the inverse to their
+// own updated tile, L_{i,p+1} = (A_{i,p+1} - L_ip L_{p+1,p}^T) L_{p+1,p+1}^{-T}.
+// On return column p + 1 is factored: one launch per step, the next
+// column's panel solve done beside the update rather than after it, for the
+// price of the diagonal factorisation repeated by the column's workgroups.
+// Every value is computed as the right-looking steps compute it; the matrix's
+// diagonal tiles keep their values from before the last update (the factor
+// is read from Ldiag).
+__global__ void __launch_bounds__(256, 2) k_chol_look(const SysDesc* __restrict__ sys, int* flags, double* Lam,
+                                                   double* Ldiag, double* Linv,
+                                                   const int* __restrict__ h_sys, const int* __restrict__ h_pre,
+                                                   int hcnt, int htot, const int* __restrict__ l_sys,
+                                                   const int* __restrict__ l_pre, int lcnt, int p) {
+  __shared__ double sa[kNB * LDT];
+  __shared__ double sb[kNB * LDT];
+  __shared__ int fl;
+  constexpr int NE = kNB * kNB / 256;
+  const bool heavy = (int)blockIdx.x < htot;
+  const int b = heavy ? (int)blockIdx.x : (int)blockIdx.x - htot;
+  const int si = heavy ? find_owner(h_pre, hcnt, b) : find_owner(l_pre, lcnt, b);
+  const int s = heavy ? h_sys[si] : l_sys[si];
+  const int t = b - (heavy ? h_pre[si] : l_pre[si]);
+  if (!(flags[s] & F_CHOLSEL)) return;
+  const SysDesc sd = sys[s];
+  const int64_t ld = sd.Kpad;
+  double* A = Lam + sd.loff;
+  int i, j;
+  if (heavy) {
+    j = p + 1;
+    i = j + t;
+  } else {
+    // column j = p + 2 + c, rows i = j .. P-1: column c holds R - c tiles,
+    // R = P - p - 2
+    const int R = sd.P - p - 2;
+    int c = 0, base = 0;
+    while (t >= base + (R - c)) { base += R - c; ++c; }
+    j = p + 2 + c;
+    i = j + (t - base);
+  }
+  auto tile = [&](int r, int cc) { return A + (int64_t)r * kNB * ld + (int64_t)cc * kNB; };
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  {
+    const double* Li = tile(i, p);
+    const double* Lj = tile(j, p);
+    double la[NE], lb[NE];   // all loads in flight first
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      la[it] = Li[(int64_t)(e >> 6) * ld + (e & 63)];
+      lb[it] = Lj[(int64_t)(e >> 6) * ld + (e & 63)];
+    }
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int e = tid + 256 * it;
+      sa[(e >> 6) * LDT + (e & 63)] = la[it];
+      sb[(e >> 6) * LDT + (e & 63)] = lb[it];
+    }
+  }
+  __syncthreads();
+  // acc = X Y^T for 64 x 64 tiles X, Y in LDS (wave w: rows 16w..16w+15)
+  auto prodT = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(16 * w + r16) * LDT + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double bv = Y[(16 * u + r16) * LDT + k0 + kq];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+      }
+    }
+  };
+  auto ld_tile = [&](double* v, const double* T) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[u * 4 + q] = T[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16];
+  };
+  double* C = tile(i, j);
+  v4d acc[4] = {};
+  double cv[16];
+  if (!heavy) {
+    prodT(sa, sb, acc);
+    ld_tile(cv, C);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int cc = 16 * u + r16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = 16 * w + 4 * q + kq;
+        if (i != j || cc <= rr) C[(int64_t)rr * ld + cc] = cv[u * 4 + q] - acc[u][q];
+      }
+    }
+    return;
+  }
+  // heavy: E = A_{i,p+1} - L_ip L_{p+1,p}^T (below the diagonal) and the
+  // updated diagonal tile D = A_{p+1,p+1} - L_{p+1,p} L_{p+1,p}^T
+  double ev[16];
+  if (i != j) {
+    prodT(sa, sb, acc);
+    ld_tile(cv, C);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ev[u * 4 + q] = cv[u * 4 + q] - acc[u][q];
+  }
+  v4d dacc[4] = {};
+  prodT(sb, sb, dacc);
+  double dv[16];
+  ld_tile(dv, tile(j, j));
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dv[u * 4 + q] -= dacc[u][q];
+  // (D is not written back: the column's other workgroups read the tile's
+  // values before this step's update; factor and inverse go to Ldiag / Linv)
+  if (tid == 0) fl = 0;
+  __syncthreads();   // the operand panels are no longer read
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sa[(16 * w + 4 * q + kq) * LDT + 16 * u + r16] = dv[u * 4 + q];
+#pragma unroll
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + 256 * it;
+    sb[(e >> 6) * LDT + (e & 63)] = 0.0;
+  }
+  __syncthreads();
+  diag_tile(sa, sb, &fl);   // sa: L_{p+1,p+1}, sb: its inverse
+  if (i == j) {
+    store_diag(sa, sb, Ldiag + sd.dgoff + (int64_t)j * kNB * kNB, Linv + sd.dgoff + (int64_t)j * kNB * kNB);
+    if (tid == 0 && fl) atomicOr(&flags[s], F_LAMFAIL);
+    return;
+  }
+  __syncthreads();   // sa (the factor) is not needed here: E goes there
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sa[(16 * w + 4 * q + kq) * LDT + 16 * u + r16] = ev[u * 4 + q];
+  __syncthreads();
+  v4d lacc[4] = {};
+  prodT(sa, sb, lacc);   // L_{i,p+1}[r][c] = sum_k E[r][k] X[c][k]
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) C[(int64_t)(16 * w + 4 * q + kq) * ld + 16 * u + r16] = lacc[u][q];
+}
+
 // Right-looking step p with the panel solve folded in (systems factored as
 // one super-panel): every workgroup of tile (i, j), j > p, forms the panel
 // tiles it needs, L_ip = C_ip L_pp^{-T} and L_jp, from the column the
@@ -1410,6 +1564,14 @@ void launch_chol_fused(hipStream_t st, const SysDesc* sys, int* flags, double* L
   if (total)
     hipLaunchKernelGGL(k_chol_fused, dim3(total), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, PB, ssys, spre,
                        cnt, p);
+}
+
+void launch_chol_look(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
+                      const int* hsys, const int* hpre, int hcnt, int htot, const int* lsys, const int* lpre,
+                      int lcnt, int ltot, int p) {
+  if (htot + ltot)
+    hipLaunchKernelGGL(k_chol_look, dim3(htot + ltot), dim3(256), 0, st, sys, flags, Lam, Ldiag, Linv, hsys, hpre,
+                       hcnt, htot, lsys, lpre, lcnt, p);
 }
 
 void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,

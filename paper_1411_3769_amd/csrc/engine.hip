@@ -250,6 +250,7 @@ struct Batch {
   StepTab pan, trs, upd, wide, mid;
   StepTab lft;   // left-looking factorisation, one step per tile column
   StepTab fus;   // right-looking steps with the panel solve folded in
+  StepTab lah, lal;   // look-ahead steps: tiles of the next column, tiles right of it
   // grouped solves of the systems not solved in one workgroup: per group q,
   // the diagonal-block sweeps (one per system), the row tiles below the
   // group (forward) and the column tiles left of it (backward)
@@ -278,6 +279,7 @@ struct Batch {
   int *d_lft_sys = nullptr, *d_lft_pre = nullptr;
   int *d_mid_sys = nullptr, *d_mid_pre = nullptr;
   int *d_fus_sys = nullptr, *d_fus_pre = nullptr;
+  int *d_lah_sys = nullptr, *d_lah_pre = nullptr, *d_lal_sys = nullptr, *d_lal_pre = nullptr;
   int *d_gin_sys = nullptr, *d_gin_pre = nullptr, *d_gap_sys = nullptr, *d_gap_pre = nullptr;
   int *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr, *d_gbu_pre = nullptr;
   int* d_flags = nullptr;
@@ -651,6 +653,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.mid.add_step();
     B.lft.add_step();
     B.fus.add_step();
+    B.lah.add_step();
+    B.lal.add_step();
 
     // last column of the narrow update of step q (super-panel end; a
     // super-panel followed by fewer than sw panels absorbs them, since
@@ -673,6 +677,19 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
         int nn = 0;
         for (int j = pstep + 1; j < P; ++j) nn += P - j;
         if (nn > 0) B.fus.add(s, nn);
+        continue;
+      }
+      if (B.sys[s].sw == -3) {   // look-ahead: diagonal and panel solve of column 0, then one launch per step
+        if (pstep == 0) {
+          B.pan.add(s, 1);
+          if (P > 1) B.trs.add(s, P - 1);
+        }
+        if (pstep <= P - 2) {
+          B.lah.add(s, P - pstep - 1);
+          int nn = 0;
+          for (int j = pstep + 2; j < P; ++j) nn += P - j;
+          if (nn > 0) B.lal.add(s, nn);
+        }
         continue;
       }
       if (B.sys[s].sw == 0) {   // left-looking: the tiles of column pstep
@@ -741,6 +758,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(B.lft.sys) + tabsize(B.lft.pre);
   tb += tabsize(B.mid.sys) + tabsize(B.mid.pre);
   tb += tabsize(B.fus.sys) + tabsize(B.fus.pre);
+  tb += tabsize(B.lah.sys) + tabsize(B.lah.pre) + tabsize(B.lal.sys) + tabsize(B.lal.pre);
   tb += tabsize(B.gin.sys) + tabsize(B.gin.pre) + tabsize(B.gap.sys) + tabsize(B.gap.pre);
   tb += tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
@@ -828,6 +846,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.mid.pre, &B.d_mid_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.fus.sys, &B.d_fus_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.fus.pre, &B.d_fus_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lah.sys, &B.d_lah_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lah.pre, &B.d_lah_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lal.sys, &B.d_lal_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lal.pre, &B.d_lal_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.sys, &B.d_gin_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.pre, &B.d_gin_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gap.sys, &B.d_gap_sys))) return rc;
@@ -1008,6 +1030,14 @@ static void op_factor(Batch& B, hipStream_t st) {
       const size_t m2 = B.prof.mark();
       launch_chol_fused(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.PB, B.d_fus_sys + g, B.d_fus_pre + g,
                         B.fus.cnt[p], B.fus.tot[p], p);
+      B.prof.add(PSDP_PROF_CHOL_UPDATE, m2, B.prof.mark());
+    }
+    if (B.lah.tot[p] > 0) {
+      const int gh = B.lah.first[p], gl = B.lal.first[p];
+      const size_t m2 = B.prof.mark();
+      launch_chol_look(st, B.d_sys, B.d_flags, B.Lam, B.Ldiag, B.Linv, B.d_lah_sys + gh, B.d_lah_pre + gh,
+                       B.lah.cnt[p], B.lah.tot[p], B.d_lal_sys + gl, B.d_lal_pre + gl, B.lal.cnt[p],
+                       B.lal.tot[p], p);
       B.prof.add(PSDP_PROF_CHOL_UPDATE, m2, B.prof.mark());
     }
     if (B.lft.tot[p] > 0) {
@@ -1571,13 +1601,14 @@ static int sw_bucket(int P) {
 // tiles, and the super-panel widths where a super-panel fits (sub-panels are
 // an explicit option only: at K = 20200 widths 16 in sub-panels of 4 or 8
 // took 2.07 and 2.04 s against 2.02 s per certificate without)
-static int fact_code(int sw, int ssw) { return (sw < 0 ? 254 : sw) | (ssw << 8); }
-static int code_sw(int code) { return (code & 255) == 254 ? -2 : code & 255; }
+static int fact_code(int sw, int ssw) { return (sw < 0 ? 256 + sw : sw) | (ssw << 8); }
+static int code_sw(int code) { return (code & 255) >= 253 ? (code & 255) - 256 : code & 255; }
 static std::vector<int> sw_candidates(int bucket) {
   std::vector<int> c;
   if ((1 << bucket) < kLeftMaxP) {
     c.push_back(0);                    // left-looking
     c.push_back(fact_code(-2, 0));     // right-looking with the panel solve folded in
+    c.push_back(fact_code(-3, 0));     // look-ahead right-looking
   }
   if ((2 << bucket) > 8) {
     c.push_back(fact_code(4, 4));
@@ -1741,8 +1772,8 @@ static int solve_core(psdp_sdp* const* sdps, int count, const psdp_opts& o, psdp
     return fail(PSDP_EINVAL, "invalid stop_rule");
   if (o.sigma_rule != PSDP_SIGMA_FIXED && o.sigma_rule != PSDP_SIGMA_MEHROTRA)
     return fail(PSDP_EINVAL, "invalid sigma_rule");
-  if (o.chol_panels < -2 || o.chol_panels > 32)
-    return fail(PSDP_EINVAL, "chol_panels must lie in [-2, 32]");
+  if (o.chol_panels < -3 || o.chol_panels > 32)
+    return fail(PSDP_EINVAL, "chol_panels must lie in [-3, 32]");
   if (o.chol_subpanels < 0 || (o.chol_subpanels > 0 && (o.chol_panels <= 0 || o.chol_panels % o.chol_subpanels)))
     return fail(PSDP_EINVAL, "chol_subpanels must divide a chol_panels width (0: none)");
   // all work runs on a private stream (capturable into graphs) ordered

@@ -193,6 +193,9 @@ void launch_chol_fused(hipStream_t st, const SysDesc* sys, int* flags, double* L
                        double* PB, const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
                       const int* ssys, const int* spre, int cnt, int total, int j);
+void launch_chol_look(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
+                      const int* hsys, const int* hpre, int hcnt, int htot, const int* lsys, const int* lpre,
+                      int lcnt, int ltot, int p);
 void launch_trsv_ginv(hipStream_t st, const SysDesc* sys, const int* flags, const int* ssys,
                       const int* spre, int cnt, int total, const double* Lam, const double* Linv,
                       double* Ginv, int m, int phase);

@@ -697,7 +697,7 @@ int psdp_eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const doub
                      double* Zi, double* BTy, double* BX, double* Lam, double* LamL, double* sol,
                      int chol_panels, int chol_subpanels, void* stream) {
   if (!sdp || !X || !Z || !y) return fail(PSDP_EINVAL, "NULL argument");
-  if (chol_panels < -2 || chol_panels > 32) return fail(PSDP_EINVAL, "chol_panels must lie in [-2, 32]");
+  if (chol_panels < -3 || chol_panels > 32) return fail(PSDP_EINVAL, "chol_panels must lie in [-3, 32]");
   if (chol_subpanels < 0 || (chol_subpanels > 0 && (chol_panels <= 0 || chol_panels % chol_subpanels)))
     return fail(PSDP_EINVAL, "chol_subpanels must divide a chol_panels width (0: none)");
   return eval_newton(sdp, X, Z, y, Zi, BTy, BX, Lam, LamL, sol, chol_panels, chol_subpanels,

@@ -161,10 +161,10 @@ def test_kernel_paths_match_oracle(P, asm_path, solve_path):
             assert r.solve_path == solve_path
 
 
-@pytest.mark.parametrize("chol_panels,sub", [(-1, 0), (-2, 0), (4, 0), (16, 0), (8, 4)])
+@pytest.mark.parametrize("chol_panels,sub", [(-1, 0), (-2, 0), (-3, 0), (4, 0), (16, 0), (8, 4)])
 def test_factorisations_match_oracle(P, chol_panels, sub):
     """The left-looking factorisation (-1), the panel solves folded into the
-    updates (-2), super-panel widths 4 and 16, and width 8 in sub-panels of 4
+    updates (-2), the look-ahead steps (-3), super-panel widths 4 and 16, and width 8 in sub-panels of 4
     give the oracle's end points on n = 10 systems (9 tiles of 64) and on the
     mixed batch's members with stored end points."""
     with open(os.path.join(GOLDEN, "oracle_results.json")) as fh:

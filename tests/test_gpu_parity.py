@@ -70,9 +70,9 @@ NEWTON_BIG = [(16, 4, 2, 1, 7), (32, 4, 1, 2, 8), (48, 3, 1, 1, 9)]
 
 
 # factorisations: default right-looking (width 8), left-looking, panel
-# solves folded into the updates, and widths 16 / 8 split in sub-panels of 4
-# (sub-panel updates of depth 256)
-@pytest.mark.parametrize("chol", [(0, 0), (-1, 0), (-2, 0), (16, 4), (8, 4)])
+# solves folded into the updates, look-ahead steps, and widths 16 / 8 split in
+# sub-panels of 4 (sub-panel updates of depth 256)
+@pytest.mark.parametrize("chol", [(0, 0), (-1, 0), (-2, 0), (-3, 0), (16, 4), (8, 4)])
 @pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES + NEWTON_BIG)
 def test_newton_step_parity(P, n, l, dp, d, seed, chol):
     _flush(f"newton n={n} l={l} dp={dp} d={d} seed={seed} chol_panels={chol}")
@@ -108,6 +108,26 @@ def test_newton_step_parity(P, n, l, dp, d, seed, chol):
     assert np.abs(Lf @ Lf.T - Lam).max() <= 1e-11 * sc
     x = np.linalg.solve(Lam, y_lib)
     assert np.abs(out["sol"] - x).max() <= 1e-9 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES)
+def test_lookahead_equals_right_looking(P, n, l, dp, d, seed):
+    """The look-ahead steps compute every value as the right-looking steps of
+    one super-panel do (the diagonal factorisation repeated in each workgroup
+    of the next column gives the same bits), so factor and solution agree bit
+    for bit."""
+    _flush(f"look-ahead n={n} l={l} dp={dp} d={d} seed={seed}")
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((l, n, n)) - 1.5 * np.eye(n)
+    g = P.polya_setup(A, n, l, dp, d)
+    o = S.make_sdp(A, n, l, dp, d)
+    X = W.random_spd_blocks(seed + 1, o.nb, n)
+    Z = W.random_spd_blocks(seed + 2, o.nb, n)
+    y = rng.standard_normal(o.K)
+    a = P.eval_newton(g, X, Z, y, chol_panels=32)
+    b = P.eval_newton(g, X, Z, y, chol_panels=-3)
+    assert np.array_equal(a["LamL"], b["LamL"])
+    assert np.array_equal(a["sol"], b["sol"])
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
