@@ -43,14 +43,16 @@ def _golden_mixed():
         return {r["index"]: r for r in json.load(fh) if r["tag"].startswith("mixed")}
 
 
-def _check(rec, r):
+def _check(rec, r, its=1):
+    """End point against the oracle's; iterations within one in FP64 (a ladder
+    rung on the Cholesky boundary), two with reduced-precision assembly."""
     assert r.verdict_name == rec["verdict"], (rec["tag"], r.verdict_name, r.reason_name)
     if rec["verdict"] == "FEASIBLE" and not rec["phase1_used"]:
         assert abs(r.psi - rec["psi"]) <= 1e-6 * abs(rec["psi"])
         assert abs(r.phi - rec["phi"]) <= 1e-6 * abs(rec["phi"])
         assert abs(r.margin - rec["margin"]) <= 1e-6 * abs(rec["margin"])
         assert r.gap_rel <= 1e-8 and r.pinf <= 1e-8 and r.dinf <= 1e-8
-        assert abs(r.iterations - rec["iterations"]) <= 2
+        assert abs(r.iterations - rec["iterations"]) <= its, (r.iterations, rec["iterations"])
 
 
 def _perm(g, n, L0):
@@ -87,7 +89,7 @@ def test_mixed_small_members_vs_oracle(P, mixed, prec):
     gs = [P.polya_setup(mixed[i].A, mixed[i].n, mixed[i].l, mixed[i].dp, mixed[i].d) for i in idx]
     rs = P.ipm_solve_batched(gs, precision=prec)
     for i, r in zip(idx, rs):
-        _check(gold[i], r)
+        _check(gold[i], r, its=1 if prec == "fp64" else 2)
 
 
 def test_mixed_uneven_batch(P, mixed):
@@ -103,7 +105,7 @@ def test_mixed_uneven_batch(P, mixed):
     rs = P.ipm_solve_batched(gs, precision="fp32")
     for i, g, r in zip(idx, gs, rs):
         if i in gold:
-            _check(gold[i], r)
+            _check(gold[i], r, its=2)
         else:
             _check_properties(mixed[i], g, r)
     for k in (0, len(small)):

@@ -158,7 +158,9 @@ def _check_against(rec, r):
         assert abs(r.phi - rec["phi"]) <= 1e-6 * abs(rec["phi"])
         assert abs(r.margin - rec["margin"]) <= 1e-6 * abs(rec["margin"])
         assert r.gap_rel <= 1e-8 and r.pinf <= 1e-8 and r.dinf <= 1e-8
-        assert abs(r.iterations - rec["iterations"]) <= 2
+        # the trajectories differ by rounding only: a ladder rung on the
+        # Cholesky boundary can shift the count by one
+        assert abs(r.iterations - rec["iterations"]) <= 1, (r.iterations, rec["iterations"])
 
 
 def test_plain_seeds_end_to_end(P):
