@@ -784,15 +784,18 @@ __device__ inline int sp_end_dev(int P, int q, int sw) {
   return P - 1 - se < sw ? P - 1 : se;
 }
 
-// mid = 0: the update after super-panel p (depth sw panels, every tile right
-// of it); mid = 1: the update after sub-panel p inside a super-panel (depth
+// mode 0: the update after super-panel p (depth sw panels, every tile right
+// of it); mode 1: the update after sub-panel p inside a super-panel (depth
 // ssw panels, the rows below it and only the columns up to the end of the
-// super-panel, whose own update adds the whole super-panel later).
+// super-panel, whose own update adds the whole super-panel later).  The
+// look-ahead splits mode 0 in two: mode 2, the next super-panel's columns
+// (every row below p), and mode 3, every tile right of the next super-panel
+// (run beside that super-panel's steps).
 __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __restrict__ sys,
                                                              const int* __restrict__ flags, double* Lam,
                                                              const int* __restrict__ st_sys,
                                                              const int* __restrict__ st_pre, int cnt,
-                                                             int p, int mid) {
+                                                             int p, int mode) {
   __shared__ double sa[2][kWT * kWLD];   // two stages: one is multiplied while
   __shared__ double sb[2][kWT * kWLD];   // the next is written
   const int g = xcd_order(blockIdx.x, gridDim.x);
@@ -803,17 +806,22 @@ __global__ void __launch_bounds__(256, 2) k_chol_update_wide(const SysDesc* __re
   const SysDesc sd = sys[s];
   const int64_t ld = sd.Kpad;
   double* A = Lam + sd.loff;
-  int bi, bj, cmax = sd.Kpad, dpan = sd.sw;
+  int bi, bj, cmax = sd.Kpad, dpan = sd.sw, q0 = p + 1;
   const int nrb = (sd.P - p - 1 + 1) / 2;
-  if (mid) {
-    const int se = sp_end_dev(sd.P, p, sd.sw);
+  if (mode == 1 || mode == 2) {
+    // the tall block range: every row below p, the columns up to the end of
+    // the super-panel of p (mode 1) or of the next one (mode 2)
+    const int se = sp_end_dev(sd.P, mode == 1 ? p : p + 1, sd.sw);
     tall_block(t, nrb, (se - p + 1) / 2, bi, bj);
     cmax = kNB * (se + 1);
-    dpan = sd.ssw;
+    if (mode == 1) dpan = sd.ssw;
+  } else if (mode == 3) {
+    const int ne = sp_end_dev(sd.P, p + 1, sd.sw);
+    q0 = ne + 1;
+    wide_block(t, (sd.P - ne) / 2, bi, bj);
   } else {
     wide_block(t, nrb, bi, bj);
   }
-  const int q0 = p + 1;
   const int r0 = kNB * (q0 + 2 * bi), c0 = kNB * (q0 + 2 * bj);
   const int nmax = sd.Kpad;
   const int d0 = kNB * (p - dpan + 1), D = kNB * dpan;
@@ -1553,10 +1561,10 @@ void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* 
 }
 
 void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
-                             const int* ssys, const int* spre, int cnt, int total, int p, int mid) {
+                             const int* ssys, const int* spre, int cnt, int total, int p, int mode) {
   if (total)
     hipLaunchKernelGGL(k_chol_update_wide, dim3(total), dim3(256), 0, st, sys, flags, Lam, ssys, spre,
-                       cnt, p, mid);
+                       cnt, p, mode);
 }
 
 void launch_chol_fused(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,

@@ -239,6 +239,37 @@ static void pin_release(void* p, size_t bytes) {
   }
 }
 
+struct StreamPool {
+  std::mutex mu;
+  std::vector<std::pair<int, hipStream_t>> idle;
+};
+static StreamPool g_streams;
+constexpr size_t kPoolStreams = 8;
+
+// a stream of device dev from the pool, or a new one (default priority)
+static hipStream_t pool_take(int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_streams.mu);
+    for (size_t i = 0; i < g_streams.idle.size(); ++i)
+      if (g_streams.idle[i].first == dev) {
+        hipStream_t st = g_streams.idle[i].second;
+        g_streams.idle.erase(g_streams.idle.begin() + i);
+        return st;
+      }
+  }
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  return st;
+}
+
+// back to the pool once idle (or destroyed)
+static void pool_give(int dev, hipStream_t st) {
+  const bool ok = hipStreamSynchronize(st) == hipSuccess;
+  std::lock_guard<std::mutex> lk(g_streams.mu);
+  if (ok && g_streams.idle.size() < kPoolStreams) g_streams.idle.push_back({dev, st});
+  else hipStreamDestroy(st);
+}
+
 struct Batch {
   Prof prof;
   int S = 0, maxn = 0, nblk = 0, npblk = 0, ndblk = 0, npairs = 0, nq2 = 0, ntiles = 0;
@@ -251,6 +282,16 @@ struct Batch {
   StepTab lft;   // left-looking factorisation, one step per tile column
   StepTab fus;   // right-looking steps with the panel solve folded in
   StepTab lah, lal;   // look-ahead steps: tiles of the next column, tiles right of it
+  // super-panel look-ahead: after super-panel s, the update of the next
+  // super-panel's columns (lw1) runs on the solver stream and the update of
+  // everything right of them (lw2) on a side stream, beside the next
+  // super-panel's steps; the solver stream waits for it before the next lw1
+  StepTab lw1, lw2;
+  bool look = false;
+  hipStream_t side = nullptr;
+  int side_dev = 0;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool side_pending = false;
   // grouped solves of the systems not solved in one workgroup: per group q,
   // the diagonal-block sweeps (one per system), the row tiles below the
   // group (forward) and the column tiles left of it (backward)
@@ -280,6 +321,7 @@ struct Batch {
   int *d_mid_sys = nullptr, *d_mid_pre = nullptr;
   int *d_fus_sys = nullptr, *d_fus_pre = nullptr;
   int *d_lah_sys = nullptr, *d_lah_pre = nullptr, *d_lal_sys = nullptr, *d_lal_pre = nullptr;
+  int *d_lw1_sys = nullptr, *d_lw1_pre = nullptr, *d_lw2_sys = nullptr, *d_lw2_pre = nullptr;
   int *d_gin_sys = nullptr, *d_gin_pre = nullptr, *d_gap_sys = nullptr, *d_gap_pre = nullptr;
   int *d_gfu_sys = nullptr, *d_gfu_pre = nullptr, *d_gbu_sys = nullptr, *d_gbu_pre = nullptr;
   int* d_flags = nullptr;
@@ -324,6 +366,9 @@ struct Batch {
   std::vector<char> h_img;
 
   ~Batch() {
+    if (side) pool_give(side_dev, side);
+    if (ev_fork) hipEventDestroy(ev_fork);
+    if (ev_join) hipEventDestroy(ev_join);
     if (ext) return;
     if (dtab) dev_release(dtab, dtab_bytes);
     if (arena) dev_release(arena, arena_bytes);
@@ -388,6 +433,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     dflt = default_choice(sdps, count);
     ch = &dflt;
   }
+  B.look = !B.ext;   // (the allocation-free solve keeps one stream)
   B.use_pair = ch->pair;
   B.use_small = ch->small;
   B.use_sw = ch->sw;
@@ -655,6 +701,8 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
     B.fus.add_step();
     B.lah.add_step();
     B.lal.add_step();
+    B.lw1.add_step();
+    B.lw2.add_step();
 
     // last column of the narrow update of step q (super-panel end; a
     // super-panel followed by fewer than sw panels absorbs them, since
@@ -715,11 +763,30 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
       }
       // wide update after the super-panel's last panel
       if (pstep == se && pstep % sw == sw - 1 && pstep < P - 1) {
-        const int nb2 = (P - pstep - 1 + 1) / 2;
-        B.wide.add(s, nb2 * (nb2 + 1) / 2);
+        if (B.look && ssw == sw) {
+          // look-ahead: the next super-panel's columns (every row below),
+          // then the tiles right of it
+          const int ne = sp_end(P, pstep + 1, sw);
+          const int nrb = (P - pstep) / 2, ncb = (ne - pstep + 1) / 2;
+          B.lw1.add(s, ncb * nrb - ncb * (ncb - 1) / 2);
+          if (ne < P - 1) {
+            const int nb2 = (P - ne) / 2;
+            B.lw2.add(s, nb2 * (nb2 + 1) / 2);
+          }
+        } else {
+          const int nb2 = (P - pstep - 1 + 1) / 2;
+          B.wide.add(s, nb2 * (nb2 + 1) / 2);
+        }
       }
 
     }
+  }
+
+  if (!B.lw2.sys.empty()) {   // the side stream of the super-panel look-ahead
+    PSDP_HIP(hipGetDevice(&B.side_dev));
+    if (!(B.side = pool_take(B.side_dev))) return fail(PSDP_EDEVICE, "stream creation failed");
+    PSDP_HIP(hipEventCreateWithFlags(&B.ev_fork, hipEventDisableTiming));
+    PSDP_HIP(hipEventCreateWithFlags(&B.ev_join, hipEventDisableTiming));
   }
 
   // ---- grouped solve tables
@@ -759,6 +826,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   tb += tabsize(B.mid.sys) + tabsize(B.mid.pre);
   tb += tabsize(B.fus.sys) + tabsize(B.fus.pre);
   tb += tabsize(B.lah.sys) + tabsize(B.lah.pre) + tabsize(B.lal.sys) + tabsize(B.lal.pre);
+  tb += tabsize(B.lw1.sys) + tabsize(B.lw1.pre) + tabsize(B.lw2.sys) + tabsize(B.lw2.pre);
   tb += tabsize(B.gin.sys) + tabsize(B.gin.pre) + tabsize(B.gap.sys) + tabsize(B.gap.pre);
   tb += tabsize(B.gfu.sys) + tabsize(B.gfu.pre) + tabsize(B.gbu.sys) + tabsize(B.gbu.pre);
   tb += tabsize(B.small_ids);
@@ -850,6 +918,10 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
   if ((rc = upload(B.dtab, stage, off, B.lah.pre, &B.d_lah_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.lal.sys, &B.d_lal_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.lal.pre, &B.d_lal_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lw1.sys, &B.d_lw1_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lw1.pre, &B.d_lw1_pre))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lw2.sys, &B.d_lw2_sys))) return rc;
+  if ((rc = upload(B.dtab, stage, off, B.lw2.pre, &B.d_lw2_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.sys, &B.d_gin_sys))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gin.pre, &B.d_gin_pre))) return rc;
   if ((rc = upload(B.dtab, stage, off, B.gap.sys, &B.d_gap_sys))) return rc;
@@ -998,7 +1070,8 @@ static void op_ginv(Batch& B, hipStream_t st) {
   }
 }
 
-static void op_factor(Batch& B, hipStream_t st) {
+static int op_factor(Batch& B, hipStream_t st) {
+  B.side_pending = false;
   for (int p = 0; p < B.maxP; ++p) {
     const int f = B.pan.first[p];
     const size_t m0 = B.prof.mark();
@@ -1023,7 +1096,26 @@ static void op_factor(Batch& B, hipStream_t st) {
       launch_chol_update_wide(st, B.d_sys, B.d_flags, B.Lam, B.d_wide_sys + g, B.d_wide_pre + g,
                               B.wide.cnt[p], B.wide.tot[p], p, 0);
     }
-    if (B.upd.tot[p] > 0 || B.mid.tot[p] > 0 || B.wide.tot[p] > 0)
+    if (B.lw1.tot[p] > 0 || B.lw2.tot[p] > 0) {
+      // the previous side update covers this one's tiles
+      if (B.side_pending) PSDP_HIP(hipStreamWaitEvent(st, B.ev_join, 0));
+      B.side_pending = false;
+      if (B.lw2.tot[p] > 0) {
+        const int g = B.lw2.first[p];
+        PSDP_HIP(hipEventRecord(B.ev_fork, st));
+        PSDP_HIP(hipStreamWaitEvent(B.side, B.ev_fork, 0));
+        launch_chol_update_wide(B.side, B.d_sys, B.d_flags, B.Lam, B.d_lw2_sys + g, B.d_lw2_pre + g,
+                                B.lw2.cnt[p], B.lw2.tot[p], p, 3);
+        PSDP_HIP(hipEventRecord(B.ev_join, B.side));
+        B.side_pending = true;
+      }
+      if (B.lw1.tot[p] > 0) {
+        const int g = B.lw1.first[p];
+        launch_chol_update_wide(st, B.d_sys, B.d_flags, B.Lam, B.d_lw1_sys + g, B.d_lw1_pre + g,
+                                B.lw1.cnt[p], B.lw1.tot[p], p, 2);
+      }
+    }
+    if (B.upd.tot[p] > 0 || B.mid.tot[p] > 0 || B.wide.tot[p] > 0 || B.lw1.tot[p] > 0 || B.lw2.tot[p] > 0)
       B.prof.add(PSDP_PROF_CHOL_UPDATE, m1, B.prof.mark());
     if (B.fus.tot[p] > 0) {
       const int g = B.fus.first[p];
@@ -1048,7 +1140,14 @@ static void op_factor(Batch& B, hipStream_t st) {
       B.prof.add(PSDP_PROF_CHOL_UPDATE, m2, B.prof.mark());
     }
   }
+  if (B.side_pending) {
+    const size_t m0 = B.prof.mark();
+    PSDP_HIP(hipStreamWaitEvent(st, B.ev_join, 0));
+    B.side_pending = false;
+    B.prof.add(PSDP_PROF_CHOL_UPDATE, m0, B.prof.mark());
+  }
   op_ginv(B, st);
+  return PSDP_OK;
 }
 
 static int op_solve(Batch& B, hipStream_t st, const double* rhs, double* x) {
@@ -1149,12 +1248,6 @@ static void set_flags(Batch& B, const std::vector<RunState>& rs, int* hf) {
 
 // Idle solver streams, kept per device (creating and destroying a stream
 // costs about a tenth of a millisecond each).
-struct StreamPool {
-  std::mutex mu;
-  std::vector<std::pair<int, hipStream_t>> idle;
-};
-static StreamPool g_streams;
-constexpr size_t kPoolStreams = 8;
 
 // Private solver stream, started after the caller's stream (default priority).
 struct SolveStream {
@@ -1163,28 +1256,14 @@ struct SolveStream {
   int dev = 0;
   int open(hipStream_t caller) {
     PSDP_HIP(hipGetDevice(&dev));
-    {
-      std::lock_guard<std::mutex> lk(g_streams.mu);
-      for (size_t i = 0; i < g_streams.idle.size(); ++i)
-        if (g_streams.idle[i].first == dev) {
-          st = g_streams.idle[i].second;
-          g_streams.idle.erase(g_streams.idle.begin() + i);
-          break;
-        }
-    }
-    if (!st) PSDP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    if (!(st = pool_take(dev))) return fail(PSDP_EDEVICE, "stream creation failed");
     PSDP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     PSDP_HIP(hipEventRecord(ev, caller));
     PSDP_HIP(hipStreamWaitEvent(st, ev, 0));
     return PSDP_OK;
   }
   ~SolveStream() {
-    if (st) {
-      const bool ok = hipStreamSynchronize(st) == hipSuccess;
-      std::lock_guard<std::mutex> lk(g_streams.mu);
-      if (ok && g_streams.idle.size() < kPoolStreams) g_streams.idle.push_back({dev, st});
-      else hipStreamDestroy(st);
-    }
+    if (st) pool_give(dev, st);
     if (ev) hipEventDestroy(ev);
   }
 };
@@ -1429,7 +1508,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
       launch_schur_shift(st, S, B.d_sys, B.d_flags, B.d_shf, B.Lam, B.d_sc);
       B.prof.add(PSDP_PROF_MISC, pm_, B.prof.mark());
     }
-    op_factor(B, st);
+    if (int rc = op_factor(B, st)) return rc;
     // blocks of order <= kSmallN take the fused chains, larger ones the
     // separate products and elementwise kernels (which skip the former)
     const int nskip = B.nmax_small ? kSmallN : 0;
@@ -1682,7 +1761,7 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
           // one iteration's share of the path: the grouped path's block
           // inverses and both Newton solves
           op_schur(T, st);
-          op_factor(T, st);
+          if (int rc = op_factor(T, st)) return rc;
           t[v] = time_ms(st, 3, [&]() {
             op_ginv(T, st);
             op_solve(T, st, T.rv1, T.dyh);
@@ -1690,7 +1769,9 @@ static int tune_choice(psdp_sdp* const* sdps, int count, const psdp_opts& o, hip
           });
         } else {
           // the assembly restores the matrix the factorisation overwrites
-          t[v] = time_ms(st, 2, [&]() { op_schur(T, st); op_factor(T, st); });
+          int frc = PSDP_OK;
+          t[v] = time_ms(st, 2, [&]() { op_schur(T, st); if (int rc = op_factor(T, st)) frc = rc; });
+          if (frc) return frc;
         }
         PSDP_HIP(hipGetLastError());
       }
@@ -2111,7 +2192,7 @@ int eval_newton(psdp_sdp* sdp, const double* X, const double* Z, const double* y
       for (int j = 0; j < d.K; ++j)
         Lam[(int64_t)i * d.K + j] = j <= i ? full[(size_t)i * d.Kpad + j] : full[(size_t)j * d.Kpad + i];
   }
-  op_factor(B, st);
+  if (int rc = op_factor(B, st)) return rc;
   op_solve(B, st, B.y, B.dyh);
   PSDP_HIP(hipGetLastError());
   if (LamL) {

@@ -186,7 +186,7 @@ void launch_chol_trsm(hipStream_t st, const SysDesc* sys, const int* flags, doub
                       const double* Linv, const int* ssys, const int* spre, int cnt, int total,
                       int p);
 void launch_chol_update_wide(hipStream_t st, const SysDesc* sys, const int* flags, double* Lam,
-                             const int* ssys, const int* spre, int cnt, int total, int p, int mid);
+                             const int* ssys, const int* spre, int cnt, int total, int p, int mode);
 void launch_chol_update(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag,
                         double* Linv, const int* ssys, const int* spre, int cnt, int total, int p);
 void launch_chol_fused(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,
