@@ -47,9 +47,9 @@ PEAK_HBM = 8000.0         # GB/s
 PMC_TRAFFIC = {
     # n = 10: one super-panel (8 or 16 panels give the same launches at 9 tiles)
     ("n10", "cholesky"): dict(fetch_kib=21931.3, fetch_scale=2.000, write_kib=17995.3, write_scale=1.000,
-                              widths={8, 16}),
-    ("n100", "cholesky"): dict(fetch_kib=50501.6, fetch_scale=2.000, write_kib=35674.3, write_scale=1.000,
-                               widths={16}),
+                              widths={8, 16}, dispatches_per_step=1411 / 3),
+    ("n100", "cholesky"): dict(fetch_kib=49848.5, fetch_scale=2.000, write_kib=34763.7, write_scale=1.000,
+                               widths={16}, dispatches_per_step=35964 / 2),
 }
 
 
@@ -380,7 +380,8 @@ def main():
                        if tr else None)
     if tr:
         roof["traffic_unit"] = "bytes per launch (HBM read + write, rocprofv3 counters)"
-        roof["traffic_GBps"] = roof["traffic"] / (avg_ms * 1e-3) / 1e9
+        # the counters' dispatches per step over the group's device time per step
+        roof["traffic_GBps"] = roof["traffic"] * tr["dispatches_per_step"] / (chol_ms * 1e-3) / 1e9
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = launches
 

@@ -145,6 +145,23 @@ def test_graph_replay_equals_eager(P, prec):
     assert prof[P.PROF_CLASSES.index("assemble"), 1] >= sum(r.iterations for r in rp[:1])
 
 
+def test_graph_replay_lookahead(P):
+    """Systems factored in several super-panels of 8 (33 tiles: the update
+    after each super-panel split over a side stream, forked and joined inside
+    the captured graph) beside one factored as a single super-panel: graph
+    replays equal eager launches bit for bit."""
+    sys_ = [W.warm_system(s) for s in range(2)] + [W.c1_system(0)]
+    gs = [P.polya_setup(sy.A, sy.n, sy.l, sy.dp, sy.d) for sy in sys_]
+    print("graph vs eager, super-panel look-ahead", flush=True)
+    rg = P.ipm_solve_batched(gs, use_graph=1, chol_panels=8)
+    re = P.ipm_solve_batched(gs, use_graph=0, chol_panels=8)
+    assert all(r.graph_replays > 0 for r in rg) and all(r.graph_replays == 0 for r in re)
+    for a, b in zip(rg, re):
+        assert a.chol_panels == 8
+        assert a.verdict == b.verdict and a.iterations == b.iterations
+        assert np.array_equal(a.y, b.y)
+
+
 @pytest.mark.parametrize("asm_path,solve_path", [(0, 0), (0, 1), (1, 0), (1, 1), (-1, -1)])
 def test_kernel_paths_match_oracle(P, asm_path, solve_path):
     """Every assembly / solve path the autotuner can pick gives the oracle's
