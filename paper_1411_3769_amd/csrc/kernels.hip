@@ -1340,15 +1340,15 @@ __global__ void __launch_bounds__(512) k_assemble_pair_1wg(const AsmTile* __rest
 }
 
 // General n: one workgroup per Schur tile (row group (g1,g2) of h, column
-// group (g3,g4) of h2; groups of 8 indices).  Wave w accumulates one of the
-// four symmetric components over the stacked terms,
+// group (g3,g4) of h2; groups of 8 indices).  Waves 2c and 2c + 1 accumulate
+// one of the four symmetric components over the stacked terms,
 //   Q1 = sum T[q,r] U[s,p],  Q2 = sum T[q,s] U[r,p],
 //   Q3 = sum T[p,r] U[s,q],  Q4 = sum T[p,s] U[r,q],
-// as a 64 x 64 MFMA product (rows (x,y), columns (z,u) of 8 x 8 indices);
-// the four are added into an LDS tile in (p,q) x (r,s) order (Q3/Q4 only for
-// p != q, Q2/Q4 only for r != s).
+// as a 64 x 64 MFMA product (rows (x,y), columns (z,u) of 8 x 8 indices), each
+// wave 32 of its columns; the four are added into an LDS tile in
+// (p,q) x (r,s) order (Q3/Q4 only for p != q, Q2/Q4 only for r != s).
 template <int PR>
-__global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restrict__ tiles,
+__global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restrict__ tiles,
                                                       const KTerm* __restrict__ terms,
                                                       const SysDesc* __restrict__ sys,
                                                       const int* __restrict__ flags,
@@ -1361,6 +1361,7 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   typedef typename AP::acc_t acc_t;
   constexpr int KC = AP::KC;                 // depth of one MFMA
   constexpr int KS = PR == 2 ? 16 : 8;       // terms per LDS stage
+  constexpr int KH = KS / 2;                 // terms a thread stages per stage
   // two stage buffers (one multiplied while the next is written) and, after
   // the last product, the combined tile share one LDS block (two workgroups
   // fit a compute unit)
@@ -1378,12 +1379,16 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   const int* gp = gpinfo_all + gpoff[tl.sys];
   const int g1 = gp[tl.rg * 4 + 0], g2 = gp[tl.rg * 4 + 1], roff = gp[tl.rg * 4 + 2];
   const int g3 = gp[tl.cg * 4 + 0], g4 = gp[tl.cg * 4 + 1], coff = gp[tl.cg * 4 + 2];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  // index offsets of the quadrant's row pair (x, y) and column pair (z, u)
-  const int xoff = w < 2 ? 8 : 0, yoff = (w & 1) ? 8 : 0;
-  const int zoff = (w & 1) ? 0 : 8, uoff = w < 2 ? 0 : 8;
-  // every thread stages entry (a, c) of T and of U for each term of a stage
-  const int sa = tid >> 4, sc = tid & 15;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cpt = w >> 1, hh = w & 1;   // component, column half
+  // index offsets of the component's row pair (x, y) and column pair (z, u)
+  const int xoff = cpt < 2 ? 8 : 0, yoff = (cpt & 1) ? 8 : 0;
+  const int zoff = (cpt & 1) ? 0 : 8, uoff = cpt < 2 ? 0 : 8;
+  // every thread stages entry (a, c) of T and of U for half of a stage's
+  // terms (the half of its four waves)
+  const int th = tid & 255, half = __builtin_amdgcn_readfirstlane(tid >> 8);
+  const int sa = th >> 4, sc = th & 15;
   const int ia = sa < 8 ? kTB * g1 + sa : kTB * g2 + (sa - 8);
   const int jc = sc < 8 ? kTB * g3 + sc : kTB * g4 + (sc - 8);
   const bool inb = ia < nbs && jc < nbs;
@@ -1395,31 +1400,32 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   // coefficient (0 past the last term) is applied when the stage is written.
   // One barrier per stage: a buffer is rewritten only after every wave has
   // passed the barrier that ends its last product.
-  double vT[KS], vU[KS], cf[KS];
+  double vT[KH], vU[KH], cf[KH];
   auto fetch = [&](int k0) {
-    KTerm kt[KS];
+    KTerm kt[KH];
+    const int kf = k0 + half * KH;
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) kt[kk] = terms[tl.kbeg + min(k0 + kk, tl.kcnt - 1)];
+    for (int kk = 0; kk < KH; ++kk) kt[kk] = terms[tl.kbeg + min(kf + kk, tl.kcnt - 1)];
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
+    for (int kk = 0; kk < KH; ++kk) {
       vT[kk] = arena[kt[kk].offT + (kt[kk].tT ? iT : iN)];
       vU[kk] = arena[kt[kk].offU + (kt[kk].tU ? iN : iT)];
-      cf[kk] = k0 + kk < tl.kcnt ? kt[kk].coef : 0.0;
+      cf[kk] = kf + kk < tl.kcnt ? kt[kk].coef : 0.0;
     }
   };
   auto put = [&](int b) {
-    real* dT = sbuf + 2 * b * kOp;
+    real* dT = sbuf + 2 * b * kOp + half * KH * 272;
     real* dU = dT + kOp;
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
+    for (int kk = 0; kk < KH; ++kk) {
       const bool ok = inb && cf[kk] != 0.0;
       dT[kk * 272 + sa * 17 + sc] = AP::cvt(ok ? cf[kk] * vT[kk] : 0.0);   // T[I_a][J_c]
       dU[kk * 272 + sc * 17 + sa] = AP::cvt(ok ? vU[kk] : 0.0);            // U[J_c][I_a]
     }
   };
-  acc_t acc[16];
+  acc_t acc[8];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  for (int t = 0; t < 8; ++t) acc[t] = acc_t{0, 0, 0, 0};
   const int kq = lane >> 4, r16 = lane & 15;
   fetch(0);
   put(0);
@@ -1442,39 +1448,41 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
         const int xi = 2 * t + (r16 >> 3), yi = r16 & 7;
         const real* pa = sT + kb * 272 + (xoff + xi) * 17 + yoff + yi;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int v = 0; v < 2; ++v) {
+          const int u = 2 * hh + v;
           const int zi = 2 * u + (r16 >> 3), ui = r16 & 7;
           const real* pb = sU + kb * 272 + (zoff + zi) * 17 + uoff + ui;
-          acc[t * 4 + u] = asm_mfma<PR>(pa, pb, 272, acc[t * 4 + u]);
+          acc[t * 2 + v] = asm_mfma<PR>(pa, pb, 272, acc[t * 2 + v]);
         }
       }
     }
     __syncthreads();
   }
-  // combine the four quadrants in LDS
+  // combine the four components in LDS (the two waves of a component write
+  // disjoint columns)
   const bool pqdiag = (g1 == g2), rsdiag = (g3 == g4);
   for (int ph = 0; ph < 4; ++ph) {
     __syncthreads();
-    if (w == ph) {
+    if (cpt == ph) {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 2; ++v)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int row = 16 * t + asm_row<PR>(lane, i);
-            const int col = 16 * u + (lane & 15);
+            const int col = 16 * (2 * hh + v) + (lane & 15);
             const int xi = row >> 3, yi = row & 7, zi = col >> 3, ui = col & 7;
             int pi, qi, ri, si;
-            if (w == 0) { pi = ui; qi = xi; ri = yi; si = zi; }
-            else if (w == 1) { pi = ui; qi = xi; ri = zi; si = yi; }
-            else if (w == 2) { pi = xi; qi = ui; ri = yi; si = zi; }
+            if (cpt == 0) { pi = ui; qi = xi; ri = yi; si = zi; }
+            else if (cpt == 1) { pi = ui; qi = xi; ri = zi; si = yi; }
+            else if (cpt == 2) { pi = xi; qi = ui; ri = yi; si = zi; }
             else { pi = xi; qi = ui; ri = zi; si = yi; }
             const bool pq_same = pqdiag && pi == qi, rs_same = rsdiag && ri == si;
-            double v = (double)acc[t * 4 + u][i];
-            if ((w >= 2 && pq_same) || ((w & 1) && rs_same)) v = 0.0;
+            double val = (double)acc[t * 2 + v][i];
+            if ((cpt >= 2 && pq_same) || ((cpt & 1) && rs_same)) val = 0.0;
             double* dst = sL + (pi * 8 + qi) * 65 + ri * 8 + si;
-            if (w == 0) *dst = v; else *dst += v;
+            if (cpt == 0) *dst = val; else *dst += val;
           }
     }
   }
@@ -1485,7 +1493,7 @@ __global__ void __launch_bounds__(256, 2) k_assemble_grp(const AsmTile* __restri
   double* Lr = Lam + sd.loff;
   // every entry goes to its lower-triangle place (col, row) (a diagonal
   // tile covers its own transpose); consecutive threads take consecutive rows
-  for (int e = tid; e < 4096; e += 256) {
+  for (int e = tid; e < 4096; e += 512) {
     const int coll = e >> 6, rowl = e & 63;
     const int pi = rowl >> 3, qi = rowl & 7, ri = coll >> 3, si = coll & 7;
     if (pi >= n1 || qi >= n2s || ri >= n3 || si >= n4) continue;
@@ -2318,12 +2326,12 @@ void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const
                          const double* arena, double* Lam, const int64_t* gpoff, int prec) {
   if (!ntiles) return;
   if (prec == PSDP_PREC_FP32)
-    hipLaunchKernelGGL(k_assemble_grp<1>, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags,
+    hipLaunchKernelGGL(k_assemble_grp<1>, dim3(ntiles), dim3(512), 0, st, tiles, terms, sys, flags,
                        gpinfo, arena, Lam, gpoff);
   if (prec == PSDP_PREC_BF16)
-    hipLaunchKernelGGL(k_assemble_grp<2>, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags,
+    hipLaunchKernelGGL(k_assemble_grp<2>, dim3(ntiles), dim3(512), 0, st, tiles, terms, sys, flags,
                        gpinfo, arena, Lam, gpoff);
-  hipLaunchKernelGGL(k_assemble_grp<0>, dim3(ntiles), dim3(256), 0, st, tiles, terms, sys, flags,
+  hipLaunchKernelGGL(k_assemble_grp<0>, dim3(ntiles), dim3(512), 0, st, tiles, terms, sys, flags,
                      gpinfo, arena, Lam, gpoff);
 }
 
