@@ -1347,8 +1347,11 @@ __global__ void __launch_bounds__(512) k_assemble_pair_1wg(const AsmTile* __rest
 // as a 64 x 64 MFMA product (rows (x,y), columns (z,u) of 8 x 8 indices), each
 // wave 32 of its columns; the four are added into an LDS tile in
 // (p,q) x (r,s) order (Q3/Q4 only for p != q, Q2/Q4 only for r != s).
+constexpr int kGrpW = 16;   // waves of a k_assemble_grp workgroup (4 components x kGrpW / 4)
+
+// two workgroups per CU: kGrpW / 2 waves per SIMD
 template <int PR>
-__global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restrict__ tiles,
+__global__ void __launch_bounds__(64 * kGrpW) __attribute__((amdgpu_waves_per_eu(kGrpW / 2))) k_assemble_grp(const AsmTile* __restrict__ tiles,
                                                       const KTerm* __restrict__ terms,
                                                       const SysDesc* __restrict__ sys,
                                                       const int* __restrict__ flags,
@@ -1361,7 +1364,9 @@ __global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restri
   typedef typename AP::acc_t acc_t;
   constexpr int KC = AP::KC;                 // depth of one MFMA
   constexpr int KS = PR == 2 ? 16 : 8;       // terms per LDS stage
-  constexpr int KH = KS / 2;                 // terms a thread stages per stage
+  constexpr int WPC = kGrpW / 4;             // waves per component
+  constexpr int NCT = 4 / WPC;               // 16-column tiles per wave
+  constexpr int KH = KS / WPC;               // terms a thread stages per stage
   // two stage buffers (one multiplied while the next is written) and, after
   // the last product, the combined tile share one LDS block (two workgroups
   // fit a compute unit)
@@ -1381,13 +1386,13 @@ __global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restri
   const int g3 = gp[tl.cg * 4 + 0], g4 = gp[tl.cg * 4 + 1], coff = gp[tl.cg * 4 + 2];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int cpt = w >> 1, hh = w & 1;   // component, column half
+  const int cpt = w / WPC, hh = w % WPC;   // component, column part
   // index offsets of the component's row pair (x, y) and column pair (z, u)
   const int xoff = cpt < 2 ? 8 : 0, yoff = (cpt & 1) ? 8 : 0;
   const int zoff = (cpt & 1) ? 0 : 8, uoff = cpt < 2 ? 0 : 8;
   // every thread stages entry (a, c) of T and of U for half of a stage's
   // terms (the half of its four waves)
-  const int th = tid & 255, half = __builtin_amdgcn_readfirstlane(tid >> 8);
+  const int th = tid & 255, half = __builtin_amdgcn_readfirstlane(tid >> 8);   // staging part
   const int sa = th >> 4, sc = th & 15;
   const int ia = sa < 8 ? kTB * g1 + sa : kTB * g2 + (sa - 8);
   const int jc = sc < 8 ? kTB * g3 + sc : kTB * g4 + (sc - 8);
@@ -1423,9 +1428,9 @@ __global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restri
       dU[kk * 272 + sc * 17 + sa] = AP::cvt(ok ? vU[kk] : 0.0);            // U[J_c][I_a]
     }
   };
-  acc_t acc[8];
+  acc_t acc[4 * NCT];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  for (int t = 0; t < 4 * NCT; ++t) acc[t] = acc_t{0, 0, 0, 0};
   const int kq = lane >> 4, r16 = lane & 15;
   fetch(0);
   put(0);
@@ -1448,11 +1453,11 @@ __global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restri
         const int xi = 2 * t + (r16 >> 3), yi = r16 & 7;
         const real* pa = sT + kb * 272 + (xoff + xi) * 17 + yoff + yi;
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          const int u = 2 * hh + v;
+        for (int v = 0; v < NCT; ++v) {
+          const int u = NCT * hh + v;
           const int zi = 2 * u + (r16 >> 3), ui = r16 & 7;
           const real* pb = sU + kb * 272 + (zoff + zi) * 17 + uoff + ui;
-          acc[t * 2 + v] = asm_mfma<PR>(pa, pb, 272, acc[t * 2 + v]);
+          acc[t * NCT + v] = asm_mfma<PR>(pa, pb, 272, acc[t * NCT + v]);
         }
       }
     }
@@ -1467,11 +1472,11 @@ __global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restri
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
+        for (int v = 0; v < NCT; ++v)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int row = 16 * t + asm_row<PR>(lane, i);
-            const int col = 16 * (2 * hh + v) + (lane & 15);
+            const int col = 16 * (NCT * hh + v) + (lane & 15);
             const int xi = row >> 3, yi = row & 7, zi = col >> 3, ui = col & 7;
             int pi, qi, ri, si;
             if (cpt == 0) { pi = ui; qi = xi; ri = yi; si = zi; }
@@ -1479,7 +1484,7 @@ __global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restri
             else if (cpt == 2) { pi = xi; qi = ui; ri = yi; si = zi; }
             else { pi = xi; qi = ui; ri = zi; si = yi; }
             const bool pq_same = pqdiag && pi == qi, rs_same = rsdiag && ri == si;
-            double val = (double)acc[t * 2 + v][i];
+            double val = (double)acc[t * NCT + v][i];
             if ((cpt >= 2 && pq_same) || ((cpt & 1) && rs_same)) val = 0.0;
             double* dst = sL + (pi * 8 + qi) * 65 + ri * 8 + si;
             if (cpt == 0) *dst = val; else *dst += val;
@@ -1493,7 +1498,7 @@ __global__ void __launch_bounds__(512, 2) k_assemble_grp(const AsmTile* __restri
   double* Lr = Lam + sd.loff;
   // every entry goes to its lower-triangle place (col, row) (a diagonal
   // tile covers its own transpose); consecutive threads take consecutive rows
-  for (int e = tid; e < 4096; e += 512) {
+  for (int e = tid; e < 4096; e += 64 * kGrpW) {
     const int coll = e >> 6, rowl = e & 63;
     const int pi = rowl >> 3, qi = rowl & 7, ri = coll >> 3, si = coll & 7;
     if (pi >= n1 || qi >= n2s || ri >= n3 || si >= n4) continue;
@@ -2326,12 +2331,12 @@ void launch_assemble_grp(hipStream_t st, int ntiles, const AsmTile* tiles, const
                          const double* arena, double* Lam, const int64_t* gpoff, int prec) {
   if (!ntiles) return;
   if (prec == PSDP_PREC_FP32)
-    hipLaunchKernelGGL(k_assemble_grp<1>, dim3(ntiles), dim3(512), 0, st, tiles, terms, sys, flags,
+    hipLaunchKernelGGL(k_assemble_grp<1>, dim3(ntiles), dim3(64 * kGrpW), 0, st, tiles, terms, sys, flags,
                        gpinfo, arena, Lam, gpoff);
   if (prec == PSDP_PREC_BF16)
-    hipLaunchKernelGGL(k_assemble_grp<2>, dim3(ntiles), dim3(512), 0, st, tiles, terms, sys, flags,
+    hipLaunchKernelGGL(k_assemble_grp<2>, dim3(ntiles), dim3(64 * kGrpW), 0, st, tiles, terms, sys, flags,
                        gpinfo, arena, Lam, gpoff);
-  hipLaunchKernelGGL(k_assemble_grp<0>, dim3(ntiles), dim3(512), 0, st, tiles, terms, sys, flags,
+  hipLaunchKernelGGL(k_assemble_grp<0>, dim3(ntiles), dim3(64 * kGrpW), 0, st, tiles, terms, sys, flags,
                      gpinfo, arena, Lam, gpoff);
 }
 
