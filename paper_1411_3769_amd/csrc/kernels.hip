@@ -1340,12 +1340,13 @@ __global__ void __launch_bounds__(512) k_assemble_pair_1wg(const AsmTile* __rest
 }
 
 // General n: one workgroup per Schur tile (row group (g1,g2) of h, column
-// group (g3,g4) of h2; groups of 8 indices).  Waves 2c and 2c + 1 accumulate
-// one of the four symmetric components over the stacked terms,
+// group (g3,g4) of h2; groups of 8 indices).  A quarter of the waves (the
+// c-th) accumulates one of the four symmetric components over the stacked
+// terms,
 //   Q1 = sum T[q,r] U[s,p],  Q2 = sum T[q,s] U[r,p],
 //   Q3 = sum T[p,r] U[s,q],  Q4 = sum T[p,s] U[r,q],
 // as a 64 x 64 MFMA product (rows (x,y), columns (z,u) of 8 x 8 indices), each
-// wave 32 of its columns; the four are added into an LDS tile in
+// wave 64 / (kGrpW / 4) of its columns; the four are added into an LDS tile in
 // (p,q) x (r,s) order (Q3/Q4 only for p != q, Q2/Q4 only for r != s).
 constexpr int kGrpW = 16;   // waves of a k_assemble_grp workgroup (4 components x kGrpW / 4)
 
