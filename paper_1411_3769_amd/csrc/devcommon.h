@@ -11,16 +11,22 @@
 namespace psdp {
 
 // C = alpha op(A) op(B) + beta D for row-major n x n matrices (leading
-// dimension n).  256 threads; 64 x 64 output tiles, 4 x 4 per thread, inner
-// dimension staged through LDS in chunks of 16.  A and B must not alias C; D
-// may alias C or be null.  sA and sB hold 16 * 64 doubles each.
-__device__ inline void wg_gemm(int n, const double* __restrict__ A, int tA,
-                               const double* __restrict__ B, int tB, double* C, double alpha,
-                               const double* D, double beta, double* sA, double* sB) {
+// dimension n), on the 64 x 64 output tiles t = part, part + nparts, ... of
+// the block (all of them for part 0 of 1; a grid that gives each block
+// several workgroups passes blockIdx.y and gridDim.y).  256 threads; 4 x 4
+// outputs per thread, inner dimension staged through LDS in chunks of 16.
+// A and B must not alias C; D may alias C or be null.  sA and sB hold
+// 16 * 64 doubles each.
+__device__ inline void wg_gemm_part(int n, const double* __restrict__ A, int tA,
+                                    const double* __restrict__ B, int tB, double* C, double alpha,
+                                    const double* D, double beta, double* sA, double* sB, int part,
+                                    int nparts) {
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  for (int i0 = 0; i0 < n; i0 += 64) {
-    for (int j0 = 0; j0 < n; j0 += 64) {
+  const int nt = (n + 63) / 64;
+  for (int t = part; t < nt * nt; t += nparts) {
+    const int i0 = 64 * (t / nt), j0 = 64 * (t % nt);
+    {
       double acc[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -71,6 +77,13 @@ __device__ inline void wg_gemm(int n, const double* __restrict__ A, int tA,
       }
     }
   }
+}
+
+// the whole block in one workgroup
+__device__ inline void wg_gemm(int n, const double* __restrict__ A, int tA,
+                               const double* __restrict__ B, int tB, double* C, double alpha,
+                               const double* D, double beta, double* sA, double* sB) {
+  wg_gemm_part(n, A, tA, B, tB, C, alpha, D, beta, sA, sB, 0, 1);
 }
 
 // 1/sqrt(d) for a positive finite d: the hardware estimate refined by two

@@ -965,7 +965,7 @@ static void gemm_big(Batch& B, hipStream_t st, const double* A, const double* Bm
                      double alpha, const double* D, double beta, int bslot) {
   if (B.maxn > kSmallN)
     launch_gemm_blocks(st, B.nblk, B.d_blk, B.d_flags, B.d_sc, A, 0, Bm, 0, C, alpha, -1, D, beta,
-                       bslot, B.nmin_big);
+                       bslot, B.nmin_big, gemm_tiles(B.maxn));
 }
 
 // W1 = sym(Z^-1 A X) on every block
@@ -996,7 +996,7 @@ static void op_BT(Batch& B, hipStream_t st, const double* yv, double* out, bool 
     const int nskip = B.nmax_small ? kSmallN : 0;
     launch_form_P(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, ybase, B.Pm, nskip);
     launch_BT_pblk(st, B.npblk, B.d_pblk, B.d_sys, B.d_flags, B.Pm, out, nskip);
-    launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out, B.nmin_big);
+    launch_BT_dblk(st, B.ndblk, B.d_dblk, B.d_sys, B.d_flags, B.Pm, out, B.nmin_big, gemm_tiles(B.maxn));
   }
   if (phase_aware && B.any_phase1) launch_sub_tD(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, yv, out);
   if (G && !Gs) launch_make_G(st, B.nblk, B.d_blk, B.d_flags, B.Cf, out, B.Z, G, 0);
@@ -1013,7 +1013,8 @@ static void op_B(Batch& B, hipStream_t st, const double* W, double* out, double 
   if (B.nmax_small)
     launch_B_small(st, B.totL0, B.d_sys, B.d_flags, B.d_ownP, B.S, W, out, asub);
   if (B.maxn > kSmallN) {
-    launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk, B.nmin_big);
+    launch_B_Y(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, W, B.arena, B.d_blk, B.nmin_big,
+               gemm_tiles(B.maxn));
     launch_B_reduce(st, B.totK, B.d_sys, B.d_flags, B.d_ownK, B.S, B.d_pairs, W, B.arena, B.d_blk,
                     out, asub, B.nmax_small ? kSmallN : 0);
   }
@@ -1030,8 +1031,8 @@ static void op_schur(Batch& B, hipStream_t st) {
   }
   if (B.maxn > kSmallN) {
     launch_pre12(st, B.npairs, B.d_pairs, B.d_sys, B.d_flags, B.Zi, B.X, B.arena, B.d_blk, B.d_offA1,
-                 B.nmin_big);
-    launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena, B.nmin_big);
+                 B.nmin_big, gemm_tiles(B.maxn));
+    launch_pre34(st, B.nq2, B.d_q2, B.d_sys, B.d_flags, B.arena, B.nmin_big, gemm_tiles(B.maxn));
   }
   const size_t m1 = B.prof.mark();
   launch_assemble_pair(st, B.nptiles, B.maxn_pair, B.d_ptiles, B.d_terms, B.d_sys, B.d_flags,
@@ -1043,7 +1044,7 @@ static void op_schur(Batch& B, hipStream_t st) {
   B.prof.add(PSDP_PROF_ASSEMBLE, m1, m2);
   if (B.any_phase1) {
     // phase-I: v = B(D Z^-1 X) and the rank-2 + border transform
-    launch_gemm_scaled(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, B.Zi, B.X, B.W1);
+    launch_gemm_scaled(st, B.nblk, B.d_blk, B.d_sys, B.d_flags, B.Zi, B.X, B.W1, gemm_tiles(B.maxn));
     launch_symmetrize(st, B.nblk, B.d_blk, B.d_flags, B.W1, B.W1);
     op_B(B, st, B.W1, B.vtmp, 0.0, false);
     launch_lam_phase1(st, B.S, B.maxK, B.d_sys, B.d_flags, B.d_blk, B.W1, B.vtmp, B.Lam);

@@ -18,6 +18,9 @@ constexpr int kTB = 8;       // index-group size of the tiled basis
 constexpr int kNB = 64;      // Schur Cholesky tile
 constexpr int kPairGrid = 1024;   // workgroups of the whole-pair assembly (grid-stride)
 constexpr int kSW = 8;       // default Cholesky panels per super-panel (depth of the wide update / 64)
+// 64 x 64 output tiles of an n x n block (the workgroups a block product
+// takes when its tiles are shared out over a grid's y dimension)
+inline int gemm_tiles(int n) { return ((n + 63) / 64) * ((n + 63) / 64); }
 constexpr int kLeftMaxP = 64;  // the autotuner tries the left-looking factorisation below this many tiles
 constexpr int kMaxDeg = 20;  // largest multinomial degree (20! < 2^63)
 constexpr int kNSC = 32;     // per-system scalar slots

@@ -21,7 +21,7 @@ void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, c
 void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                         const double* sc, const double* A, int tA, const double* B, int tB,
                         double* C, double alpha, int aslot, const double* D, double beta,
-                        int bslot, int nmin);
+                        int bslot, int nmin, int tiles = 1);
 void launch_make_G(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                    const double* Cf, const double* S, const double* Z, double* G, int nskip = 0);
 void launch_axpby(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, double a,
@@ -48,9 +48,10 @@ void launch_BT_small(hipStream_t st, int nblk, const BlkDesc* blks, const SysDes
                      const double* y, double* out, const double* Cf = nullptr, const double* Z = nullptr,
                      double* G = nullptr);
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
-                    const int* flags, const double* Pm, double* out, int nmin);
+                    const int* flags, const double* Pm, double* out, int nmin, int tiles = 1);
 void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
-                const int* flags, const double* W, double* arena, const BlkDesc* blks, int nmin);
+                const int* flags, const double* W, double* arena, const BlkDesc* blks, int nmin,
+                int tiles = 1);
 void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
                      const int* own_pre, int S, const HMPair* pairs, const double* W,
                      const double* arena, const BlkDesc* blks, double* out, double asub, int nskip);
@@ -58,9 +59,9 @@ void launch_B_small(hipStream_t st, int totL0, const SysDesc* sys, const int* fl
                     int S, const double* W, double* out, double asub);
 void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
                   const int* flags, const double* Zi, const double* X, double* arena,
-                  const BlkDesc* blks, const int64_t* offA1, int nmin);
+                  const BlkDesc* blks, const int64_t* offA1, int nmin, int tiles = 1);
 void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, const int* flags,
-                  double* arena, int nmin);
+                  double* arena, int nmin, int tiles = 1);
 void launch_assemble_pair(hipStream_t st, int ntiles, int maxn, const AsmTile* tiles,
                           const KTerm* terms, const SysDesc* sys, const int* flags,
                           const double* arena, double* Lam, int prec, double* rscr);
@@ -114,7 +115,7 @@ void launch_sub_tD(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc*
 void launch_B_phase1(hipStream_t st, int S, const SysDesc* sys, const int* flags,
                      const BlkDesc* blks, const double* W, double* out, double asub);
 void launch_gemm_scaled(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
-                        const int* flags, const double* A, const double* B, double* C);
+                        const int* flags, const double* A, const double* B, double* C, int tiles = 1);
 void launch_lam_phase1(hipStream_t st, int S, int maxK, const SysDesc* sys, const int* flags,
                        const BlkDesc* blks, const double* W, const double* v, double* Lam);
 void launch_phase1_vectors(hipStream_t st, int S, const SysDesc* sys, const int* flags, double* yp,

@@ -297,7 +297,8 @@ __global__ void __launch_bounds__(256) k_gemm_blocks(const BlkDesc* __restrict__
   double a = alpha, c = beta;
   if (aslot >= 0) a *= sc[bd.sys * kNSC + aslot];
   if (bslot >= 0) c *= sc[bd.sys * kNSC + bslot];
-  wg_gemm(bd.n, A + bd.off, tA, B + bd.off, tB, C + bd.off, a, D ? D + bd.off : nullptr, c, sA, sB);
+  wg_gemm_part(bd.n, A + bd.off, tA, B + bd.off, tB, C + bd.off, a, D ? D + bd.off : nullptr, c, sA, sB,
+               blockIdx.y, gridDim.y);
 }
 
 // G = C - S + Z (eq. G with S = B^T(y))
@@ -544,8 +545,9 @@ __global__ void k_BT_pblk(const BlkDesc* __restrict__ pblks, const SysDesc* __re
   }
 }
 
-// derivative blocks of B^T(y): Q = sum_h P_h H_{h,m} over the h with
-// H_{h,m} != 0 (gamma_m >= h); out = -(Q + Q^T)
+// derivative blocks of B^T(y), first part: Q = sum_h P_h H_{h,m} over the h
+// with H_{h,m} != 0 (gamma_m >= h), the block's 64 x 64 tiles shared out over
+// the grid's y dimension; k_BT_dsym then forms out = -(Q + Q^T)
 __global__ void __launch_bounds__(256) k_BT_dblk(const BlkDesc* __restrict__ dblks,
                                                  const SysDesc* __restrict__ sys,
                                                  const int* __restrict__ flags,
@@ -562,15 +564,26 @@ __global__ void __launch_bounds__(256) k_BT_dblk(const BlkDesc* __restrict__ dbl
   double* O = out + bd.off;
   const int c0 = sd.h_by_m[m], c1 = sd.h_by_m[m + 1];
   if (c0 == c1) {
-    for (int e = threadIdx.x; e < nn; e += blockDim.x) O[e] = 0.0;
+    if (blockIdx.y == 0)
+      for (int e = threadIdx.x; e < nn; e += blockDim.x) O[e] = 0.0;
     return;
   }
   for (int c = c0; c < c1; ++c) {
     const int h = sd.h_list[c];
     const double* Hm = sd.H + ((int64_t)m * sd.L0 + h) * nn;
-    wg_gemm(n, Pm + sd.poff + (int64_t)h * nn, 0, Hm, 0, O, 1.0, c == c0 ? nullptr : O, 1.0, sA, sB);
-    __syncthreads();
+    wg_gemm_part(n, Pm + sd.poff + (int64_t)h * nn, 0, Hm, 0, O, 1.0, c == c0 ? nullptr : O, 1.0, sA, sB,
+                 blockIdx.y, gridDim.y);
   }
+}
+
+// derivative blocks of B^T(y), second part: out = -(Q + Q^T) in place
+__global__ void __launch_bounds__(256) k_BT_dsym(const BlkDesc* __restrict__ dblks,
+                                                 const int* __restrict__ flags, double* out, int nmin) {
+  const BlkDesc bd = dblks[blockIdx.x];
+  ACTIVE_OR_RETURN(bd.sys);
+  if (bd.n < nmin) return;
+  const int n = bd.n, nn = n * n;
+  double* O = out + bd.off;
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
     const int i = e / n, j = e % n;
     if (j < i) continue;
@@ -595,7 +608,7 @@ __global__ void __launch_bounds__(256) k_B_Y(const HMPair* __restrict__ pairs,
   const int n = pr.n, nn = n * n;
   const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
   const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
-  wg_gemm(n, Hm, 0, W + bd.off, 0, arena + pr.offY, 1.0, nullptr, 0.0, sA, sB);
+  wg_gemm_part(n, Hm, 0, W + bd.off, 0, arena + pr.offY, 1.0, nullptr, 0.0, sA, sB, blockIdx.y, gridDim.y);
 }
 
 // B operator, second stage: four lanes per (system, k = (h, b)), each taking
@@ -674,9 +687,9 @@ __global__ void __launch_bounds__(256) k_pre12(const HMPair* __restrict__ pairs,
   const int n = pr.n, nn = n * n;
   const double* Hm = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
   const BlkDesc bd = blks[sd.blk0 + sd.L + pr.m];
-  wg_gemm(n, Zi + bd.off, 0, Hm, 1, arena + offA1[blockIdx.x], 1.0, nullptr, 0.0, sA, sB);
-  __syncthreads();
-  wg_gemm(n, X + bd.off, 0, Hm, 1, arena + pr.offA2, 1.0, nullptr, 0.0, sA, sB);
+  wg_gemm_part(n, Zi + bd.off, 0, Hm, 1, arena + offA1[blockIdx.x], 1.0, nullptr, 0.0, sA, sB, blockIdx.y,
+               gridDim.y);
+  wg_gemm_part(n, X + bd.off, 0, Hm, 1, arena + pr.offA2, 1.0, nullptr, 0.0, sA, sB, blockIdx.y, gridDim.y);
 }
 
 // A3 = H_h A2[m][h2] = H_h X H_h2^T,  A4 = H_h A1[m][h2] = H_h Zi H_h2^T
@@ -691,9 +704,10 @@ __global__ void __launch_bounds__(256) k_pre34(const HM2* __restrict__ q,
   const SysDesc sd = sys[pr.sys];
   const int n = pr.n, nn = n * n;
   const double* Hh = sd.H + ((int64_t)pr.m * sd.L0 + pr.h) * nn;
-  wg_gemm(n, Hh, 0, arena + pr.srcA2, 0, arena + pr.offA3, 1.0, nullptr, 0.0, sA, sB);
-  __syncthreads();
-  wg_gemm(n, Hh, 0, arena + pr.srcA1, 0, arena + pr.offA4, 1.0, nullptr, 0.0, sA, sB);
+  wg_gemm_part(n, Hh, 0, arena + pr.srcA2, 0, arena + pr.offA3, 1.0, nullptr, 0.0, sA, sB, blockIdx.y,
+               gridDim.y);
+  wg_gemm_part(n, Hh, 0, arena + pr.srcA1, 0, arena + pr.offA4, 1.0, nullptr, 0.0, sA, sB, blockIdx.y,
+               gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1035,7 +1049,8 @@ __global__ void __launch_bounds__(256) k_gemm_scaled(const BlkDesc* __restrict__
   ACTIVE_OR_RETURN(bd.sys);
   const SysDesc sd = sys[bd.sys];
   if (sd.mode != 1) return;
-  wg_gemm(bd.n, A + bd.off, 0, B + bd.off, 0, C + bd.off, sd.scale[bd.j], nullptr, 0.0, sA, sB);
+  wg_gemm_part(bd.n, A + bd.off, 0, B + bd.off, 0, C + bd.off, sd.scale[bd.j], nullptr, 0.0, sA, sB,
+               blockIdx.y, gridDim.y);
 }
 
 // Lambda'_ij = Lambda_ij - Lambda_{K-1,i} - Lambda_{K-1,j} + Lambda_{K-1,K-1}
@@ -2142,8 +2157,8 @@ void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, c
 void launch_gemm_blocks(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags,
                         const double* sc, const double* A, int tA, const double* B, int tB,
                         double* C, double alpha, int aslot, const double* D, double beta,
-                        int bslot, int nmin) {
-  hipLaunchKernelGGL(k_gemm_blocks, dim3(nblk), dim3(256), 0, st, blks, flags, sc, A, tA, B, tB, C,
+                        int bslot, int nmin, int tiles) {
+  hipLaunchKernelGGL(k_gemm_blocks, dim3(nblk, tiles), dim3(256), 0, st, blks, flags, sc, A, tA, B, tB, C,
                      alpha, aslot, D, beta, bslot, nmin);
 }
 
@@ -2205,14 +2220,17 @@ void launch_BT_small(hipStream_t st, int nblk, const BlkDesc* blks, const SysDes
 }
 
 void launch_BT_dblk(hipStream_t st, int n, const BlkDesc* dblks, const SysDesc* sys,
-                    const int* flags, const double* Pm, double* out, int nmin) {
-  if (n)
-    hipLaunchKernelGGL(k_BT_dblk, dim3(n), dim3(256), 0, st, dblks, sys, flags, Pm, out, nmin);
+                    const int* flags, const double* Pm, double* out, int nmin, int tiles) {
+  if (n) {
+    hipLaunchKernelGGL(k_BT_dblk, dim3(n, tiles), dim3(256), 0, st, dblks, sys, flags, Pm, out, nmin);
+    hipLaunchKernelGGL(k_BT_dsym, dim3(n), dim3(256), 0, st, dblks, flags, out, nmin);
+  }
 }
 
 void launch_B_Y(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
-                const int* flags, const double* W, double* arena, const BlkDesc* blks, int nmin) {
-  if (np) hipLaunchKernelGGL(k_B_Y, dim3(np), dim3(256), 0, st, pairs, sys, flags, W, arena, blks, nmin);
+                const int* flags, const double* W, double* arena, const BlkDesc* blks, int nmin, int tiles) {
+  if (np)
+    hipLaunchKernelGGL(k_B_Y, dim3(np, tiles), dim3(256), 0, st, pairs, sys, flags, W, arena, blks, nmin);
 }
 
 void launch_B_reduce(hipStream_t st, int totalK, const SysDesc* sys, const int* flags,
@@ -2230,15 +2248,15 @@ void launch_B_small(hipStream_t st, int totL0, const SysDesc* sys, const int* fl
 
 void launch_pre12(hipStream_t st, int np, const HMPair* pairs, const SysDesc* sys,
                   const int* flags, const double* Zi, const double* X, double* arena,
-                  const BlkDesc* blks, const int64_t* offA1, int nmin) {
+                  const BlkDesc* blks, const int64_t* offA1, int nmin, int tiles) {
   if (np)
-    hipLaunchKernelGGL(k_pre12, dim3(np), dim3(256), 0, st, pairs, sys, flags, Zi, X, arena, blks, offA1,
-                       nmin);
+    hipLaunchKernelGGL(k_pre12, dim3(np, tiles), dim3(256), 0, st, pairs, sys, flags, Zi, X, arena, blks,
+                       offA1, nmin);
 }
 
 void launch_pre34(hipStream_t st, int nq, const HM2* q, const SysDesc* sys, const int* flags,
-                  double* arena, int nmin) {
-  if (nq) hipLaunchKernelGGL(k_pre34, dim3(nq), dim3(256), 0, st, q, sys, flags, arena, nmin);
+                  double* arena, int nmin, int tiles) {
+  if (nq) hipLaunchKernelGGL(k_pre34, dim3(nq, tiles), dim3(256), 0, st, q, sys, flags, arena, nmin);
 }
 
 void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
@@ -2270,8 +2288,8 @@ void launch_B_phase1(hipStream_t st, int S, const SysDesc* sys, const int* flags
   hipLaunchKernelGGL(k_B_phase1, dim3(S), dim3(256), 0, st, sys, flags, blks, W, out, asub);
 }
 void launch_gemm_scaled(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
-                        const int* flags, const double* A, const double* B, double* C) {
-  hipLaunchKernelGGL(k_gemm_scaled, dim3(nblk), dim3(256), 0, st, blks, sys, flags, A, B, C);
+                        const int* flags, const double* A, const double* B, double* C, int tiles) {
+  hipLaunchKernelGGL(k_gemm_scaled, dim3(nblk, tiles), dim3(256), 0, st, blks, sys, flags, A, B, C);
 }
 void launch_lam_phase1(hipStream_t st, int S, int maxK, const SysDesc* sys, const int* flags,
                        const BlkDesc* blks, const double* W, const double* v, double* Lam) {
