@@ -192,6 +192,102 @@ __device__ inline void store_diag(const double* sA, const double* sX, double* D,
   }
 }
 
+// Step-length ladder for blocks of order 64 < n <= 128 (the reading of the
+// paper's line search that keeps X and Z positive definite): r_0 = 1,
+// r_{k+1} = rho r_k; block b records the first k at which V_b + (r_k / frac)
+// dV_b passes Cholesky, -1 if none up to len.  The trial matrix (formed with
+// a separate multiply and add) is padded with the identity to 128 and
+// tested with the Schur Cholesky's blocked tile factorisation: diag_tile on
+// A_11, then L_21 = A_21 L_11^{-T} and A_22 - L_21 L_21^T on MFMA, and
+// diag_tile on that (a non-positive pivot anywhere fails the rung).  Smaller
+// orders keep the column-by-column test, which is faster there.
+__global__ void __launch_bounds__(256) k_ladder_tile(const BlkDesc* __restrict__ blks,
+                                                     const int* __restrict__ flags,
+                                                     const double* __restrict__ V,
+                                                     const double* __restrict__ dV, double rho,
+                                                     double frac, int len, int* kout) {
+  __shared__ double sA[kNB * kLD];   // A_11, then L_11
+  __shared__ double sX[kNB * kLD];   // L_11^{-1} (zero before each diag_tile)
+  __shared__ double sB[kNB * kLD];   // A_21, then L_21
+  __shared__ double sC[kNB * kLD];   // A_22
+  __shared__ int fl;
+  const BlkDesc bd = blks[blockIdx.x];
+  if (bd.n <= kNB || bd.n > 2 * kNB) return;   // k_ladder16 / k_ladder
+  const int tid = threadIdx.x;
+  if (!(flags[bd.sys] & F_ACTIVE)) {
+    if (tid == 0) kout[blockIdx.x] = 0;
+    return;
+  }
+  const int n = bd.n;
+  const double* Vb = V + bd.off;
+  const double* dVb = dV + bd.off;
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  // acc = X Y^T for 64 x 64 tiles in LDS (wave w: rows 16w..16w+15)
+  auto prodT = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(16 * w + r16) * kLD + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double b = Y[(16 * u + r16) * kLD + k0 + kq];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+      }
+    }
+  };
+  // entry (i, j) of the padded trial matrix
+  auto trial = [&](int i, int j, double t) {
+    if (i < n && j < n) return __dadd_rn(Vb[i * n + j], __dmul_rn(t, dVb[i * n + j]));
+    return i == j ? 1.0 : 0.0;
+  };
+  double r = 1.0;
+  int found = -1;
+  for (int k = 0; k <= len; ++k) {
+    const double t = r / frac;
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int i = e >> 6, j = e & 63;
+      sA[i * kLD + j] = trial(i, j, t);
+      sX[i * kLD + j] = 0.0;
+      sB[i * kLD + j] = trial(kNB + i, j, t);
+      sC[i * kLD + j] = trial(kNB + i, kNB + j, t);
+    }
+    if (tid == 0) fl = 0;
+    __syncthreads();
+    diag_tile(sA, sX, &fl);
+    __syncthreads();
+    v4d acc[4] = {};
+    prodT(sB, sX, acc);   // L_21 = A_21 L_11^{-T}
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sB[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] = acc[u][q];
+    __syncthreads();
+    v4d upd[4] = {};
+    prodT(sB, sB, upd);   // L_21 L_21^T
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sC[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] -= upd[u][q];
+    for (int e = tid; e < kNB * kNB; e += 256) sX[(e >> 6) * kLD + (e & 63)] = 0.0;
+    __syncthreads();
+    diag_tile(sC, sX, &fl);
+    __syncthreads();
+    const int f = fl;
+    __syncthreads();
+    if (!f) {
+      found = k;
+      break;
+    }
+    r = r * rho;
+  }
+  if (tid == 0) kout[blockIdx.x] = found;
+}
+
+void launch_ladder_tile(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, const double* V,
+                        const double* dV, double rho, double frac, int len, int* kout) {
+  hipLaunchKernelGGL(k_ladder_tile, dim3(nblk), dim3(256), 0, st, blks, flags, V, dV, rho, frac, len, kout);
+}
+
 // Diagonal step p: one workgroup per system factors the 64 x 64 tile A_pp
 // and inverts the factor, storing L_pp and L_pp^{-1}.  (Inside a
 // super-panel the narrow update of step p - 1 does this instead.)

@@ -117,11 +117,11 @@ __global__ void __launch_bounds__(256) k_ladder(const BlkDesc* __restrict__ blks
                                                 const int* __restrict__ flags,
                                                 const double* __restrict__ V,
                                                 const double* __restrict__ dV, double rho,
-                                                double frac, int len, int* kout) {
+                                                double frac, int len, int* kout, int nmax) {
   extern __shared__ double sm[];
   __shared__ int fl;
   const BlkDesc bd = blks[blockIdx.x];
-  if (bd.n <= kSmallN) return;   // k_ladder16
+  if (bd.n <= kSmallN || bd.n > nmax) return;   // k_ladder16 / k_ladder_tile
   if (!(flags[bd.sys] & F_ACTIVE)) {
     if (threadIdx.x == 0) kout[blockIdx.x] = 0;
     return;
@@ -2121,10 +2121,16 @@ void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const Blk
   if (nmax_small)
     hipLaunchKernelGGL(k_ladder16, dim3((nblk + 15) / 16), dim3(256), 0, st, blks, nblk, flags, V, dV, rho, frac,
                        len, kout, 1, nullptr, nullptr, nullptr);
+  // orders 64 < n <= 128: the tile test; 16 < n <= 64 (or every order above
+  // 16 when some block exceeds 128): the column test in LDS
+  const bool tile = maxn > kNB && maxn <= 2 * kNB;
+  if (tile) launch_ladder_tile(st, nblk, blks, flags, V, dV, rho, frac, len, kout);
   if (maxn > kSmallN) {
-    const size_t lds = (size_t)maxn * maxn * 8;
+    const int nmax = tile ? kNB : maxn;
+    const size_t lds = (size_t)std::min(maxn, nmax) * std::min(maxn, nmax) * 8;
     set_lds((const void*)k_ladder, lds);
-    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, V, dV, rho, frac, len, kout);
+    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, V, dV, rho, frac, len, kout,
+                       nmax);
   }
 }
 
@@ -2134,11 +2140,19 @@ void launch_ladder2(hipStream_t st, int nblk, int maxn, int nmax_small, const Bl
   if (nmax_small)
     hipLaunchKernelGGL(k_ladder16, dim3((2 * nblk + 15) / 16), dim3(256), 0, st, blks, nblk, flags, X, dX, rho,
                        frac, len, koutX, 2, Z, dZ, koutZ);
+  const bool tile = maxn > kNB && maxn <= 2 * kNB;
+  if (tile) {
+    launch_ladder_tile(st, nblk, blks, flags, X, dX, rho, frac, len, koutX);
+    launch_ladder_tile(st, nblk, blks, flags, Z, dZ, rho, frac, len, koutZ);
+  }
   if (maxn > kSmallN) {
-    const size_t lds = (size_t)maxn * maxn * 8;
+    const int nmax = tile ? kNB : maxn;
+    const size_t lds = (size_t)std::min(maxn, nmax) * std::min(maxn, nmax) * 8;
     set_lds((const void*)k_ladder, lds);
-    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, X, dX, rho, frac, len, koutX);
-    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, Z, dZ, rho, frac, len, koutZ);
+    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, X, dX, rho, frac, len, koutX,
+                       nmax);
+    hipLaunchKernelGGL(k_ladder, dim3(nblk), dim3(256), lds, st, blks, flags, Z, dZ, rho, frac, len, koutZ,
+                       nmax);
   }
 }
 
