@@ -283,6 +283,134 @@ __global__ void __launch_bounds__(256) k_ladder_tile(const BlkDesc* __restrict__
   if (tid == 0) kout[blockIdx.x] = found;
 }
 
+// Z^{-1} for blocks of order 64 < n <= 128: Z padded with the identity to
+// 128 and factored by the tile routine, Z = L L^T with L = [[L11, 0], [L21,
+// L22]]; X = L^{-1} = [[X11, 0], [X21, X22]] with X21 = -X22 L21 X11; then
+// Z^{-1} = X^T X, whose blocks X11^T X11 + X21^T X21, X22^T X21 and
+// X22^T X22 are MFMA products written upper triangle and mirror (exactly
+// symmetric).  A non-positive pivot sets F_ZFAIL.
+__global__ void __launch_bounds__(256) k_cholinv_tile(const BlkDesc* __restrict__ blks, int* flags,
+                                                      const double* __restrict__ Z, double* Zi) {
+  __shared__ double sA[kNB * kLD];   // A_11 -> L_11; later X_22
+  __shared__ double sX[kNB * kLD];   // X_11
+  __shared__ double sB[kNB * kLD];   // A_21 -> L_21 -> L_21 X_11
+  __shared__ double sC[kNB * kLD];   // A_22 -> S -> L_22 -> X_21
+  __shared__ int fl;
+  const BlkDesc bd = blks[blockIdx.x];
+  if (bd.n <= kNB || bd.n > 2 * kNB) return;   // k_cholinv16 / k_cholinv
+  if (!(flags[bd.sys] & F_ACTIVE)) return;
+  const int n = bd.n, tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  const double* Zb = Z + bd.off;
+  auto zpad = [&](int i, int j) { return i < n && j < n ? Zb[i * n + j] : (i == j ? 1.0 : 0.0); };
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    sA[i * kLD + j] = zpad(i, j);
+    sX[i * kLD + j] = 0.0;
+    sB[i * kLD + j] = zpad(kNB + i, j);
+    sC[i * kLD + j] = zpad(kNB + i, kNB + j);
+  }
+  if (tid == 0) fl = 0;
+  __syncthreads();
+  // products of 64 x 64 tiles in LDS (wave w: rows 16w..16w+15): XYt = X Y^T,
+  // XY = X Y, XtY = X^T Y
+  auto XYt = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(16 * w + r16) * kLD + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Y[(16 * u + r16) * kLD + k0 + kq], acc[u], 0, 0, 0);
+    }
+  };
+  auto XY = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(16 * w + r16) * kLD + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Y[(k0 + kq) * kLD + 16 * u + r16], acc[u], 0, 0, 0);
+    }
+  };
+  auto XtY = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(k0 + kq) * kLD + 16 * w + r16];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Y[(k0 + kq) * kLD + 16 * u + r16], acc[u], 0, 0, 0);
+    }
+  };
+  // result register q of lane l, tile u: row 16w + 4q + kq, column 16u + r16
+  auto put = [&](double* D, const v4d* acc, double sg) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) D[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] = sg * acc[u][q];
+  };
+  diag_tile(sA, sX, &fl);   // L_11, X_11
+  __syncthreads();
+  {
+    v4d acc[4] = {};
+    XYt(sB, sX, acc);       // L_21 = A_21 X_11^T
+    __syncthreads();
+    put(sB, acc, 1.0);
+    __syncthreads();
+    v4d upd[4] = {};
+    XYt(sB, sB, upd);       // L_21 L_21^T
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sC[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] -= upd[u][q];
+  }
+  for (int e = tid; e < kNB * kNB; e += 256) sA[(e >> 6) * kLD + (e & 63)] = 0.0;
+  __syncthreads();
+  diag_tile(sC, sA, &fl);   // L_22 (sC), X_22 (sA)
+  __syncthreads();
+  if (tid == 0 && fl) atomicOr(&flags[bd.sys], F_ZFAIL);
+  {
+    v4d acc[4] = {};
+    XY(sB, sX, acc);        // T = L_21 X_11
+    __syncthreads();
+    put(sB, acc, 1.0);
+    __syncthreads();
+    v4d x21[4] = {};
+    XY(sA, sB, x21);        // X_21 = -X_22 T
+    __syncthreads();
+    put(sC, x21, -1.0);
+    __syncthreads();
+  }
+  double* out = Zi + bd.off;
+  auto store_sym = [&](const v4d* acc, int r0, int c0, bool diag) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + 16 * w + 4 * q + kq, c = c0 + 16 * u + r16;
+        if (r >= n || c >= n || (diag && c < r)) continue;
+        out[r * n + c] = acc[u][q];
+        out[c * n + r] = acc[u][q];
+      }
+  };
+  {
+    v4d z11[4] = {};
+    XtY(sX, sX, z11);       // X_11^T X_11 + X_21^T X_21
+    XtY(sC, sC, z11);
+    store_sym(z11, 0, 0, true);
+    v4d z21[4] = {};
+    XtY(sA, sC, z21);       // X_22^T X_21 (rows 64.., columns ..64)
+    store_sym(z21, kNB, 0, false);
+    v4d z22[4] = {};
+    XtY(sA, sA, z22);       // X_22^T X_22
+    store_sym(z22, kNB, kNB, true);
+  }
+}
+
+void launch_cholinv_tile(hipStream_t st, int nblk, const BlkDesc* blks, int* flags, const double* Z,
+                         double* Zi) {
+  hipLaunchKernelGGL(k_cholinv_tile, dim3(nblk), dim3(256), 0, st, blks, flags, Z, Zi);
+}
+
 void launch_ladder_tile(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, const double* V,
                         const double* dV, double rho, double frac, int len, int* kout) {
   hipLaunchKernelGGL(k_ladder_tile, dim3(nblk), dim3(256), 0, st, blks, flags, V, dV, rho, frac, len, kout);

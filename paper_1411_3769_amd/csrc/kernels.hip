@@ -19,11 +19,11 @@ namespace psdp {
 
 // Z_j -> Z_j^{-1} = L^{-T} L^{-1} through the in-LDS Cholesky factor.
 __global__ void __launch_bounds__(256) k_cholinv(const BlkDesc* __restrict__ blks, int* flags,
-                                                 const double* __restrict__ Z, double* Zi) {
+                                                 const double* __restrict__ Z, double* Zi, int nmax) {
   extern __shared__ double sm[];
   __shared__ int fl;
   const BlkDesc bd = blks[blockIdx.x];
-  if (bd.n <= kSmallN) return;   // k_cholinv16
+  if (bd.n <= kSmallN || bd.n > nmax) return;   // k_cholinv16 / k_cholinv_tile
   ACTIVE_OR_RETURN(bd.sys);
   const int n = bd.n, nn = n * n;
   const double* Zb = Z + bd.off;
@@ -2108,10 +2108,15 @@ void launch_cholinv(hipStream_t st, int nblk, int maxn, int nmax_small, const Bl
                     int* flags, const double* Z, double* Zi) {
   if (nmax_small)
     hipLaunchKernelGGL(k_cholinv16, dim3((nblk + 15) / 16), dim3(256), 0, st, blks, nblk, flags, Z, Zi);
+  // orders 64 < n <= 128: the tile factorisation; 16 < n <= 64 (or every
+  // order above 16 when some block exceeds 128): the column factorisation in LDS
+  const bool tile = maxn > kNB && maxn <= 2 * kNB;
+  if (tile) launch_cholinv_tile(st, nblk, blks, flags, Z, Zi);
   if (maxn > kSmallN) {
-    const size_t lds = (size_t)maxn * maxn * 8;
+    const int nmax = tile ? kNB : maxn;
+    const size_t lds = (size_t)std::min(maxn, nmax) * std::min(maxn, nmax) * 8;
     set_lds((const void*)k_cholinv, lds);
-    hipLaunchKernelGGL(k_cholinv, dim3(nblk), dim3(256), lds, st, blks, flags, Z, Zi);
+    hipLaunchKernelGGL(k_cholinv, dim3(nblk), dim3(256), lds, st, blks, flags, Z, Zi, nmax);
   }
 }
 

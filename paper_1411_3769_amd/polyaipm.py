@@ -506,18 +506,22 @@ def ipm_solve_batched(sdps: Sequence[SDP], warm_y=None, warm_logx=None, **opts) 
 
 
 def eval_newton(sdp: SDP, X: np.ndarray, Z: np.ndarray, y: np.ndarray, chol_panels=0,
-                chol_subpanels=0, stream=None) -> dict:
+                chol_subpanels=0, stream=None, schur=True) -> dict:
+    """psdp_eval_newton; schur=False leaves out the K x K matrices Lam and LamL
+    (NULL in the call)."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     Z = np.ascontiguousarray(Z, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     nb, n, K = sdp.nb, sdp.bo, sdp.K
-    out = dict(Zi=np.zeros((nb, n, n)), BTy=np.zeros((nb, n, n)), BX=np.zeros(K),
-               Lam=np.zeros((K, K)), LamL=np.zeros((K, K)), sol=np.zeros(K))
+    out = dict(Zi=np.zeros((nb, n, n)), BTy=np.zeros((nb, n, n)), BX=np.zeros(K), sol=np.zeros(K))
+    if schur:
+        out["Lam"], out["LamL"] = np.zeros((K, K)), np.zeros((K, K))
     st = stream if stream is not None else _current_stream()
     _check(load().psdp_eval_newton(sdp.handle, _ptr(X), _ptr(Z), _ptr(y), _ptr(out["Zi"]),
-                                   _ptr(out["BTy"]), _ptr(out["BX"]), _ptr(out["Lam"]),
-                                   _ptr(out["LamL"]), _ptr(out["sol"]), int(chol_panels),
-                                   int(chol_subpanels), st))
+                                   _ptr(out["BTy"]), _ptr(out["BX"]),
+                                   _ptr(out["Lam"]) if schur else None,
+                                   _ptr(out["LamL"]) if schur else None, _ptr(out["sol"]),
+                                   int(chol_panels), int(chol_subpanels), st))
     return out
 
 

@@ -110,6 +110,27 @@ def test_newton_step_parity(P, n, l, dp, d, seed, chol):
     assert np.abs(out["sol"] - x).max() <= 1e-9 * np.abs(x).max()
 
 
+@pytest.mark.parametrize("n", [65, 100, 128])
+def test_block_inverse_tile_orders(P, n):
+    """Z^{-1} and B^T(y) of blocks of order 64 < n <= 128 (the tile
+    factorisation of Z padded to 128; B^T's tiled block products) against
+    numpy's inverse and the oracle's operator."""
+    _flush(f"block inverse n={n}")
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((2, n, n)) - 1.5 * np.eye(n)
+    g = P.polya_setup(A, n, 2, 1, 1)
+    o = S.make_sdp(A, n, 2, 1, 1)
+    X = W.random_spd_blocks(n + 1, o.nb, n)
+    Z = W.random_spd_blocks(n + 2, o.nb, n)
+    y_or = rng.standard_normal(o.K)
+    out = P.eval_newton(g, X, Z, y_or[_perm(g, n, o.L0)], schur=False)
+    Zi = np.linalg.inv(Z)
+    assert np.abs(out["Zi"] - Zi).max() <= 1e-11 * np.abs(Zi).max()
+    assert np.array_equal(out["Zi"], np.transpose(out["Zi"], (0, 2, 1)))
+    BT = o.BT(y_or)
+    assert np.abs(out["BTy"] - BT).max() <= 1e-12 * np.abs(BT).max()
+
+
 @pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES)
 def test_lookahead_equals_right_looking(P, n, l, dp, d, seed):
     """The look-ahead steps compute every value as the right-looking steps of
