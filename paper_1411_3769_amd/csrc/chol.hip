@@ -192,6 +192,49 @@ __device__ inline void store_diag(const double* sA, const double* sX, double* D,
   }
 }
 
+// Cholesky test of the 128 x 128 matrix [[A11, A21^T], [A21, A22]] held in
+// sA (A11), sB (A21) and sC (A22) by the tile routine: diag_tile on A11,
+// L21 = A21 L11^{-T} and A22 - L21 L21^T on MFMA, diag_tile on that; a
+// non-positive pivot anywhere sets *fl.  sX is scratch; the four tiles are
+// overwritten.  Entered and left with every thread past a barrier.
+__device__ void tile_chol_test(double* sA, double* sX, double* sB, double* sC, int* fl) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+  // acc = X Y^T for 64 x 64 tiles in LDS (wave w: rows 16w..16w+15)
+  auto prodT = [&](const double* X, const double* Y, v4d* acc) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < kNB; k0 += 4) {
+      const double a = X[(16 * w + r16) * kLD + k0 + kq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double b = Y[(16 * u + r16) * kLD + k0 + kq];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+      }
+    }
+  };
+  for (int e = tid; e < kNB * kNB; e += 256) sX[(e >> 6) * kLD + (e & 63)] = 0.0;
+  __syncthreads();
+  diag_tile(sA, sX, fl);
+  __syncthreads();
+  v4d acc[4] = {};
+  prodT(sB, sX, acc);   // L_21 = A_21 L_11^{-T}
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sB[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] = acc[u][q];
+  __syncthreads();
+  v4d upd[4] = {};
+  prodT(sB, sB, upd);   // L_21 L_21^T
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sC[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] -= upd[u][q];
+  for (int e = tid; e < kNB * kNB; e += 256) sX[(e >> 6) * kLD + (e & 63)] = 0.0;
+  __syncthreads();
+  diag_tile(sC, sX, fl);
+  __syncthreads();
+}
+
 // Step-length ladder for blocks of order 64 < n <= 128 (the reading of the
 // paper's line search that keeps X and Z positive definite): r_0 = 1,
 // r_{k+1} = rho r_k; block b records the first k at which V_b + (r_k / frac)
@@ -221,19 +264,6 @@ __global__ void __launch_bounds__(256) k_ladder_tile(const BlkDesc* __restrict__
   const int n = bd.n;
   const double* Vb = V + bd.off;
   const double* dVb = dV + bd.off;
-  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
-  // acc = X Y^T for 64 x 64 tiles in LDS (wave w: rows 16w..16w+15)
-  auto prodT = [&](const double* X, const double* Y, v4d* acc) {
-#pragma unroll 4
-    for (int k0 = 0; k0 < kNB; k0 += 4) {
-      const double a = X[(16 * w + r16) * kLD + k0 + kq];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double b = Y[(16 * u + r16) * kLD + k0 + kq];
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
-      }
-    }
-  };
   // entry (i, j) of the padded trial matrix
   auto trial = [&](int i, int j, double t) {
     if (i < n && j < n) return __dadd_rn(Vb[i * n + j], __dmul_rn(t, dVb[i * n + j]));
@@ -246,32 +276,11 @@ __global__ void __launch_bounds__(256) k_ladder_tile(const BlkDesc* __restrict__
     for (int e = tid; e < kNB * kNB; e += 256) {
       const int i = e >> 6, j = e & 63;
       sA[i * kLD + j] = trial(i, j, t);
-      sX[i * kLD + j] = 0.0;
       sB[i * kLD + j] = trial(kNB + i, j, t);
       sC[i * kLD + j] = trial(kNB + i, kNB + j, t);
     }
     if (tid == 0) fl = 0;
-    __syncthreads();
-    diag_tile(sA, sX, &fl);
-    __syncthreads();
-    v4d acc[4] = {};
-    prodT(sB, sX, acc);   // L_21 = A_21 L_11^{-T}
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sB[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] = acc[u][q];
-    __syncthreads();
-    v4d upd[4] = {};
-    prodT(sB, sB, upd);   // L_21 L_21^T
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sC[(16 * w + 4 * q + kq) * kLD + 16 * u + r16] -= upd[u][q];
-    for (int e = tid; e < kNB * kNB; e += 256) sX[(e >> 6) * kLD + (e & 63)] = 0.0;
-    __syncthreads();
-    diag_tile(sC, sX, &fl);
-    __syncthreads();
+    tile_chol_test(sA, sX, sB, sC, &fl);
     const int f = fl;
     __syncthreads();
     if (!f) {
@@ -409,6 +418,72 @@ __global__ void __launch_bounds__(256) k_cholinv_tile(const BlkDesc* __restrict_
 void launch_cholinv_tile(hipStream_t st, int nblk, const BlkDesc* blks, int* flags, const double* Z,
                          double* Zi) {
   hipLaunchKernelGGL(k_cholinv_tile, dim3(nblk), dim3(256), 0, st, blks, flags, Z, Zi);
+}
+
+// Certificate for blocks of order 64 < n <= 128: pass = Q_j = B^T(y)_j
+// passes Cholesky; margin_j = lambda_min(Q_j) / s_j by bisection on the
+// Cholesky of Q_j - tau s_j I, each test the tile routine on Q_j padded with
+// the identity to 128 (the steps of the column-test kernel otherwise).
+__global__ void __launch_bounds__(256) k_certificate_tile(const BlkDesc* __restrict__ blks,
+                                                          const SysDesc* __restrict__ sys,
+                                                          const int* __restrict__ flags,
+                                                          const double* __restrict__ Q, int iters,
+                                                          double* out) {
+  __shared__ double sA[kNB * kLD];
+  __shared__ double sX[kNB * kLD];
+  __shared__ double sB[kNB * kLD];
+  __shared__ double sC[kNB * kLD];
+  __shared__ int fl;
+  __shared__ double fro;
+  const BlkDesc bd = blks[blockIdx.x];
+  if (bd.n <= kNB || bd.n > 2 * kNB) return;   // k_certificate16 / k_certificate
+  if (!(flags[bd.sys] & F_ACTIVE)) return;
+  const SysDesc sd = sys[bd.sys];
+  const int n = bd.n, nn = n * n, tid = threadIdx.x;
+  const double sj = sd.scale[bd.j];
+  const double* Qb = Q + bd.off;
+  if (tid == 0) {
+    double f = 0;
+    for (int e = 0; e < nn; ++e) f += Qb[e] * Qb[e];
+    fro = sqrt(f);
+  }
+  auto entry = [&](int i, int j, double shift) {
+    if (i < n && j < n) return i == j ? Qb[i * n + j] - shift : Qb[i * n + j];
+    return i == j ? 1.0 : 0.0;
+  };
+  double lo = 0, hi = 0;
+  int pass0 = 0;
+  for (int it = -1; it < iters; ++it) {
+    const double tau = it < 0 ? 0.0 : 0.5 * (lo + hi);
+    __syncthreads();
+    const double shift = tau * sj;
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int i = e >> 6, j = e & 63;
+      sA[i * kLD + j] = entry(i, j, shift);
+      sB[i * kLD + j] = entry(kNB + i, j, shift);
+      sC[i * kLD + j] = entry(kNB + i, kNB + j, shift);
+    }
+    if (tid == 0) fl = 0;
+    tile_chol_test(sA, sX, sB, sC, &fl);
+    const int ok = !fl;
+    __syncthreads();
+    if (it < 0) {
+      pass0 = ok;
+      const double bnd = fro / sj + 1.0;
+      if (ok) { lo = 0.0; hi = bnd; } else { lo = -bnd; hi = 0.0; }
+    } else {
+      if (ok) lo = tau; else hi = tau;
+    }
+  }
+  if (tid == 0) {
+    out[blockIdx.x * 2 + 0] = pass0;
+    out[blockIdx.x * 2 + 1] = 0.5 * (lo + hi);
+  }
+}
+
+void launch_certificate_tile(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                             const int* flags, const double* Q, int iters, double* out) {
+  hipLaunchKernelGGL(k_certificate_tile, dim3(nblk), dim3(256), 0, st, blks, sys, flags, Q, iters, out);
 }
 
 void launch_ladder_tile(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, const double* V,

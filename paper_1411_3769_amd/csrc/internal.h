@@ -198,6 +198,8 @@ void launch_chol_left(hipStream_t st, const SysDesc* sys, int* flags, double* La
                       const int* ssys, const int* spre, int cnt, int total, int j);
 void launch_cholinv_tile(hipStream_t st, int nblk, const BlkDesc* blks, int* flags, const double* Z,
                          double* Zi);
+void launch_certificate_tile(hipStream_t st, int nblk, const BlkDesc* blks, const SysDesc* sys,
+                             const int* flags, const double* Q, int iters, double* out);
 void launch_ladder_tile(hipStream_t st, int nblk, const BlkDesc* blks, const int* flags, const double* V,
                         const double* dV, double rho, double frac, int len, int* kout);
 void launch_chol_look(hipStream_t st, const SysDesc* sys, int* flags, double* Lam, double* Ldiag, double* Linv,

@@ -718,12 +718,12 @@ __global__ void __launch_bounds__(256) k_certificate(const BlkDesc* __restrict__
                                                      const SysDesc* __restrict__ sys,
                                                      const int* __restrict__ flags,
                                                      const double* __restrict__ Q, int iters,
-                                                     double* out) {
+                                                     double* out, int nmax) {
   extern __shared__ double sm[];
   __shared__ int fl;
   __shared__ double fro;
   const BlkDesc bd = blks[blockIdx.x];
-  if (bd.n <= kSmallN) return;   // k_certificate16
+  if (bd.n <= kSmallN || bd.n > nmax) return;   // k_certificate16 / k_certificate_tile
   ACTIVE_OR_RETURN(bd.sys);
   const SysDesc sd = sys[bd.sys];
   const int n = bd.n, nn = n * n;
@@ -2283,10 +2283,13 @@ void launch_certificate(hipStream_t st, int nblk, int maxn, const BlkDesc* blks,
                         double* out) {
   hipLaunchKernelGGL(k_certificate16, dim3((nblk + 15) / 16), dim3(256), 0, st, blks, nblk, sys, flags, Q,
                      iters, out);
+  const bool tile = maxn > kNB && maxn <= 2 * kNB;
+  if (tile) launch_certificate_tile(st, nblk, blks, sys, flags, Q, iters, out);
   if (maxn > kSmallN) {
-    const size_t lds = (size_t)maxn * maxn * 8;
+    const int nmax = tile ? kNB : maxn;
+    const size_t lds = (size_t)std::min(maxn, nmax) * std::min(maxn, nmax) * 8;
     set_lds((const void*)k_certificate, lds);
-    hipLaunchKernelGGL(k_certificate, dim3(nblk), dim3(256), lds, st, blks, sys, flags, Q, iters, out);
+    hipLaunchKernelGGL(k_certificate, dim3(nblk), dim3(256), lds, st, blks, sys, flags, Q, iters, out, nmax);
   }
 }
 

@@ -131,6 +131,26 @@ def test_block_inverse_tile_orders(P, n):
     assert np.abs(out["BTy"] - BT).max() <= 1e-12 * np.abs(BT).max()
 
 
+@pytest.mark.parametrize("n", [65, 128])
+def test_certificate_tile_orders(P, n):
+    """The certificate of blocks of order 64 < n <= 128 (each bisection test
+    the tile Cholesky of the block padded with the identity to 128): every
+    block of B^T(y) positive definite and the margin equal to
+    min_j lambda_min(B^T(y)_j) / s_j through the oracle's operators."""
+    _flush(f"certificate n={n}")
+    sy = W.paper_shape_system(n, 2, seed=n)
+    g = P.polya_setup(sy.A, sy.n, sy.l, sy.dp, sy.d)
+    r = P.ipm_solve(g)
+    assert r.verdict_name == "FEASIBLE" and not r.phase1_used, (r.verdict_name, r.reason_name)
+    o = S.make_sdp(sy.A, sy.n, sy.l, sy.dp, sy.d)
+    y = np.empty_like(r.y)
+    y[_perm(g, n, o.L0)] = r.y
+    Q = o.BT(y)
+    lam = np.array([np.linalg.eigvalsh(Q[j])[0] for j in range(o.nb)])
+    assert lam.min() > 0
+    assert abs(r.margin - float(np.min(lam / o.scale))) <= 1e-6 * abs(r.margin)
+
+
 @pytest.mark.parametrize("n,l,dp,d,seed", NEWTON_CASES)
 def test_lookahead_equals_right_looking(P, n, l, dp, d, seed):
     """The look-ahead steps compute every value as the right-looking steps of
