@@ -54,9 +54,13 @@ def test_n10_batch_reduced_precision(P, prec):
         _check(recs[s], r)
         assert r.iters_lowprec >= 1
         assert np.isfinite(r.ir_eta_max) or r.iters_lowprec < r.iterations
+    share = [r.iters_lowprec / r.iterations for r in rs]
+    fell_back = sum(r.iters_lowprec < r.iterations for r in rs)
+    print(f"n10 {prec}: low-precision share of the iterations median {np.median(share):.2f}, "
+          f"min {min(share):.2f}; {fell_back} of {len(rs)} systems went on in FP64", flush=True)
     if prec == "fp32":
         # FP32 assembly stays in use for most of the run
-        assert np.median([r.iters_lowprec / r.iterations for r in rs]) >= 0.5
+        assert np.median(share) >= 0.5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
