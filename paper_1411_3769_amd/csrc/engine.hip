@@ -1563,7 +1563,7 @@ static int run_ipm(Batch& B, const psdp_opts& o, hipStream_t st, std::vector<Run
     { const size_t pm_ = B.prof.mark();
     launch_ladder2(st, B.nblk, B.maxn, B.nmax_small, B.d_blk, B.d_flags, B.X, B.dX, B.Z, B.dZ, o.ladder_rho,
                    o.step_frac, o.ladder_len, B.d_kout, B.d_kout + B.nblk);
-    launch_steps_update_y(st, B.d_sys, S, B.d_flags, B.d_kout, B.d_kout + B.nblk, o.ladder_rho, B.d_sc, B.y,
+    launch_steps_update_y(st, B.d_sys, S, B.maxK, B.d_flags, B.d_kout, B.d_kout + B.nblk, o.ladder_rho, B.d_sc, B.y,
                           B.dyh, B.dyb);
       B.prof.add(PSDP_PROF_LADDER, pm_, B.prof.mark()); }
     { const size_t pm_ = B.prof.mark();

@@ -13,7 +13,7 @@ void launch_ladder(hipStream_t st, int nblk, int maxn, int nmax_small, const Blk
 void launch_ladder2(hipStream_t st, int nblk, int maxn, int nmax_small, const BlkDesc* blks,
                     const int* flags, const double* X, const double* dX, const double* Z,
                     const double* dZ, double rho, double frac, int len, int* koutX, int* koutZ);
-void launch_steps_update_y(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* koutX,
+void launch_steps_update_y(hipStream_t st, const SysDesc* sys, int S, int maxK, int* flags, const int* koutX,
                            const int* koutZ, double rho, double* sc, double* y, const double* dyh,
                            const double* dyb);
 void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,

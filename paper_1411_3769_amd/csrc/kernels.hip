@@ -229,11 +229,14 @@ __global__ void __launch_bounds__(256) k_ladder_step(const SysDesc* __restrict__
   sc[s * kNSC + slot] = r;
 }
 
-// Both step lengths and the y update (eq. y), one wave per system: for each
-// ladder, the step is rho^{k*} with k* the largest first passing rung over
-// the system's blocks (repeated multiplication), 0 with F_LADDERFAIL if a
-// block found none; S_TP from koutX, S_TD from koutZ; then, unless the
-// Newton system or a ladder failed, y += t_D (dy^ + dy_bar).
+// Both step lengths and the y update (eq. y), one wave per system and
+// kYChunk entries of its y (grid dimension y): for each ladder, the step is
+// rho^{k*} with k* the largest first passing rung over the system's blocks
+// (repeated multiplication), 0 with F_LADDERFAIL if a block found none; S_TP
+// from koutX, S_TD from koutZ (written by the chunk-0 wave; every wave
+// derives the same values); then, unless the Newton system or a ladder
+// failed, y += t_D (dy^ + dy_bar) on the wave's chunk.
+constexpr int kYChunk = 256;
 __global__ void __launch_bounds__(256) k_steps_update_y(const SysDesc* __restrict__ sys, int S, int* flags,
                                                         const int* __restrict__ koutX,
                                                         const int* __restrict__ koutZ, double rho,
@@ -267,13 +270,14 @@ __global__ void __launch_bounds__(256) k_steps_update_y(const SysDesc* __restric
   for (int k = 0; k < kz; ++k) td = td * rho;
   if (bx) tp = 0.0;
   if (bz) td = 0.0;
-  if (lane == 0) {
+  if (lane == 0 && blockIdx.y == 0) {
     if (bx || bz) flags[s] = f0 | F_LADDERFAIL;
     sc[s * kNSC + S_TP] = tp;
     sc[s * kNSC + S_TD] = td;
   }
   if ((f0 & F_LAMFAIL) || bx || bz) return;
-  for (int k = lane; k < sd.K; k += 64) {
+  const int kend = min(sd.K, (int)(blockIdx.y + 1) * kYChunk);
+  for (int k = (int)blockIdx.y * kYChunk + lane; k < kend; k += 64) {
     const int64_t o = sd.voff + k;
     const double d = dyh[o] + dyb[o];
     y[o] = y[o] + td * d;
@@ -2161,11 +2165,12 @@ void launch_ladder2(hipStream_t st, int nblk, int maxn, int nmax_small, const Bl
   }
 }
 
-void launch_steps_update_y(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* koutX,
+void launch_steps_update_y(hipStream_t st, const SysDesc* sys, int S, int maxK, int* flags, const int* koutX,
                            const int* koutZ, double rho, double* sc, double* y, const double* dyh,
                            const double* dyb) {
-  hipLaunchKernelGGL(k_steps_update_y, dim3((S + 3) / 4), dim3(256), 0, st, sys, S, flags, koutX, koutZ, rho,
-                     sc, y, dyh, dyb);
+  const int chunks = std::max(1, (maxK + kYChunk - 1) / kYChunk);
+  hipLaunchKernelGGL(k_steps_update_y, dim3((S + 3) / 4, chunks), dim3(256), 0, st, sys, S, flags, koutX, koutZ,
+                     rho, sc, y, dyh, dyb);
 }
 
 void launch_ladder_step(hipStream_t st, const SysDesc* sys, int S, int* flags, const int* kout,
