@@ -197,7 +197,7 @@ __device__ inline void store_diag(const double* sA, const double* sX, double* D,
 // L21 = A21 L11^{-T} and A22 - L21 L21^T on MFMA, diag_tile on that; a
 // non-positive pivot anywhere sets *fl.  sX is scratch; the four tiles are
 // overwritten.  Entered and left with every thread past a barrier.
-__device__ void tile_chol_test(double* sA, double* sX, double* sB, double* sC, int* fl) {
+__device__ __forceinline__ void tile_chol_test(double* sA, double* sX, double* sB, double* sC, int* fl) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
   // acc = X Y^T for 64 x 64 tiles in LDS (wave w: rows 16w..16w+15)
   auto prodT = [&](const double* X, const double* Y, v4d* acc) {
