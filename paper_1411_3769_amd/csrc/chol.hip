@@ -1763,34 +1763,42 @@ __device__ __forceinline__ void gfwd_part(double* sz, const SysDesc& sd, int t, 
   if (j == 0) r[sd.voff + i0] -= v;
 }
 
-// Backward update part: z_c -= L_{q,c}^T x_q for the 64 columns of column
-// tile c0t + t (64 columns x the group's rows, 4 row phases of 64 lanes; 32
-// loads in flight per lane and batch).
+// Backward update part: z_c -= L_{q,c}^T x_q for the kBwdCW columns of
+// column strip t (strips of kBwdCW columns from column tile c0t on, so that
+// late groups, which have few column tiles to their left, still spread over
+// many workgroups): 256 / kBwdCW row phases, each 16-lane row read one
+// 128-byte line, 32 loads in flight per lane and batch; the phases' partial
+// sums are added in a fixed order.
 __device__ __forceinline__ void gbwd_part(double* sx, double* sp, const SysDesc& sd, int t,
                                           const double* __restrict__ Lam, const double* __restrict__ x, double* z,
                                           int q, int c0t) {
+  constexpr int NRG = 256 / kBwdCW;
   const int64_t ld = sd.Kpad;
   const int p0 = kSG * q, nrow = (min(sd.P, kSG * (q + 1)) - p0) * kNB;
   const int base = p0 * kNB;
-  const int tid = threadIdx.x, cc = tid & 63, rg = tid >> 6;
-  const int ct = c0t + t;
+  const int tid = threadIdx.x, cc = tid % kBwdCW, rg = tid / kBwdCW;
+  const int col0 = c0t * kNB + t * kBwdCW;
   for (int k = tid; k < kGS; k += 256) sx[k] = k < nrow ? x[sd.voff + base + k] : 0.0;
   __syncthreads();
-  const double* A = Lam + sd.loff + (int64_t)base * ld + ct * kNB + cc;
+  const double* A = Lam + sd.loff + (int64_t)base * ld + col0 + cc;
   double acc = 0.0;
-  for (int r0 = 0; r0 < kGS; r0 += 128) {
+  for (int r0 = 0; r0 < kGS; r0 += 32 * NRG) {
     double a[32];
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
-      const int rr = r0 + rg + 4 * u;
+      const int rr = r0 + rg + NRG * u;
       a[u] = rr < nrow ? A[(int64_t)rr * ld] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 32; ++u) acc += a[u] * sx[r0 + rg + 4 * u];
+    for (int u = 0; u < 32; ++u) acc += a[u] * sx[r0 + rg + NRG * u];
   }
-  sp[rg * kNB + cc] = acc;
+  sp[rg * kBwdCW + cc] = acc;
   __syncthreads();
-  if (tid < kNB) z[sd.voff + ct * kNB + tid] -= sp[tid] + sp[kNB + tid] + sp[2 * kNB + tid] + sp[3 * kNB + tid];
+  if (tid < kBwdCW) {
+    double v = 0.0;
+    for (int g = 0; g < NRG; ++g) v += sp[g * kBwdCW + tid];
+    z[sd.voff + col0 + tid] -= v;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_trsv_gapply(const SysDesc* __restrict__ sys,
@@ -1829,7 +1837,7 @@ __global__ void __launch_bounds__(256) k_trsv_gbwd(const SysDesc* __restrict__ s
                                                    const double* __restrict__ Lam,
                                                    const double* __restrict__ x, double* z, int q) {
   __shared__ double sx[kGS];
-  __shared__ double sp[4 * kNB];
+  __shared__ double sp[256];
   const int si = find_owner(st_pre, cnt, blockIdx.x);
   const int s = st_sys[si];
   if (!(flags[s] & F_ACTIVE)) return;

@@ -809,7 +809,7 @@ static int build_batch(Batch& B, psdp_sdp* const* sdps, int count, const Choice*
       if (!tiled(s) || P <= kSG * q) continue;
       B.gap.add(s, (std::min(P, kSG * (q + 1)) - kSG * q) * (kNB / 16));
       if (P > kSG * (q + 1)) B.gfu.add(s, (P - kSG * (q + 1)) * (kNB / 16));
-      if (q > 0) B.gbu.add(s, kSG * q);
+      if (q > 0) B.gbu.add(s, kSG * q * (kNB / kBwdCW));
     }
   }
 

@@ -17,6 +17,7 @@ constexpr int kMaxN = 128;   // largest block order held whole in LDS (128 KB)
 constexpr int kTB = 8;       // index-group size of the tiled basis
 constexpr int kNB = 64;      // Schur Cholesky tile
 constexpr int kPairGrid = 1024;   // workgroups of the whole-pair assembly (grid-stride)
+constexpr int kBwdCW = 16;   // columns of a backward-sweep workgroup's strip (divides 64)
 constexpr int kSW = 8;       // default Cholesky panels per super-panel (depth of the wide update / 64)
 // 64 x 64 output tiles of an n x n block (the workgroups a block product
 // takes when its tiles are shared out over a grid's y dimension)
